@@ -1,0 +1,8 @@
+"""CPU oracle for the GST likelihood path -- test infrastructure only.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
+``bench.py`` may import this package.  The product library never does.
+"""
+from .binding import (  # noqa: F401
+    build, probs, probs_extended, loglik, vjp, OracleError, library_path,
+)

@@ -1,0 +1,475 @@
+"""Seeded synthetic GST workloads: gate sets, sequence lists and outcome counts.
+
+This module only *prepares inputs*.  It encodes gates as Pauli-transfer
+matrices (thesis Sec. 2.4.1, Eqs. paulibasis / paulitransfermatrix), lists
+gate sequences with the fiducial x germ-power x fiducial structure of
+Sec. 6.3.1 (Eq. GSTFullFiducialsGerms), and samples outcome counts from a
+"black box" that is emulated in Hilbert space (state vectors and unitaries, no
+transfer matrices).  It never evaluates the probability chain, the likelihood
+or its gradient on transfer matrices: that is the method, and it lives in the
+HIP library (product) and in ``oracle/`` (test infrastructure) only.
+
+Conventions (thesis Sec. 2.1.3 and Sec. 2.4.1):
+  * qubit 0 is the most significant bit of a basis index and the leftmost
+    tensor factor;
+  * Pauli index ``i = sum_q a_q 4**(n-1-q)`` with ``a in {I:0, X:1, Y:2, Z:3}``;
+  * normalized basis ``P_i / sqrt(d)``, ``d = 2**n``, ``D = d*d``;
+  * a gate word is stored in time order ``s_1 .. s_L`` (the matrix product is
+    the reverse, Sec. 2.2.2).
+
+Sequence lists are CSR: ``offsets`` int64 ``[S+1]`` and ``gates`` uint8
+``[offsets[S]]``.
+"""
+from __future__ import annotations
+
+import dataclasses
+import itertools
+from typing import Dict, List, Optional, Sequence, Tuple
+
+import numpy as np
+
+# ---------------------------------------------------------------------------
+# Pauli basis and transfer-matrix encoding (Sec. 2.4.1)
+# ---------------------------------------------------------------------------
+_I2 = np.eye(2, dtype=np.complex128)
+_SX = np.array([[0, 1], [1, 0]], dtype=np.complex128)
+_SY = np.array([[0, -1j], [1j, 0]], dtype=np.complex128)
+_SZ = np.array([[1, 0], [0, -1]], dtype=np.complex128)
+PAULI_1Q = (_I2, _SX, _SY, _SZ)
+
+
+def pauli_basis(n: int) -> np.ndarray:
+    """Unnormalized n-qubit Pauli products ``P_i``, shape ``[4**n, 2**n, 2**n]``.
+
+    Index ``i`` has base-4 digits ``a_0 .. a_{n-1}`` (qubit 0 most significant),
+    so ``P_1 = I x .. x I x sigma^x`` as in Eq. paulibasis.
+    """
+    out = []
+    for digits in itertools.product(range(4), repeat=n):
+        m = np.ones((1, 1), dtype=np.complex128)
+        for a in digits:
+            m = np.kron(m, PAULI_1Q[a])
+        out.append(m)
+    return np.array(out)
+
+
+def ptm_from_kraus(kraus: Sequence[np.ndarray]) -> np.ndarray:
+    """Transfer matrix ``G_ij = Tr(P_i E(P_j)) / d`` of ``E(r) = sum_a K_a r K_a^+``."""
+    d = kraus[0].shape[0]
+    n = int(round(np.log2(d)))
+    P = pauli_basis(n)
+    D = d * d
+    img = np.zeros((D, d, d), dtype=np.complex128)
+    for K in kraus:
+        img += np.einsum("ab,jbc,dc->jad", K, P, K.conj())
+    G = np.einsum("iab,jba->ij", P, img) / d
+    return np.ascontiguousarray(G.real)
+
+
+def ptm_from_unitary(U: np.ndarray) -> np.ndarray:
+    return ptm_from_kraus([U])
+
+
+def vec_operator(A: np.ndarray) -> np.ndarray:
+    """Coefficients ``Tr(P_i A) / sqrt(d)`` of a Hermitian operator (Eqs. GSTVectorizedRho/EJ)."""
+    d = A.shape[0]
+    n = int(round(np.log2(d)))
+    P = pauli_basis(n)
+    return np.ascontiguousarray(np.einsum("iab,ba->i", P, A).real / np.sqrt(d))
+
+
+def depolarizing_ptm(lam: float, n: int) -> np.ndarray:
+    """Global symmetric depolarizing ``F r + (1-F) I/d`` with ``F = 1 - lam`` (Eq. singletDepolarizingChannelSymmetricMixture)."""
+    D = 4 ** n
+    return np.diag(np.concatenate([[1.0], np.full(D - 1, 1.0 - lam)]))
+
+
+# ---------------------------------------------------------------------------
+# Elementary unitaries (Sec. 2.2.1, App. B)
+# ---------------------------------------------------------------------------
+def rx(theta: float) -> np.ndarray:
+    c, s = np.cos(theta / 2), np.sin(theta / 2)
+    return np.array([[c, -1j * s], [-1j * s, c]], dtype=np.complex128)
+
+
+def ry(theta: float) -> np.ndarray:
+    c, s = np.cos(theta / 2), np.sin(theta / 2)
+    return np.array([[c, -s], [s, c]], dtype=np.complex128)
+
+
+def rz(theta: float) -> np.ndarray:
+    return np.diag([np.exp(-0.5j * theta), np.exp(0.5j * theta)]).astype(np.complex128)
+
+
+def on_qubit(U1: np.ndarray, q: int, n: int) -> np.ndarray:
+    m = np.ones((1, 1), dtype=np.complex128)
+    for k in range(n):
+        m = np.kron(m, U1 if k == q else _I2)
+    return m
+
+
+def cz(q0: int, q1: int, n: int) -> np.ndarray:
+    d = 2 ** n
+    diag = np.ones(d, dtype=np.complex128)
+    for J in range(d):
+        b0 = (J >> (n - 1 - q0)) & 1
+        b1 = (J >> (n - 1 - q1)) & 1
+        if b0 and b1:
+            diag[J] = -1
+    return np.diag(diag)
+
+
+def cnot(control: int, target: int, n: int) -> np.ndarray:
+    d = 2 ** n
+    U = np.zeros((d, d), dtype=np.complex128)
+    for J in range(d):
+        bc = (J >> (n - 1 - control)) & 1
+        J2 = J ^ (bc << (n - 1 - target))
+        U[J2, J] = 1
+    return U
+
+
+def expm_hermitian(H: np.ndarray, t: float) -> np.ndarray:
+    """``exp(-i t H)`` for Hermitian ``H`` via its eigendecomposition."""
+    w, V = np.linalg.eigh(H)
+    return (V * np.exp(-1j * t * w)) @ V.conj().T
+
+
+# ---------------------------------------------------------------------------
+# Gate sets
+# ---------------------------------------------------------------------------
+@dataclasses.dataclass
+class GateSet:
+    n_qubits: int
+    names: List[str]
+    rho: np.ndarray        # [D]
+    effects: np.ndarray    # [M, D]
+    gates: np.ndarray      # [K, D, D] row-major
+    unitaries: Optional[np.ndarray] = None  # [K, d, d] coherent parts (None for general CPTP sets)
+    lam: float = 0.0       # global depolarizing strength applied after every gate
+
+    @property
+    def D(self) -> int:
+        return 4 ** self.n_qubits
+
+    @property
+    def M(self) -> int:
+        return self.effects.shape[0]
+
+    @property
+    def K(self) -> int:
+        return self.gates.shape[0]
+
+    def n_params(self) -> int:
+        return self.D + self.M * self.D + self.K * self.D * self.D
+
+
+def ideal_unitaries(kind: str) -> Tuple[List[str], List[np.ndarray], int]:
+    """Ideal gate lists of the workload families (thesis Tab. GSTPulseImplementations, App. B)."""
+    h = np.pi / 2
+    if kind == "1q":
+        n = 1
+        return ["Gi", "Gx", "Gy"], [_I2.copy(), rx(h), ry(h)], n
+    if kind == "2q":
+        n = 2
+        return (["Gii", "Gxi", "Gix", "Gyi", "Giy", "Gcz"],
+                [np.eye(4, dtype=np.complex128), on_qubit(rx(h), 0, n), on_qubit(rx(h), 1, n),
+                 on_qubit(ry(h), 0, n), on_qubit(ry(h), 1, n), cz(0, 1, n)], n)
+    if kind == "3q":
+        n = 3
+        X3 = np.kron(np.kron(rx(h), rx(h)), rx(h))
+        Y3 = np.kron(np.kron(ry(h), ry(h)), ry(h))
+        return (["Giii", "Gxxx", "Gyyy", "Gcz01", "Gcz12"],
+                [np.eye(8, dtype=np.complex128), X3, Y3, cz(0, 1, n), cz(1, 2, n)], n)
+    raise ValueError(kind)
+
+
+def random_axis(rng: np.random.Generator, D: int) -> np.ndarray:
+    v = rng.standard_normal(D - 1)
+    return v / np.linalg.norm(v)
+
+
+def noisy_gateset(kind: str, lam: float, sigma: float, rng: np.random.Generator) -> GateSet:
+    """Ideal gates composed with a seeded over-rotation and global depolarizing.
+
+    ``U_k = exp(-i delta_k H_k / 2) U_k^ideal`` with ``H_k = sum_{j>=1} h_kj P_j``,
+    ``h_k`` uniform on the unit sphere and ``delta_k ~ N(0, sigma^2)`` (the
+    axis-angle form of Eqs. GSTGateHamiltonian-GSTHamiltonianAxis); then
+    ``G_k = diag(1, (1-lam) 1) R(U_k)``.  Global depolarizing commutes with
+    every unitary channel, so the order of the composition is immaterial.
+    """
+    names, Us, n = ideal_unitaries(kind)
+    d, D = 2 ** n, 4 ** n
+    P = pauli_basis(n)
+    dep = depolarizing_ptm(lam, n)
+    coh, G = [], []
+    for U0 in Us:
+        h = random_axis(rng, D)
+        delta = rng.normal(0.0, sigma)
+        H = np.einsum("j,jab->ab", h, P[1:])
+        U = expm_hermitian(H, delta / 2.0) @ U0
+        coh.append(U)
+        G.append(dep @ ptm_from_unitary(U))
+    rho = vec_operator(np.diag(np.eye(d)[0]).astype(np.complex128))
+    E = np.array([vec_operator(np.diag(np.eye(d)[m]).astype(np.complex128)) for m in range(d)])
+    return GateSet(n, names, rho, E, np.ascontiguousarray(np.array(G)), np.array(coh), lam)
+
+
+# ---------------------------------------------------------------------------
+# Sequence lists (Sec. 6.3.1, Eq. GSTFullFiducialsGerms)
+# ---------------------------------------------------------------------------
+def shortlex_words(alphabet: Sequence[int], count: int) -> List[Tuple[int, ...]]:
+    """First ``count`` words over ``alphabet`` in shortlex order, starting with the empty word."""
+    out: List[Tuple[int, ...]] = []
+    length = 0
+    while len(out) < count:
+        for w in itertools.product(alphabet, repeat=length):
+            out.append(tuple(w))
+            if len(out) == count:
+                break
+        length += 1
+    return out
+
+
+def _is_power(w: Tuple[int, ...]) -> bool:
+    L = len(w)
+    for p in range(1, L):
+        if L % p == 0 and w == w[:p] * (L // p):
+            return True
+    return False
+
+
+def random_germs(K: int, spec: Sequence[Tuple[int, int]], rng: np.random.Generator) -> List[Tuple[int, ...]]:
+    """Every single-gate word, then ``count`` distinct random words per ``(length, count)`` in ``spec``
+    that are not powers of shorter words."""
+    germs: List[Tuple[int, ...]] = [(k,) for k in range(K)]
+    seen = set(germs)
+    for length, count in spec:
+        pool = [w for w in itertools.product(range(K), repeat=length) if not _is_power(w) and w not in seen]
+        if count > len(pool):
+            raise ValueError(f"only {len(pool)} germs of length {length} exist")
+        pick = rng.choice(len(pool), size=count, replace=False)
+        for i in sorted(pick.tolist()):
+            germs.append(tuple(pool[i]))
+            seen.add(tuple(pool[i]))
+    return germs
+
+
+@dataclasses.dataclass
+class SeqList:
+    offsets: np.ndarray   # int64 [S+1]
+    gates: np.ndarray     # uint8 [sum L]
+    # optional structure labels (p, q, germ, power); -1 for bare sequences
+    labels: Optional[np.ndarray] = None
+
+    @property
+    def S(self) -> int:
+        return len(self.offsets) - 1
+
+    def lengths(self) -> np.ndarray:
+        return np.diff(self.offsets)
+
+    def word(self, s: int) -> np.ndarray:
+        return self.gates[self.offsets[s]:self.offsets[s + 1]]
+
+    def subset(self, idx: np.ndarray) -> "SeqList":
+        idx = np.asarray(idx, dtype=np.int64)
+        lens = self.lengths()[idx]
+        off = np.zeros(len(idx) + 1, dtype=np.int64)
+        np.cumsum(lens, out=off[1:])
+        g = np.concatenate([self.word(int(s)) for s in idx]) if len(idx) else np.zeros(0, np.uint8)
+        lab = self.labels[idx] if self.labels is not None else None
+        return SeqList(off, np.ascontiguousarray(g.astype(np.uint8)), lab)
+
+
+def from_words(words: Sequence[Sequence[int]], labels=None) -> SeqList:
+    lens = np.array([len(w) for w in words], dtype=np.int64)
+    off = np.zeros(len(words) + 1, dtype=np.int64)
+    np.cumsum(lens, out=off[1:])
+    flat = np.fromiter(itertools.chain.from_iterable(words), dtype=np.uint8, count=int(off[-1]))
+    return SeqList(off, flat, None if labels is None else np.asarray(labels))
+
+
+def structured_list(preps, meas, germs, powers) -> SeqList:
+    """Bare ``F_q F_p`` for all (p, q), then ``F_q g^l F_p`` for each germ, power, p, q.
+
+    Words are in time order: ``F_p`` acts first.
+    """
+    words, labels = [], []
+    for ip, fp in enumerate(preps):
+        for iq, fq in enumerate(meas):
+            words.append(tuple(fp) + tuple(fq))
+            labels.append((ip, iq, -1, 0))
+    for ig, g in enumerate(germs):
+        for l in powers:
+            gl = tuple(g) * l
+            for ip, fp in enumerate(preps):
+                for iq, fq in enumerate(meas):
+                    words.append(tuple(fp) + gl + tuple(fq))
+                    labels.append((ip, iq, ig, l))
+    return from_words(words, labels)
+
+
+def random_list(S: int, K: int, lmin: int, lmax: int, rng: np.random.Generator) -> SeqList:
+    lens = rng.integers(lmin, lmax + 1, size=S).astype(np.int64)
+    off = np.zeros(S + 1, dtype=np.int64)
+    np.cumsum(lens, out=off[1:])
+    g = rng.integers(0, K, size=int(off[-1]), dtype=np.uint8)
+    return SeqList(off, g, None)
+
+
+# ---------------------------------------------------------------------------
+# The black box: outcome statistics emulated in Hilbert space
+# ---------------------------------------------------------------------------
+def _device_probs_words(gs: GateSet, sl: SeqList, idx: np.ndarray) -> np.ndarray:
+    """Outcome distribution of the emulated device for the sequences ``idx``.
+
+    The device applies the coherent unitaries to the state vector ``|0..0>``
+    and the global depolarizing channel after every gate; since the latter
+    commutes with unitaries, ``p = 1/d + (1-lam)^L (|<m|U_L..U_1|0>|^2 - 1/d)``
+    (Eq. singletDepolarizingChannelSymmetricMixture).  Sequences are advanced
+    together, one time step at a time.
+    """
+    d = 2 ** gs.n_qubits
+    lens = sl.lengths()[idx]
+    psi = np.zeros((len(idx), d), dtype=np.complex128)
+    psi[:, 0] = 1.0
+    order = np.argsort(-lens, kind="stable")
+    Ls = lens[order]
+    starts = sl.offsets[idx][order]
+    U = gs.unitaries
+    for t in range(int(Ls.max()) if len(Ls) else 0):
+        active = int(np.searchsorted(-Ls, -t, side="left"))  # sequences with L > t
+        active = int(np.sum(Ls > t))
+        g = sl.gates[starts[:active] + t]
+        psi[order[:active]] = np.einsum("sab,sb->sa", U[g], psi[order[:active]])
+    pc = np.abs(psi) ** 2
+    f = (1.0 - gs.lam) ** lens.astype(np.float64)
+    return 1.0 / d + f[:, None] * (pc - 1.0 / d)
+
+
+def device_probs_structured(gs: GateSet, preps, meas, germs, powers, sl: SeqList) -> np.ndarray:
+    """Same emulation, using the fiducial/germ structure to multiply unitaries once."""
+    d = 2 ** gs.n_qubits
+    U = gs.unitaries
+
+    def word_u(w):
+        m = np.eye(d, dtype=np.complex128)
+        for k in w:
+            m = U[k] @ m
+        return m
+
+    Up = [word_u(w) for w in preps]
+    Uq = [word_u(w) for w in meas]
+    out = np.empty((sl.S, d))
+    lens = sl.lengths().astype(np.float64)
+    lab = sl.labels
+    e0 = np.zeros(d, dtype=np.complex128)
+    e0[0] = 1
+    cache: Dict[Tuple[int, int], np.ndarray] = {}
+    for s in range(sl.S):
+        ip, iq, ig, l = lab[s]
+        if ig < 0:
+            M = Uq[iq] @ Up[ip]
+        else:
+            key = (int(ig), int(l))
+            if key not in cache:
+                gu = word_u(germs[ig])
+                cache[key] = np.linalg.matrix_power(gu, int(l))
+            M = Uq[iq] @ cache[key] @ Up[ip]
+        amp = M @ e0
+        out[s] = np.abs(amp) ** 2
+    f = (1.0 - gs.lam) ** lens
+    return 1.0 / d + f[:, None] * (out - 1.0 / d)
+
+
+def sample_counts(p: np.ndarray, n_shots: int, rng: np.random.Generator) -> np.ndarray:
+    p = np.clip(p, 0.0, None)
+    p = p / p.sum(axis=1, keepdims=True)
+    return rng.multinomial(n_shots, p).astype(np.int32)
+
+
+# ---------------------------------------------------------------------------
+# Named workloads
+# ---------------------------------------------------------------------------
+MASTER_SEEDS = {"c1": 2008134901, "c2": 2008134902, "c3": 2008134903, "c4": 2008134904, "c5": 2008134905}
+LAMBDA = 1e-3
+SIGMA = 0.01
+N_SHOTS = 1000
+
+
+@dataclasses.dataclass
+class Workload:
+    name: str
+    truth: GateSet     # generates the counts
+    model: GateSet     # the evaluation point (over-rotations redrawn, same lambda)
+    seqs: SeqList
+    counts: np.ndarray  # int32 [S, M]
+
+    @property
+    def n_qubits(self) -> int:
+        return self.model.n_qubits
+
+
+def _streams(name: str, n: int = 6):
+    ss = np.random.SeedSequence(MASTER_SEEDS[name])
+    return [np.random.default_rng(s) for s in ss.spawn(n)]
+
+
+_STRUCTURED = {
+    # kind, fiducial alphabet, number of fiducials, germ spec, powers
+    "c1": ("1q", (1, 2), 6, [(3, 1)], [1, 2, 4, 8, 16, 32, 64]),
+    "c2": ("2q", (1, 2, 3, 4), 11, [(2, 3), (3, 3)], [1, 2, 4, 8, 16, 32, 64, 128, 256]),
+    "c4": ("3q", (1, 2), 16, [(2, 20), (3, 73)], [1, 2, 4, 8, 16, 32, 64, 128]),
+}
+
+
+def structured_workload(name: str) -> Workload:
+    """C1 (1 qubit), C2 (2 qubits) or C4 (3 qubits): fiducial x germ-power x fiducial lists."""
+    kind, alpha, nf, spec, powers = _STRUCTURED[name]
+    r_rot, r_germ, r_cnt, r_pert, _, _ = _streams(name)
+    truth = noisy_gateset(kind, LAMBDA, SIGMA, r_rot)
+    model = noisy_gateset(kind, LAMBDA, SIGMA, r_pert)
+    fids = shortlex_words(alpha, nf)
+    germs = random_germs(truth.K, spec, r_germ)
+    sl = structured_list(fids, fids, germs, powers)
+    p = device_probs_structured(truth, fids, fids, germs, powers, sl)
+    counts = sample_counts(p, N_SHOTS, r_cnt)
+    return Workload(name, truth, model, sl, counts)
+
+
+def random_workload(kind: str, S: int, lmax: int, seed: int, lmin: int = 1) -> Workload:
+    """Random words over the gate set of ``kind``, lengths uniform in ``lmin..lmax``."""
+    ss = np.random.SeedSequence(seed)
+    r_rot, r_seq, r_cnt, r_pert = [np.random.default_rng(s) for s in ss.spawn(4)]
+    truth = noisy_gateset(kind, LAMBDA, SIGMA, r_rot)
+    model = noisy_gateset(kind, LAMBDA, SIGMA, r_pert)
+    sl = random_list(S, truth.K, lmin, lmax, r_seq)
+    p = _device_probs_words(truth, sl, np.arange(S))
+    counts = sample_counts(p, N_SHOTS, r_cnt)
+    return Workload(f"random-{kind}-S{S}-L{lmax}-seed{seed}", truth, model, sl, counts)
+
+
+def c3_plan(n_sets: int = 512, seed: Optional[int] = None):
+    """Uneven batch: per gate set (kind, S, seed).  70% one-qubit, 30% two-qubit
+    (a seeded permutation), ``S ~ U{500..20000}``, lengths ``U{1..1024}``."""
+    rng = np.random.default_rng(np.random.SeedSequence(MASTER_SEEDS["c3"] if seed is None else seed).spawn(5)[4])
+    n1 = int(round(0.7 * n_sets))
+    kinds = np.array(["1q"] * n1 + ["2q"] * (n_sets - n1))
+    kinds = kinds[rng.permutation(n_sets)]
+    S = rng.integers(500, 20001, size=n_sets)
+    seeds = rng.integers(1, 2 ** 62, size=n_sets)
+    return [(str(k), int(s), int(sd)) for k, s, sd in zip(kinds, S, seeds)]
+
+
+def pack_params(gs: GateSet) -> np.ndarray:
+    """Full parameter vector in gradient layout ``[rho (D) | E (M*D) | G (K*D*D)]``."""
+    return np.concatenate([gs.rho.ravel(), gs.effects.ravel(), gs.gates.ravel()])
+
+
+def unpack_params(theta: np.ndarray, n_qubits: int, M: int, K: int):
+    D = 4 ** n_qubits
+    rho = theta[:D]
+    E = theta[D:D + M * D].reshape(M, D)
+    G = theta[D + M * D:].reshape(K, D, D)
+    return rho, E, G

@@ -1,0 +1,482 @@
+"""Pins for the CPU oracle: values and identities fixed by the thesis or by mathematics.
+
+None of these checks re-types the oracle's own formula.  They compare the
+oracle (transfer matrices, right-to-left products, chain rule) with
+independent routes: printed matrices and distributions, Hilbert-space
+state-vector and Kraus simulations, closed forms, invariants and brute-force
+multilinear derivatives.
+"""
+import itertools
+import os
+
+import numpy as np
+import pytest
+
+from paper_2008_13490_amd import workloads as W
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+U_ROUND = 2.0 ** -53
+
+
+# ---------------------------------------------------------------------------
+# independent helpers (Hilbert space, no transfer matrices)
+# ---------------------------------------------------------------------------
+def haar_unitary(rng, d):
+    z = (rng.standard_normal((d, d)) + 1j * rng.standard_normal((d, d))) / np.sqrt(2)
+    q, r = np.linalg.qr(z)
+    return q * (np.diag(r) / np.abs(np.diag(r)))
+
+
+def random_kraus(rng, d, rank):
+    """Kraus operators of a random CPTP map from a Stinespring dilation (Sec. 2.4.2):
+    a unitary on system x environment, environment starting in |e_0>."""
+    V = haar_unitary(rng, d * rank)
+    # E_a = (1 x <e_a|) V (1 x |e_0>), environment is the second (fast) factor
+    V4 = V.reshape(d, rank, d, rank)
+    return [np.ascontiguousarray(V4[:, a, :, 0]) for a in range(rank)]
+
+
+def random_density(rng, d):
+    A = rng.standard_normal((d, d)) + 1j * rng.standard_normal((d, d))
+    rho = A @ A.conj().T
+    return rho / np.trace(rho).real
+
+
+def random_povm(rng, d, m):
+    """m positive operators summing to the identity."""
+    As = [rng.standard_normal((d, d)) + 1j * rng.standard_normal((d, d)) for _ in range(m)]
+    Ps = [a @ a.conj().T for a in As]
+    S = sum(Ps)
+    w, V = np.linalg.eigh(S)
+    Sm = (V * w ** -0.5) @ V.conj().T
+    return [Sm @ p @ Sm for p in Ps]
+
+
+def kraus_probs(kraus_list, word, rho, povm):
+    """Tr(E_m  Phi_{s_L}( ... Phi_{s_1}(rho))) with density matrices only."""
+    r = rho.copy()
+    for k in word:
+        r = sum(K @ r @ K.conj().T for K in kraus_list[k])
+    return np.array([np.trace(E @ r).real for E in povm])
+
+
+def statevector_probs(unitaries, word, d):
+    psi = np.zeros(d, complex)
+    psi[0] = 1
+    for k in word:
+        psi = unitaries[k] @ psi
+    return np.abs(psi) ** 2
+
+
+def ideal_spam(n):
+    d = 2 ** n
+    rho = W.vec_operator(np.diag(np.eye(d)[0]).astype(complex))
+    E = np.array([W.vec_operator(np.diag(np.eye(d)[m]).astype(complex)) for m in range(d)])
+    return rho, E
+
+
+def csr(words):
+    sl = W.from_words(words)
+    return sl.offsets, sl.gates
+
+
+# ---------------------------------------------------------------------------
+# P1: printed values
+# ---------------------------------------------------------------------------
+def test_parameter_count_matches_thesis(oracle_lib):
+    vals = {}
+    for line in open(os.path.join(GOLDEN, "gst_param_count.txt")):
+        if line.startswith("#") or not line.strip():
+            continue
+        k, v = line.split()
+        vals[k] = int(v)
+    rng = np.random.default_rng(0)
+    gs = W.noisy_gateset("2q", 1e-3, 0.01, rng)
+    assert (gs.n_qubits, gs.M, gs.K) == (vals["n_qubits"], vals["n_outcomes"], vals["n_gates"])
+    assert gs.n_params() == vals["n_params"]
+    off, g = csr([(0, 1, 5)])
+    _, _, grad, _, _ = oracle_lib.loglik(gs.rho, gs.effects, gs.gates, off, g, np.array([[1, 2, 3, 4]]))
+    assert grad.shape == (vals["n_params"],)
+
+
+def test_pauli_index_order():
+    """P_1 = I x sigma^x (Eq. paulibasis); Z x Z is index 15 for two qubits (Sec. 6.3.3)."""
+    P = W.pauli_basis(2)
+    assert np.allclose(P[1], np.kron(W._I2, W._SX))
+    assert np.allclose(P[4], np.kron(W._SX, W._I2))
+    assert np.allclose(P[15], np.kron(W._SZ, W._SZ))
+    n = 3
+    P3 = W.pauli_basis(n)
+    assert np.allclose(P3[1 * 16 + 2 * 4 + 3], np.kron(np.kron(W._SX, W._SY), W._SZ))
+    # orthogonality Tr P_i P_j = N delta_ij
+    gram = np.einsum("iab,jba->ij", P3, P3)
+    assert np.allclose(gram, 8 * np.eye(64))
+
+
+def test_ptm_properties():
+    """Real entries in [-1,1], TP row, unital column, Clifford = signed permutation,
+    composition = matrix product (Sec. 2.4.1)."""
+    h = np.pi / 2
+    for U in [W.rx(h), W.ry(h), W.on_qubit(W.rx(h), 1, 2), W.cz(0, 1, 2), W.cnot(0, 1, 2)]:
+        G = W.ptm_from_unitary(U)
+        assert np.allclose(G[0], np.eye(len(G))[0])
+        assert np.allclose(G[:, 0], np.eye(len(G))[0])
+        assert np.all(np.abs(G) <= 1 + 1e-12)
+        nz = np.abs(G) > 1e-12
+        assert np.all(nz.sum(0) == 1) and np.all(nz.sum(1) == 1)
+        assert np.allclose(np.abs(G[nz]), 1)
+    rng = np.random.default_rng(1)
+    U1, U2 = haar_unitary(rng, 4), haar_unitary(rng, 4)
+    assert np.allclose(W.ptm_from_unitary(U1 @ U2), W.ptm_from_unitary(U1) @ W.ptm_from_unitary(U2), atol=1e-13)
+
+
+def _qft_gates():
+    """Elementary gates of the printed QFT2 decomposition (Eq. twoqubitqft)."""
+    H = np.array([[1, 1], [1, -1]], complex) / np.sqrt(2)
+    T = np.diag([1, np.exp(0.25j * np.pi)])
+    S = np.diag([1, 1j])
+    names = ["CNOT01", "CNOT10", "H1", "T1", "S0", "Tdag0", "H0", "X0", "X1", "V"]
+    X = np.array([[0, 1], [1, 0]], complex)
+    V = np.kron(H, W.ry(0.7))  # a fixed non-diagonal basis change for the measurement
+    Us = [W.cnot(0, 1, 2), W.cnot(1, 0, 2), W.on_qubit(H, 1, 2), W.on_qubit(T, 1, 2), W.on_qubit(S, 0, 2),
+          W.on_qubit(T.conj().T, 0, 2), W.on_qubit(H, 0, 2), W.on_qubit(X, 0, 2), W.on_qubit(X, 1, 2), V]
+    return names, Us
+
+
+def test_qft2_printed_matrix(oracle_lib):
+    """The oracle's chain over the eleven-gate decomposition reproduces the distribution of
+    the printed QFT2 matrix, for every computational input state and a measurement basis that
+    makes the phases of the printed matrix visible."""
+    rows = [l.split() for l in open(os.path.join(GOLDEN, "qft2_matrix.txt")) if l.strip() and not l.startswith("#")]
+    Q = np.array([[float(r[2 * c]) + 1j * float(r[2 * c + 1]) for c in range(4)] for r in rows]) / 2
+    names, Us = _qft_gates()
+    idx = {n: i for i, n in enumerate(names)}
+    G = np.array([W.ptm_from_unitary(U) for U in Us])
+    rho, E = ideal_spam(2)
+    # time order: the rightmost factor of the printed product acts first
+    qft_time = ["H0", "Tdag0", "CNOT10", "Tdag0", "CNOT10", "S0", "T1", "H1", "CNOT01", "CNOT10", "CNOT01"]
+    words, expected = [], []
+    V = Us[idx["V"]]
+    for J in range(4):
+        prep = ([idx["X0"]] if J & 2 else []) + ([idx["X1"]] if J & 1 else [])
+        words.append(prep + [idx[n] for n in qft_time] + [idx["V"]])
+        expected.append(np.abs(V @ Q[:, J]) ** 2)
+    off, g = csr(words)
+    p = oracle_lib.probs(rho, E, G, off, g)
+    assert np.allclose(p, np.array(expected), atol=1e-14)
+
+
+def test_cz_identity(oracle_lib):
+    """CZ = H_2 CNOT_12 H_2 (Sec. 7.3.1) as a transfer-matrix chain."""
+    H = np.array([[1, 1], [1, -1]], complex) / np.sqrt(2)
+    Us = [W.on_qubit(H, 1, 2), W.cnot(0, 1, 2), W.cz(0, 1, 2), W.on_qubit(W.ry(0.3), 0, 2), W.on_qubit(W.rx(1.1), 1, 2)]
+    G = np.array([W.ptm_from_unitary(U) for U in Us])
+    rho, E = ideal_spam(2)
+    off, g = csr([(3, 4, 0, 1, 0), (3, 4, 2)])
+    p = oracle_lib.probs(rho, E, G, off, g)
+    assert np.allclose(p[0], p[1], atol=1e-15)
+    # and the transfer matrices compose to the same map
+    assert np.allclose(G[0] @ G[1] @ G[0], G[2], atol=1e-14)
+
+
+def test_gst_preparation_sequences(oracle_lib):
+    """The four preparation words of Sec. 6.3.3 give |00>, |10>, |++> and the singlet."""
+    h = np.pi / 2
+    names = ["XI", "YI", "IX", "IY", "II", "CNOT"]
+    Us = [W.on_qubit(W.rx(h), 0, 2), W.on_qubit(W.ry(h), 0, 2), W.on_qubit(W.rx(h), 1, 2),
+          W.on_qubit(W.ry(h), 1, 2), np.eye(4, dtype=complex), W.cnot(0, 1, 2)]
+    G = np.array([W.ptm_from_unitary(U) for U in Us])
+    rho, E = ideal_spam(2)
+    words, expected = [], []
+    for line in open(os.path.join(GOLDEN, "gst_prep_states.txt")):
+        if line.startswith("#") or not line.strip():
+            continue
+        _, word, probs = [x.strip() for x in line.split("|")]
+        words.append([names.index(w) for w in word.split()])
+        expected.append([float(x) for x in probs.split()])
+    off, g = csr(words)
+    p = oracle_lib.probs(rho, E, G, off, g)
+    assert np.allclose(p, np.array(expected), atol=1e-15)
+
+
+def test_singlet_measurement_distribution(oracle_lib):
+    """p(j0 j1 | t0 t1) = (1 - (-1)^(j0+j1) cos(t1 - t0)) / 4 (Eq. singletProgramGatesResult),
+    singlet prepared as CNOT_01 H_0 X_0 X_1 |00>, measured after H U1(t) H on each qubit."""
+    H = np.array([[1, 1], [1, -1]], complex) / np.sqrt(2)
+    X = np.array([[0, 1], [1, 0]], complex)
+    rho, E = ideal_spam(2)
+    rng = np.random.default_rng(7)
+    for _ in range(5):
+        t0, t1 = rng.uniform(0, 2 * np.pi, 2)
+        u1 = lambda t: np.diag([1, np.exp(1j * t)])
+        Us = [W.on_qubit(X, 0, 2), W.on_qubit(X, 1, 2), W.on_qubit(H, 0, 2), W.cnot(0, 1, 2),
+              W.on_qubit(H @ u1(t0) @ H, 0, 2), W.on_qubit(H @ u1(t1) @ H, 1, 2)]
+        G = np.array([W.ptm_from_unitary(U) for U in Us])
+        off, g = csr([(0, 1, 2, 3, 4, 5)])
+        p = oracle_lib.probs(rho, E, G, off, g)[0]
+        want = [(1 - (-1) ** (j0 + j1) * np.cos(t1 - t0)) / 4 for j0 in (0, 1) for j1 in (0, 1)]
+        assert np.allclose(p, want, atol=1e-14)
+
+
+# ---------------------------------------------------------------------------
+# P2 / P3: closed forms and textbook special cases
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("kind", ["1q", "2q", "3q"])
+def test_depolarizing_closed_form(oracle_lib, kind):
+    """Ideal Clifford gates with lambda-depolarizing: p = 1/d + (1-lambda)^L (p_ideal - 1/d),
+    p_ideal from a state-vector simulation (Eq. singletDepolarizingChannelSymmetricMixture)."""
+    names, Us, n = W.ideal_unitaries(kind)
+    d = 2 ** n
+    lam = 1e-3
+    G = np.array([W.depolarizing_ptm(lam, n) @ W.ptm_from_unitary(U) for U in Us])
+    rho, E = ideal_spam(n)
+    rng = np.random.default_rng(11)
+    words = [[]] + [list(rng.integers(0, len(Us), size=L)) for L in (1, 2, 3, 7, 64, 200, 800 if n < 3 else 300)]
+    off, g = csr(words)
+    p = oracle_lib.probs(rho, E, G, off, g)
+    for s, w in enumerate(words):
+        pid = statevector_probs(Us, w, d)
+        want = 1 / d + (1 - lam) ** len(w) * (pid - 1 / d)
+        assert np.allclose(p[s], want, atol=5e-14), (s, len(w))
+    assert abs((1 - 1e-3) ** 800 - 0.449149) < 1e-6
+
+
+def test_pauli_and_amplitude_damping_channels(oracle_lib):
+    """Pauli channel (Eq. singletDepolarizingChannel) has PTM diag(1, 1-2(py+pz), 1-2(px+pz), 1-2(px+py));
+    generalized amplitude damping (Eqs. singletAmplitudeDampingChannel1/2) is non-unital.
+    The oracle chain agrees with a Kraus density-matrix simulation."""
+    px, py, pz = 0.01, 0.02, 0.03
+    I2, X, Y, Z = W.PAULI_1Q
+    kr_dep = [np.sqrt(1 - px - py - pz) * I2, np.sqrt(px) * X, np.sqrt(py) * Y, np.sqrt(pz) * Z]
+    Gdep = W.ptm_from_kraus(kr_dep)
+    assert np.allclose(Gdep, np.diag([1, 1 - 2 * (py + pz), 1 - 2 * (px + pz), 1 - 2 * (px + py)]), atol=1e-15)
+    p, gam = 0.8, 0.05
+    kr_amp = [np.sqrt(p) * np.array([[1, 0], [0, np.sqrt(1 - gam)]]), np.sqrt(p) * np.array([[0, np.sqrt(gam)], [0, 0]]),
+              np.sqrt(1 - p) * np.array([[np.sqrt(1 - gam), 0], [0, 1]]), np.sqrt(1 - p) * np.array([[0, 0], [np.sqrt(gam), 0]])]
+    kr_amp = [k.astype(complex) for k in kr_amp]
+    Gamp = W.ptm_from_kraus(kr_amp)
+    assert np.allclose(Gamp[0], [1, 0, 0, 0]) and not np.allclose(Gamp[:, 0], [1, 0, 0, 0])
+    kr_x = [W.rx(np.pi / 2)]
+    kraus = [kr_dep, kr_amp, kr_x]
+    G = np.array([Gdep, Gamp, W.ptm_from_kraus(kr_x)])
+    rho_m = random_density(np.random.default_rng(3), 2)
+    povm = random_povm(np.random.default_rng(4), 2, 3)
+    rho = W.vec_operator(rho_m)
+    E = np.array([W.vec_operator(e) for e in povm])
+    rng = np.random.default_rng(5)
+    words = [list(rng.integers(0, 3, size=L)) for L in range(0, 13)]
+    off, g = csr(words)
+    pr = oracle_lib.probs(rho, E, G, off, g)
+    for s, w in enumerate(words):
+        assert np.allclose(pr[s], kraus_probs(kraus, w, rho_m, povm), atol=1e-14)
+
+
+@pytest.mark.parametrize("n", [1, 2])
+def test_random_cptp_against_kraus_simulation(oracle_lib, n):
+    """Random Stinespring gates, random state and POVM; lengths up to 12."""
+    d = 2 ** n
+    rng = np.random.default_rng(100 + n)
+    K = 4
+    kraus = [random_kraus(rng, d, rank=1 + (k % 3)) for k in range(K)]
+    G = np.array([W.ptm_from_kraus(k) for k in kraus])
+    rho_m = random_density(rng, d)
+    povm = random_povm(rng, d, d + 1)
+    rho = W.vec_operator(rho_m)
+    E = np.array([W.vec_operator(e) for e in povm])
+    words = [list(rng.integers(0, K, size=L)) for L in range(0, 13) for _ in range(3)]
+    off, g = csr(words)
+    p = oracle_lib.probs(rho, E, G, off, g)
+    for s, w in enumerate(words):
+        assert np.allclose(p[s], kraus_probs(kraus, w, rho_m, povm), atol=2e-14)
+    # invariants: POVM completeness + TP => sum_m p = 1 ; CPTP => p >= -O(L D u)
+    assert np.allclose(p.sum(1), 1.0, atol=1e-13)
+    assert p.min() > -1e-13
+
+
+def test_device_emulator_agrees(oracle_lib):
+    """The Hilbert-space black box that samples the counts and the oracle agree at the true model."""
+    w = W.structured_workload("c1")
+    t = w.truth
+    p = oracle_lib.probs(t.rho, t.effects, t.gates, w.seqs.offsets, w.seqs.gates)
+    kind, alpha, nf, spec, powers = W._STRUCTURED["c1"]
+    fids = W.shortlex_words(alpha, nf)
+    germs = W.random_germs(t.K, spec, W._streams("c1")[1])
+    pd = W.device_probs_structured(t, fids, fids, germs, powers, w.seqs)
+    assert np.allclose(p, pd, atol=1e-13)
+    pw = W._device_probs_words(t, w.seqs, np.arange(0, w.seqs.S, 7))
+    assert np.allclose(p[::7], pw, atol=1e-13)
+
+
+def test_extended_precision_bound(oracle_lib):
+    """binary64 oracle vs the extended-precision rerun: difference within the forward error
+    bound of a length-L chain of D-term dot products."""
+    w = W.structured_workload("c2")
+    m = w.model
+    sub = w.seqs.subset(np.arange(0, w.seqs.S, 13))
+    p = oracle_lib.probs(m.rho, m.effects, m.gates, sub.offsets, sub.gates)
+    px = oracle_lib.probs_extended(m.rho, m.effects, m.gates, sub.offsets, sub.gates)
+    L = sub.lengths()
+    D = 16
+    bound = (L[:, None] + 1) * D * U_ROUND * 4 + 1e-300
+    assert np.all(np.abs(p - px) <= bound)
+
+
+# ---------------------------------------------------------------------------
+# P4: gauge and Euler invariants of the objective and gradient
+# ---------------------------------------------------------------------------
+def _small_problem(rng, n=1, K=3, S=40, Lmax=9):
+    d = 2 ** n
+    kraus = [random_kraus(rng, d, rank=2) for _ in range(K)]
+    G = np.array([W.ptm_from_kraus(k) for k in kraus])
+    rho = W.vec_operator(random_density(rng, d))
+    E = np.array([W.vec_operator(e) for e in random_povm(rng, d, d)])
+    words = [list(rng.integers(0, K, size=int(rng.integers(0, Lmax + 1)))) for _ in range(S)]
+    off, g = csr(words)
+    N = rng.integers(0, 50, size=(S, d)).astype(np.int32)
+    N[0, 0] = 0
+    return rho, E, G, off, g, N, words
+
+
+def test_gauge_invariance_and_covariance(oracle_lib):
+    """p(E M^-1, M G M^-1, M rho) = p(theta) (Sec. 6.3.1); the gradient transforms covariantly:
+    dF/dG' = M^-T dF/dG M^T, dF/drho' = M^-T dF/drho, dF/dE' = dF/dE M^T."""
+    rng = np.random.default_rng(21)
+    rho, E, G, off, g, N, _ = _small_problem(rng, n=2, K=3, S=30, Lmax=6)
+    Mg = np.eye(16) + 0.1 * rng.standard_normal((16, 16))
+    Mi = np.linalg.inv(Mg)
+    G2 = np.einsum("ab,kbc,cd->kad", Mg, G, Mi)
+    rho2, E2 = Mg @ rho, E @ Mi
+    F1, p1, g1, _, _ = oracle_lib.loglik(rho, E, G, off, g, N)
+    F2, p2, g2, _, _ = oracle_lib.loglik(rho2, E2, G2, off, g, N)
+    assert np.allclose(p1, p2, atol=1e-12)
+    assert abs(F1 - F2) <= 1e-10 * abs(F1)
+    r1, e1, gg1 = W.unpack_params(g1, 2, 4, 3)
+    r2, e2, gg2 = W.unpack_params(g2, 2, 4, 3)
+    assert np.allclose(r2, Mi.T @ r1, rtol=1e-8, atol=1e-8 * np.abs(r1).max())
+    assert np.allclose(e2, e1 @ Mg.T, rtol=1e-8, atol=1e-8 * np.abs(e1).max())
+    want = np.einsum("ab,kbc,cd->kad", Mi.T, gg1, Mg.T)
+    assert np.allclose(gg2, want, rtol=1e-8, atol=1e-8 * np.abs(gg1).max())
+
+
+def test_euler_identities(oracle_lib):
+    """p is linear in rho, in each e_m and in each occurrence of G_k, so with F = -sum N log p:
+    rho . dF/drho = -sum N ; e_m . dF/de_m = -sum_s N_sm ; <G_k, dF/dG_k> = -sum_s n_k(s) sum_m N_sm."""
+    rng = np.random.default_rng(22)
+    rho, E, G, off, g, N, words = _small_problem(rng, n=2, K=4, S=60, Lmax=10)
+    F, p, grad, _, _ = oracle_lib.loglik(rho, E, G, off, g, N)
+    gr, gE, gG = W.unpack_params(grad, 2, 4, 4)
+    tot = N.sum()
+    assert np.isclose(rho @ gr, -tot, rtol=1e-12)
+    assert np.allclose(np.einsum("mj,mj->m", E, gE), -N.sum(0), rtol=1e-12)
+    occ = np.array([[w.count(k) for k in range(4)] for w in words])
+    want = -(occ * N.sum(1)[:, None]).sum(0)
+    assert np.allclose(np.einsum("kij,kij->k", G, gG), want, rtol=1e-11)
+
+
+# ---------------------------------------------------------------------------
+# P5: brute-force multilinear derivatives and finite differences
+# ---------------------------------------------------------------------------
+def _brute_dp(rho, E, G, word):
+    """dp_m/dtheta for one word by multilinearity: every occurrence of a gate contributes
+    e^T G_L .. G_{t+1} E^(ij) G_{t-1} .. G_1 rho."""
+    D = len(rho)
+    M = E.shape[0]
+    K = G.shape[0]
+    L = len(word)
+
+    def prod(a, b):  # G_{s_b} ... G_{s_{a+1}}  (time steps a+1..b)
+        P = np.eye(D)
+        for t in range(a, b):
+            P = G[word[t]] @ P
+        return P
+
+    full = prod(0, L)
+    f = full @ rho
+    d_rho = np.array([E[m] @ full for m in range(M)])          # [M, D]
+    d_E = np.zeros((M, M, D))
+    for m in range(M):
+        d_E[m, m] = f
+    d_G = np.zeros((M, K, D, D))
+    for t in range(L):
+        before = prod(0, t) @ rho
+        after = prod(t + 1, L)
+        for m in range(M):
+            d_G[m, word[t]] += np.outer(E[m] @ after, before)
+    return np.concatenate([d_rho, d_E.reshape(M, -1), d_G.reshape(M, -1)], axis=1)
+
+
+def test_bruteforce_gradient(oracle_lib):
+    rng = np.random.default_rng(23)
+    for n in (1, 2):
+        rho, E, G, off, g, N, words = _small_problem(rng, n=n, K=3, S=12, Lmax=5)
+        F, p, grad, _, _ = oracle_lib.loglik(rho, E, G, off, g, N)
+        want = np.zeros_like(grad)
+        for s, w in enumerate(words):
+            dp = _brute_dp(rho, E, G, w)
+            for m in range(E.shape[0]):
+                if N[s, m] > 0:
+                    want -= N[s, m] / p[s, m] * dp[m]
+        assert np.allclose(grad, want, rtol=1e-11, atol=1e-11 * np.abs(want).max())
+        # vector-Jacobian product with an arbitrary upstream weight
+        Wt = rng.standard_normal(p.shape)
+        gv = oracle_lib.vjp(rho, E, G, off, g, Wt)
+        want = sum(Wt[s] @ _brute_dp(rho, E, G, w) for s, w in enumerate(words))
+        assert np.allclose(gv, want, rtol=1e-11, atol=1e-11 * np.abs(want).max())
+
+
+def test_central_finite_differences(oracle_lib):
+    """Central differences with h = 1e-6 on random coordinates and random directions."""
+    rng = np.random.default_rng(24)
+    for trial in range(3):
+        n = 1 + trial % 2
+        rho, E, G, off, g, N, _ = _small_problem(rng, n=n, K=3, S=25, Lmax=8)
+        M, K = E.shape[0], G.shape[0]
+        theta = np.concatenate([rho, E.ravel(), G.ravel()])
+        F0, _, grad, _, _ = oracle_lib.loglik(rho, E, G, off, g, N)
+
+        def F(th):
+            r, e, gg = W.unpack_params(th, n, M, K)
+            return oracle_lib.loglik(r, e, gg, off, g, N, want_grad=False)[0]
+
+        h = 1e-6
+        for c in rng.choice(len(theta), size=20, replace=False):
+            t1, t2 = theta.copy(), theta.copy()
+            t1[c] += h
+            t2[c] -= h
+            fd = (F(t1) - F(t2)) / (2 * h)
+            assert abs(fd - grad[c]) <= 1e-6 * max(1.0, np.abs(grad).max())
+        v = rng.standard_normal(len(theta))
+        fd = (F(theta + h * v) - F(theta - h * v)) / (2 * h)
+        assert abs(fd - grad @ v) <= 1e-6 * max(1.0, abs(grad @ v), np.abs(grad).max())
+
+
+# ---------------------------------------------------------------------------
+# edge cases and error behaviour
+# ---------------------------------------------------------------------------
+def test_edge_cases(oracle_lib):
+    rng = np.random.default_rng(25)
+    rho, E, G, off, g, N, words = _small_problem(rng, n=1, K=2, S=5, Lmax=3)
+    # empty list
+    p = oracle_lib.probs(rho, E, G, np.zeros(1, np.int64), np.zeros(0, np.uint8))
+    assert p.shape == (0, 2)
+    F, _, grad, _, _ = oracle_lib.loglik(rho, E, G, np.zeros(1, np.int64), np.zeros(0, np.uint8), np.zeros((0, 2)))
+    assert F == 0.0 and np.all(grad == 0)
+    # empty sequence: p = E rho
+    p = oracle_lib.probs(rho, E, G, np.array([0, 0]), np.zeros(0, np.uint8))
+    assert np.allclose(p[0], E @ rho, atol=1e-16)
+    # gate index out of range
+    with pytest.raises(oracle_lib.OracleError) as ei:
+        oracle_lib.probs(rho, E, G, np.array([0, 2]), np.array([0, 2], np.uint8))
+    assert ei.value.code == -2
+    # p <= 0 with N > 0: objective +inf and the offending entries are counted
+    Ez = E.copy()
+    Ez[1] = 0.0
+    F, p, _, nbad, rc = oracle_lib.loglik(rho, Ez, G, off, g, np.ones((5, 2), np.int32), raise_nonpos=False)
+    assert rc == -3 and nbad == 5 and F == np.inf
+    # zero counts never contribute, even where p = 0
+    Nz = np.zeros((5, 2), np.int32)
+    Nz[:, 0] = 3
+    F, p, grad, nbad, rc = oracle_lib.loglik(rho, Ez, G, off, g, Nz)
+    assert rc == 0 and np.isfinite(F)
+    _, gE, _ = W.unpack_params(grad, 1, 2, 2)
+    assert np.all(gE[1] == 0.0) and np.any(gE[0] != 0.0)  # dF/de_1 is exactly zero
