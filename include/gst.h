@@ -1,0 +1,155 @@
+/*
+ * gst.h -- C ABI of the MI355X gate-set-tomography likelihood library.
+ *
+ * The library evaluates, for a gate set of Pauli-transfer matrices and a list
+ * of gate sequences (thesis Sec. 6.3.1, Eqs. GSTBornRuleVectorized and
+ * GSTFullFiducialsGerms):
+ *
+ *   p[s][m] = e_m^T G[s_L] ... G[s_1] rho          outcome probabilities
+ *   F       = - sum_{s,m: N[s][m] > 0} N[s][m] log p[s][m]
+ *                                                   negative multinomial log-likelihood
+ *                                                   of the outcome counts (the data-only
+ *                                                   multinomial constant is dropped and
+ *                                                   0 log 0 := 0)
+ *   dF/dtheta                                       gradient with respect to every entry of
+ *                                                   rho, of each e_m and of each G_k
+ *
+ * These are the three quantities of the black-box problem of Sec. 6.3.1: a state
+ * (INIT), gates (buttons), a measurement (MEAS) and the counts of each outcome.
+ *
+ * Numbers and layouts (all IEEE binary64 unless stated):
+ *   n_qubits n in 1..3, d = 2^n, D = d*d = 4^n.
+ *   Pauli index i = sum_q a_q 4^(n-1-q), a in {I:0, X:1, Y:2, Z:3}, qubit 0 the
+ *     leftmost tensor factor (Eq. paulibasis); basis normalized by 1/sqrt(d).
+ *   rho[D]; effects[M][D], row m = e_m; gates[K][D][D] row-major,
+ *     gates[k][i][j] = Tr(P_i G_k(P_j))/d (Eq. paulitransfermatrix).
+ *   Sequences in CSR form: offsets[S+1] (int64, offsets[0] = 0, non-decreasing),
+ *     gate_idx[offsets[S]] (uint8, time order: gate_idx[offsets[s]] acts first;
+ *     Sec. 2.2.2: the matrix product is the reverse of time order). Empty
+ *     sequences are allowed.
+ *   counts[S][M] int32 >= 0; probs[S][M]; dLoss/dp weights w[S][M].
+ *   Gradient layout: [rho (D) | effects (M*D) | gates (K*D*D)], D + M*D + K*D*D
+ *     doubles (1616 for two qubits with M = 4, K = 6, the count of Sec. 6.3.1).
+ *
+ * Memory and ownership: unless a name ends in _host, every pointer is a DEVICE
+ * pointer on the context's device, owned by the caller; inputs must stay valid
+ * and unmodified until the stream reaches the call, outputs are written in
+ * stream order.  The library owns contexts, requests and their workspaces.
+ *
+ * Streams and errors: calls are enqueued on the stream given to gst_create and
+ * return immediately.  Argument errors detectable on the host are returned at
+ * once (negative gst_status) and nothing is enqueued.  Data-dependent errors
+ * (a gate index >= K, a probability <= 0 where the count is > 0) are recorded
+ * on the device and reported by gst_sync.  For GST_ENONPOS the objective is
+ * written as +inf and the gradient output is left untouched.
+ *
+ * Probabilities are computed with one fused multiply-add per term, in ascending
+ * column order from zero, exactly like the plain definition of the product;
+ * objective and gradient are sums whose order differs from a sequential loop.
+ * Results do not depend on what else runs on the device.
+ *
+ * Thread safety: a context must not be used by two host threads at once.
+ */
+#ifndef GST_H_
+#define GST_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum gst_status {
+  GST_OK = 0,
+  GST_EINVAL = -1,   /* bad shape, null pointer, unsupported size */
+  GST_EINDEX = -2,   /* a gate index >= n_gates */
+  GST_ENONPOS = -3,  /* p <= 0 where N > 0: objective = +inf */
+  GST_ENOMEM = -4,   /* device allocation failed */
+  GST_EDEVICE = -5,  /* HIP runtime error */
+  GST_EBUSY = -6     /* admission refused (footprint or slots) */
+} gst_status;
+
+typedef struct gst_ctx gst_ctx;  /* opaque; one device, one stream */
+typedef struct gst_req gst_req;  /* opaque resident request */
+
+/* Gate set theta = (rho, effects, gates).  Device pointers. */
+typedef struct gst_gateset {
+  int n_qubits;          /* 1..3 */
+  int n_gates;           /* K, 1..gst_max_gates(n_qubits) */
+  int n_outcomes;        /* M, 1..D */
+  const double* rho;     /* [D] */
+  const double* effects; /* [M][D] */
+  const double* gates;   /* [K][D][D] row-major */
+} gst_gateset;
+
+/* Sequence list.  Device pointers (host pointers for gst_req_create_host). */
+typedef struct gst_seqlist {
+  int64_t n_seq;            /* S >= 0 */
+  const int64_t* offsets;   /* [S+1] */
+  const uint8_t* gate_idx;  /* [offsets[S]] */
+  int64_t max_len;          /* max_s (offsets[s+1]-offsets[s]) if known, else -1 */
+} gst_seqlist;
+
+/* Data-dependent diagnostics collected since the previous gst_sync. */
+typedef struct gst_diag {
+  int64_t n_bad_index;  /* gate indices >= K that were seen */
+  int64_t n_nonpos;     /* entries with p <= 0 and N > 0 */
+} gst_diag;
+
+/* Largest K supported for a qubit count (register budget of the on-chip
+   gradient accumulation). */
+int gst_max_gates(int n_qubits);
+
+/* Create a context on device `device_ordinal` that enqueues work on
+   `hip_stream` (a hipStream_t; NULL = the default stream). */
+int gst_create(gst_ctx** out, int device_ordinal, void* hip_stream);
+int gst_destroy(gst_ctx* ctx);
+
+/* Wait for all work enqueued by this context and report data-dependent
+   errors since the previous call (GST_EINDEX before GST_ENONPOS).  `diag`
+   may be NULL.  Resets the counters. */
+int gst_sync(gst_ctx* ctx, gst_diag* diag);
+
+/* Probabilities only: probs[S][M]. */
+int gst_probs(gst_ctx* ctx, const gst_gateset* gs, const gst_seqlist* seqs, double* probs);
+
+/* Objective (objective[0]), optionally probabilities and the gradient.
+   probs and grad may be NULL; objective must not be NULL. */
+int gst_loglik(gst_ctx* ctx, const gst_gateset* gs, const gst_seqlist* seqs,
+               const int32_t* counts, double* probs, double* objective, double* grad);
+
+/* Vector-Jacobian product: grad = sum_{s,m} w[s][m] dp[s][m]/dtheta (the
+   backward of probs for automatic differentiation). */
+int gst_vjp(gst_ctx* ctx, const gst_gateset* gs, const gst_seqlist* seqs, const double* w,
+            double* grad);
+
+/*
+ * Resident requests: the sequence list and the counts are copied to the
+ * device once, the prefix-sharing plan (a trie of the sequences, thesis Eq.
+ * GSTFullFiducialsGerms: every distinct prefix is evaluated once) is built
+ * once, and each evaluation only supplies a new gate set, as in the
+ * iterations of a maximum-likelihood fit.
+ *
+ * gst_req_create_host: offsets, gate_idx and counts are HOST pointers; they
+ * are copied before the call returns.  counts may be NULL (probs/vjp only).
+ */
+int gst_req_create_host(gst_ctx* ctx, int n_qubits, int n_gates, int n_outcomes,
+                        const gst_seqlist* seqs_host, const int32_t* counts_host,
+                        gst_req** out);
+/* Device bytes held by the request (plan, copies of the inputs, workspace). */
+int gst_req_footprint(const gst_req* req, size_t* bytes);
+/* Evaluate at gate set `theta`; same outputs and conventions as gst_loglik. */
+int gst_req_eval(gst_req* req, const gst_gateset* theta, double* probs, double* objective,
+                 double* grad);
+/* vjp with the request's resident sequence list. */
+int gst_req_vjp(gst_req* req, const gst_gateset* theta, const double* w, double* grad);
+int gst_req_destroy(gst_req* req);
+
+/* Message of the last failing call on this host thread ("" if none). */
+const char* gst_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GST_H_ */

@@ -1,0 +1,163 @@
+"""Python front end of the HIP library: torch tensors in, torch tensors out.
+
+Argument marshalling only (``_lib`` holds the ctypes declarations).  Every
+probability, objective and gradient is computed by the kernels in
+``libgst.so``; there is no CPU path.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+from typing import Optional, Tuple
+
+import numpy as np
+import torch
+
+from . import _lib
+
+_DEV = torch.device("cuda")
+
+
+def _require_cuda(t: torch.Tensor, dtype, name: str) -> torch.Tensor:
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}")
+    return t.contiguous()
+
+
+@dataclasses.dataclass
+class DeviceGateSet:
+    """theta = (rho [D], effects [M, D], gates [K, D, D]) as float64 device tensors."""
+    n_qubits: int
+    rho: torch.Tensor
+    effects: torch.Tensor
+    gates: torch.Tensor
+
+    @property
+    def D(self):
+        return 4 ** self.n_qubits
+
+    @property
+    def M(self):
+        return self.effects.shape[0]
+
+    @property
+    def K(self):
+        return self.gates.shape[0]
+
+    def n_params(self):
+        return self.D + self.M * self.D + self.K * self.D * self.D
+
+    @staticmethod
+    def from_numpy(n_qubits, rho, effects, gates, device=None):
+        dev = device or _DEV
+        f = lambda a: torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64), device=dev)
+        return DeviceGateSet(n_qubits, f(rho), f(effects), f(gates))
+
+    def as_struct(self) -> _lib.GstGateset:
+        D = self.D
+        rho = _require_cuda(self.rho, torch.float64, "rho")
+        E = _require_cuda(self.effects, torch.float64, "effects")
+        G = _require_cuda(self.gates, torch.float64, "gates")
+        if rho.shape != (D,) or E.dim() != 2 or E.shape[1] != D or G.dim() != 3 or G.shape[1:] != (D, D):
+            raise ValueError("gate set shapes do not match n_qubits")
+        self._keep = (rho, E, G)
+        return _lib.GstGateset(self.n_qubits, G.shape[0], E.shape[0], rho.data_ptr(), E.data_ptr(), G.data_ptr())
+
+
+@dataclasses.dataclass
+class DeviceSeqs:
+    """CSR sequence list on the device: offsets int64 [S+1], gate indices uint8 (time order)."""
+    offsets: torch.Tensor
+    gates: torch.Tensor
+    max_len: int
+
+    @property
+    def S(self):
+        return self.offsets.shape[0] - 1
+
+    @staticmethod
+    def from_numpy(offsets, gates, device=None):
+        dev = device or _DEV
+        off = np.ascontiguousarray(offsets, dtype=np.int64)
+        g = np.ascontiguousarray(gates, dtype=np.uint8)
+        if g.size == 0:
+            g = np.zeros(1, np.uint8)
+        ml = int(np.diff(off).max()) if len(off) > 1 else 0
+        return DeviceSeqs(torch.as_tensor(off, device=dev), torch.as_tensor(g, device=dev), ml)
+
+    def as_struct(self) -> _lib.GstSeqlist:
+        off = _require_cuda(self.offsets, torch.int64, "offsets")
+        g = _require_cuda(self.gates, torch.uint8, "gates")
+        self._keep = (off, g)
+        return _lib.GstSeqlist(off.shape[0] - 1, off.data_ptr(), g.data_ptr(), int(self.max_len))
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+class Context:
+    """One ``gst_ctx`` bound to a device and a torch stream."""
+
+    def __init__(self, device: int = 0, stream: Optional[torch.cuda.Stream] = None):
+        self.lib = _lib.load()
+        torch.cuda.set_device(device)
+        self.stream = stream or torch.cuda.current_stream(device)
+        h = ctypes.c_void_p()
+        _lib.check(self.lib.gst_create(ctypes.byref(h), device, ctypes.c_void_p(self.stream.cuda_stream)))
+        self.handle = h
+        self.device = device
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.gst_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _dev(self):
+        return torch.device("cuda", self.device)
+
+    def sync(self, raise_on_error: bool = True) -> Tuple[int, int, int]:
+        """Wait for the context's work; returns (status, n_bad_index, n_nonpos)."""
+        d = _lib.GstDiag()
+        rc = self.lib.gst_sync(self.handle, ctypes.byref(d))
+        if raise_on_error and rc not in (_lib.GST_OK,):
+            _lib.check(rc)
+        return rc, d.n_bad_index, d.n_nonpos
+
+    def probs(self, gs: DeviceGateSet, seqs: DeviceSeqs, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        out = out if out is not None else torch.empty((seqs.S, gs.M), dtype=torch.float64, device=self._dev())
+        _lib.check(self.lib.gst_probs(self.handle, ctypes.byref(gs.as_struct()), ctypes.byref(seqs.as_struct()),
+                                      _ptr(out)))
+        return out
+
+    def loglik(self, gs: DeviceGateSet, seqs: DeviceSeqs, counts: torch.Tensor, want_probs: bool = False,
+               want_grad: bool = True):
+        """Returns (objective [1], probs [S, M] or None, grad [P] or None), all on the device."""
+        counts = _require_cuda(counts, torch.int32, "counts")
+        obj = torch.empty(1, dtype=torch.float64, device=self._dev())
+        p = torch.empty((seqs.S, gs.M), dtype=torch.float64, device=self._dev()) if want_probs else None
+        g = torch.empty(gs.n_params(), dtype=torch.float64, device=self._dev()) if want_grad else None
+        _lib.check(self.lib.gst_loglik(self.handle, ctypes.byref(gs.as_struct()), ctypes.byref(seqs.as_struct()),
+                                       _ptr(counts), _ptr(p), _ptr(obj), _ptr(g)))
+        return obj, p, g
+
+    def vjp(self, gs: DeviceGateSet, seqs: DeviceSeqs, w: torch.Tensor) -> torch.Tensor:
+        w = _require_cuda(w, torch.float64, "w")
+        g = torch.empty(gs.n_params(), dtype=torch.float64, device=self._dev())
+        _lib.check(self.lib.gst_vjp(self.handle, ctypes.byref(gs.as_struct()), ctypes.byref(seqs.as_struct()),
+                                    _ptr(w), _ptr(g)))
+        return g
+
+
+def split_grad(g: torch.Tensor, n_qubits: int, M: int, K: int):
+    """Gradient layout [rho (D) | E (M*D) | G (K*D*D)] -> (d_rho, d_E, d_G) views."""
+    D = 4 ** n_qubits
+    return g[:D], g[D:D + M * D].view(M, D), g[D + M * D:].view(K, D, D)

@@ -1,0 +1,211 @@
+// Prefix-sharing plan (see gst_plan.h).
+#include "gst_plan.h"
+
+#include <algorithm>
+#include <cstring>
+#include <numeric>
+
+namespace gst {
+
+int64_t HostPlan::plan_steps() const {
+  int64_t s = trunk_steps();
+  for (int64_t q = 0; q < n_items(); ++q) s += items[4 * q + 2] - items[4 * q + 1];
+  return s;
+}
+
+bool build_plan(const int64_t* off, const uint8_t* gates, int64_t S, int K, const PlanOptions& opt,
+                HostPlan* out) {
+  HostPlan& P = *out;
+  P = HostPlan();
+  P.K = K;
+  P.S = S;
+  P.sum_len = S > 0 ? off[S] - off[0] : 0;
+  for (int64_t s = 0; s < S; ++s) P.max_len = std::max(P.max_len, off[s + 1] - off[s]);
+  if (S == 0 || P.sum_len == 0) return false;
+
+  // ---- 1. trie over the words in time order ----
+  std::vector<int32_t> parent{-1};
+  std::vector<uint8_t> gate{0};
+  std::vector<int32_t> depth{0};
+  std::vector<int32_t> child((size_t)K, -1);
+  std::vector<int32_t> term((size_t)S);
+  for (int64_t s = 0; s < S; ++s) {
+    int32_t n = 0;
+    for (int64_t t = off[s]; t < off[s + 1]; ++t) {
+      const int g = gates[t];
+      int32_t c = child[(size_t)n * K + g];
+      if (c < 0) {
+        if ((int64_t)parent.size() >= opt.max_nodes) return false;
+        c = (int32_t)parent.size();
+        parent.push_back(n);
+        gate.push_back((uint8_t)g);
+        depth.push_back(depth[n] + 1);
+        child.resize(child.size() + K, -1);
+        child[(size_t)n * K + g] = c;
+      }
+      n = c;
+    }
+    term[s] = n;
+  }
+  const int64_t N = (int64_t)parent.size();
+  P.n_nodes = N;
+  // quick rejection: the trie alone bounds the saving
+  if ((double)(N - 1) > opt.max_share_ratio * (double)P.sum_len) return false;
+
+  // ---- 2. heights and heavy children (children have larger ids than parents) ----
+  std::vector<int32_t> height((size_t)N, 0);
+  for (int64_t n = N - 1; n >= 1; --n) height[parent[n]] = std::max(height[parent[n]], height[n] + 1);
+  std::vector<int32_t> heavy((size_t)N, -1);
+  for (int64_t n = 1; n < N; ++n) {
+    const int32_t p = parent[n];
+    if (heavy[p] < 0 || height[n] > height[heavy[p]]) heavy[p] = (int32_t)n;
+  }
+
+  // ---- 3. chains of the heavy-path decomposition; long ones become trunks ----
+  // chain heads: heavy child of the root and every node that is not the heavy
+  // child of its parent.
+  std::vector<int32_t> heads;
+  for (int64_t n = 1; n < N; ++n)
+    if (heavy[parent[n]] != n || parent[n] == 0) heads.push_back((int32_t)n);
+  // owner trunk and position of stored nodes
+  std::vector<int32_t> owner((size_t)N, -1);
+  std::vector<int32_t> chain_pos((size_t)N, -1);
+  struct Trunk {
+    int32_t head;
+    int32_t anchor_node;  // 0 = root (recompute from rho)
+    int32_t len_chain;
+    int32_t len_prefix;   // unstored steps recomputed before the head
+    int level;
+  };
+  std::vector<Trunk> trunks;
+  for (int32_t h : heads) {
+    if (height[h] + 1 < opt.min_trunk) continue;
+    const int32_t t = (int32_t)trunks.size();
+    int32_t len = 0;
+    for (int32_t n = h; n >= 0; n = heavy[n]) {
+      owner[n] = t;
+      chain_pos[n] = len++;
+    }
+    trunks.push_back(Trunk{h, 0, len, 0, 0});
+  }
+  // anchors and levels; heads are in increasing node id, so a trunk's anchor
+  // owner (an ancestor) has already been assigned a level when its head has a
+  // smaller id -- not guaranteed in general, hence the fixed-point loop.
+  for (auto& T : trunks) {
+    int32_t a = parent[T.head];
+    int32_t steps = 0;
+    while (a != 0 && owner[a] < 0) {
+      a = parent[a];
+      ++steps;
+    }
+    if (a != 0 && depth[a] <= opt.reanchor_depth) {
+      steps += depth[a];
+      a = 0;
+    }
+    T.anchor_node = a;
+    T.len_prefix = steps;
+  }
+  bool changed = true;
+  for (int it = 0; changed && it < 64; ++it) {
+    changed = false;
+    for (auto& T : trunks) {
+      const int lvl = T.anchor_node == 0 ? 0 : trunks[owner[T.anchor_node]].level + 1;
+      if (lvl != T.level) {
+        T.level = lvl;
+        changed = true;
+      }
+    }
+  }
+  // order: level ascending, then total length descending, then head id
+  std::vector<int32_t> order(trunks.size());
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
+    const Trunk &A = trunks[x], &B = trunks[y];
+    if (A.level != B.level) return A.level < B.level;
+    return A.len_prefix + A.len_chain > B.len_prefix + B.len_chain;
+  });
+  std::vector<int32_t> rank(trunks.size());
+  for (size_t r = 0; r < order.size(); ++r) rank[order[r]] = (int32_t)r;
+  // state locations: trunk r owns locations [trunk_ptr[r], trunk_ptr[r+1]);
+  // the state after its j-th step is at trunk_ptr[r] + j.
+  const int64_t nT = (int64_t)trunks.size();
+  P.trunk_ptr.assign(nT + 1, 0);
+  for (int64_t r = 0; r < nT; ++r) {
+    const Trunk& T = trunks[order[r]];
+    P.trunk_ptr[r + 1] = P.trunk_ptr[r] + T.len_prefix + T.len_chain;
+  }
+  auto loc_of = [&](int32_t n) -> int64_t {  // canonical location of a stored node
+    const int32_t t = owner[n];
+    return P.trunk_ptr[rank[t]] + trunks[t].len_prefix + chain_pos[n];
+  };
+  P.trunk_gates.resize(P.trunk_ptr[nT]);
+  P.trunk_inj.assign(P.trunk_ptr[nT], -1);
+  P.trunk_anchor.resize(nT);
+  int max_level = 0;
+  for (int64_t r = 0; r < nT; ++r) {
+    const Trunk& T = trunks[order[r]];
+    max_level = std::max(max_level, T.level);
+    P.trunk_anchor[r] = T.anchor_node == 0 ? -1 : loc_of(T.anchor_node);
+    // gates: walk up from the chain end to the anchor, then reverse
+    int64_t w = P.trunk_ptr[r + 1] - 1;
+    int32_t end = T.head;
+    while (heavy[end] >= 0) end = heavy[end];
+    for (int32_t n = end; n != T.anchor_node; n = parent[n]) P.trunk_gates[w--] = gate[n];
+    P.trunk_max_len = std::max<int64_t>(P.trunk_max_len, T.len_prefix + T.len_chain);
+  }
+  P.n_levels = nT ? max_level + 1 : 0;
+  P.trunk_level_ptr.assign(P.n_levels + 1, 0);
+  for (int64_t r = 0; r < nT; ++r) P.trunk_level_ptr[trunks[order[r]].level + 1] = r + 1;
+  for (int l = 1; l <= P.n_levels; ++l) P.trunk_level_ptr[l] = std::max(P.trunk_level_ptr[l], P.trunk_level_ptr[l - 1]);
+
+  // ---- 4. items: each sequence from its deepest stored prefix ----
+  std::vector<int64_t> it((size_t)S * 4);
+  for (int64_t s = 0; s < S; ++s) {
+    int32_t n = term[s];
+    while (n != 0 && owner[n] < 0) n = parent[n];
+    it[4 * s + 0] = s;
+    it[4 * s + 1] = off[s] + depth[n];
+    it[4 * s + 2] = off[s + 1];
+    it[4 * s + 3] = n == 0 ? -1 : loc_of(n);
+  }
+  std::vector<int64_t> iorder((size_t)S);
+  std::iota(iorder.begin(), iorder.end(), 0);
+  std::stable_sort(iorder.begin(), iorder.end(), [&](int64_t x, int64_t y) {
+    return it[4 * x + 2] - it[4 * x + 1] > it[4 * y + 2] - it[4 * y + 1];
+  });
+  P.items.resize((size_t)S * 4);
+  for (int64_t q = 0; q < S; ++q)
+    for (int c = 0; c < 4; ++c) P.items[4 * q + c] = it[4 * iorder[q] + c];
+  for (int64_t q = 0; q < S; ++q) P.item_max_len = std::max(P.item_max_len, P.items[4 * q + 2] - P.items[4 * q + 1]);
+
+  // ---- 5. injection slots: stored locations that receive adjoints ----
+  // sources: items anchored there and trunks (level >= 1) anchored there.
+  std::vector<std::pair<int64_t, int64_t>> src;  // (loc, source)
+  for (int64_t q = 0; q < S; ++q)
+    if (P.items[4 * q + 3] >= 0) src.emplace_back(P.items[4 * q + 3], q);
+  for (int64_t r = 0; r < nT; ++r)
+    if (P.trunk_anchor[r] >= 0) src.emplace_back(P.trunk_anchor[r], -(r + 1));
+  std::stable_sort(src.begin(), src.end(),
+                   [](const std::pair<int64_t, int64_t>& a, const std::pair<int64_t, int64_t>& b) {
+                     return a.first < b.first;
+                   });
+  P.inj_ptr.push_back(0);
+  for (size_t x = 0; x < src.size();) {
+    size_t y = x;
+    while (y < src.size() && src[y].first == src[x].first) ++y;
+    const int32_t slot = (int32_t)P.inj_loc.size();
+    P.inj_loc.push_back(src[x].first);
+    for (size_t z = x; z < y; ++z) P.inj_src.push_back(src[z].second);
+    P.inj_ptr.push_back((int64_t)P.inj_src.size());
+    P.trunk_inj[src[x].first] = slot;
+    x = y;
+  }
+  P.trunk_anchor_inj.assign(nT, -1);
+  for (int64_t r = 0; r < nT; ++r)
+    if (P.trunk_anchor[r] >= 0) P.trunk_anchor_inj[r] = P.trunk_inj[P.trunk_anchor[r]];
+
+  if ((double)P.plan_steps() > opt.max_share_ratio * (double)P.sum_len) return false;
+  return true;
+}
+
+}  // namespace gst

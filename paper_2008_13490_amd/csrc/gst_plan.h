@@ -1,0 +1,68 @@
+// Prefix-sharing plan of a sequence list (host side).
+//
+// Thesis Eq. GSTFullFiducialsGerms: GST sequences are F_q g^l F_p, so for a
+// fixed preparation fiducial and germ every power g^l is a prefix of the
+// next one, and all measurement fiducials of one (p, g, l) share F_p g^l.
+// The plan is a trie of the sequences in time order; every distinct prefix
+// state is computed once.
+//
+// Decomposition:
+//   * long chains of the trie ("trunks", heavy paths by remaining depth) are
+//     evaluated by one team each; the state after every step is stored;
+//   * every sequence becomes a work item for the sequence kernel: it starts
+//     from the deepest stored state on its path (or rho) and applies the rest
+//     of its own word (usually the measurement fiducial);
+//   * in the reverse sweep the adjoints of the items are summed per stored
+//     state ("injections") and the trunks carry them back to rho.
+// The probabilities computed this way are the same floating-point numbers as
+// those of the plain per-sequence evaluation: the shared prefixes are the
+// same operations on the same values.
+#pragma once
+#include <stdint.h>
+
+#include <vector>
+
+namespace gst {
+
+struct HostPlan {
+  int K = 0;
+  int64_t S = 0;
+  int64_t sum_len = 0;        // total steps of the plain evaluation
+  int64_t n_nodes = 0;        // distinct prefixes (trie nodes, root included)
+  int64_t max_len = 0;        // longest sequence
+  // trunks, sorted by level then by length (descending)
+  int n_levels = 0;
+  std::vector<int64_t> trunk_level_ptr;  // [n_levels + 1] trunk index ranges per level
+  std::vector<int64_t> trunk_anchor;     // [n_trunks] state location of the anchor, -1 = rho
+  std::vector<int64_t> trunk_ptr;        // [n_trunks + 1] step ranges in trunk_gates / state locations
+  std::vector<uint8_t> trunk_gates;      // [trunk_steps]
+  std::vector<int32_t> trunk_inj;        // [trunk_steps] injection slot of the node reached by the step, -1 none
+  std::vector<int64_t> trunk_anchor_inj; // [n_trunks] injection slot that receives the adjoint at the anchor (-1 = rho)
+  int64_t trunk_max_len = 0;
+  // items: (seq, beg, end, anchor location), sorted by end - beg descending
+  std::vector<int64_t> items;            // [n_items * 4]
+  int64_t item_max_len = 0;
+  // injection slots: state location and the items / trunks feeding it
+  std::vector<int64_t> inj_loc;          // [n_inj]
+  std::vector<int64_t> inj_ptr;          // [n_inj + 1] ranges into inj_src
+  std::vector<int64_t> inj_src;          // item indices (>= 0) or -(trunk index + 1)
+  int64_t n_items() const { return (int64_t)items.size() / 4; }
+  int64_t n_trunks() const { return (int64_t)trunk_anchor.size(); }
+  int64_t trunk_steps() const { return (int64_t)trunk_gates.size(); }
+  int64_t plan_steps() const;            // trunk steps + item steps
+};
+
+struct PlanOptions {
+  int min_trunk = 24;        // shortest chain that is stored
+  int reanchor_depth = 8;    // chains branching off at depth <= this restart from rho
+  double max_share_ratio = 0.8;  // use the plan only if plan_steps <= ratio * sum_len
+  int64_t max_nodes = 1LL << 26;
+};
+
+// Builds the plan.  Returns false (plan unused: evaluate sequence by
+// sequence) when sharing saves too little or the trie would be too large.
+// Gate indices must already be validated (< K).
+bool build_plan(const int64_t* offsets, const uint8_t* gates, int64_t S, int K, const PlanOptions& opt,
+                HostPlan* out);
+
+}  // namespace gst
