@@ -1,0 +1,260 @@
+#!/usr/bin/env python3
+"""Benchmark: sequence evaluations per second including the gradient, 2 qubits, FP64.
+
+One step = one evaluation of the whole path on the two-qubit GST list: outcome
+probabilities of every sequence, the negative log-likelihood of the counts and
+its gradient with respect to every entry of rho, the effects and the gates
+(resident request: the sequence list and counts stay on the device, the gate
+set is new every step, as in the iterations of a fit).  Inputs are resident in
+HBM before the timed region starts.
+
+Prints one JSON line (see the design doc for the fields).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "sequence evals/s incl. gradient (2q, FP64); p50/p99 latency of served fits"
+# MI355X published FP64 vector peak: 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
+PEAK_FP64 = 78.6
+
+
+def workload_desc(w):
+    L = w.seqs.lengths()
+    return {
+        "workload": "c2: two-qubit GST list, 11 prep x 11 meas fiducials x 12 germs, powers 1..256, "
+                    "gates {Gii,Gxi,Gix,Gyi,Giy,Gcz} with 1e-3 depolarizing + N(0,0.01) over-rotations, "
+                    "counts ~ Multinomial(1000)",
+        "sequences": int(w.seqs.S),
+        "sum_len": int(L.sum()),
+        "max_len": int(L.max()),
+        "n_qubits": 2,
+        "params": int(w.model.n_params()),
+    }
+
+
+# ---------------------------------------------------------------------------
+# CPU baseline: the oracle, unchanged, on the machine's host cores
+# ---------------------------------------------------------------------------
+def _cpu_worker(args):
+    name, seconds = args
+    sys.path.insert(0, ROOT)
+    import oracle
+    from paper_2008_13490_amd import workloads as W
+    w = W.structured_workload(name)
+    m = w.model
+    n = 0
+    t0 = time.perf_counter()
+    while True:
+        oracle.loglik(m.rho, m.effects, m.gates, w.seqs.offsets, w.seqs.gates, w.counts)
+        n += 1
+        if time.perf_counter() - t0 >= seconds:
+            break
+    return n, time.perf_counter() - t0, w.seqs.S
+
+
+def cpu_baseline(name: str, seconds: float, workers: int):
+    import multiprocessing as mp
+    import oracle
+    oracle.build(force=not os.path.exists(oracle.library_path()))
+    ctx = mp.get_context("spawn")
+    t0 = time.perf_counter()
+    with ctx.Pool(workers) as pool:
+        res = pool.map(_cpu_worker, [(name, seconds)] * workers)
+    wall = time.perf_counter() - t0
+    evals = sum(r[0] for r in res)
+    S = res[0][2]
+    busy = max(r[1] for r in res)
+    return {
+        "value": evals * S / busy,
+        "unit": "sequence evals/s",
+        "cores": workers,
+        "kind": "oracle",
+        "sample": f"{name} full list ({S} sequences) evaluated {evals} times with gradient, "
+                  f"{workers} single-threaded processes for ~{seconds:.0f} s each (wall {wall:.1f} s)",
+    }
+
+
+# ---------------------------------------------------------------------------
+def kernel_source_hash():
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2008_13490_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".h", ".cpp")):
+            h.update(open(os.path.join(csrc, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(family: str):
+    """HBM bytes per launch from the committed counter summary, if it was taken
+    on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_c2.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if line.startswith("#") or "=" not in line:
+            continue
+        k, v = line.split("=", 1)
+        vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    key = f"{family}_bytes_per_launch"
+    return float(vals[key]) if key in vals else None
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="c2")
+    ap.add_argument("--path", choices=["resident", "plain"], default="resident")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--cpu-workers", type=int, default=0)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build measures one GPU only; the path shards by sequence and "
+                                   "all-reduces the gradient (see DESIGN.md), but no multi-GPU run is part "
+                                   "of it", "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    # CPU baseline first, before anything touches the GPU.
+    cpu = None
+    if not args.no_cpu:
+        workers = args.cpu_workers or max(1, min(16, os.cpu_count() or 1))
+        cpu = cpu_baseline(args.workload, args.cpu_seconds, workers)
+
+    import numpy as np
+    import torch
+    from paper_2008_13490_amd import api
+    from paper_2008_13490_amd import workloads as W
+
+    w = W.structured_workload(args.workload)
+    desc = workload_desc(w)
+    m = w.model
+    ctx = api.Context(0)
+    gs = api.DeviceGateSet.from_numpy(m.n_qubits, m.rho, m.effects, m.gates)
+    dev = torch.device("cuda", 0)
+    obj = torch.empty(1, dtype=torch.float64, device=dev)
+    grad = torch.empty(m.n_params(), dtype=torch.float64, device=dev)
+    if args.path == "resident":
+        req = api.Request(ctx, m.n_qubits, m.K, m.M, w.seqs.offsets, w.seqs.gates, w.counts)
+
+        def step():
+            req.eval(gs, want_probs=False, want_grad=True, out=(obj, None, grad))
+    else:
+        seqs = api.DeviceSeqs.from_numpy(w.seqs.offsets, w.seqs.gates)
+        counts = torch.as_tensor(w.counts, device=dev)
+        import ctypes
+
+        def step():
+            api._lib.check(ctx.lib.gst_loglik(ctx.handle, ctypes.byref(gs.as_struct()),
+                                              ctypes.byref(seqs.as_struct()), api._ptr(counts), None,
+                                              api._ptr(obj), api._ptr(grad)))
+
+    for _ in range(args.warmup):
+        step()
+    ctx.sync()
+    api.profile_enable(ctx, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ctx.sync()
+    fams = {}
+    for fam in ("leaf", "reduce", "trunk_fwd", "trunk_bwd", "inject", "grad_gemm"):
+        ms, n = api.profile_read(ctx, fam)
+        if n:
+            fams[fam] = (ms, n)
+    api.profile_enable(ctx, False)
+    elapsed = t1 - t0
+    S = w.seqs.S
+    value = S * args.steps / elapsed
+
+    # dominant kernel and its algorithmic FP64 work per launch
+    dom = max(fams, key=lambda f: fams[f][0])
+    ms_tot, n_launch = fams[dom]
+    avg_s = ms_tot / n_launch * 1e-3
+    D, M = 16, m.M
+    L = w.seqs.lengths()
+    info = req_plan_info(req) if args.path == "resident" else None
+    flops = algorithmic_flops(dom, D, M, S, int(L.sum()), info)
+    achieved = flops / avg_s / 1e12
+    traffic = read_traffic(dom)
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "sequence evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": dict(desc, path=args.path),
+        "roofline": {
+            "bound": "alu",
+            "kernel": dom,
+            "achieved": achieved,
+            "peak": PEAK_FP64,
+            "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP64,
+            "traffic": traffic,
+            "avg_launch_us": avg_s * 1e6,
+            "algorithmic_flop_per_launch": flops,
+        },
+        "kernels_ms_per_step": {f: fams[f][0] / args.steps for f in fams},
+        "plan": info,
+        "useful_tflops": (6.0 * D * D * (info["trunk_steps"] + info["item_steps"]) if info else
+                          6.0 * D * D * int(L.sum())) / (elapsed / args.steps) / 1e12 if True else None,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
+def req_plan_info(req):
+    info = req.plan_info()
+    return info if info["plan_used"] else None
+
+
+def algorithmic_flops(family, D, M, S, sum_len, info):
+    """FP64 flops the method must do in one launch of `family`.
+
+    Per step of a chain: forward mat-vec 2D^2, adjoint mat-vec 2D^2, gradient
+    outer product 2D^2; per sequence: readout, seed and effect gradient 2DM
+    each.  Without the sharing plan every sequence is its own chain; with it,
+    the chains are the stored trunk steps plus the remaining item steps
+    (launch counts: one per trunk level)."""
+    if info is None:
+        if family == "leaf":
+            return 6.0 * D * D * sum_len + 6.0 * D * M * S
+        return 0.0
+    ts, its, lv = info["trunk_steps"], info["item_steps"], max(1, info["levels"])
+    if family == "leaf":   # items: forward + adjoint mat-vecs, readout, seed, dE
+        return 4.0 * D * D * its + 6.0 * D * M * S
+    if family == "trunk_fwd":
+        return 2.0 * D * D * ts / lv
+    if family == "trunk_bwd":
+        return 2.0 * D * D * ts / lv
+    if family == "grad_gemm":
+        return 2.0 * D * D * (ts + its)
+    return 0.0
+
+
+if __name__ == "__main__":
+    main()

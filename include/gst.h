@@ -142,9 +142,27 @@ int gst_req_footprint(const gst_req* req, size_t* bytes);
 /* Evaluate at gate set `theta`; same outputs and conventions as gst_loglik. */
 int gst_req_eval(gst_req* req, const gst_gateset* theta, double* probs, double* objective,
                  double* grad);
+/* Probabilities only, with the request's resident sequence list. */
+int gst_req_probs(gst_req* req, const gst_gateset* theta, double* probs);
 /* vjp with the request's resident sequence list. */
 int gst_req_vjp(gst_req* req, const gst_gateset* theta, const double* w, double* grad);
 int gst_req_destroy(gst_req* req);
+/* Sharing-plan statistics of a request (diagnostics): info[0..n) receives
+   {plan used (0/1), total steps of the plain evaluation, trie nodes, trunks,
+    trunk steps, item steps, trunk levels, injection slots}. */
+int gst_req_plan_info(const gst_req* req, int64_t* info, int n);
+
+/*
+ * Kernel timing (diagnostics).  While enabled, every kernel the context
+ * enqueues is bracketed by two HIP events recorded on the context's stream.
+ * gst_profile_read synchronizes the stream and returns, for the kernel family
+ * `kernel` ("leaf", "reduce", "trunk_fwd", "trunk_bwd", "inject",
+ * "grad_gemm"), the summed
+ * elapsed milliseconds and the number of launches since profiling was
+ * enabled; the counters are not reset by reading.
+ */
+int gst_profile_enable(gst_ctx* ctx, int enable);
+int gst_profile_read(gst_ctx* ctx, const char* kernel, double* total_ms, int64_t* launches);
 
 /* Message of the last failing call on this host thread ("" if none). */
 const char* gst_last_error(void);

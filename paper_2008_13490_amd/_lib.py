@@ -21,8 +21,8 @@ _NAMES = {0: "GST_OK", -1: "GST_EINVAL", -2: "GST_EINDEX", -3: "GST_ENONPOS", -4
 
 EXPORTED = [
     "gst_max_gates", "gst_create", "gst_destroy", "gst_sync", "gst_probs", "gst_loglik", "gst_vjp",
-    "gst_req_create_host", "gst_req_footprint", "gst_req_eval", "gst_req_vjp", "gst_req_destroy",
-    "gst_last_error",
+    "gst_req_create_host", "gst_req_footprint", "gst_req_eval", "gst_req_probs", "gst_req_vjp",
+    "gst_req_destroy", "gst_req_plan_info", "gst_profile_enable", "gst_profile_read", "gst_last_error",
 ]
 
 
@@ -73,12 +73,21 @@ def load():
         lib.gst_last_error.restype = ctypes.c_char_p
         for name in ("gst_max_gates", "gst_create", "gst_destroy", "gst_sync", "gst_probs", "gst_loglik", "gst_vjp"):
             getattr(lib, name).restype = I
+        lib.gst_profile_enable.argtypes = [P, I]
+        lib.gst_profile_read.argtypes = [P, ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
+                                         ctypes.POINTER(ctypes.c_int64)]
+        lib.gst_profile_enable.restype = I
+        lib.gst_profile_read.restype = I
         if hasattr(lib, "gst_req_create_host"):
             lib.gst_req_create_host.argtypes = [P, I, I, I, ctypes.POINTER(GstSeqlist), P, ctypes.POINTER(P)]
             lib.gst_req_footprint.argtypes = [P, ctypes.POINTER(ctypes.c_size_t)]
             lib.gst_req_eval.argtypes = [P, ctypes.POINTER(GstGateset), P, P, P]
             lib.gst_req_vjp.argtypes = [P, ctypes.POINTER(GstGateset), P, P]
+            lib.gst_req_probs.argtypes = [P, ctypes.POINTER(GstGateset), P]
+            lib.gst_req_probs.restype = I
             lib.gst_req_destroy.argtypes = [P]
+            lib.gst_req_plan_info.argtypes = [P, ctypes.POINTER(ctypes.c_int64), I]
+            lib.gst_req_plan_info.restype = I
             for name in ("gst_req_create_host", "gst_req_footprint", "gst_req_eval", "gst_req_vjp", "gst_req_destroy"):
                 getattr(lib, name).restype = I
         _lib = lib

@@ -157,6 +157,85 @@ class Context:
         return g
 
 
+class Request:
+    """A resident request (``gst_req``): sequences and counts live on the device,
+    the sharing plan is built once, and each evaluation takes a new gate set."""
+
+    def __init__(self, ctx: Context, n_qubits: int, n_gates: int, n_outcomes: int, offsets, gates, counts=None):
+        self.ctx = ctx
+        self.lib = ctx.lib
+        off = np.ascontiguousarray(offsets, dtype=np.int64)
+        g = np.ascontiguousarray(gates, dtype=np.uint8)
+        if g.size == 0:
+            g = np.zeros(1, np.uint8)
+        ml = int(np.diff(off).max()) if len(off) > 1 else 0
+        sl = _lib.GstSeqlist(len(off) - 1, off.ctypes.data, g.ctypes.data, ml)
+        c = None
+        if counts is not None:
+            c = np.ascontiguousarray(counts, dtype=np.int32)
+        h = ctypes.c_void_p()
+        _lib.check(self.lib.gst_req_create_host(ctx.handle, n_qubits, n_gates, n_outcomes, ctypes.byref(sl),
+                                                None if c is None else c.ctypes.data, ctypes.byref(h)))
+        self.handle = h
+        self.S = len(off) - 1
+        self.M = n_outcomes
+        self.n_params = 4 ** n_qubits * (1 + n_outcomes) + n_gates * 16 ** n_qubits
+
+    def plan_info(self) -> dict:
+        v = (ctypes.c_int64 * 8)()
+        _lib.check(self.lib.gst_req_plan_info(self.handle, v, 8))
+        keys = ["plan_used", "sum_len", "trie_nodes", "trunks", "trunk_steps", "item_steps", "levels", "inj_slots"]
+        return dict(zip(keys, [int(x) for x in v]))
+
+    def footprint(self) -> int:
+        b = ctypes.c_size_t()
+        _lib.check(self.lib.gst_req_footprint(self.handle, ctypes.byref(b)))
+        return b.value
+
+    def eval(self, gs: DeviceGateSet, want_probs=False, want_grad=True, out=None):
+        dev = self.ctx._dev()
+        obj, p, g = out if out is not None else (
+            torch.empty(1, dtype=torch.float64, device=dev),
+            torch.empty((self.S, self.M), dtype=torch.float64, device=dev) if want_probs else None,
+            torch.empty(self.n_params, dtype=torch.float64, device=dev) if want_grad else None)
+        _lib.check(self.lib.gst_req_eval(self.handle, ctypes.byref(gs.as_struct()), _ptr(p), _ptr(obj), _ptr(g)))
+        return obj, p, g
+
+    def probs(self, gs: DeviceGateSet, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        p = out if out is not None else torch.empty((self.S, self.M), dtype=torch.float64, device=self.ctx._dev())
+        _lib.check(self.lib.gst_req_probs(self.handle, ctypes.byref(gs.as_struct()), _ptr(p)))
+        return p
+
+    def vjp(self, gs: DeviceGateSet, w: torch.Tensor) -> torch.Tensor:
+        w = _require_cuda(w, torch.float64, "w")
+        g = torch.empty(self.n_params, dtype=torch.float64, device=self.ctx._dev())
+        _lib.check(self.lib.gst_req_vjp(self.handle, ctypes.byref(gs.as_struct()), _ptr(w), _ptr(g)))
+        return g
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.gst_req_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def profile_enable(ctx: Context, on: bool = True):
+    _lib.check(ctx.lib.gst_profile_enable(ctx.handle, 1 if on else 0))
+
+
+def profile_read(ctx: Context, family: str):
+    """(total_ms, launches) of one kernel family since profiling was enabled."""
+    ms = ctypes.c_double()
+    n = ctypes.c_int64()
+    _lib.check(ctx.lib.gst_profile_read(ctx.handle, family.encode(), ctypes.byref(ms), ctypes.byref(n)))
+    return ms.value, n.value
+
+
 def split_grad(g: torch.Tensor, n_qubits: int, M: int, K: int):
     """Gradient layout [rho (D) | E (M*D) | G (K*D*D)] -> (d_rho, d_E, d_G) views."""
     D = 4 ** n_qubits

@@ -13,6 +13,7 @@
 
 #include "../../include/gst.h"
 #include "gst_internal.h"
+#include "gst_plan.h"
 
 namespace {
 
@@ -57,18 +58,107 @@ struct DevBuf {
   }
 };
 
+// Per-kernel-family event timing (gst_profile_*).
+struct Profiler {
+  bool on = false;
+  struct Pending {
+    int family;
+    hipEvent_t a, b;
+  };
+  std::vector<Pending> pending;
+  std::vector<hipEvent_t> pool;
+  double total_ms[8] = {0};
+  int64_t launches[8] = {0};
+  hipEvent_t get() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
+  ~Profiler() {
+    for (auto& p : pending) {
+      (void)hipEventDestroy(p.a);
+      (void)hipEventDestroy(p.b);
+    }
+    for (auto e : pool) (void)hipEventDestroy(e);
+  }
+};
+
+enum Family { FAM_LEAF = 0, FAM_REDUCE = 1, FAM_TRUNK_FWD = 2, FAM_TRUNK_BWD = 3, FAM_INJECT = 4, FAM_GEMM = 5,
+              FAM_N = 6 };
+static const char* kFamilyNames[FAM_N] = {"leaf", "reduce", "trunk_fwd", "trunk_bwd", "inject", "grad_gemm"};
+
 struct gst_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
   unsigned long long* status = nullptr;  // device [2]
   DevBuf ws;
+  Profiler prof;
+};
+
+// Brackets one launch with events when profiling is on.
+struct ProfScope {
+  gst_ctx* c;
+  int fam;
+  hipEvent_t a = nullptr;
+  ProfScope(gst_ctx* ctx, int family) : c(ctx), fam(family) {
+    if (c->prof.on) {
+      a = c->prof.get();
+      if (a) (void)hipEventRecord(a, c->stream);
+    }
+  }
+  ~ProfScope() {
+    if (c->prof.on && a) {
+      hipEvent_t b = c->prof.get();
+      if (b) {
+        (void)hipEventRecord(b, c->stream);
+        c->prof.pending.push_back({fam, a, b});
+      } else {
+        c->prof.pool.push_back(a);
+      }
+    }
+  }
+};
+
+// Device copy of a sharing plan (gst_plan.h).
+struct DevicePlan {
+  bool used = false;
+  gst::HostPlan host;                    // kept for sizes and level ranges
+  std::vector<int64_t> inj_level_ptr;    // [n_levels + 1] injection slot ranges per level
+  DevBuf buf;
+  int64_t* items = nullptr;
+  int64_t* trunk_ptr = nullptr;
+  int64_t* trunk_anchor = nullptr;
+  uint8_t* trunk_gates = nullptr;
+  int32_t* trunk_inj = nullptr;
+  int64_t* inj_ptr = nullptr;
+  int64_t* inj_src = nullptr;
+  int64_t* item_step_ptr = nullptr;
+  int64_t* rec_b = nullptr;
+  int64_t* rec_f = nullptr;
+  int64_t* chunk_gate = nullptr;
+  int64_t* chunk_beg = nullptr;
+  int64_t* chunk_end = nullptr;
+  double* FA = nullptr;         // state arena [1 + trunk_steps + item_steps][D]
+  double* BA = nullptr;         // adjoint arena [trunk_steps + item_steps][D]
+  double* item_adj = nullptr;   // [n_items][D]
+  double* trunk_adj = nullptr;  // [n_trunks][D]
+  double* inj = nullptr;        // [n_inj][D]
 };
 
 struct gst_req {
   gst_ctx* ctx = nullptr;
   int n_qubits = 0, D = 0, M = 0, K = 0;
-  int64_t S = 0;
+  int64_t S = 0, max_len = 0;
+  DevBuf data;  // offsets | gate indices | counts
+  int64_t* offsets = nullptr;
+  uint8_t* gates = nullptr;
   int32_t* counts = nullptr;
+  DevicePlan plan;
   DevBuf ws;
   size_t resident_bytes = 0;
 };
@@ -124,17 +214,25 @@ int run_leaf(gst_ctx* ctx, DevBuf& ws, const gst::LeafLaunch& base, int64_t max_
   const int C = gst::leaf_ckpt_interval(D);
   const int64_t ck_team = a.want_grad ? ((max_len + C - 1) / C + 1) * 16 : 0;
   const size_t slab_bytes = need_slab ? (size_t)blocks * P * 8 : 0;
+  const size_t part_bytes = need_slab ? (size_t)gst::reduce_parts(blocks) * P * 8 : 0;
   const size_t ck_bytes = (size_t)blocks * gst::leaf_teams_per_block(D) * ck_team * 8;
-  int rc = ws.reserve(slab_bytes + ck_bytes + 256, ctx->stream);
+  int rc = ws.reserve(slab_bytes + part_bytes + ck_bytes + 256, ctx->stream);
   if (rc) return rc;
   a.slab = need_slab ? reinterpret_cast<double*>(ws.p) : nullptr;
-  a.ckpt = a.want_grad ? reinterpret_cast<double*>((char*)ws.p + slab_bytes) : nullptr;
+  double* part = reinterpret_cast<double*>((char*)ws.p + slab_bytes);
+  a.ckpt = a.want_grad ? reinterpret_cast<double*>((char*)ws.p + slab_bytes + part_bytes) : nullptr;
   a.ckpt_per_team = ck_team;
   a.max_len = (int)max_len;
   a.status = ctx->status;
   if (max_len > (int64_t)1 << 30) return fail(GST_EINVAL, "sequence too long");
-  HIP_TRY(gst::launch_leaf(a, blocks, ctx->stream));
-  if (need_slab) HIP_TRY(gst::launch_reduce(a.slab, blocks, P, objective, grad, ctx->status, ctx->stream));
+  {
+    ProfScope ps(ctx, FAM_LEAF);
+    HIP_TRY(gst::launch_leaf(a, blocks, ctx->stream));
+  }
+  if (need_slab) {
+    ProfScope ps(ctx, FAM_REDUCE);
+    HIP_TRY(gst::launch_reduce(a.slab, blocks, P, objective, grad, ctx->status, nullptr, D, part, ctx->stream));
+  }
   return GST_OK;
 }
 
@@ -170,6 +268,194 @@ int plain_eval(gst_ctx* ctx, const gst_gateset* gs, const gst_seqlist* sl, int m
   a.mode = mode;
   a.want_grad = grad != nullptr;
   return run_leaf(ctx, ctx->ws, a, max_len, objective, grad);
+}
+
+// Carve consecutive aligned regions out of one allocation.
+struct Carver {
+  size_t off = 0;
+  template <class T>
+  size_t take(size_t n) {
+    off = (off + 255) / 256 * 256;
+    const size_t at = off;
+    off += n * sizeof(T);
+    return at;
+  }
+};
+
+int upload_plan(gst_req* r, const gst::HostPlan& P) {
+  DevicePlan& d = r->plan;
+  d.host = P;
+  const int D = r->D;
+  const int64_t nI = P.n_items(), nT = P.n_trunks(), nTS = P.trunk_steps(), nJ = (int64_t)P.inj_loc.size(),
+                nIS = P.item_steps(), nR = (int64_t)P.rec_b.size(), nC = P.n_chunks();
+  Carver c;
+  const size_t o_items = c.take<int64_t>(4 * nI), o_tp = c.take<int64_t>(nT + 1), o_ta = c.take<int64_t>(nT + 1),
+               o_tg = c.take<uint8_t>(nTS + 1), o_ti = c.take<int32_t>(nTS + 1), o_ip = c.take<int64_t>(nJ + 1),
+               o_is = c.take<int64_t>(P.inj_src.size() + 1), o_isp = c.take<int64_t>(nI + 1),
+               o_rb = c.take<int64_t>(nR + 1), o_rf = c.take<int64_t>(nR + 1), o_cg = c.take<int64_t>(nC + 1),
+               o_cb = c.take<int64_t>(nC + 1), o_ce = c.take<int64_t>(nC + 1),
+               o_fa = c.take<double>((size_t)(1 + nTS + nIS) * D), o_ba = c.take<double>((size_t)(nTS + nIS + 1) * D),
+               o_ia = c.take<double>((size_t)(nI + 1) * D), o_tad = c.take<double>((size_t)(nT + 1) * D),
+               o_inj = c.take<double>((size_t)(nJ + 1) * D);
+  int rc = d.buf.reserve(c.off + 256, r->ctx->stream);
+  if (rc) return rc;
+  char* b = reinterpret_cast<char*>(d.buf.p);
+  d.items = reinterpret_cast<int64_t*>(b + o_items);
+  d.trunk_ptr = reinterpret_cast<int64_t*>(b + o_tp);
+  d.trunk_anchor = reinterpret_cast<int64_t*>(b + o_ta);
+  d.trunk_gates = reinterpret_cast<uint8_t*>(b + o_tg);
+  d.trunk_inj = reinterpret_cast<int32_t*>(b + o_ti);
+  d.inj_ptr = reinterpret_cast<int64_t*>(b + o_ip);
+  d.inj_src = reinterpret_cast<int64_t*>(b + o_is);
+  d.item_step_ptr = reinterpret_cast<int64_t*>(b + o_isp);
+  d.rec_b = reinterpret_cast<int64_t*>(b + o_rb);
+  d.rec_f = reinterpret_cast<int64_t*>(b + o_rf);
+  d.chunk_gate = reinterpret_cast<int64_t*>(b + o_cg);
+  d.chunk_beg = reinterpret_cast<int64_t*>(b + o_cb);
+  d.chunk_end = reinterpret_cast<int64_t*>(b + o_ce);
+  d.FA = reinterpret_cast<double*>(b + o_fa);
+  d.BA = reinterpret_cast<double*>(b + o_ba);
+  d.item_adj = reinterpret_cast<double*>(b + o_ia);
+  d.trunk_adj = reinterpret_cast<double*>(b + o_tad);
+  d.inj = reinterpret_cast<double*>(b + o_inj);
+  auto put = [&](void* dst, const void* src, size_t bytes) -> int {
+    if (bytes) HIP_TRY(hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice));
+    return GST_OK;
+  };
+  if ((rc = put(d.items, P.items.data(), P.items.size() * 8))) return rc;
+  if ((rc = put(d.trunk_ptr, P.trunk_ptr.data(), P.trunk_ptr.size() * 8))) return rc;
+  if ((rc = put(d.trunk_anchor, P.trunk_anchor.data(), P.trunk_anchor.size() * 8))) return rc;
+  if ((rc = put(d.trunk_gates, P.trunk_gates.data(), P.trunk_gates.size()))) return rc;
+  if ((rc = put(d.trunk_inj, P.trunk_inj.data(), P.trunk_inj.size() * 4))) return rc;
+  if ((rc = put(d.inj_ptr, P.inj_ptr.data(), P.inj_ptr.size() * 8))) return rc;
+  if ((rc = put(d.inj_src, P.inj_src.data(), P.inj_src.size() * 8))) return rc;
+  if ((rc = put(d.item_step_ptr, P.item_step_ptr.data(), P.item_step_ptr.size() * 8))) return rc;
+  if ((rc = put(d.rec_b, P.rec_b.data(), P.rec_b.size() * 8))) return rc;
+  if ((rc = put(d.rec_f, P.rec_f.data(), P.rec_f.size() * 8))) return rc;
+  if ((rc = put(d.chunk_gate, P.chunk_gate.data(), P.chunk_gate.size() * 8))) return rc;
+  if ((rc = put(d.chunk_beg, P.chunk_beg.data(), P.chunk_beg.size() * 8))) return rc;
+  if ((rc = put(d.chunk_end, P.chunk_end.data(), P.chunk_end.size() * 8))) return rc;
+  // injection slots of each level: slots of stored locations are sorted by
+  // location (the root slot comes last) and a level's locations are contiguous
+  d.inj_level_ptr.assign(P.n_levels + 1, 0);
+  const auto loc_end = P.inj_loc.begin() + P.root_slot;
+  for (int l = 0; l <= P.n_levels; ++l) {
+    const int64_t loc = P.trunk_ptr[P.trunk_level_ptr[l]];
+    d.inj_level_ptr[l] = std::lower_bound(P.inj_loc.begin(), loc_end, loc) - P.inj_loc.begin();
+  }
+  d.inj_level_ptr[P.n_levels] = P.root_slot;
+  d.used = true;
+  return GST_OK;
+}
+
+// One evaluation with the sharing plan: trunks forward (per level), items,
+// injections and trunks backward (deepest level first), the gradient GEMM
+// over all stored steps, and the slab reduction.
+int run_plan(gst_req* r, const gst_gateset* th, int mode, const double* w, double* probs, double* objective,
+             double* grad) {
+  gst_ctx* ctx = r->ctx;
+  const DevicePlan& d = r->plan;
+  const gst::HostPlan& P = d.host;
+  const int D = r->D;
+  const bool want_grad = grad != nullptr;
+  const bool need_slab = want_grad || mode == gst::MODE_LOGLIK;
+  const int64_t Pw = gst::slab_width(D, r->M, r->K);
+  const int item_blocks = gst::item_blocks_for(P.n_items());
+  const int n_slabs = need_slab ? item_blocks + (want_grad ? (int)P.n_chunks() : 0) : 0;
+  const size_t slab_bytes = (size_t)n_slabs * Pw * 8;
+  const size_t part_bytes = need_slab ? (size_t)gst::reduce_parts(n_slabs) * Pw * 8 : 0;
+  int rc = r->ws.reserve(slab_bytes + part_bytes + 256, ctx->stream);
+  if (rc) return rc;
+  double* slab = reinterpret_cast<double*>(r->ws.p);
+  double* part = reinterpret_cast<double*>((char*)r->ws.p + slab_bytes);
+
+  HIP_TRY(hipMemcpyAsync(d.FA, th->rho, sizeof(double) * D, hipMemcpyDeviceToDevice, ctx->stream));
+  gst::PlanArgs a{};
+  a.D = D;
+  a.M = r->M;
+  a.K = r->K;
+  a.rho = th->rho;
+  a.E = th->effects;
+  a.G = th->gates;
+  a.nTS = P.trunk_steps();
+  a.trunk_ptr = d.trunk_ptr;
+  a.trunk_anchor = d.trunk_anchor;
+  a.trunk_gates = d.trunk_gates;
+  a.trunk_inj = d.trunk_inj;
+  a.trunk_adj = d.trunk_adj;
+  a.n_items = P.n_items();
+  a.items = d.items;
+  a.item_step_ptr = d.item_step_ptr;
+  a.gates = r->gates;
+  a.item_adj = d.item_adj;
+  a.counts = r->counts;
+  a.W = w;
+  a.probs = probs;
+  a.mode = mode;
+  a.want_grad = want_grad;
+  a.FA = d.FA;
+  a.BA = d.BA;
+  a.inj = d.inj;
+  a.slab = slab;
+  a.status = ctx->status;
+  for (int l = 0; l < P.n_levels; ++l) {
+    a.t_begin = P.trunk_level_ptr[l];
+    a.t_end = P.trunk_level_ptr[l + 1];
+    ProfScope ps(ctx, FAM_TRUNK_FWD);
+    HIP_TRY(gst::launch_trunk_fwd(a, ctx->stream));
+  }
+  {
+    ProfScope ps(ctx, FAM_LEAF);
+    HIP_TRY(gst::launch_items(a, item_blocks, ctx->stream));
+  }
+  if (want_grad) {
+    gst::InjectLaunch in{};
+    in.D = D;
+    in.inj_ptr = d.inj_ptr;
+    in.inj_src = d.inj_src;
+    in.item_adj = d.item_adj;
+    in.trunk_adj = d.trunk_adj;
+    in.inj = d.inj;
+    for (int l = P.n_levels - 1; l >= 0; --l) {
+      in.s_begin = d.inj_level_ptr[l];
+      in.s_end = d.inj_level_ptr[l + 1];
+      {
+        ProfScope ps(ctx, FAM_INJECT);
+        HIP_TRY(gst::launch_inject(in, ctx->stream));
+      }
+      a.t_begin = P.trunk_level_ptr[l];
+      a.t_end = P.trunk_level_ptr[l + 1];
+      ProfScope ps(ctx, FAM_TRUNK_BWD);
+      HIP_TRY(gst::launch_trunk_bwd(a, ctx->stream));
+    }
+    in.s_begin = P.root_slot;
+    in.s_end = P.root_slot + 1;
+    {
+      ProfScope ps(ctx, FAM_INJECT);
+      HIP_TRY(gst::launch_inject(in, ctx->stream));
+    }
+    gst::GemmLaunch g{};
+    g.D = D;
+    g.M = r->M;
+    g.K = r->K;
+    g.n_chunks = P.n_chunks();
+    g.chunk_gate = d.chunk_gate;
+    g.chunk_beg = d.chunk_beg;
+    g.chunk_end = d.chunk_end;
+    g.rec_b = d.rec_b;
+    g.rec_f = d.rec_f;
+    g.FA = d.FA;
+    g.BA = d.BA;
+    g.slab = slab + (size_t)item_blocks * Pw;
+    ProfScope ps(ctx, FAM_GEMM);
+    HIP_TRY(gst::launch_grad_gemm(g, ctx->stream));
+  }
+  if (need_slab) {
+    ProfScope ps(ctx, FAM_REDUCE);
+    HIP_TRY(gst::launch_reduce(slab, n_slabs, Pw, objective, grad, ctx->status,
+                               want_grad ? d.inj + P.root_slot * D : nullptr, D, part, ctx->stream));
+  }
+  return GST_OK;
 }
 
 }  // namespace
@@ -246,6 +532,160 @@ int gst_vjp(gst_ctx* ctx, const gst_gateset* gs, const gst_seqlist* seqs, const 
   if (!grad) return fail(GST_EINVAL, "grad is NULL");
   if (seqs && seqs->n_seq > 0 && !w) return fail(GST_EINVAL, "w is NULL");
   return plain_eval(ctx, gs, seqs, gst::MODE_VJP, nullptr, w, nullptr, nullptr, grad);
+}
+
+int gst_profile_enable(gst_ctx* ctx, int enable) {
+  if (!ctx) return fail(GST_EINVAL, "ctx is NULL");
+  ctx->prof.on = enable != 0;
+  return GST_OK;
+}
+
+int gst_profile_read(gst_ctx* ctx, const char* kernel, double* total_ms, int64_t* launches) {
+  if (!ctx || !kernel) return fail(GST_EINVAL, "NULL argument");
+  int fam = -1;
+  for (int f = 0; f < FAM_N; ++f)
+    if (std::strcmp(kernel, kFamilyNames[f]) == 0) fam = f;
+  if (fam < 0) return fail(GST_EINVAL, std::string("unknown kernel family ") + kernel);
+  HIP_TRY(hipSetDevice(ctx->device));
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  for (auto& p : ctx->prof.pending) {
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, p.a, p.b));
+    ctx->prof.total_ms[p.family] += ms;
+    ctx->prof.launches[p.family] += 1;
+    ctx->prof.pool.push_back(p.a);
+    ctx->prof.pool.push_back(p.b);
+  }
+  ctx->prof.pending.clear();
+  if (total_ms) *total_ms = ctx->prof.total_ms[fam];
+  if (launches) *launches = ctx->prof.launches[fam];
+  return GST_OK;
+}
+
+int gst_req_create_host(gst_ctx* ctx, int n_qubits, int n_gates, int n_outcomes, const gst_seqlist* sl,
+                        const int32_t* counts_host, gst_req** out) {
+  if (!ctx || !out) return fail(GST_EINVAL, "NULL argument");
+  const int D = dim_of(n_qubits);
+  if (!D) return fail(GST_EINVAL, "n_qubits must be 1, 2 or 3");
+  if (n_gates < 1 || n_gates > gst_max_gates(n_qubits)) return fail(GST_EINVAL, "n_gates out of range");
+  if (n_outcomes < 1 || n_outcomes > D) return fail(GST_EINVAL, "n_outcomes must be in 1..D");
+  int rc = check_seqs(sl);
+  if (rc) return rc;
+  const int64_t S = sl->n_seq;
+  if (S > 0 && sl->offsets[0] != 0) return fail(GST_EINVAL, "offsets[0] != 0");
+  int64_t max_len = 0;
+  for (int64_t s = 0; s < S; ++s) {
+    const int64_t L = sl->offsets[s + 1] - sl->offsets[s];
+    if (L < 0) return fail(GST_EINVAL, "offsets decrease");
+    max_len = std::max(max_len, L);
+  }
+  const int64_t n_steps = S > 0 ? sl->offsets[S] : 0;
+  for (int64_t t = 0; t < n_steps; ++t)
+    if (sl->gate_idx[t] >= n_gates) return fail(GST_EINDEX, "gate index >= n_gates at step " + std::to_string(t));
+  if (counts_host)
+    for (int64_t x = 0; x < S * n_outcomes; ++x)
+      if (counts_host[x] < 0) return fail(GST_EINVAL, "negative count");
+  HIP_TRY(hipSetDevice(ctx->device));
+  std::unique_ptr<gst_req> r(new (std::nothrow) gst_req());
+  if (!r) return fail(GST_ENOMEM, "host allocation failed");
+  r->ctx = ctx;
+  r->n_qubits = n_qubits;
+  r->D = D;
+  r->M = n_outcomes;
+  r->K = n_gates;
+  r->S = S;
+  r->max_len = max_len;
+  const size_t b_off = (size_t)(S + 1) * 8, b_g = (size_t)std::max<int64_t>(n_steps, 1),
+               b_c = counts_host ? (size_t)S * n_outcomes * 4 : 0;
+  rc = r->data.reserve(b_off + b_g + b_c + 64, ctx->stream);
+  if (rc) return rc;
+  char* base = reinterpret_cast<char*>(r->data.p);
+  r->offsets = reinterpret_cast<int64_t*>(base);
+  r->gates = reinterpret_cast<uint8_t*>(base + b_off);
+  r->counts = counts_host ? reinterpret_cast<int32_t*>(base + ((b_off + b_g + 15) / 16) * 16) : nullptr;
+  std::vector<int64_t> zero_off(1, 0);
+  HIP_TRY(hipMemcpy(r->offsets, S > 0 ? sl->offsets : zero_off.data(), b_off, hipMemcpyHostToDevice));
+  if (n_steps > 0) HIP_TRY(hipMemcpy(r->gates, sl->gate_idx, (size_t)n_steps, hipMemcpyHostToDevice));
+  if (counts_host && b_c) HIP_TRY(hipMemcpy(r->counts, counts_host, b_c, hipMemcpyHostToDevice));
+  if (S > 0 && D <= 16) {
+    gst::HostPlan hp;
+    gst::PlanOptions opt;
+    if (gst::build_plan(sl->offsets, sl->gate_idx, S, n_gates, opt, &hp)) {
+      rc = upload_plan(r.get(), hp);
+      if (rc) return rc;
+    }
+  }
+  r->resident_bytes = r->data.bytes + r->plan.buf.bytes;
+  *out = r.release();
+  return GST_OK;
+}
+
+int gst_req_footprint(const gst_req* req, size_t* bytes) {
+  if (!req || !bytes) return fail(GST_EINVAL, "NULL argument");
+  *bytes = req->resident_bytes + req->ws.bytes;
+  return GST_OK;
+}
+
+static int req_run(gst_req* r, const gst_gateset* th, int mode, const double* w, double* probs, double* objective,
+                   double* grad) {
+  if (!r) return fail(GST_EINVAL, "req is NULL");
+  int D = 0;
+  int rc = check_gateset(th, &D);
+  if (rc) return rc;
+  if (th->n_qubits != r->n_qubits || th->n_gates != r->K || th->n_outcomes != r->M)
+    return fail(GST_EINVAL, "gate set does not match the request");
+  if (mode == gst::MODE_LOGLIK && !r->counts) return fail(GST_EINVAL, "request has no counts");
+  gst_ctx* ctx = r->ctx;
+  HIP_TRY(hipSetDevice(ctx->device));
+  if (r->plan.used) return run_plan(r, th, mode, w, probs, objective, grad);
+  gst::LeafLaunch a{};
+  a.D = D;
+  a.M = r->M;
+  a.K = r->K;
+  a.rho = th->rho;
+  a.E = th->effects;
+  a.G = th->gates;
+  a.n_items = r->S;
+  a.off = r->offsets;
+  a.gates = r->gates;
+  a.counts = r->counts;
+  a.W = w;
+  a.probs = probs;
+  a.mode = mode;
+  a.want_grad = grad != nullptr;
+  return run_leaf(ctx, r->ws, a, r->max_len, objective, grad);
+}
+
+int gst_req_eval(gst_req* req, const gst_gateset* theta, double* probs, double* objective, double* grad) {
+  if (!objective) return fail(GST_EINVAL, "objective is NULL");
+  return req_run(req, theta, gst::MODE_LOGLIK, nullptr, probs, objective, grad);
+}
+
+int gst_req_probs(gst_req* req, const gst_gateset* theta, double* probs) {
+  if (!probs && req && req->S > 0) return fail(GST_EINVAL, "probs is NULL");
+  return req_run(req, theta, gst::MODE_PROBS, nullptr, probs, nullptr, nullptr);
+}
+
+int gst_req_vjp(gst_req* req, const gst_gateset* theta, const double* w, double* grad) {
+  if (!grad || (req && req->S > 0 && !w)) return fail(GST_EINVAL, "NULL argument");
+  return req_run(req, theta, gst::MODE_VJP, w, nullptr, nullptr, grad);
+}
+
+int gst_req_plan_info(const gst_req* req, int64_t* info, int n) {
+  if (!req || !info || n < 1) return fail(GST_EINVAL, "NULL argument");
+  const gst::HostPlan& P = req->plan.host;
+  int64_t vals[8] = {req->plan.used ? 1 : 0, P.sum_len, P.n_nodes, P.n_trunks(), P.trunk_steps(),
+                     P.item_steps(), P.n_levels, (int64_t)P.inj_loc.size()};
+  for (int x = 0; x < n && x < 8; ++x) info[x] = vals[x];
+  return GST_OK;
+}
+
+int gst_req_destroy(gst_req* req) {
+  if (!req) return GST_OK;
+  (void)hipSetDevice(req->ctx->device);
+  (void)hipStreamSynchronize(req->ctx->stream);
+  delete req;
+  return GST_OK;
 }
 
 }  // extern "C"

@@ -1,0 +1,330 @@
+// Device-side helpers shared by the kernels of the one- and two-qubit path.
+// Included by exactly the .hip files of this library; everything is internal.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "gst_internal.h"
+
+namespace gst {
+namespace {
+
+constexpr int TEAM = 16;               // lanes per chain
+constexpr int WAVES = 4;               // waves per workgroup
+constexpr int TPW = 64 / TEAM;         // chains per wave
+constexpr int ROW = 18;                // padded LDS row stride in doubles
+constexpr int GATE_STRIDE = 16 * ROW;  // doubles per gate matrix in LDS
+constexpr int KMAX = 8;                // gates accumulated on chip
+constexpr int C = 8;                   // steps per reverse segment (checkpoint interval)
+constexpr int ENT = TPW * C;           // stash entries per wave (<= 64)
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+// ---------------------------------------------------------------------------
+// cross-lane helpers
+// ---------------------------------------------------------------------------
+template <int J>
+__device__ __forceinline__ int bcast_i32(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, 0x150 + J, 0xF, 0xF, false);
+}
+
+template <int J>
+__device__ __forceinline__ double bcast_f64(double v) {
+  long long x = __double_as_longlong(v);
+  int lo = __builtin_amdgcn_update_dpp(0, (int)x, 0x150 + J, 0xF, 0xF, false);
+  int hi = __builtin_amdgcn_update_dpp(0, (int)(x >> 32), 0x150 + J, 0xF, 0xF, false);
+  return __longlong_as_double((long long)(unsigned)lo | ((long long)hi << 32));
+}
+
+// acc = fma(r[15], x@15, ... fma(r[1], x@1, fma(r[0], x@0, 0.0))) where x@j is
+// x in lane j of this 16-lane row (DPP row_newbcast).  The leading s_nop
+// covers the VALU-write -> DPP-read hazard on x.
+__device__ __forceinline__ double dot16_bcast(double x, const double2* __restrict__ row) {
+  const double2 a0 = row[0], a1 = row[1], a2 = row[2], a3 = row[3];
+  const double2 a4 = row[4], a5 = row[5], a6 = row[6], a7 = row[7];
+  double acc = 0.0;
+  asm volatile(
+      "s_nop 1\n\t"
+      "v_fmac_f64_dpp %0, %1, %2 row_newbcast:0 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f64_dpp %0, %1, %3 row_newbcast:1 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f64_dpp %0, %1, %4 row_newbcast:2 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f64_dpp %0, %1, %5 row_newbcast:3 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f64_dpp %0, %1, %6 row_newbcast:4 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f64_dpp %0, %1, %7 row_newbcast:5 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f64_dpp %0, %1, %8 row_newbcast:6 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f64_dpp %0, %1, %9 row_newbcast:7 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f64_dpp %0, %1, %10 row_newbcast:8 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f64_dpp %0, %1, %11 row_newbcast:9 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f64_dpp %0, %1, %12 row_newbcast:10 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f64_dpp %0, %1, %13 row_newbcast:11 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f64_dpp %0, %1, %14 row_newbcast:12 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f64_dpp %0, %1, %15 row_newbcast:13 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f64_dpp %0, %1, %16 row_newbcast:14 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f64_dpp %0, %1, %17 row_newbcast:15 row_mask:0xf bank_mask:0xf"
+      : "+v"(acc)
+      : "v"(x), "v"(a0.x), "v"(a0.y), "v"(a1.x), "v"(a1.y), "v"(a2.x), "v"(a2.y), "v"(a3.x),
+        "v"(a3.y), "v"(a4.x), "v"(a4.y), "v"(a5.x), "v"(a5.y), "v"(a6.x), "v"(a6.y), "v"(a7.x),
+        "v"(a7.y));
+  return acc;
+}
+
+// A 16-double row held in registers (eight 16-byte LDS reads).
+struct Row16 {
+  double2 a0, a1, a2, a3, a4, a5, a6, a7;
+};
+
+__device__ __forceinline__ Row16 load_row(const double* p) {
+  const double2* r = reinterpret_cast<const double2*>(p);
+  Row16 x;
+  x.a0 = r[0];
+  x.a1 = r[1];
+  x.a2 = r[2];
+  x.a3 = r[3];
+  x.a4 = r[4];
+  x.a5 = r[5];
+  x.a6 = r[6];
+  x.a7 = r[7];
+  return x;
+}
+
+// Same as dot16_bcast with the row already in registers.
+__device__ __forceinline__ double dot16(double x, const Row16& r) {
+  double acc = 0.0;
+  asm volatile(
+      "s_nop 1\n\t"
+      "v_fmac_f64_dpp %0, %1, %2 row_newbcast:0 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f64_dpp %0, %1, %3 row_newbcast:1 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f64_dpp %0, %1, %4 row_newbcast:2 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f64_dpp %0, %1, %5 row_newbcast:3 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f64_dpp %0, %1, %6 row_newbcast:4 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f64_dpp %0, %1, %7 row_newbcast:5 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f64_dpp %0, %1, %8 row_newbcast:6 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f64_dpp %0, %1, %9 row_newbcast:7 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f64_dpp %0, %1, %10 row_newbcast:8 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f64_dpp %0, %1, %11 row_newbcast:9 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f64_dpp %0, %1, %12 row_newbcast:10 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f64_dpp %0, %1, %13 row_newbcast:11 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f64_dpp %0, %1, %14 row_newbcast:12 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f64_dpp %0, %1, %15 row_newbcast:13 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f64_dpp %0, %1, %16 row_newbcast:14 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f64_dpp %0, %1, %17 row_newbcast:15 row_mask:0xf bank_mask:0xf"
+      : "+v"(acc)
+      : "v"(x), "v"(r.a0.x), "v"(r.a0.y), "v"(r.a1.x), "v"(r.a1.y), "v"(r.a2.x), "v"(r.a2.y), "v"(r.a3.x),
+        "v"(r.a3.y), "v"(r.a4.x), "v"(r.a4.y), "v"(r.a5.x), "v"(r.a5.y), "v"(r.a6.x), "v"(r.a6.y), "v"(r.a7.x),
+        "v"(r.a7.y));
+  return acc;
+}
+
+// Sum over j of r[j] * x@j as four interleaved partial chains (j mod 4),
+// combined as (s0 + s1) + (s2 + s3): a quarter of the dependent latency of
+// dot16.  Used only where the summation order is free (adjoints).
+__device__ __forceinline__ double dot16_split(double x, const Row16& r) {
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  asm volatile(
+      "s_nop 1\n\t"
+      "v_fmac_f64_dpp %0, %4, %5 row_newbcast:0 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f64_dpp %1, %4, %6 row_newbcast:1 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f64_dpp %2, %4, %7 row_newbcast:2 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f64_dpp %3, %4, %8 row_newbcast:3 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f64_dpp %0, %4, %9 row_newbcast:4 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f64_dpp %1, %4, %10 row_newbcast:5 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f64_dpp %2, %4, %11 row_newbcast:6 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f64_dpp %3, %4, %12 row_newbcast:7 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f64_dpp %0, %4, %13 row_newbcast:8 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f64_dpp %1, %4, %14 row_newbcast:9 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f64_dpp %2, %4, %15 row_newbcast:10 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f64_dpp %3, %4, %16 row_newbcast:11 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f64_dpp %0, %4, %17 row_newbcast:12 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f64_dpp %1, %4, %18 row_newbcast:13 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f64_dpp %2, %4, %19 row_newbcast:14 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f64_dpp %3, %4, %20 row_newbcast:15 row_mask:0xf bank_mask:0xf"
+      : "+v"(s0), "+v"(s1), "+v"(s2), "+v"(s3)
+      : "v"(x), "v"(r.a0.x), "v"(r.a0.y), "v"(r.a1.x), "v"(r.a1.y), "v"(r.a2.x), "v"(r.a2.y), "v"(r.a3.x),
+        "v"(r.a3.y), "v"(r.a4.x), "v"(r.a4.y), "v"(r.a5.x), "v"(r.a5.y), "v"(r.a6.x), "v"(r.a6.y), "v"(r.a7.x),
+        "v"(r.a7.y));
+  return (s0 + s1) + (s2 + s3);
+}
+
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// max over the four 16-lane rows of a wave, as a wave-uniform value
+__device__ __forceinline__ int wave_max4(int v) {
+  v = max(v, __shfl_xor(v, 16));
+  v = max(v, __shfl_xor(v, 32));
+  return __builtin_amdgcn_readfirstlane(v);
+}
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// ---------------------------------------------------------------------------
+// LDS layout (doubles): Gs[K][16][ROW] | GTs[K][16][ROW] | Es[16][ROW] | ETs[16][ROW] |
+//   rho[16] | per wave stash: b[ENT][16], f[ENT][16] | stash gate bytes [WAVES][ENT]
+// ---------------------------------------------------------------------------
+struct Lds {
+  double* Gs;
+  double* GTs;
+  double* Es;
+  double* ETs;
+  double* rho;
+  double* stash;
+  uint8_t* sk;
+};
+
+__host__ __device__ inline size_t lds_main_bytes(int K) {
+  size_t d = (size_t)2 * K * GATE_STRIDE + 2 * 16 * ROW + 16 + (size_t)WAVES * 2 * ENT * 16;
+  return d * 8 + (size_t)WAVES * ENT;
+}
+
+__host__ __device__ inline size_t lds_red_bytes(int K) {
+  return (size_t)WAVES * (1 + 16 + 256 + (size_t)K * 256) * 8;
+}
+
+__host__ inline size_t lds_bytes(int K) {
+  const size_t a = lds_main_bytes(K), b = lds_red_bytes(K);
+  return a > b ? a : b;
+}
+
+__device__ __forceinline__ Lds carve(double* base, int K) {
+  Lds l;
+  l.Gs = base;
+  l.GTs = l.Gs + (size_t)K * GATE_STRIDE;
+  l.Es = l.GTs + (size_t)K * GATE_STRIDE;
+  l.ETs = l.Es + 16 * ROW;
+  l.rho = l.ETs + 16 * ROW;
+  l.stash = l.rho + 16;
+  l.sk = reinterpret_cast<uint8_t*>(l.stash + (size_t)WAVES * 2 * ENT * 16);
+  return l;
+}
+
+// Gate set into LDS, zero-padded to 16 x 16.
+template <int D>
+__device__ void stage_gateset(const Lds& s, const double* __restrict__ G, const double* __restrict__ E,
+                              const double* __restrict__ rho, int K, int M) {
+  const int tid = threadIdx.x;
+  for (int x = tid; x < K * 16 * ROW; x += blockDim.x) {
+    const int k = x / (16 * ROW), r = (x / ROW) % 16, c = x % ROW;
+    double g = 0.0, gt = 0.0;
+    if (r < D && c < D) {
+      g = G[((size_t)k * D + r) * D + c];
+      gt = G[((size_t)k * D + c) * D + r];
+    }
+    s.Gs[x] = g;
+    s.GTs[x] = gt;
+  }
+  for (int x = tid; x < 16 * ROW; x += blockDim.x) {
+    const int r = x / ROW, c = x % ROW;
+    s.Es[x] = (r < M && c < D) ? E[(size_t)r * D + c] : 0.0;
+    s.ETs[x] = (c < M && r < D) ? E[(size_t)c * D + r] : 0.0;
+  }
+  if (tid < 16) s.rho[tid] = tid < D ? rho[tid] : 0.0;
+  __syncthreads();
+}
+
+__device__ __forceinline__ const double2* grow(const Lds& s, int k, int i) {
+  return reinterpret_cast<const double2*>(s.Gs + k * GATE_STRIDE + i * ROW);
+}
+__device__ __forceinline__ const double2* gtrow(const Lds& s, int k, int i) {
+  return reinterpret_cast<const double2*>(s.GTs + k * GATE_STRIDE + i * ROW);
+}
+
+// dG_k += sum over the wave's stashed steps with gate k of b f^T, four steps
+// per MFMA 16x16x4 (A[i][z] = b_z[i], B[z][j] = f_z[j]).
+__device__ __forceinline__ void flush_stash(const double* st_b, const double* st_f, const uint8_t* st_k, int K,
+                                            d4 (&acc)[KMAX], int lane) {
+  const int i = lane & 15;
+  const int my_k = lane < ENT ? (int)st_k[lane] : 0xFF;
+#pragma unroll
+  for (int k = 0; k < KMAX; ++k) {
+    if (k < K) {
+      unsigned long long mask = __ballot(my_k == k);
+      while (mask) {
+        int e4[4];
+#pragma unroll
+        for (int z = 0; z < 4; ++z) {
+          if (mask) {
+            e4[z] = __ffsll((long long)mask) - 1;
+            mask &= mask - 1;
+          } else {
+            e4[z] = -1;
+          }
+        }
+        const int sel = lane >> 4;
+        const int e = sel == 0 ? e4[0] : sel == 1 ? e4[1] : sel == 2 ? e4[2] : e4[3];
+        const double av = e >= 0 ? st_b[e * 16 + i] : 0.0;
+        const double bv = e >= 0 ? st_f[e * 16 + i] : 0.0;
+        acc[k] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[k], 0, 0, 0);
+      }
+    }
+  }
+}
+
+// Adds the four chains of each wave and the four waves, writes one slab
+// [objective | drho (D) | dE (M*D) | dG (K*D*D)] for this workgroup.
+template <int D>
+__device__ void write_slab(double* lds_raw, double obj, double drho, double (&dE)[16], d4 (&acc)[KMAX], int M,
+                           int K, double* slab) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  __syncthreads();  // LDS is reused from here on
+  const int P16 = 1 + 16 + 256 + K * 256;
+  double* mine = lds_raw + (size_t)wave * P16;
+  double o = obj;
+#pragma unroll
+  for (int sh = 1; sh < 64; sh <<= 1) o += __shfl_xor(o, sh);
+  double dr = drho;
+  dr += __shfl_xor(dr, 16);
+  dr += __shfl_xor(dr, 32);
+#pragma unroll
+  for (int m = 0; m < 16; ++m) {
+    dE[m] += __shfl_xor(dE[m], 16);
+    dE[m] += __shfl_xor(dE[m], 32);
+  }
+  if (lane == 0) mine[0] = o;
+  if (lane < 16) {
+    mine[1 + lane] = dr;
+#pragma unroll
+    for (int m = 0; m < 16; ++m) mine[17 + m * 16 + lane] = dE[m];
+  }
+  // tile element C[r][c] sits in lane 16*(r&3)+c, register r>>2
+#pragma unroll
+  for (int k = 0; k < KMAX; ++k) {
+    if (k < K) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = 4 * v + (lane >> 4), c = lane & 15;
+        mine[273 + k * 256 + r * 16 + c] = acc[k][v];
+      }
+    }
+  }
+  __syncthreads();
+  const int64_t P = slab_width(D, M, K);
+  double* out = slab + (int64_t)blockIdx.x * P;
+  const double* red = lds_raw;
+  for (int x = tid; x < P; x += blockDim.x) {
+    int src;
+    if (x == 0) {
+      src = 0;
+    } else if (x < 1 + D) {
+      src = x;
+    } else if (x < 1 + D + M * D) {
+      const int y = x - 1 - D;
+      src = 17 + (y / D) * 16 + (y % D);
+    } else {
+      const int y = x - 1 - D - M * D;
+      const int k = y / (D * D), r = (y / D) % D, c = y % D;
+      src = 273 + k * 256 + r * 16 + c;
+    }
+    double v = red[src];
+    v += red[P16 + src];
+    v += red[2 * P16 + src];
+    v += red[3 * P16 + src];
+    out[x] = v;
+  }
+}
+
+}  // namespace
+}  // namespace gst

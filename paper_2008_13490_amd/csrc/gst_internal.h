@@ -36,6 +36,77 @@ struct LeafLaunch {
   unsigned long long* status;  // [0] bad gate indices, [1] p <= 0 with N > 0
 };
 
+__host__ __device__ // Kernels of the shared-prefix plan.  Row conventions:
+//   state arena FA: row 0 = rho, row 1 + j = state after trunk step j,
+//                   row 1 + nTS + x = state before item step x;
+//   adjoint arena BA: row j = adjoint after trunk step j,
+//                     row nTS + x = adjoint after item step x.
+struct PlanArgs {
+  int D, M, K;
+  const double* rho;
+  const double* E;
+  const double* G;
+  int64_t nTS;                   // trunk steps
+  // trunks (level range t_begin..t_end)
+  int64_t t_begin, t_end;
+  const int64_t* trunk_ptr;      // [n_trunks + 1]
+  const int64_t* trunk_anchor;   // [n_trunks] location (state after trunk step), -1 = rho
+  const uint8_t* trunk_gates;    // [nTS]
+  const int32_t* trunk_inj;      // [nTS] injection slot of the state after the step, -1 none
+  double* trunk_adj;             // [n_trunks][D] adjoint arriving at the anchor
+  // items
+  int64_t n_items;
+  const int64_t* items;          // [n_items][4] seq, beg, end, anchor location
+  const int64_t* item_step_ptr;  // [n_items + 1]
+  const uint8_t* gates;          // sequence gate indices (beg/end index into it)
+  double* item_adj;              // [n_items][D]
+  const int32_t* counts;
+  const double* W;
+  double* probs;
+  int mode;
+  int want_grad;
+  // arenas and injections
+  double* FA;
+  double* BA;
+  const double* inj;             // [n_inj][D]
+  double* slab;
+  unsigned long long* status;
+};
+
+// inj[slot] = sum over its sources (ascending): item adjoints (src >= 0) and
+// trunk anchor adjoints (src = -(t+1)).
+struct InjectLaunch {
+  int D;
+  int64_t s_begin, s_end;
+  const int64_t* inj_ptr;
+  const int64_t* inj_src;
+  const double* item_adj;   // [n_items][D]
+  const double* trunk_adj;  // [n_trunks][D]
+  double* inj;              // [n_inj][D]
+};
+
+// dG from the reverse-sweep records: chunk c adds, for gate chunk_gate[c],
+// sum over records r in [chunk_beg[c], chunk_end[c]) of BA[rec_b[r]] FA[rec_f[r]]^T.
+struct GemmLaunch {
+  int D, M, K;
+  int64_t n_chunks;
+  const int64_t* chunk_gate;
+  const int64_t* chunk_beg;
+  const int64_t* chunk_end;
+  const int64_t* rec_b;
+  const int64_t* rec_f;
+  const double* FA;
+  const double* BA;
+  double* slab;  // [n_chunks][P]
+};
+
+hipError_t launch_trunk_fwd(const PlanArgs& a, hipStream_t stream);
+hipError_t launch_trunk_bwd(const PlanArgs& a, hipStream_t stream);
+hipError_t launch_items(const PlanArgs& a, int n_blocks, hipStream_t stream);
+int item_blocks_for(int64_t n_items);
+hipError_t launch_inject(const InjectLaunch& a, hipStream_t stream);
+hipError_t launch_grad_gemm(const GemmLaunch& a, hipStream_t stream);
+
 __host__ __device__ inline int64_t slab_width(int D, int M, int K) { return 1 + D + (int64_t)M * D + (int64_t)K * D * D; }
 
 hipError_t launch_leaf(const LeafLaunch& a, int n_blocks, hipStream_t stream);
@@ -44,10 +115,13 @@ int leaf_ckpt_interval(int D);
 int leaf_teams_per_block(int D);
 int max_gates_for(int D);
 
-// out[p] = sum_w slab[w][p] in ascending w; writes objective (p = 0) and the
-// gradient (p >= 1).  When status[1] > 0 the objective is +inf and grad is
-// left untouched.
-hipError_t launch_reduce(const double* slab, int n_slabs, int64_t P, double* objective,
-                         double* grad, const unsigned long long* status, hipStream_t stream);
+// out[p] = sum of slab[w][p] over w (fixed two-stage order) plus extra_rho on
+// the rho entries; writes objective (p = 0) and the gradient (p >= 1).  When
+// status[1] > 0 the objective is +inf and grad is left untouched.  `part`
+// holds reduce_parts(n_slabs) * P doubles of scratch.
+int reduce_parts(int n_slabs);
+hipError_t launch_reduce(const double* slab, int n_slabs, int64_t P, double* objective, double* grad,
+                         const unsigned long long* status, const double* extra_rho, int D, double* part,
+                         hipStream_t stream);
 
 }  // namespace gst

@@ -203,8 +203,48 @@ bool build_plan(const int64_t* off, const uint8_t* gates, int64_t S, int K, cons
   P.trunk_anchor_inj.assign(nT, -1);
   for (int64_t r = 0; r < nT; ++r)
     if (P.trunk_anchor[r] >= 0) P.trunk_anchor_inj[r] = P.trunk_inj[P.trunk_anchor[r]];
+  // root slot: everything anchored at rho
+  P.root_slot = (int64_t)P.inj_loc.size();
+  P.inj_loc.push_back(-1);
+  for (int64_t q = 0; q < S; ++q)
+    if (P.items[4 * q + 3] < 0) P.inj_src.push_back(q);
+  for (int64_t r = 0; r < nT; ++r)
+    if (P.trunk_anchor[r] < 0) P.inj_src.push_back(-(r + 1));
+  P.inj_ptr.push_back((int64_t)P.inj_src.size());
 
   if ((double)P.plan_steps() > opt.max_share_ratio * (double)P.sum_len) return false;
+
+  // ---- 6. reverse-sweep records, grouped by gate ----
+  P.item_step_ptr.assign(S + 1, 0);
+  for (int64_t q = 0; q < S; ++q) P.item_step_ptr[q + 1] = P.item_step_ptr[q] + (P.items[4 * q + 2] - P.items[4 * q + 1]);
+  if (P.item_steps() > opt.max_item_steps) return false;
+  const int64_t nTS = P.trunk_steps();
+  std::vector<std::vector<std::pair<int64_t, int64_t>>> by_gate(K);
+  for (int64_t r = 0; r < nT; ++r) {
+    const int64_t anchor_row = P.trunk_anchor[r] < 0 ? 0 : 1 + P.trunk_anchor[r];
+    for (int64_t j = P.trunk_ptr[r]; j < P.trunk_ptr[r + 1]; ++j)
+      by_gate[P.trunk_gates[j]].emplace_back(j, j == P.trunk_ptr[r] ? anchor_row : 1 + (j - 1));
+  }
+  for (int64_t q = 0; q < S; ++q) {
+    const int64_t beg = P.items[4 * q + 1], end = P.items[4 * q + 2];
+    for (int64_t x = beg; x < end; ++x) {
+      const int64_t row = P.item_step_ptr[q] + (x - beg);
+      by_gate[gates[x]].emplace_back(nTS + row, 1 + nTS + row);
+    }
+  }
+  P.rec_gate_ptr.assign(K + 1, 0);
+  for (int k = 0; k < K; ++k) {
+    for (auto& pr : by_gate[k]) {
+      P.rec_b.push_back(pr.first);
+      P.rec_f.push_back(pr.second);
+    }
+    P.rec_gate_ptr[k + 1] = (int64_t)P.rec_b.size();
+    for (int64_t c = P.rec_gate_ptr[k]; c < P.rec_gate_ptr[k + 1]; c += opt.chunk) {
+      P.chunk_gate.push_back(k);
+      P.chunk_beg.push_back(c);
+      P.chunk_end.push_back(std::min<int64_t>(c + opt.chunk, P.rec_gate_ptr[k + 1]));
+    }
+  }
   return true;
 }
 

@@ -46,10 +46,23 @@ struct HostPlan {
   std::vector<int64_t> inj_loc;          // [n_inj]
   std::vector<int64_t> inj_ptr;          // [n_inj + 1] ranges into inj_src
   std::vector<int64_t> inj_src;          // item indices (>= 0) or -(trunk index + 1)
+  // the last injection slot (location -1) collects the adjoints that reach rho
+  // (items and trunks anchored at rho): its value is dF/drho.
+  int64_t root_slot = -1;
+  // reverse-sweep records for the grouped gradient GEMM
+  //   state rows:   0 = rho, 1 + j = state after trunk step j,
+  //                 1 + trunk_steps + x = state before item step x
+  //   adjoint rows: j = after trunk step j, trunk_steps + x = after item step x
+  std::vector<int64_t> item_step_ptr;    // [n_items + 1] item step ranges
+  std::vector<int64_t> rec_b, rec_f;     // [n_rec] adjoint row, state row; grouped by gate
+  std::vector<int64_t> rec_gate_ptr;     // [K + 1]
+  std::vector<int64_t> chunk_gate, chunk_beg, chunk_end;  // record chunks of one gate each
   int64_t n_items() const { return (int64_t)items.size() / 4; }
   int64_t n_trunks() const { return (int64_t)trunk_anchor.size(); }
   int64_t trunk_steps() const { return (int64_t)trunk_gates.size(); }
   int64_t plan_steps() const;            // trunk steps + item steps
+  int64_t item_steps() const { return item_step_ptr.empty() ? 0 : item_step_ptr.back(); }
+  int64_t n_chunks() const { return (int64_t)chunk_gate.size(); }
 };
 
 struct PlanOptions {
@@ -57,6 +70,8 @@ struct PlanOptions {
   int reanchor_depth = 8;    // chains branching off at depth <= this restart from rho
   double max_share_ratio = 0.8;  // use the plan only if plan_steps <= ratio * sum_len
   int64_t max_nodes = 1LL << 26;
+  int64_t max_item_steps = 1LL << 24;   // bound on stored item-step states (memory)
+  int chunk = 512;                      // gradient GEMM records per chunk
 };
 
 // Builds the plan.  Returns false (plan unused: evaluate sequence by

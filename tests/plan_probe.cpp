@@ -1,0 +1,55 @@
+// Test helper: exposes the host sharing plan (paper_2008_13490_amd/csrc/gst_plan.*)
+// to Python through a C function, so the plan can be checked on the CPU.
+#include <cstring>
+
+#include "gst_plan.h"
+
+namespace {
+gst::HostPlan g_plan;
+}
+
+extern "C" int plan_build(const int64_t* off, const uint8_t* gates, int64_t S, int K, int min_trunk,
+                          int reanchor_depth, double ratio, int64_t* sizes) {
+  gst::PlanOptions opt;
+  opt.min_trunk = min_trunk;
+  opt.reanchor_depth = reanchor_depth;
+  opt.max_share_ratio = ratio;
+  const bool used = gst::build_plan(off, gates, S, K, opt, &g_plan);
+  const gst::HostPlan& P = g_plan;
+  sizes[0] = used;
+  sizes[1] = P.n_items();
+  sizes[2] = P.n_trunks();
+  sizes[3] = P.trunk_steps();
+  sizes[4] = (int64_t)P.inj_loc.size();
+  sizes[5] = (int64_t)P.inj_src.size();
+  sizes[6] = P.n_levels;
+  sizes[7] = P.n_nodes;
+  sizes[8] = P.sum_len;
+  sizes[9] = (int64_t)P.rec_b.size();
+  sizes[10] = P.root_slot;
+  sizes[11] = P.item_steps();
+  return 0;
+}
+
+extern "C" void plan_copy(int64_t* items, int64_t* trunk_ptr, int64_t* trunk_anchor, uint8_t* trunk_gates,
+                          int32_t* trunk_inj, int64_t* inj_loc, int64_t* inj_ptr, int64_t* inj_src,
+                          int64_t* level_ptr) {
+  const gst::HostPlan& P = g_plan;
+  std::memcpy(items, P.items.data(), P.items.size() * 8);
+  std::memcpy(trunk_ptr, P.trunk_ptr.data(), P.trunk_ptr.size() * 8);
+  std::memcpy(trunk_anchor, P.trunk_anchor.data(), P.trunk_anchor.size() * 8);
+  std::memcpy(trunk_gates, P.trunk_gates.data(), P.trunk_gates.size());
+  std::memcpy(trunk_inj, P.trunk_inj.data(), P.trunk_inj.size() * 4);
+  std::memcpy(inj_loc, P.inj_loc.data(), P.inj_loc.size() * 8);
+  std::memcpy(inj_ptr, P.inj_ptr.data(), P.inj_ptr.size() * 8);
+  std::memcpy(inj_src, P.inj_src.data(), P.inj_src.size() * 8);
+  std::memcpy(level_ptr, P.trunk_level_ptr.data(), P.trunk_level_ptr.size() * 8);
+}
+
+extern "C" void plan_copy_records(int64_t* item_step_ptr, int64_t* rec_b, int64_t* rec_f, int64_t* rec_gate_ptr) {
+  const gst::HostPlan& P = g_plan;
+  std::memcpy(item_step_ptr, P.item_step_ptr.data(), P.item_step_ptr.size() * 8);
+  std::memcpy(rec_b, P.rec_b.data(), P.rec_b.size() * 8);
+  std::memcpy(rec_f, P.rec_f.data(), P.rec_f.size() * 8);
+  std::memcpy(rec_gate_ptr, P.rec_gate_ptr.data(), P.rec_gate_ptr.size() * 8);
+}

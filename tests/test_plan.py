@@ -1,0 +1,248 @@
+"""The prefix-sharing plan, checked on the CPU.
+
+The plan (a trie of the sequences, thesis Eq. GSTFullFiducialsGerms: F_q g^l F_p
+shares F_p g^l between measurement fiducials and powers) is executed here by
+a small numpy interpreter that follows the same schedule as the kernels
+(trunks forward, items from stored states, injections, trunks backward) and
+compared with the oracle.  Probabilities must be bit-identical: the
+interpreter uses the same fused multiply-add order as the oracle, and sharing
+reuses identical operations.
+"""
+import ctypes
+import math
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+from paper_2008_13490_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+CSRC = os.path.join(ROOT, "paper_2008_13490_amd", "csrc")
+
+
+@pytest.fixture(scope="module")
+def planlib(tmp_path_factory):
+    out = str(tmp_path_factory.mktemp("plan") / "libplanprobe.so")
+    subprocess.run(["g++", "-std=c++17", "-O2", "-fPIC", "-shared", "-I", CSRC,
+                    os.path.join(ROOT, "tests", "plan_probe.cpp"), os.path.join(CSRC, "gst_plan.cpp"), "-o", out],
+                   check=True)
+    lib = ctypes.CDLL(out)
+    P = ctypes.c_void_p
+    lib.plan_build.argtypes = [P, P, ctypes.c_int64, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double, P]
+    lib.plan_copy.argtypes = [P] * 9
+    lib.plan_copy_records.argtypes = [P] * 4
+    return lib
+
+
+def get_plan(lib, sl, K, min_trunk=24, reanchor=8, ratio=0.8):
+    K = int(K)
+    sizes = np.zeros(12, np.int64)
+    off = np.ascontiguousarray(sl.offsets, np.int64)
+    g = np.ascontiguousarray(sl.gates if sl.gates.size else np.zeros(1, np.uint8), np.uint8)
+    lib.plan_build(off.ctypes.data, g.ctypes.data, sl.S, K, min_trunk, reanchor, ratio, sizes.ctypes.data)
+    used, nI, nT, nTS, nJ, nSrc, nL, nN, sumL, nR, root, nIS = [int(x) for x in sizes]
+    P = dict(used=bool(used), items=np.zeros((nI, 4), np.int64), trunk_ptr=np.zeros(nT + 1, np.int64),
+             trunk_anchor=np.zeros(nT, np.int64), trunk_gates=np.zeros(max(nTS, 1), np.uint8),
+             trunk_inj=np.zeros(max(nTS, 1), np.int32), inj_loc=np.zeros(max(nJ, 1), np.int64),
+             inj_ptr=np.zeros(nJ + 1, np.int64), inj_src=np.zeros(max(nSrc, 1), np.int64),
+             level_ptr=np.zeros(nL + 1, np.int64), n_nodes=nN, sum_len=sumL, n_levels=nL)
+    lib.plan_copy(*[P[k].ctypes.data for k in ["items", "trunk_ptr", "trunk_anchor", "trunk_gates", "trunk_inj",
+                                              "inj_loc", "inj_ptr", "inj_src", "level_ptr"]])
+    if used:
+        P["item_step_ptr"] = np.zeros(nI + 1, np.int64)
+        P["rec_b"] = np.zeros(max(nR, 1), np.int64)
+        P["rec_f"] = np.zeros(max(nR, 1), np.int64)
+        P["rec_gate_ptr"] = np.zeros(K + 1, np.int64)
+        lib.plan_copy_records(P["item_step_ptr"].ctypes.data, P["rec_b"].ctypes.data, P["rec_f"].ctypes.data,
+                              P["rec_gate_ptr"].ctypes.data)
+        P["rec_b"], P["rec_f"] = P["rec_b"][:nR], P["rec_f"][:nR]
+        P["root_slot"] = root
+    P["trunk_gates"] = P["trunk_gates"][:nTS]
+    P["trunk_inj"] = P["trunk_inj"][:nTS]
+    P["inj_loc"] = P["inj_loc"][:nJ]
+    P["inj_src"] = P["inj_src"][:nSrc]
+    return P
+
+
+_libm = ctypes.CDLL("libm.so.6")
+_libm.fma.argtypes = [ctypes.c_double] * 3
+_libm.fma.restype = ctypes.c_double
+fma = _libm.fma  # correctly rounded fused multiply-add (C99)
+
+
+def fma_matvec(G, f):
+    out = np.empty_like(f)
+    for i in range(len(f)):
+        acc = 0.0
+        for j in range(len(f)):
+            acc = fma(G[i, j], f[j], acc)
+        out[i] = acc
+    return out
+
+
+def run_plan(P, gs, sl, counts):
+    """Executes the plan: probabilities (same fma order) and gradient (float64)."""
+    D, M, K = gs.D, gs.M, gs.K
+    G, E, rho = gs.gates, gs.effects, gs.rho
+    nTS = len(P["trunk_gates"])
+    states = np.zeros((nTS, D))
+    tp, ta, tg = P["trunk_ptr"], P["trunk_anchor"], P["trunk_gates"]
+    for t in range(len(ta)):            # levels are in order of t
+        f = rho.copy() if ta[t] < 0 else states[ta[t]].copy()
+        for j in range(tp[t], tp[t + 1]):
+            f = fma_matvec(G[tg[j]], f)
+            states[j] = f
+    S = sl.S
+    probs = np.zeros((S, M))
+    grad_rho = np.zeros(D)
+    grad_E = np.zeros((M, D))
+    grad_G = np.zeros((K, D, D))
+    item_adj = np.zeros((len(P["items"]), D))
+    for q, (s, beg, end, anc) in enumerate(P["items"]):
+        f = rho.copy() if anc < 0 else states[anc].copy()
+        fs = [f]
+        for x in range(beg, end):
+            f = fma_matvec(G[sl.gates[x]], f)
+            fs.append(f)
+        for m in range(M):
+            acc = 0.0
+            for j in range(D):
+                acc = fma(E[m, j], f[j], acc)
+            probs[s, m] = acc
+        dp = np.where(counts[s] > 0, -counts[s] / np.where(probs[s] > 0, probs[s], 1.0), 0.0)
+        grad_E += np.outer(dp, f)
+        b = dp @ E
+        for x in range(end - 1, beg - 1, -1):
+            k = sl.gates[x]
+            grad_G[k] += np.outer(b, fs[x - beg])
+            b = G[k].T @ b
+        if anc < 0:
+            grad_rho += b
+        else:
+            item_adj[q] = b
+    trunk_adj = np.zeros((len(ta), D))
+    inj = np.zeros((len(P["inj_loc"]), D))
+    lp = P["level_ptr"]
+    for lvl in range(P["n_levels"] - 1, -1, -1):
+        for slot in range(len(P["inj_loc"])):
+            v = np.zeros(D)
+            for z in range(P["inj_ptr"][slot], P["inj_ptr"][slot + 1]):
+                src = P["inj_src"][z]
+                v += item_adj[src] if src >= 0 else trunk_adj[-src - 1]
+            inj[slot] = v
+        for t in range(lp[lvl], lp[lvl + 1]):
+            b = np.zeros(D)
+            for j in range(tp[t + 1] - 1, tp[t] - 1, -1):
+                if P["trunk_inj"][j] >= 0:
+                    b = b + inj[P["trunk_inj"][j]]
+                fprev = (rho if ta[t] < 0 else states[ta[t]]) if j == tp[t] else states[j - 1]
+                k = tg[j]
+                grad_G[k] += np.outer(b, fprev)
+                b = G[k].T @ b
+            if ta[t] < 0:
+                grad_rho += b
+            else:
+                trunk_adj[t] = b
+    # the gradient GEMM's view: arenas of states and adjoints, records grouped by gate
+    if "rec_b" in P:
+        nIS = int(P["item_step_ptr"][-1])
+        FA = np.zeros((1 + nTS + nIS, D))
+        BA = np.zeros((nTS + nIS, D))
+        FA[0] = rho
+        FA[1:1 + nTS] = states
+        item_adj2 = np.zeros((len(P["items"]), D))
+        for q, (s, beg, end, anc) in enumerate(P["items"]):
+            f = rho.copy() if anc < 0 else states[anc].copy()
+            row0 = int(P["item_step_ptr"][q])
+            for x in range(beg, end):
+                FA[1 + nTS + row0 + x - beg] = f
+                f = fma_matvec(G[sl.gates[x]], f)
+            dp = np.where(counts[s] > 0, -counts[s] / np.where(probs[s] > 0, probs[s], 1.0), 0.0)
+            b = dp @ E
+            for x in range(end - 1, beg - 1, -1):
+                BA[nTS + row0 + x - beg] = b
+                b = G[sl.gates[x]].T @ b
+            item_adj2[q] = b
+        tadj = np.zeros((len(ta), D))
+        inj2 = np.zeros((len(P["inj_loc"]), D))
+        for lvl in range(P["n_levels"] - 1, -1, -1):
+            for slot in range(len(P["inj_loc"])):
+                if P["inj_loc"][slot] < 0:
+                    continue
+                inj2[slot] = sum((item_adj2[src] if src >= 0 else tadj[-src - 1]
+                                  for src in P["inj_src"][P["inj_ptr"][slot]:P["inj_ptr"][slot + 1]]), np.zeros(D))
+            for t in range(lp[lvl], lp[lvl + 1]):
+                b = np.zeros(D)
+                for j in range(tp[t + 1] - 1, tp[t] - 1, -1):
+                    if P["trunk_inj"][j] >= 0:
+                        b = b + inj2[P["trunk_inj"][j]]
+                    BA[j] = b
+                    b = G[tg[j]].T @ b
+                tadj[t] = b
+        root = P["root_slot"]
+        drho = sum((item_adj2[src] if src >= 0 else tadj[-src - 1]
+                    for src in P["inj_src"][P["inj_ptr"][root]:P["inj_ptr"][root + 1]]), np.zeros(D))
+        dG2 = np.zeros((K, D, D))
+        gp = P["rec_gate_ptr"]
+        for k in range(K):
+            for r in range(gp[k], gp[k + 1]):
+                dG2[k] += np.outer(BA[P["rec_b"][r]], FA[P["rec_f"][r]])
+        scale = np.abs(grad_G).max()
+        assert np.abs(dG2 - grad_G).max() <= 1e-10 * scale
+        assert np.abs(drho - grad_rho).max() <= 1e-10 * np.abs(grad_rho).max()
+    return probs, np.concatenate([grad_rho, grad_E.ravel(), grad_G.ravel()])
+
+
+def test_plan_c1_structure_and_execution(planlib, oracle_lib):
+    w = W.structured_workload("c1")
+    P = get_plan(planlib, w.seqs, w.model.K)
+    assert P["used"]
+    # every sequence is one item; items are sorted by remaining length
+    assert sorted(P["items"][:, 0].tolist()) == list(range(w.seqs.S))
+    rem = P["items"][:, 2] - P["items"][:, 1]
+    assert np.all(np.diff(rem) <= 0)
+    steps = len(P["trunk_gates"]) + rem.sum()
+    assert steps < 0.2 * P["sum_len"]
+    gs = w.model
+    p, g = run_plan(P, gs, w.seqs, w.counts)
+    _, p_or, g_or, _, _ = oracle_lib.loglik(gs.rho, gs.effects, gs.gates, w.seqs.offsets, w.seqs.gates, w.counts)
+    assert np.array_equal(p, p_or)
+    assert np.abs(g - g_or).max() <= 1e-10 * np.abs(g_or).max()
+
+
+def test_plan_c2_sharing_ratio(planlib):
+    w = W.structured_workload("c2")
+    P = get_plan(planlib, w.seqs, w.model.K)
+    assert P["used"] and P["n_levels"] == 1
+    rem = P["items"][:, 2] - P["items"][:, 1]
+    steps = len(P["trunk_gates"]) + rem.sum()
+    # the germ chains dominate: sharing saves more than 10x
+    assert steps * 10 < P["sum_len"]
+    # every item starts at a stored state or at rho, and its remaining word is a suffix of its own word
+    for s, beg, end, anc in P["items"][::97]:
+        assert w.seqs.offsets[s] <= beg <= end == w.seqs.offsets[s + 1]
+
+
+def test_plan_multilevel_and_random(planlib, oracle_lib):
+    rng = np.random.default_rng(12)
+    # a long common prefix, then long branches at depth > reanchor depth: two levels
+    base = list(rng.integers(0, 3, 40))
+    words = [base + list(rng.integers(0, 3, int(rng.integers(20, 40)))) + list(rng.integers(0, 3, k))
+             for k in range(6) for _ in range(3)]
+    words += [base[:30 + k] for k in range(5)] + [[]]
+    sl = W.from_words(words)
+    gs = W.noisy_gateset("1q", 1e-3, 0.01, rng)
+    counts = rng.integers(0, 20, size=(sl.S, gs.M)).astype(np.int32)
+    counts[oracle_lib.probs(gs.rho, gs.effects, gs.gates, sl.offsets, sl.gates) <= 0] = 0
+    P = get_plan(planlib, sl, gs.K, min_trunk=8, reanchor=4, ratio=1.0)
+    assert P["used"] and P["n_levels"] >= 2
+    p, g = run_plan(P, gs, sl, counts)
+    _, p_or, g_or, _, _ = oracle_lib.loglik(gs.rho, gs.effects, gs.gates, sl.offsets, sl.gates, counts)
+    assert np.array_equal(p, p_or)
+    assert np.abs(g - g_or).max() <= 1e-10 * np.abs(g_or).max()
+    # random words share almost nothing: the plan is declined
+    wr = W.random_workload("2q", 300, 200, 3)
+    P = get_plan(planlib, wr.seqs, 6)
+    assert not P["used"]
