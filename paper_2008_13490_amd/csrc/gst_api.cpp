@@ -137,6 +137,15 @@ struct DevicePlan {
   int32_t* trunk_inj = nullptr;
   int64_t* inj_ptr = nullptr;
   int64_t* inj_src = nullptr;
+  int64_t* tinj_ptr = nullptr;
+  int32_t* tinj_step = nullptr;
+  int64_t* tinj_slot = nullptr;
+  int64_t* seg_ptr = nullptr;
+  int32_t* seg_start = nullptr;
+  int32_t* seg_count = nullptr;
+  uint32_t* seg_pattern = nullptr;
+  uint8_t* seg_gate3 = nullptr;
+  int64_t* seg_inj = nullptr;
   int64_t* item_step_ptr = nullptr;
   int64_t* rec_b = nullptr;
   int64_t* rec_f = nullptr;
@@ -288,7 +297,24 @@ int upload_plan(gst_req* r, const gst::HostPlan& P) {
   const int D = r->D;
   const int64_t nI = P.n_items(), nT = P.n_trunks(), nTS = P.trunk_steps(), nJ = (int64_t)P.inj_loc.size(),
                 nIS = P.item_steps(), nR = (int64_t)P.rec_b.size(), nC = P.n_chunks();
+  // injection list of each trunk, steps descending
+  std::vector<int64_t> tip(nT + 1, 0), tslot;
+  std::vector<int32_t> tstep;
+  for (int64_t t = 0; t < nT; ++t) {
+    for (int64_t j = P.trunk_ptr[t + 1] - 1; j >= P.trunk_ptr[t]; --j)
+      if (P.trunk_inj[j] >= 0) {
+        tstep.push_back((int32_t)(j - P.trunk_ptr[t]));
+        tslot.push_back(P.trunk_inj[j]);
+      }
+    tip[t + 1] = (int64_t)tslot.size();
+  }
   Carver c;
+  const size_t o_tip = c.take<int64_t>(nT + 1), o_tst = c.take<int32_t>(tstep.size() + 1),
+               o_tsl = c.take<int64_t>(tslot.size() + 1);
+  const size_t nSeg = P.seg_start.size();
+  const size_t o_sp = c.take<int64_t>(nT + 1), o_ss = c.take<int32_t>(nSeg + 1), o_sc = c.take<int32_t>(nSeg + 1),
+               o_spat = c.take<uint32_t>(nSeg + 1), o_sg3 = c.take<uint8_t>(nSeg + 1),
+               o_sinj = c.take<int64_t>(nSeg + 1);
   const size_t o_items = c.take<int64_t>(4 * nI), o_tp = c.take<int64_t>(nT + 1), o_ta = c.take<int64_t>(nT + 1),
                o_tg = c.take<uint8_t>(nTS + 1), o_ti = c.take<int32_t>(nTS + 1), o_ip = c.take<int64_t>(nJ + 1),
                o_is = c.take<int64_t>(P.inj_src.size() + 1), o_isp = c.take<int64_t>(nI + 1),
@@ -300,6 +326,15 @@ int upload_plan(gst_req* r, const gst::HostPlan& P) {
   int rc = d.buf.reserve(c.off + 256, r->ctx->stream);
   if (rc) return rc;
   char* b = reinterpret_cast<char*>(d.buf.p);
+  d.tinj_ptr = reinterpret_cast<int64_t*>(b + o_tip);
+  d.tinj_step = reinterpret_cast<int32_t*>(b + o_tst);
+  d.tinj_slot = reinterpret_cast<int64_t*>(b + o_tsl);
+  d.seg_ptr = reinterpret_cast<int64_t*>(b + o_sp);
+  d.seg_start = reinterpret_cast<int32_t*>(b + o_ss);
+  d.seg_count = reinterpret_cast<int32_t*>(b + o_sc);
+  d.seg_pattern = reinterpret_cast<uint32_t*>(b + o_spat);
+  d.seg_gate3 = reinterpret_cast<uint8_t*>(b + o_sg3);
+  d.seg_inj = reinterpret_cast<int64_t*>(b + o_sinj);
   d.items = reinterpret_cast<int64_t*>(b + o_items);
   d.trunk_ptr = reinterpret_cast<int64_t*>(b + o_tp);
   d.trunk_anchor = reinterpret_cast<int64_t*>(b + o_ta);
@@ -322,6 +357,15 @@ int upload_plan(gst_req* r, const gst::HostPlan& P) {
     if (bytes) HIP_TRY(hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice));
     return GST_OK;
   };
+  if ((rc = put(d.tinj_ptr, tip.data(), tip.size() * 8))) return rc;
+  if ((rc = put(d.tinj_step, tstep.data(), tstep.size() * 4))) return rc;
+  if ((rc = put(d.tinj_slot, tslot.data(), tslot.size() * 8))) return rc;
+  if ((rc = put(d.seg_ptr, P.seg_ptr.data(), P.seg_ptr.size() * 8))) return rc;
+  if ((rc = put(d.seg_start, P.seg_start.data(), P.seg_start.size() * 4))) return rc;
+  if ((rc = put(d.seg_count, P.seg_count.data(), P.seg_count.size() * 4))) return rc;
+  if ((rc = put(d.seg_pattern, P.seg_pattern.data(), P.seg_pattern.size() * 4))) return rc;
+  if ((rc = put(d.seg_gate3, P.seg_gate3.data(), P.seg_gate3.size()))) return rc;
+  if ((rc = put(d.seg_inj, P.seg_inj.data(), P.seg_inj.size() * 8))) return rc;
   if ((rc = put(d.items, P.items.data(), P.items.size() * 8))) return rc;
   if ((rc = put(d.trunk_ptr, P.trunk_ptr.data(), P.trunk_ptr.size() * 8))) return rc;
   if ((rc = put(d.trunk_anchor, P.trunk_anchor.data(), P.trunk_anchor.size() * 8))) return rc;
@@ -361,7 +405,13 @@ int run_plan(gst_req* r, const gst_gateset* th, int mode, const double* w, doubl
   const bool need_slab = want_grad || mode == gst::MODE_LOGLIK;
   const int64_t Pw = gst::slab_width(D, r->M, r->K);
   const int item_blocks = gst::item_blocks_for(P.n_items());
-  const int n_slabs = need_slab ? item_blocks + (want_grad ? (int)P.n_chunks() : 0) : 0;
+  std::vector<int> tb_blocks(P.n_levels), tb_at(P.n_levels);
+  int n_slabs = need_slab ? item_blocks + (want_grad ? (int)P.n_chunks() : 0) : 0;
+  for (int l = 0; l < P.n_levels; ++l) {
+    tb_blocks[l] = gst::trunk_blocks_for(P.trunk_level_ptr[l + 1] - P.trunk_level_ptr[l]);
+    tb_at[l] = n_slabs;
+    if (want_grad) n_slabs += tb_blocks[l];
+  }
   const size_t slab_bytes = (size_t)n_slabs * Pw * 8;
   const size_t part_bytes = need_slab ? (size_t)gst::reduce_parts(n_slabs) * Pw * 8 : 0;
   int rc = r->ws.reserve(slab_bytes + part_bytes + 256, ctx->stream);
@@ -369,7 +419,6 @@ int run_plan(gst_req* r, const gst_gateset* th, int mode, const double* w, doubl
   double* slab = reinterpret_cast<double*>(r->ws.p);
   double* part = reinterpret_cast<double*>((char*)r->ws.p + slab_bytes);
 
-  HIP_TRY(hipMemcpyAsync(d.FA, th->rho, sizeof(double) * D, hipMemcpyDeviceToDevice, ctx->stream));
   gst::PlanArgs a{};
   a.D = D;
   a.M = r->M;
@@ -383,6 +432,15 @@ int run_plan(gst_req* r, const gst_gateset* th, int mode, const double* w, doubl
   a.trunk_gates = d.trunk_gates;
   a.trunk_inj = d.trunk_inj;
   a.trunk_adj = d.trunk_adj;
+  a.tinj_ptr = d.tinj_ptr;
+  a.tinj_step = d.tinj_step;
+  a.tinj_slot = d.tinj_slot;
+  a.seg_ptr = d.seg_ptr;
+  a.seg_start = d.seg_start;
+  a.seg_count = d.seg_count;
+  a.seg_pattern = d.seg_pattern;
+  a.seg_gate3 = d.seg_gate3;
+  a.seg_inj = d.seg_inj;
   a.n_items = P.n_items();
   a.items = d.items;
   a.item_step_ptr = d.item_step_ptr;
@@ -425,14 +483,9 @@ int run_plan(gst_req* r, const gst_gateset* th, int mode, const double* w, doubl
       }
       a.t_begin = P.trunk_level_ptr[l];
       a.t_end = P.trunk_level_ptr[l + 1];
+      a.slab = slab + (size_t)tb_at[l] * Pw;
       ProfScope ps(ctx, FAM_TRUNK_BWD);
       HIP_TRY(gst::launch_trunk_bwd(a, ctx->stream));
-    }
-    in.s_begin = P.root_slot;
-    in.s_end = P.root_slot + 1;
-    {
-      ProfScope ps(ctx, FAM_INJECT);
-      HIP_TRY(gst::launch_inject(in, ctx->stream));
     }
     gst::GemmLaunch g{};
     g.D = D;
@@ -452,8 +505,7 @@ int run_plan(gst_req* r, const gst_gateset* th, int mode, const double* w, doubl
   }
   if (need_slab) {
     ProfScope ps(ctx, FAM_REDUCE);
-    HIP_TRY(gst::launch_reduce(slab, n_slabs, Pw, objective, grad, ctx->status,
-                               want_grad ? d.inj + P.root_slot * D : nullptr, D, part, ctx->stream));
+    HIP_TRY(gst::launch_reduce(slab, n_slabs, Pw, objective, grad, ctx->status, nullptr, D, part, ctx->stream));
   }
   return GST_OK;
 }

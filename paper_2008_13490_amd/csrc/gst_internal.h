@@ -54,6 +54,15 @@ struct PlanArgs {
   const uint8_t* trunk_gates;    // [nTS]
   const int32_t* trunk_inj;      // [nTS] injection slot of the state after the step, -1 none
   double* trunk_adj;             // [n_trunks][D] adjoint arriving at the anchor
+  const int64_t* tinj_ptr;       // [n_trunks + 1] injection list of each trunk
+  const int32_t* tinj_step;      // step index within the trunk, descending
+  const int64_t* tinj_slot;      // injection slot
+  const int64_t* seg_ptr;        // [n_trunks + 1] periodic segments of each trunk
+  const int32_t* seg_start;
+  const int32_t* seg_count;
+  const uint32_t* seg_pattern;
+  const uint8_t* seg_gate3;
+  const int64_t* seg_inj;        // injection slot at the segment's last step, -1 none
   // items
   int64_t n_items;
   const int64_t* items;          // [n_items][4] seq, beg, end, anchor location
@@ -104,6 +113,7 @@ hipError_t launch_trunk_fwd(const PlanArgs& a, hipStream_t stream);
 hipError_t launch_trunk_bwd(const PlanArgs& a, hipStream_t stream);
 hipError_t launch_items(const PlanArgs& a, int n_blocks, hipStream_t stream);
 int item_blocks_for(int64_t n_items);
+int trunk_blocks_for(int64_t n_trunks);
 hipError_t launch_inject(const InjectLaunch& a, hipStream_t stream);
 hipError_t launch_grad_gemm(const GemmLaunch& a, hipStream_t stream);
 

@@ -239,19 +239,26 @@ __global__ __launch_bounds__(256) void reduce_stage1(const double* __restrict__ 
   if (ty == 0 && p < P) part[(int64_t)g * P + p] = (red[0][tx] + red[1][tx]) + (red[2][tx] + red[3][tx]);
 }
 
-__global__ void reduce_stage2(const double* __restrict__ part, int n_part, int64_t P, double* objective,
-                              double* grad, const unsigned long long* __restrict__ status,
-                              const double* __restrict__ extra_rho, int D) {
+__global__ __launch_bounds__(256) void reduce_stage2(const double* __restrict__ part, int n_part, int64_t P,
+                                                     double* objective, double* grad,
+                                                     const unsigned long long* __restrict__ status,
+                                                     const double* __restrict__ extra_rho, int D) {
+  __shared__ double red[4][64];
   const bool nonpos = status && status[1] != 0;
-  for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < P; x += (int64_t)gridDim.x * blockDim.x) {
-    double v = 0.0;
-    for (int g = 0; g < n_part; ++g) v += part[(int64_t)g * P + x];
-    if (extra_rho && x >= 1 && x <= D) v += extra_rho[x - 1];
-    if (x == 0) {
-      if (objective) *objective = nonpos ? INFINITY : v;
-    } else if (grad && !nonpos) {
-      grad[x - 1] = v;
-    }
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  const int64_t x = (int64_t)blockIdx.x * 64 + tx;
+  double v = 0.0;
+  if (x < P)
+    for (int g = ty; g < n_part; g += 4) v += part[(int64_t)g * P + x];
+  red[ty][tx] = v;
+  __syncthreads();
+  if (ty != 0 || x >= P) return;
+  v = (red[0][tx] + red[1][tx]) + (red[2][tx] + red[3][tx]);
+  if (extra_rho && x >= 1 && x <= D) v += extra_rho[x - 1];
+  if (x == 0) {
+    if (objective) *objective = nonpos ? INFINITY : v;
+  } else if (grad && !nonpos) {
+    grad[x - 1] = v;
   }
 }
 
@@ -293,9 +300,8 @@ hipError_t launch_reduce(const double* slab, int n_slabs, int64_t P, double* obj
   const int per = (n_slabs + G - 1) / G;
   hipLaunchKernelGGL(reduce_stage1, dim3((unsigned)((P + 63) / 64), G), dim3(256), 0, stream, slab, n_slabs, P, per,
                      part);
-  int blocks = (int)((P + 255) / 256);
-  hipLaunchKernelGGL(reduce_stage2, dim3(blocks), dim3(256), 0, stream, part, G, P, objective, grad, status, extra_rho,
-                     D);
+  hipLaunchKernelGGL(reduce_stage2, dim3((unsigned)((P + 63) / 64)), dim3(256), 0, stream, part, G, P, objective, grad,
+                     status, extra_rho, D);
   return hipGetLastError();
 }
 

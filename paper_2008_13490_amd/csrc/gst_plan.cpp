@@ -200,14 +200,49 @@ bool build_plan(const int64_t* off, const uint8_t* gates, int64_t S, int K, cons
     P.trunk_inj[src[x].first] = slot;
     x = y;
   }
+  // ---- periodic segments of every trunk's gate word; a segment never runs
+  // past a step whose resulting state receives an injection, so injections
+  // happen only at segment ends ----
+  P.seg_ptr.assign(nT + 1, 0);
+  for (int64_t r = 0; r < nT; ++r) {
+    const int64_t base = P.trunk_ptr[r];
+    const uint8_t* w = P.trunk_gates.data() + base;
+    const int64_t L = P.trunk_ptr[r + 1] - base;
+    int64_t j = 0;
+    while (j < L) {
+      int64_t piece_end = j;  // last step of the injection-free piece starting at j
+      while (piece_end < L - 1 && P.trunk_inj[base + piece_end] < 0) ++piece_end;
+      const int64_t n = piece_end - j + 1;
+      int bp = 1;
+      int64_t bc = 1;
+      for (int p = 1; p <= 4 && p <= n; ++p) {
+        int64_t c = 1;
+        while ((c + 1) * p <= n && std::memcmp(w + j, w + j + c * p, p) == 0) ++c;
+        if (c * p > bc * bp) {
+          bp = p;
+          bc = c;
+        }
+      }
+      uint32_t pat = (uint32_t)bp;
+      for (int q = 0; q < bp && q < 3; ++q) pat |= (uint32_t)w[j + q] << (8 * (q + 1));
+      P.seg_start.push_back((int32_t)j);
+      P.seg_count.push_back((int32_t)bc);
+      P.seg_pattern.push_back(pat);
+      P.seg_gate3.push_back(bp == 4 ? w[j + 3] : 0);
+      const int64_t last = j + bp * bc - 1;
+      P.seg_inj.push_back(P.trunk_inj[base + last]);
+      j = last + 1;
+    }
+    P.seg_ptr[r + 1] = (int64_t)P.seg_start.size();
+  }
+
   P.trunk_anchor_inj.assign(nT, -1);
   for (int64_t r = 0; r < nT; ++r)
     if (P.trunk_anchor[r] >= 0) P.trunk_anchor_inj[r] = P.trunk_inj[P.trunk_anchor[r]];
-  // root slot: everything anchored at rho
+  // root slot: trunks anchored at rho (items anchored at rho add their
+  // adjoints to the per-workgroup partial sums of the item kernel)
   P.root_slot = (int64_t)P.inj_loc.size();
   P.inj_loc.push_back(-1);
-  for (int64_t q = 0; q < S; ++q)
-    if (P.items[4 * q + 3] < 0) P.inj_src.push_back(q);
   for (int64_t r = 0; r < nT; ++r)
     if (P.trunk_anchor[r] < 0) P.inj_src.push_back(-(r + 1));
   P.inj_ptr.push_back((int64_t)P.inj_src.size());

@@ -46,8 +46,8 @@ struct HostPlan {
   std::vector<int64_t> inj_loc;          // [n_inj]
   std::vector<int64_t> inj_ptr;          // [n_inj + 1] ranges into inj_src
   std::vector<int64_t> inj_src;          // item indices (>= 0) or -(trunk index + 1)
-  // the last injection slot (location -1) collects the adjoints that reach rho
-  // (items and trunks anchored at rho): its value is dF/drho.
+  // the last injection slot (location -1) collects the adjoints that trunks
+  // anchored at rho carry back (added to dF/drho).
   int64_t root_slot = -1;
   // reverse-sweep records for the grouped gradient GEMM
   //   state rows:   0 = rho, 1 + j = state after trunk step j,
@@ -57,6 +57,14 @@ struct HostPlan {
   std::vector<int64_t> rec_b, rec_f;     // [n_rec] adjoint row, state row; grouped by gate
   std::vector<int64_t> rec_gate_ptr;     // [K + 1]
   std::vector<int64_t> chunk_gate, chunk_beg, chunk_end;  // record chunks of one gate each
+  // each trunk's gate word as periodic segments: pattern of period 1..4 repeated
+  // `count` times (germ powers of Eq. GSTFullFiducialsGerms are such runs)
+  std::vector<int64_t> seg_ptr;          // [n_trunks + 1]
+  std::vector<int32_t> seg_start;        // step of the segment's first gate within its trunk
+  std::vector<int32_t> seg_count;        // repetitions of the pattern
+  std::vector<uint32_t> seg_pattern;     // period in bits 0..7, gates in bits 8..15, 16..23, 24..31 and
+  std::vector<uint8_t> seg_gate3;        // the fourth gate
+  std::vector<int64_t> seg_inj;          // injection slot of the state after the segment's last step, -1 none
   int64_t n_items() const { return (int64_t)items.size() / 4; }
   int64_t n_trunks() const { return (int64_t)trunk_anchor.size(); }
   int64_t trunk_steps() const { return (int64_t)trunk_gates.size(); }
@@ -71,7 +79,7 @@ struct PlanOptions {
   double max_share_ratio = 0.8;  // use the plan only if plan_steps <= ratio * sum_len
   int64_t max_nodes = 1LL << 26;
   int64_t max_item_steps = 1LL << 24;   // bound on stored item-step states (memory)
-  int chunk = 512;                      // gradient GEMM records per chunk
+  int chunk = 128;                      // gradient GEMM records per chunk (the kernel takes at most 128)
 };
 
 // Builds the plan.  Returns false (plan unused: evaluate sequence by

@@ -33,45 +33,101 @@ __device__ __forceinline__ double load_state(const double* FA, int64_t row, int 
 }
 
 // ---------------------------------------------------------------------------
-// trunk forward: one trunk per team
+// Trunk kernels: one trunk per wave.  The chains are latency bound.  Each
+// trunk's gate word comes as periodic segments (a pattern of 1..4 gates
+// repeated; germ powers are exactly this), so the rows of a segment's gates are
+// loaded into registers once and the steps of the segment run with no memory
+// access other than the store of the result.  Lanes 16..63 repeat the work of
+// lanes 0..15 (same rows, same inputs); only lanes 0..D-1 store.
 // ---------------------------------------------------------------------------
+constexpr int TI = 32;  // injection vectors staged per wave
+
+__host__ __device__ inline size_t trunk_lds_bytes(int K) {
+  const size_t head = ((size_t)2 * K * GATE_STRIDE + 2 * 16 * ROW + 16) * 8;
+  const size_t a = head + (size_t)WAVES * TI * 16 * 8 + 64;
+  const size_t r = lds_red_bytes(K);
+  return a > r ? a : r;
+}
+
+struct Seg {
+  int start, count, per, g0, g1, g2, g3;
+};
+
+__device__ __forceinline__ Seg load_seg(const PlanArgs& a, int64_t sg) {
+  Seg x;
+  const uint32_t pat = (uint32_t)uniform((int)a.seg_pattern[sg]);
+  x.start = uniform(a.seg_start[sg]);
+  x.count = uniform(a.seg_count[sg]);
+  x.per = (int)(pat & 0xffu);
+  x.g0 = (int)((pat >> 8) & 0xffu);
+  x.g1 = (int)((pat >> 16) & 0xffu);
+  x.g2 = (int)((pat >> 24) & 0xffu);
+  x.g3 = uniform((int)a.seg_gate3[sg]);
+  return x;
+}
+
 template <int D>
 __global__ __launch_bounds__(256) void trunk_fwd_kernel(const PlanArgs a) {
   extern __shared__ double lds_raw[];
   const int K = a.K;
   const Lds s = carve(lds_raw, K);
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, i = lane & 15, team = lane >> 4;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, i = lane & 15;
   stage_gateset<D>(s, a.G, a.E, a.rho, K, a.M);
-  const int64_t nT = a.t_end - a.t_begin;
-  const int64_t n_groups = (nT + TPW - 1) / TPW;
-  for (int64_t grp = (int64_t)blockIdx.x * WAVES + wave; grp < n_groups; grp += (int64_t)gridDim.x * WAVES) {
-    const int64_t t = a.t_begin + grp * TPW + team;
-    const bool has = t < a.t_end;
-    const int64_t beg = has ? a.trunk_ptr[t] : 0;
-    const int L = has ? (int)(a.trunk_ptr[t + 1] - beg) : 0;
-    const int Lw = wave_max4(L);
-    const int64_t anc = has ? a.trunk_anchor[t] : -1;
-    double f = load_state(a.FA, anc >= 0 ? 1 + anc : 0, D, i);
-    const uint8_t* word = a.trunk_gates + beg;
-    double* out = a.FA + (1 + beg) * D;
-    int kv = i < L ? (int)word[i] : 0;
-    Row16 cur = load_row(s.Gs + bcast_i32<0>(kv) * GATE_STRIDE + i * ROW);
-    for (int t0 = 0; t0 < Lw; t0 += 16) {
-      const int kvn = (t0 + 16 + i < L) ? (int)word[t0 + 16 + i] : 0;
-#define GST_TF(R)                                                                    \
-  if (t0 + R < Lw) {                                                                 \
-    const int j = t0 + R;                                                            \
-    const int kn = (R < 15) ? bcast_i32<(R + 1) & 15>(kv) : bcast_i32<0>(kvn);       \
-    const Row16 nxt = load_row(s.Gs + kn * GATE_STRIDE + i * ROW);                   \
-    const double fn = dot16(f, cur);                                                 \
-    f = j < L ? fn : f;                                                              \
-    if (j < L && i < D) out[(int64_t)j * D + i] = f;                                 \
-    cur = nxt;                                                                       \
-  }
-      GST_TF(0) GST_TF(1) GST_TF(2) GST_TF(3) GST_TF(4) GST_TF(5) GST_TF(6) GST_TF(7)
-      GST_TF(8) GST_TF(9) GST_TF(10) GST_TF(11) GST_TF(12) GST_TF(13) GST_TF(14) GST_TF(15)
-#undef GST_TF
-      kv = kvn;
+  if (blockIdx.x == 0 && tid < D) a.FA[tid] = a.rho[tid];
+  const double* gl = s.Gs + i * ROW;
+  for (int64_t t = a.t_begin + (int64_t)blockIdx.x * WAVES + wave; t < a.t_end; t += (int64_t)gridDim.x * WAVES) {
+    const int64_t beg = a.trunk_ptr[t];
+    const int64_t anc = a.trunk_anchor[t];
+    double f = anc >= 0 ? load_state(a.FA, 1 + anc, D, i) : s.rho[i];
+    double* out = a.FA + (1 + beg) * D + i;
+    const bool st = (D == 16) || lane < D;  // rows 1..3 store the same values as row 0
+    for (int64_t sg = a.seg_ptr[t]; sg < a.seg_ptr[t + 1]; ++sg) {
+      const Seg g = load_seg(a, sg);
+      double* o = out + (int64_t)g.start * D;
+      const Row16 R0 = load_row(gl + g.g0 * GATE_STRIDE);
+      if (g.per == 1) {
+        for (int c = 0; c < g.count; ++c) {
+          f = dot16(f, R0);
+          if (st) o[0] = f;
+          o += D;
+        }
+      } else if (g.per == 2) {
+        const Row16 R1 = load_row(gl + g.g1 * GATE_STRIDE);
+        for (int c = 0; c < g.count; ++c) {
+          f = dot16(f, R0);
+          if (st) o[0] = f;
+          f = dot16(f, R1);
+          if (st) o[D] = f;
+          o += 2 * D;
+        }
+      } else if (g.per == 3) {
+        const Row16 R1 = load_row(gl + g.g1 * GATE_STRIDE);
+        const Row16 R2 = load_row(gl + g.g2 * GATE_STRIDE);
+        for (int c = 0; c < g.count; ++c) {
+          f = dot16(f, R0);
+          if (st) o[0] = f;
+          f = dot16(f, R1);
+          if (st) o[D] = f;
+          f = dot16(f, R2);
+          if (st) o[2 * D] = f;
+          o += 3 * D;
+        }
+      } else {
+        const Row16 R1 = load_row(gl + g.g1 * GATE_STRIDE);
+        const Row16 R2 = load_row(gl + g.g2 * GATE_STRIDE);
+        const Row16 R3 = load_row(gl + g.g3 * GATE_STRIDE);
+        for (int c = 0; c < g.count; ++c) {
+          f = dot16(f, R0);
+          if (st) o[0] = f;
+          f = dot16(f, R1);
+          if (st) o[D] = f;
+          f = dot16(f, R2);
+          if (st) o[2 * D] = f;
+          f = dot16(f, R3);
+          if (st) o[3 * D] = f;
+          o += 4 * D;
+        }
+      }
     }
   }
 }
@@ -87,7 +143,7 @@ __global__ __launch_bounds__(256) void item_kernel(const PlanArgs a) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, i = lane & 15, team = lane >> 4;
   stage_gateset<D>(s, a.G, a.E, a.rho, K, M);
   const bool grad = a.want_grad != 0;
-  double obj = 0.0;
+  double obj = 0.0, drho = 0.0;
   double dE[16];
 #pragma unroll
   for (int m = 0; m < 16; ++m) dE[m] = 0.0;
@@ -110,7 +166,7 @@ __global__ __launch_bounds__(256) void item_kernel(const PlanArgs a) {
     const uint8_t* word = a.gates + beg;
     double* fa = a.FA + (1 + a.nTS + isp) * D;  // state before item step x: fa[x*D + i]
     double* ba = a.BA + (a.nTS + isp) * D;      // adjoint after item step x
-    double f = load_state(a.FA, anc >= 0 ? 1 + anc : 0, D, i);
+    double f = anc >= 0 ? load_state(a.FA, 1 + anc, D, i) : s.rho[i];
 
     // ---- forward over the rest of the word ----
     for (int t0 = 0; t0 < Lw; t0 += 16) {
@@ -174,112 +230,128 @@ __global__ __launch_bounds__(256) void item_kernel(const PlanArgs a) {
 #undef GST_IB
     }
     if (has && i < D) a.item_adj[q * D + i] = b;
+    if (has && anc < 0) drho += b;
   }
   if (nonpos) atomicAdd(a.status + 1, (unsigned long long)nonpos);
   if (a.mode != MODE_LOGLIK && !grad) return;
   d4 zero[KMAX];
 #pragma unroll
   for (int k = 0; k < KMAX; ++k) zero[k] = d4{0.0, 0.0, 0.0, 0.0};
-  write_slab<D>(lds_raw, obj, 0.0, dE, zero, M, K, a.slab);
+  write_slab<D>(lds_raw, obj, drho, dE, zero, M, K, a.slab);
 }
 
 // ---------------------------------------------------------------------------
-// trunk reverse sweep
+// trunk reverse sweep, one trunk per wave: segments in reverse, G^T rows of a
+// segment in registers; adjoints injected at stored states (a descending list
+// per trunk, staged in LDS) are added on the way back
 // ---------------------------------------------------------------------------
 template <int D>
 __global__ __launch_bounds__(256) void trunk_bwd_kernel(const PlanArgs a) {
   extern __shared__ double lds_raw[];
   const int K = a.K;
   const Lds s = carve(lds_raw, K);
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, i = lane & 15, team = lane >> 4;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, i = lane & 15;
   stage_gateset<D>(s, a.G, a.E, a.rho, K, a.M);
-  const int64_t nT = a.t_end - a.t_begin;
-  const int64_t n_groups = (nT + TPW - 1) / TPW;
-  for (int64_t grp = (int64_t)blockIdx.x * WAVES + wave; grp < n_groups; grp += (int64_t)gridDim.x * WAVES) {
-    const int64_t t = a.t_begin + grp * TPW + team;
-    const bool has = t < a.t_end;
-    const int64_t beg = has ? a.trunk_ptr[t] : 0;
-    const int L = has ? (int)(a.trunk_ptr[t + 1] - beg) : 0;
-    const int Lw = wave_max4(L);
-    const int nb = (Lw + 15) / 16;
-    const uint8_t* word = a.trunk_gates + beg;
-    const int32_t* injs = a.trunk_inj + beg;
-    double* ba = a.BA + beg * D;
+  const double* gl = s.GTs + i * ROW;
+  double drho = 0.0;
+  for (int64_t t = a.t_begin + (int64_t)blockIdx.x * WAVES + wave; t < a.t_end; t += (int64_t)gridDim.x * WAVES) {
+    const int64_t beg = a.trunk_ptr[t];
+    double* ba = a.BA + beg * D + i;
+    const bool st = (D == 16) || lane < D;
+    const int64_t sg0 = a.seg_ptr[t], sg1 = a.seg_ptr[t + 1];
     double b = 0.0;
-    // Software pipeline over 16-step blocks, walked from the end: gate
-    // indices and injection slots are loaded two blocks ahead, the injected
-    // vectors one block ahead of their use.
-    auto ld_idx = [&](int c, int& kvo, int& jvo) {
-      kvo = 0;
-      jvo = -1;
-      if (c >= 0 && c * 16 + i < L) {
-        kvo = word[c * 16 + i];
-        jvo = injs[c * 16 + i];
-      }
-    };
-    int kv_c, jv_c, kv_n, jv_n;
-    ld_idx(nb - 1, kv_c, jv_c);
-    ld_idx(nb - 2, kv_n, jv_n);
-    double ij_c[16], ij_n[16];
-#define GST_LDI(DST, JV, R)                                                       \
-  {                                                                               \
-    const int slot = bcast_i32<R>(JV);                                            \
-    DST[R] = (slot >= 0 && i < D) ? a.inj[(int64_t)slot * D + i] : 0.0;           \
-  }
-#define GST_LDI16(DST, JV)                                                                      \
-  GST_LDI(DST, JV, 0) GST_LDI(DST, JV, 1) GST_LDI(DST, JV, 2) GST_LDI(DST, JV, 3)              \
-  GST_LDI(DST, JV, 4) GST_LDI(DST, JV, 5) GST_LDI(DST, JV, 6) GST_LDI(DST, JV, 7)              \
-  GST_LDI(DST, JV, 8) GST_LDI(DST, JV, 9) GST_LDI(DST, JV, 10) GST_LDI(DST, JV, 11)            \
-  GST_LDI(DST, JV, 12) GST_LDI(DST, JV, 13) GST_LDI(DST, JV, 14) GST_LDI(DST, JV, 15)
-    GST_LDI16(ij_c, jv_c)
-    for (int c = nb - 1; c >= 0; --c) {
-      const int t0 = c * 16;
-      // loads for later blocks
-      GST_LDI16(ij_n, jv_n)
-      int kv_nn, jv_nn;
-      ld_idx(c - 2, kv_nn, jv_nn);
-      // the block runs from its last valid step down to step 0
-      const int rstart = min(15, Lw - 1 - t0);
-      Row16 cur = load_row(s.GTs + __shfl(kv_c, (lane & 48) | rstart, 64) * GATE_STRIDE + i * ROW);
-#define GST_TB(R)                                                                     \
-  if (R <= rstart) {                                                                  \
-    const int j = t0 + R;                                                             \
-    const bool v = j < L;                                                             \
-    const int kn = bcast_i32<(R + 15) & 15>(kv_c);                                    \
-    const Row16 nxt = load_row(s.GTs + kn * GATE_STRIDE + i * ROW);                   \
-    if (v) b += ij_c[R];                                                              \
-    if (v && i < D) ba[(int64_t)j * D + i] = b;                                       \
-    const double bn = dot16_split(b, cur);                                            \
-    b = v ? bn : b;                                                                   \
-    cur = nxt;                                                                        \
-  }
-      GST_TB(15) GST_TB(14) GST_TB(13) GST_TB(12) GST_TB(11) GST_TB(10) GST_TB(9) GST_TB(8)
-      GST_TB(7) GST_TB(6) GST_TB(5) GST_TB(4) GST_TB(3) GST_TB(2) GST_TB(1) GST_TB(0)
-#undef GST_TB
-      kv_c = kv_n;
-      kv_n = kv_nn;
-      jv_n = jv_nn;
-#pragma unroll
-      for (int r = 0; r < 16; ++r) ij_c[r] = ij_n[r];
+    // injected vector of the segment about to run, loaded one segment ahead
+    double cv = 0.0;
+    if (sg1 > sg0) {
+      const int64_t slot = a.seg_inj[sg1 - 1];
+      cv = (slot >= 0 && i < D) ? a.inj[slot * D + i] : 0.0;
     }
-#undef GST_LDI16
-#undef GST_LDI
-    if (has && i < D) a.trunk_adj[t * D + i] = b;
+#define GST_TBSTEP(RT, J)                    \
+  {                                          \
+    if (st) ba[(int64_t)(J) * D] = b;        \
+    b = dot16_split(b, RT);                  \
   }
+    for (int64_t sg = sg1 - 1; sg >= sg0; --sg) {
+      const Seg g = load_seg(a, sg);
+      double nv = 0.0;
+      if (sg > sg0) {
+        const int64_t slot = a.seg_inj[sg - 1];
+        nv = (slot >= 0 && i < D) ? a.inj[slot * D + i] : 0.0;
+      }
+      b += cv;  // adjoint arriving at the state after the segment's last step
+      const Row16 R0 = load_row(gl + g.g0 * GATE_STRIDE);
+      if (g.per == 1) {
+        for (int c = g.count - 1; c >= 0; --c) GST_TBSTEP(R0, g.start + c)
+      } else if (g.per == 2) {
+        const Row16 R1 = load_row(gl + g.g1 * GATE_STRIDE);
+        for (int c = g.count - 1; c >= 0; --c) {
+          const int j0 = g.start + 2 * c;
+          GST_TBSTEP(R1, j0 + 1)
+          GST_TBSTEP(R0, j0)
+        }
+      } else if (g.per == 3) {
+        const Row16 R1 = load_row(gl + g.g1 * GATE_STRIDE);
+        const Row16 R2 = load_row(gl + g.g2 * GATE_STRIDE);
+        for (int c = g.count - 1; c >= 0; --c) {
+          const int j0 = g.start + 3 * c;
+          GST_TBSTEP(R2, j0 + 2)
+          GST_TBSTEP(R1, j0 + 1)
+          GST_TBSTEP(R0, j0)
+        }
+      } else {
+        const Row16 R1 = load_row(gl + g.g1 * GATE_STRIDE);
+        const Row16 R2 = load_row(gl + g.g2 * GATE_STRIDE);
+        const Row16 R3 = load_row(gl + g.g3 * GATE_STRIDE);
+        for (int c = g.count - 1; c >= 0; --c) {
+          const int j0 = g.start + 4 * c;
+          GST_TBSTEP(R3, j0 + 3)
+          GST_TBSTEP(R2, j0 + 2)
+          GST_TBSTEP(R1, j0 + 1)
+          GST_TBSTEP(R0, j0)
+        }
+      }
+      cv = nv;
+    }
+#undef GST_TBSTEP
+    if (lane < D) a.trunk_adj[t * D + i] = b;
+    if (a.trunk_anchor[t] < 0) drho += b;
+  }
+  // lanes 16..63 repeat lanes 0..15: only row 0 contributes
+  if (lane >= 16) drho = 0.0;
+  double dE[16];
+#pragma unroll
+  for (int m = 0; m < 16; ++m) dE[m] = 0.0;
+  d4 zero[KMAX];
+#pragma unroll
+  for (int k = 0; k < KMAX; ++k) zero[k] = d4{0.0, 0.0, 0.0, 0.0};
+  write_slab<D>(lds_raw, 0.0, drho, dE, zero, a.M, K, a.slab);
 }
 
-__global__ void inject_kernel(const InjectLaunch a) {
+// One wave per injection slot: four groups of 16 lanes take every fourth
+// source (two independent partial sums each), then the groups are combined
+// in a fixed order.
+__global__ __launch_bounds__(64) void inject_kernel(const InjectLaunch a) {
   const int D = a.D;
-  const int64_t n = (a.s_end - a.s_begin) * D;
-  for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t slot = a.s_begin + x / D;
-    const int i = (int)(x % D);
-    double v = 0.0;
-    for (int64_t z = a.inj_ptr[slot]; z < a.inj_ptr[slot + 1]; ++z) {
-      const int64_t src = a.inj_src[z];
-      v += src >= 0 ? a.item_adj[src * D + i] : a.trunk_adj[(-src - 1) * D + i];
+  const int lane = threadIdx.x, g = lane >> 4, i = lane & 15;
+  for (int64_t slot = a.s_begin + blockIdx.x; slot < a.s_end; slot += gridDim.x) {
+    const int64_t z0 = a.inj_ptr[slot], z1 = a.inj_ptr[slot + 1];
+    double v0 = 0.0, v1 = 0.0;
+    if (i < D) {
+      int64_t z = z0 + g;
+      for (; z + 4 < z1; z += 8) {
+        const int64_t s0 = a.inj_src[z], s1 = a.inj_src[z + 4];
+        v0 += s0 >= 0 ? a.item_adj[s0 * D + i] : a.trunk_adj[(-s0 - 1) * D + i];
+        v1 += s1 >= 0 ? a.item_adj[s1 * D + i] : a.trunk_adj[(-s1 - 1) * D + i];
+      }
+      if (z < z1) {
+        const int64_t s0 = a.inj_src[z];
+        v0 += s0 >= 0 ? a.item_adj[s0 * D + i] : a.trunk_adj[(-s0 - 1) * D + i];
+      }
     }
-    a.inj[slot * D + i] = v;
+    double v = v0 + v1;
+    v += __shfl_xor(v, 16);
+    v += __shfl_xor(v, 32);
+    if (lane < D) a.inj[slot * D + i] = v;
   }
 }
 
@@ -295,22 +367,22 @@ __global__ __launch_bounds__(256) void grad_gemm_kernel(const GemmLaunch a) {
   const int64_t r0 = a.chunk_beg[c], r1 = a.chunk_end[c];
   const int k = (int)a.chunk_gate[c];
   d4 acc = {0.0, 0.0, 0.0, 0.0};
-  // records r0 + 16*g + 4*wave + z for g = 0, 1, ...
-  for (int64_t base = r0 + 4 * wave; base < r1; base += 4 * 4 * WAVES) {
-    double av[4], bv[4];
+  // records r0 + 16*u + 4*wave + z, u = 0..7 (chunks hold at most 128 records)
+  int64_t rb[8], rf[8];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int64_t r = base + u * 4 * WAVES + z;
-      av[u] = 0.0;
-      bv[u] = 0.0;
-      if (r < r1 && i < D) {
-        av[u] = a.BA[a.rec_b[r] * D + i];
-        bv[u] = a.FA[a.rec_f[r] * D + i];
-      }
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[u], acc, 0, 0, 0);
+  for (int u = 0; u < 8; ++u) {
+    const int64_t r = r0 + 16 * u + 4 * wave + z;
+    rb[u] = r < r1 ? a.rec_b[r] : -1;
+    rf[u] = r < r1 ? a.rec_f[r] : -1;
   }
+  double av[8], bv[8];
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    av[u] = (rb[u] >= 0 && i < D) ? a.BA[rb[u] * D + i] : 0.0;
+    bv[u] = (rf[u] >= 0 && i < D) ? a.FA[rf[u] * D + i] : 0.0;
+  }
+#pragma unroll
+  for (int u = 0; u < 8; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[u], acc, 0, 0, 0);
 #pragma unroll
   for (int v = 0; v < 4; ++v) tile[wave][(4 * v + (lane >> 4)) * 16 + (lane & 15)] = acc[v];
   __syncthreads();
@@ -332,18 +404,18 @@ __global__ __launch_bounds__(256) void grad_gemm_kernel(const GemmLaunch a) {
 int item_blocks_for(int64_t n_items) {
   int64_t b = (n_items + WAVES * TPW - 1) / (WAVES * TPW);
   if (b < 1) b = 1;
-  if (b > 1024) b = 1024;
+  if (b > 256) b = 256;
   return (int)b;
 }
 
-static int trunk_blocks(int64_t n) {
-  int64_t b = (n + WAVES * TPW - 1) / (WAVES * TPW);
-  return (int)(b < 1 ? 1 : (b > 2048 ? 2048 : b));
+int trunk_blocks_for(int64_t n) {
+  int64_t b = (n + WAVES - 1) / WAVES;
+  return (int)(b < 1 ? 1 : (b > 4096 ? 4096 : b));
 }
 
 hipError_t launch_trunk_fwd(const PlanArgs& a, hipStream_t stream) {
-  const int blocks = trunk_blocks(a.t_end - a.t_begin);
-  const size_t bytes = lds_main_bytes(a.K);
+  const int blocks = trunk_blocks_for(a.t_end - a.t_begin);
+  const size_t bytes = trunk_lds_bytes(a.K);
   if (a.D == 16)
     hipLaunchKernelGGL(trunk_fwd_kernel<16>, dim3(blocks), dim3(256), bytes, stream, a);
   else if (a.D == 4)
@@ -354,8 +426,8 @@ hipError_t launch_trunk_fwd(const PlanArgs& a, hipStream_t stream) {
 }
 
 hipError_t launch_trunk_bwd(const PlanArgs& a, hipStream_t stream) {
-  const int blocks = trunk_blocks(a.t_end - a.t_begin);
-  const size_t bytes = lds_main_bytes(a.K);
+  const int blocks = trunk_blocks_for(a.t_end - a.t_begin);
+  const size_t bytes = trunk_lds_bytes(a.K);
   if (a.D == 16)
     hipLaunchKernelGGL(trunk_bwd_kernel<16>, dim3(blocks), dim3(256), bytes, stream, a);
   else if (a.D == 4)
@@ -377,11 +449,10 @@ hipError_t launch_items(const PlanArgs& a, int n_blocks, hipStream_t stream) {
 }
 
 hipError_t launch_inject(const InjectLaunch& a, hipStream_t stream) {
-  const int64_t n = (a.s_end - a.s_begin) * a.D;
+  const int64_t n = a.s_end - a.s_begin;
   if (n <= 0) return hipSuccess;
-  int blocks = (int)((n + 255) / 256);
-  if (blocks > 4096) blocks = 4096;
-  hipLaunchKernelGGL(inject_kernel, dim3(blocks), dim3(256), 0, stream, a);
+  const int blocks = (int)(n < 65536 ? n : 65536);
+  hipLaunchKernelGGL(inject_kernel, dim3(blocks), dim3(64), 0, stream, a);
   return hipGetLastError();
 }
 

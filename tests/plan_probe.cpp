@@ -28,6 +28,7 @@ extern "C" int plan_build(const int64_t* off, const uint8_t* gates, int64_t S, i
   sizes[9] = (int64_t)P.rec_b.size();
   sizes[10] = P.root_slot;
   sizes[11] = P.item_steps();
+  sizes[12] = (int64_t)P.seg_start.size();
   return 0;
 }
 
@@ -52,4 +53,13 @@ extern "C" void plan_copy_records(int64_t* item_step_ptr, int64_t* rec_b, int64_
   std::memcpy(rec_b, P.rec_b.data(), P.rec_b.size() * 8);
   std::memcpy(rec_f, P.rec_f.data(), P.rec_f.size() * 8);
   std::memcpy(rec_gate_ptr, P.rec_gate_ptr.data(), P.rec_gate_ptr.size() * 8);
+}
+
+extern "C" void plan_copy_segments(int64_t* seg_ptr, int32_t* start, int32_t* count, uint32_t* pattern, uint8_t* g3) {
+  const gst::HostPlan& P = g_plan;
+  std::memcpy(seg_ptr, P.seg_ptr.data(), P.seg_ptr.size() * 8);
+  std::memcpy(start, P.seg_start.data(), P.seg_start.size() * 4);
+  std::memcpy(count, P.seg_count.data(), P.seg_count.size() * 4);
+  std::memcpy(pattern, P.seg_pattern.data(), P.seg_pattern.size() * 4);
+  std::memcpy(g3, P.seg_gate3.data(), P.seg_gate3.size());
 }

@@ -33,16 +33,17 @@ def planlib(tmp_path_factory):
     lib.plan_build.argtypes = [P, P, ctypes.c_int64, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double, P]
     lib.plan_copy.argtypes = [P] * 9
     lib.plan_copy_records.argtypes = [P] * 4
+    lib.plan_copy_segments.argtypes = [P] * 5
     return lib
 
 
 def get_plan(lib, sl, K, min_trunk=24, reanchor=8, ratio=0.8):
     K = int(K)
-    sizes = np.zeros(12, np.int64)
+    sizes = np.zeros(13, np.int64)
     off = np.ascontiguousarray(sl.offsets, np.int64)
     g = np.ascontiguousarray(sl.gates if sl.gates.size else np.zeros(1, np.uint8), np.uint8)
     lib.plan_build(off.ctypes.data, g.ctypes.data, sl.S, K, min_trunk, reanchor, ratio, sizes.ctypes.data)
-    used, nI, nT, nTS, nJ, nSrc, nL, nN, sumL, nR, root, nIS = [int(x) for x in sizes]
+    used, nI, nT, nTS, nJ, nSrc, nL, nN, sumL, nR, root, nIS, nSeg = [int(x) for x in sizes]
     P = dict(used=bool(used), items=np.zeros((nI, 4), np.int64), trunk_ptr=np.zeros(nT + 1, np.int64),
              trunk_anchor=np.zeros(nT, np.int64), trunk_gates=np.zeros(max(nTS, 1), np.uint8),
              trunk_inj=np.zeros(max(nTS, 1), np.int32), inj_loc=np.zeros(max(nJ, 1), np.int64),
@@ -59,6 +60,13 @@ def get_plan(lib, sl, K, min_trunk=24, reanchor=8, ratio=0.8):
                               P["rec_gate_ptr"].ctypes.data)
         P["rec_b"], P["rec_f"] = P["rec_b"][:nR], P["rec_f"][:nR]
         P["root_slot"] = root
+        P["seg_ptr"] = np.zeros(nT + 1, np.int64)
+        P["seg_start"] = np.zeros(max(nSeg, 1), np.int32)
+        P["seg_count"] = np.zeros(max(nSeg, 1), np.int32)
+        P["seg_pattern"] = np.zeros(max(nSeg, 1), np.uint32)
+        P["seg_gate3"] = np.zeros(max(nSeg, 1), np.uint8)
+        lib.plan_copy_segments(*[P[k].ctypes.data for k in ["seg_ptr", "seg_start", "seg_count", "seg_pattern",
+                                                              "seg_gate3"]])
     P["trunk_gates"] = P["trunk_gates"][:nTS]
     P["trunk_inj"] = P["trunk_inj"][:nTS]
     P["inj_loc"] = P["inj_loc"][:nJ]
@@ -184,6 +192,7 @@ def run_plan(P, gs, sl, counts):
         root = P["root_slot"]
         drho = sum((item_adj2[src] if src >= 0 else tadj[-src - 1]
                     for src in P["inj_src"][P["inj_ptr"][root]:P["inj_ptr"][root + 1]]), np.zeros(D))
+        drho = drho + sum((item_adj2[q] for q in range(len(P["items"])) if P["items"][q, 3] < 0), np.zeros(D))
         dG2 = np.zeros((K, D, D))
         gp = P["rec_gate_ptr"]
         for k in range(K):
@@ -246,3 +255,29 @@ def test_plan_multilevel_and_random(planlib, oracle_lib):
     wr = W.random_workload("2q", 300, 200, 3)
     P = get_plan(planlib, wr.seqs, 6)
     assert not P["used"]
+
+
+def segments_word(P, t):
+    """Rebuilds trunk t's gate word from its periodic segments."""
+    out = []
+    for sg in range(P["seg_ptr"][t], P["seg_ptr"][t + 1]):
+        pat = int(P["seg_pattern"][sg])
+        per = pat & 0xff
+        gates = [(pat >> 8) & 0xff, (pat >> 16) & 0xff, (pat >> 24) & 0xff, int(P["seg_gate3"][sg])][:per]
+        assert P["seg_start"][sg] == len(out)
+        out += gates * int(P["seg_count"][sg])
+    return out
+
+
+@pytest.mark.parametrize("name", ["c1", "c2"])
+def test_trunk_segments_rebuild_words(planlib, name):
+    w = W.structured_workload(name)
+    P = get_plan(planlib, w.seqs, w.model.K)
+    tp = P["trunk_ptr"]
+    nseg = 0
+    for t in range(len(tp) - 1):
+        word = segments_word(P, t)
+        assert word == list(P["trunk_gates"][tp[t]:tp[t + 1]])
+        nseg += P["seg_ptr"][t + 1] - P["seg_ptr"][t]
+    # germ powers compress: far fewer segments than steps
+    assert nseg * 4 < len(P["trunk_gates"])
