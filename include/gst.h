@@ -153,11 +153,37 @@ int gst_req_destroy(gst_req* req);
 int gst_req_plan_info(const gst_req* req, int64_t* info, int n);
 
 /*
+ * Batches: several resident requests evaluated together, as the continuous
+ * batching of a fit service needs.  Requests without a sharing plan are cut
+ * into tiles of 128 sequences (sorted by length; the cut depends on the
+ * request alone) that one persistent launch takes from a work queue; every
+ * tile writes its own partial sums and each request's tiles are added in
+ * tile order, so each result is identical whether the request is evaluated
+ * alone or in any batch.  Requests with a plan run their own launch sequence
+ * after the batched launch.
+ *
+ * gst_batch_create fixes the requests, the gate sets (device pointers whose
+ * contents may change between runs) and the output pointers; any of probs,
+ * objectives, grads may be NULL or hold NULL entries (an objective is needed
+ * for a gradient).  capture_graph != 0 records the batched launch sequence
+ * into a HIP graph once; gst_batch_run then replays it on the context stream.
+ * gst_batch_nonpos synchronizes and returns, per request, the number of
+ * p <= 0 entries with positive counts in the last run (objective +inf).
+ */
+typedef struct gst_batch gst_batch;
+int gst_batch_create(gst_ctx* ctx, int n, gst_req* const* reqs, const gst_gateset* thetas,
+                     double* const* probs, double* const* objectives, double* const* grads,
+                     int capture_graph, gst_batch** out);
+int gst_batch_run(gst_batch* batch);
+int gst_batch_nonpos(gst_batch* batch, int64_t* counts);
+int gst_batch_destroy(gst_batch* batch);
+
+/*
  * Kernel timing (diagnostics).  While enabled, every kernel the context
  * enqueues is bracketed by two HIP events recorded on the context's stream.
  * gst_profile_read synchronizes the stream and returns, for the kernel family
  * `kernel` ("leaf", "reduce", "trunk_fwd", "trunk_bwd", "inject",
- * "grad_gemm"), the summed
+ * "grad_gemm", "batch"), the summed
  * elapsed milliseconds and the number of launches since profiling was
  * enabled; the counters are not reset by reading.
  */

@@ -22,7 +22,8 @@ _NAMES = {0: "GST_OK", -1: "GST_EINVAL", -2: "GST_EINDEX", -3: "GST_ENONPOS", -4
 EXPORTED = [
     "gst_max_gates", "gst_create", "gst_destroy", "gst_sync", "gst_probs", "gst_loglik", "gst_vjp",
     "gst_req_create_host", "gst_req_footprint", "gst_req_eval", "gst_req_probs", "gst_req_vjp",
-    "gst_req_destroy", "gst_req_plan_info", "gst_profile_enable", "gst_profile_read", "gst_last_error",
+    "gst_req_destroy", "gst_req_plan_info", "gst_batch_create", "gst_batch_run", "gst_batch_nonpos",
+    "gst_batch_destroy", "gst_profile_enable", "gst_profile_read", "gst_last_error",
 ]
 
 
@@ -89,6 +90,14 @@ def load():
             lib.gst_req_plan_info.argtypes = [P, ctypes.POINTER(ctypes.c_int64), I]
             lib.gst_req_plan_info.restype = I
             for name in ("gst_req_create_host", "gst_req_footprint", "gst_req_eval", "gst_req_vjp", "gst_req_destroy"):
+                getattr(lib, name).restype = I
+        if hasattr(lib, "gst_batch_create"):
+            PP = ctypes.POINTER(ctypes.c_void_p)
+            lib.gst_batch_create.argtypes = [P, I, PP, ctypes.POINTER(GstGateset), PP, PP, PP, I, ctypes.POINTER(P)]
+            lib.gst_batch_run.argtypes = [P]
+            lib.gst_batch_nonpos.argtypes = [P, ctypes.POINTER(ctypes.c_int64)]
+            lib.gst_batch_destroy.argtypes = [P]
+            for name in ("gst_batch_create", "gst_batch_run", "gst_batch_nonpos", "gst_batch_destroy"):
                 getattr(lib, name).restype = I
         _lib = lib
         return lib

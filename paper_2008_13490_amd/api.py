@@ -177,6 +177,7 @@ class Request:
         _lib.check(self.lib.gst_req_create_host(ctx.handle, n_qubits, n_gates, n_outcomes, ctypes.byref(sl),
                                                 None if c is None else c.ctypes.data, ctypes.byref(h)))
         self.handle = h
+        self.has_counts = counts is not None
         self.S = len(off) - 1
         self.M = n_outcomes
         self.n_params = 4 ** n_qubits * (1 + n_outcomes) + n_gates * 16 ** n_qubits
@@ -215,6 +216,49 @@ class Request:
     def close(self):
         if getattr(self, "handle", None):
             self.lib.gst_req_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Several resident requests evaluated together (``gst_batch``).
+
+    ``thetas`` are DeviceGateSets whose tensors stay allocated (their contents
+    may change between runs); outputs are allocated here per request."""
+
+    def __init__(self, ctx: Context, reqs, thetas, want_probs=False, want_grad=True, capture_graph=False):
+        self.ctx, self.lib = ctx, ctx.lib
+        n = len(reqs)
+        dev = ctx._dev()
+        self.reqs, self.thetas = list(reqs), list(thetas)
+        self.obj = [torch.empty(1, dtype=torch.float64, device=dev) if r.has_counts else None for r in reqs]
+        self.probs = [torch.empty((r.S, r.M), dtype=torch.float64, device=dev) if want_probs else None for r in reqs]
+        self.grad = [torch.empty(r.n_params, dtype=torch.float64, device=dev) if want_grad and r.has_counts else None
+                     for r in reqs]
+        gs = (_lib.GstGateset * max(n, 1))(*[t.as_struct() for t in self.thetas])
+        ptrs = lambda ts: (ctypes.c_void_p * max(n, 1))(*[None if t is None else t.data_ptr() for t in ts])
+        h = ctypes.c_void_p()
+        rq = (ctypes.c_void_p * max(n, 1))(*[r.handle.value for r in reqs])
+        _lib.check(self.lib.gst_batch_create(ctx.handle, n, rq, gs, ptrs(self.probs), ptrs(self.obj), ptrs(self.grad),
+                                             1 if capture_graph else 0, ctypes.byref(h)))
+        self.handle = h
+
+    def run(self):
+        _lib.check(self.lib.gst_batch_run(self.handle))
+
+    def nonpos(self):
+        v = (ctypes.c_int64 * max(len(self.reqs), 1))()
+        _lib.check(self.lib.gst_batch_nonpos(self.handle, v))
+        return [int(x) for x in v[:len(self.reqs)]]
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.gst_batch_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

@@ -89,11 +89,24 @@ struct Profiler {
 };
 
 enum Family { FAM_LEAF = 0, FAM_REDUCE = 1, FAM_TRUNK_FWD = 2, FAM_TRUNK_BWD = 3, FAM_INJECT = 4, FAM_GEMM = 5,
-              FAM_N = 6 };
-static const char* kFamilyNames[FAM_N] = {"leaf", "reduce", "trunk_fwd", "trunk_bwd", "inject", "grad_gemm"};
+              FAM_BATCH = 6, FAM_N = 7 };
+static const char* kFamilyNames[FAM_N] = {"leaf", "reduce", "trunk_fwd", "trunk_bwd", "inject", "grad_gemm", "batch"};
+
+// Carve consecutive aligned regions out of one allocation.
+struct Carver {
+  size_t off = 0;
+  template <class T>
+  size_t take(size_t n) {
+    off = (off + 255) / 256 * 256;
+    const size_t at = off;
+    off += n * sizeof(T);
+    return at;
+  }
+};
 
 struct gst_ctx {
   int device = 0;
+  int n_cu = 0;
   hipStream_t stream = nullptr;
   unsigned long long* status = nullptr;  // device [2]
   DevBuf ws;
@@ -159,17 +172,57 @@ struct DevicePlan {
   double* inj = nullptr;        // [n_inj][D]
 };
 
+// Sequences per batch tile: a request's sequences, sorted by length, are cut
+// into tiles of this many (16 chains x 8); fixed, so a request's tiling and
+// summation order depend on the request alone.
+// Sequences per tile of a request: a multiple of the 16 chains of one
+// workgroup, chosen from S alone so that the cut (and with it the order of
+// the partial sums) is a property of the request.
+static int64_t tile_seqs_for(int64_t S) {
+  const int64_t per = (S + 16 * 1024 - 1) / (16 * 1024);
+  return 16 * std::min<int64_t>(std::max<int64_t>(per, 1), 8);
+}
+
 struct gst_req {
   gst_ctx* ctx = nullptr;
   int n_qubits = 0, D = 0, M = 0, K = 0;
   int64_t S = 0, max_len = 0;
-  DevBuf data;  // offsets | gate indices | counts
+  DevBuf data;  // offsets | gate indices | counts | order | tile slabs
   int64_t* offsets = nullptr;
   uint8_t* gates = nullptr;
   int32_t* counts = nullptr;
+  int64_t* order = nullptr;             // sequences by length, descending
+  std::vector<int64_t> tile_q;          // tile boundaries in `order` (n_tiles + 1)
+  std::vector<int64_t> tile_cost;       // summed lengths per tile
+  double* tile_slab = nullptr;          // [n_tiles][P]
+  gst::BatchTile* tiles = nullptr;      // device tile list of the request alone (longest first)
+  unsigned* queue = nullptr;            // device: work-queue counter [64] + nonpos counter
   DevicePlan plan;
   DevBuf ws;
   size_t resident_bytes = 0;
+  int64_t n_tiles() const { return tile_q.empty() ? 0 : (int64_t)tile_q.size() - 1; }
+};
+
+struct gst_batch {
+  gst_ctx* ctx = nullptr;
+  std::vector<gst_req*> reqs;
+  std::vector<gst_gateset> thetas;
+  std::vector<double*> probs, objectives, grads;
+  std::vector<int> plan_reqs;           // evaluated through their own plans
+  int n_t16 = 0, n_t4 = 0, n_items = 0, grid = 0, grid16 = 0, grid4 = 0, kmax = 1;
+  int64_t max_len = 0;
+  DevBuf desc;
+  gst::BatchLaunch l16{}, l4{};
+  gst::BatchReduce red{};
+  unsigned long long* req_nonpos = nullptr;
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  ~gst_batch() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
+  }
 };
 
 namespace {
@@ -240,7 +293,7 @@ int run_leaf(gst_ctx* ctx, DevBuf& ws, const gst::LeafLaunch& base, int64_t max_
   }
   if (need_slab) {
     ProfScope ps(ctx, FAM_REDUCE);
-    HIP_TRY(gst::launch_reduce(a.slab, blocks, P, objective, grad, ctx->status, nullptr, D, part, ctx->stream));
+    HIP_TRY(gst::launch_reduce(a.slab, blocks, P, objective, grad, nullptr, D, part, ctx->stream));
   }
   return GST_OK;
 }
@@ -278,18 +331,6 @@ int plain_eval(gst_ctx* ctx, const gst_gateset* gs, const gst_seqlist* sl, int m
   a.want_grad = grad != nullptr;
   return run_leaf(ctx, ctx->ws, a, max_len, objective, grad);
 }
-
-// Carve consecutive aligned regions out of one allocation.
-struct Carver {
-  size_t off = 0;
-  template <class T>
-  size_t take(size_t n) {
-    off = (off + 255) / 256 * 256;
-    const size_t at = off;
-    off += n * sizeof(T);
-    return at;
-  }
-};
 
 int upload_plan(gst_req* r, const gst::HostPlan& P) {
   DevicePlan& d = r->plan;
@@ -396,7 +437,7 @@ int upload_plan(gst_req* r, const gst::HostPlan& P) {
 // injections and trunks backward (deepest level first), the gradient GEMM
 // over all stored steps, and the slab reduction.
 int run_plan(gst_req* r, const gst_gateset* th, int mode, const double* w, double* probs, double* objective,
-             double* grad) {
+             double* grad, unsigned long long* req_nonpos = nullptr) {
   gst_ctx* ctx = r->ctx;
   const DevicePlan& d = r->plan;
   const gst::HostPlan& P = d.host;
@@ -456,6 +497,7 @@ int run_plan(gst_req* r, const gst_gateset* th, int mode, const double* w, doubl
   a.inj = d.inj;
   a.slab = slab;
   a.status = ctx->status;
+  a.req_nonpos = req_nonpos;
   for (int l = 0; l < P.n_levels; ++l) {
     a.t_begin = P.trunk_level_ptr[l];
     a.t_end = P.trunk_level_ptr[l + 1];
@@ -505,7 +547,7 @@ int run_plan(gst_req* r, const gst_gateset* th, int mode, const double* w, doubl
   }
   if (need_slab) {
     ProfScope ps(ctx, FAM_REDUCE);
-    HIP_TRY(gst::launch_reduce(slab, n_slabs, Pw, objective, grad, ctx->status, nullptr, D, part, ctx->stream));
+    HIP_TRY(gst::launch_reduce(slab, n_slabs, Pw, objective, grad, nullptr, D, part, ctx->stream));
   }
   return GST_OK;
 }
@@ -534,6 +576,7 @@ int gst_create(gst_ctx** out, int device_ordinal, void* hip_stream) {
   std::unique_ptr<gst_ctx> c(new (std::nothrow) gst_ctx());
   if (!c) return fail(GST_ENOMEM, "host allocation failed");
   c->device = device_ordinal;
+  c->n_cu = prop.multiProcessorCount;
   c->stream = reinterpret_cast<hipStream_t>(hip_stream);
   HIP_TRY(hipMalloc(&c->status, 2 * sizeof(unsigned long long)));
   HIP_TRY(hipMemset(c->status, 0, 2 * sizeof(unsigned long long)));
@@ -647,18 +690,48 @@ int gst_req_create_host(gst_ctx* ctx, int n_qubits, int n_gates, int n_outcomes,
   r->K = n_gates;
   r->S = S;
   r->max_len = max_len;
-  const size_t b_off = (size_t)(S + 1) * 8, b_g = (size_t)std::max<int64_t>(n_steps, 1),
-               b_c = counts_host ? (size_t)S * n_outcomes * 4 : 0;
-  rc = r->data.reserve(b_off + b_g + b_c + 64, ctx->stream);
+  // batch tiles: sequences by length (descending, stable), kTileSeqs per tile
+  std::vector<int64_t> order((size_t)S);
+  for (int64_t q = 0; q < S; ++q) order[q] = q;
+  std::stable_sort(order.begin(), order.end(), [&](int64_t x, int64_t y) {
+    return sl->offsets[x + 1] - sl->offsets[x] > sl->offsets[y + 1] - sl->offsets[y];
+  });
+  const int64_t tile_seqs = tile_seqs_for(S);
+  for (int64_t q0 = 0; q0 < S; q0 += tile_seqs) {
+    r->tile_q.push_back(q0);
+    int64_t cost = 0;
+    for (int64_t q = q0; q < std::min(S, q0 + tile_seqs); ++q) cost += sl->offsets[order[q] + 1] - sl->offsets[order[q]];
+    r->tile_cost.push_back(cost);
+  }
+  if (S > 0) r->tile_q.push_back(S);
+  std::vector<gst::BatchTile> tiles((size_t)r->n_tiles());
+  for (int64_t t = 0; t < r->n_tiles(); ++t) tiles[t] = gst::BatchTile{0, (int32_t)t, r->tile_q[t], r->tile_q[t + 1]};
+  std::stable_sort(tiles.begin(), tiles.end(), [&](const gst::BatchTile& x, const gst::BatchTile& y) {
+    return r->tile_cost[x.local] > r->tile_cost[y.local];
+  });
+  const int64_t Pw = gst::slab_width(D, n_outcomes, n_gates);
+  Carver cv;
+  const size_t o_off = cv.take<int64_t>(S + 1), o_g = cv.take<uint8_t>(std::max<int64_t>(n_steps, 1)),
+               o_c = cv.take<int32_t>(counts_host ? S * n_outcomes : 1), o_ord = cv.take<int64_t>(S + 1),
+               o_sl = cv.take<double>((size_t)std::max<int64_t>(r->n_tiles(), 1) * Pw),
+               o_t = cv.take<gst::BatchTile>(tiles.size() + 1), o_q = cv.take<unsigned>(64 + 2);
+  rc = r->data.reserve(cv.off + 256, ctx->stream);
   if (rc) return rc;
   char* base = reinterpret_cast<char*>(r->data.p);
-  r->offsets = reinterpret_cast<int64_t*>(base);
-  r->gates = reinterpret_cast<uint8_t*>(base + b_off);
-  r->counts = counts_host ? reinterpret_cast<int32_t*>(base + ((b_off + b_g + 15) / 16) * 16) : nullptr;
+  r->offsets = reinterpret_cast<int64_t*>(base + o_off);
+  r->gates = reinterpret_cast<uint8_t*>(base + o_g);
+  r->counts = counts_host ? reinterpret_cast<int32_t*>(base + o_c) : nullptr;
+  r->order = reinterpret_cast<int64_t*>(base + o_ord);
+  r->tile_slab = reinterpret_cast<double*>(base + o_sl);
+  r->tiles = reinterpret_cast<gst::BatchTile*>(base + o_t);
+  r->queue = reinterpret_cast<unsigned*>(base + o_q);
+  if (!tiles.empty())
+    HIP_TRY(hipMemcpy(r->tiles, tiles.data(), tiles.size() * sizeof(gst::BatchTile), hipMemcpyHostToDevice));
   std::vector<int64_t> zero_off(1, 0);
-  HIP_TRY(hipMemcpy(r->offsets, S > 0 ? sl->offsets : zero_off.data(), b_off, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(r->offsets, S > 0 ? sl->offsets : zero_off.data(), (size_t)(S + 1) * 8, hipMemcpyHostToDevice));
   if (n_steps > 0) HIP_TRY(hipMemcpy(r->gates, sl->gate_idx, (size_t)n_steps, hipMemcpyHostToDevice));
-  if (counts_host && b_c) HIP_TRY(hipMemcpy(r->counts, counts_host, b_c, hipMemcpyHostToDevice));
+  if (counts_host && S > 0) HIP_TRY(hipMemcpy(r->counts, counts_host, (size_t)S * n_outcomes * 4, hipMemcpyHostToDevice));
+  if (S > 0) HIP_TRY(hipMemcpy(r->order, order.data(), (size_t)S * 8, hipMemcpyHostToDevice));
   if (S > 0 && D <= 16) {
     gst::HostPlan hp;
     gst::PlanOptions opt;
@@ -678,6 +751,78 @@ int gst_req_footprint(const gst_req* req, size_t* bytes) {
   return GST_OK;
 }
 
+// Checkpoint rows per chain of the tile kernel for sequences up to max_len.
+static int64_t tile_ckpt_per_team(int64_t max_len) {
+  const int C = gst::leaf_ckpt_interval(16);
+  return ((max_len + C - 1) / C + 1) * 16;
+}
+
+static gst::BatchReq batch_req_of(const gst_req* r, const gst_gateset* th, int mode, const double* w,
+                                  double* probs, bool want_grad) {
+  gst::BatchReq q{};
+  q.rho = th->rho;
+  q.E = th->effects;
+  q.G = th->gates;
+  q.off = r->offsets;
+  q.gates = r->gates;
+  q.order = r->order;
+  q.counts = r->counts;
+  q.W = w;
+  q.probs = probs;
+  q.slab = r->tile_slab;
+  q.M = r->M;
+  q.K = r->K;
+  q.mode = mode;
+  q.want_grad = want_grad ? 1 : 0;
+  return q;
+}
+
+// A request without a sharing plan: its tiles through the batched kernel
+// (the same kernels and summation order as inside any batch).
+static int run_tiles(gst_req* r, const gst_gateset* th, int mode, const double* w, double* probs, double* objective,
+                     double* grad) {
+  gst_ctx* ctx = r->ctx;
+  const int64_t nt = r->n_tiles();  // 0 for an empty list: the reduce then writes zeros
+  const bool want_grad = grad != nullptr;
+  const int bpc = gst::batch_blocks_per_cu(r->D, r->K);
+  const int grid = (int)std::min<int64_t>(nt, (int64_t)bpc * ctx->n_cu);
+  const int64_t ck_team = tile_ckpt_per_team(r->max_len);
+  const size_t ck_bytes = want_grad ? (size_t)grid * gst::leaf_teams_per_block(16) * ck_team * 8 : 0;
+  int rc = r->ws.reserve(ck_bytes + 256, ctx->stream);
+  if (rc) return rc;
+  gst::BatchLaunch l{};
+  l.D = r->D;
+  l.kmax = r->K;
+  l.reqs = nullptr;
+  l.one = batch_req_of(r, th, mode, w, probs, want_grad);
+  l.tiles = r->tiles;
+  l.n_tiles = (int)nt;
+  l.queue = r->queue;
+  l.ckpt = want_grad ? reinterpret_cast<double*>(r->ws.p) : nullptr;
+  l.ckpt_per_team = ck_team;
+  l.status = ctx->status;
+  l.req_nonpos = reinterpret_cast<unsigned long long*>(r->queue + 64);
+  {
+    ProfScope ps(ctx, FAM_LEAF);
+    HIP_TRY(gst::launch_queue_reset(r->queue, l.req_nonpos, 1, ctx->stream));
+    if (grid > 0) HIP_TRY(gst::launch_batch(l, grid, ctx->stream));
+  }
+  if (objective || grad) {
+    ProfScope ps(ctx, FAM_REDUCE);
+    gst::BatchReduce red{};
+    red.items = nullptr;
+    red.one.req = 0;
+    red.one.n_tiles = (int)nt;
+    red.one.P = gst::slab_width(r->D, r->M, r->K);
+    red.one.slab = r->tile_slab;
+    red.one.objective = objective;
+    red.one.grad = grad;
+    red.req_nonpos = l.req_nonpos;
+    HIP_TRY(gst::launch_batch_reduce(red, (int)((red.one.P + 63) / 64), ctx->stream));
+  }
+  return GST_OK;
+}
+
 static int req_run(gst_req* r, const gst_gateset* th, int mode, const double* w, double* probs, double* objective,
                    double* grad) {
   if (!r) return fail(GST_EINVAL, "req is NULL");
@@ -690,22 +835,7 @@ static int req_run(gst_req* r, const gst_gateset* th, int mode, const double* w,
   gst_ctx* ctx = r->ctx;
   HIP_TRY(hipSetDevice(ctx->device));
   if (r->plan.used) return run_plan(r, th, mode, w, probs, objective, grad);
-  gst::LeafLaunch a{};
-  a.D = D;
-  a.M = r->M;
-  a.K = r->K;
-  a.rho = th->rho;
-  a.E = th->effects;
-  a.G = th->gates;
-  a.n_items = r->S;
-  a.off = r->offsets;
-  a.gates = r->gates;
-  a.counts = r->counts;
-  a.W = w;
-  a.probs = probs;
-  a.mode = mode;
-  a.want_grad = grad != nullptr;
-  return run_leaf(ctx, r->ws, a, r->max_len, objective, grad);
+  return run_tiles(r, th, mode, w, probs, objective, grad);
 }
 
 int gst_req_eval(gst_req* req, const gst_gateset* theta, double* probs, double* objective, double* grad) {
@@ -721,6 +851,194 @@ int gst_req_probs(gst_req* req, const gst_gateset* theta, double* probs) {
 int gst_req_vjp(gst_req* req, const gst_gateset* theta, const double* w, double* grad) {
   if (!grad || (req && req->S > 0 && !w)) return fail(GST_EINVAL, "NULL argument");
   return req_run(req, theta, gst::MODE_VJP, w, nullptr, nullptr, grad);
+}
+
+static int batch_enqueue(gst_batch* b, hipStream_t stream) {
+  if (!b->reqs.empty())
+    HIP_TRY(gst::launch_queue_reset(reinterpret_cast<unsigned*>(b->l16.queue), b->req_nonpos,
+                                    (int)b->reqs.size(), stream));
+  if (b->n_t16 > 0 || b->n_t4 > 0) {
+    if (b->n_t16 > 0) HIP_TRY(gst::launch_batch(b->l16, b->grid16, stream));
+    if (b->n_t4 > 0) HIP_TRY(gst::launch_batch(b->l4, b->grid4, stream));
+    HIP_TRY(gst::launch_batch_reduce(b->red, b->n_items, stream));
+  }
+  return GST_OK;
+}
+
+int gst_batch_create(gst_ctx* ctx, int n, gst_req* const* reqs, const gst_gateset* thetas, double* const* probs,
+                     double* const* objectives, double* const* grads, int capture_graph, gst_batch** out) {
+  if (!ctx || !out || n < 0 || (n > 0 && (!reqs || !thetas))) return fail(GST_EINVAL, "NULL argument");
+  HIP_TRY(hipSetDevice(ctx->device));
+  std::unique_ptr<gst_batch> b(new (std::nothrow) gst_batch());
+  if (!b) return fail(GST_ENOMEM, "host allocation failed");
+  b->ctx = ctx;
+  std::vector<gst::BatchReq> rq;
+  std::vector<std::pair<int64_t, gst::BatchTile>> t16, t4;  // (cost, tile)
+  std::vector<gst::BatchReduceItem> items;
+  for (int x = 0; x < n; ++x) {
+    gst_req* r = reqs[x];
+    if (!r || r->ctx != ctx) return fail(GST_EINVAL, "request missing or from another context");
+    int D = 0;
+    int rc = check_gateset(&thetas[x], &D);
+    if (rc) return rc;
+    if (thetas[x].n_qubits != r->n_qubits || thetas[x].n_gates != r->K || thetas[x].n_outcomes != r->M)
+      return fail(GST_EINVAL, "gate set does not match its request");
+    double* po = probs ? probs[x] : nullptr;
+    double* ob = objectives ? objectives[x] : nullptr;
+    double* gr = grads ? grads[x] : nullptr;
+    if (ob && !r->counts) return fail(GST_EINVAL, "objective requested for a request without counts");
+    if (!ob && gr) return fail(GST_EINVAL, "gradient requested without the objective");
+    b->reqs.push_back(r);
+    b->thetas.push_back(thetas[x]);
+    b->probs.push_back(po);
+    b->objectives.push_back(ob);
+    b->grads.push_back(gr);
+    if (r->plan.used) {
+      b->plan_reqs.push_back(x);
+      rq.push_back(gst::BatchReq{});
+      continue;
+    }
+    gst::BatchReq q{};
+    q.rho = thetas[x].rho;
+    q.E = thetas[x].effects;
+    q.G = thetas[x].gates;
+    q.off = r->offsets;
+    q.gates = r->gates;
+    q.order = r->order;
+    q.counts = r->counts;
+    q.W = nullptr;
+    q.probs = po;
+    q.slab = r->tile_slab;
+    q.M = r->M;
+    q.K = r->K;
+    q.mode = ob ? gst::MODE_LOGLIK : gst::MODE_PROBS;
+    q.want_grad = gr != nullptr;
+    rq.push_back(q);
+    b->kmax = std::max(b->kmax, r->K);
+    b->max_len = std::max(b->max_len, r->max_len);
+    for (int64_t t = 0; t < r->n_tiles(); ++t) {
+      gst::BatchTile T{};
+      T.req = x;
+      T.local = (int32_t)t;
+      T.q0 = r->tile_q[t];
+      T.q1 = r->tile_q[t + 1];
+      (D == 16 ? t16 : t4).emplace_back(r->tile_cost[t], T);
+    }
+    if (ob) {
+      const int64_t P = gst::slab_width(D, r->M, r->K);
+      for (int64_t c0 = 0; c0 < P; c0 += 64) {
+        gst::BatchReduceItem it{};
+        it.req = x;
+        it.n_tiles = (int)r->n_tiles();
+        it.P = P;
+        it.col0 = c0;
+        it.slab = r->tile_slab;
+        it.objective = ob;
+        it.grad = gr;
+        items.push_back(it);
+      }
+    }
+  }
+  // longest tiles first (balance); execution order does not change results
+  auto by_cost = [](const std::pair<int64_t, gst::BatchTile>& a, const std::pair<int64_t, gst::BatchTile>& c) {
+    return a.first > c.first;
+  };
+  std::stable_sort(t16.begin(), t16.end(), by_cost);
+  std::stable_sort(t4.begin(), t4.end(), by_cost);
+  b->n_t16 = (int)t16.size();
+  b->n_t4 = (int)t4.size();
+  b->n_items = (int)items.size();
+  b->grid16 = (int)std::min<int64_t>(b->n_t16, (int64_t)gst::batch_blocks_per_cu(16, b->kmax) * ctx->n_cu);
+  b->grid4 = (int)std::min<int64_t>(b->n_t4, (int64_t)gst::batch_blocks_per_cu(4, b->kmax) * ctx->n_cu);
+  b->grid = std::max(b->grid16, b->grid4);
+  const int64_t ck_team = tile_ckpt_per_team(b->max_len);
+  Carver cv;
+  const size_t o_rq = cv.take<gst::BatchReq>(rq.size() + 1), o_t16 = cv.take<gst::BatchTile>(t16.size() + 1),
+               o_t4 = cv.take<gst::BatchTile>(t4.size() + 1), o_it = cv.take<gst::BatchReduceItem>(items.size() + 1),
+               o_q = cv.take<unsigned>(64), o_np = cv.take<unsigned long long>(rq.size() + 1),
+               o_ck = cv.take<double>((size_t)b->grid * gst::leaf_teams_per_block(16) * ck_team);
+  int rc = b->desc.reserve(cv.off + 256, ctx->stream);
+  if (rc) return rc;
+  char* base = reinterpret_cast<char*>(b->desc.p);
+  std::vector<gst::BatchTile> v16, v4;
+  for (auto& pr : t16) v16.push_back(pr.second);
+  for (auto& pr : t4) v4.push_back(pr.second);
+  if (!rq.empty()) HIP_TRY(hipMemcpy(base + o_rq, rq.data(), rq.size() * sizeof(gst::BatchReq), hipMemcpyHostToDevice));
+  if (!v16.empty()) HIP_TRY(hipMemcpy(base + o_t16, v16.data(), v16.size() * sizeof(gst::BatchTile), hipMemcpyHostToDevice));
+  if (!v4.empty()) HIP_TRY(hipMemcpy(base + o_t4, v4.data(), v4.size() * sizeof(gst::BatchTile), hipMemcpyHostToDevice));
+  if (!items.empty())
+    HIP_TRY(hipMemcpy(base + o_it, items.data(), items.size() * sizeof(gst::BatchReduceItem), hipMemcpyHostToDevice));
+  unsigned* queues = reinterpret_cast<unsigned*>(base + o_q);
+  b->req_nonpos = reinterpret_cast<unsigned long long*>(base + o_np);
+  for (int D : {16, 4}) {
+    gst::BatchLaunch& l = D == 16 ? b->l16 : b->l4;
+    l.D = D;
+    l.kmax = b->kmax;
+    l.reqs = reinterpret_cast<const gst::BatchReq*>(base + o_rq);
+    l.tiles = reinterpret_cast<const gst::BatchTile*>(base + (D == 16 ? o_t16 : o_t4));
+    l.n_tiles = D == 16 ? b->n_t16 : b->n_t4;
+    l.queue = queues + (D == 16 ? 0 : 16);
+    l.ckpt = reinterpret_cast<double*>(base + o_ck);
+    l.ckpt_per_team = ck_team;
+    l.status = ctx->status;
+    l.req_nonpos = b->req_nonpos;
+  }
+  b->red.items = reinterpret_cast<const gst::BatchReduceItem*>(base + o_it);
+  b->red.req_nonpos = b->req_nonpos;
+  if (capture_graph && !b->reqs.empty()) {
+    HIP_TRY(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
+    HIP_TRY(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
+    rc = batch_enqueue(b.get(), b->cap_stream);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(b->cap_stream, &g);
+    if (rc) return rc;
+    if (e != hipSuccess) return fail(GST_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+    b->graph = g;
+    HIP_TRY(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+  }
+  *out = b.release();
+  return GST_OK;
+}
+
+int gst_batch_run(gst_batch* b) {
+  if (!b) return fail(GST_EINVAL, "batch is NULL");
+  gst_ctx* ctx = b->ctx;
+  HIP_TRY(hipSetDevice(ctx->device));
+  {
+    ProfScope ps(ctx, FAM_BATCH);
+    if (b->exec) {
+      HIP_TRY(hipGraphLaunch(b->exec, ctx->stream));
+    } else {
+      int rc = batch_enqueue(b, ctx->stream);
+      if (rc) return rc;
+    }
+  }
+  for (int x : b->plan_reqs) {
+    gst_req* r = b->reqs[x];
+    const int mode = b->objectives[x] ? gst::MODE_LOGLIK : gst::MODE_PROBS;
+    int rc = run_plan(r, &b->thetas[x], mode, nullptr, b->probs[x], b->objectives[x], b->grads[x],
+                      b->req_nonpos + x);
+    if (rc) return rc;
+  }
+  return GST_OK;
+}
+
+int gst_batch_nonpos(gst_batch* b, int64_t* counts) {
+  if (!b || !counts) return fail(GST_EINVAL, "NULL argument");
+  HIP_TRY(hipSetDevice(b->ctx->device));
+  HIP_TRY(hipStreamSynchronize(b->ctx->stream));
+  std::vector<unsigned long long> v(b->reqs.size());
+  if (!v.empty()) HIP_TRY(hipMemcpy(v.data(), b->req_nonpos, v.size() * 8, hipMemcpyDeviceToHost));
+  for (size_t x = 0; x < v.size(); ++x) counts[x] = (int64_t)v[x];
+  return GST_OK;
+}
+
+int gst_batch_destroy(gst_batch* b) {
+  if (!b) return GST_OK;
+  (void)hipSetDevice(b->ctx->device);
+  (void)hipStreamSynchronize(b->ctx->stream);
+  delete b;
+  return GST_OK;
 }
 
 int gst_req_plan_info(const gst_req* req, int64_t* info, int n) {

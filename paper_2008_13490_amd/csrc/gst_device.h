@@ -354,8 +354,10 @@ __device__ __forceinline__ void flush_stash(const double* st_b, const double* st
   }
 }
 
-// Adds the four chains of each wave and the four waves, writes one slab
-// [objective | drho (D) | dE (M*D) | dG (K*D*D)] for this workgroup.
+// Adds the four chains of each wave and the four waves and writes the slab
+// row `slab` = [objective | drho (D) | dE (M*D) | dG (K*D*D)] (the caller
+// picks the row).  Reuses the LDS from its start: the staged gate set is
+// overwritten.
 template <int D>
 __device__ void write_slab(double* lds_raw, double obj, double drho, double (&dE)[16], d4 (&acc)[KMAX], int M,
                            int K, double* slab) {
@@ -393,7 +395,7 @@ __device__ void write_slab(double* lds_raw, double obj, double drho, double (&dE
   }
   __syncthreads();
   const int64_t P = slab_width(D, M, K);
-  double* out = slab + (int64_t)blockIdx.x * P;
+  double* out = slab;
   const double* red = lds_raw;
   for (int x = tid; x < P; x += blockDim.x) {
     int src;

@@ -80,6 +80,7 @@ struct PlanArgs {
   const double* inj;             // [n_inj][D]
   double* slab;
   unsigned long long* status;
+  unsigned long long* req_nonpos;  // optional per-request count of p <= 0 with N > 0
 };
 
 // inj[slot] = sum over its sources (ascending): item adjoints (src >= 0) and
@@ -109,6 +110,59 @@ struct GemmLaunch {
   double* slab;  // [n_chunks][P]
 };
 
+// Batched evaluation of many requests (persistent kernel, tile queue).
+struct BatchReq {
+  const double* rho;
+  const double* E;
+  const double* G;
+  const int64_t* off;
+  const uint8_t* gates;
+  const int64_t* order;    // sequence order (by length, descending) or null
+  const int32_t* counts;
+  const double* W;
+  double* probs;
+  double* slab;            // [n_tiles][P] of this request
+  int M, K, mode, want_grad;
+};
+struct BatchTile {
+  int32_t req;    // index into reqs
+  int32_t local;  // tile index within its request (slab row)
+  int64_t q0, q1; // positions in the request's order
+};
+struct BatchLaunch {
+  int D;
+  int kmax;
+  const BatchReq* reqs;            // null: every tile belongs to `one`
+  BatchReq one;
+  const BatchTile* tiles;
+  int n_tiles;
+  unsigned* queue;
+  double* ckpt;
+  int64_t ckpt_per_team;
+  unsigned long long* status;
+  unsigned long long* req_nonpos;  // [n_req]
+};
+struct BatchReduceItem {
+  int req;
+  int n_tiles;
+  int64_t P;
+  int64_t col0;
+  const double* slab;
+  double* objective;
+  double* grad;
+};
+struct BatchReduce {
+  const BatchReduceItem* items;    // null: block b reduces columns [64b, 64b+64) of `one`
+  BatchReduceItem one;
+  const unsigned long long* req_nonpos;
+};
+size_t batch_lds(int kmax);
+// Resident workgroups per CU of the batched kernel (occupancy with its LDS).
+int batch_blocks_per_cu(int D, int kmax);
+hipError_t launch_batch(const BatchLaunch& a, int n_blocks, hipStream_t stream);
+hipError_t launch_queue_reset(unsigned* q, unsigned long long* req_nonpos, int n_req, hipStream_t stream);
+hipError_t launch_batch_reduce(const BatchReduce& a, int n_items, hipStream_t stream);
+
 hipError_t launch_trunk_fwd(const PlanArgs& a, hipStream_t stream);
 hipError_t launch_trunk_bwd(const PlanArgs& a, hipStream_t stream);
 hipError_t launch_items(const PlanArgs& a, int n_blocks, hipStream_t stream);
@@ -126,12 +180,12 @@ int leaf_teams_per_block(int D);
 int max_gates_for(int D);
 
 // out[p] = sum of slab[w][p] over w (fixed two-stage order) plus extra_rho on
-// the rho entries; writes objective (p = 0) and the gradient (p >= 1).  When
-// status[1] > 0 the objective is +inf and grad is left untouched.  `part`
-// holds reduce_parts(n_slabs) * P doubles of scratch.
+// the rho entries; writes objective (p = 0) and the gradient (p >= 1).  The
+// kernels write +inf into their objective partial for p <= 0 with N > 0; the
+// objective is then +inf and grad is left untouched.  `part` holds
+// reduce_parts(n_slabs) * P doubles of scratch.
 int reduce_parts(int n_slabs);
 hipError_t launch_reduce(const double* slab, int n_slabs, int64_t P, double* objective, double* grad,
-                         const unsigned long long* status, const double* extra_rho, int D, double* part,
-                         hipStream_t stream);
+                         const double* extra_rho, int D, double* part, hipStream_t stream);
 
 }  // namespace gst

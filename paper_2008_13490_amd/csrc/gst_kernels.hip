@@ -148,6 +148,7 @@ __global__ __launch_bounds__(256) void leaf_kernel(const LeafLaunch a) {
         if (N > 0) {
           if (p <= 0.0) {
             ++nonpos;
+            obj = INFINITY;  // -N log p with p <= 0; no term is ever -inf
           } else {
             obj -= (double)N * log(p);
             dp = -(double)N / p;
@@ -217,7 +218,7 @@ __global__ __launch_bounds__(256) void leaf_kernel(const LeafLaunch a) {
   if (bad) atomicAdd(a.status + 0, (unsigned long long)bad);
   if (nonpos) atomicAdd(a.status + 1, (unsigned long long)nonpos);
   if (!grad && a.mode != MODE_LOGLIK) return;
-  write_slab<D>(lds_raw, obj, drho, dE, acc, M, K, a.slab);
+  write_slab<D>(lds_raw, obj, drho, dE, acc, M, K, a.slab + (int64_t)blockIdx.x * slab_width(D, M, K));
 }
 
 // Slab sums in two deterministic stages.  Stage 1: block (x, g) adds slabs
@@ -241,17 +242,25 @@ __global__ __launch_bounds__(256) void reduce_stage1(const double* __restrict__ 
 
 __global__ __launch_bounds__(256) void reduce_stage2(const double* __restrict__ part, int n_part, int64_t P,
                                                      double* objective, double* grad,
-                                                     const unsigned long long* __restrict__ status,
                                                      const double* __restrict__ extra_rho, int D) {
+  // An objective partial of +inf marks p <= 0 with N > 0 in this evaluation:
+  // the objective is then +inf and the gradient is not written.  Every block
+  // checks the n_part (<= 64) objective partials itself.
   __shared__ double red[4][64];
-  const bool nonpos = status && status[1] != 0;
+  __shared__ int nonpos_sh;
   const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
   const int64_t x = (int64_t)blockIdx.x * 64 + tx;
   double v = 0.0;
   if (x < P)
     for (int g = ty; g < n_part; g += 4) v += part[(int64_t)g * P + x];
   red[ty][tx] = v;
+  if (ty == 1) {
+    const bool inf = tx < n_part && isinf(part[(int64_t)tx * P]);
+    const bool any = __ballot(inf) != 0ull;
+    if (tx == 0) nonpos_sh = any ? 1 : 0;
+  }
   __syncthreads();
+  const bool nonpos = nonpos_sh != 0;
   if (ty != 0 || x >= P) return;
   v = (red[0][tx] + red[1][tx]) + (red[2][tx] + red[3][tx]);
   if (extra_rho && x >= 1 && x <= D) v += extra_rho[x - 1];
@@ -294,14 +303,13 @@ int reduce_parts(int n_slabs) {
 }
 
 hipError_t launch_reduce(const double* slab, int n_slabs, int64_t P, double* objective, double* grad,
-                         const unsigned long long* status, const double* extra_rho, int D, double* part,
-                         hipStream_t stream) {
+                         const double* extra_rho, int D, double* part, hipStream_t stream) {
   const int G = reduce_parts(n_slabs);
   const int per = (n_slabs + G - 1) / G;
   hipLaunchKernelGGL(reduce_stage1, dim3((unsigned)((P + 63) / 64), G), dim3(256), 0, stream, slab, n_slabs, P, per,
                      part);
   hipLaunchKernelGGL(reduce_stage2, dim3((unsigned)((P + 63) / 64)), dim3(256), 0, stream, part, G, P, objective, grad,
-                     status, extra_rho, D);
+                     extra_rho, D);
   return hipGetLastError();
 }
 

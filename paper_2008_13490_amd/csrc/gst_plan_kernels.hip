@@ -195,6 +195,7 @@ __global__ __launch_bounds__(256) void item_kernel(const PlanArgs a) {
         if (N > 0) {
           if (p <= 0.0) {
             ++nonpos;
+            obj = INFINITY;  // -N log p with p <= 0; no term is ever -inf
           } else {
             obj -= (double)N * log(p);
             dp = -(double)N / p;
@@ -232,12 +233,15 @@ __global__ __launch_bounds__(256) void item_kernel(const PlanArgs a) {
     if (has && i < D) a.item_adj[q * D + i] = b;
     if (has && anc < 0) drho += b;
   }
-  if (nonpos) atomicAdd(a.status + 1, (unsigned long long)nonpos);
+  if (nonpos) {
+    atomicAdd(a.status + 1, (unsigned long long)nonpos);
+    if (a.req_nonpos) atomicAdd(a.req_nonpos, (unsigned long long)nonpos);
+  }
   if (a.mode != MODE_LOGLIK && !grad) return;
   d4 zero[KMAX];
 #pragma unroll
   for (int k = 0; k < KMAX; ++k) zero[k] = d4{0.0, 0.0, 0.0, 0.0};
-  write_slab<D>(lds_raw, obj, drho, dE, zero, M, K, a.slab);
+  write_slab<D>(lds_raw, obj, drho, dE, zero, M, K, a.slab + (int64_t)blockIdx.x * slab_width(D, M, K));
 }
 
 // ---------------------------------------------------------------------------
@@ -324,7 +328,7 @@ __global__ __launch_bounds__(256) void trunk_bwd_kernel(const PlanArgs a) {
   d4 zero[KMAX];
 #pragma unroll
   for (int k = 0; k < KMAX; ++k) zero[k] = d4{0.0, 0.0, 0.0, 0.0};
-  write_slab<D>(lds_raw, 0.0, drho, dE, zero, a.M, K, a.slab);
+  write_slab<D>(lds_raw, 0.0, drho, dE, zero, a.M, K, a.slab + (int64_t)blockIdx.x * slab_width(D, a.M, K));
 }
 
 // One wave per injection slot: four groups of 16 lanes take every fourth

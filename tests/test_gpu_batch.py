@@ -1,0 +1,170 @@
+"""Batched evaluation of several resident requests (one persistent launch).
+
+Each request's result in a batch must be identical, bit for bit, to its
+standalone evaluation, and the standalone results must match the oracle
+(probabilities bit for bit, objective 1e-10 relative, gradient 1e-10
+normwise).  The graph-captured form is replayed several times with other
+work and synchronizations between replays, every replay checked against the
+eager result at the gate sets current at that time.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2008_13490_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2008_13490_amd import api
+    return api, api.Context(0)
+
+
+def _mix():
+    """(label, workload-like tuple) of a mixed batch: ragged 1q and 2q random
+    lists (plain tiles), one tiny list, the structured 1q list (sharing plan)
+    and an empty list."""
+    out = []
+    for kind, S, lmax, seed in (("1q", 700, 300, 11), ("2q", 500, 200, 12), ("1q", 37, 40, 13),
+                                ("2q", 170, 1030, 14)):
+        w = W.random_workload(kind, S, lmax, seed)
+        out.append((w.name, w.model, w.seqs, w.counts))
+    w = W.structured_workload("c1")
+    out.append(("c1", w.model, w.seqs, w.counts))
+    gs = W.noisy_gateset("2q", 1e-3, 0.01, np.random.default_rng(15))
+    empty = W.SeqList(np.zeros(1, np.int64), np.zeros(0, np.uint8), None)
+    out.append(("empty-2q", gs, empty, np.zeros((0, gs.M), np.int32)))
+    return out
+
+
+def _requests(api, ctx, mix):
+    reqs, thetas = [], []
+    for label, gs, sl, counts in mix:
+        r = api.Request(ctx, gs.n_qubits, gs.K, gs.M, sl.offsets, sl.gates, counts)
+        reqs.append(r)
+        thetas.append(api.DeviceGateSet.from_numpy(gs.n_qubits, gs.rho, gs.effects, gs.gates))
+        say(f"[batch] request {label}: S={sl.S} D={gs.D} K={gs.K} plan={r.plan_info()['plan_used']}")
+    return reqs, thetas
+
+
+def _standalone(ctx, reqs, thetas):
+    res = []
+    for r, t in zip(reqs, thetas):
+        obj, p, g = r.eval(t, want_probs=True, want_grad=True)
+        res.append((obj, p, g))
+    ctx.sync()
+    return [(o.clone(), p.clone(), g.clone()) for o, p, g in res]
+
+
+def _assert_same(batch, ref, labels):
+    import torch
+    for x, (o, p, g) in enumerate(ref):
+        assert torch.equal(batch.obj[x], o), (labels[x], batch.obj[x], o)
+        assert torch.equal(batch.probs[x], p), labels[x]
+        assert torch.equal(batch.grad[x], g), labels[x]
+
+
+def test_batch_equals_standalone_and_oracle(oracle_lib, gpu):
+    api, ctx = gpu
+    mix = _mix()
+    labels = [m[0] for m in mix]
+    reqs, thetas = _requests(api, ctx, mix)
+    ref = _standalone(ctx, reqs, thetas)
+    for (label, gs, sl, counts), (o, p, g) in zip(mix, ref):
+        say(f"[batch] oracle check {label}")
+        F, p_or, g_or, _, _ = oracle_lib.loglik(gs.rho, gs.effects, gs.gates, sl.offsets, sl.gates, counts)
+        assert np.array_equal(p.cpu().numpy(), p_or), label
+        Fg = float(o.cpu()[0])
+        assert abs(Fg - F) <= 1e-10 * max(abs(F), 1e-300), (label, Fg, F)
+        gg = g.cpu().numpy()
+        assert np.abs(gg - g_or).max() <= 1e-10 * max(np.abs(g_or).max(), 1e-300), label
+    say("[batch] eager batch")
+    b = api.Batch(ctx, reqs, thetas, want_probs=True, want_grad=True, capture_graph=False)
+    for _ in range(2):
+        b.run()
+        ctx.sync()
+        _assert_same(b, ref, labels)
+    assert b.nonpos() == [0] * len(reqs)
+    # a sub-batch in another order gives the same results for its members
+    say("[batch] sub-batch, reversed order")
+    sub = [4, 1, 0]
+    b2 = api.Batch(ctx, [reqs[x] for x in sub], [thetas[x] for x in sub], want_probs=True, want_grad=True)
+    b2.run()
+    ctx.sync()
+    _assert_same(b2, [ref[x] for x in sub], [labels[x] for x in sub])
+    b.close()
+    b2.close()
+
+
+def test_batch_graph_replays(gpu):
+    import torch
+    api, ctx = gpu
+    mix = _mix()
+    labels = [m[0] for m in mix]
+    reqs, thetas = _requests(api, ctx, mix)
+    b = api.Batch(ctx, reqs, thetas, want_probs=True, want_grad=True, capture_graph=True)
+    rng = np.random.default_rng(21)
+    scratch = torch.zeros(1 << 20, dtype=torch.float64, device="cuda")
+    for rep in range(4):
+        say(f"[batch] graph replay {rep}")
+        if rep > 0:
+            # new gate sets in place (the graph holds the pointers)
+            for (label, gs, _, _), t in zip(mix, thetas):
+                g2 = W.noisy_gateset({1: "1q", 2: "2q"}[gs.n_qubits], 1e-3, 0.01, rng)
+                t.gates.copy_(torch.as_tensor(g2.gates, device="cuda"))
+        ref = _standalone(ctx, reqs, thetas)
+        scratch.add_(1.0)                        # unrelated eager work between replays
+        b.run()
+        torch.cuda.synchronize()
+        ctx.sync()
+        _assert_same(b, ref, labels)
+        for r, t in zip(reqs[:2], thetas[:2]):   # more eager library work on the same stream
+            r.eval(t, want_probs=False, want_grad=True)
+        ctx.sync()
+    b.close()
+
+
+def test_batch_nonpos_is_per_request(oracle_lib, gpu):
+    api, ctx = gpu
+    good = W.random_workload("2q", 300, 120, 31)
+    bad = W.random_workload("1q", 200, 60, 32)
+    E0 = bad.model.effects.copy()
+    E0[1] = 0.0                                 # p_1 = 0 wherever N_1 > 0
+    reqs, thetas = [], []
+    for gs, sl, cnt, E in ((good.model, good.seqs, good.counts, good.model.effects),
+                           (bad.model, bad.seqs, bad.counts, E0)):
+        reqs.append(api.Request(ctx, gs.n_qubits, gs.K, gs.M, sl.offsets, sl.gates, cnt))
+        thetas.append(api.DeviceGateSet.from_numpy(gs.n_qubits, gs.rho, E, gs.gates))
+    p_or = oracle_lib.probs(bad.model.rho, E0, bad.model.gates, bad.seqs.offsets, bad.seqs.gates)
+    n_expected = int(np.count_nonzero((p_or <= 0) & (bad.counts > 0)))
+    assert n_expected > 0
+    say("[batch] nonpos: standalone")
+    o_bad, _, _ = reqs[1].eval(thetas[1])
+    o_good, _, g_good = reqs[0].eval(thetas[0])
+    rc, _, nnp = ctx.sync(raise_on_error=False)
+    assert rc == -3 and nnp == n_expected
+    assert float(o_bad.cpu()[0]) == float("inf")
+    # a failing evaluation does not leak into the next one
+    F, _, g_or, _, _ = oracle_lib.loglik(good.model.rho, good.model.effects, good.model.gates, good.seqs.offsets,
+                                         good.seqs.gates, good.counts)
+    assert abs(float(o_good.cpu()[0]) - F) <= 1e-10 * abs(F)
+    say("[batch] nonpos: batched")
+    b = api.Batch(ctx, reqs, thetas, want_probs=False, want_grad=True, capture_graph=True)
+    b.run()
+    assert b.nonpos() == [0, n_expected]
+    rc, _, nnp = ctx.sync(raise_on_error=False)
+    assert rc == -3 and nnp == n_expected
+    import torch
+    assert torch.equal(b.obj[0], o_good) and torch.equal(b.grad[0], g_good)
+    assert float(b.obj[1].cpu()[0]) == float("inf")
+    b.close()
