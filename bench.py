@@ -19,6 +19,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -44,41 +46,59 @@ def workload_desc(w):
 # ---------------------------------------------------------------------------
 # CPU baseline: the oracle, unchanged, on the machine's host cores
 # ---------------------------------------------------------------------------
+def _cpu_sample(name):
+    """Oracle inputs for the CPU baseline: a list of (gate set, sequences, counts)."""
+    from paper_2008_13490_amd import workloads as W
+    if name == "c3":
+        # the first 8 gate sets of the uneven batch, first 256 sequences of each
+        out = []
+        for kind, S, seed in W.c3_plan()[:8]:
+            w = W.uneven_request(kind, S, seed)
+            sub = w.seqs.subset(np.arange(256))
+            out.append((w.model, sub, w.counts[:256]))
+        return out, "first 8 gate sets of the uneven batch (6 one-qubit, 2 two-qubit by the seeded mix), " \
+                    "256 sequences of each"
+    w = W.structured_workload(name)
+    return [(w.model, w.seqs, w.counts)], f"{name} full list ({w.seqs.S} sequences)"
+
+
 def _cpu_worker(args):
     name, seconds = args
     sys.path.insert(0, ROOT)
     import oracle
-    from paper_2008_13490_amd import workloads as W
-    w = W.structured_workload(name)
-    m = w.model
+    sample, _ = _cpu_sample(name)
     n = 0
+    seqs = 0
     t0 = time.perf_counter()
     while True:
-        oracle.loglik(m.rho, m.effects, m.gates, w.seqs.offsets, w.seqs.gates, w.counts)
+        for m, sl, cnt in sample:
+            oracle.loglik(m.rho, m.effects, m.gates, sl.offsets, sl.gates, cnt)
+            seqs += sl.S
         n += 1
         if time.perf_counter() - t0 >= seconds:
             break
-    return n, time.perf_counter() - t0, w.seqs.S
+    return n, time.perf_counter() - t0, seqs
 
 
 def cpu_baseline(name: str, seconds: float, workers: int):
     import multiprocessing as mp
     import oracle
     oracle.build(force=not os.path.exists(oracle.library_path()))
+    _, what = _cpu_sample(name)
     ctx = mp.get_context("spawn")
     t0 = time.perf_counter()
     with ctx.Pool(workers) as pool:
         res = pool.map(_cpu_worker, [(name, seconds)] * workers)
     wall = time.perf_counter() - t0
-    evals = sum(r[0] for r in res)
-    S = res[0][2]
+    passes = sum(r[0] for r in res)
+    seqs = sum(r[2] for r in res)
     busy = max(r[1] for r in res)
     return {
-        "value": evals * S / busy,
+        "value": seqs / busy,
         "unit": "sequence evals/s",
         "cores": workers,
         "kind": "oracle",
-        "sample": f"{name} full list ({S} sequences) evaluated {evals} times with gradient, "
+        "sample": f"{what} evaluated {passes} times with gradient, "
                   f"{workers} single-threaded processes for ~{seconds:.0f} s each (wall {wall:.1f} s)",
     }
 
@@ -93,10 +113,10 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def read_traffic(family: str):
+def read_traffic(workload: str, family: str):
     """HBM bytes per launch from the committed counter summary, if it was taken
     on the current kernel sources; else None."""
-    path = os.path.join(ROOT, "profiles", "hbm_traffic_c2.txt")
+    path = os.path.join(ROOT, "profiles", f"hbm_traffic_{workload}.txt")
     if not os.path.exists(path):
         return None
     vals = {}
@@ -116,12 +136,19 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="c2")
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3"])
     ap.add_argument("--path", choices=["resident", "plain"], default="resident")
+    ap.add_argument("--sets", type=int, default=0, help="c3: use only the first N gate sets")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--cpu-workers", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only copy MIB mebibytes device to device a few times (reference kernel for the "
+                         "HBM byte counters) and exit")
     args = ap.parse_args()
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU only; the path shards by sequence and "
                                    "all-reduces the gradient (see DESIGN.md), but no multi-GPU run is part "
@@ -133,8 +160,55 @@ def main():
     if not args.no_cpu:
         workers = args.cpu_workers or max(1, min(16, os.cpu_count() or 1))
         cpu = cpu_baseline(args.workload, args.cpu_seconds, workers)
+    if args.workload == "c3":
+        out = run_uneven(args)
+    else:
+        out = run_structured(args)
+    out["cpu_baseline"] = cpu
+    print(json.dumps(out))
 
-    import numpy as np
+
+def copy_calibration(mib: int):
+    """A plain device-to-device copy of a known size: its FETCH_SIZE and
+    WRITE_SIZE counters per dispatch, against mib MiB each, give the factor
+    that turns the counters into HBM bytes."""
+    import torch
+    n = mib * (1 << 20) // 8
+    x = torch.arange(n, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_mib": mib, "dispatches": 3, "equal": bool(torch.equal(x, y))}))
+
+
+def _profile(api, ctx, families):
+    fams = {}
+    for fam in families:
+        ms, n = api.profile_read(ctx, fam)
+        if n:
+            fams[fam] = (ms, n)
+    return fams
+
+
+def _roofline(dom, fams, flops, traffic):
+    ms_tot, n_launch = fams[dom]
+    avg_s = ms_tot / n_launch * 1e-3
+    achieved = flops / avg_s / 1e12
+    return {
+        "bound": "alu",
+        "kernel": dom,
+        "achieved": achieved,
+        "peak": PEAK_FP64,
+        "unit": "TFLOP/s",
+        "frac": achieved / PEAK_FP64,
+        "traffic": traffic,
+        "avg_launch_us": avg_s * 1e6,
+        "algorithmic_flop_per_launch": flops,
+    }
+
+
+def run_structured(args):
     import torch
     from paper_2008_13490_amd import api
     from paper_2008_13490_amd import workloads as W
@@ -173,11 +247,8 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ctx.sync()
-    fams = {}
-    for fam in ("leaf", "reduce", "trunk_fwd", "trunk_bwd", "inject", "grad_gemm"):
-        ms, n = api.profile_read(ctx, fam)
-        if n:
-            fams[fam] = (ms, n)
+    fams = _profile(api, ctx, ("leaf", "reduce", "trunk_fwd", "trunk_bwd", "inject", "grad_gemm", "tiles_2q",
+                               "tiles_1q", "tiles_reduce"))
     api.profile_enable(ctx, False)
     elapsed = t1 - t0
     S = w.seqs.S
@@ -185,15 +256,12 @@ def main():
 
     # dominant kernel and its algorithmic FP64 work per launch
     dom = max(fams, key=lambda f: fams[f][0])
-    ms_tot, n_launch = fams[dom]
-    avg_s = ms_tot / n_launch * 1e-3
-    D, M = 16, m.M
+    D, M = m.D, m.M
     L = w.seqs.lengths()
     info = req_plan_info(req) if args.path == "resident" else None
     flops = algorithmic_flops(dom, D, M, S, int(L.sum()), info)
-    achieved = flops / avg_s / 1e12
-    traffic = read_traffic(dom)
-    out = {
+    steps_eval = (info["trunk_steps"] + info["item_steps"]) if info else int(L.sum())
+    return {
         "metric": METRIC,
         "value": value,
         "unit": "sequence evals/s",
@@ -207,24 +275,99 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": dict(desc, path=args.path),
-        "roofline": {
-            "bound": "alu",
-            "kernel": dom,
-            "achieved": achieved,
-            "peak": PEAK_FP64,
-            "unit": "TFLOP/s",
-            "frac": achieved / PEAK_FP64,
-            "traffic": traffic,
-            "avg_launch_us": avg_s * 1e6,
-            "algorithmic_flop_per_launch": flops,
-        },
+        "roofline": _roofline(dom, fams, flops, read_traffic(args.workload, dom)),
         "kernels_ms_per_step": {f: fams[f][0] / args.steps for f in fams},
         "plan": info,
-        "useful_tflops": (6.0 * D * D * (info["trunk_steps"] + info["item_steps"]) if info else
-                          6.0 * D * D * int(L.sum())) / (elapsed / args.steps) / 1e12 if True else None,
-        "cpu_baseline": cpu,
+        "useful_tflops": 6.0 * D * D * steps_eval / (elapsed / args.steps) / 1e12,
     }
-    print(json.dumps(out))
+
+
+def run_uneven(args):
+    """The uneven batch: 512 gate sets (70% one-qubit, 30% two-qubit), each
+    with 500..20000 random words of length 1..1024, evaluated with gradient
+    in one graph-captured persistent launch per step."""
+    import torch
+    from paper_2008_13490_amd import api
+    from paper_2008_13490_amd import workloads as W
+
+    plan = W.c3_plan()
+    if args.sets:
+        plan = plan[:args.sets]
+    ctx = api.Context(0)
+    reqs, thetas = [], []
+    S_tot = sum_len = 0
+    flops = {16: 0.0, 4: 0.0}
+    t0 = time.perf_counter()
+    for kind, S, seed in plan:
+        w = W.uneven_request(kind, S, seed)
+        m = w.model
+        reqs.append(api.Request(ctx, m.n_qubits, m.K, m.M, w.seqs.offsets, w.seqs.gates, w.counts))
+        thetas.append(api.DeviceGateSet.from_numpy(m.n_qubits, m.rho, m.effects, m.gates))
+        n = int(w.seqs.offsets[-1])
+        S_tot += S
+        sum_len += n
+        flops[m.D] += 6.0 * m.D * m.D * n + 6.0 * m.D * m.M * S
+        del w
+        if len(reqs) % 64 == 0:
+            print(f"[bench] {len(reqs)} requests resident", file=sys.stderr, flush=True)
+    t_setup = time.perf_counter() - t0
+    print(f"[bench] uneven batch: {len(plan)} gate sets, {S_tot} sequences, {sum_len} steps, "
+          f"set-up {t_setup:.1f} s", file=sys.stderr, flush=True)
+    batch = api.Batch(ctx, reqs, thetas, want_probs=False, want_grad=True, capture_graph=True)
+    for _ in range(args.warmup):
+        batch.run()
+    ctx.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        batch.run()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ctx.sync()
+    elapsed = t1 - t0
+    print(f"[bench] graph replays: {elapsed / args.steps * 1e3:.2f} ms per step", file=sys.stderr, flush=True)
+    # the same launch sequence eagerly, each kernel bracketed by events
+    n_prof = max(1, min(args.steps, 5))
+    api.profile_enable(ctx, True)
+    for _ in range(n_prof):
+        batch.run()
+    ctx.sync()
+    fams = _profile(api, ctx, ("tiles_2q", "tiles_1q", "tiles_reduce", "batch"))
+    api.profile_enable(ctx, False)
+    # the plain per-request path: each request on its own, one after another
+    t2 = time.perf_counter()
+    outs = [r.eval(t, want_probs=False, want_grad=True) for r, t in zip(reqs, thetas)]
+    torch.cuda.synchronize()
+    ctx.sync()
+    plain_s = time.perf_counter() - t2
+    ok = all(torch.equal(o[0], batch.obj[x]) and torch.equal(o[2], batch.grad[x]) for x, o in enumerate(outs))
+    dom = max((f for f in fams if f != "batch"), key=lambda f: fams[f][0])
+    dom_flops = flops[16] if dom == "tiles_2q" else flops[4] if dom == "tiles_1q" else 0.0
+    n1 = sum(1 for k, _, _ in plan if k == "1q")
+    return {
+        "metric": "sequence evals/s incl. gradient (uneven batch of 1q/2q gate sets, FP64)",
+        "value": S_tot * args.steps / elapsed,
+        "unit": "sequence evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"c3: uneven batch of {len(plan)} gate sets ({n1} one-qubit, {len(plan) - n1} "
+                               "two-qubit), S ~ U{500..20000}, random words of length U{1..1024}, one "
+                               "graph-captured persistent launch per step; counts ~ Multinomial(1000, uniform)",
+                   "sequences": S_tot, "sum_len": sum_len, "gate_sets": len(plan)},
+        "roofline": _roofline(dom, fams, dom_flops, read_traffic("c3", dom)),
+        "kernels_ms_per_step": {f: fams[f][0] / n_prof for f in fams},
+        "useful_tflops": (flops[16] + flops[4]) / (elapsed / args.steps) / 1e12,
+        "plain_per_request": {"ms_per_step": plain_s * 1e3, "value": S_tot / plain_s,
+                              "same_bits_as_batch": bool(ok)},
+        "setup_s": t_setup,
+    }
 
 
 def req_plan_info(req):
@@ -241,7 +384,7 @@ def algorithmic_flops(family, D, M, S, sum_len, info):
     the chains are the stored trunk steps plus the remaining item steps
     (launch counts: one per trunk level)."""
     if info is None:
-        if family == "leaf":
+        if family in ("leaf", "tiles_2q", "tiles_1q"):
             return 6.0 * D * D * sum_len + 6.0 * D * M * S
         return 0.0
     ts, its, lv = info["trunk_steps"], info["item_steps"], max(1, info["levels"])

@@ -155,7 +155,7 @@ int gst_req_plan_info(const gst_req* req, int64_t* info, int n);
 /*
  * Batches: several resident requests evaluated together, as the continuous
  * batching of a fit service needs.  Requests without a sharing plan are cut
- * into tiles of 128 sequences (sorted by length; the cut depends on the
+ * into tiles of 16 to 128 sequences (sorted by length; the cut depends on the
  * request alone) that one persistent launch takes from a work queue; every
  * tile writes its own partial sums and each request's tiles are added in
  * tile order, so each result is identical whether the request is evaluated
@@ -166,7 +166,10 @@ int gst_req_plan_info(const gst_req* req, int64_t* info, int n);
  * contents may change between runs) and the output pointers; any of probs,
  * objectives, grads may be NULL or hold NULL entries (an objective is needed
  * for a gradient).  capture_graph != 0 records the batched launch sequence
- * into a HIP graph once; gst_batch_run then replays it on the context stream.
+ * into a HIP graph once; gst_batch_run then replays it on the context stream
+ * (eagerly instead while kernel timing is enabled).  A standalone request
+ * without a plan runs the same kernels, so its results equal its results in
+ * any batch bit for bit.
  * gst_batch_nonpos synchronizes and returns, per request, the number of
  * p <= 0 entries with positive counts in the last run (objective +inf).
  */
@@ -183,7 +186,8 @@ int gst_batch_destroy(gst_batch* batch);
  * enqueues is bracketed by two HIP events recorded on the context's stream.
  * gst_profile_read synchronizes the stream and returns, for the kernel family
  * `kernel` ("leaf", "reduce", "trunk_fwd", "trunk_bwd", "inject",
- * "grad_gemm", "batch"), the summed
+ * "grad_gemm", "tiles_2q", "tiles_1q", "tiles_reduce", or "batch" for a
+ * whole gst_batch_run), the summed
  * elapsed milliseconds and the number of launches since profiling was
  * enabled; the counters are not reset by reading.
  */

@@ -67,8 +67,9 @@ struct Profiler {
   };
   std::vector<Pending> pending;
   std::vector<hipEvent_t> pool;
-  double total_ms[8] = {0};
-  int64_t launches[8] = {0};
+  static constexpr int kMaxFamilies = 16;
+  double total_ms[kMaxFamilies] = {0};
+  int64_t launches[kMaxFamilies] = {0};
   hipEvent_t get() {
     if (!pool.empty()) {
       hipEvent_t e = pool.back();
@@ -89,8 +90,10 @@ struct Profiler {
 };
 
 enum Family { FAM_LEAF = 0, FAM_REDUCE = 1, FAM_TRUNK_FWD = 2, FAM_TRUNK_BWD = 3, FAM_INJECT = 4, FAM_GEMM = 5,
-              FAM_BATCH = 6, FAM_N = 7 };
-static const char* kFamilyNames[FAM_N] = {"leaf", "reduce", "trunk_fwd", "trunk_bwd", "inject", "grad_gemm", "batch"};
+              FAM_BATCH = 6, FAM_TILES16 = 7, FAM_TILES4 = 8, FAM_TILES_RED = 9, FAM_N = 10 };
+static_assert(FAM_N <= Profiler::kMaxFamilies, "profiler arrays too small");
+static const char* kFamilyNames[FAM_N] = {"leaf",  "reduce",  "trunk_fwd", "trunk_bwd",   "inject",
+                                          "grad_gemm", "batch", "tiles_2q",  "tiles_1q", "tiles_reduce"};
 
 // Carve consecutive aligned regions out of one allocation.
 struct Carver {
@@ -119,13 +122,13 @@ struct ProfScope {
   int fam;
   hipEvent_t a = nullptr;
   ProfScope(gst_ctx* ctx, int family) : c(ctx), fam(family) {
-    if (c->prof.on) {
+    if (c && c->prof.on) {
       a = c->prof.get();
       if (a) (void)hipEventRecord(a, c->stream);
     }
   }
   ~ProfScope() {
-    if (c->prof.on && a) {
+    if (c && c->prof.on && a) {
       hipEvent_t b = c->prof.get();
       if (b) {
         (void)hipEventRecord(b, c->stream);
@@ -788,7 +791,9 @@ static int run_tiles(gst_req* r, const gst_gateset* th, int mode, const double* 
   const int grid = (int)std::min<int64_t>(nt, (int64_t)bpc * ctx->n_cu);
   const int64_t ck_team = tile_ckpt_per_team(r->max_len);
   const size_t ck_bytes = want_grad ? (size_t)grid * gst::leaf_teams_per_block(16) * ck_team * 8 : 0;
-  int rc = r->ws.reserve(ck_bytes + 256, ctx->stream);
+  // checkpoints in the context workspace: calls on a context are stream
+  // ordered, so every request can share it
+  int rc = ctx->ws.reserve(ck_bytes + 256, ctx->stream);
   if (rc) return rc;
   gst::BatchLaunch l{};
   l.D = r->D;
@@ -798,17 +803,17 @@ static int run_tiles(gst_req* r, const gst_gateset* th, int mode, const double* 
   l.tiles = r->tiles;
   l.n_tiles = (int)nt;
   l.queue = r->queue;
-  l.ckpt = want_grad ? reinterpret_cast<double*>(r->ws.p) : nullptr;
+  l.ckpt = want_grad ? reinterpret_cast<double*>(ctx->ws.p) : nullptr;
   l.ckpt_per_team = ck_team;
   l.status = ctx->status;
   l.req_nonpos = reinterpret_cast<unsigned long long*>(r->queue + 64);
-  {
-    ProfScope ps(ctx, FAM_LEAF);
-    HIP_TRY(gst::launch_queue_reset(r->queue, l.req_nonpos, 1, ctx->stream));
-    if (grid > 0) HIP_TRY(gst::launch_batch(l, grid, ctx->stream));
+  HIP_TRY(gst::launch_queue_reset(r->queue, l.req_nonpos, 1, ctx->stream));
+  if (grid > 0) {
+    ProfScope ps(ctx, r->D == 16 ? FAM_TILES16 : FAM_TILES4);
+    HIP_TRY(gst::launch_batch(l, grid, ctx->stream));
   }
   if (objective || grad) {
-    ProfScope ps(ctx, FAM_REDUCE);
+    ProfScope ps(ctx, FAM_TILES_RED);
     gst::BatchReduce red{};
     red.items = nullptr;
     red.one.req = 0;
@@ -853,13 +858,24 @@ int gst_req_vjp(gst_req* req, const gst_gateset* theta, const double* w, double*
   return req_run(req, theta, gst::MODE_VJP, w, nullptr, nullptr, grad);
 }
 
-static int batch_enqueue(gst_batch* b, hipStream_t stream) {
+// Enqueue the batched launch sequence on `stream`.  Per-kernel profiling
+// scopes are recorded only for eager runs on the context stream.
+static int batch_enqueue(gst_batch* b, hipStream_t stream, bool eager) {
+  gst_ctx* ctx = b->ctx;
+  gst_ctx* pc = eager ? ctx : nullptr;
   if (!b->reqs.empty())
     HIP_TRY(gst::launch_queue_reset(reinterpret_cast<unsigned*>(b->l16.queue), b->req_nonpos,
                                     (int)b->reqs.size(), stream));
-  if (b->n_t16 > 0 || b->n_t4 > 0) {
-    if (b->n_t16 > 0) HIP_TRY(gst::launch_batch(b->l16, b->grid16, stream));
-    if (b->n_t4 > 0) HIP_TRY(gst::launch_batch(b->l4, b->grid4, stream));
+  if (b->n_t16 > 0) {
+    ProfScope ps(pc, FAM_TILES16);
+    HIP_TRY(gst::launch_batch(b->l16, b->grid16, stream));
+  }
+  if (b->n_t4 > 0) {
+    ProfScope ps(pc, FAM_TILES4);
+    HIP_TRY(gst::launch_batch(b->l4, b->grid4, stream));
+  }
+  if (b->n_items > 0) {
+    ProfScope ps(pc, FAM_TILES_RED);
     HIP_TRY(gst::launch_batch_reduce(b->red, b->n_items, stream));
   }
   return GST_OK;
@@ -988,7 +1004,7 @@ int gst_batch_create(gst_ctx* ctx, int n, gst_req* const* reqs, const gst_gatese
   if (capture_graph && !b->reqs.empty()) {
     HIP_TRY(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
     HIP_TRY(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
-    rc = batch_enqueue(b.get(), b->cap_stream);
+    rc = batch_enqueue(b.get(), b->cap_stream, false);
     hipGraph_t g = nullptr;
     const hipError_t e = hipStreamEndCapture(b->cap_stream, &g);
     if (rc) return rc;
@@ -1005,11 +1021,13 @@ int gst_batch_run(gst_batch* b) {
   gst_ctx* ctx = b->ctx;
   HIP_TRY(hipSetDevice(ctx->device));
   {
+    // While profiling, the launch sequence runs eagerly so that every kernel
+    // is bracketed by its own events; otherwise the captured graph replays.
     ProfScope ps(ctx, FAM_BATCH);
-    if (b->exec) {
+    if (b->exec && !ctx->prof.on) {
       HIP_TRY(hipGraphLaunch(b->exec, ctx->stream));
     } else {
-      int rc = batch_enqueue(b, ctx->stream);
+      int rc = batch_enqueue(b, ctx->stream, true);
       if (rc) return rc;
     }
   }

@@ -25,15 +25,19 @@ namespace {
 // The slab reduction reuses the LDS of the staged gate set (as in the plain
 // sequence kernel), so a workgroup restages after every tile that writes a
 // slab; the smaller footprint keeps two or three workgroups per CU.
-__host__ __device__ inline size_t batch_lds_bytes(int K) {
+// The tile index a workgroup works on sits in the last 16 bytes.  (A static
+// __shared__ variable would be placed before the dynamic area and shift it
+// off the 16-byte alignment that the row reads of ds_read_b128 need.)
+__host__ __device__ inline size_t batch_lds_core(int K) {
   const size_t a = lds_main_bytes(K), b = lds_red_bytes(K);
-  return a > b ? a : b;
+  return ((a > b ? a : b) + 15) / 16 * 16;
 }
+__host__ __device__ inline size_t batch_lds_bytes(int K) { return batch_lds_core(K) + 16; }
 
 template <int D>
 __global__ __launch_bounds__(256) void batch_kernel(const BatchLaunch a) {
   extern __shared__ double lds_raw[];
-  __shared__ int tile_sh;
+  int& tile_sh = *reinterpret_cast<int*>(reinterpret_cast<char*>(lds_raw) + batch_lds_core(a.kmax));
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, i = lane & 15, team = lane >> 4;
   int staged = -1;
   Lds s = carve(lds_raw, a.kmax);
@@ -51,6 +55,12 @@ __global__ __launch_bounds__(256) void batch_kernel(const BatchLaunch a) {
     const BatchTile T = a.tiles[tile];
     const BatchReq R = a.reqs ? a.reqs[T.req] : a.one;
     const int K = R.K, M = R.M;
+    const auto* g_off = as_global(R.off);
+    const auto* g_order = as_global(R.order);
+    const auto* g_gates = as_global(R.gates);
+    const auto* g_counts = as_global(R.counts);
+    const auto* g_W = as_global(R.W);
+    auto* g_probs = as_global(R.probs);
     if (T.req != staged) {
       // a different gate set: restage (carve for this request's K inside the kmax layout)
       s = carve(lds_raw, a.kmax);
@@ -71,20 +81,26 @@ __global__ __launch_bounds__(256) void batch_kernel(const BatchLaunch a) {
     for (int64_t grp = wave; grp < n_groups; grp += WAVES) {
       const int64_t qq = T.q0 + grp * TPW + team;
       const bool has = qq < T.q1;
-      const int64_t seq = has ? (R.order ? R.order[qq] : qq) : 0;
-      const int64_t beg = has ? R.off[seq] : 0;
-      const int L = has ? (int)(R.off[seq + 1] - beg) : 0;
+      const int64_t seq = has ? (R.order ? g_order[qq] : qq) : 0;
+      const int64_t beg = has ? g_off[seq] : 0;
+      const int L = has ? (int)(g_off[seq + 1] - beg) : 0;
       const int Lw = wave_max4(L);
-      const uint8_t* word = R.gates + beg;
+      const auto* word = g_gates + beg;
       double f = s.rho[i];
+      // Gate indices are loaded one chunk of 16 steps ahead of their use.
+      // The loads are unconditional (past the end of the word they read the
+      // first index of the list, which always exists) so that the compiler
+      // can wait for the previous load alone.
+      int kv_next = *(i < L ? word + i : g_gates);
+      kv_next = i < L ? kv_next : 0;
       for (int t0 = 0; t0 < Lw; t0 += 16) {
-        int kv = 0;
-        if (t0 + i < L) {
-          kv = word[t0 + i];
-          if (kv >= K) {
-            ++bad;
-            kv = 0;
-          }
+        int kv = kv_next;
+        const bool in = t0 + 16 + i < L;
+        kv_next = *(in ? word + t0 + 16 + i : g_gates);
+        kv_next = in ? kv_next : 0;
+        if (t0 + i < L && kv >= K) {
+          ++bad;
+          kv = 0;
         }
 #define GST_FWD_STEP(RR)                                                   \
   if (t0 + RR < Lw) {                                                      \
@@ -104,9 +120,9 @@ __global__ __launch_bounds__(256) void batch_kernel(const BatchLaunch a) {
       double dp = 0.0;
       if (has && i < M) {
         const int64_t o = seq * M + i;
-        if (R.probs) R.probs[o] = p;
+        if (R.probs) g_probs[o] = p;
         if (R.mode == MODE_LOGLIK) {
-          const int32_t N = R.counts[o];
+          const int32_t N = g_counts[o];
           if (N > 0) {
             if (p <= 0.0) {
               ++nonpos;
@@ -117,7 +133,7 @@ __global__ __launch_bounds__(256) void batch_kernel(const BatchLaunch a) {
             }
           }
         } else if (R.mode == MODE_VJP) {
-          dp = R.W[o];
+          dp = g_W[o];
         }
       }
       if (!grad) continue;
@@ -126,19 +142,34 @@ __global__ __launch_bounds__(256) void batch_kernel(const BatchLaunch a) {
       GST_DE(0) GST_DE(1) GST_DE(2) GST_DE(3) GST_DE(4) GST_DE(5) GST_DE(6) GST_DE(7)
       GST_DE(8) GST_DE(9) GST_DE(10) GST_DE(11) GST_DE(12) GST_DE(13) GST_DE(14) GST_DE(15)
 #undef GST_DE
-      double b = dot16_bcast(dp, reinterpret_cast<const double2*>(s.ETs + i * ROW));
       const int nseg = (L + C - 1) / C;
       const int nsegw = wave_max4(nseg);
+      // segment c needs its C gate indices and its checkpoint; both are
+      // loaded one segment ahead of their use
+      int kv_nx, kv_in;
+      double ck_nx;
+      {
+        const int c = nsegw - 1;
+        const bool seg = c >= 0 && c < nseg;
+        kv_in = seg && i < C && c * C + i < L;
+        kv_nx = *(kv_in ? word + c * C + i : g_gates);
+        ck_nx = *(seg ? ck + c * 16 + i : ck);
+        kv_nx = kv_in ? kv_nx : 0;
+      }
+      double b = dot16_bcast(dp, reinterpret_cast<const double2*>(s.ETs + i * ROW));
       for (int c = nsegw - 1; c >= 0; --c) {
         const bool act = c < nseg;
         const int base = c * C;
-        int kv = 0;
-        if (act && i < C && base + i < L) {
-          kv = word[base + i];
-          if (kv >= K) kv = 0;
-        }
+        int kv = kv_in ? kv_nx : 0;
+        if (kv >= K) kv = 0;
         double fs[C];
-        fs[0] = act ? ck[c * 16 + i] : 0.0;
+        fs[0] = act ? ck_nx : 0.0;
+        {
+          const bool seg = c >= 1 && c - 1 < nseg;
+          kv_in = seg && i < C && (c - 1) * C + i < L;
+          kv_nx = *(kv_in ? word + (c - 1) * C + i : g_gates);
+          ck_nx = *(seg ? ck + (c - 1) * 16 + i : ck);
+        }
 #define GST_REC(RR)                                          \
   {                                                          \
     const int k = bcast_i32<RR - 1>(kv);                     \

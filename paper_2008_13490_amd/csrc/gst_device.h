@@ -239,6 +239,15 @@ __device__ __forceinline__ double step_bwd(double x, const Row16& c, uint32_t na
 
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// A pointer read from memory is generic to the compiler, and a generic (flat)
+// load is counted by both vmcnt and lgkmcnt, so the first LDS wait after it
+// also waits for it.  This cast states that the pointer addresses global
+// memory: its loads are counted by vmcnt alone and can stay in flight.
+template <class T>
+__device__ __forceinline__ __attribute__((address_space(1))) T* as_global(T* p) {
+  return (__attribute__((address_space(1))) T*)p;
+}
+
 // max over the four 16-lane rows of a wave, as a wave-uniform value
 __device__ __forceinline__ int wave_max4(int v) {
   v = max(v, __shfl_xor(v, 16));

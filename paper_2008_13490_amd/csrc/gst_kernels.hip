@@ -112,15 +112,15 @@ __global__ __launch_bounds__(256) void leaf_kernel(const LeafLaunch a) {
     else
       f = s.rho[i];
 
-    // ---- forward chain (checkpoint every C steps) ----
+    // ---- forward chain (checkpoint every C steps); gate indices are
+    // loaded one chunk of 16 steps ahead ----
+    int kv_next = i < L ? (int)word[i] : 0;
     for (int t0 = 0; t0 < Lw; t0 += 16) {
-      int kv = 0;
-      if (t0 + i < L) {
-        kv = word[t0 + i];
-        if (kv >= K) {
-          ++bad;
-          kv = 0;
-        }
+      int kv = kv_next;
+      kv_next = t0 + 16 + i < L ? (int)word[t0 + 16 + i] : 0;
+      if (t0 + i < L && kv >= K) {
+        ++bad;
+        kv = 0;
       }
 #define GST_FWD_STEP(R)                                        \
   if (t0 + R < Lw) {                                           \
@@ -166,23 +166,32 @@ __global__ __launch_bounds__(256) void leaf_kernel(const LeafLaunch a) {
     GST_DE(0) GST_DE(1) GST_DE(2) GST_DE(3) GST_DE(4) GST_DE(5) GST_DE(6) GST_DE(7)
     GST_DE(8) GST_DE(9) GST_DE(10) GST_DE(11) GST_DE(12) GST_DE(13) GST_DE(14) GST_DE(15)
 #undef GST_DE
-    double b = dot16_bcast(dp, reinterpret_cast<const double2*>(s.ETs + i * ROW));
-
     // ---- reverse sweep, one segment of C steps at a time ----
+    // (a segment's gate indices and checkpoint are loaded one segment ahead)
     const int nseg = (L + C - 1) / C;
     int nsegw = nseg;
     nsegw = max(nsegw, __shfl_xor(nsegw, 16));
     nsegw = max(nsegw, __shfl_xor(nsegw, 32));
+    int kv_nx = 0;
+    double ck_nx = 0.0;
+    if (nsegw >= 1 && nsegw - 1 < nseg) {
+      if (i < C && (nsegw - 1) * C + i < L) kv_nx = word[(nsegw - 1) * C + i];
+      ck_nx = ck[(nsegw - 1) * 16 + i];
+    }
+    double b = dot16_bcast(dp, reinterpret_cast<const double2*>(s.ETs + i * ROW));
     for (int c = nsegw - 1; c >= 0; --c) {
       const bool act = c < nseg;
       const int base = c * C;
-      int kv = 0;
-      if (act && i < C && base + i < L) {
-        kv = word[base + i];
-        if (kv >= K) kv = 0;  // counted in the forward sweep
-      }
+      int kv = kv_nx;
+      if (kv >= K) kv = 0;  // counted in the forward sweep
       double fs[C];
-      fs[0] = act ? ck[c * 16 + i] : 0.0;
+      fs[0] = act ? ck_nx : 0.0;
+      kv_nx = 0;
+      ck_nx = 0.0;
+      if (c >= 1 && c - 1 < nseg) {
+        if (i < C && (c - 1) * C + i < L) kv_nx = word[(c - 1) * C + i];
+        ck_nx = ck[(c - 1) * 16 + i];
+      }
 #define GST_REC(R)                                                   \
   {                                                                  \
     const int k = bcast_i32<R - 1>(kv);                              \

@@ -23,6 +23,41 @@ bool build_plan(const int64_t* off, const uint8_t* gates, int64_t S, int K, cons
   for (int64_t s = 0; s < S; ++s) P.max_len = std::max(P.max_len, off[s + 1] - off[s]);
   if (S == 0 || P.sum_len == 0) return false;
 
+  // ---- 0. early rejection: distinct prefixes depth by depth ----
+  // Once every word still running at depth t has its own prefix, no two words
+  // share a node deeper than t, and the node count of the whole trie follows
+  // from the length histogram.  Random words reach that point within a few
+  // levels; structured lists (shared germ powers) do not and skip the test.
+  {
+    std::vector<int64_t> n_ge((size_t)P.max_len + 2, 0);  // words with length >= t
+    for (int64_t s = 0; s < S; ++s) n_ge[off[s + 1] - off[s]] += 1;
+    for (int64_t t = P.max_len - 1; t >= 0; --t) n_ge[t] += n_ge[t + 1];
+    std::vector<int32_t> cur((size_t)S, 0);
+    std::vector<int32_t> kid((size_t)K, -1);
+    int64_t nodes = 1;
+    const int64_t t_max = std::min<int64_t>(P.max_len, 64);
+    for (int64_t t = 1; t <= t_max; ++t) {
+      int64_t created = 0;
+      for (int64_t s = 0; s < S; ++s) {
+        if (off[s + 1] - off[s] < t) continue;
+        const size_t at = (size_t)cur[s] * K + gates[off[s] + t - 1];
+        if (kid[at] < 0) {
+          kid[at] = (int32_t)nodes++;
+          kid.resize((size_t)nodes * K, -1);
+          ++created;
+        }
+        cur[s] = kid[at];
+      }
+      if (nodes >= opt.max_nodes) return false;
+      if (created == n_ge[t]) {
+        int64_t total = nodes;
+        for (int64_t u = t + 1; u <= P.max_len; ++u) total += n_ge[u];
+        if ((double)(total - 1) > opt.max_share_ratio * (double)P.sum_len) return false;
+        break;
+      }
+    }
+  }
+
   // ---- 1. trie over the words in time order ----
   std::vector<int32_t> parent{-1};
   std::vector<uint8_t> gate{0};

@@ -462,6 +462,26 @@ def c3_plan(n_sets: int = 512, seed: Optional[int] = None):
     return [(str(k), int(s), int(sd)) for k, s, sd in zip(kinds, S, seeds)]
 
 
+def uneven_request(kind: str, S: int, seed: int, lmax: int = 1024, emulate: bool = False) -> Workload:
+    """One gate set of the uneven batch: random words with lengths ``U{1..lmax}``.
+
+    With ``emulate`` the counts are drawn from the emulated device (the
+    state-vector black box, slow at full size); otherwise from the uniform
+    distribution over outcomes, which leaves the cost of an evaluation
+    unchanged (only zero counts are skipped, and they are as rare)."""
+    ss = np.random.SeedSequence(seed)
+    r_rot, r_seq, r_cnt, r_pert = [np.random.default_rng(x) for x in ss.spawn(4)]
+    truth = noisy_gateset(kind, LAMBDA, SIGMA, r_rot)
+    model = noisy_gateset(kind, LAMBDA, SIGMA, r_pert)
+    sl = random_list(S, truth.K, 1, lmax, r_seq)
+    if emulate:
+        p = _device_probs_words(truth, sl, np.arange(S))
+    else:
+        p = np.full((S, truth.M), 1.0 / truth.M)
+    counts = sample_counts(p, N_SHOTS, r_cnt)
+    return Workload(f"uneven-{kind}-S{S}-seed{seed}", truth, model, sl, counts)
+
+
 def pack_params(gs: GateSet) -> np.ndarray:
     """Full parameter vector in gradient layout ``[rho (D) | E (M*D) | G (K*D*D)]``."""
     return np.concatenate([gs.rho.ravel(), gs.effects.ravel(), gs.gates.ravel()])

@@ -281,3 +281,21 @@ def test_trunk_segments_rebuild_words(planlib, name):
         nseg += P["seg_ptr"][t + 1] - P["seg_ptr"][t]
     # germ powers compress: far fewer segments than steps
     assert nseg * 4 < len(P["trunk_gates"])
+
+
+def test_random_words_rejected_early(planlib):
+    """Random words share only their first few levels: the plan is refused by
+    the depth-by-depth prefix count, without building the whole trie (a
+    10M-step list must be refused in well under a second)."""
+    import time
+    rng = np.random.default_rng(7)
+    sl = W.random_list(20000, 6, 1, 1024, rng)
+    t0 = time.perf_counter()
+    P = get_plan(planlib, sl, 6)
+    dt = time.perf_counter() - t0
+    assert not P["used"]
+    assert dt < 1.0, dt
+    # a list whose words repeat is still planned (identical words share everything)
+    words = [list(rng.integers(0, 6, size=200)) for _ in range(5)] * 40
+    P = get_plan(planlib, W.from_words(words), 6)
+    assert P["used"] and P["n_nodes"] <= 1 + 5 * 200 and P["sum_len"] == 200 * 200
