@@ -90,10 +90,12 @@ struct Profiler {
 };
 
 enum Family { FAM_LEAF = 0, FAM_REDUCE = 1, FAM_TRUNK_FWD = 2, FAM_TRUNK_BWD = 3, FAM_INJECT = 4, FAM_GEMM = 5,
-              FAM_BATCH = 6, FAM_TILES16 = 7, FAM_TILES4 = 8, FAM_TILES_RED = 9, FAM_N = 10 };
+              FAM_BATCH = 6, FAM_TILES16 = 7, FAM_TILES4 = 8, FAM_TILES_RED = 9, FAM_CHAIN64 = 10,
+              FAM_GEMM64 = 11, FAM_REDUCE64 = 12, FAM_N = 13 };
 static_assert(FAM_N <= Profiler::kMaxFamilies, "profiler arrays too small");
 static const char* kFamilyNames[FAM_N] = {"leaf",  "reduce",  "trunk_fwd", "trunk_bwd",   "inject",
-                                          "grad_gemm", "batch", "tiles_2q",  "tiles_1q", "tiles_reduce"};
+                                          "grad_gemm", "batch", "tiles_2q",  "tiles_1q", "tiles_reduce",
+                                          "chain_3q",  "gemm_3q", "reduce_3q"};
 
 // Carve consecutive aligned regions out of one allocation.
 struct Carver {
@@ -200,6 +202,16 @@ struct gst_req {
   double* tile_slab = nullptr;          // [n_tiles][P]
   gst::BatchTile* tiles = nullptr;      // device tile list of the request alone (longest first)
   unsigned* queue = nullptr;            // device: work-queue counter [64] + nonpos counter
+  int64_t n_steps = 0;
+  // three-qubit requests (D = 64)
+  int64_t tile_seqs64 = 0, n_tiles64 = 0, n_chunks64 = 0;
+  int64_t* pos64 = nullptr;             // step positions grouped by gate
+  int64_t* chunk_beg64 = nullptr;
+  int64_t* chunk_end64 = nullptr;
+  int64_t* gate_chunk_ptr64 = nullptr;  // [K + 1]
+  double* tile_slab64 = nullptr;        // [n_tiles64][1 + 64 + 64 M]
+  double* chunk_slab64 = nullptr;       // [n_chunks64][4096]
+  size_t eval_ws_bytes = 0;             // context workspace one evaluation with gradient needs
   DevicePlan plan;
   DevBuf ws;
   size_t resident_bytes = 0;
@@ -236,7 +248,8 @@ int check_gateset(const gst_gateset* gs, int* D) {
   if (!d) return fail(GST_EINVAL, "n_qubits must be 1, 2 or 3");
   if (gs->n_gates < 1 || gs->n_gates > gst_max_gates(gs->n_qubits))
     return fail(GST_EINVAL, "n_gates out of range for this qubit count (see gst_max_gates)");
-  if (gs->n_outcomes < 1 || gs->n_outcomes > d) return fail(GST_EINVAL, "n_outcomes must be in 1..D");
+  if (gs->n_outcomes < 1 || gs->n_outcomes > std::min(d, 16))
+    return fail(GST_EINVAL, "n_outcomes must be in 1..min(D, 16)");
   if (!gs->rho || !gs->effects || !gs->gates) return fail(GST_EINVAL, "gateset pointer is NULL");
   *D = d;
   return GST_OK;
@@ -301,6 +314,9 @@ int run_leaf(gst_ctx* ctx, DevBuf& ws, const gst::LeafLaunch& base, int64_t max_
   return GST_OK;
 }
 
+int plain_eval64(gst_ctx* ctx, const gst_gateset* gs, const gst_seqlist* sl, int mode, const int32_t* counts,
+                 const double* w, double* probs, double* objective, double* grad);
+
 int plain_eval(gst_ctx* ctx, const gst_gateset* gs, const gst_seqlist* sl, int mode, const int32_t* counts,
                const double* w, double* probs, double* objective, double* grad) {
   if (!ctx) return fail(GST_EINVAL, "ctx is NULL");
@@ -309,8 +325,8 @@ int plain_eval(gst_ctx* ctx, const gst_gateset* gs, const gst_seqlist* sl, int m
   if (rc) return rc;
   rc = check_seqs(sl);
   if (rc) return rc;
-  if (D == 64) return fail(GST_EINVAL, "three-qubit gate sets are not supported by this build");
   HIP_TRY(hipSetDevice(ctx->device));
+  if (D == 64) return plain_eval64(ctx, gs, sl, mode, counts, w, probs, objective, grad);
   int64_t max_len = 0;
   rc = resolve_max_len(sl, ctx->stream, &max_len);
   if (rc) return rc;
@@ -666,7 +682,7 @@ int gst_req_create_host(gst_ctx* ctx, int n_qubits, int n_gates, int n_outcomes,
   const int D = dim_of(n_qubits);
   if (!D) return fail(GST_EINVAL, "n_qubits must be 1, 2 or 3");
   if (n_gates < 1 || n_gates > gst_max_gates(n_qubits)) return fail(GST_EINVAL, "n_gates out of range");
-  if (n_outcomes < 1 || n_outcomes > D) return fail(GST_EINVAL, "n_outcomes must be in 1..D");
+  if (n_outcomes < 1 || n_outcomes > std::min(D, 16)) return fail(GST_EINVAL, "n_outcomes must be in 1..min(D, 16)");
   int rc = check_seqs(sl);
   if (rc) return rc;
   const int64_t S = sl->n_seq;
@@ -699,25 +715,57 @@ int gst_req_create_host(gst_ctx* ctx, int n_qubits, int n_gates, int n_outcomes,
   std::stable_sort(order.begin(), order.end(), [&](int64_t x, int64_t y) {
     return sl->offsets[x + 1] - sl->offsets[x] > sl->offsets[y + 1] - sl->offsets[y];
   });
-  const int64_t tile_seqs = tile_seqs_for(S);
-  for (int64_t q0 = 0; q0 < S; q0 += tile_seqs) {
+  // tiles of the one- and two-qubit tile kernel (three-qubit requests use
+  // their own tiles below)
+  const int64_t tile_seqs = D == 64 ? std::max<int64_t>(S, 1) : tile_seqs_for(S);
+  for (int64_t q0 = 0; q0 < S && D <= 16; q0 += tile_seqs) {
     r->tile_q.push_back(q0);
     int64_t cost = 0;
     for (int64_t q = q0; q < std::min(S, q0 + tile_seqs); ++q) cost += sl->offsets[order[q] + 1] - sl->offsets[order[q]];
     r->tile_cost.push_back(cost);
   }
-  if (S > 0) r->tile_q.push_back(S);
+  if (S > 0 && D <= 16) r->tile_q.push_back(S);
   std::vector<gst::BatchTile> tiles((size_t)r->n_tiles());
   for (int64_t t = 0; t < r->n_tiles(); ++t) tiles[t] = gst::BatchTile{0, (int32_t)t, r->tile_q[t], r->tile_q[t + 1]};
   std::stable_sort(tiles.begin(), tiles.end(), [&](const gst::BatchTile& x, const gst::BatchTile& y) {
     return r->tile_cost[x.local] > r->tile_cost[y.local];
   });
   const int64_t Pw = gst::slab_width(D, n_outcomes, n_gates);
+  // three-qubit requests: tiles of 16 sequences for the chain kernel, and the
+  // step positions of each gate (ascending) cut into chunks for the
+  // gate-gradient kernel
+  std::vector<int64_t> pos64, cbeg64, cend64, gcp64;
+  if (D == 64) {
+    r->tile_seqs64 = 16;
+    r->n_tiles64 = (S + 15) / 16;
+    std::vector<int64_t> gp((size_t)n_gates + 1, 0);
+    for (int64_t t = 0; t < n_steps; ++t) gp[sl->gate_idx[t] + 1] += 1;
+    for (int k = 0; k < n_gates; ++k) gp[k + 1] += gp[k];
+    pos64.resize((size_t)n_steps);
+    std::vector<int64_t> fill(gp.begin(), gp.end() - 1);
+    for (int64_t t = 0; t < n_steps; ++t) pos64[fill[sl->gate_idx[t]]++] = t;
+    gcp64.assign((size_t)n_gates + 1, 0);
+    for (int k = 0; k < n_gates; ++k) {
+      gcp64[k] = (int64_t)cbeg64.size();
+      for (int64_t b = gp[k]; b < gp[k + 1]; b += gst::GEMM64_CHUNK) {
+        cbeg64.push_back(b);
+        cend64.push_back(std::min(b + gst::GEMM64_CHUNK, gp[k + 1]));
+      }
+    }
+    gcp64[n_gates] = (int64_t)cbeg64.size();
+    r->n_chunks64 = (int64_t)cbeg64.size();
+    r->eval_ws_bytes = (size_t)n_steps * 64 * 8 * 2 + 256;
+  }
+  const int64_t Pc64 = 1 + 64 + (int64_t)n_outcomes * 64;
   Carver cv;
   const size_t o_off = cv.take<int64_t>(S + 1), o_g = cv.take<uint8_t>(std::max<int64_t>(n_steps, 1)),
                o_c = cv.take<int32_t>(counts_host ? S * n_outcomes : 1), o_ord = cv.take<int64_t>(S + 1),
                o_sl = cv.take<double>((size_t)std::max<int64_t>(r->n_tiles(), 1) * Pw),
-               o_t = cv.take<gst::BatchTile>(tiles.size() + 1), o_q = cv.take<unsigned>(64 + 2);
+               o_t = cv.take<gst::BatchTile>(tiles.size() + 1), o_q = cv.take<unsigned>(64 + 2),
+               o_p64 = cv.take<int64_t>(pos64.size() + 1), o_cb64 = cv.take<int64_t>(cbeg64.size() + 1),
+               o_ce64 = cv.take<int64_t>(cend64.size() + 1), o_gc64 = cv.take<int64_t>(gcp64.size() + 1),
+               o_ts64 = cv.take<double>((size_t)std::max<int64_t>(r->n_tiles64, 1) * (D == 64 ? Pc64 : 1)),
+               o_cs64 = cv.take<double>((size_t)std::max<int64_t>(r->n_chunks64, 1) * (D == 64 ? 4096 : 1));
   rc = r->data.reserve(cv.off + 256, ctx->stream);
   if (rc) return rc;
   char* base = reinterpret_cast<char*>(r->data.p);
@@ -728,6 +776,21 @@ int gst_req_create_host(gst_ctx* ctx, int n_qubits, int n_gates, int n_outcomes,
   r->tile_slab = reinterpret_cast<double*>(base + o_sl);
   r->tiles = reinterpret_cast<gst::BatchTile*>(base + o_t);
   r->queue = reinterpret_cast<unsigned*>(base + o_q);
+  r->n_steps = n_steps;
+  if (D == 64) {
+    r->pos64 = reinterpret_cast<int64_t*>(base + o_p64);
+    r->chunk_beg64 = reinterpret_cast<int64_t*>(base + o_cb64);
+    r->chunk_end64 = reinterpret_cast<int64_t*>(base + o_ce64);
+    r->gate_chunk_ptr64 = reinterpret_cast<int64_t*>(base + o_gc64);
+    r->tile_slab64 = reinterpret_cast<double*>(base + o_ts64);
+    r->chunk_slab64 = reinterpret_cast<double*>(base + o_cs64);
+    if (!pos64.empty()) HIP_TRY(hipMemcpy(r->pos64, pos64.data(), pos64.size() * 8, hipMemcpyHostToDevice));
+    if (!cbeg64.empty()) {
+      HIP_TRY(hipMemcpy(r->chunk_beg64, cbeg64.data(), cbeg64.size() * 8, hipMemcpyHostToDevice));
+      HIP_TRY(hipMemcpy(r->chunk_end64, cend64.data(), cend64.size() * 8, hipMemcpyHostToDevice));
+    }
+    HIP_TRY(hipMemcpy(r->gate_chunk_ptr64, gcp64.data(), gcp64.size() * 8, hipMemcpyHostToDevice));
+  }
   if (!tiles.empty())
     HIP_TRY(hipMemcpy(r->tiles, tiles.data(), tiles.size() * sizeof(gst::BatchTile), hipMemcpyHostToDevice));
   std::vector<int64_t> zero_off(1, 0);
@@ -744,13 +807,14 @@ int gst_req_create_host(gst_ctx* ctx, int n_qubits, int n_gates, int n_outcomes,
     }
   }
   r->resident_bytes = r->data.bytes + r->plan.buf.bytes;
+  (void)o_off;
   *out = r.release();
   return GST_OK;
 }
 
 int gst_req_footprint(const gst_req* req, size_t* bytes) {
   if (!req || !bytes) return fail(GST_EINVAL, "NULL argument");
-  *bytes = req->resident_bytes + req->ws.bytes;
+  *bytes = req->resident_bytes + std::max(req->ws.bytes, req->eval_ws_bytes);
   return GST_OK;
 }
 
@@ -828,6 +892,79 @@ static int run_tiles(gst_req* r, const gst_gateset* th, int mode, const double* 
   return GST_OK;
 }
 
+// A three-qubit request: chain kernel over its tiles, gate-gradient kernel
+// over the recorded steps, ordered reduction.  `nonpos` (optional) receives
+// the count of p <= 0 with N > 0 of this evaluation.
+static int run64(gst_req* r, const gst_gateset* th, int mode, const double* w, double* probs, double* objective,
+                 double* grad, unsigned long long* nonpos = nullptr) {
+  gst_ctx* ctx = r->ctx;
+  const bool want_grad = grad != nullptr;
+  unsigned long long* np = nonpos ? nonpos : reinterpret_cast<unsigned long long*>(r->queue + 64);
+  if (want_grad) {
+    // per-step records in the context workspace (calls on a context are stream ordered)
+    int rc = ctx->ws.reserve(r->eval_ws_bytes, ctx->stream);
+    if (rc) return rc;
+  }
+  double* rec_b = want_grad ? reinterpret_cast<double*>(ctx->ws.p) : nullptr;
+  double* rec_f = want_grad ? rec_b + (size_t)r->n_steps * 64 : nullptr;
+  HIP_TRY(gst::launch_queue_reset(r->queue, np, 1, ctx->stream));
+  gst::Chain64Launch a{};
+  a.M = r->M;
+  a.K = r->K;
+  a.rho = th->rho;
+  a.E = th->effects;
+  a.G = th->gates;
+  a.off = r->offsets;
+  a.gates = r->gates;
+  a.order = r->order;
+  a.counts = r->counts;
+  a.W = w;
+  a.probs = probs;
+  a.mode = mode;
+  a.want_grad = want_grad ? 1 : 0;
+  a.S = r->S;
+  a.tile_seqs = (int)r->tile_seqs64;
+  a.n_tiles = r->n_tiles64;
+  a.queue = r->queue;
+  a.rec_b = rec_b;
+  a.rec_f = rec_f;
+  a.slab = r->tile_slab64;
+  a.status = ctx->status;
+  a.nonpos = np;
+  const int grid = (int)std::min<int64_t>(r->n_tiles64, (int64_t)gst::chain64_blocks_per_cu(r->K) * ctx->n_cu);
+  if (grid > 0) {
+    ProfScope ps(ctx, FAM_CHAIN64);
+    HIP_TRY(gst::launch_chain64(a, grid, ctx->stream));
+  }
+  if (want_grad && r->n_chunks64 > 0) {
+    ProfScope ps(ctx, FAM_GEMM64);
+    gst::Gemm64Launch g{};
+    g.rec_b = rec_b;
+    g.rec_f = rec_f;
+    g.pos = r->pos64;
+    g.chunk_beg = r->chunk_beg64;
+    g.chunk_end = r->chunk_end64;
+    g.slab = r->chunk_slab64;
+    g.n_chunks = (int)r->n_chunks64;
+    HIP_TRY(gst::launch_gemm64(g, ctx->stream));
+  }
+  if (objective || grad) {
+    ProfScope ps(ctx, FAM_REDUCE64);
+    gst::Reduce64Launch red{};
+    red.M = r->M;
+    red.K = want_grad ? r->K : 0;  // without the gradient only the tile columns are added
+    red.tile_slab = r->tile_slab64;
+    red.n_tiles = r->n_tiles64;
+    red.chunk_slab = r->chunk_slab64;
+    red.gate_chunk_ptr = r->gate_chunk_ptr64;
+    red.objective = objective;
+    red.grad = grad;
+    red.nonpos = np;
+    HIP_TRY(gst::launch_reduce64(red, ctx->stream));
+  }
+  return GST_OK;
+}
+
 static int req_run(gst_req* r, const gst_gateset* th, int mode, const double* w, double* probs, double* objective,
                    double* grad) {
   if (!r) return fail(GST_EINVAL, "req is NULL");
@@ -839,6 +976,7 @@ static int req_run(gst_req* r, const gst_gateset* th, int mode, const double* w,
   if (mode == gst::MODE_LOGLIK && !r->counts) return fail(GST_EINVAL, "request has no counts");
   gst_ctx* ctx = r->ctx;
   HIP_TRY(hipSetDevice(ctx->device));
+  if (r->D == 64) return run64(r, th, mode, w, probs, objective, grad);
   if (r->plan.used) return run_plan(r, th, mode, w, probs, objective, grad);
   return run_tiles(r, th, mode, w, probs, objective, grad);
 }
@@ -909,7 +1047,7 @@ int gst_batch_create(gst_ctx* ctx, int n, gst_req* const* reqs, const gst_gatese
     b->probs.push_back(po);
     b->objectives.push_back(ob);
     b->grads.push_back(gr);
-    if (r->plan.used) {
+    if (r->plan.used || r->D == 64) {
       b->plan_reqs.push_back(x);
       rq.push_back(gst::BatchReq{});
       continue;
@@ -1034,8 +1172,10 @@ int gst_batch_run(gst_batch* b) {
   for (int x : b->plan_reqs) {
     gst_req* r = b->reqs[x];
     const int mode = b->objectives[x] ? gst::MODE_LOGLIK : gst::MODE_PROBS;
-    int rc = run_plan(r, &b->thetas[x], mode, nullptr, b->probs[x], b->objectives[x], b->grads[x],
-                      b->req_nonpos + x);
+    int rc = r->D == 64 ? run64(r, &b->thetas[x], mode, nullptr, b->probs[x], b->objectives[x], b->grads[x],
+                                b->req_nonpos + x)
+                        : run_plan(r, &b->thetas[x], mode, nullptr, b->probs[x], b->objectives[x], b->grads[x],
+                                   b->req_nonpos + x);
     if (rc) return rc;
   }
   return GST_OK;
@@ -1077,3 +1217,38 @@ int gst_req_destroy(gst_req* req) {
 }
 
 }  // extern "C"
+
+namespace {
+
+// Context-level calls with a three-qubit gate set: the list (and counts) are
+// read back to the host and evaluated as a temporary resident request, whose
+// per-gate step positions the gate-gradient kernel needs.
+int plain_eval64(gst_ctx* ctx, const gst_gateset* gs, const gst_seqlist* sl, int mode, const int32_t* counts,
+                 const double* w, double* probs, double* objective, double* grad) {
+  const int64_t S = sl->n_seq;
+  std::vector<int64_t> off((size_t)S + 1, 0);
+  if (S > 0) HIP_TRY(hipMemcpyAsync(off.data(), sl->offsets, off.size() * 8, hipMemcpyDeviceToHost, ctx->stream));
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  if (off[0] != 0) return fail(GST_EINVAL, "offsets[0] != 0");
+  for (int64_t s = 0; s < S; ++s)
+    if (off[s + 1] < off[s]) return fail(GST_EINVAL, "offsets decrease");
+  std::vector<uint8_t> g((size_t)std::max<int64_t>(off[S], 1));
+  if (off[S] > 0) HIP_TRY(hipMemcpyAsync(g.data(), sl->gate_idx, (size_t)off[S], hipMemcpyDeviceToHost, ctx->stream));
+  std::vector<int32_t> c;
+  if (mode == gst::MODE_LOGLIK) {
+    c.resize((size_t)std::max<int64_t>(S * gs->n_outcomes, 1));
+    if (S > 0)
+      HIP_TRY(hipMemcpyAsync(c.data(), counts, (size_t)S * gs->n_outcomes * 4, hipMemcpyDeviceToHost, ctx->stream));
+  }
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  gst_seqlist hs{S, off.data(), g.data(), -1};
+  gst_req* r = nullptr;
+  int rc = gst_req_create_host(ctx, gs->n_qubits, gs->n_gates, gs->n_outcomes, &hs,
+                               mode == gst::MODE_LOGLIK ? c.data() : nullptr, &r);
+  if (rc) return rc;
+  rc = req_run(r, gs, mode, w, probs, objective, grad);
+  gst_req_destroy(r);  // waits for the stream first
+  return rc;
+}
+
+}  // namespace

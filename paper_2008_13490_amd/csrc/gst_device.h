@@ -88,9 +88,9 @@ __device__ __forceinline__ Row16 load_row(const double* p) {
   return x;
 }
 
-// Same as dot16_bcast with the row already in registers.
-__device__ __forceinline__ double dot16(double x, const Row16& r) {
-  double acc = 0.0;
+// Continues a chain: acc = fma(r[15], x@15, ... fma(r[0], x@0, acc)), the
+// row already in registers.  dot16 starts from acc = 0.
+__device__ __forceinline__ double dot16_from(double acc, double x, const Row16& r) {
   asm volatile(
       "s_nop 1\n\t"
       "v_fmac_f64_dpp %0, %1, %2 row_newbcast:0 row_mask:0xf bank_mask:0xf\n\t"
@@ -115,6 +115,9 @@ __device__ __forceinline__ double dot16(double x, const Row16& r) {
         "v"(r.a7.y));
   return acc;
 }
+
+// Same as dot16_bcast with the row already in registers.
+__device__ __forceinline__ double dot16(double x, const Row16& r) { return dot16_from(0.0, x, r); }
 
 // Sum over j of r[j] * x@j as four interleaved partial chains (j mod 4),
 // combined as (s0 + s1) + (s2 + s3): a quarter of the dependent latency of

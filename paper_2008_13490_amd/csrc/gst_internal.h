@@ -36,7 +36,7 @@ struct LeafLaunch {
   unsigned long long* status;  // [0] bad gate indices, [1] p <= 0 with N > 0
 };
 
-__host__ __device__ // Kernels of the shared-prefix plan.  Row conventions:
+// Kernels of the shared-prefix plan.  Row conventions:
 //   state arena FA: row 0 = rho, row 1 + j = state after trunk step j,
 //                   row 1 + nTS + x = state before item step x;
 //   adjoint arena BA: row j = adjoint after trunk step j,
@@ -162,6 +162,57 @@ int batch_blocks_per_cu(int D, int kmax);
 hipError_t launch_batch(const BatchLaunch& a, int n_blocks, hipStream_t stream);
 hipError_t launch_queue_reset(unsigned* q, unsigned long long* req_nonpos, int n_req, hipStream_t stream);
 hipError_t launch_batch_reduce(const BatchReduce& a, int n_items, hipStream_t stream);
+
+// Three-qubit gate sets (D = 64): one chain per wave, the gate set in LDS,
+// per-step records for the gate gradient (see gst_kernels64.hip).
+constexpr int CHAIN64_WAVES = 8;        // waves per workgroup of the chain kernel
+constexpr int64_t GEMM64_CHUNK = 8192;  // positions per chunk of the gate-gradient kernel
+struct Chain64Launch {
+  int M, K;
+  const double* rho;        // [64]
+  const double* E;          // [M][64]
+  const double* G;          // [K][64][64]
+  const int64_t* off;       // [S+1]
+  const uint8_t* gates;     // [sum L]
+  const int64_t* order;     // sequences by length, descending
+  const int32_t* counts;    // [S][M] (MODE_LOGLIK)
+  const double* W;          // [S][M] (MODE_VJP)
+  double* probs;            // [S][M] or null
+  int mode, want_grad;
+  int64_t S;
+  int tile_seqs;            // sequences per tile (consecutive in `order`)
+  int64_t n_tiles;
+  unsigned* queue;          // tile counter, zero before the launch
+  double* rec_b;            // [sum L][64]: adjoint after each step (want_grad)
+  double* rec_f;            // [sum L][64]: state before each step (want_grad)
+  double* slab;             // [n_tiles][1 + 64 + 64 M]
+  unsigned long long* status;
+  unsigned long long* nonpos;
+};
+struct Gemm64Launch {
+  const double* rec_b;
+  const double* rec_f;
+  const int64_t* pos;        // step positions grouped by gate, ascending within a gate
+  const int64_t* chunk_beg;  // [n_chunks] ranges in pos (one gate each)
+  const int64_t* chunk_end;
+  double* slab;              // [n_chunks][4096]
+  int n_chunks;
+};
+struct Reduce64Launch {
+  int M, K;
+  const double* tile_slab;         // [n_tiles][1 + 64 + 64 M]
+  int64_t n_tiles;
+  const double* chunk_slab;        // [n_chunks][4096]
+  const int64_t* gate_chunk_ptr;   // [K + 1] chunk range of each gate
+  double* objective;
+  double* grad;
+  const unsigned long long* nonpos;
+};
+size_t chain64_lds(int K);
+int chain64_blocks_per_cu(int K);
+hipError_t launch_chain64(const Chain64Launch& a, int n_blocks, hipStream_t stream);
+hipError_t launch_gemm64(const Gemm64Launch& a, hipStream_t stream);
+hipError_t launch_reduce64(const Reduce64Launch& a, hipStream_t stream);
 
 hipError_t launch_trunk_fwd(const PlanArgs& a, hipStream_t stream);
 hipError_t launch_trunk_bwd(const PlanArgs& a, hipStream_t stream);

@@ -1,0 +1,328 @@
+// Kernels for three-qubit gate sets (D = 64).
+//
+// Thesis Sec. 6.3.1: p[s][m] = e_m^T G[s_L] ... G[s_1] rho, the multinomial
+// log-likelihood of the counts and its gradient.
+//
+// Layout on the chip
+//   * One chain per wave: lane i holds component i of the state.  A step is
+//     the 64 fused multiply-adds acc = fma(G[k][i][j], f[j], acc), j
+//     ascending from acc = 0 (the order of the plain definition, so states
+//     and probabilities are bit-identical to a sequential loop).  f[j] is
+//     broadcast inside its 16-lane row by DPP row_newbcast; the four rows
+//     reach every lane through four row copies (ds_bpermute).
+//   * The whole gate set sits in LDS (K <= 5 gates of 32 KB).  Inside a gate
+//     the column pairs of row i are XOR-permuted by i mod 32, so the row
+//     reads of the forward product (lane i reads row i) and the column reads
+//     of the adjoint product (lane j reads column j) are both free of bank
+//     conflicts.
+//   * With the LDS full, the gradient of the gates is not accumulated on
+//     chip: the chain kernel writes, for every step of every sequence, the
+//     state before the step and the adjoint after it (one 512-byte row each,
+//     at the step's position in the sequence list), and a second kernel adds
+//     dG_k = sum b f^T over the positions of gate k with FP64 MFMA 16x16x4
+//     tiles, in fixed chunks.  A third kernel adds the per-tile and per-chunk
+//     partial sums in a fixed order.
+//   * Work is cut into tiles of consecutive sequences of the length-sorted
+//     order; each wave takes tiles from an atomic counter and writes one row
+//     of partial sums per tile, so results do not depend on scheduling.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "gst_device.h"
+#include "gst_internal.h"
+
+namespace gst {
+namespace {
+
+constexpr int N64 = 64;
+constexpr int GATE64 = N64 * N64;  // doubles per gate in LDS
+
+// Position (in doubles) of G[i][j] inside a gate: column pairs XOR-permuted
+// by the row.
+__device__ __forceinline__ int swz(int i, int j) { return i * N64 + ((((j >> 1) ^ (i & 31)) << 1) | (j & 1)); }
+
+// x of lane 16 r + (l & 15), in every lane l.
+__device__ __forceinline__ double row_copy(double x, int r, int lane) { return __shfl(x, 16 * r + (lane & 15)); }
+
+// Row i of gate Gk dotted with x, columns ascending from 0 (bit-exact chain).
+__device__ __forceinline__ double mv_row(const double* Gk, int i, double x) {
+  const double* row = Gk + i * N64;
+  const int s = i & 31;
+  double acc = 0.0;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const double xr = row_copy(x, r, i);
+    Row16 R;
+    R.a0 = *reinterpret_cast<const double2*>(row + 2 * ((8 * r + 0) ^ s));
+    R.a1 = *reinterpret_cast<const double2*>(row + 2 * ((8 * r + 1) ^ s));
+    R.a2 = *reinterpret_cast<const double2*>(row + 2 * ((8 * r + 2) ^ s));
+    R.a3 = *reinterpret_cast<const double2*>(row + 2 * ((8 * r + 3) ^ s));
+    R.a4 = *reinterpret_cast<const double2*>(row + 2 * ((8 * r + 4) ^ s));
+    R.a5 = *reinterpret_cast<const double2*>(row + 2 * ((8 * r + 5) ^ s));
+    R.a6 = *reinterpret_cast<const double2*>(row + 2 * ((8 * r + 6) ^ s));
+    R.a7 = *reinterpret_cast<const double2*>(row + 2 * ((8 * r + 7) ^ s));
+    acc = dot16_from(acc, xr, R);
+  }
+  return acc;
+}
+
+// Column j of gate Gk dotted with x (the adjoint product G^T x): four
+// independent partial chains, one per row block, added in a fixed order.
+__device__ __forceinline__ double mv_col(const double* Gk, int j, double x) {
+  double part[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const double xr = row_copy(x, r, j);
+    Row16 R;
+    const int i0 = 16 * r;
+    R.a0 = double2{Gk[swz(i0 + 0, j)], Gk[swz(i0 + 1, j)]};
+    R.a1 = double2{Gk[swz(i0 + 2, j)], Gk[swz(i0 + 3, j)]};
+    R.a2 = double2{Gk[swz(i0 + 4, j)], Gk[swz(i0 + 5, j)]};
+    R.a3 = double2{Gk[swz(i0 + 6, j)], Gk[swz(i0 + 7, j)]};
+    R.a4 = double2{Gk[swz(i0 + 8, j)], Gk[swz(i0 + 9, j)]};
+    R.a5 = double2{Gk[swz(i0 + 10, j)], Gk[swz(i0 + 11, j)]};
+    R.a6 = double2{Gk[swz(i0 + 12, j)], Gk[swz(i0 + 13, j)]};
+    R.a7 = double2{Gk[swz(i0 + 14, j)], Gk[swz(i0 + 15, j)]};
+    part[r] = dot16(xr, R);
+  }
+  return (part[0] + part[1]) + (part[2] + part[3]);
+}
+
+// E row m (global memory) dotted with x, columns ascending from 0.
+__device__ __forceinline__ double mv_global_row(const double* __restrict__ row, int lane, double x) {
+  const auto* g = as_global(row);
+  double acc = 0.0;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const double xr = row_copy(x, r, lane);
+    const auto* q = g + 16 * r;
+    Row16 R;
+    R.a0 = double2{q[0], q[1]};
+    R.a1 = double2{q[2], q[3]};
+    R.a2 = double2{q[4], q[5]};
+    R.a3 = double2{q[6], q[7]};
+    R.a4 = double2{q[8], q[9]};
+    R.a5 = double2{q[10], q[11]};
+    R.a6 = double2{q[12], q[13]};
+    R.a7 = double2{q[14], q[15]};
+    acc = dot16_from(acc, xr, R);
+  }
+  return acc;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int sh = 1; sh < 64; sh <<= 1) v += __shfl_xor(v, sh);
+  return v;
+}
+
+__global__ __launch_bounds__(CHAIN64_WAVES * 64) void chain64_kernel(const Chain64Launch a) {
+  extern __shared__ double G_lds[];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int K = a.K, M = a.M;
+  for (int x = tid; x < K * GATE64; x += CHAIN64_WAVES * 64) {
+    const int k = x >> 12, i = (x >> 6) & 63, j = x & 63;
+    G_lds[k * GATE64 + swz(i, j)] = a.G[x];
+  }
+  __syncthreads();
+  const auto* g_off = as_global(a.off);
+  const auto* g_order = as_global(a.order);
+  const auto* g_gates = as_global(a.gates);
+  const auto* g_counts = as_global(a.counts);
+  const auto* g_W = as_global(a.W);
+  auto* g_probs = as_global(a.probs);
+  auto* g_rec_b = as_global(a.rec_b);
+  auto* g_rec_f = as_global(a.rec_f);
+  const bool grad = a.want_grad != 0;
+  const double rho_i = a.rho[lane];
+  const int mrow = lane < M ? lane : M - 1;       // lanes >= M compute a discarded readout
+  const double* Erow = a.E + (size_t)mrow * N64;
+  unsigned bad = 0, nonpos = 0;
+  for (;;) {
+    int tile = 0;
+    if (lane == 0) tile = (int)atomicAdd(a.queue, 1u);
+    tile = __builtin_amdgcn_readfirstlane(tile);
+    if (tile >= a.n_tiles) break;
+    double obj = 0.0, drho = 0.0;
+    double dE[16];
+#pragma unroll
+    for (int m = 0; m < 16; ++m) dE[m] = 0.0;
+    const int64_t q0 = (int64_t)tile * a.tile_seqs;
+    const int64_t q1 = q0 + a.tile_seqs < a.S ? q0 + a.tile_seqs : a.S;
+    for (int64_t q = q0; q < q1; ++q) {
+      const int64_t seq = g_order[q];
+      const int64_t beg = g_off[seq];
+      const int L = (int)(g_off[seq + 1] - beg);
+      double f = rho_i;
+      // ---- forward: gate indices of 64 steps per load, broadcast by readlane ----
+      for (int t0 = 0; t0 < L; t0 += 64) {
+        const int n = L - t0 < 64 ? L - t0 : 64;
+        const int kv = lane < n ? (int)g_gates[beg + t0 + lane] : 0;
+        for (int x = 0; x < n; ++x) {
+          int k = __builtin_amdgcn_readlane(kv, x);
+          if (k >= K) {
+            bad += lane == 0;
+            k = 0;
+          }
+          if (grad) g_rec_f[(beg + t0 + x) * N64 + lane] = f;
+          f = mv_row(G_lds + k * GATE64, lane, f);
+        }
+      }
+      // ---- readout: lane m < M holds p_m ----
+      const double p = mv_global_row(Erow, lane, f);
+      double dp = 0.0;
+      if (lane < M) {
+        const int64_t o = seq * M + lane;
+        if (a.probs) g_probs[o] = p;
+        if (a.mode == MODE_LOGLIK) {
+          const int32_t N = g_counts[o];
+          if (N > 0) {
+            if (p <= 0.0) {
+              ++nonpos;
+              obj = INFINITY;  // -N log p with p <= 0; no term is ever -inf
+            } else {
+              obj -= (double)N * log(p);
+              dp = -(double)N / p;
+            }
+          }
+        } else if (a.mode == MODE_VJP) {
+          dp = g_W[o];
+        }
+      }
+      if (!grad) continue;
+      // ---- effect gradient dE[m][j] += dp_m f_j and seed b_j = sum_m E[m][j] dp_m ----
+      double b = 0.0;
+#pragma unroll
+      for (int m = 0; m < 16; ++m) {
+        if (m < M) {
+          const double dpm = __shfl(dp, m);
+          dE[m] = fma(dpm, f, dE[m]);
+          b = fma(a.E[(size_t)m * N64 + lane], dpm, b);
+        }
+      }
+      // ---- reverse sweep: record (b after step, state before step) ----
+      for (int c0 = ((L - 1) / 64) * 64; c0 >= 0 && L > 0; c0 -= 64) {
+        const int n = L - c0 < 64 ? L - c0 : 64;
+        int kv = lane < n ? (int)g_gates[beg + c0 + lane] : 0;
+        if (kv >= K) kv = 0;  // counted in the forward sweep
+        for (int x = n - 1; x >= 0; --x) {
+          const int k = __builtin_amdgcn_readlane(kv, x);
+          g_rec_b[(beg + c0 + x) * N64 + lane] = b;
+          b = mv_col(G_lds + k * GATE64, lane, b);
+        }
+      }
+      drho += b;
+    }
+    // ---- this tile's partial sums ----
+    const int64_t Pc = 1 + N64 + (int64_t)M * N64;
+    double* out = a.slab + (int64_t)tile * Pc;
+    const double o = wave_sum(obj);
+    if (lane == 0) out[0] = o;
+    out[1 + lane] = drho;
+#pragma unroll
+    for (int m = 0; m < 16; ++m)
+      if (m < M) out[1 + N64 + m * N64 + lane] = dE[m];
+  }
+  if (lane == 0 && bad) atomicAdd(a.status + 0, (unsigned long long)bad);
+  const unsigned np = (unsigned)wave_sum((double)nonpos);
+  if (lane == 0 && np) {
+    atomicAdd(a.status + 1, (unsigned long long)np);
+    atomicAdd(a.nonpos, (unsigned long long)np);
+  }
+}
+
+// dG_k partial over one chunk of positions of gate k: wave w owns rows
+// 16w .. 16w+15 (four 16x16 tiles); four positions per MFMA, in order.
+__global__ __launch_bounds__(256) void gemm64_kernel(const Gemm64Launch a) {
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int z = lane >> 4, ii = lane & 15;
+  const int c = blockIdx.x;
+  const int64_t r0 = a.chunk_beg[c], r1 = a.chunk_end[c];
+  const auto* g_pos = as_global(a.pos);
+  const auto* g_b = as_global(a.rec_b);
+  const auto* g_f = as_global(a.rec_f);
+  d4 acc[4];
+#pragma unroll
+  for (int tc = 0; tc < 4; ++tc) acc[tc] = d4{0.0, 0.0, 0.0, 0.0};
+  for (int64_t r = r0; r < r1; r += 4) {
+    const bool v = r + z < r1;
+    const int64_t p = g_pos[v ? r + z : r0];
+    const double av = v ? g_b[p * N64 + 16 * w + ii] : 0.0;
+    double bv[4];
+#pragma unroll
+    for (int tc = 0; tc < 4; ++tc) bv[tc] = v ? g_f[p * N64 + 16 * tc + ii] : 0.0;
+#pragma unroll
+    for (int tc = 0; tc < 4; ++tc) acc[tc] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv[tc], acc[tc], 0, 0, 0);
+  }
+  // tile element C[r][cc] sits in lane 16*(r&3)+cc, register r>>2
+  double* out = a.slab + (int64_t)c * GATE64;
+#pragma unroll
+  for (int tc = 0; tc < 4; ++tc)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = 4 * v + (lane >> 4), cc = lane & 15;
+      out[(16 * w + r) * N64 + 16 * tc + cc] = acc[tc][v];
+    }
+}
+
+// Output column x of [objective | rho | E | G]: the tile partials (x < Pc)
+// or the chunk partials of gate (x - Pc) / 4096, added in order with four
+// interleaved partial sums.
+__global__ __launch_bounds__(256) void reduce64_kernel(const Reduce64Launch a) {
+  __shared__ double red[4][64];
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  const int64_t Pc = 1 + N64 + (int64_t)a.M * N64;
+  const int64_t P = Pc + (int64_t)a.K * GATE64;
+  const int64_t x = (int64_t)blockIdx.x * 64 + tx;
+  double v = 0.0;
+  if (x < Pc) {
+    for (int64_t t = ty; t < a.n_tiles; t += 4) v += a.tile_slab[t * Pc + x];
+  } else if (x < P) {
+    const int64_t y = x - Pc;
+    const int k = (int)(y / GATE64);
+    const int64_t e = y % GATE64;
+    for (int64_t c = a.gate_chunk_ptr[k] + ty; c < a.gate_chunk_ptr[k + 1]; c += 4) v += a.chunk_slab[c * GATE64 + e];
+  }
+  red[ty][tx] = v;
+  __syncthreads();
+  if (ty != 0 || x >= P) return;
+  v = (red[0][tx] + red[1][tx]) + (red[2][tx] + red[3][tx]);
+  const bool nonpos = a.nonpos && *a.nonpos != 0;
+  if (x == 0) {
+    if (a.objective) *a.objective = nonpos ? INFINITY : v;
+  } else if (a.grad && !nonpos) {
+    a.grad[x - 1] = v;
+  }
+}
+
+}  // namespace
+
+size_t chain64_lds(int K) { return (size_t)K * GATE64 * sizeof(double); }
+
+int chain64_blocks_per_cu(int K) {
+  int n = 0;
+  const hipError_t e =
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, chain64_kernel, CHAIN64_WAVES * 64, chain64_lds(K));
+  return (e == hipSuccess && n > 0) ? n : 1;
+}
+
+hipError_t launch_chain64(const Chain64Launch& a, int n_blocks, hipStream_t stream) {
+  if (a.K < 1 || a.K > 5 || a.M < 1 || a.M > 16) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(chain64_kernel, dim3(n_blocks), dim3(CHAIN64_WAVES * 64), chain64_lds(a.K), stream, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_gemm64(const Gemm64Launch& a, hipStream_t stream) {
+  if (a.n_chunks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(gemm64_kernel, dim3(a.n_chunks), dim3(256), 0, stream, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce64(const Reduce64Launch& a, hipStream_t stream) {
+  const int64_t P = 1 + N64 + (int64_t)a.M * N64 + (int64_t)a.K * GATE64;
+  hipLaunchKernelGGL(reduce64_kernel, dim3((unsigned)((P + 63) / 64)), dim3(256), 0, stream, a);
+  return hipGetLastError();
+}
+
+}  // namespace gst

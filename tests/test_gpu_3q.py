@@ -1,0 +1,178 @@
+"""GPU parity of the three-qubit path (D = 64) against the oracle.
+
+Probabilities must be bit-identical to the oracle's (same fused multiply-add
+order); objective 1e-10 relative, gradient 1e-10 normwise.  At the full size
+of the structured three-qubit list the oracle checks sampled probabilities
+one sequence at a time, and the gradient is checked through the Euler
+identities of the multilinear likelihood (exact at any size).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2008_13490_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2008_13490_amd import api
+    return api, api.Context(0)
+
+
+def _dev(api, gs):
+    return api.DeviceGateSet.from_numpy(gs.n_qubits, gs.rho, gs.effects, gs.gates)
+
+
+def _check(oracle_lib, gs, sl, counts, obj, p, g, label):
+    F, p_or, g_or, _, rc = oracle_lib.loglik(gs.rho, gs.effects, gs.gates, sl.offsets, sl.gates, counts)
+    assert rc == 0
+    p = p.cpu().numpy()
+    mism = np.count_nonzero(p != p_or)
+    assert mism == 0, f"{label}: {mism} probabilities differ, max {np.abs(p - p_or).max()}"
+    Fg = float(obj.cpu()[0])
+    assert abs(Fg - F) <= 1e-10 * abs(F), (label, Fg, F)
+    g = g.cpu().numpy()
+    err = np.abs(g - g_or).max() / np.abs(g_or).max()
+    assert err <= 1e-10, (label, err)
+    return F
+
+
+def test_3q_random_ragged(oracle_lib, gpu):
+    import torch
+    api, ctx = gpu
+    w = W.random_workload("3q", 300, 150, 41)
+    sl = w.seqs
+    # an empty word and a single-gate word among them
+    words = [list(sl.word(s)) for s in range(sl.S)]
+    words[5] = []
+    words[17] = [3]
+    sl = W.from_words(words)
+    gs = w.model
+    # the replaced words keep their counts only where the model gives p > 0
+    counts = w.counts.copy()
+    counts[oracle_lib.probs(gs.rho, gs.effects, gs.gates, sl.offsets, sl.gates) <= 0] = 0
+    say(f"[3q] random: S={sl.S} sumL={int(sl.offsets[-1])} K={gs.K} M={gs.M}")
+    req = api.Request(ctx, 3, gs.K, gs.M, sl.offsets, sl.gates, counts)
+    obj, p, g = req.eval(_dev(api, gs), want_probs=True, want_grad=True)
+    ctx.sync()
+    _check(oracle_lib, gs, sl, counts, obj, p, g, "request")
+    say("[3q] random: context-level call")
+    seqs = api.DeviceSeqs.from_numpy(sl.offsets, sl.gates)
+    cnt = torch.as_tensor(counts, device="cuda")
+    obj2, p2, g2 = ctx.loglik(_dev(api, gs), seqs, cnt, want_probs=True, want_grad=True)
+    ctx.sync()
+    assert torch.equal(p2, p) and torch.equal(obj2, obj) and torch.equal(g2, g)
+    say("[3q] random: probabilities only and objective only")
+    p3 = req.probs(_dev(api, gs))
+    obj4, _, _ = req.eval(_dev(api, gs), want_probs=False, want_grad=False)
+    ctx.sync()
+    assert torch.equal(p3, p) and torch.equal(obj4, obj)
+
+
+def test_3q_vjp(oracle_lib, gpu):
+    import torch
+    api, ctx = gpu
+    w = W.random_workload("3q", 64, 40, 42)
+    gs, sl = w.model, w.seqs
+    rng = np.random.default_rng(3)
+    Wt = rng.standard_normal((sl.S, gs.M))
+    say(f"[3q] vjp: S={sl.S}")
+    req = api.Request(ctx, 3, gs.K, gs.M, sl.offsets, sl.gates, None)
+    g = req.vjp(_dev(api, gs), torch.as_tensor(Wt, device="cuda"))
+    ctx.sync()
+    g_or = oracle_lib.vjp(gs.rho, gs.effects, gs.gates, sl.offsets, sl.gates, Wt)
+    err = np.abs(g.cpu().numpy() - g_or).max() / np.abs(g_or).max()
+    assert err <= 1e-10, err
+
+
+def test_c4_subset(oracle_lib, gpu):
+    api, ctx = gpu
+    w = W.structured_workload("c4")
+    idx = np.arange(0, w.seqs.S, 97)
+    sl = w.seqs.subset(idx)
+    cnt = w.counts[idx]
+    gs = w.model
+    say(f"[3q] c4 subset: S={sl.S} sumL={int(sl.offsets[-1])}")
+    req = api.Request(ctx, 3, gs.K, gs.M, sl.offsets, sl.gates, cnt)
+    obj, p, g = req.eval(_dev(api, gs), want_probs=True, want_grad=True)
+    ctx.sync()
+    _check(oracle_lib, gs, sl, cnt, obj, p, g, "c4 subset")
+
+
+def test_c4_full_sampled_and_euler(oracle_lib, gpu):
+    api, ctx = gpu
+    w = W.structured_workload("c4")
+    gs, sl = w.model, w.seqs
+    say(f"[3q] c4 full: S={sl.S} sumL={int(sl.offsets[-1])}")
+    req = api.Request(ctx, 3, gs.K, gs.M, sl.offsets, sl.gates, w.counts)
+    obj, p, g = req.eval(_dev(api, gs), want_probs=True, want_grad=True)
+    ctx.sync()
+    p = p.cpu().numpy()
+    g = g.cpu().numpy()
+    F = float(obj.cpu()[0])
+    rng = np.random.default_rng(5)
+    idx = np.sort(rng.choice(sl.S, 400, replace=False))
+    sub = sl.subset(idx)
+    p_or = oracle_lib.probs(gs.rho, gs.effects, gs.gates, sub.offsets, sub.gates)
+    assert np.array_equal(p[idx], p_or)
+    # the objective from the (sample-checked) probabilities
+    N = w.counts.astype(np.float64)
+    F_np = -np.sum(np.where(N > 0, N * np.log(np.where(N > 0, p, 1.0)), 0.0))
+    assert abs(F - F_np) <= 1e-10 * abs(F_np), (F, F_np)
+    # Euler identities of l = -F (multilinear in rho, in each e_m, in the gates)
+    D, M, K = 64, gs.M, gs.K
+    rho_g, E_g, G_g = g[:D], g[D:D + M * D].reshape(M, D), g[D + M * D:].reshape(K, D, D)
+    total = N.sum()
+    assert abs(-np.dot(gs.rho, rho_g) - total) <= 1e-10 * total
+    for m in range(M):
+        t = N[:, m].sum()
+        assert abs(-np.dot(gs.effects[m], E_g[m]) - t) <= 1e-10 * max(t, 1.0)
+    L = sl.lengths()
+    occ = np.zeros((sl.S, K))
+    seq_of_step = np.repeat(np.arange(sl.S), L)
+    np.add.at(occ, (seq_of_step, sl.gates.astype(np.int64)), 1.0)
+    Ns = N.sum(axis=1)
+    for k in range(K):
+        t = float(np.dot(occ[:, k], Ns))
+        assert abs(-np.sum(gs.gates[k] * G_g[k]) - t) <= 1e-10 * t, k
+
+
+def test_3q_in_batch_and_nonpos(oracle_lib, gpu):
+    import torch
+    api, ctx = gpu
+    a = W.random_workload("3q", 120, 60, 43)
+    b = W.random_workload("2q", 200, 80, 44)
+    reqs = [api.Request(ctx, x.n_qubits, x.model.K, x.model.M, x.seqs.offsets, x.seqs.gates, x.counts)
+            for x in (a, b)]
+    th = [_dev(api, x.model) for x in (a, b)]
+    ref = [r.eval(t, want_probs=True) for r, t in zip(reqs, th)]
+    ctx.sync()
+    say("[3q] batch with a two-qubit request")
+    bt = api.Batch(ctx, reqs, th, want_probs=True, want_grad=True, capture_graph=True)
+    for _ in range(2):
+        bt.run()
+        ctx.sync()
+        for x, (o, p, g) in enumerate(ref):
+            assert torch.equal(bt.obj[x], o) and torch.equal(bt.probs[x], p) and torch.equal(bt.grad[x], g)
+    assert bt.nonpos() == [0, 0]
+    say("[3q] p <= 0 with N > 0")
+    E0 = a.model.effects.copy()
+    E0[2] = 0.0
+    bad = api.DeviceGateSet.from_numpy(3, a.model.rho, E0, a.model.gates)
+    o, _, _ = reqs[0].eval(bad)
+    rc, _, nnp = ctx.sync(raise_on_error=False)
+    n_exp = int(np.count_nonzero(a.counts[:, 2] > 0))
+    assert rc == -3 and nnp == n_exp and float(o.cpu()[0]) == float("inf")
+    o2, _, _ = reqs[0].eval(th[0])
+    ctx.sync()
+    assert torch.equal(o2, ref[0][0])
