@@ -29,16 +29,25 @@ METRIC = "sequence evals/s incl. gradient (2q, FP64); p50/p99 latency of served 
 PEAK_FP64 = 78.6
 
 
+_DESC = {
+    "c1": "c1: one-qubit GST list, 6 prep x 6 meas fiducials x 4 germs, powers 1..64, gates {Gi,Gx,Gy} "
+          "with 1e-3 depolarizing + N(0,0.01) over-rotations, counts ~ Multinomial(1000)",
+    "c2": "c2: two-qubit GST list, 11 prep x 11 meas fiducials x 12 germs, powers 1..256, "
+          "gates {Gii,Gxi,Gix,Gyi,Giy,Gcz} with 1e-3 depolarizing + N(0,0.01) over-rotations, "
+          "counts ~ Multinomial(1000)",
+    "c4": "c4: three-qubit GST list, 16 prep x 16 meas fiducials x 98 germs, powers 1..128, gates "
+          "{Gi,Gx,Gy,CZ01,CZ12} with 1e-3 depolarizing + N(0,0.01) over-rotations, counts ~ Multinomial(1000)",
+}
+
+
 def workload_desc(w):
     L = w.seqs.lengths()
     return {
-        "workload": "c2: two-qubit GST list, 11 prep x 11 meas fiducials x 12 germs, powers 1..256, "
-                    "gates {Gii,Gxi,Gix,Gyi,Giy,Gcz} with 1e-3 depolarizing + N(0,0.01) over-rotations, "
-                    "counts ~ Multinomial(1000)",
+        "workload": _DESC[w.name],
         "sequences": int(w.seqs.S),
         "sum_len": int(L.sum()),
         "max_len": int(L.max()),
-        "n_qubits": 2,
+        "n_qubits": int(w.model.n_qubits),
         "params": int(w.model.n_params()),
     }
 
@@ -58,7 +67,18 @@ def _cpu_sample(name):
             out.append((w.model, sub, w.counts[:256]))
         return out, "first 8 gate sets of the uneven batch (6 one-qubit, 2 two-qubit by the seeded mix), " \
                     "256 sequences of each"
+    if name == "c5":
+        out = []
+        for _, kind, S, seed in W.serving_trace(100.0, 8):
+            d = W.serving_request(kind, S, seed, 1)
+            out.append((d.iterates[0], d.seqs.subset(np.arange(256)), d.counts[:256]))
+        return out, "first 8 requests of the serving trace, 256 sequences of each, first iterate"
     w = W.structured_workload(name)
+    if name == "c4":
+        # the full three-qubit list takes minutes per evaluation on one core
+        idx = np.arange(0, w.seqs.S, 97)
+        return [(w.model, w.seqs.subset(idx), w.counts[idx])], \
+            f"c4 every 97th sequence ({len(idx)} of {w.seqs.S})"
     return [(w.model, w.seqs, w.counts)], f"{name} full list ({w.seqs.S} sequences)"
 
 
@@ -136,7 +156,13 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3"])
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5"])
+    ap.add_argument("--rate", type=float, default=100.0, help="c5 / serving: arrivals per second")
+    ap.add_argument("--requests", type=int, default=100, help="c5 / serving: requests in the trace")
+    ap.add_argument("--iters", type=int, default=20, help="c5 / serving: iterations per request")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving measurement of the default run")
+    ap.add_argument("--round-work", type=float, default=4e6,
+                    help="serving: bound on the work of one round, in two-qubit sequence steps")
     ap.add_argument("--path", choices=["resident", "plain"], default="resident")
     ap.add_argument("--sets", type=int, default=0, help="c3: use only the first N gate sets")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
@@ -162,10 +188,69 @@ def main():
         cpu = cpu_baseline(args.workload, args.cpu_seconds, workers)
     if args.workload == "c3":
         out = run_uneven(args)
+    elif args.workload == "c5":
+        out = run_serving(args)
     else:
         out = run_structured(args)
+        if args.workload == "c2" and not args.no_serving:
+            out["serving"] = serving_summary(args)
     out["cpu_baseline"] = cpu
     print(json.dumps(out))
+
+
+def serving_summary(args):
+    """Served fits (continuous batching) and the plain per-request path on the
+    same Poisson trace of mixed one/two/three-qubit fit requests."""
+    import torch
+    from paper_2008_13490_amd import api
+    from paper_2008_13490_amd import serving as SV
+    from paper_2008_13490_amd import workloads as W
+
+    t0 = time.perf_counter()
+    trace = W.serving_trace(args.rate, args.requests)
+    jobs = SV.make_jobs(trace, n_iter=args.iters)
+    t_gen = time.perf_counter() - t0
+    print(f"[bench] serving trace: {len(jobs)} requests at {args.rate} /s, generated in {t_gen:.1f} s",
+          file=sys.stderr, flush=True)
+    ctx = api.Context(0)
+    free, _ = torch.cuda.mem_get_info()
+    budget = int(0.8 * free)
+    served = SV.Scheduler(SV.GPUEngine(ctx), budget, max_active=64, round_work=args.round_work).run(jobs)
+    print(f"[bench] served: {served}", file=sys.stderr, flush=True)
+    SV.reset(jobs)
+    plain = SV.Scheduler(SV.PlainEngine(ctx), budget, max_active=1).run(jobs)
+    print(f"[bench] plain: {plain}", file=sys.stderr, flush=True)
+    kinds = [k for _, k, _, _ in trace]
+    return {
+        "workload": f"c5: Poisson arrivals at {args.rate:g} requests/s, {len(jobs)} fit requests "
+                    f"({kinds.count('1q')} one-qubit, {kinds.count('2q')} two-qubit, {kinds.count('3q')} "
+                    f"three-qubit), S log-uniform in [1000, 100000], random words (L <= 256, three qubits "
+                    f"L <= 128), {args.iters} closed-loop iterations each with gradient, HBM budget "
+                    f"{budget / 2**30:.0f} GiB, 64 slots, rounds of <= {args.round_work:.0e} two-qubit steps",
+        "served": served,
+        "plain_per_request": plain,
+    }
+
+
+def run_serving(args):
+    s = serving_summary(args)
+    sv = s["served"]
+    return {
+        "metric": "p50/p99 latency of served fits; sequence evals/s (FP64, with gradient)",
+        "value": sv["seq_evals_per_s"],
+        "unit": "sequence evals/s",
+        "n_gpus": 1,
+        "steps": sv["iterations"],
+        "warmup": 0,
+        "ms_per_step": sv["wall_s"] * 1e3 / max(sv["rounds"], 1),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": s["workload"]},
+        "serving": s,
+    }
 
 
 def copy_calibration(mib: int):
@@ -248,7 +333,7 @@ def run_structured(args):
     t1 = time.perf_counter()
     ctx.sync()
     fams = _profile(api, ctx, ("leaf", "reduce", "trunk_fwd", "trunk_bwd", "inject", "grad_gemm", "tiles_2q",
-                               "tiles_1q", "tiles_reduce"))
+                               "tiles_1q", "tiles_reduce", "chain_3q", "gemm_3q", "reduce_3q"))
     api.profile_enable(ctx, False)
     elapsed = t1 - t0
     S = w.seqs.S
@@ -386,6 +471,10 @@ def algorithmic_flops(family, D, M, S, sum_len, info):
     if info is None:
         if family in ("leaf", "tiles_2q", "tiles_1q"):
             return 6.0 * D * D * sum_len + 6.0 * D * M * S
+        if family == "chain_3q":   # forward and adjoint products, readout, seed, dE
+            return 4.0 * D * D * sum_len + 6.0 * D * M * S
+        if family == "gemm_3q":    # dG_k = sum b f^T
+            return 2.0 * D * D * sum_len
         return 0.0
     ts, its, lv = info["trunk_steps"], info["item_steps"], max(1, info["levels"])
     if family == "leaf":   # items: forward + adjoint mat-vecs, readout, seed, dE

@@ -211,6 +211,7 @@ struct gst_req {
   int64_t* gate_chunk_ptr64 = nullptr;  // [K + 1]
   double* tile_slab64 = nullptr;        // [n_tiles64][1 + 64 + 64 M]
   double* chunk_slab64 = nullptr;       // [n_chunks64][4096]
+  double* part64 = nullptr;             // scratch of the ordered tile reduction
   size_t eval_ws_bytes = 0;             // context workspace one evaluation with gradient needs
   DevicePlan plan;
   DevBuf ws;
@@ -765,7 +766,9 @@ int gst_req_create_host(gst_ctx* ctx, int n_qubits, int n_gates, int n_outcomes,
                o_p64 = cv.take<int64_t>(pos64.size() + 1), o_cb64 = cv.take<int64_t>(cbeg64.size() + 1),
                o_ce64 = cv.take<int64_t>(cend64.size() + 1), o_gc64 = cv.take<int64_t>(gcp64.size() + 1),
                o_ts64 = cv.take<double>((size_t)std::max<int64_t>(r->n_tiles64, 1) * (D == 64 ? Pc64 : 1)),
-               o_cs64 = cv.take<double>((size_t)std::max<int64_t>(r->n_chunks64, 1) * (D == 64 ? 4096 : 1));
+               o_cs64 = cv.take<double>((size_t)std::max<int64_t>(r->n_chunks64, 1) * (D == 64 ? 4096 : 1)),
+               o_pt64 = cv.take<double>(D == 64 ? (size_t)gst::reduce_parts((int)std::max<int64_t>(r->n_tiles64, 1)) *
+                                                      Pc64 : 1);
   rc = r->data.reserve(cv.off + 256, ctx->stream);
   if (rc) return rc;
   char* base = reinterpret_cast<char*>(r->data.p);
@@ -784,12 +787,15 @@ int gst_req_create_host(gst_ctx* ctx, int n_qubits, int n_gates, int n_outcomes,
     r->gate_chunk_ptr64 = reinterpret_cast<int64_t*>(base + o_gc64);
     r->tile_slab64 = reinterpret_cast<double*>(base + o_ts64);
     r->chunk_slab64 = reinterpret_cast<double*>(base + o_cs64);
+    r->part64 = reinterpret_cast<double*>(base + o_pt64);
     if (!pos64.empty()) HIP_TRY(hipMemcpy(r->pos64, pos64.data(), pos64.size() * 8, hipMemcpyHostToDevice));
     if (!cbeg64.empty()) {
       HIP_TRY(hipMemcpy(r->chunk_beg64, cbeg64.data(), cbeg64.size() * 8, hipMemcpyHostToDevice));
       HIP_TRY(hipMemcpy(r->chunk_end64, cend64.data(), cend64.size() * 8, hipMemcpyHostToDevice));
     }
     HIP_TRY(hipMemcpy(r->gate_chunk_ptr64, gcp64.data(), gcp64.size() * 8, hipMemcpyHostToDevice));
+    // an empty list has no tiles: its single partial row stays zero
+    if (r->n_tiles64 == 0) HIP_TRY(hipMemset(r->tile_slab64, 0, (size_t)Pc64 * 8));
   }
   if (!tiles.empty())
     HIP_TRY(hipMemcpy(r->tiles, tiles.data(), tiles.size() * sizeof(gst::BatchTile), hipMemcpyHostToDevice));
@@ -950,14 +956,16 @@ static int run64(gst_req* r, const gst_gateset* th, int mode, const double* w, d
   }
   if (objective || grad) {
     ProfScope ps(ctx, FAM_REDUCE64);
+    // [objective | rho | E] from the tile partials (two ordered stages) ...
+    const int64_t Pc = 1 + 64 + (int64_t)r->M * 64;
+    HIP_TRY(gst::launch_reduce(r->tile_slab64, (int)std::max<int64_t>(r->n_tiles64, 1), Pc, objective, grad,
+                               nullptr, 64, r->part64, ctx->stream));
+    // ... and the gate columns from the chunk partials
     gst::Reduce64Launch red{};
     red.M = r->M;
-    red.K = want_grad ? r->K : 0;  // without the gradient only the tile columns are added
-    red.tile_slab = r->tile_slab64;
-    red.n_tiles = r->n_tiles64;
+    red.K = r->K;
     red.chunk_slab = r->chunk_slab64;
     red.gate_chunk_ptr = r->gate_chunk_ptr64;
-    red.objective = objective;
     red.grad = grad;
     red.nonpos = np;
     HIP_TRY(gst::launch_reduce64(red, ctx->stream));

@@ -198,13 +198,10 @@ struct Gemm64Launch {
   double* slab;              // [n_chunks][4096]
   int n_chunks;
 };
-struct Reduce64Launch {
+struct Reduce64Launch {            // gate columns only
   int M, K;
-  const double* tile_slab;         // [n_tiles][1 + 64 + 64 M]
-  int64_t n_tiles;
   const double* chunk_slab;        // [n_chunks][4096]
   const int64_t* gate_chunk_ptr;   // [K + 1] chunk range of each gate
-  double* objective;
   double* grad;
   const unsigned long long* nonpos;
 };

@@ -266,34 +266,27 @@ __global__ __launch_bounds__(256) void gemm64_kernel(const Gemm64Launch a) {
     }
 }
 
-// Output column x of [objective | rho | E | G]: the tile partials (x < Pc)
-// or the chunk partials of gate (x - Pc) / 4096, added in order with four
-// interleaved partial sums.
+// Gate columns of the gradient: entry e of dG_k is the sum of the chunk
+// partials of gate k, added in order with four interleaved partial sums.
+// (The tile columns [objective | rho | E] go through the two-stage ordered
+// reduction of the other kernels.)
 __global__ __launch_bounds__(256) void reduce64_kernel(const Reduce64Launch a) {
   __shared__ double red[4][64];
   const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-  const int64_t Pc = 1 + N64 + (int64_t)a.M * N64;
-  const int64_t P = Pc + (int64_t)a.K * GATE64;
-  const int64_t x = (int64_t)blockIdx.x * 64 + tx;
+  const int64_t y = (int64_t)blockIdx.x * 64 + tx;  // index into [K][4096]
+  const int64_t Y = (int64_t)a.K * GATE64;
   double v = 0.0;
-  if (x < Pc) {
-    for (int64_t t = ty; t < a.n_tiles; t += 4) v += a.tile_slab[t * Pc + x];
-  } else if (x < P) {
-    const int64_t y = x - Pc;
+  if (y < Y) {
     const int k = (int)(y / GATE64);
     const int64_t e = y % GATE64;
     for (int64_t c = a.gate_chunk_ptr[k] + ty; c < a.gate_chunk_ptr[k + 1]; c += 4) v += a.chunk_slab[c * GATE64 + e];
   }
   red[ty][tx] = v;
   __syncthreads();
-  if (ty != 0 || x >= P) return;
+  if (ty != 0 || y >= Y) return;
   v = (red[0][tx] + red[1][tx]) + (red[2][tx] + red[3][tx]);
   const bool nonpos = a.nonpos && *a.nonpos != 0;
-  if (x == 0) {
-    if (a.objective) *a.objective = nonpos ? INFINITY : v;
-  } else if (a.grad && !nonpos) {
-    a.grad[x - 1] = v;
-  }
+  if (a.grad && !nonpos) a.grad[1 + N64 + (int64_t)a.M * N64 - 1 + y] = v;
 }
 
 }  // namespace
@@ -320,8 +313,9 @@ hipError_t launch_gemm64(const Gemm64Launch& a, hipStream_t stream) {
 }
 
 hipError_t launch_reduce64(const Reduce64Launch& a, hipStream_t stream) {
-  const int64_t P = 1 + N64 + (int64_t)a.M * N64 + (int64_t)a.K * GATE64;
-  hipLaunchKernelGGL(reduce64_kernel, dim3((unsigned)((P + 63) / 64)), dim3(256), 0, stream, a);
+  const int64_t Y = (int64_t)a.K * GATE64;
+  if (Y == 0 || !a.grad) return hipSuccess;
+  hipLaunchKernelGGL(reduce64_kernel, dim3((unsigned)((Y + 63) / 64)), dim3(256), 0, stream, a);
   return hipGetLastError();
 }
 

@@ -38,12 +38,24 @@ _SZ = np.array([[1, 0], [0, -1]], dtype=np.complex128)
 PAULI_1Q = (_I2, _SX, _SY, _SZ)
 
 
+_PAULI_CACHE: dict = {}
+
+
 def pauli_basis(n: int) -> np.ndarray:
     """Unnormalized n-qubit Pauli products ``P_i``, shape ``[4**n, 2**n, 2**n]``.
 
     Index ``i`` has base-4 digits ``a_0 .. a_{n-1}`` (qubit 0 most significant),
-    so ``P_1 = I x .. x I x sigma^x`` as in Eq. paulibasis.
+    so ``P_1 = I x .. x I x sigma^x`` as in Eq. paulibasis.  (Cached; the
+    returned array is read-only.)
     """
+    if n not in _PAULI_CACHE:
+        b = _pauli_basis(n)
+        b.setflags(write=False)
+        _PAULI_CACHE[n] = b
+    return _PAULI_CACHE[n]
+
+
+def _pauli_basis(n: int) -> np.ndarray:
     out = []
     for digits in itertools.product(range(4), repeat=n):
         m = np.ones((1, 1), dtype=np.complex128)
@@ -61,8 +73,8 @@ def ptm_from_kraus(kraus: Sequence[np.ndarray]) -> np.ndarray:
     D = d * d
     img = np.zeros((D, d, d), dtype=np.complex128)
     for K in kraus:
-        img += np.einsum("ab,jbc,dc->jad", K, P, K.conj())
-    G = np.einsum("iab,jba->ij", P, img) / d
+        img += np.einsum("ab,jbc,dc->jad", K, P, K.conj(), optimize=True)
+    G = np.einsum("iab,jba->ij", P, img, optimize=True) / d
     return np.ascontiguousarray(G.real)
 
 
@@ -198,14 +210,25 @@ def noisy_gateset(kind: str, lam: float, sigma: float, rng: np.random.Generator)
     ``G_k = diag(1, (1-lam) 1) R(U_k)``.  Global depolarizing commutes with
     every unitary channel, so the order of the composition is immaterial.
     """
+    _, Us, n = ideal_unitaries(kind)
+    D = 4 ** n
+    axes, deltas = [], []
+    for _ in Us:
+        axes.append(random_axis(rng, D))
+        deltas.append(rng.normal(0.0, sigma))
+    return gateset_from_rotations(kind, lam, axes, deltas)
+
+
+def gateset_from_rotations(kind: str, lam: float, axes, deltas) -> GateSet:
+    """The gate set of ``kind`` with over-rotation axes ``axes[k]`` (unit
+    vectors over the non-identity Paulis) and angles ``deltas[k]``, composed
+    with global depolarizing of strength ``lam``; ideal SPAM."""
     names, Us, n = ideal_unitaries(kind)
-    d, D = 2 ** n, 4 ** n
+    d = 2 ** n
     P = pauli_basis(n)
     dep = depolarizing_ptm(lam, n)
     coh, G = [], []
-    for U0 in Us:
-        h = random_axis(rng, D)
-        delta = rng.normal(0.0, sigma)
+    for U0, h, delta in zip(Us, axes, deltas):
         H = np.einsum("j,jab->ab", h, P[1:])
         U = expm_hermitian(H, delta / 2.0) @ U0
         coh.append(U)
@@ -480,6 +503,55 @@ def uneven_request(kind: str, S: int, seed: int, lmax: int = 1024, emulate: bool
         p = np.full((S, truth.M), 1.0 / truth.M)
     counts = sample_counts(p, N_SHOTS, r_cnt)
     return Workload(f"uneven-{kind}-S{S}-seed{seed}", truth, model, sl, counts)
+
+
+@dataclasses.dataclass
+class FitRequestData:
+    """A fit request of the serving workload: random words, counts, and the
+    gate sets of its optimizer iterations."""
+    kind: str
+    seqs: SeqList
+    counts: np.ndarray
+    iterates: List[GateSet]
+
+    @property
+    def n_qubits(self) -> int:
+        return self.iterates[0].n_qubits
+
+
+def serving_trace(rate: float, n_requests: int, seed: Optional[int] = None, smin: int = 1000,
+                  smax: int = 100000):
+    """Poisson arrivals at ``rate`` per second: (arrival time, kind, S, seed)
+    with kinds one/two/three qubits in 60/30/10 proportion and S log-uniform
+    in [smin, smax]."""
+    rng = np.random.default_rng(np.random.SeedSequence(MASTER_SEEDS["c5"] if seed is None else seed).spawn(6)[5])
+    gaps = rng.exponential(1.0 / rate, size=n_requests)
+    t = np.cumsum(gaps) - gaps[0]
+    kinds = rng.choice(np.array(["1q", "2q", "3q"]), size=n_requests, p=[0.6, 0.3, 0.1])
+    S = np.exp(rng.uniform(np.log(smin), np.log(smax), size=n_requests)).astype(np.int64)
+    seeds = rng.integers(1, 2 ** 62, size=n_requests)
+    return [(float(a), str(k), int(s), int(sd)) for a, k, s, sd in zip(t, kinds, S, seeds)]
+
+
+def serving_request(kind: str, S: int, seed: int, n_iter: int = 20) -> FitRequestData:
+    """Random words with lengths U{1..256} (one and two qubits) or U{1..128}
+    (three qubits); counts ~ Multinomial(1000, uniform) (the cost of an
+    evaluation does not depend on their values); iterate k has the
+    over-rotation angles delta_true + (1 - k / n_iter) * delta_pert about
+    fixed axes, a CPTP schedule ending next to the truth."""
+    ss = np.random.SeedSequence(seed)
+    r_rot, r_seq, r_cnt, r_pert = [np.random.default_rng(x) for x in ss.spawn(4)]
+    _, Us, n = ideal_unitaries(kind)
+    D = 4 ** n
+    axes = [random_axis(r_rot, D) for _ in Us]
+    d_true = r_rot.normal(0.0, SIGMA, size=len(Us))
+    d_pert = r_pert.normal(0.0, SIGMA, size=len(Us))
+    lmax = 128 if kind == "3q" else 256
+    sl = random_list(S, len(Us), 1, lmax, r_seq)
+    M = 2 ** n
+    counts = sample_counts(np.full((S, M), 1.0 / M), N_SHOTS, r_cnt)
+    its = [gateset_from_rotations(kind, LAMBDA, axes, d_true + (1.0 - k / n_iter) * d_pert) for k in range(n_iter)]
+    return FitRequestData(kind, sl, counts, its)
 
 
 def pack_params(gs: GateSet) -> np.ndarray:

@@ -176,3 +176,15 @@ def test_3q_in_batch_and_nonpos(oracle_lib, gpu):
     o2, _, _ = reqs[0].eval(th[0])
     ctx.sync()
     assert torch.equal(o2, ref[0][0])
+
+
+def test_3q_empty_list(gpu):
+    import torch
+    api, ctx = gpu
+    gs = W.noisy_gateset("3q", 1e-3, 0.01, np.random.default_rng(9))
+    say("[3q] empty list")
+    req = api.Request(ctx, 3, gs.K, gs.M, np.zeros(1, np.int64), np.zeros(0, np.uint8),
+                      np.zeros((0, gs.M), np.int32))
+    obj, _, g = req.eval(_dev(api, gs))
+    ctx.sync()
+    assert float(obj.cpu()[0]) == 0.0 and not torch.any(g != 0)
