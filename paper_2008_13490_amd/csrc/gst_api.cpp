@@ -183,6 +183,10 @@ struct DevicePlan {
 // Sequences per tile of a request: a multiple of the 16 chains of one
 // workgroup, chosen from S alone so that the cut (and with it the order of
 // the partial sums) is a property of the request.
+// Device words of a request's work-queue area: six queue counters 16 words
+// apart (zeroed by the queue-reset kernel), then the nonpos counter (64-bit).
+constexpr int kQueueWords = 96;
+
 static int64_t tile_seqs_for(int64_t S) {
   const int64_t per = (S + 16 * 1024 - 1) / (16 * 1024);
   return 16 * std::min<int64_t>(std::max<int64_t>(per, 1), 8);
@@ -224,11 +228,13 @@ struct gst_batch {
   std::vector<gst_req*> reqs;
   std::vector<gst_gateset> thetas;
   std::vector<double*> probs, objectives, grads;
-  std::vector<int> plan_reqs;           // evaluated through their own plans
-  int n_t16 = 0, n_t4 = 0, n_items = 0, grid = 0, grid16 = 0, grid4 = 0, kmax = 1;
+  std::vector<int> plan_reqs;           // evaluated through their own launch sequences
+  // one group of tiles per tile kernel (see TileKind), each with its own queue
+  int n_tiles[6] = {0, 0, 0, 0, 0, 0}, grid_of[6] = {0, 0, 0, 0, 0, 0};
+  gst::BatchLaunch launch[6] = {};
+  int n_items = 0, kmax = 1;
   int64_t max_len = 0;
   DevBuf desc;
-  gst::BatchLaunch l16{}, l4{};
   gst::BatchReduce red{};
   unsigned long long* req_nonpos = nullptr;
   hipStream_t cap_stream = nullptr;
@@ -240,6 +246,44 @@ struct gst_batch {
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
   }
 };
+
+// Checkpoint rows per chain of the tile kernel for sequences up to max_len.
+static int64_t tile_ckpt_per_team(int64_t max_len) {
+  const int C = gst::leaf_ckpt_interval(16);
+  return ((max_len + C - 1) / C + 1) * 16;
+}
+
+// Tile kernels of the requests without a plan.  Group g of a batch: 0 = the
+// 16-lane-team kernel for two qubits, 1 = the same for one qubit with more
+// than four gates, 2 + K - 1 = the lane-per-chain one-qubit kernel for K
+// gates (K <= 4).
+static int tile_group(int D, int K) { return D == 16 ? 0 : (gst::lane1q_supported(K) ? 1 + K : 1); }
+static bool group_is_lane(int g) { return g >= 2; }
+static int64_t tile_seqs_of_group(int g, int64_t S) { return group_is_lane(g) ? 64 : tile_seqs_for(S); }
+static int group_family(int g) { return g == 0 ? FAM_TILES16 : FAM_TILES4; }
+
+// Workgroups of a launch over n tiles (lane kernel: four waves, one tile each).
+static int group_grid(gst_ctx* ctx, int g, int kmax, int64_t n) {
+  if (n <= 0) return 0;
+  if (group_is_lane(g)) {
+    const int64_t blocks = (n + 3) / 4;
+    return (int)std::min<int64_t>(blocks, (int64_t)gst::lane1q_blocks_per_cu(g - 1) * ctx->n_cu);
+  }
+  return (int)std::min<int64_t>(n, (int64_t)gst::batch_blocks_per_cu(g == 0 ? 16 : 4, kmax) * ctx->n_cu);
+}
+
+// Checkpoint doubles of one chain group (team or wave) and of a whole launch.
+static int64_t group_ckpt_stride(int g, int64_t max_len) {
+  return group_is_lane(g) ? gst::lane1q_ckpt_per_wave(max_len) : tile_ckpt_per_team(max_len);
+}
+static size_t group_ckpt_doubles(int g, int grid, int64_t max_len) {
+  return (size_t)grid * (group_is_lane(g) ? 4 : gst::leaf_teams_per_block(16)) * group_ckpt_stride(g, max_len);
+}
+
+static hipError_t group_launch(int g, const gst::BatchLaunch& l, int grid, hipStream_t stream) {
+  return group_is_lane(g) ? gst::launch_lane1q(l, g - 1, grid, stream) : gst::launch_batch(l, grid, stream);
+}
+
 
 namespace {
 
@@ -718,7 +762,7 @@ int gst_req_create_host(gst_ctx* ctx, int n_qubits, int n_gates, int n_outcomes,
   });
   // tiles of the one- and two-qubit tile kernel (three-qubit requests use
   // their own tiles below)
-  const int64_t tile_seqs = D == 64 ? std::max<int64_t>(S, 1) : tile_seqs_for(S);
+  const int64_t tile_seqs = D == 64 ? std::max<int64_t>(S, 1) : tile_seqs_of_group(tile_group(D, n_gates), S);
   for (int64_t q0 = 0; q0 < S && D <= 16; q0 += tile_seqs) {
     r->tile_q.push_back(q0);
     int64_t cost = 0;
@@ -762,7 +806,7 @@ int gst_req_create_host(gst_ctx* ctx, int n_qubits, int n_gates, int n_outcomes,
   const size_t o_off = cv.take<int64_t>(S + 1), o_g = cv.take<uint8_t>(std::max<int64_t>(n_steps, 1)),
                o_c = cv.take<int32_t>(counts_host ? S * n_outcomes : 1), o_ord = cv.take<int64_t>(S + 1),
                o_sl = cv.take<double>((size_t)std::max<int64_t>(r->n_tiles(), 1) * Pw),
-               o_t = cv.take<gst::BatchTile>(tiles.size() + 1), o_q = cv.take<unsigned>(64 + 2),
+               o_t = cv.take<gst::BatchTile>(tiles.size() + 1), o_q = cv.take<unsigned>(kQueueWords + 2),
                o_p64 = cv.take<int64_t>(pos64.size() + 1), o_cb64 = cv.take<int64_t>(cbeg64.size() + 1),
                o_ce64 = cv.take<int64_t>(cend64.size() + 1), o_gc64 = cv.take<int64_t>(gcp64.size() + 1),
                o_ts64 = cv.take<double>((size_t)std::max<int64_t>(r->n_tiles64, 1) * (D == 64 ? Pc64 : 1)),
@@ -824,11 +868,6 @@ int gst_req_footprint(const gst_req* req, size_t* bytes) {
   return GST_OK;
 }
 
-// Checkpoint rows per chain of the tile kernel for sequences up to max_len.
-static int64_t tile_ckpt_per_team(int64_t max_len) {
-  const int C = gst::leaf_ckpt_interval(16);
-  return ((max_len + C - 1) / C + 1) * 16;
-}
 
 static gst::BatchReq batch_req_of(const gst_req* r, const gst_gateset* th, int mode, const double* w,
                                   double* probs, bool want_grad) {
@@ -857,10 +896,9 @@ static int run_tiles(gst_req* r, const gst_gateset* th, int mode, const double* 
   gst_ctx* ctx = r->ctx;
   const int64_t nt = r->n_tiles();  // 0 for an empty list: the reduce then writes zeros
   const bool want_grad = grad != nullptr;
-  const int bpc = gst::batch_blocks_per_cu(r->D, r->K);
-  const int grid = (int)std::min<int64_t>(nt, (int64_t)bpc * ctx->n_cu);
-  const int64_t ck_team = tile_ckpt_per_team(r->max_len);
-  const size_t ck_bytes = want_grad ? (size_t)grid * gst::leaf_teams_per_block(16) * ck_team * 8 : 0;
+  const int g = tile_group(r->D, r->K);
+  const int grid = group_grid(ctx, g, r->K, nt);
+  const size_t ck_bytes = want_grad ? group_ckpt_doubles(g, grid, r->max_len) * 8 : 0;
   // checkpoints in the context workspace: calls on a context are stream
   // ordered, so every request can share it
   int rc = ctx->ws.reserve(ck_bytes + 256, ctx->stream);
@@ -874,13 +912,13 @@ static int run_tiles(gst_req* r, const gst_gateset* th, int mode, const double* 
   l.n_tiles = (int)nt;
   l.queue = r->queue;
   l.ckpt = want_grad ? reinterpret_cast<double*>(ctx->ws.p) : nullptr;
-  l.ckpt_per_team = ck_team;
+  l.ckpt_per_team = group_ckpt_stride(g, r->max_len);
   l.status = ctx->status;
-  l.req_nonpos = reinterpret_cast<unsigned long long*>(r->queue + 64);
+  l.req_nonpos = reinterpret_cast<unsigned long long*>(r->queue + kQueueWords);
   HIP_TRY(gst::launch_queue_reset(r->queue, l.req_nonpos, 1, ctx->stream));
   if (grid > 0) {
-    ProfScope ps(ctx, r->D == 16 ? FAM_TILES16 : FAM_TILES4);
-    HIP_TRY(gst::launch_batch(l, grid, ctx->stream));
+    ProfScope ps(ctx, group_family(g));
+    HIP_TRY(group_launch(g, l, grid, ctx->stream));
   }
   if (objective || grad) {
     ProfScope ps(ctx, FAM_TILES_RED);
@@ -905,7 +943,7 @@ static int run64(gst_req* r, const gst_gateset* th, int mode, const double* w, d
                  double* grad, unsigned long long* nonpos = nullptr) {
   gst_ctx* ctx = r->ctx;
   const bool want_grad = grad != nullptr;
-  unsigned long long* np = nonpos ? nonpos : reinterpret_cast<unsigned long long*>(r->queue + 64);
+  unsigned long long* np = nonpos ? nonpos : reinterpret_cast<unsigned long long*>(r->queue + kQueueWords);
   if (want_grad) {
     // per-step records in the context workspace (calls on a context are stream ordered)
     int rc = ctx->ws.reserve(r->eval_ws_bytes, ctx->stream);
@@ -1010,15 +1048,11 @@ static int batch_enqueue(gst_batch* b, hipStream_t stream, bool eager) {
   gst_ctx* ctx = b->ctx;
   gst_ctx* pc = eager ? ctx : nullptr;
   if (!b->reqs.empty())
-    HIP_TRY(gst::launch_queue_reset(reinterpret_cast<unsigned*>(b->l16.queue), b->req_nonpos,
-                                    (int)b->reqs.size(), stream));
-  if (b->n_t16 > 0) {
-    ProfScope ps(pc, FAM_TILES16);
-    HIP_TRY(gst::launch_batch(b->l16, b->grid16, stream));
-  }
-  if (b->n_t4 > 0) {
-    ProfScope ps(pc, FAM_TILES4);
-    HIP_TRY(gst::launch_batch(b->l4, b->grid4, stream));
+    HIP_TRY(gst::launch_queue_reset(b->launch[0].queue, b->req_nonpos, (int)b->reqs.size(), stream));
+  for (int g = 0; g < 6; ++g) {
+    if (b->n_tiles[g] == 0) continue;
+    ProfScope ps(pc, group_family(g));
+    HIP_TRY(group_launch(g, b->launch[g], b->grid_of[g], stream));
   }
   if (b->n_items > 0) {
     ProfScope ps(pc, FAM_TILES_RED);
@@ -1035,7 +1069,7 @@ int gst_batch_create(gst_ctx* ctx, int n, gst_req* const* reqs, const gst_gatese
   if (!b) return fail(GST_ENOMEM, "host allocation failed");
   b->ctx = ctx;
   std::vector<gst::BatchReq> rq;
-  std::vector<std::pair<int64_t, gst::BatchTile>> t16, t4;  // (cost, tile)
+  std::vector<std::pair<int64_t, gst::BatchTile>> tiles[6];  // per tile kernel: (cost, tile)
   std::vector<gst::BatchReduceItem> items;
   for (int x = 0; x < n; ++x) {
     gst_req* r = reqs[x];
@@ -1084,7 +1118,7 @@ int gst_batch_create(gst_ctx* ctx, int n, gst_req* const* reqs, const gst_gatese
       T.local = (int32_t)t;
       T.q0 = r->tile_q[t];
       T.q1 = r->tile_q[t + 1];
-      (D == 16 ? t16 : t4).emplace_back(r->tile_cost[t], T);
+      tiles[tile_group(D, r->K)].emplace_back(r->tile_cost[t], T);
     }
     if (ob) {
       const int64_t P = gst::slab_width(D, r->M, r->K);
@@ -1105,43 +1139,44 @@ int gst_batch_create(gst_ctx* ctx, int n, gst_req* const* reqs, const gst_gatese
   auto by_cost = [](const std::pair<int64_t, gst::BatchTile>& a, const std::pair<int64_t, gst::BatchTile>& c) {
     return a.first > c.first;
   };
-  std::stable_sort(t16.begin(), t16.end(), by_cost);
-  std::stable_sort(t4.begin(), t4.end(), by_cost);
-  b->n_t16 = (int)t16.size();
-  b->n_t4 = (int)t4.size();
+  int64_t ck_doubles = 0;
+  for (int g = 0; g < 6; ++g) {
+    std::stable_sort(tiles[g].begin(), tiles[g].end(), by_cost);
+    b->n_tiles[g] = (int)tiles[g].size();
+    b->grid_of[g] = group_grid(ctx, g, b->kmax, b->n_tiles[g]);
+    // the groups run one after another on the stream and share the checkpoints
+    ck_doubles = std::max<int64_t>(ck_doubles, (int64_t)group_ckpt_doubles(g, b->grid_of[g], b->max_len));
+  }
   b->n_items = (int)items.size();
-  b->grid16 = (int)std::min<int64_t>(b->n_t16, (int64_t)gst::batch_blocks_per_cu(16, b->kmax) * ctx->n_cu);
-  b->grid4 = (int)std::min<int64_t>(b->n_t4, (int64_t)gst::batch_blocks_per_cu(4, b->kmax) * ctx->n_cu);
-  b->grid = std::max(b->grid16, b->grid4);
-  const int64_t ck_team = tile_ckpt_per_team(b->max_len);
   Carver cv;
-  const size_t o_rq = cv.take<gst::BatchReq>(rq.size() + 1), o_t16 = cv.take<gst::BatchTile>(t16.size() + 1),
-               o_t4 = cv.take<gst::BatchTile>(t4.size() + 1), o_it = cv.take<gst::BatchReduceItem>(items.size() + 1),
-               o_q = cv.take<unsigned>(64), o_np = cv.take<unsigned long long>(rq.size() + 1),
-               o_ck = cv.take<double>((size_t)b->grid * gst::leaf_teams_per_block(16) * ck_team);
+  size_t o_t[6];
+  const size_t o_rq = cv.take<gst::BatchReq>(rq.size() + 1);
+  for (int g = 0; g < 6; ++g) o_t[g] = cv.take<gst::BatchTile>(tiles[g].size() + 1);
+  const size_t o_it = cv.take<gst::BatchReduceItem>(items.size() + 1), o_q = cv.take<unsigned>(16 * 6),
+               o_np = cv.take<unsigned long long>(rq.size() + 1), o_ck = cv.take<double>((size_t)ck_doubles + 1);
   int rc = b->desc.reserve(cv.off + 256, ctx->stream);
   if (rc) return rc;
   char* base = reinterpret_cast<char*>(b->desc.p);
-  std::vector<gst::BatchTile> v16, v4;
-  for (auto& pr : t16) v16.push_back(pr.second);
-  for (auto& pr : t4) v4.push_back(pr.second);
   if (!rq.empty()) HIP_TRY(hipMemcpy(base + o_rq, rq.data(), rq.size() * sizeof(gst::BatchReq), hipMemcpyHostToDevice));
-  if (!v16.empty()) HIP_TRY(hipMemcpy(base + o_t16, v16.data(), v16.size() * sizeof(gst::BatchTile), hipMemcpyHostToDevice));
-  if (!v4.empty()) HIP_TRY(hipMemcpy(base + o_t4, v4.data(), v4.size() * sizeof(gst::BatchTile), hipMemcpyHostToDevice));
+  for (int g = 0; g < 6; ++g) {
+    std::vector<gst::BatchTile> v;
+    for (auto& pr : tiles[g]) v.push_back(pr.second);
+    if (!v.empty()) HIP_TRY(hipMemcpy(base + o_t[g], v.data(), v.size() * sizeof(gst::BatchTile), hipMemcpyHostToDevice));
+  }
   if (!items.empty())
     HIP_TRY(hipMemcpy(base + o_it, items.data(), items.size() * sizeof(gst::BatchReduceItem), hipMemcpyHostToDevice));
   unsigned* queues = reinterpret_cast<unsigned*>(base + o_q);
   b->req_nonpos = reinterpret_cast<unsigned long long*>(base + o_np);
-  for (int D : {16, 4}) {
-    gst::BatchLaunch& l = D == 16 ? b->l16 : b->l4;
-    l.D = D;
+  for (int g = 0; g < 6; ++g) {
+    gst::BatchLaunch& l = b->launch[g];
+    l.D = g == 0 ? 16 : 4;
     l.kmax = b->kmax;
     l.reqs = reinterpret_cast<const gst::BatchReq*>(base + o_rq);
-    l.tiles = reinterpret_cast<const gst::BatchTile*>(base + (D == 16 ? o_t16 : o_t4));
-    l.n_tiles = D == 16 ? b->n_t16 : b->n_t4;
-    l.queue = queues + (D == 16 ? 0 : 16);
+    l.tiles = reinterpret_cast<const gst::BatchTile*>(base + o_t[g]);
+    l.n_tiles = b->n_tiles[g];
+    l.queue = queues + 16 * g;
     l.ckpt = reinterpret_cast<double*>(base + o_ck);
-    l.ckpt_per_team = ck_team;
+    l.ckpt_per_team = group_ckpt_stride(g, b->max_len);
     l.status = ctx->status;
     l.req_nonpos = b->req_nonpos;
   }

@@ -210,10 +210,7 @@ __global__ __launch_bounds__(256) void batch_kernel(const BatchLaunch a) {
 
 __global__ void queue_reset_kernel(unsigned* q, unsigned long long* req_nonpos, int n_req) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t == 0) {
-    q[0] = 0u;   // queue of the two-qubit tiles
-    q[16] = 0u;  // queue of the one-qubit tiles
-  }
+  if (t < 6) q[16 * t] = 0u;  // the queues of the six tile groups (16 words apart)
   for (int r = t; r < n_req; r += gridDim.x * blockDim.x) req_nonpos[r] = 0ull;
 }
 

@@ -157,6 +157,13 @@ struct BatchReduce {
   const unsigned long long* req_nonpos;
 };
 size_t batch_lds(int kmax);
+// One-qubit requests with K <= 4 gates: one chain per lane, a wave per tile
+// of 64 sequences (gst_lane1q.hip).  ckpt_per_team of the launch is the
+// checkpoint stride of one wave.
+bool lane1q_supported(int K);
+int lane1q_ckpt_per_wave(int64_t max_len);
+int lane1q_blocks_per_cu(int K);
+hipError_t launch_lane1q(const BatchLaunch& a, int K, int n_blocks, hipStream_t stream);
 // Resident workgroups per CU of the batched kernel (occupancy with its LDS).
 int batch_blocks_per_cu(int D, int kmax);
 hipError_t launch_batch(const BatchLaunch& a, int n_blocks, hipStream_t stream);

@@ -168,3 +168,37 @@ def test_batch_nonpos_is_per_request(oracle_lib, gpu):
     assert torch.equal(b.obj[0], o_good) and torch.equal(b.grad[0], g_good)
     assert float(b.obj[1].cpu()[0]) == float("inf")
     b.close()
+
+
+@pytest.mark.parametrize("K", [1, 2, 3, 4, 5, 8])
+def test_one_qubit_gate_counts(oracle_lib, gpu, K):
+    """One-qubit requests with K gates: K <= 4 run one chain per lane, larger
+    K the 16-lane teams; both must match the oracle and give the same bits
+    alone and next to a two-qubit request in a batch."""
+    import torch
+    api, ctx = gpu
+    rng = np.random.default_rng(100 + K)
+    pool = [W.noisy_gateset("1q", 1e-3, 0.01, rng) for _ in range(3)]
+    G = np.concatenate([g.gates for g in pool])[:K]
+    gs = W.GateSet(1, [f"g{k}" for k in range(K)], pool[0].rho, pool[0].effects, np.ascontiguousarray(G))
+    sl = W.random_list(300, K, 0, 200, rng)
+    counts = W.sample_counts(np.full((sl.S, 2), 0.5), 1000, rng)
+    counts[oracle_lib.probs(gs.rho, gs.effects, gs.gates, sl.offsets, sl.gates) <= 0] = 0  # empty words
+    say(f"[batch] one qubit, K={K}: S={sl.S} sumL={int(sl.offsets[-1])}")
+    req = api.Request(ctx, 1, K, 2, sl.offsets, sl.gates, counts)
+    th = api.DeviceGateSet.from_numpy(1, gs.rho, gs.effects, gs.gates)
+    obj, p, g = req.eval(th, want_probs=True, want_grad=True)
+    ctx.sync()
+    F, p_or, g_or, _, rc = oracle_lib.loglik(gs.rho, gs.effects, gs.gates, sl.offsets, sl.gates, counts)
+    assert rc == 0
+    assert np.array_equal(p.cpu().numpy(), p_or)
+    assert abs(float(obj.cpu()[0]) - F) <= 1e-10 * abs(F)
+    assert np.abs(g.cpu().numpy() - g_or).max() <= 1e-10 * np.abs(g_or).max()
+    other = W.random_workload("2q", 90, 60, 7)
+    r2 = api.Request(ctx, 2, other.model.K, other.model.M, other.seqs.offsets, other.seqs.gates, other.counts)
+    t2 = api.DeviceGateSet.from_numpy(2, other.model.rho, other.model.effects, other.model.gates)
+    b = api.Batch(ctx, [r2, req], [t2, th], want_probs=True, want_grad=True, capture_graph=True)
+    b.run()
+    ctx.sync()
+    assert torch.equal(b.obj[1], obj) and torch.equal(b.probs[1], p) and torch.equal(b.grad[1], g)
+    b.close()
