@@ -161,6 +161,7 @@ def main():
     ap.add_argument("--requests", type=int, default=100, help="c5 / serving: requests in the trace")
     ap.add_argument("--iters", type=int, default=20, help="c5 / serving: iterations per request")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving measurement of the default run")
+    ap.add_argument("--no-autotune", action="store_true", help="c3: keep the default tile policy")
     ap.add_argument("--round-work", type=float, default=4e6,
                     help="serving: bound on the work of one round, in two-qubit sequence steps")
     ap.add_argument("--path", choices=["resident", "plain"], default="resident")
@@ -379,6 +380,12 @@ def run_uneven(args):
     if args.sets:
         plan = plan[:args.sets]
     ctx = api.Context(0)
+    tuned = None
+    if not args.no_autotune:
+        from paper_2008_13490_amd import autotune
+        t0 = time.perf_counter()
+        tuned = autotune.tune(ctx, {1: (32, 16384, 1, 1024), 2: (16, 4096, 1, 1024)})
+        print(f"[bench] autotune ({time.perf_counter() - t0:.1f} s): {tuned}", file=sys.stderr, flush=True)
     reqs, thetas = [], []
     S_tot = sum_len = 0
     flops = {16: 0.0, 4: 0.0}
@@ -452,6 +459,8 @@ def run_uneven(args):
         "plain_per_request": {"ms_per_step": plain_s * 1e3, "value": S_tot / plain_s,
                               "same_bits_as_batch": bool(ok)},
         "setup_s": t_setup,
+        "autotune": {str(n): {"best": f"{v['best'][0]} seqs/tile x {v['best'][1] or 'max'} blocks/CU",
+                              "ms": v["ms"]} for n, v in tuned.items()} if tuned else None,
     }
 
 

@@ -182,6 +182,17 @@ int gst_batch_nonpos(gst_batch* batch, int64_t* counts);
 int gst_batch_destroy(gst_batch* batch);
 
 /*
+ * Tile policy (the knob of the autotuner): sequences per tile and workgroups
+ * per CU of the tile kernels for gate sets of `n_qubits` qubits, for the
+ * requests created afterwards on this context (a request keeps the tile cut
+ * it was created with, so its results stay the same alone and in any
+ * batch).  seqs_per_tile is rounded up to the kernel's granularity (64 for
+ * one qubit with at most four gates, else 16; any value for three qubits);
+ * 0 restores the default.  blocks_per_cu = 0 uses as many as fit.
+ */
+int gst_tune_set(gst_ctx* ctx, int n_qubits, int seqs_per_tile, int blocks_per_cu);
+
+/*
  * Kernel timing (diagnostics).  While enabled, every kernel the context
  * enqueues is bracketed by two HIP events recorded on the context's stream.
  * gst_profile_read synchronizes the stream and returns, for the kernel family

@@ -268,6 +268,11 @@ class Batch:
             pass
 
 
+def tune_set(ctx: Context, n_qubits: int, seqs_per_tile: int = 0, blocks_per_cu: int = 0):
+    """Tile policy for requests created afterwards on ``ctx`` (``gst_tune_set``)."""
+    _lib.check(ctx.lib.gst_tune_set(ctx.handle, n_qubits, seqs_per_tile, blocks_per_cu))
+
+
 def profile_enable(ctx: Context, on: bool = True):
     _lib.check(ctx.lib.gst_profile_enable(ctx.handle, 1 if on else 0))
 

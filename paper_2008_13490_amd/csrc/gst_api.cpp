@@ -112,6 +112,8 @@ struct Carver {
 struct gst_ctx {
   int device = 0;
   int n_cu = 0;
+  int tune_tile[4] = {0, 0, 0, 0};  // sequences per tile by qubit count (0 = default)
+  int tune_bpc[4] = {0, 0, 0, 0};   // workgroups per CU by qubit count (0 = as many as fit)
   hipStream_t stream = nullptr;
   unsigned long long* status = nullptr;  // device [2]
   DevBuf ws;
@@ -259,17 +261,28 @@ static int64_t tile_ckpt_per_team(int64_t max_len) {
 // gates (K <= 4).
 static int tile_group(int D, int K) { return D == 16 ? 0 : (gst::lane1q_supported(K) ? 1 + K : 1); }
 static bool group_is_lane(int g) { return g >= 2; }
-static int64_t tile_seqs_of_group(int g, int64_t S) { return group_is_lane(g) ? 64 : tile_seqs_for(S); }
+// Sequences per tile: the context's tuned value (rounded up to the kernel's
+// granularity: 64 for the lane kernel, 16 for the team kernels) or the
+// default.  Fixed into the request when it is created.
+static int64_t tile_seqs_of_group(const gst_ctx* ctx, int g, int64_t S) {
+  const int t = ctx->tune_tile[g == 0 ? 2 : 1];
+  const int64_t gran = group_is_lane(g) ? 64 : 16;
+  if (t > 0) return (t + gran - 1) / gran * gran;
+  return group_is_lane(g) ? 64 : tile_seqs_for(S);
+}
 static int group_family(int g) { return g == 0 ? FAM_TILES16 : FAM_TILES4; }
 
 // Workgroups of a launch over n tiles (lane kernel: four waves, one tile each).
+static int capped(int bpc, int cap) { return cap > 0 ? std::min(bpc, cap) : bpc; }
+
 static int group_grid(gst_ctx* ctx, int g, int kmax, int64_t n) {
   if (n <= 0) return 0;
+  const int cap = ctx->tune_bpc[g == 0 ? 2 : 1];
   if (group_is_lane(g)) {
     const int64_t blocks = (n + 3) / 4;
-    return (int)std::min<int64_t>(blocks, (int64_t)gst::lane1q_blocks_per_cu(g - 1) * ctx->n_cu);
+    return (int)std::min<int64_t>(blocks, (int64_t)capped(gst::lane1q_blocks_per_cu(g - 1), cap) * ctx->n_cu);
   }
-  return (int)std::min<int64_t>(n, (int64_t)gst::batch_blocks_per_cu(g == 0 ? 16 : 4, kmax) * ctx->n_cu);
+  return (int)std::min<int64_t>(n, (int64_t)capped(gst::batch_blocks_per_cu(g == 0 ? 16 : 4, kmax), cap) * ctx->n_cu);
 }
 
 // Checkpoint doubles of one chain group (team or wave) and of a whole launch.
@@ -693,6 +706,16 @@ int gst_vjp(gst_ctx* ctx, const gst_gateset* gs, const gst_seqlist* seqs, const 
   return plain_eval(ctx, gs, seqs, gst::MODE_VJP, nullptr, w, nullptr, nullptr, grad);
 }
 
+int gst_tune_set(gst_ctx* ctx, int n_qubits, int seqs_per_tile, int blocks_per_cu) {
+  if (!ctx) return fail(GST_EINVAL, "ctx is NULL");
+  if (n_qubits < 1 || n_qubits > 3) return fail(GST_EINVAL, "n_qubits must be 1, 2 or 3");
+  if (seqs_per_tile < 0 || seqs_per_tile > 4096 || blocks_per_cu < 0 || blocks_per_cu > 64)
+    return fail(GST_EINVAL, "tile policy out of range");
+  ctx->tune_tile[n_qubits] = seqs_per_tile;
+  ctx->tune_bpc[n_qubits] = blocks_per_cu;
+  return GST_OK;
+}
+
 int gst_profile_enable(gst_ctx* ctx, int enable) {
   if (!ctx) return fail(GST_EINVAL, "ctx is NULL");
   ctx->prof.on = enable != 0;
@@ -762,7 +785,7 @@ int gst_req_create_host(gst_ctx* ctx, int n_qubits, int n_gates, int n_outcomes,
   });
   // tiles of the one- and two-qubit tile kernel (three-qubit requests use
   // their own tiles below)
-  const int64_t tile_seqs = D == 64 ? std::max<int64_t>(S, 1) : tile_seqs_of_group(tile_group(D, n_gates), S);
+  const int64_t tile_seqs = D == 64 ? std::max<int64_t>(S, 1) : tile_seqs_of_group(ctx, tile_group(D, n_gates), S);
   for (int64_t q0 = 0; q0 < S && D <= 16; q0 += tile_seqs) {
     r->tile_q.push_back(q0);
     int64_t cost = 0;
@@ -781,8 +804,8 @@ int gst_req_create_host(gst_ctx* ctx, int n_qubits, int n_gates, int n_outcomes,
   // gate-gradient kernel
   std::vector<int64_t> pos64, cbeg64, cend64, gcp64;
   if (D == 64) {
-    r->tile_seqs64 = 16;
-    r->n_tiles64 = (S + 15) / 16;
+    r->tile_seqs64 = ctx->tune_tile[3] > 0 ? ctx->tune_tile[3] : 16;
+    r->n_tiles64 = (S + r->tile_seqs64 - 1) / r->tile_seqs64;
     std::vector<int64_t> gp((size_t)n_gates + 1, 0);
     for (int64_t t = 0; t < n_steps; ++t) gp[sl->gate_idx[t] + 1] += 1;
     for (int k = 0; k < n_gates; ++k) gp[k + 1] += gp[k];
@@ -975,7 +998,8 @@ static int run64(gst_req* r, const gst_gateset* th, int mode, const double* w, d
   a.slab = r->tile_slab64;
   a.status = ctx->status;
   a.nonpos = np;
-  const int grid = (int)std::min<int64_t>(r->n_tiles64, (int64_t)gst::chain64_blocks_per_cu(r->K) * ctx->n_cu);
+  const int grid = (int)std::min<int64_t>(
+      r->n_tiles64, (int64_t)capped(gst::chain64_blocks_per_cu(r->K), ctx->tune_bpc[3]) * ctx->n_cu);
   if (grid > 0) {
     ProfScope ps(ctx, FAM_CHAIN64);
     HIP_TRY(gst::launch_chain64(a, grid, ctx->stream));

@@ -202,3 +202,41 @@ def test_one_qubit_gate_counts(oracle_lib, gpu, K):
     ctx.sync()
     assert torch.equal(b.obj[1], obj) and torch.equal(b.probs[1], p) and torch.equal(b.grad[1], g)
     b.close()
+
+
+def test_tile_policy(oracle_lib, gpu):
+    """A request created under another tile policy (the autotuner's knob)
+    gives the same probabilities, the objective and gradient within the
+    tolerance, and the same bits alone and in a batch."""
+    import torch
+    api, ctx = gpu
+    w = W.random_workload("2q", 400, 300, 51)
+    v = W.random_workload("1q", 500, 300, 52)
+    ref = {}
+    for n, x in ((2, w), (1, v)):
+        r = api.Request(ctx, n, x.model.K, x.model.M, x.seqs.offsets, x.seqs.gates, x.counts)
+        t = api.DeviceGateSet.from_numpy(n, x.model.rho, x.model.effects, x.model.gates)
+        ref[n] = r.eval(t, want_probs=True)
+    ctx.sync()
+    for tile, bpc in ((48, 1), (128, 0)):
+        say(f"[batch] tile policy {tile} x {bpc}")
+        api.tune_set(ctx, 2, tile, bpc)
+        api.tune_set(ctx, 1, tile, bpc)
+        reqs, ths = [], []
+        for n, x in ((2, w), (1, v)):
+            reqs.append(api.Request(ctx, n, x.model.K, x.model.M, x.seqs.offsets, x.seqs.gates, x.counts))
+            ths.append(api.DeviceGateSet.from_numpy(n, x.model.rho, x.model.effects, x.model.gates))
+        outs = [r.eval(t, want_probs=True) for r, t in zip(reqs, ths)]
+        ctx.sync()
+        b = api.Batch(ctx, reqs, ths, want_probs=True, want_grad=True)
+        b.run()
+        ctx.sync()
+        for x, (n, (o, p, g)) in enumerate(zip((2, 1), outs)):
+            o0, p0, g0 = ref[n]
+            assert torch.equal(p, p0)
+            assert abs(float(o.cpu()[0]) - float(o0.cpu()[0])) <= 1e-12 * abs(float(o0.cpu()[0]))
+            assert float((g - g0).abs().max()) <= 1e-12 * float(g0.abs().max())
+            assert torch.equal(b.obj[x], o) and torch.equal(b.grad[x], g) and torch.equal(b.probs[x], p)
+        b.close()
+    api.tune_set(ctx, 2, 0, 0)
+    api.tune_set(ctx, 1, 0, 0)
