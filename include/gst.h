@@ -203,6 +203,10 @@ int gst_tune_set(gst_ctx* ctx, int n_qubits, int seqs_per_tile, int blocks_per_c
  * enabled; the counters are not reset by reading.
  */
 int gst_profile_enable(gst_ctx* ctx, int enable);
+/* Restrict the events to one kernel family (NULL = all families): a timed
+   region can then carry the events of the kernel it reports on and no
+   others. */
+int gst_profile_only(gst_ctx* ctx, const char* kernel);
 int gst_profile_read(gst_ctx* ctx, const char* kernel, double* total_ms, int64_t* launches);
 
 /* Message of the last failing call on this host thread ("" if none). */

@@ -23,7 +23,8 @@ EXPORTED = [
     "gst_max_gates", "gst_create", "gst_destroy", "gst_sync", "gst_probs", "gst_loglik", "gst_vjp",
     "gst_req_create_host", "gst_req_footprint", "gst_req_eval", "gst_req_probs", "gst_req_vjp",
     "gst_req_destroy", "gst_req_plan_info", "gst_batch_create", "gst_batch_run", "gst_batch_nonpos",
-    "gst_batch_destroy", "gst_tune_set", "gst_profile_enable", "gst_profile_read", "gst_last_error",
+    "gst_batch_destroy", "gst_tune_set", "gst_profile_enable", "gst_profile_only", "gst_profile_read",
+    "gst_last_error",
 ]
 
 
@@ -78,6 +79,8 @@ def load():
         lib.gst_profile_read.argtypes = [P, ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
                                          ctypes.POINTER(ctypes.c_int64)]
         lib.gst_profile_enable.restype = I
+        lib.gst_profile_only.argtypes = [P, ctypes.c_char_p]
+        lib.gst_profile_only.restype = I
         lib.gst_tune_set.argtypes = [P, I, I, I]
         lib.gst_tune_set.restype = I
         lib.gst_profile_read.restype = I

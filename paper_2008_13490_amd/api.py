@@ -273,6 +273,11 @@ def tune_set(ctx: Context, n_qubits: int, seqs_per_tile: int = 0, blocks_per_cu:
     _lib.check(ctx.lib.gst_tune_set(ctx.handle, n_qubits, seqs_per_tile, blocks_per_cu))
 
 
+def profile_only(ctx: Context, family: Optional[str] = None):
+    """Record kernel events for one family only (None = all)."""
+    _lib.check(ctx.lib.gst_profile_only(ctx.handle, None if family is None else family.encode()))
+
+
 def profile_enable(ctx: Context, on: bool = True):
     _lib.check(ctx.lib.gst_profile_enable(ctx.handle, 1 if on else 0))
 

@@ -61,6 +61,7 @@ struct DevBuf {
 // Per-kernel-family event timing (gst_profile_*).
 struct Profiler {
   bool on = false;
+  int only = -1;  // record only this family (-1 = all)
   struct Pending {
     int family;
     hipEvent_t a, b;
@@ -126,7 +127,7 @@ struct ProfScope {
   int fam;
   hipEvent_t a = nullptr;
   ProfScope(gst_ctx* ctx, int family) : c(ctx), fam(family) {
-    if (c && c->prof.on) {
+    if (c && c->prof.on && (c->prof.only < 0 || c->prof.only == fam)) {
       a = c->prof.get();
       if (a) (void)hipEventRecord(a, c->stream);
     }
@@ -720,6 +721,20 @@ int gst_profile_enable(gst_ctx* ctx, int enable) {
   if (!ctx) return fail(GST_EINVAL, "ctx is NULL");
   ctx->prof.on = enable != 0;
   return GST_OK;
+}
+
+int gst_profile_only(gst_ctx* ctx, const char* kernel) {
+  if (!ctx) return fail(GST_EINVAL, "ctx is NULL");
+  if (!kernel) {
+    ctx->prof.only = -1;
+    return GST_OK;
+  }
+  for (int f = 0; f < FAM_N; ++f)
+    if (std::strcmp(kernel, kFamilyNames[f]) == 0) {
+      ctx->prof.only = f;
+      return GST_OK;
+    }
+  return fail(GST_EINVAL, std::string("unknown kernel family ") + kernel);
 }
 
 int gst_profile_read(gst_ctx* ctx, const char* kernel, double* total_ms, int64_t* launches) {
