@@ -185,7 +185,7 @@ __global__ __launch_bounds__(256) void batch_kernel(const BatchLaunch a) {
     st_b[e * 16 + i] = b;                                    \
     st_f[e * 16 + i] = fs[RR];                               \
     if (i == 0) st_k[e] = v ? (uint8_t)k : (uint8_t)0xFF;    \
-    const double bn = dot16_split(b, load_row(s.GTs + k * GATE_STRIDE + i * ROW)); \
+    const double bn = dot16(b, load_row(s.GTs + k * GATE_STRIDE + i * ROW)); \
     b = v ? bn : b;                                          \
   }
         GST_BWD(7) GST_BWD(6) GST_BWD(5) GST_BWD(4) GST_BWD(3) GST_BWD(2) GST_BWD(1) GST_BWD(0)

@@ -119,126 +119,6 @@ __device__ __forceinline__ double dot16_from(double acc, double x, const Row16& 
 // Same as dot16_bcast with the row already in registers.
 __device__ __forceinline__ double dot16(double x, const Row16& r) { return dot16_from(0.0, x, r); }
 
-// Sum over j of r[j] * x@j as four interleaved partial chains (j mod 4),
-// combined as (s0 + s1) + (s2 + s3): a quarter of the dependent latency of
-// dot16.  Used only where the summation order is free (adjoints).
-__device__ __forceinline__ double dot16_split(double x, const Row16& r) {
-  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-  asm volatile(
-      "s_nop 1\n\t"
-      "v_fmac_f64_dpp %0, %4, %5 row_newbcast:0 row_mask:0xf bank_mask:0xf\n\t"
-      "v_fmac_f64_dpp %1, %4, %6 row_newbcast:1 row_mask:0xf bank_mask:0xf\n\t"
-      "v_fmac_f64_dpp %2, %4, %7 row_newbcast:2 row_mask:0xf bank_mask:0xf\n\t"
-      "v_fmac_f64_dpp %3, %4, %8 row_newbcast:3 row_mask:0xf bank_mask:0xf\n\t"
-      "v_fmac_f64_dpp %0, %4, %9 row_newbcast:4 row_mask:0xf bank_mask:0xf\n\t"
-      "v_fmac_f64_dpp %1, %4, %10 row_newbcast:5 row_mask:0xf bank_mask:0xf\n\t"
-      "v_fmac_f64_dpp %2, %4, %11 row_newbcast:6 row_mask:0xf bank_mask:0xf\n\t"
-      "v_fmac_f64_dpp %3, %4, %12 row_newbcast:7 row_mask:0xf bank_mask:0xf\n\t"
-      "v_fmac_f64_dpp %0, %4, %13 row_newbcast:8 row_mask:0xf bank_mask:0xf\n\t"
-      "v_fmac_f64_dpp %1, %4, %14 row_newbcast:9 row_mask:0xf bank_mask:0xf\n\t"
-      "v_fmac_f64_dpp %2, %4, %15 row_newbcast:10 row_mask:0xf bank_mask:0xf\n\t"
-      "v_fmac_f64_dpp %3, %4, %16 row_newbcast:11 row_mask:0xf bank_mask:0xf\n\t"
-      "v_fmac_f64_dpp %0, %4, %17 row_newbcast:12 row_mask:0xf bank_mask:0xf\n\t"
-      "v_fmac_f64_dpp %1, %4, %18 row_newbcast:13 row_mask:0xf bank_mask:0xf\n\t"
-      "v_fmac_f64_dpp %2, %4, %19 row_newbcast:14 row_mask:0xf bank_mask:0xf\n\t"
-      "v_fmac_f64_dpp %3, %4, %20 row_newbcast:15 row_mask:0xf bank_mask:0xf"
-      : "+v"(s0), "+v"(s1), "+v"(s2), "+v"(s3)
-      : "v"(x), "v"(r.a0.x), "v"(r.a0.y), "v"(r.a1.x), "v"(r.a1.y), "v"(r.a2.x), "v"(r.a2.y), "v"(r.a3.x),
-        "v"(r.a3.y), "v"(r.a4.x), "v"(r.a4.y), "v"(r.a5.x), "v"(r.a5.y), "v"(r.a6.x), "v"(r.a6.y), "v"(r.a7.x),
-        "v"(r.a7.y));
-  return (s0 + s1) + (s2 + s3);
-}
-
-// LDS byte address of a __shared__ pointer.
-__device__ __forceinline__ uint32_t lds_addr(const void* p) {
-  return (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) void*)p;
-}
-
-// One forward step of a chain whose next row is already known: returns
-// dot16(x, cur) (same order as dot16) and loads the next row (LDS byte address
-// `na`) into `nx`, issuing the eight reads in the gaps of the dependent chain.
-// The loads are complete when the block ends.
-__device__ __forceinline__ double step_fwd(double x, const Row16& c, uint32_t na, Row16& nx) {
-  double acc;
-  asm volatile(
-      "v_mov_b64 %0, 0\n\t"
-      "s_nop 0\n\t"
-      "v_fmac_f64_dpp %0, %9, %11 row_newbcast:0 row_mask:0xf bank_mask:0xf\n\t"
-      "ds_read_b128 %1, %10\n\t"
-      "v_fmac_f64_dpp %0, %9, %12 row_newbcast:1 row_mask:0xf bank_mask:0xf\n\t"
-      "ds_read_b128 %2, %10 offset:16\n\t"
-      "v_fmac_f64_dpp %0, %9, %13 row_newbcast:2 row_mask:0xf bank_mask:0xf\n\t"
-      "ds_read_b128 %3, %10 offset:32\n\t"
-      "v_fmac_f64_dpp %0, %9, %14 row_newbcast:3 row_mask:0xf bank_mask:0xf\n\t"
-      "ds_read_b128 %4, %10 offset:48\n\t"
-      "v_fmac_f64_dpp %0, %9, %15 row_newbcast:4 row_mask:0xf bank_mask:0xf\n\t"
-      "ds_read_b128 %5, %10 offset:64\n\t"
-      "v_fmac_f64_dpp %0, %9, %16 row_newbcast:5 row_mask:0xf bank_mask:0xf\n\t"
-      "ds_read_b128 %6, %10 offset:80\n\t"
-      "v_fmac_f64_dpp %0, %9, %17 row_newbcast:6 row_mask:0xf bank_mask:0xf\n\t"
-      "ds_read_b128 %7, %10 offset:96\n\t"
-      "v_fmac_f64_dpp %0, %9, %18 row_newbcast:7 row_mask:0xf bank_mask:0xf\n\t"
-      "ds_read_b128 %8, %10 offset:112\n\t"
-      "v_fmac_f64_dpp %0, %9, %19 row_newbcast:8 row_mask:0xf bank_mask:0xf\n\t"
-      "v_fmac_f64_dpp %0, %9, %20 row_newbcast:9 row_mask:0xf bank_mask:0xf\n\t"
-      "v_fmac_f64_dpp %0, %9, %21 row_newbcast:10 row_mask:0xf bank_mask:0xf\n\t"
-      "v_fmac_f64_dpp %0, %9, %22 row_newbcast:11 row_mask:0xf bank_mask:0xf\n\t"
-      "v_fmac_f64_dpp %0, %9, %23 row_newbcast:12 row_mask:0xf bank_mask:0xf\n\t"
-      "v_fmac_f64_dpp %0, %9, %24 row_newbcast:13 row_mask:0xf bank_mask:0xf\n\t"
-      "v_fmac_f64_dpp %0, %9, %25 row_newbcast:14 row_mask:0xf bank_mask:0xf\n\t"
-      "v_fmac_f64_dpp %0, %9, %26 row_newbcast:15 row_mask:0xf bank_mask:0xf\n\t"
-      "s_waitcnt lgkmcnt(0)"
-      : "=&v"(acc), "=&v"(nx.a0), "=&v"(nx.a1), "=&v"(nx.a2), "=&v"(nx.a3), "=&v"(nx.a4), "=&v"(nx.a5),
-        "=&v"(nx.a6), "=&v"(nx.a7)
-      : "v"(x), "v"(na), "v"(c.a0.x), "v"(c.a0.y), "v"(c.a1.x), "v"(c.a1.y), "v"(c.a2.x), "v"(c.a2.y),
-        "v"(c.a3.x), "v"(c.a3.y), "v"(c.a4.x), "v"(c.a4.y), "v"(c.a5.x), "v"(c.a5.y), "v"(c.a6.x),
-        "v"(c.a6.y), "v"(c.a7.x), "v"(c.a7.y)
-      : "memory");
-  return acc;
-}
-
-// Adjoint step: returns the four-way split sum of dot16_split(x, cur) and
-// loads the next row like step_fwd.
-__device__ __forceinline__ double step_bwd(double x, const Row16& c, uint32_t na, Row16& nx) {
-  double s0, s1, s2, s3;
-  asm volatile(
-      "v_mov_b64 %0, 0\n\t"
-      "v_mov_b64 %1, 0\n\t"
-      "v_mov_b64 %2, 0\n\t"
-      "v_mov_b64 %3, 0\n\t"
-      "v_fmac_f64_dpp %0, %12, %14 row_newbcast:0 row_mask:0xf bank_mask:0xf\n\t"
-      "v_fmac_f64_dpp %1, %12, %15 row_newbcast:1 row_mask:0xf bank_mask:0xf\n\t"
-      "ds_read_b128 %4, %13\n\t"
-      "v_fmac_f64_dpp %2, %12, %16 row_newbcast:2 row_mask:0xf bank_mask:0xf\n\t"
-      "v_fmac_f64_dpp %3, %12, %17 row_newbcast:3 row_mask:0xf bank_mask:0xf\n\t"
-      "ds_read_b128 %5, %13 offset:16\n\t"
-      "v_fmac_f64_dpp %0, %12, %18 row_newbcast:4 row_mask:0xf bank_mask:0xf\n\t"
-      "v_fmac_f64_dpp %1, %12, %19 row_newbcast:5 row_mask:0xf bank_mask:0xf\n\t"
-      "ds_read_b128 %6, %13 offset:32\n\t"
-      "v_fmac_f64_dpp %2, %12, %20 row_newbcast:6 row_mask:0xf bank_mask:0xf\n\t"
-      "v_fmac_f64_dpp %3, %12, %21 row_newbcast:7 row_mask:0xf bank_mask:0xf\n\t"
-      "ds_read_b128 %7, %13 offset:48\n\t"
-      "v_fmac_f64_dpp %0, %12, %22 row_newbcast:8 row_mask:0xf bank_mask:0xf\n\t"
-      "v_fmac_f64_dpp %1, %12, %23 row_newbcast:9 row_mask:0xf bank_mask:0xf\n\t"
-      "ds_read_b128 %8, %13 offset:64\n\t"
-      "v_fmac_f64_dpp %2, %12, %24 row_newbcast:10 row_mask:0xf bank_mask:0xf\n\t"
-      "v_fmac_f64_dpp %3, %12, %25 row_newbcast:11 row_mask:0xf bank_mask:0xf\n\t"
-      "ds_read_b128 %9, %13 offset:80\n\t"
-      "v_fmac_f64_dpp %0, %12, %26 row_newbcast:12 row_mask:0xf bank_mask:0xf\n\t"
-      "v_fmac_f64_dpp %1, %12, %27 row_newbcast:13 row_mask:0xf bank_mask:0xf\n\t"
-      "ds_read_b128 %10, %13 offset:96\n\t"
-      "v_fmac_f64_dpp %2, %12, %28 row_newbcast:14 row_mask:0xf bank_mask:0xf\n\t"
-      "v_fmac_f64_dpp %3, %12, %29 row_newbcast:15 row_mask:0xf bank_mask:0xf\n\t"
-      "ds_read_b128 %11, %13 offset:112\n\t"
-      "s_waitcnt lgkmcnt(0)"
-      : "=&v"(s0), "=&v"(s1), "=&v"(s2), "=&v"(s3), "=&v"(nx.a0), "=&v"(nx.a1), "=&v"(nx.a2), "=&v"(nx.a3),
-        "=&v"(nx.a4), "=&v"(nx.a5), "=&v"(nx.a6), "=&v"(nx.a7)
-      : "v"(x), "v"(na), "v"(c.a0.x), "v"(c.a0.y), "v"(c.a1.x), "v"(c.a1.y), "v"(c.a2.x), "v"(c.a2.y),
-        "v"(c.a3.x), "v"(c.a3.y), "v"(c.a4.x), "v"(c.a4.y), "v"(c.a5.x), "v"(c.a5.y), "v"(c.a6.x),
-        "v"(c.a6.y), "v"(c.a7.x), "v"(c.a7.y)
-      : "memory");
-  return (s0 + s1) + (s2 + s3);
-}
 
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 

@@ -40,11 +40,16 @@ __device__ __forceinline__ double load_state(const double* FA, int64_t row, int 
 // access other than the store of the result.  Lanes 16..63 repeat the work of
 // lanes 0..15 (same rows, same inputs); only lanes 0..D-1 store.
 // ---------------------------------------------------------------------------
-constexpr int TI = 32;  // injection vectors staged per wave
+constexpr int SEGW = 64;  // segment descriptors held at a time (one per lane)
+
+// Doubles of LDS in front of the per-wave staging of injected vectors (the
+// gate set, its transpose, the effects and rho).
+__host__ __device__ inline size_t trunk_head_doubles(int K) {
+  return (size_t)2 * K * GATE_STRIDE + 2 * 16 * ROW + 16;
+}
 
 __host__ __device__ inline size_t trunk_lds_bytes(int K) {
-  const size_t head = ((size_t)2 * K * GATE_STRIDE + 2 * 16 * ROW + 16) * 8;
-  const size_t a = head + (size_t)WAVES * TI * 16 * 8 + 64;
+  const size_t a = (trunk_head_doubles(K) + (size_t)WAVES * SEGW * 16) * 8 + 64;
   const size_t r = lds_red_bytes(K);
   return a > r ? a : r;
 }
@@ -53,17 +58,37 @@ struct Seg {
   int start, count, per, g0, g1, g2, g3;
 };
 
-__device__ __forceinline__ Seg load_seg(const PlanArgs& a, int64_t sg) {
-  Seg x;
-  const uint32_t pat = (uint32_t)uniform((int)a.seg_pattern[sg]);
-  x.start = uniform(a.seg_start[sg]);
-  x.count = uniform(a.seg_count[sg]);
-  x.per = (int)(pat & 0xffu);
-  x.g0 = (int)((pat >> 8) & 0xffu);
-  x.g1 = (int)((pat >> 16) & 0xffu);
-  x.g2 = (int)((pat >> 24) & 0xffu);
-  x.g3 = uniform((int)a.seg_gate3[sg]);
-  return x;
+// Descriptors of up to 64 consecutive segments, lane j holding segment
+// base + j: one batch of loads per 64 segments instead of a dependent load
+// at the start of every segment (segments can be a single step long).
+struct SegLanes {
+  int start, count, pat, g3;
+  int64_t slot;
+};
+
+__device__ __forceinline__ SegLanes load_seg_lanes(const PlanArgs& a, int64_t sg, int64_t sg_end, bool want_slot) {
+  SegLanes d{0, 0, 0, 0, -1};
+  if (sg < sg_end) {
+    d.start = a.seg_start[sg];
+    d.count = a.seg_count[sg];
+    d.pat = (int)a.seg_pattern[sg];
+    d.g3 = (int)a.seg_gate3[sg];
+    if (want_slot) d.slot = a.seg_inj[sg];
+  }
+  return d;
+}
+
+__device__ __forceinline__ Seg seg_of(const SegLanes& d, int x) {
+  Seg g;
+  const uint32_t pat = (uint32_t)__builtin_amdgcn_readlane(d.pat, x);
+  g.start = __builtin_amdgcn_readlane(d.start, x);
+  g.count = __builtin_amdgcn_readlane(d.count, x);
+  g.per = (int)(pat & 0xffu);
+  g.g0 = (int)((pat >> 8) & 0xffu);
+  g.g1 = (int)((pat >> 16) & 0xffu);
+  g.g2 = (int)((pat >> 24) & 0xffu);
+  g.g3 = __builtin_amdgcn_readlane(d.g3, x);
+  return g;
 }
 
 template <int D>
@@ -81,8 +106,12 @@ __global__ __launch_bounds__(256) void trunk_fwd_kernel(const PlanArgs a) {
     double f = anc >= 0 ? load_state(a.FA, 1 + anc, D, i) : s.rho[i];
     double* out = a.FA + (1 + beg) * D + i;
     const bool st = (D == 16) || lane < D;  // rows 1..3 store the same values as row 0
-    for (int64_t sg = a.seg_ptr[t]; sg < a.seg_ptr[t + 1]; ++sg) {
-      const Seg g = load_seg(a, sg);
+    const int64_t sg0 = a.seg_ptr[t], sg1 = a.seg_ptr[t + 1];
+    for (int64_t cb = sg0; cb < sg1; cb += SEGW) {
+    const SegLanes d = load_seg_lanes(a, cb + lane, sg1, false);
+    const int n = (int)(sg1 - cb < SEGW ? sg1 - cb : SEGW);
+    for (int x = 0; x < n; ++x) {
+      const Seg g = seg_of(d, x);
       double* o = out + (int64_t)g.start * D;
       const Row16 R0 = load_row(gl + g.g0 * GATE_STRIDE);
       if (g.per == 1) {
@@ -128,6 +157,7 @@ __global__ __launch_bounds__(256) void trunk_fwd_kernel(const PlanArgs a) {
           o += 4 * D;
         }
       }
+    }
     }
   }
 }
@@ -211,7 +241,7 @@ __global__ __launch_bounds__(256) void item_kernel(const PlanArgs a) {
     GST_DE(0) GST_DE(1) GST_DE(2) GST_DE(3) GST_DE(4) GST_DE(5) GST_DE(6) GST_DE(7)
     GST_DE(8) GST_DE(9) GST_DE(10) GST_DE(11) GST_DE(12) GST_DE(13) GST_DE(14) GST_DE(15)
 #undef GST_DE
-    double b = dot16_split(dp, load_row(s.ETs + i * ROW));
+    double b = dot16(dp, load_row(s.ETs + i * ROW));
 
     // ---- reverse sweep of the rest of the word ----
     const int nb = (Lw + 15) / 16;
@@ -223,7 +253,7 @@ __global__ __launch_bounds__(256) void item_kernel(const PlanArgs a) {
     const int x = t0 + R;                                                 \
     const int k = bcast_i32<R>(kv);                                       \
     if (x < L && i < D) ba[(int64_t)x * D + i] = b;                       \
-    const double bn = dot16_split(b, load_row(s.GTs + k * GATE_STRIDE + i * ROW)); \
+    const double bn = dot16(b, load_row(s.GTs + k * GATE_STRIDE + i * ROW)); \
     b = x < L ? bn : b;                                                   \
   }
       GST_IB(15) GST_IB(14) GST_IB(13) GST_IB(12) GST_IB(11) GST_IB(10) GST_IB(9) GST_IB(8)
@@ -257,6 +287,7 @@ __global__ __launch_bounds__(256) void trunk_bwd_kernel(const PlanArgs a) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, i = lane & 15;
   stage_gateset<D>(s, a.G, a.E, a.rho, K, a.M);
   const double* gl = s.GTs + i * ROW;
+  double* inj_st = lds_raw + trunk_head_doubles(K) + (size_t)wave * SEGW * 16;
   double drho = 0.0;
   for (int64_t t = a.t_begin + (int64_t)blockIdx.x * WAVES + wave; t < a.t_end; t += (int64_t)gridDim.x * WAVES) {
     const int64_t beg = a.trunk_ptr[t];
@@ -264,25 +295,30 @@ __global__ __launch_bounds__(256) void trunk_bwd_kernel(const PlanArgs a) {
     const bool st = (D == 16) || lane < D;
     const int64_t sg0 = a.seg_ptr[t], sg1 = a.seg_ptr[t + 1];
     double b = 0.0;
-    // injected vector of the segment about to run, loaded one segment ahead
-    double cv = 0.0;
-    if (sg1 > sg0) {
-      const int64_t slot = a.seg_inj[sg1 - 1];
-      cv = (slot >= 0 && i < D) ? a.inj[slot * D + i] : 0.0;
-    }
 #define GST_TBSTEP(RT, J)                    \
   {                                          \
     if (st) ba[(int64_t)(J) * D] = b;        \
-    b = dot16_split(b, RT);                  \
+    b = dot16(b, RT);                  \
   }
-    for (int64_t sg = sg1 - 1; sg >= sg0; --sg) {
-      const Seg g = load_seg(a, sg);
-      double nv = 0.0;
-      if (sg > sg0) {
-        const int64_t slot = a.seg_inj[sg - 1];
-        nv = (slot >= 0 && i < D) ? a.inj[slot * D + i] : 0.0;
-      }
-      b += cv;  // adjoint arriving at the state after the segment's last step
+    // segments in reverse, 64 at a time: their descriptors in registers and
+    // their injected vectors (the adjoint arriving at the state after each
+    // segment's last step) staged in this wave's LDS, all loaded up front
+    for (int64_t ce = sg1; ce > sg0; ce -= SEGW) {
+    const int64_t cb = ce - SEGW > sg0 ? ce - SEGW : sg0;
+    const int n = (int)(ce - cb);
+    const SegLanes d = load_seg_lanes(a, cb + lane, ce, true);
+    wave_sync();  // the previous chunk's vectors have been read
+#pragma unroll 4
+    for (int q = 0; q < SEGW / 4; ++q) {
+      const int x = 4 * q + (lane >> 4);
+      const int64_t slot = __shfl(d.slot, x);
+      const double v = (x < n && slot >= 0 && i < D) ? a.inj[slot * D + i] : 0.0;
+      inj_st[x * 16 + i] = v;
+    }
+    wave_sync();
+    for (int x = n - 1; x >= 0; --x) {
+      const Seg g = seg_of(d, x);
+      b += inj_st[x * 16 + i];  // adjoint arriving at the state after the segment's last step
       const Row16 R0 = load_row(gl + g.g0 * GATE_STRIDE);
       if (g.per == 1) {
         for (int c = g.count - 1; c >= 0; --c) GST_TBSTEP(R0, g.start + c)
@@ -314,7 +350,7 @@ __global__ __launch_bounds__(256) void trunk_bwd_kernel(const PlanArgs a) {
           GST_TBSTEP(R0, j0)
         }
       }
-      cv = nv;
+    }
     }
 #undef GST_TBSTEP
     if (lane < D) a.trunk_adj[t * D + i] = b;
@@ -408,7 +444,7 @@ __global__ __launch_bounds__(256) void grad_gemm_kernel(const GemmLaunch a) {
 int item_blocks_for(int64_t n_items) {
   int64_t b = (n_items + WAVES * TPW - 1) / (WAVES * TPW);
   if (b < 1) b = 1;
-  if (b > 256) b = 256;
+  if (b > 512) b = 512;  // two resident workgroups per CU
   return (int)b;
 }
 
