@@ -522,21 +522,45 @@ int run_plan(gst_req* r, const gst_gateset* th, int mode, const double* w, doubl
   const int D = r->D;
   const bool want_grad = grad != nullptr;
   const bool need_slab = want_grad || mode == gst::MODE_LOGLIK;
-  const int64_t Pw = gst::slab_width(D, r->M, r->K);
+  // head rows [objective | dL/drho | dL/dE] from the item and trunk-backward
+  // workgroups; one D x D tile per gradient chunk
+  const int64_t H = gst::slab_width(D, r->M, 0);
+  const int64_t Pw = want_grad ? gst::slab_width(D, r->M, r->K) : H;
   const int item_blocks = gst::item_blocks_for(P.n_items());
   std::vector<int> tb_blocks(P.n_levels), tb_at(P.n_levels);
-  int n_slabs = need_slab ? item_blocks + (want_grad ? (int)P.n_chunks() : 0) : 0;
+  int n_head = need_slab ? item_blocks : 0;
   for (int l = 0; l < P.n_levels; ++l) {
     tb_blocks[l] = gst::trunk_blocks_for(P.trunk_level_ptr[l + 1] - P.trunk_level_ptr[l]);
-    tb_at[l] = n_slabs;
-    if (want_grad) n_slabs += tb_blocks[l];
+    tb_at[l] = n_head;
+    if (want_grad) n_head += tb_blocks[l];
   }
-  const size_t slab_bytes = (size_t)n_slabs * Pw * 8;
-  const size_t part_bytes = need_slab ? (size_t)gst::reduce_parts(n_slabs) * Pw * 8 : 0;
-  int rc = r->ws.reserve(slab_bytes + part_bytes + 256, ctx->stream);
+  const int64_t n_chunks = want_grad ? P.n_chunks() : 0;
+  gst::PlanReduce red{};
+  red.D = D;
+  red.M = r->M;
+  red.K = want_grad ? r->K : 0;
+  red.n_head = n_head;
+  red.P = Pw;
+  red.n_part = gst::reduce_parts(n_head);
+  for (int k = 0; k <= red.K; ++k) {
+    red.chunk_ptr[k] = std::lower_bound(P.chunk_gate.begin(), P.chunk_gate.end(), (int64_t)k) - P.chunk_gate.begin();
+    if (k > 0) {
+      const int64_t nk = red.chunk_ptr[k] - red.chunk_ptr[k - 1];
+      red.n_part = std::max(red.n_part, gst::reduce_parts((int)std::min<int64_t>(nk, 1 << 20)));
+    }
+  }
+  const size_t head_bytes = (size_t)n_head * H * 8, tile_bytes = (size_t)n_chunks * D * D * 8;
+  const size_t part_bytes = need_slab ? (size_t)red.n_part * Pw * 8 : 0;
+  int rc = r->ws.reserve(head_bytes + tile_bytes + part_bytes + 256, ctx->stream);
   if (rc) return rc;
   double* slab = reinterpret_cast<double*>(r->ws.p);
-  double* part = reinterpret_cast<double*>((char*)r->ws.p + slab_bytes);
+  double* tiles = reinterpret_cast<double*>((char*)r->ws.p + head_bytes);
+  double* part = reinterpret_cast<double*>((char*)r->ws.p + head_bytes + tile_bytes);
+  red.head = slab;
+  red.tiles = tiles;
+  red.part = part;
+  red.objective = objective;
+  red.grad = grad;
 
   gst::PlanArgs a{};
   a.D = D;
@@ -603,7 +627,7 @@ int run_plan(gst_req* r, const gst_gateset* th, int mode, const double* w, doubl
       }
       a.t_begin = P.trunk_level_ptr[l];
       a.t_end = P.trunk_level_ptr[l + 1];
-      a.slab = slab + (size_t)tb_at[l] * Pw;
+      a.slab = slab + (size_t)tb_at[l] * H;
       ProfScope ps(ctx, FAM_TRUNK_BWD);
       HIP_TRY(gst::launch_trunk_bwd(a, ctx->stream));
     }
@@ -619,13 +643,13 @@ int run_plan(gst_req* r, const gst_gateset* th, int mode, const double* w, doubl
     g.rec_f = d.rec_f;
     g.FA = d.FA;
     g.BA = d.BA;
-    g.slab = slab + (size_t)item_blocks * Pw;
+    g.tiles = tiles;
     ProfScope ps(ctx, FAM_GEMM);
     HIP_TRY(gst::launch_grad_gemm(g, ctx->stream));
   }
   if (need_slab) {
     ProfScope ps(ctx, FAM_REDUCE);
-    HIP_TRY(gst::launch_reduce(slab, n_slabs, Pw, objective, grad, nullptr, D, part, ctx->stream));
+    HIP_TRY(gst::launch_reduce_plan(red, ctx->stream));
   }
   return GST_OK;
 }

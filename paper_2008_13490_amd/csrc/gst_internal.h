@@ -78,7 +78,7 @@ struct PlanArgs {
   double* FA;
   double* BA;
   const double* inj;             // [n_inj][D]
-  double* slab;
+  double* slab;                  // [blocks][1 + D + M*D]: objective, dL/drho, dL/dE
   unsigned long long* status;
   unsigned long long* req_nonpos;  // optional per-request count of p <= 0 with N > 0
 };
@@ -107,7 +107,26 @@ struct GemmLaunch {
   const int64_t* rec_f;
   const double* FA;
   const double* BA;
-  double* slab;  // [n_chunks][P]
+  double* tiles;  // [n_chunks][D*D]: the chunk's contribution to its gate's gradient tile
+};
+
+// Ordered sum of the sharing plan's partial results.  Head rows hold
+// [objective | dL/drho | dL/dE] (width H = 1 + D + M*D); each gradient chunk
+// holds one D x D tile of gate chunk_gate, the chunks of gate k being rows
+// chunk_ptr[k] .. chunk_ptr[k+1] of `tiles`.  Output column x of the width
+// P = H + K*D*D result (0: objective, x >= 1: grad[x-1]) adds the rows of its
+// own region in two fixed stages.  `part` holds n_part * P doubles.
+struct PlanReduce {
+  int D, M, K;
+  int n_head;
+  const double* head;
+  const double* tiles;
+  int64_t chunk_ptr[9];  // K + 1 entries; K <= max_gates_for(D) <= 8
+  int64_t P;
+  int n_part;  // reduce_parts of the largest region
+  double* part;
+  double* objective;
+  double* grad;
 };
 
 // Batched evaluation of many requests (persistent kernel, tile queue).
@@ -225,6 +244,7 @@ int item_blocks_for(int64_t n_items);
 int trunk_blocks_for(int64_t n_trunks);
 hipError_t launch_inject(const InjectLaunch& a, hipStream_t stream);
 hipError_t launch_grad_gemm(const GemmLaunch& a, hipStream_t stream);
+hipError_t launch_reduce_plan(const PlanReduce& a, hipStream_t stream);
 
 __host__ __device__ inline int64_t slab_width(int D, int M, int K) { return 1 + D + (int64_t)M * D + (int64_t)K * D * D; }
 

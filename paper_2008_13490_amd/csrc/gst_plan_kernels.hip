@@ -268,10 +268,8 @@ __global__ __launch_bounds__(256) void item_kernel(const PlanArgs a) {
     if (a.req_nonpos) atomicAdd(a.req_nonpos, (unsigned long long)nonpos);
   }
   if (a.mode != MODE_LOGLIK && !grad) return;
-  d4 zero[KMAX];
-#pragma unroll
-  for (int k = 0; k < KMAX; ++k) zero[k] = d4{0.0, 0.0, 0.0, 0.0};
-  write_slab<D>(lds_raw, obj, drho, dE, zero, M, K, a.slab + (int64_t)blockIdx.x * slab_width(D, M, K));
+  d4 none[KMAX];
+  write_slab<D>(lds_raw, obj, drho, dE, none, M, 0, a.slab + (int64_t)blockIdx.x * slab_width(D, M, 0));
 }
 
 // ---------------------------------------------------------------------------
@@ -361,10 +359,8 @@ __global__ __launch_bounds__(256) void trunk_bwd_kernel(const PlanArgs a) {
   double dE[16];
 #pragma unroll
   for (int m = 0; m < 16; ++m) dE[m] = 0.0;
-  d4 zero[KMAX];
-#pragma unroll
-  for (int k = 0; k < KMAX; ++k) zero[k] = d4{0.0, 0.0, 0.0, 0.0};
-  write_slab<D>(lds_raw, 0.0, drho, dE, zero, a.M, K, a.slab + (int64_t)blockIdx.x * slab_width(D, a.M, K));
+  d4 none[KMAX];
+  write_slab<D>(lds_raw, 0.0, drho, dE, none, a.M, 0, a.slab + (int64_t)blockIdx.x * slab_width(D, a.M, 0));
 }
 
 // One wave per injection slot: four groups of 16 lanes take every fourth
@@ -426,16 +422,83 @@ __global__ __launch_bounds__(256) void grad_gemm_kernel(const GemmLaunch a) {
 #pragma unroll
   for (int v = 0; v < 4; ++v) tile[wave][(4 * v + (lane >> 4)) * 16 + (lane & 15)] = acc[v];
   __syncthreads();
-  const int64_t P = slab_width(D, a.M, a.K);
-  double* out = a.slab + c * P;
-  const int64_t g0 = 1 + D + (int64_t)a.M * D + (int64_t)k * D * D;
-  for (int64_t x = tid; x < P; x += blockDim.x) {
-    double v = 0.0;
-    if (x >= g0 && x < g0 + D * D) {
-      const int y = (int)(x - g0), r = y / D, cc = y % D;
-      v = (tile[0][r * 16 + cc] + tile[1][r * 16 + cc]) + (tile[2][r * 16 + cc] + tile[3][r * 16 + cc]);
-    }
-    out[x] = v;
+  if (tid < D * D) {
+    const int r = tid / D, cc = tid % D;
+    a.tiles[c * D * D + tid] =
+        (tile[0][r * 16 + cc] + tile[1][r * 16 + cc]) + (tile[2][r * 16 + cc] + tile[3][r * 16 + cc]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// ordered sum of head rows and per-gate chunk tiles (two stages, fixed order)
+// ---------------------------------------------------------------------------
+struct Rows {
+  const double* src;  // row 0, this column
+  int64_t stride;
+  int64_t n;
+};
+
+__device__ inline int parts_of(int64_t n) {
+  const int64_t g = (n + 15) / 16;
+  return g < 1 ? 1 : (g > 64 ? 64 : (int)g);
+}
+
+__device__ inline Rows rows_of(const PlanReduce& a, int64_t x) {
+  const int64_t H = 1 + a.D + (int64_t)a.M * a.D, DD = (int64_t)a.D * a.D;
+  if (x < H) return Rows{a.head + x, H, a.n_head};
+  const int64_t y = x - H, k = y / DD;
+  const int64_t c0 = a.chunk_ptr[k], c1 = a.chunk_ptr[k + 1];
+  return Rows{a.tiles + c0 * DD + (y - k * DD), DD, c1 - c0};
+}
+
+// Block (x, g): rows [g*per, (g+1)*per) of each column's region, four
+// interleaved partial sums combined in a fixed order.
+__global__ __launch_bounds__(256) void plan_reduce_stage1(const PlanReduce a) {
+  __shared__ double red[4][64];
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  const int64_t x = (int64_t)blockIdx.x * 64 + tx;
+  const int g = blockIdx.y;
+  double v = 0.0;
+  int G = 0;
+  if (x < a.P) {
+    const Rows R = rows_of(a, x);
+    G = parts_of(R.n);
+    const int64_t per = (R.n + G - 1) / G, w0 = g * per, w1 = min(R.n, w0 + per);
+    if (g < G)
+      for (int64_t w = w0 + ty; w < w1; w += 4) v += R.src[w * R.stride];
+  }
+  red[ty][tx] = v;
+  __syncthreads();
+  if (ty == 0 && x < a.P && g < G) a.part[(int64_t)g * a.P + x] = (red[0][tx] + red[1][tx]) + (red[2][tx] + red[3][tx]);
+}
+
+// Column x adds its region's stage-1 partials in ascending g.  A +inf
+// objective partial marks p <= 0 with N > 0: the objective is then +inf and
+// the gradient is not written.
+__global__ __launch_bounds__(256) void plan_reduce_stage2(const PlanReduce a) {
+  __shared__ double red[4][64];
+  __shared__ int nonpos_sh;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  const int64_t x = (int64_t)blockIdx.x * 64 + tx;
+  double v = 0.0;
+  if (x < a.P) {
+    const int G = parts_of(rows_of(a, x).n);
+    for (int g = ty; g < G; g += 4) v += a.part[(int64_t)g * a.P + x];
+  }
+  red[ty][tx] = v;
+  if (ty == 1) {
+    const bool inf = tx < parts_of(a.n_head) && isinf(a.part[(int64_t)tx * a.P]);
+    const bool any = __ballot(inf) != 0ull;
+    if (tx == 0) nonpos_sh = any ? 1 : 0;
+  }
+  __syncthreads();
+  const bool nonpos = nonpos_sh != 0;
+  if (ty != 0 || x >= a.P) return;
+  v = (red[0][tx] + red[1][tx]) + (red[2][tx] + red[3][tx]);
+  if (x == 0) {
+    if (a.objective) *a.objective = nonpos ? INFINITY : v;
+  } else if (a.grad && !nonpos) {
+    a.grad[x - 1] = v;
   }
 }
 
@@ -493,6 +556,14 @@ hipError_t launch_inject(const InjectLaunch& a, hipStream_t stream) {
   if (n <= 0) return hipSuccess;
   const int blocks = (int)(n < 65536 ? n : 65536);
   hipLaunchKernelGGL(inject_kernel, dim3(blocks), dim3(64), 0, stream, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_plan(const PlanReduce& a, hipStream_t stream) {
+  if (a.P <= 0 || a.n_part < 1 || a.n_part > 64 || a.K < 0 || a.K > 8) return hipErrorInvalidValue;
+  const unsigned xb = (unsigned)((a.P + 63) / 64);
+  hipLaunchKernelGGL(plan_reduce_stage1, dim3(xb, (unsigned)a.n_part), dim3(256), 0, stream, a);
+  hipLaunchKernelGGL(plan_reduce_stage2, dim3(xb), dim3(256), 0, stream, a);
   return hipGetLastError();
 }
 
