@@ -324,7 +324,7 @@ def run_structured(args):
                                               ctypes.byref(seqs.as_struct()), api._ptr(counts), None,
                                               api._ptr(obj), api._ptr(grad)))
 
-    families = ("leaf", "reduce", "trunk_fwd", "trunk_bwd", "inject", "grad_gemm", "tiles_2q", "tiles_1q",
+    families = ("leaf", "reduce", "trunk_fwd", "trunk_bwd", "inject", "grad_gemm", "fill", "tiles_2q", "tiles_1q",
                 "tiles_reduce", "chain_3q", "gemm_3q", "reduce_3q")
     for _ in range(args.warmup):
         step()
@@ -501,10 +501,8 @@ def algorithmic_flops(family, D, M, S, sum_len, info):
     ts, its, lv = info["trunk_steps"], info["item_steps"], max(1, info["levels"])
     if family == "leaf":   # items: forward + adjoint mat-vecs, readout, seed, dE
         return 4.0 * D * D * its + 6.0 * D * M * S
-    if family == "trunk_fwd":
-        return 2.0 * D * D * ts / lv
-    if family == "trunk_bwd":
-        return 2.0 * D * D * ts / lv
+    if family in ("trunk_fwd", "trunk_bwd"):   # the chain's mat-vecs (a germ-power jump counts once)
+        return 2.0 * D * D * info.get("chain_steps", ts) / lv
     if family == "grad_gemm":
         return 2.0 * D * D * (ts + its)
     return 0.0

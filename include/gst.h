@@ -149,7 +149,9 @@ int gst_req_vjp(gst_req* req, const gst_gateset* theta, const double* w, double*
 int gst_req_destroy(gst_req* req);
 /* Sharing-plan statistics of a request (diagnostics): info[0..n) receives
    {plan used (0/1), total steps of the plain evaluation, trie nodes, trunks,
-    trunk steps, item steps, trunk levels, injection slots}. */
+    trunk steps, item steps, trunk levels, injection slots, chain mat-vecs of
+    the trunks (jumps counted once), longest trunk chain, trunks with jumps,
+    fill tasks}; n <= 12. */
 int gst_req_plan_info(const gst_req* req, int64_t* info, int n);
 
 /*
@@ -193,12 +195,28 @@ int gst_batch_destroy(gst_batch* batch);
 int gst_tune_set(gst_ctx* ctx, int n_qubits, int seqs_per_tile, int blocks_per_cu);
 
 /*
+ * Germ-power jumps of the sharing plan, for requests created afterwards on
+ * this context.  Germ-power sequences (thesis Eq. GSTFullFiducialsGerms) put
+ * long runs of one repeated germ on a trunk.  With reps > 0 the trunk chain
+ * applies such a run `reps` repetitions at a time with the matrix power of
+ * the germ (built per evaluation in LDS by repeated squaring), and independent
+ * fill tasks compute the states and adjoints inside each jump; this shortens
+ * the sequential chain several times over.  The states after a jump carry the
+ * rounding of the matrix products, so probabilities agree with the plain
+ * evaluation to rounding (a few 1e-13 relative on the germ-power lists)
+ * instead of bit for bit.  reps = 0 turns jumps off (bit-identical
+ * probabilities); otherwise a power of two from 2 to 16.  Default 8.
+ */
+int gst_set_plan_jump(gst_ctx* ctx, int reps);
+
+/*
  * Kernel timing (diagnostics).  While enabled, every kernel the context
  * enqueues is bracketed by two HIP events recorded on the context's stream.
  * gst_profile_read synchronizes the stream and returns, for the kernel family
  * `kernel` ("leaf", "reduce", "trunk_fwd", "trunk_bwd", "inject",
- * "grad_gemm", "tiles_2q", "tiles_1q", "tiles_reduce", or "batch" for a
- * whole gst_batch_run), the summed
+ * "grad_gemm", "fill", "tiles_2q", "tiles_1q", "tiles_reduce",
+ * "chain_3q", "gemm_3q", "reduce_3q", or "batch" for a whole
+ * gst_batch_run), the summed
  * elapsed milliseconds and the number of launches since profiling was
  * enabled; the counters are not reset by reading.
  */

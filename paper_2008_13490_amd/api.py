@@ -183,9 +183,10 @@ class Request:
         self.n_params = 4 ** n_qubits * (1 + n_outcomes) + n_gates * 16 ** n_qubits
 
     def plan_info(self) -> dict:
-        v = (ctypes.c_int64 * 8)()
-        _lib.check(self.lib.gst_req_plan_info(self.handle, v, 8))
-        keys = ["plan_used", "sum_len", "trie_nodes", "trunks", "trunk_steps", "item_steps", "levels", "inj_slots"]
+        v = (ctypes.c_int64 * 12)()
+        _lib.check(self.lib.gst_req_plan_info(self.handle, v, 12))
+        keys = ["plan_used", "sum_len", "trie_nodes", "trunks", "trunk_steps", "item_steps", "levels", "inj_slots",
+                "chain_steps", "chain_max", "jump_trunks", "fill_tasks"]
         return dict(zip(keys, [int(x) for x in v]))
 
     def footprint(self) -> int:
@@ -271,6 +272,13 @@ class Batch:
 def tune_set(ctx: Context, n_qubits: int, seqs_per_tile: int = 0, blocks_per_cu: int = 0):
     """Tile policy for requests created afterwards on ``ctx`` (``gst_tune_set``)."""
     _lib.check(ctx.lib.gst_tune_set(ctx.handle, n_qubits, seqs_per_tile, blocks_per_cu))
+
+
+def set_plan_jump(ctx: Context, reps: int):
+    """Germ-power jump repetitions of the sharing plans of requests created
+    afterwards on ``ctx`` (``gst_set_plan_jump``; 0 = off, bit-identical
+    probabilities)."""
+    _lib.check(ctx.lib.gst_set_plan_jump(ctx.handle, int(reps)))
 
 
 def profile_only(ctx: Context, family: Optional[str] = None):

@@ -92,11 +92,11 @@ struct Profiler {
 
 enum Family { FAM_LEAF = 0, FAM_REDUCE = 1, FAM_TRUNK_FWD = 2, FAM_TRUNK_BWD = 3, FAM_INJECT = 4, FAM_GEMM = 5,
               FAM_BATCH = 6, FAM_TILES16 = 7, FAM_TILES4 = 8, FAM_TILES_RED = 9, FAM_CHAIN64 = 10,
-              FAM_GEMM64 = 11, FAM_REDUCE64 = 12, FAM_N = 13 };
+              FAM_GEMM64 = 11, FAM_REDUCE64 = 12, FAM_FILL = 13, FAM_N = 14 };
 static_assert(FAM_N <= Profiler::kMaxFamilies, "profiler arrays too small");
 static const char* kFamilyNames[FAM_N] = {"leaf",  "reduce",  "trunk_fwd", "trunk_bwd",   "inject",
                                           "grad_gemm", "batch", "tiles_2q",  "tiles_1q", "tiles_reduce",
-                                          "chain_3q",  "gemm_3q", "reduce_3q"};
+                                          "chain_3q",  "gemm_3q", "reduce_3q", "fill"};
 
 // Carve consecutive aligned regions out of one allocation.
 struct Carver {
@@ -115,6 +115,7 @@ struct gst_ctx {
   int n_cu = 0;
   int tune_tile[4] = {0, 0, 0, 0};  // sequences per tile by qubit count (0 = default)
   int tune_bpc[4] = {0, 0, 0, 0};   // workgroups per CU by qubit count (0 = as many as fit)
+  int plan_jump = gst::PlanOptions().jump;  // germ-power jump repetitions of new plans (0 = none)
   hipStream_t stream = nullptr;
   unsigned long long* status = nullptr;  // device [2]
   DevBuf ws;
@@ -178,6 +179,14 @@ struct DevicePlan {
   double* item_adj = nullptr;   // [n_items][D]
   double* trunk_adj = nullptr;  // [n_trunks][D]
   double* inj = nullptr;        // [n_inj][D]
+  // germ-power jumps: each trunk's jump pattern, and the fill tasks
+  uint32_t* trunk_jpat = nullptr;
+  uint8_t* trunk_jg3 = nullptr;
+  int64_t* fill_first = nullptr;
+  int64_t* fill_in = nullptr;
+  int32_t* fill_n = nullptr;
+  uint32_t* fill_pattern = nullptr;
+  uint8_t* fill_gate3 = nullptr;
 };
 
 // Sequences per batch tile: a request's sequences, sorted by length, are cut
@@ -442,6 +451,10 @@ int upload_plan(gst_req* r, const gst::HostPlan& P) {
                o_fa = c.take<double>((size_t)(1 + nTS + nIS) * D), o_ba = c.take<double>((size_t)(nTS + nIS + 1) * D),
                o_ia = c.take<double>((size_t)(nI + 1) * D), o_tad = c.take<double>((size_t)(nT + 1) * D),
                o_inj = c.take<double>((size_t)(nJ + 1) * D);
+  const size_t nF = P.fill_first.size();
+  const size_t o_jp = c.take<uint32_t>(nT + 1), o_jg3 = c.take<uint8_t>(nT + 1), o_ff = c.take<int64_t>(nF + 1),
+               o_fi = c.take<int64_t>(nF + 1), o_fn = c.take<int32_t>(nF + 1), o_fp = c.take<uint32_t>(nF + 1),
+               o_fg3 = c.take<uint8_t>(nF + 1);
   int rc = d.buf.reserve(c.off + 256, r->ctx->stream);
   if (rc) return rc;
   char* b = reinterpret_cast<char*>(d.buf.p);
@@ -472,6 +485,13 @@ int upload_plan(gst_req* r, const gst::HostPlan& P) {
   d.item_adj = reinterpret_cast<double*>(b + o_ia);
   d.trunk_adj = reinterpret_cast<double*>(b + o_tad);
   d.inj = reinterpret_cast<double*>(b + o_inj);
+  d.trunk_jpat = reinterpret_cast<uint32_t*>(b + o_jp);
+  d.trunk_jg3 = reinterpret_cast<uint8_t*>(b + o_jg3);
+  d.fill_first = reinterpret_cast<int64_t*>(b + o_ff);
+  d.fill_in = reinterpret_cast<int64_t*>(b + o_fi);
+  d.fill_n = reinterpret_cast<int32_t*>(b + o_fn);
+  d.fill_pattern = reinterpret_cast<uint32_t*>(b + o_fp);
+  d.fill_gate3 = reinterpret_cast<uint8_t*>(b + o_fg3);
   auto put = [&](void* dst, const void* src, size_t bytes) -> int {
     if (bytes) HIP_TRY(hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice));
     return GST_OK;
@@ -498,6 +518,13 @@ int upload_plan(gst_req* r, const gst::HostPlan& P) {
   if ((rc = put(d.chunk_gate, P.chunk_gate.data(), P.chunk_gate.size() * 8))) return rc;
   if ((rc = put(d.chunk_beg, P.chunk_beg.data(), P.chunk_beg.size() * 8))) return rc;
   if ((rc = put(d.chunk_end, P.chunk_end.data(), P.chunk_end.size() * 8))) return rc;
+  if ((rc = put(d.trunk_jpat, P.trunk_jump_pattern.data(), P.trunk_jump_pattern.size() * 4))) return rc;
+  if ((rc = put(d.trunk_jg3, P.trunk_jump_gate3.data(), P.trunk_jump_gate3.size()))) return rc;
+  if ((rc = put(d.fill_first, P.fill_first.data(), nF * 8))) return rc;
+  if ((rc = put(d.fill_in, P.fill_in.data(), nF * 8))) return rc;
+  if ((rc = put(d.fill_n, P.fill_n.data(), nF * 4))) return rc;
+  if ((rc = put(d.fill_pattern, P.fill_pattern.data(), nF * 4))) return rc;
+  if ((rc = put(d.fill_gate3, P.fill_gate3.data(), nF))) return rc;
   // injection slots of each level: slots of stored locations are sorted by
   // location (the root slot comes last) and a level's locations are contiguous
   d.inj_level_ptr.assign(P.n_levels + 1, 0);
@@ -600,13 +627,23 @@ int run_plan(gst_req* r, const gst_gateset* th, int mode, const double* w, doubl
   a.slab = slab;
   a.status = ctx->status;
   a.req_nonpos = req_nonpos;
+  a.trunk_jpat = d.trunk_jpat;
+  a.trunk_jg3 = d.trunk_jg3;
+  a.jump_levels = P.jump_levels;
+  a.item_blocks = item_blocks;
+  a.n_fill = P.n_fill();
+  a.fill_first = d.fill_first;
+  a.fill_in = d.fill_in;
+  a.fill_n = d.fill_n;
+  a.fill_pattern = d.fill_pattern;
+  a.fill_gate3 = d.fill_gate3;
   for (int l = 0; l < P.n_levels; ++l) {
     a.t_begin = P.trunk_level_ptr[l];
     a.t_end = P.trunk_level_ptr[l + 1];
     ProfScope ps(ctx, FAM_TRUNK_FWD);
     HIP_TRY(gst::launch_trunk_fwd(a, ctx->stream));
   }
-  {
+  {  // with the gradient, extra workgroups fill the states inside the jumps
     ProfScope ps(ctx, FAM_LEAF);
     HIP_TRY(gst::launch_items(a, item_blocks, ctx->stream));
   }
@@ -630,6 +667,10 @@ int run_plan(gst_req* r, const gst_gateset* th, int mode, const double* w, doubl
       a.slab = slab + (size_t)tb_at[l] * H;
       ProfScope ps(ctx, FAM_TRUNK_BWD);
       HIP_TRY(gst::launch_trunk_bwd(a, ctx->stream));
+    }
+    if (a.n_fill > 0) {
+      ProfScope ps(ctx, FAM_FILL);
+      HIP_TRY(gst::launch_fill_rev(a, ctx->stream));
     }
     gst::GemmLaunch g{};
     g.D = D;
@@ -738,6 +779,14 @@ int gst_tune_set(gst_ctx* ctx, int n_qubits, int seqs_per_tile, int blocks_per_c
     return fail(GST_EINVAL, "tile policy out of range");
   ctx->tune_tile[n_qubits] = seqs_per_tile;
   ctx->tune_bpc[n_qubits] = blocks_per_cu;
+  return GST_OK;
+}
+
+int gst_set_plan_jump(gst_ctx* ctx, int reps) {
+  if (!ctx) return fail(GST_EINVAL, "ctx is NULL");
+  if (reps != 0 && (reps < 2 || reps > 16 || (reps & (reps - 1)) != 0))
+    return fail(GST_EINVAL, "jump repetitions must be 0 or a power of two from 2 to 16");
+  ctx->plan_jump = reps;
   return GST_OK;
 }
 
@@ -913,6 +962,7 @@ int gst_req_create_host(gst_ctx* ctx, int n_qubits, int n_gates, int n_outcomes,
   if (S > 0 && D <= 16) {
     gst::HostPlan hp;
     gst::PlanOptions opt;
+    opt.jump = ctx->plan_jump;
     if (gst::build_plan(sl->offsets, sl->gate_idx, S, n_gates, opt, &hp)) {
       rc = upload_plan(r.get(), hp);
       if (rc) return rc;
@@ -1308,9 +1358,20 @@ int gst_batch_destroy(gst_batch* b) {
 int gst_req_plan_info(const gst_req* req, int64_t* info, int n) {
   if (!req || !info || n < 1) return fail(GST_EINVAL, "NULL argument");
   const gst::HostPlan& P = req->plan.host;
-  int64_t vals[8] = {req->plan.used ? 1 : 0, P.sum_len, P.n_nodes, P.n_trunks(), P.trunk_steps(),
-                     P.item_steps(), P.n_levels, (int64_t)P.inj_loc.size()};
-  for (int x = 0; x < n && x < 8; ++x) info[x] = vals[x];
+  int64_t chain = 0, chain_max = 0;
+  for (int64_t t = 0; t < P.n_trunks(); ++t) {
+    int64_t c = 0;
+    for (int64_t sg = P.seg_ptr[t]; sg < P.seg_ptr[t + 1]; ++sg) {
+      const int per = (int)(P.seg_pattern[sg] & 0xffu);
+      c += (int64_t)P.seg_count[sg] * (per == 0 ? 1 : per);
+    }
+    chain += c;
+    chain_max = std::max(chain_max, c);
+  }
+  int64_t vals[12] = {req->plan.used ? 1 : 0, P.sum_len, P.n_nodes, P.n_trunks(), P.trunk_steps(),
+                      P.item_steps(), P.n_levels, (int64_t)P.inj_loc.size(), chain, chain_max,
+                      P.n_jump_trunks(), P.n_fill()};
+  for (int x = 0; x < n && x < 12; ++x) info[x] = vals[x];
   return GST_OK;
 }
 

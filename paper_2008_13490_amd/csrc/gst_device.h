@@ -131,6 +131,21 @@ __device__ __forceinline__ __attribute__((address_space(1))) T* as_global(T* p) 
   return (__attribute__((address_space(1))) T*)p;
 }
 
+// 16 consecutive doubles of global memory (16-byte aligned) as a Row16.
+__device__ __forceinline__ Row16 load_row_global(const double* p) {
+  const auto* q = as_global(p);
+  Row16 R;
+  R.a0 = double2{q[0], q[1]};
+  R.a1 = double2{q[2], q[3]};
+  R.a2 = double2{q[4], q[5]};
+  R.a3 = double2{q[6], q[7]};
+  R.a4 = double2{q[8], q[9]};
+  R.a5 = double2{q[10], q[11]};
+  R.a6 = double2{q[12], q[13]};
+  R.a7 = double2{q[14], q[15]};
+  return R;
+}
+
 // max over the four 16-lane rows of a wave, as a wave-uniform value
 __device__ __forceinline__ int wave_max4(int v) {
   v = max(v, __shfl_xor(v, 16));

@@ -81,6 +81,19 @@ struct PlanArgs {
   double* slab;                  // [blocks][1 + D + M*D]: objective, dL/drho, dL/dE
   unsigned long long* status;
   unsigned long long* req_nonpos;  // optional per-request count of p <= 0 with N > 0
+  // germ-power jumps (segments of period 0): each trunk's jump pattern (0 =
+  // none), whose product powers the trunk kernels build in LDS
+  const uint32_t* trunk_jpat;
+  const uint8_t* trunk_jg3;
+  int jump_levels;
+  int item_blocks;               // item workgroups; the item launch adds the forward fill workgroups
+  // fill tasks: states (forward) or adjoints (reverse) inside each jump
+  int64_t n_fill;
+  const int64_t* fill_first;
+  const int64_t* fill_in;
+  const int32_t* fill_n;
+  const uint32_t* fill_pattern;
+  const uint8_t* fill_gate3;
 };
 
 // inj[slot] = sum over its sources (ascending): item adjoints (src >= 0) and
@@ -245,6 +258,9 @@ int trunk_blocks_for(int64_t n_trunks);
 hipError_t launch_inject(const InjectLaunch& a, hipStream_t stream);
 hipError_t launch_grad_gemm(const GemmLaunch& a, hipStream_t stream);
 hipError_t launch_reduce_plan(const PlanReduce& a, hipStream_t stream);
+// reverse fill tasks (adjoints inside the jumps into BA)
+hipError_t launch_fill_rev(const PlanArgs& a, hipStream_t stream);
+int fill_blocks_for(int64_t n_fill);
 
 __host__ __device__ inline int64_t slab_width(int D, int M, int K) { return 1 + D + (int64_t)M * D + (int64_t)K * D * D; }
 

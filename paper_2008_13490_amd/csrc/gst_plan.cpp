@@ -239,12 +239,34 @@ bool build_plan(const int64_t* off, const uint8_t* gates, int64_t S, int K, cons
   // past a step whose resulting state receives an injection, so injections
   // happen only at segment ends ----
   P.seg_ptr.assign(nT + 1, 0);
+  const int B = opt.jump;
+  const bool jump_on = B >= 2 && B <= 16 && (B & (B - 1)) == 0;
+  int lb = 0;
+  while (jump_on && (1 << lb) < B) ++lb;
+  P.jump_levels = jump_on ? lb + 1 : 0;
+  P.trunk_jump_pattern.assign(nT, 0);
+  P.trunk_jump_gate3.assign(nT, 0);
+  struct Run {
+    int64_t j, count;
+    int per;
+    uint32_t pat;
+    uint8_t g3;
+  };
+  // chain mat-vecs of a run applied with jumps: count / B jumps by the B-th
+  // power, then one jump per set bit of the remainder (a one-gate pattern
+  // takes its last single repetition as an ordinary step)
+  auto chain_of = [&](const Run& u) {
+    int64_t c = u.count >> lb;
+    for (int e = 0; e < lb; ++e) c += (u.count >> e) & 1;
+    return c;
+  };
+  std::vector<Run> runs;
   for (int64_t r = 0; r < nT; ++r) {
     const int64_t base = P.trunk_ptr[r];
     const uint8_t* w = P.trunk_gates.data() + base;
     const int64_t L = P.trunk_ptr[r + 1] - base;
-    int64_t j = 0;
-    while (j < L) {
+    runs.clear();
+    for (int64_t j = 0; j < L;) {
       int64_t piece_end = j;  // last step of the injection-free piece starting at j
       while (piece_end < L - 1 && P.trunk_inj[base + piece_end] < 0) ++piece_end;
       const int64_t n = piece_end - j + 1;
@@ -260,15 +282,89 @@ bool build_plan(const int64_t* off, const uint8_t* gates, int64_t S, int K, cons
       }
       uint32_t pat = (uint32_t)bp;
       for (int q = 0; q < bp && q < 3; ++q) pat |= (uint32_t)w[j + q] << (8 * (q + 1));
-      P.seg_start.push_back((int32_t)j);
-      P.seg_count.push_back((int32_t)bc);
+      runs.push_back(Run{j, bc, bp, pat, (uint8_t)(bp == 4 ? w[j + 3] : 0)});
+      j += bp * bc;
+    }
+    // the trunk's jump pattern: the one whose qualifying runs save the most
+    // chain steps (its germ)
+    auto saves = [&](const Run& u) { return u.per * u.count - chain_of(u); };
+    uint32_t jp = 0;
+    uint8_t jg3 = 0;
+    if (jump_on) {
+      int64_t best = 0;
+      for (const Run& u : runs) {
+        if (saves(u) < opt.jump_min_save) continue;
+        int64_t tot = 0;
+        for (const Run& v : runs)
+          if (v.pat == u.pat && v.g3 == u.g3 && saves(v) >= opt.jump_min_save) tot += saves(v);
+        if (tot > best) {
+          best = tot;
+          jp = u.pat;
+          jg3 = u.g3;
+        }
+      }
+    }
+    P.trunk_jump_pattern[r] = jp;
+    P.trunk_jump_gate3[r] = jg3;
+    auto emit_plain = [&](int64_t start, int64_t count, uint32_t pat, uint8_t g3, int64_t inj) {
+      P.seg_start.push_back((int32_t)start);
+      P.seg_count.push_back((int32_t)count);
       P.seg_pattern.push_back(pat);
-      P.seg_gate3.push_back(bp == 4 ? w[j + 3] : 0);
-      const int64_t last = j + bp * bc - 1;
-      P.seg_inj.push_back(P.trunk_inj[base + last]);
-      j = last + 1;
+      P.seg_gate3.push_back(g3);
+      P.seg_inj.push_back(inj);
+    };
+    for (const Run& u : runs) {
+      const int64_t last = u.j + (int64_t)u.per * u.count - 1;
+      const int64_t inj = P.trunk_inj[base + last];
+      if (jp == 0 || u.pat != jp || u.g3 != jg3 || saves(u) < opt.jump_min_save) {
+        emit_plain(u.j, u.count, u.pat, u.g3, inj);
+        continue;
+      }
+      int64_t s = u.j;
+      auto emit_jump = [&](int e, int64_t count) {
+        const int64_t stride = ((int64_t)1 << e) * u.per;
+        P.seg_start.push_back((int32_t)s);
+        P.seg_count.push_back((int32_t)count);
+        P.seg_pattern.push_back((uint32_t)stride << 8 | (uint32_t)e << 16);
+        P.seg_gate3.push_back(0);
+        P.seg_inj.push_back(s + count * stride - 1 == last ? inj : -1);
+        for (int64_t c = 0; c < count; ++c, s += stride) {
+          if (stride < 2) continue;
+          P.fill_first.push_back(base + s);
+          P.fill_in.push_back(s == 0 ? (P.trunk_anchor[r] < 0 ? 0 : 1 + P.trunk_anchor[r]) : 1 + base + s - 1);
+          P.fill_n.push_back((int32_t)stride);
+          P.fill_pattern.push_back(u.pat);
+          P.fill_gate3.push_back(u.g3);
+        }
+      };
+      const int64_t q_full = u.count >> lb, rem = u.count & (B - 1);
+      if (q_full > 0) emit_jump(lb, q_full);
+      for (int e = lb - 1; e >= 0; --e) {
+        if (!((rem >> e) & 1)) continue;
+        if (e == 0 && u.per == 1) {  // one gate: an ordinary step
+          emit_plain(s, 1, u.pat, u.g3, s == last ? inj : -1);
+          s += 1;
+        } else {
+          emit_jump(e, 1);
+        }
+      }
     }
     P.seg_ptr[r + 1] = (int64_t)P.seg_start.size();
+  }
+  // fill tasks longest first (load balance)
+  if (!P.fill_first.empty()) {
+    std::vector<int64_t> ord(P.fill_first.size());
+    for (size_t x = 0; x < ord.size(); ++x) ord[x] = (int64_t)x;
+    std::stable_sort(ord.begin(), ord.end(), [&](int64_t x, int64_t y) { return P.fill_n[x] > P.fill_n[y]; });
+    auto perm = [&](auto& v) {
+      auto c = v;
+      for (size_t x = 0; x < ord.size(); ++x) v[x] = c[ord[x]];
+    };
+    perm(P.fill_first);
+    perm(P.fill_in);
+    perm(P.fill_n);
+    perm(P.fill_pattern);
+    perm(P.fill_gate3);
   }
 
   P.trunk_anchor_inj.assign(nT, -1);

@@ -14,9 +14,11 @@
 //     of its own word (usually the measurement fiducial);
 //   * in the reverse sweep the adjoints of the items are summed per stored
 //     state ("injections") and the trunks carry them back to rho.
-// The probabilities computed this way are the same floating-point numbers as
-// those of the plain per-sequence evaluation: the shared prefixes are the
-// same operations on the same values.
+// Without germ-power jumps the probabilities computed this way are the same
+// floating-point numbers as those of the plain per-sequence evaluation: the
+// shared prefixes are the same operations on the same values.  A jump applies
+// a matrix power of a germ instead of its gates one by one, which changes the
+// rounding of the states after it (not their value in exact arithmetic).
 #pragma once
 #include <stdint.h>
 
@@ -65,12 +67,34 @@ struct HostPlan {
   std::vector<uint32_t> seg_pattern;     // period in bits 0..7, gates in bits 8..15, 16..23, 24..31 and
   std::vector<uint8_t> seg_gate3;        // the fourth gate
   std::vector<int64_t> seg_inj;          // injection slot of the state after the segment's last step, -1 none
+  // Germ-power jumps.  A long periodic run of a trunk's jump pattern (one
+  // pattern per trunk, its germ) is applied several repetitions at a time by
+  // a power of the pattern's product matrix: a jump segment has period 0 in
+  // seg_pattern, the steps per jump in bits 8..15 and e in bits 16..23, the
+  // matrix being the pattern product to the power 2^e.  The chain then
+  // stores only the state after each jump; the states inside a jump are
+  // written by independent fill tasks that start from the stored state
+  // before it.
+  int jump_levels = 0;                   // e = 0 .. jump_levels - 1
+  std::vector<uint32_t> trunk_jump_pattern;  // [n_trunks] period and gates as in seg_pattern, 0 = no jumps
+  std::vector<uint8_t> trunk_jump_gate3;     // fourth gate of the pattern
+  std::vector<int64_t> fill_first;       // [n_fill] trunk-arena index of the task's first step
+  std::vector<int64_t> fill_in;          // state row (0 = rho, 1 + j = after trunk step j) before that step
+  std::vector<int32_t> fill_n;           // steps covered by the jump (n - 1 states are filled)
+  std::vector<uint32_t> fill_pattern;    // pattern repeated over the n steps
+  std::vector<uint8_t> fill_gate3;
   int64_t n_items() const { return (int64_t)items.size() / 4; }
   int64_t n_trunks() const { return (int64_t)trunk_anchor.size(); }
   int64_t trunk_steps() const { return (int64_t)trunk_gates.size(); }
   int64_t plan_steps() const;            // trunk steps + item steps
   int64_t item_steps() const { return item_step_ptr.empty() ? 0 : item_step_ptr.back(); }
   int64_t n_chunks() const { return (int64_t)chunk_gate.size(); }
+  int64_t n_fill() const { return (int64_t)fill_first.size(); }
+  int64_t n_jump_trunks() const {
+    int64_t n = 0;
+    for (uint32_t p : trunk_jump_pattern) n += p != 0;
+    return n;
+  }
 };
 
 struct PlanOptions {
@@ -80,6 +104,8 @@ struct PlanOptions {
   int64_t max_nodes = 1LL << 26;
   int64_t max_item_steps = 1LL << 24;   // bound on stored item-step states (memory)
   int chunk = 128;                      // gradient GEMM records per chunk (the kernel takes at most 128)
+  int jump = 8;                         // repetitions per germ-power jump (power of two, <= 16); 0 = none
+  int jump_min_save = 12;               // jump a run only if it shortens the chain by this many steps
 };
 
 // Builds the plan.  Returns false (plan unused: evaluate sequence by

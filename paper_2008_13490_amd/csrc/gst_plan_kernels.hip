@@ -48,8 +48,14 @@ __host__ __device__ inline size_t trunk_head_doubles(int K) {
   return (size_t)2 * K * GATE_STRIDE + 2 * 16 * ROW + 16;
 }
 
-__host__ __device__ inline size_t trunk_lds_bytes(int K) {
-  const size_t a = (trunk_head_doubles(K) + (size_t)WAVES * SEGW * 16) * 8 + 64;
+// Per wave after the staging area: the trunk's jump matrices, `levels` of
+// them in the gate layout.
+__host__ __device__ inline size_t trunk_jump_doubles(int K, int wave, int levels) {
+  return trunk_head_doubles(K) + (size_t)WAVES * SEGW * 16 + (size_t)wave * levels * GATE_STRIDE;
+}
+
+__host__ __device__ inline size_t trunk_lds_bytes(int K, int levels) {
+  const size_t a = trunk_jump_doubles(K, WAVES, levels) * 8 + 64;
   const size_t r = lds_red_bytes(K);
   return a > r ? a : r;
 }
@@ -91,6 +97,43 @@ __device__ __forceinline__ Seg seg_of(const SegLanes& d, int x) {
   return g;
 }
 
+// C = A B for 16 x 16 matrices in the gate layout, by one wave: column c of
+// C is A times column c of B, a dot16 per 16-lane team, four columns per team.
+__device__ __forceinline__ void wave_matmul(double* C, const double* A, const double* B, int lane) {
+  const int i = lane & 15, t = lane >> 4;
+  const Row16 Ar = load_row(A + i * ROW);
+  double y[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) y[u] = dot16(B[i * ROW + 4 * u + t], Ar);
+#pragma unroll
+  for (int u = 0; u < 4; ++u) C[i * ROW + 4 * u + t] = y[u];
+  wave_sync();
+}
+
+// The trunk's jump matrices into the wave's slots js[e * GATE_STRIDE]: slot 0
+// = G_{g_per-1} ... G_{g_0} of the pattern (reverse: its transpose G_{g_0}^T
+// ... G_{g_per-1}^T, from the transposed gate set), slot e = slot e-1 squared.
+__device__ void build_jumps(double* js, const double* gates, uint32_t pat, int g3, int levels, bool rev,
+                            int lane) {
+  const int per = (int)(pat & 0xffu);
+  const int g[4] = {(int)((pat >> 8) & 0xffu), (int)((pat >> 16) & 0xffu), (int)((pat >> 24) & 0xffu), g3};
+  const int i = lane & 15, t = lane >> 4;
+  if (per == 1) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) js[i * ROW + 4 * u + t] = gates[g[0] * GATE_STRIDE + i * ROW + 4 * u + t];
+    wave_sync();
+  } else {
+    const double* src = gates + g[rev ? per - 1 : 0] * GATE_STRIDE;
+    for (int k = 1; k < per; ++k) {  // the last product lands in slot 0
+      double* dst = js + (((per - 1 - k) & 1) ? GATE_STRIDE : 0);
+      wave_matmul(dst, gates + g[rev ? per - 1 - k : k] * GATE_STRIDE, src, lane);
+      src = dst;
+    }
+  }
+  for (int e = 1; e < levels; ++e)
+    wave_matmul(js + e * GATE_STRIDE, js + (e - 1) * GATE_STRIDE, js + (e - 1) * GATE_STRIDE, lane);
+}
+
 template <int D>
 __global__ __launch_bounds__(256) void trunk_fwd_kernel(const PlanArgs a) {
   extern __shared__ double lds_raw[];
@@ -100,9 +143,12 @@ __global__ __launch_bounds__(256) void trunk_fwd_kernel(const PlanArgs a) {
   stage_gateset<D>(s, a.G, a.E, a.rho, K, a.M);
   if (blockIdx.x == 0 && tid < D) a.FA[tid] = a.rho[tid];
   const double* gl = s.Gs + i * ROW;
+  double* js = lds_raw + trunk_jump_doubles(K, wave, a.jump_levels);
   for (int64_t t = a.t_begin + (int64_t)blockIdx.x * WAVES + wave; t < a.t_end; t += (int64_t)gridDim.x * WAVES) {
     const int64_t beg = a.trunk_ptr[t];
     const int64_t anc = a.trunk_anchor[t];
+    const uint32_t jp = (uint32_t)__builtin_amdgcn_readfirstlane((int)a.trunk_jpat[t]);
+    if (jp != 0u) build_jumps(js, s.Gs, jp, a.trunk_jg3[t], a.jump_levels, false, lane);
     double f = anc >= 0 ? load_state(a.FA, 1 + anc, D, i) : s.rho[i];
     double* out = a.FA + (1 + beg) * D + i;
     const bool st = (D == 16) || lane < D;  // rows 1..3 store the same values as row 0
@@ -112,6 +158,17 @@ __global__ __launch_bounds__(256) void trunk_fwd_kernel(const PlanArgs a) {
     const int n = (int)(sg1 - cb < SEGW ? sg1 - cb : SEGW);
     for (int x = 0; x < n; ++x) {
       const Seg g = seg_of(d, x);
+      if (g.per == 0) {  // count jumps of g.g0 steps by jump matrix g.g1; the state after each is stored
+        const Row16 RC = load_row(js + g.g1 * GATE_STRIDE + i * ROW);
+        const int64_t stride = g.g0;
+        double* o = out + (g.start + stride - 1) * D;
+        for (int c = 0; c < g.count; ++c) {
+          f = dot16(f, RC);
+          if (st) o[0] = f;
+          o += stride * D;
+        }
+        continue;
+      }
       double* o = out + (int64_t)g.start * D;
       const Row16 R0 = load_row(gl + g.g0 * GATE_STRIDE);
       if (g.per == 1) {
@@ -165,6 +222,11 @@ __global__ __launch_bounds__(256) void trunk_fwd_kernel(const PlanArgs a) {
 // ---------------------------------------------------------------------------
 // items: one sequence per team, from its anchor state
 // ---------------------------------------------------------------------------
+template <int D, bool REV>
+__device__ void run_fills(const PlanArgs& a, const Lds& s, int64_t blk, int64_t n_blk);
+
+// Workgroups from a.item_blocks on run the forward fill tasks instead (they
+// need only the trunk states, like the items).
 template <int D>
 __global__ __launch_bounds__(256) void item_kernel(const PlanArgs a) {
   extern __shared__ double lds_raw[];
@@ -172,6 +234,10 @@ __global__ __launch_bounds__(256) void item_kernel(const PlanArgs a) {
   const Lds s = carve(lds_raw, K);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, i = lane & 15, team = lane >> 4;
   stage_gateset<D>(s, a.G, a.E, a.rho, K, M);
+  if ((int)blockIdx.x >= a.item_blocks) {
+    run_fills<D, false>(a, s, (int64_t)blockIdx.x - a.item_blocks, (int64_t)gridDim.x - a.item_blocks);
+    return;
+  }
   const bool grad = a.want_grad != 0;
   double obj = 0.0, drho = 0.0;
   double dE[16];
@@ -179,7 +245,7 @@ __global__ __launch_bounds__(256) void item_kernel(const PlanArgs a) {
   for (int m = 0; m < 16; ++m) dE[m] = 0.0;
   unsigned nonpos = 0;
   const int64_t n_groups = (a.n_items + TPW - 1) / TPW;
-  for (int64_t grp = (int64_t)blockIdx.x * WAVES + wave; grp < n_groups; grp += (int64_t)gridDim.x * WAVES) {
+  for (int64_t grp = (int64_t)blockIdx.x * WAVES + wave; grp < n_groups; grp += (int64_t)a.item_blocks * WAVES) {
     const int64_t q = grp * TPW + team;
     const bool has = q < a.n_items;
     int64_t seq = 0, beg = 0, end = 0, anc = -1, isp = 0;
@@ -286,9 +352,12 @@ __global__ __launch_bounds__(256) void trunk_bwd_kernel(const PlanArgs a) {
   stage_gateset<D>(s, a.G, a.E, a.rho, K, a.M);
   const double* gl = s.GTs + i * ROW;
   double* inj_st = lds_raw + trunk_head_doubles(K) + (size_t)wave * SEGW * 16;
+  double* js = lds_raw + trunk_jump_doubles(K, wave, a.jump_levels);
   double drho = 0.0;
   for (int64_t t = a.t_begin + (int64_t)blockIdx.x * WAVES + wave; t < a.t_end; t += (int64_t)gridDim.x * WAVES) {
     const int64_t beg = a.trunk_ptr[t];
+    const uint32_t jp = (uint32_t)__builtin_amdgcn_readfirstlane((int)a.trunk_jpat[t]);
+    if (jp != 0u) build_jumps(js, s.GTs, jp, a.trunk_jg3[t], a.jump_levels, true, lane);
     double* ba = a.BA + beg * D + i;
     const bool st = (D == 16) || lane < D;
     const int64_t sg0 = a.seg_ptr[t], sg1 = a.seg_ptr[t + 1];
@@ -317,6 +386,12 @@ __global__ __launch_bounds__(256) void trunk_bwd_kernel(const PlanArgs a) {
     for (int x = n - 1; x >= 0; --x) {
       const Seg g = seg_of(d, x);
       b += inj_st[x * 16 + i];  // adjoint arriving at the state after the segment's last step
+      if (g.per == 0) {  // jumps in reverse with the transposed matrix
+        const Row16 RC = load_row(js + g.g1 * GATE_STRIDE + i * ROW);
+        const int stride = g.g0;
+        for (int c = g.count - 1; c >= 0; --c) GST_TBSTEP(RC, g.start + (c + 1) * stride - 1)
+        continue;
+      }
       const Row16 R0 = load_row(gl + g.g0 * GATE_STRIDE);
       if (g.per == 1) {
         for (int c = g.count - 1; c >= 0; --c) GST_TBSTEP(R0, g.start + c)
@@ -361,6 +436,76 @@ __global__ __launch_bounds__(256) void trunk_bwd_kernel(const PlanArgs a) {
   for (int m = 0; m < 16; ++m) dE[m] = 0.0;
   d4 none[KMAX];
   write_slab<D>(lds_raw, 0.0, drho, dE, none, a.M, 0, a.slab + (int64_t)blockIdx.x * slab_width(D, a.M, 0));
+}
+
+// ---------------------------------------------------------------------------
+// fill tasks: the states (forward) or adjoints (reverse) inside one jump, one
+// task per 16-lane team, from the stored value at the jump's start (forward)
+// or end (reverse).  Step j of a task applies gate pattern[j % period].
+// ---------------------------------------------------------------------------
+template <int D, bool REV>
+__device__ void run_fills(const PlanArgs& a, const Lds& s, int64_t blk, int64_t n_blk) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, i = lane & 15, team = lane >> 4;
+  const double* gl = (REV ? s.GTs : s.Gs) + i * ROW;
+  const int64_t n_groups = (a.n_fill + TPW - 1) / TPW;
+  for (int64_t grp = blk * WAVES + wave; grp < n_groups; grp += n_blk * WAVES) {
+    const int64_t q = grp * TPW + team;
+    const bool has = q < a.n_fill;
+    int64_t first = 0, in = 0;
+    int n = 1;
+    uint32_t pat = 1u;
+    int g3 = 0;
+    if (has) {
+      first = a.fill_first[q];
+      in = a.fill_in[q];
+      n = a.fill_n[q];
+      pat = a.fill_pattern[q];
+      g3 = a.fill_gate3[q];
+    }
+    const int per = (int)(pat & 0xffu);
+    const int nw = wave_max4(n);
+    const bool st = has && i < D;
+    auto gate = [&](int j) {
+      const int ph = j % per;
+      return ph == 0 ? (int)((pat >> 8) & 0xffu) : ph == 1 ? (int)((pat >> 16) & 0xffu)
+                                                 : ph == 2 ? (int)((pat >> 24) & 0xffu) : g3;
+    };
+    if (!REV) {
+      // states after steps 0 .. n-2 (the one after step n-1 is the jump's)
+      double f = load_state(a.FA, in, D, i);
+      double* o = a.FA + (1 + first) * D + i;
+      Row16 R = load_row(gl + gate(0) * GATE_STRIDE);
+      for (int j = 0; j + 1 < nw; ++j) {
+        const Row16 Rn = load_row(gl + gate(j + 1) * GATE_STRIDE);
+        f = dot16(f, R);
+        if (st && j + 1 < n) o[(int64_t)j * D] = f;
+        R = Rn;
+      }
+    } else {
+      // adjoints after steps n-2 .. 0, from the one after step n-1
+      double b = st ? a.BA[(first + n - 1) * D + i] : 0.0;
+      double* o = a.BA + first * D + i;
+      Row16 R = load_row(gl + gate(nw - 1) * GATE_STRIDE);
+      for (int j = nw - 1; j >= 1; --j) {
+        const Row16 Rn = load_row(gl + gate(j - 1) * GATE_STRIDE);
+        const double nb = dot16(b, R);
+        if (j < n) {
+          b = nb;
+          if (st) o[(int64_t)(j - 1) * D] = b;
+        }
+        R = Rn;
+      }
+    }
+  }
+}
+
+// reverse fill tasks (the forward ones run in the item kernel's extra workgroups)
+template <int D>
+__global__ __launch_bounds__(256) void fill_rev_kernel(const PlanArgs a) {
+  extern __shared__ double lds_raw[];
+  const Lds s = carve(lds_raw, a.K);
+  stage_gateset<D>(s, a.G, a.E, a.rho, a.K, a.M);
+  run_fills<D, true>(a, s, blockIdx.x, gridDim.x);
 }
 
 // One wave per injection slot: four groups of 16 lanes take every fourth
@@ -504,6 +649,11 @@ __global__ __launch_bounds__(256) void plan_reduce_stage2(const PlanReduce a) {
 
 }  // namespace
 
+int fill_blocks_for(int64_t n_fill) {
+  const int64_t b = (n_fill + WAVES * TPW - 1) / (WAVES * TPW);
+  return (int)(b < 1 ? 1 : (b > 1024 ? 1024 : b));
+}
+
 int item_blocks_for(int64_t n_items) {
   int64_t b = (n_items + WAVES * TPW - 1) / (WAVES * TPW);
   if (b < 1) b = 1;
@@ -518,7 +668,7 @@ int trunk_blocks_for(int64_t n) {
 
 hipError_t launch_trunk_fwd(const PlanArgs& a, hipStream_t stream) {
   const int blocks = trunk_blocks_for(a.t_end - a.t_begin);
-  const size_t bytes = trunk_lds_bytes(a.K);
+  const size_t bytes = trunk_lds_bytes(a.K, a.jump_levels);
   if (a.D == 16)
     hipLaunchKernelGGL(trunk_fwd_kernel<16>, dim3(blocks), dim3(256), bytes, stream, a);
   else if (a.D == 4)
@@ -530,7 +680,7 @@ hipError_t launch_trunk_fwd(const PlanArgs& a, hipStream_t stream) {
 
 hipError_t launch_trunk_bwd(const PlanArgs& a, hipStream_t stream) {
   const int blocks = trunk_blocks_for(a.t_end - a.t_begin);
-  const size_t bytes = trunk_lds_bytes(a.K);
+  const size_t bytes = trunk_lds_bytes(a.K, a.jump_levels);
   if (a.D == 16)
     hipLaunchKernelGGL(trunk_bwd_kernel<16>, dim3(blocks), dim3(256), bytes, stream, a);
   else if (a.D == 4)
@@ -541,11 +691,13 @@ hipError_t launch_trunk_bwd(const PlanArgs& a, hipStream_t stream) {
 }
 
 hipError_t launch_items(const PlanArgs& a, int n_blocks, hipStream_t stream) {
+  if (a.item_blocks != n_blocks) return hipErrorInvalidValue;
   const size_t bytes = lds_bytes(a.K);
+  const unsigned grid = (unsigned)n_blocks + (a.want_grad && a.n_fill > 0 ? (unsigned)fill_blocks_for(a.n_fill) : 0u);
   if (a.D == 16)
-    hipLaunchKernelGGL(item_kernel<16>, dim3(n_blocks), dim3(256), bytes, stream, a);
+    hipLaunchKernelGGL(item_kernel<16>, dim3(grid), dim3(256), bytes, stream, a);
   else if (a.D == 4)
-    hipLaunchKernelGGL(item_kernel<4>, dim3(n_blocks), dim3(256), bytes, stream, a);
+    hipLaunchKernelGGL(item_kernel<4>, dim3(grid), dim3(256), bytes, stream, a);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
@@ -556,6 +708,19 @@ hipError_t launch_inject(const InjectLaunch& a, hipStream_t stream) {
   if (n <= 0) return hipSuccess;
   const int blocks = (int)(n < 65536 ? n : 65536);
   hipLaunchKernelGGL(inject_kernel, dim3(blocks), dim3(64), 0, stream, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_rev(const PlanArgs& a, hipStream_t stream) {
+  if (a.n_fill <= 0) return hipSuccess;
+  const int blocks = fill_blocks_for(a.n_fill);
+  const size_t bytes = lds_bytes(a.K);
+  if (a.D == 16)
+    hipLaunchKernelGGL(fill_rev_kernel<16>, dim3((unsigned)blocks), dim3(256), bytes, stream, a);
+  else if (a.D == 4)
+    hipLaunchKernelGGL(fill_rev_kernel<4>, dim3((unsigned)blocks), dim3(256), bytes, stream, a);
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 

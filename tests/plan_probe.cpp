@@ -6,6 +6,14 @@
 
 namespace {
 gst::HostPlan g_plan;
+int g_jump = gst::PlanOptions().jump;
+int g_jump_min_save = gst::PlanOptions().jump_min_save;
+}
+
+// Germ-power jump options of the following plan_build calls.
+extern "C" void plan_set_jump(int jump, int min_save) {
+  g_jump = jump;
+  g_jump_min_save = min_save;
 }
 
 extern "C" int plan_build(const int64_t* off, const uint8_t* gates, int64_t S, int K, int min_trunk,
@@ -14,6 +22,8 @@ extern "C" int plan_build(const int64_t* off, const uint8_t* gates, int64_t S, i
   opt.min_trunk = min_trunk;
   opt.reanchor_depth = reanchor_depth;
   opt.max_share_ratio = ratio;
+  opt.jump = g_jump;
+  opt.jump_min_save = g_jump_min_save;
   const bool used = gst::build_plan(off, gates, S, K, opt, &g_plan);
   const gst::HostPlan& P = g_plan;
   sizes[0] = used;
@@ -62,4 +72,24 @@ extern "C" void plan_copy_segments(int64_t* seg_ptr, int32_t* start, int32_t* co
   std::memcpy(count, P.seg_count.data(), P.seg_count.size() * 4);
   std::memcpy(pattern, P.seg_pattern.data(), P.seg_pattern.size() * 4);
   std::memcpy(g3, P.seg_gate3.data(), P.seg_gate3.size());
+}
+
+extern "C" void plan_jump_sizes(int64_t* sizes) {
+  const gst::HostPlan& P = g_plan;
+  sizes[0] = P.jump_levels;
+  sizes[1] = P.n_jump_trunks();
+  sizes[2] = P.n_fill();
+}
+
+// pattern, g3: per trunk (pattern 0 = no jumps)
+extern "C" void plan_copy_jumps(uint32_t* pattern, uint8_t* g3, int64_t* first, int64_t* in, int32_t* n,
+                                uint32_t* fpat, uint8_t* fg3) {
+  const gst::HostPlan& P = g_plan;
+  std::memcpy(pattern, P.trunk_jump_pattern.data(), P.trunk_jump_pattern.size() * 4);
+  std::memcpy(g3, P.trunk_jump_gate3.data(), P.trunk_jump_gate3.size());
+  std::memcpy(first, P.fill_first.data(), P.fill_first.size() * 8);
+  std::memcpy(in, P.fill_in.data(), P.fill_in.size() * 8);
+  std::memcpy(n, P.fill_n.data(), P.fill_n.size() * 4);
+  std::memcpy(fpat, P.fill_pattern.data(), P.fill_pattern.size() * 4);
+  std::memcpy(fg3, P.fill_gate3.data(), P.fill_gate3.size());
 }

@@ -93,5 +93,7 @@ def test_autograd_probs_vjp(oracle_lib, gpu):
     ctx.sync()
     g = torch.cat([rho.grad.ravel(), E.grad.ravel(), G.grad.ravel()]).cpu().numpy()
     want = oracle_lib.vjp(m.rho, m.effects, m.gates, sl.offsets, sl.gates, Wt.cpu().numpy())
-    assert np.array_equal(p.detach().cpu().numpy(), oracle_lib.probs(m.rho, m.effects, m.gates, sl.offsets, sl.gates))
+    p_or = oracle_lib.probs(m.rho, m.effects, m.gates, sl.offsets, sl.gates)
+    # germ-power jumps of the sharing plan: 1e-12 relative on p
+    assert np.all(np.abs(p.detach().cpu().numpy() - p_or) <= 1e-12 * np.abs(p_or))
     assert np.abs(g - want).max() <= 1e-10 * np.abs(want).max()

@@ -2,8 +2,8 @@
 
 Each request's result in a batch must be identical, bit for bit, to its
 standalone evaluation, and the standalone results must match the oracle
-(probabilities bit for bit, objective 1e-10 relative, gradient 1e-10
-normwise).  The graph-captured form is replayed several times with other
+(probabilities bit for bit, or to 1e-12 relative for a sharing plan with
+germ-power jumps; objective 1e-10 relative, gradient 1e-10 normwise).  The graph-captured form is replayed several times with other
 work and synchronizations between replays, every replay checked against the
 eager result at the gate sets current at that time.
 """
@@ -80,10 +80,14 @@ def test_batch_equals_standalone_and_oracle(oracle_lib, gpu):
     labels = [m[0] for m in mix]
     reqs, thetas = _requests(api, ctx, mix)
     ref = _standalone(ctx, reqs, thetas)
-    for (label, gs, sl, counts), (o, p, g) in zip(mix, ref):
+    for (label, gs, sl, counts), (o, p, g), r in zip(mix, ref, reqs):
         say(f"[batch] oracle check {label}")
         F, p_or, g_or, _, _ = oracle_lib.loglik(gs.rho, gs.effects, gs.gates, sl.offsets, sl.gates, counts)
-        assert np.array_equal(p.cpu().numpy(), p_or), label
+        if r.plan_info()["jump_trunks"] == 0:
+            assert np.array_equal(p.cpu().numpy(), p_or), label
+        else:  # germ-power jumps: rounding of the matrix powers, 1e-12 relative
+            pp = p.cpu().numpy()
+            assert np.all(np.abs(pp - p_or) <= 1e-12 * np.abs(p_or)), label
         Fg = float(o.cpu()[0])
         assert abs(Fg - F) <= 1e-10 * max(abs(F), 1e-300), (label, Fg, F)
         gg = g.cpu().numpy()

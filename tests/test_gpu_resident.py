@@ -1,4 +1,10 @@
-"""GPU parity of the resident request (prefix-sharing plan) against the oracle."""
+"""GPU parity of the resident request (prefix-sharing plan) against the oracle.
+
+Without germ-power jumps the plan's probabilities are bit-identical to the
+oracle's.  With jumps (the default) the states after each jump come from
+matrix powers of the germ, and the probabilities are checked at the stated
+1e-12 relative tolerance; objective and gradient at 1e-10 either way.
+"""
 import sys
 
 import numpy as np
@@ -22,20 +28,42 @@ def gpu():
     return api, api.Context(0)
 
 
-def run_request(oracle_lib, api, ctx, gs, sl, counts, label, expect_plan=None):
-    say(f"[resident] {label}: S={sl.S} D={gs.D} K={gs.K} sumL={int(sl.offsets[-1])}")
+P_RTOL = 1e-12
+
+
+def check_probs(p, p_or, exact):
+    if exact:
+        mism = np.count_nonzero(p != p_or)
+        assert mism == 0, f"{mism} probabilities differ, max {np.abs(p - p_or).max()}"
+    else:
+        rel = np.abs(p - p_or) / np.maximum(np.abs(p_or), 1e-300)
+        rel[(p == p_or)] = 0.0
+        assert rel.max() <= P_RTOL, (rel.max(), p_or.flat[int(np.argmax(rel))])
+        say(f"[resident] max relative probability difference {rel.max():.3g}")
+
+
+def run_request(oracle_lib, api, ctx, gs, sl, counts, label, expect_plan=None, jump=8):
+    say(f"[resident] {label}: S={sl.S} D={gs.D} K={gs.K} sumL={int(sl.offsets[-1])} jump={jump}")
+    api.set_plan_jump(ctx, jump)
+    try:
+        return _run_request(oracle_lib, api, ctx, gs, sl, counts, label, expect_plan)
+    finally:
+        api.set_plan_jump(ctx, 8)
+
+
+def _run_request(oracle_lib, api, ctx, gs, sl, counts, label, expect_plan):
     req = api.Request(ctx, gs.n_qubits, gs.K, gs.M, sl.offsets, sl.gates, counts)
     info = req.plan_info()
     say(f"[resident] {label}: plan {info}")
     if expect_plan is not None:
         assert bool(info["plan_used"]) == expect_plan
+    exact = info["jump_trunks"] == 0
     dg = api.DeviceGateSet.from_numpy(gs.n_qubits, gs.rho, gs.effects, gs.gates)
     obj, p, g = req.eval(dg, want_probs=True, want_grad=True)
     ctx.sync()
     F, p_or, g_or, _, _ = oracle_lib.loglik(gs.rho, gs.effects, gs.gates, sl.offsets, sl.gates, counts)
     p = p.cpu().numpy()
-    mism = np.count_nonzero(p != p_or)
-    assert mism == 0, f"{mism} probabilities differ, max {np.abs(p - p_or).max()}"
+    check_probs(p, p_or, exact)
     Fg = float(obj.cpu()[0])
     assert abs(Fg - F) <= 1e-10 * abs(F), (Fg, F)
     g = g.cpu().numpy()
@@ -43,7 +71,7 @@ def run_request(oracle_lib, api, ctx, gs, sl, counts, label, expect_plan=None):
     # probabilities only, and objective only
     obj2, p2, g2 = req.eval(dg, want_probs=True, want_grad=False)
     ctx.sync()
-    assert np.array_equal(p2.cpu().numpy(), p_or)
+    assert np.array_equal(p2.cpu().numpy(), p)
     assert abs(float(obj2.cpu()[0]) - F) <= 1e-10 * abs(F)
     # a second evaluation at another gate set reuses the resident plan
     rng = np.random.default_rng(1)
@@ -56,22 +84,29 @@ def run_request(oracle_lib, api, ctx, gs, sl, counts, label, expect_plan=None):
     obj3, p3, g3 = req2.eval(dg2, want_probs=True)
     ctx.sync()
     F3, _, g_or3, _, _ = oracle_lib.loglik(gs2.rho, gs2.effects, gs2.gates, sl.offsets, sl.gates, c2)
-    assert np.array_equal(p3.cpu().numpy(), p_or2)
+    check_probs(p3.cpu().numpy(), p_or2, exact)
     assert abs(float(obj3.cpu()[0]) - F3) <= 1e-10 * abs(F3)
     assert np.abs(g3.cpu().numpy() - g_or3).max() <= 1e-10 * np.abs(g_or3).max()
     return req
 
 
-def test_resident_c1(oracle_lib, gpu):
+@pytest.mark.parametrize("jump", [8, 0])
+def test_resident_c1(oracle_lib, gpu, jump):
     api, ctx = gpu
     w = W.structured_workload("c1")
-    run_request(oracle_lib, api, ctx, w.model, w.seqs, w.counts, "c1", expect_plan=True)
+    req = run_request(oracle_lib, api, ctx, w.model, w.seqs, w.counts, "c1", expect_plan=True, jump=jump)
+    assert (req.plan_info()["jump_trunks"] > 0) == (jump > 0)
 
 
-def test_resident_c2(oracle_lib, gpu):
+@pytest.mark.parametrize("jump", [8, 0, 2, 16])
+def test_resident_c2(oracle_lib, gpu, jump):
     api, ctx = gpu
     w = W.structured_workload("c2")
-    run_request(oracle_lib, api, ctx, w.model, w.seqs, w.counts, "c2", expect_plan=True)
+    req = run_request(oracle_lib, api, ctx, w.model, w.seqs, w.counts, "c2", expect_plan=True, jump=jump)
+    info = req.plan_info()
+    assert (info["jump_trunks"] > 0) == (jump > 0)
+    if jump == 8:
+        assert info["chain_max"] <= 100 and info["fill_tasks"] > 0  # longest trunk: 772 steps
 
 
 def test_resident_two_levels(oracle_lib, gpu):

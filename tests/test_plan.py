@@ -34,6 +34,9 @@ def planlib(tmp_path_factory):
     lib.plan_copy.argtypes = [P] * 9
     lib.plan_copy_records.argtypes = [P] * 4
     lib.plan_copy_segments.argtypes = [P] * 5
+    lib.plan_set_jump.argtypes = [ctypes.c_int, ctypes.c_int]
+    lib.plan_jump_sizes.argtypes = [P]
+    lib.plan_copy_jumps.argtypes = [P] * 7
     return lib
 
 
@@ -67,6 +70,24 @@ def get_plan(lib, sl, K, min_trunk=24, reanchor=8, ratio=0.8):
         P["seg_gate3"] = np.zeros(max(nSeg, 1), np.uint8)
         lib.plan_copy_segments(*[P[k].ctypes.data for k in ["seg_ptr", "seg_start", "seg_count", "seg_pattern",
                                                               "seg_gate3"]])
+        js = np.zeros(3, np.int64)
+        lib.plan_jump_sizes(js.ctypes.data)
+        levels, nJT, nF = [int(x) for x in js]
+        P["jump_levels"] = levels
+        P["jump_trunks"] = nJT
+        P["jump_pattern"] = np.zeros(max(nT, 1), np.uint32)
+        P["jump_gate3"] = np.zeros(max(nT, 1), np.uint8)
+        P["fill_first"] = np.zeros(max(nF, 1), np.int64)
+        P["fill_in"] = np.zeros(max(nF, 1), np.int64)
+        P["fill_n"] = np.zeros(max(nF, 1), np.int32)
+        P["fill_pattern"] = np.zeros(max(nF, 1), np.uint32)
+        P["fill_gate3"] = np.zeros(max(nF, 1), np.uint8)
+        lib.plan_copy_jumps(*[P[k].ctypes.data for k in ["jump_pattern", "jump_gate3", "fill_first", "fill_in",
+                                                           "fill_n", "fill_pattern", "fill_gate3"]])
+        for k in ("jump_pattern", "jump_gate3"):
+            P[k] = P[k][:nT]
+        for k in ("fill_first", "fill_in", "fill_n", "fill_pattern", "fill_gate3"):
+            P[k] = P[k][:nF]
     P["trunk_gates"] = P["trunk_gates"][:nTS]
     P["trunk_inj"] = P["trunk_inj"][:nTS]
     P["inj_loc"] = P["inj_loc"][:nJ]
@@ -257,16 +278,122 @@ def test_plan_multilevel_and_random(planlib, oracle_lib):
     assert not P["used"]
 
 
+def pattern_gates(pat, g3):
+    per = pat & 0xff
+    return [(pat >> 8) & 0xff, (pat >> 16) & 0xff, (pat >> 24) & 0xff, int(g3)][:per]
+
+
 def segments_word(P, t):
-    """Rebuilds trunk t's gate word from its periodic segments."""
+    """Rebuilds trunk t's gate word from its periodic segments; a jump segment
+    (period 0) stands for 2^e repetitions of its pattern per jump."""
     out = []
     for sg in range(P["seg_ptr"][t], P["seg_ptr"][t + 1]):
         pat = int(P["seg_pattern"][sg])
-        per = pat & 0xff
-        gates = [(pat >> 8) & 0xff, (pat >> 16) & 0xff, (pat >> 24) & 0xff, int(P["seg_gate3"][sg])][:per]
         assert P["seg_start"][sg] == len(out)
-        out += gates * int(P["seg_count"][sg])
+        if pat & 0xff == 0:
+            stride, e = (pat >> 8) & 0xff, pat >> 16
+            assert e < P["jump_levels"]
+            gates = pattern_gates(int(P["jump_pattern"][t]), P["jump_gate3"][t])
+            assert stride == (1 << e) * len(gates)
+            out += gates * ((1 << e) * int(P["seg_count"][sg]))
+        else:
+            out += pattern_gates(pat, P["seg_gate3"][sg]) * int(P["seg_count"][sg])
     return out
+
+
+def jump_matrices(P, G, t):
+    """Trunk t's jump pattern product to the powers 2^e, e < jump_levels
+    (plain numpy)."""
+    out = []
+    A = np.eye(G.shape[1])
+    for g in pattern_gates(int(P["jump_pattern"][t]), P["jump_gate3"][t]):
+        A = G[g] @ A
+    for e in range(P["jump_levels"]):
+        out.append(A)
+        A = A @ A
+    return out
+
+
+def chain_schedule(P, G, rho, inj):
+    """The trunk sweeps as the kernels order them with germ-power jumps: the
+    chain over segments (a jump applies its matrix and stores only the state
+    after it), then the fill tasks; the reverse sweep likewise with the
+    transposes, adding inj[slot] at the states that receive injections.
+    Returns the state and adjoint arenas and how often each row was written."""
+    D = G.shape[1]
+    tp, ta, tg, ti = P["trunk_ptr"], P["trunk_anchor"], P["trunk_gates"], P["trunk_inj"]
+    nTS = len(tg)
+    FA = np.full((1 + nTS, D), np.nan)
+    FA[0] = rho
+    BA = np.full((nTS, D), np.nan)
+    wf = np.zeros(nTS, np.int64)
+    wb = np.zeros(nTS, np.int64)
+    tadj = np.zeros((len(ta), D))
+    segs = lambda t: range(P["seg_ptr"][t], P["seg_ptr"][t + 1])
+    for t in range(len(ta)):
+        f = FA[0] if ta[t] < 0 else FA[1 + ta[t]]
+        base = tp[t]
+        J = jump_matrices(P, G, t)
+        for sg in segs(t):
+            st, cnt, pat = int(P["seg_start"][sg]), int(P["seg_count"][sg]), int(P["seg_pattern"][sg])
+            if pat & 0xff == 0:
+                stride = (pat >> 8) & 0xff
+                for c in range(cnt):
+                    f = J[pat >> 16] @ f
+                    j = base + st + (c + 1) * stride - 1
+                    FA[1 + j] = f
+                    wf[j] += 1
+            else:
+                gates = pattern_gates(pat, P["seg_gate3"][sg])
+                for c in range(cnt):
+                    for q, g in enumerate(gates):
+                        f = G[g] @ f
+                        j = base + st + c * len(gates) + q
+                        FA[1 + j] = f
+                        wf[j] += 1
+    for q in range(len(P["fill_first"])):
+        first, n = int(P["fill_first"][q]), int(P["fill_n"][q])
+        gates = pattern_gates(int(P["fill_pattern"][q]), P["fill_gate3"][q])
+        f = FA[P["fill_in"][q]]
+        for j in range(n - 1):
+            f = G[gates[j % len(gates)]] @ f
+            FA[1 + first + j] = f
+            wf[first + j] += 1
+    for t in range(len(ta) - 1, -1, -1):
+        b = np.zeros(D)
+        base = tp[t]
+        J = jump_matrices(P, G, t)
+        for sg in reversed(segs(t)):
+            st, cnt, pat = int(P["seg_start"][sg]), int(P["seg_count"][sg]), int(P["seg_pattern"][sg])
+            if pat & 0xff == 0:
+                stride = (pat >> 8) & 0xff
+                last = base + st + cnt * stride - 1
+                if ti[last] >= 0:
+                    b = b + inj[ti[last]]
+                for c in range(cnt - 1, -1, -1):
+                    j = base + st + (c + 1) * stride - 1
+                    BA[j] = b
+                    wb[j] += 1
+                    b = J[pat >> 16].T @ b
+            else:
+                gates = pattern_gates(pat, P["seg_gate3"][sg])
+                last = base + st + cnt * len(gates) - 1
+                if ti[last] >= 0:
+                    b = b + inj[ti[last]]
+                for j in range(last, base + st - 1, -1):
+                    BA[j] = b
+                    wb[j] += 1
+                    b = G[tg[j]].T @ b
+        tadj[t] = b
+    for q in range(len(P["fill_first"])):
+        first, n = int(P["fill_first"][q]), int(P["fill_n"][q])
+        gates = pattern_gates(int(P["fill_pattern"][q]), P["fill_gate3"][q])
+        b = BA[first + n - 1]
+        for j in range(n - 1, 0, -1):
+            b = G[gates[j % len(gates)]].T @ b
+            BA[first + j - 1] = b
+            wb[first + j - 1] += 1
+    return FA, BA, tadj, wf, wb
 
 
 @pytest.mark.parametrize("name", ["c1", "c2"])
@@ -299,3 +426,55 @@ def test_random_words_rejected_early(planlib):
     words = [list(rng.integers(0, 6, size=200)) for _ in range(5)] * 40
     P = get_plan(planlib, W.from_words(words), 6)
     assert P["used"] and P["n_nodes"] <= 1 + 5 * 200 and P["sum_len"] == 200 * 200
+
+
+@pytest.mark.parametrize("name,jump", [("c1", 8), ("c2", 8), ("c2", 4), ("c2", 16), ("c2", 2)])
+def test_germ_power_jumps(planlib, name, jump):
+    """Germ-power jumps (a run of a periodic pattern applied 2^e repetitions at
+    a time by the matrix power) plus the fill tasks write every trunk state and
+    adjoint exactly once, and give the values of the plain step-by-step
+    sweeps up to rounding; injections land only where the chain stores."""
+    w = W.structured_workload(name)
+    G, rho = w.model.gates, w.model.rho
+    D = G.shape[1]
+    planlib.plan_set_jump(jump, 4)
+    try:
+        P = get_plan(planlib, w.seqs, w.model.K)
+    finally:
+        planlib.plan_set_jump(8, 12)
+    assert P["used"] and len(P["fill_first"]) > 0 and P["jump_trunks"] > 0
+    tp, ta, tg, ti = P["trunk_ptr"], P["trunk_anchor"], P["trunk_gates"], P["trunk_inj"]
+    for t in range(len(ta)):
+        assert segments_word(P, t) == list(tg[tp[t]:tp[t + 1]])
+    rng = np.random.default_rng(3)
+    inj = rng.standard_normal((len(P["inj_loc"]), D))
+    FA, BA, tadj, wf, wb = chain_schedule(P, G, rho, inj)
+    assert np.all(wf == 1) and np.all(wb == 1)
+    # plain sweeps (levels in order; the anchors are states of earlier trunks)
+    F = np.zeros((1 + len(tg), D))
+    F[0] = rho
+    B = np.zeros((len(tg), D))
+    for t in range(len(ta)):
+        f = F[0] if ta[t] < 0 else F[1 + ta[t]]
+        for j in range(tp[t], tp[t + 1]):
+            f = G[tg[j]] @ f
+            F[1 + j] = f
+    tadj0 = np.zeros_like(tadj)
+    for t in range(len(ta) - 1, -1, -1):
+        b = np.zeros(D)
+        for j in range(tp[t + 1] - 1, tp[t] - 1, -1):
+            if ti[j] >= 0:
+                b = b + inj[ti[j]]
+            B[j] = b
+            b = G[tg[j]].T @ b
+        tadj0[t] = b
+    assert np.abs(FA - F).max() <= 1e-13 * np.abs(F).max()
+    assert np.abs(BA - B).max() <= 1e-12 * np.abs(B).max()
+    assert np.abs(tadj - tadj0).max() <= 1e-12 * np.abs(tadj0).max()
+    # the chain is much shorter than the trunk: count chain mat-vecs of the longest trunk
+    t = int(np.argmax(np.diff(tp)))
+    chain = sum(int(P["seg_count"][sg]) if P["seg_pattern"][sg] & 0xff == 0
+                else int(P["seg_count"][sg]) * int(P["seg_pattern"][sg] & 0xff)
+                for sg in range(P["seg_ptr"][t], P["seg_ptr"][t + 1]))
+    if name == "c2" and jump == 8:
+        assert chain * 4 < tp[t + 1] - tp[t]
