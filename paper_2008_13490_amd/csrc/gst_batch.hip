@@ -64,7 +64,7 @@ __global__ __launch_bounds__(256) void batch_kernel(const BatchLaunch a) {
     if (T.req != staged) {
       // a different gate set: restage (carve for this request's K inside the kmax layout)
       s = carve(lds_raw, a.kmax);
-      stage_gateset<D>(s, R.G, R.E, R.rho, K, M);
+      stage_gateset_compact<D>(s, R.G, R.E, R.rho, K, M);  // the tile loop is short of registers
       staged = T.req;
     }
     const bool grad = R.want_grad != 0;

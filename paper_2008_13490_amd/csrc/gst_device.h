@@ -199,10 +199,53 @@ __device__ __forceinline__ Lds carve(double* base, int K) {
   return l;
 }
 
-// Gate set into LDS, zero-padded to 16 x 16.
+// Gate set into LDS, zero-padded to 16 x 16 (and the two padding columns of
+// each row zeroed).  Workgroups of 256 threads: thread (r, c) loads entry
+// (r, c) of every gate and of E up front, so the global loads are in flight
+// together, then writes them and their transposes.
 template <int D>
 __device__ void stage_gateset(const Lds& s, const double* __restrict__ G, const double* __restrict__ E,
                               const double* __restrict__ rho, int K, int M) {
+  const int tid = threadIdx.x, r = tid >> 4, c = tid & 15;
+  const bool in = r < D && c < D;
+  const auto* g = as_global(G);
+  const auto* e = as_global(E);
+  double v[KMAX];
+#pragma unroll
+  for (int k = 0; k < KMAX; ++k) {
+    const bool use = k < K && in;
+    const double x = g[use ? ((size_t)k * D + r) * D + c : 0];
+    v[k] = use ? x : 0.0;
+  }
+  const bool use_e = r < M && c < D;
+  const double ex = e[use_e ? (size_t)r * D + c : 0];
+  const double rh = as_global(rho)[tid < D ? tid : 0];
+#pragma unroll
+  for (int k = 0; k < KMAX; ++k) {
+    if (k < K) {
+      s.Gs[k * GATE_STRIDE + r * ROW + c] = v[k];
+      s.GTs[k * GATE_STRIDE + c * ROW + r] = v[k];
+      if (c < ROW - 16) {
+        s.Gs[k * GATE_STRIDE + r * ROW + 16 + c] = 0.0;
+        s.GTs[k * GATE_STRIDE + r * ROW + 16 + c] = 0.0;
+      }
+    }
+  }
+  s.Es[r * ROW + c] = use_e ? ex : 0.0;
+  s.ETs[c * ROW + r] = use_e ? ex : 0.0;
+  if (c < ROW - 16) {
+    s.Es[r * ROW + 16 + c] = 0.0;
+    s.ETs[r * ROW + 16 + c] = 0.0;
+  }
+  if (tid < 16) s.rho[tid] = tid < D ? rh : 0.0;
+  __syncthreads();
+}
+
+// The same layout with one entry per thread and iteration: few registers, for
+// a kernel that stages inside its hot loop and is short of them.
+template <int D>
+__device__ void stage_gateset_compact(const Lds& s, const double* __restrict__ G, const double* __restrict__ E,
+                                      const double* __restrict__ rho, int K, int M) {
   const int tid = threadIdx.x;
   for (int x = tid; x < K * 16 * ROW; x += blockDim.x) {
     const int k = x / (16 * ROW), r = (x / ROW) % 16, c = x % ROW;

@@ -48,6 +48,13 @@ __host__ __device__ inline size_t trunk_head_doubles(int K) {
   return (size_t)2 * K * GATE_STRIDE + 2 * 16 * ROW + 16;
 }
 
+// Item and fill workgroups hold only the gate set (no checkpoint stash); the
+// head-row reduction reuses it afterwards.
+__host__ __device__ inline size_t item_lds_bytes(int K) {
+  const size_t a = trunk_head_doubles(K) * 8, r = (size_t)WAVES * (1 + 16 + 256) * 8;
+  return (a > r ? a : r) + 64;
+}
+
 // Per wave after the staging area: the trunk's jump matrices, `levels` of
 // them in the gate layout.
 __host__ __device__ inline size_t trunk_jump_doubles(int K, int wave, int levels) {
@@ -657,7 +664,7 @@ int fill_blocks_for(int64_t n_fill) {
 int item_blocks_for(int64_t n_items) {
   int64_t b = (n_items + WAVES * TPW - 1) / (WAVES * TPW);
   if (b < 1) b = 1;
-  if (b > 512) b = 512;  // two resident workgroups per CU
+  if (b > 1024) b = 1024;  // four resident workgroups per CU
   return (int)b;
 }
 
@@ -692,7 +699,7 @@ hipError_t launch_trunk_bwd(const PlanArgs& a, hipStream_t stream) {
 
 hipError_t launch_items(const PlanArgs& a, int n_blocks, hipStream_t stream) {
   if (a.item_blocks != n_blocks) return hipErrorInvalidValue;
-  const size_t bytes = lds_bytes(a.K);
+  const size_t bytes = item_lds_bytes(a.K);
   const unsigned grid = (unsigned)n_blocks + (a.want_grad && a.n_fill > 0 ? (unsigned)fill_blocks_for(a.n_fill) : 0u);
   if (a.D == 16)
     hipLaunchKernelGGL(item_kernel<16>, dim3(grid), dim3(256), bytes, stream, a);
@@ -714,7 +721,7 @@ hipError_t launch_inject(const InjectLaunch& a, hipStream_t stream) {
 hipError_t launch_fill_rev(const PlanArgs& a, hipStream_t stream) {
   if (a.n_fill <= 0) return hipSuccess;
   const int blocks = fill_blocks_for(a.n_fill);
-  const size_t bytes = lds_bytes(a.K);
+  const size_t bytes = item_lds_bytes(a.K);
   if (a.D == 16)
     hipLaunchKernelGGL(fill_rev_kernel<16>, dim3((unsigned)blocks), dim3(256), bytes, stream, a);
   else if (a.D == 4)
