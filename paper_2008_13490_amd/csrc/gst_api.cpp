@@ -155,19 +155,12 @@ struct DevicePlan {
   int64_t* items = nullptr;
   int64_t* trunk_ptr = nullptr;
   int64_t* trunk_anchor = nullptr;
-  uint8_t* trunk_gates = nullptr;
-  int32_t* trunk_inj = nullptr;
+
   int64_t* inj_ptr = nullptr;
   int64_t* inj_src = nullptr;
-  int64_t* tinj_ptr = nullptr;
-  int32_t* tinj_step = nullptr;
-  int64_t* tinj_slot = nullptr;
-  int64_t* seg_ptr = nullptr;
-  int32_t* seg_start = nullptr;
-  int32_t* seg_count = nullptr;
-  uint32_t* seg_pattern = nullptr;
-  uint8_t* seg_gate3 = nullptr;
-  int64_t* seg_inj = nullptr;
+  int64_t* op_ptr = nullptr;
+  uint32_t* op_desc = nullptr;
+  int32_t* op_slot = nullptr;
   int64_t* item_step_ptr = nullptr;
   int64_t* rec_b = nullptr;
   int64_t* rec_f = nullptr;
@@ -426,25 +419,11 @@ int upload_plan(gst_req* r, const gst::HostPlan& P) {
   const int64_t nI = P.n_items(), nT = P.n_trunks(), nTS = P.trunk_steps(), nJ = (int64_t)P.inj_loc.size(),
                 nIS = P.item_steps(), nR = (int64_t)P.rec_b.size(), nC = P.n_chunks();
   // injection list of each trunk, steps descending
-  std::vector<int64_t> tip(nT + 1, 0), tslot;
-  std::vector<int32_t> tstep;
-  for (int64_t t = 0; t < nT; ++t) {
-    for (int64_t j = P.trunk_ptr[t + 1] - 1; j >= P.trunk_ptr[t]; --j)
-      if (P.trunk_inj[j] >= 0) {
-        tstep.push_back((int32_t)(j - P.trunk_ptr[t]));
-        tslot.push_back(P.trunk_inj[j]);
-      }
-    tip[t + 1] = (int64_t)tslot.size();
-  }
   Carver c;
-  const size_t o_tip = c.take<int64_t>(nT + 1), o_tst = c.take<int32_t>(tstep.size() + 1),
-               o_tsl = c.take<int64_t>(tslot.size() + 1);
-  const size_t nSeg = P.seg_start.size();
-  const size_t o_sp = c.take<int64_t>(nT + 1), o_ss = c.take<int32_t>(nSeg + 1), o_sc = c.take<int32_t>(nSeg + 1),
-               o_spat = c.take<uint32_t>(nSeg + 1), o_sg3 = c.take<uint8_t>(nSeg + 1),
-               o_sinj = c.take<int64_t>(nSeg + 1);
+  const size_t nOp = P.op_desc.size();
+  const size_t o_op = c.take<int64_t>(nT + 1), o_od = c.take<uint32_t>(nOp + 1), o_os = c.take<int32_t>(nOp + 1);
   const size_t o_items = c.take<int64_t>(4 * nI), o_tp = c.take<int64_t>(nT + 1), o_ta = c.take<int64_t>(nT + 1),
-               o_tg = c.take<uint8_t>(nTS + 1), o_ti = c.take<int32_t>(nTS + 1), o_ip = c.take<int64_t>(nJ + 1),
+               o_ip = c.take<int64_t>(nJ + 1),
                o_is = c.take<int64_t>(P.inj_src.size() + 1), o_isp = c.take<int64_t>(nI + 1),
                o_rb = c.take<int64_t>(nR + 1), o_rf = c.take<int64_t>(nR + 1), o_cg = c.take<int64_t>(nC + 1),
                o_cb = c.take<int64_t>(nC + 1), o_ce = c.take<int64_t>(nC + 1),
@@ -458,20 +437,12 @@ int upload_plan(gst_req* r, const gst::HostPlan& P) {
   int rc = d.buf.reserve(c.off + 256, r->ctx->stream);
   if (rc) return rc;
   char* b = reinterpret_cast<char*>(d.buf.p);
-  d.tinj_ptr = reinterpret_cast<int64_t*>(b + o_tip);
-  d.tinj_step = reinterpret_cast<int32_t*>(b + o_tst);
-  d.tinj_slot = reinterpret_cast<int64_t*>(b + o_tsl);
-  d.seg_ptr = reinterpret_cast<int64_t*>(b + o_sp);
-  d.seg_start = reinterpret_cast<int32_t*>(b + o_ss);
-  d.seg_count = reinterpret_cast<int32_t*>(b + o_sc);
-  d.seg_pattern = reinterpret_cast<uint32_t*>(b + o_spat);
-  d.seg_gate3 = reinterpret_cast<uint8_t*>(b + o_sg3);
-  d.seg_inj = reinterpret_cast<int64_t*>(b + o_sinj);
+  d.op_ptr = reinterpret_cast<int64_t*>(b + o_op);
+  d.op_desc = reinterpret_cast<uint32_t*>(b + o_od);
+  d.op_slot = reinterpret_cast<int32_t*>(b + o_os);
   d.items = reinterpret_cast<int64_t*>(b + o_items);
   d.trunk_ptr = reinterpret_cast<int64_t*>(b + o_tp);
   d.trunk_anchor = reinterpret_cast<int64_t*>(b + o_ta);
-  d.trunk_gates = reinterpret_cast<uint8_t*>(b + o_tg);
-  d.trunk_inj = reinterpret_cast<int32_t*>(b + o_ti);
   d.inj_ptr = reinterpret_cast<int64_t*>(b + o_ip);
   d.inj_src = reinterpret_cast<int64_t*>(b + o_is);
   d.item_step_ptr = reinterpret_cast<int64_t*>(b + o_isp);
@@ -496,20 +467,12 @@ int upload_plan(gst_req* r, const gst::HostPlan& P) {
     if (bytes) HIP_TRY(hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice));
     return GST_OK;
   };
-  if ((rc = put(d.tinj_ptr, tip.data(), tip.size() * 8))) return rc;
-  if ((rc = put(d.tinj_step, tstep.data(), tstep.size() * 4))) return rc;
-  if ((rc = put(d.tinj_slot, tslot.data(), tslot.size() * 8))) return rc;
-  if ((rc = put(d.seg_ptr, P.seg_ptr.data(), P.seg_ptr.size() * 8))) return rc;
-  if ((rc = put(d.seg_start, P.seg_start.data(), P.seg_start.size() * 4))) return rc;
-  if ((rc = put(d.seg_count, P.seg_count.data(), P.seg_count.size() * 4))) return rc;
-  if ((rc = put(d.seg_pattern, P.seg_pattern.data(), P.seg_pattern.size() * 4))) return rc;
-  if ((rc = put(d.seg_gate3, P.seg_gate3.data(), P.seg_gate3.size()))) return rc;
-  if ((rc = put(d.seg_inj, P.seg_inj.data(), P.seg_inj.size() * 8))) return rc;
+  if ((rc = put(d.op_ptr, P.op_ptr.data(), P.op_ptr.size() * 8))) return rc;
+  if ((rc = put(d.op_desc, P.op_desc.data(), nOp * 4))) return rc;
+  if ((rc = put(d.op_slot, P.op_slot.data(), nOp * 4))) return rc;
   if ((rc = put(d.items, P.items.data(), P.items.size() * 8))) return rc;
   if ((rc = put(d.trunk_ptr, P.trunk_ptr.data(), P.trunk_ptr.size() * 8))) return rc;
   if ((rc = put(d.trunk_anchor, P.trunk_anchor.data(), P.trunk_anchor.size() * 8))) return rc;
-  if ((rc = put(d.trunk_gates, P.trunk_gates.data(), P.trunk_gates.size()))) return rc;
-  if ((rc = put(d.trunk_inj, P.trunk_inj.data(), P.trunk_inj.size() * 4))) return rc;
   if ((rc = put(d.inj_ptr, P.inj_ptr.data(), P.inj_ptr.size() * 8))) return rc;
   if ((rc = put(d.inj_src, P.inj_src.data(), P.inj_src.size() * 8))) return rc;
   if ((rc = put(d.item_step_ptr, P.item_step_ptr.data(), P.item_step_ptr.size() * 8))) return rc;
@@ -599,18 +562,11 @@ int run_plan(gst_req* r, const gst_gateset* th, int mode, const double* w, doubl
   a.nTS = P.trunk_steps();
   a.trunk_ptr = d.trunk_ptr;
   a.trunk_anchor = d.trunk_anchor;
-  a.trunk_gates = d.trunk_gates;
-  a.trunk_inj = d.trunk_inj;
+
   a.trunk_adj = d.trunk_adj;
-  a.tinj_ptr = d.tinj_ptr;
-  a.tinj_step = d.tinj_step;
-  a.tinj_slot = d.tinj_slot;
-  a.seg_ptr = d.seg_ptr;
-  a.seg_start = d.seg_start;
-  a.seg_count = d.seg_count;
-  a.seg_pattern = d.seg_pattern;
-  a.seg_gate3 = d.seg_gate3;
-  a.seg_inj = d.seg_inj;
+  a.op_ptr = d.op_ptr;
+  a.op_desc = d.op_desc;
+  a.op_slot = d.op_slot;
   a.n_items = P.n_items();
   a.items = d.items;
   a.item_step_ptr = d.item_step_ptr;

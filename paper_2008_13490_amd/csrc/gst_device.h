@@ -200,42 +200,53 @@ __device__ __forceinline__ Lds carve(double* base, int K) {
 }
 
 // Gate set into LDS, zero-padded to 16 x 16 (and the two padding columns of
-// each row zeroed).  Workgroups of 256 threads: thread (r, c) loads entry
-// (r, c) of every gate and of E up front, so the global loads are in flight
-// together, then writes them and their transposes.
-template <int D>
+// each row zeroed).  Workgroups of NT threads (64 or 256): every thread loads
+// its entries (r, c) of every gate and of E up front, so the global loads are
+// in flight together, then writes them and their transposes.
+template <int D, int NT = 256>
 __device__ void stage_gateset(const Lds& s, const double* __restrict__ G, const double* __restrict__ E,
                               const double* __restrict__ rho, int K, int M) {
-  const int tid = threadIdx.x, r = tid >> 4, c = tid & 15;
-  const bool in = r < D && c < D;
+  static_assert(NT == 64 || NT == 256, "workgroups of 64 or 256 threads");
+  constexpr int U = 256 / NT;
+  const int tid = threadIdx.x;
   const auto* g = as_global(G);
   const auto* e = as_global(E);
-  double v[KMAX];
+  double v[KMAX][U], ex[U];
 #pragma unroll
-  for (int k = 0; k < KMAX; ++k) {
-    const bool use = k < K && in;
-    const double x = g[use ? ((size_t)k * D + r) * D + c : 0];
-    v[k] = use ? x : 0.0;
+  for (int u = 0; u < U; ++u) {
+    const int r = (tid + NT * u) >> 4, c = (tid + NT * u) & 15;
+    const bool in = r < D && c < D;
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) {
+      const bool use = k < K && in;
+      const double x = g[use ? ((size_t)k * D + r) * D + c : 0];
+      v[k][u] = use ? x : 0.0;
+    }
+    const bool use_e = r < M && c < D;
+    const double y = e[use_e ? (size_t)r * D + c : 0];
+    ex[u] = use_e ? y : 0.0;
   }
-  const bool use_e = r < M && c < D;
-  const double ex = e[use_e ? (size_t)r * D + c : 0];
   const double rh = as_global(rho)[tid < D ? tid : 0];
 #pragma unroll
-  for (int k = 0; k < KMAX; ++k) {
-    if (k < K) {
-      s.Gs[k * GATE_STRIDE + r * ROW + c] = v[k];
-      s.GTs[k * GATE_STRIDE + c * ROW + r] = v[k];
-      if (c < ROW - 16) {
-        s.Gs[k * GATE_STRIDE + r * ROW + 16 + c] = 0.0;
-        s.GTs[k * GATE_STRIDE + r * ROW + 16 + c] = 0.0;
+  for (int u = 0; u < U; ++u) {
+    const int r = (tid + NT * u) >> 4, c = (tid + NT * u) & 15;
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) {
+      if (k < K) {
+        s.Gs[k * GATE_STRIDE + r * ROW + c] = v[k][u];
+        s.GTs[k * GATE_STRIDE + c * ROW + r] = v[k][u];
+        if (c < ROW - 16) {
+          s.Gs[k * GATE_STRIDE + r * ROW + 16 + c] = 0.0;
+          s.GTs[k * GATE_STRIDE + r * ROW + 16 + c] = 0.0;
+        }
       }
     }
-  }
-  s.Es[r * ROW + c] = use_e ? ex : 0.0;
-  s.ETs[c * ROW + r] = use_e ? ex : 0.0;
-  if (c < ROW - 16) {
-    s.Es[r * ROW + 16 + c] = 0.0;
-    s.ETs[r * ROW + 16 + c] = 0.0;
+    s.Es[r * ROW + c] = ex[u];
+    s.ETs[c * ROW + r] = ex[u];
+    if (c < ROW - 16) {
+      s.Es[r * ROW + 16 + c] = 0.0;
+      s.ETs[r * ROW + 16 + c] = 0.0;
+    }
   }
   if (tid < 16) s.rho[tid] = tid < D ? rh : 0.0;
   __syncthreads();

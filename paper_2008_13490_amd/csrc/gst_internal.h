@@ -51,18 +51,13 @@ struct PlanArgs {
   int64_t t_begin, t_end;
   const int64_t* trunk_ptr;      // [n_trunks + 1]
   const int64_t* trunk_anchor;   // [n_trunks] location (state after trunk step), -1 = rho
-  const uint8_t* trunk_gates;    // [nTS]
-  const int32_t* trunk_inj;      // [nTS] injection slot of the state after the step, -1 none
   double* trunk_adj;             // [n_trunks][D] adjoint arriving at the anchor
-  const int64_t* tinj_ptr;       // [n_trunks + 1] injection list of each trunk
-  const int32_t* tinj_step;      // step index within the trunk, descending
-  const int64_t* tinj_slot;      // injection slot
-  const int64_t* seg_ptr;        // [n_trunks + 1] periodic segments of each trunk
-  const int32_t* seg_start;
-  const int32_t* seg_count;
-  const uint32_t* seg_pattern;
-  const uint8_t* seg_gate3;
-  const int64_t* seg_inj;        // injection slot at the segment's last step, -1 none
+  // each trunk's chain as ops: bits 0..6 gate index, or jump level with bit 7
+  // set; bits 8..15 the steps the op spans; op_slot = injection slot of the
+  // state after the op (-1 none)
+  const int64_t* op_ptr;         // [n_trunks + 1]
+  const uint32_t* op_desc;
+  const int32_t* op_slot;
   // items
   int64_t n_items;
   const int64_t* items;          // [n_items][4] seq, beg, end, anchor location

@@ -351,6 +351,30 @@ bool build_plan(const int64_t* off, const uint8_t* gates, int64_t S, int K, cons
     }
     P.seg_ptr[r + 1] = (int64_t)P.seg_start.size();
   }
+  // ops of each trunk's chain, from its segments
+  P.op_ptr.assign(nT + 1, 0);
+  for (int64_t r = 0; r < nT; ++r) {
+    for (int64_t sg = P.seg_ptr[r]; sg < P.seg_ptr[r + 1]; ++sg) {
+      const uint32_t pat = P.seg_pattern[sg];
+      const int per = (int)(pat & 0xffu);
+      const int64_t count = P.seg_count[sg];
+      if (per == 0) {  // jumps
+        const uint32_t span = (pat >> 8) & 0xffu, e = (pat >> 16) & 0x7fu;
+        for (int64_t c = 0; c < count; ++c) {
+          P.op_desc.push_back(0x80u | e | span << 8);
+          P.op_slot.push_back(c == count - 1 ? (int32_t)P.seg_inj[sg] : -1);
+        }
+      } else {
+        const uint32_t g[4] = {(pat >> 8) & 0xffu, (pat >> 16) & 0xffu, (pat >> 24) & 0xffu, P.seg_gate3[sg]};
+        for (int64_t c = 0; c < count; ++c)
+          for (int q = 0; q < per; ++q) {
+            P.op_desc.push_back(g[q] | 1u << 8);
+            P.op_slot.push_back(c == count - 1 && q == per - 1 ? (int32_t)P.seg_inj[sg] : -1);
+          }
+      }
+    }
+    P.op_ptr[r + 1] = (int64_t)P.op_desc.size();
+  }
   // fill tasks longest first (load balance)
   if (!P.fill_first.empty()) {
     std::vector<int64_t> ord(P.fill_first.size());

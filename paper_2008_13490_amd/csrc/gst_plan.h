@@ -83,6 +83,13 @@ struct HostPlan {
   std::vector<int32_t> fill_n;           // steps covered by the jump (n - 1 states are filled)
   std::vector<uint32_t> fill_pattern;    // pattern repeated over the n steps
   std::vector<uint8_t> fill_gate3;
+  // The trunk chains as flat op lists (what the trunk kernels run): an op is
+  // one gate step or one jump; bits 0..6 hold the gate index, or the jump
+  // level e with bit 7 set, and bits 8..15 the steps it spans.  op_slot is
+  // the injection slot of the state after the op (-1 none).
+  std::vector<int64_t> op_ptr;           // [n_trunks + 1]
+  std::vector<uint32_t> op_desc;
+  std::vector<int32_t> op_slot;
   int64_t n_items() const { return (int64_t)items.size() / 4; }
   int64_t n_trunks() const { return (int64_t)trunk_anchor.size(); }
   int64_t trunk_steps() const { return (int64_t)trunk_gates.size(); }

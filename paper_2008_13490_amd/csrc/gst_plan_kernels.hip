@@ -33,75 +33,75 @@ __device__ __forceinline__ double load_state(const double* FA, int64_t row, int 
 }
 
 // ---------------------------------------------------------------------------
-// Trunk kernels: one trunk per wave.  The chains are latency bound.  Each
-// trunk's gate word comes as periodic segments (a pattern of 1..4 gates
-// repeated; germ powers are exactly this), so the rows of a segment's gates are
-// loaded into registers once and the steps of the segment run with no memory
-// access other than the store of the result.  Lanes 16..63 repeat the work of
-// lanes 0..15 (same rows, same inputs); only lanes 0..D-1 store.
+// Trunk kernels: one trunk per workgroup of a single wave, so that the wave has
+// its CU's LDS bandwidth to itself.  A trunk's chain is a flat list of ops,
+// each a gate step or a germ-power jump; the rows of the next op are read
+// from LDS while the current op's product runs.  The chains are latency
+// bound.  Lanes 16..63 repeat the work of lanes 0..15 (same rows, same
+// inputs); only lanes 0..D-1 store.
 // ---------------------------------------------------------------------------
-constexpr int SEGW = 64;  // segment descriptors held at a time (one per lane)
+constexpr int OPW = 64;  // op descriptors held at a time (one per lane)
 
-// Doubles of LDS in front of the per-wave staging of injected vectors (the
-// gate set, its transpose, the effects and rho).
+// Doubles of LDS in front of the staging of injected vectors (the gate set,
+// its transpose, the effects and rho).
 __host__ __device__ inline size_t trunk_head_doubles(int K) {
   return (size_t)2 * K * GATE_STRIDE + 2 * 16 * ROW + 16;
+}
+
+// A workgroup's head row [objective | dL/drho | dL/dE]: every 16-lane team
+// leaves its partial sums in LDS (no shuffles across teams), and the
+// workgroup adds the team partials in a fixed order.
+constexpr int HEAD_W = 1 + 16 + 256;
+__host__ __device__ inline size_t head_red_bytes(int n_waves) { return (size_t)n_waves * TPW * HEAD_W * 8; }
+
+template <int D, bool WITH_E, int NW>
+__device__ void write_head(double* lds_raw, double obj, double drho, const double (&dE)[16], int M, double* out) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, i = lane & 15, team = lane >> 4;
+  __syncthreads();  // LDS is reused from here on
+  double* mine = lds_raw + (size_t)(wave * TPW + team) * HEAD_W;
+  double o = obj;
+#pragma unroll
+  for (int sh = 1; sh < 16; sh <<= 1) o += __shfl_xor(o, sh);
+  if (i == 0) mine[0] = o;
+  mine[1 + i] = drho;
+  if (WITH_E) {
+#pragma unroll
+    for (int m = 0; m < 16; ++m)
+      if (m < M) mine[17 + m * 16 + i] = dE[m];
+  }
+  __syncthreads();
+  const int H = 1 + D + M * D;
+  for (int x = tid; x < H; x += blockDim.x) {
+    int src = -1;
+    if (x < 1 + D) {
+      src = x;
+    } else if (WITH_E) {
+      const int y = x - 1 - D;
+      src = 17 + (y / D) * 16 + (y % D);
+    }
+    double v = 0.0;
+    if (src >= 0) {
+#pragma unroll
+      for (int p = 0; p < NW * TPW; ++p) v += lds_raw[p * HEAD_W + src];
+    }
+    out[x] = v;
+  }
 }
 
 // Item and fill workgroups hold only the gate set (no checkpoint stash); the
 // head-row reduction reuses it afterwards.
 __host__ __device__ inline size_t item_lds_bytes(int K) {
-  const size_t a = trunk_head_doubles(K) * 8, r = (size_t)WAVES * (1 + 16 + 256) * 8;
+  const size_t a = trunk_head_doubles(K) * 8, r = head_red_bytes(WAVES);
   return (a > r ? a : r) + 64;
 }
 
-// Per wave after the staging area: the trunk's jump matrices, `levels` of
-// them in the gate layout.
-__host__ __device__ inline size_t trunk_jump_doubles(int K, int wave, int levels) {
-  return trunk_head_doubles(K) + (size_t)WAVES * SEGW * 16 + (size_t)wave * levels * GATE_STRIDE;
-}
+// After the staging area: the trunk's jump matrices in the gate layout.
+__host__ __device__ inline size_t trunk_jump_doubles(int K) { return trunk_head_doubles(K) + (size_t)OPW * 16; }
 
 __host__ __device__ inline size_t trunk_lds_bytes(int K, int levels) {
-  const size_t a = trunk_jump_doubles(K, WAVES, levels) * 8 + 64;
-  const size_t r = lds_red_bytes(K);
+  const size_t a = (trunk_jump_doubles(K) + (size_t)levels * GATE_STRIDE) * 8 + 64;
+  const size_t r = head_red_bytes(1);
   return a > r ? a : r;
-}
-
-struct Seg {
-  int start, count, per, g0, g1, g2, g3;
-};
-
-// Descriptors of up to 64 consecutive segments, lane j holding segment
-// base + j: one batch of loads per 64 segments instead of a dependent load
-// at the start of every segment (segments can be a single step long).
-struct SegLanes {
-  int start, count, pat, g3;
-  int64_t slot;
-};
-
-__device__ __forceinline__ SegLanes load_seg_lanes(const PlanArgs& a, int64_t sg, int64_t sg_end, bool want_slot) {
-  SegLanes d{0, 0, 0, 0, -1};
-  if (sg < sg_end) {
-    d.start = a.seg_start[sg];
-    d.count = a.seg_count[sg];
-    d.pat = (int)a.seg_pattern[sg];
-    d.g3 = (int)a.seg_gate3[sg];
-    if (want_slot) d.slot = a.seg_inj[sg];
-  }
-  return d;
-}
-
-__device__ __forceinline__ Seg seg_of(const SegLanes& d, int x) {
-  Seg g;
-  const uint32_t pat = (uint32_t)__builtin_amdgcn_readlane(d.pat, x);
-  g.start = __builtin_amdgcn_readlane(d.start, x);
-  g.count = __builtin_amdgcn_readlane(d.count, x);
-  g.per = (int)(pat & 0xffu);
-  g.g0 = (int)((pat >> 8) & 0xffu);
-  g.g1 = (int)((pat >> 16) & 0xffu);
-  g.g2 = (int)((pat >> 24) & 0xffu);
-  g.g3 = __builtin_amdgcn_readlane(d.g3, x);
-  return g;
 }
 
 // C = A B for 16 x 16 matrices in the gate layout, by one wave: column c of
@@ -141,87 +141,58 @@ __device__ void build_jumps(double* js, const double* gates, uint32_t pat, int g
     wave_matmul(js + e * GATE_STRIDE, js + (e - 1) * GATE_STRIDE, js + (e - 1) * GATE_STRIDE, lane);
 }
 
+// Lane i's row of the matrix of op `od`: a gate (of the gate set or its
+// transpose) or a jump matrix slot.
+__device__ __forceinline__ const double* op_row(const double* gates, const double* js, uint32_t od, int i) {
+  const double* base = (od & 0x80u) ? js : gates;
+  return base + (od & 0x7fu) * GATE_STRIDE + i * ROW;
+}
+
+__device__ __forceinline__ uint32_t lane_u32(uint32_t v, int x) {
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, x);
+}
+
 template <int D>
-__global__ __launch_bounds__(256) void trunk_fwd_kernel(const PlanArgs a) {
+__global__ __launch_bounds__(64) void trunk_fwd_kernel(const PlanArgs a) {
   extern __shared__ double lds_raw[];
   const int K = a.K;
   const Lds s = carve(lds_raw, K);
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, i = lane & 15;
-  stage_gateset<D>(s, a.G, a.E, a.rho, K, a.M);
-  if (blockIdx.x == 0 && tid < D) a.FA[tid] = a.rho[tid];
-  const double* gl = s.Gs + i * ROW;
-  double* js = lds_raw + trunk_jump_doubles(K, wave, a.jump_levels);
-  for (int64_t t = a.t_begin + (int64_t)blockIdx.x * WAVES + wave; t < a.t_end; t += (int64_t)gridDim.x * WAVES) {
+  const int lane = threadIdx.x & 63, i = lane & 15;
+  stage_gateset<D, 64>(s, a.G, a.E, a.rho, K, a.M);
+  if (blockIdx.x == 0 && lane < D) a.FA[lane] = a.rho[lane];
+  double* js = lds_raw + trunk_jump_doubles(K);
+  const bool st = (D == 16) || lane < D;  // rows 1..3 store the same values as row 0
+  for (int64_t t = a.t_begin + blockIdx.x; t < a.t_end; t += gridDim.x) {
     const int64_t beg = a.trunk_ptr[t];
     const int64_t anc = a.trunk_anchor[t];
+    const int64_t o0 = a.op_ptr[t], o1 = a.op_ptr[t + 1];
     const uint32_t jp = (uint32_t)__builtin_amdgcn_readfirstlane((int)a.trunk_jpat[t]);
     if (jp != 0u) build_jumps(js, s.Gs, jp, a.trunk_jg3[t], a.jump_levels, false, lane);
     double f = anc >= 0 ? load_state(a.FA, 1 + anc, D, i) : s.rho[i];
-    double* out = a.FA + (1 + beg) * D + i;
-    const bool st = (D == 16) || lane < D;  // rows 1..3 store the same values as row 0
-    const int64_t sg0 = a.seg_ptr[t], sg1 = a.seg_ptr[t + 1];
-    for (int64_t cb = sg0; cb < sg1; cb += SEGW) {
-    const SegLanes d = load_seg_lanes(a, cb + lane, sg1, false);
-    const int n = (int)(sg1 - cb < SEGW ? sg1 - cb : SEGW);
-    for (int x = 0; x < n; ++x) {
-      const Seg g = seg_of(d, x);
-      if (g.per == 0) {  // count jumps of g.g0 steps by jump matrix g.g1; the state after each is stored
-        const Row16 RC = load_row(js + g.g1 * GATE_STRIDE + i * ROW);
-        const int64_t stride = g.g0;
-        double* o = out + (g.start + stride - 1) * D;
-        for (int c = 0; c < g.count; ++c) {
-          f = dot16(f, RC);
-          if (st) o[0] = f;
-          o += stride * D;
-        }
-        continue;
+    double* out = a.FA + (1 + beg) * D + i;  // state after trunk step j: out[j*D]
+    int64_t pos = 0;                         // steps done
+    for (int64_t ob = o0; ob < o1; ob += OPW) {
+      const int n = (int)(o1 - ob < OPW ? o1 - ob : OPW);
+      const uint32_t dl = ob + lane < o1 ? a.op_desc[ob + lane] : 0u;
+      // two ops per iteration, the rows of the next op in flight
+      Row16 RA = load_row(op_row(s.Gs, js, lane_u32(dl, 0), i));
+      int x = 0;
+      for (; x + 2 <= n; x += 2) {
+        const uint32_t d0 = lane_u32(dl, x), d1 = lane_u32(dl, x + 1);
+        const Row16 RB = load_row(op_row(s.Gs, js, d1, i));
+        f = dot16(f, RA);
+        pos += (d0 >> 8) & 0xffu;
+        if (st) out[(pos - 1) * D] = f;
+        RA = load_row(op_row(s.Gs, js, lane_u32(dl, x + 2 < n ? x + 2 : x + 1), i));
+        f = dot16(f, RB);
+        pos += (d1 >> 8) & 0xffu;
+        if (st) out[(pos - 1) * D] = f;
       }
-      double* o = out + (int64_t)g.start * D;
-      const Row16 R0 = load_row(gl + g.g0 * GATE_STRIDE);
-      if (g.per == 1) {
-        for (int c = 0; c < g.count; ++c) {
-          f = dot16(f, R0);
-          if (st) o[0] = f;
-          o += D;
-        }
-      } else if (g.per == 2) {
-        const Row16 R1 = load_row(gl + g.g1 * GATE_STRIDE);
-        for (int c = 0; c < g.count; ++c) {
-          f = dot16(f, R0);
-          if (st) o[0] = f;
-          f = dot16(f, R1);
-          if (st) o[D] = f;
-          o += 2 * D;
-        }
-      } else if (g.per == 3) {
-        const Row16 R1 = load_row(gl + g.g1 * GATE_STRIDE);
-        const Row16 R2 = load_row(gl + g.g2 * GATE_STRIDE);
-        for (int c = 0; c < g.count; ++c) {
-          f = dot16(f, R0);
-          if (st) o[0] = f;
-          f = dot16(f, R1);
-          if (st) o[D] = f;
-          f = dot16(f, R2);
-          if (st) o[2 * D] = f;
-          o += 3 * D;
-        }
-      } else {
-        const Row16 R1 = load_row(gl + g.g1 * GATE_STRIDE);
-        const Row16 R2 = load_row(gl + g.g2 * GATE_STRIDE);
-        const Row16 R3 = load_row(gl + g.g3 * GATE_STRIDE);
-        for (int c = 0; c < g.count; ++c) {
-          f = dot16(f, R0);
-          if (st) o[0] = f;
-          f = dot16(f, R1);
-          if (st) o[D] = f;
-          f = dot16(f, R2);
-          if (st) o[2 * D] = f;
-          f = dot16(f, R3);
-          if (st) o[3 * D] = f;
-          o += 4 * D;
-        }
+      if (x < n) {
+        f = dot16(f, RA);
+        pos += (lane_u32(dl, x) >> 8) & 0xffu;
+        if (st) out[(pos - 1) * D] = f;
       }
-    }
     }
   }
 }
@@ -341,108 +312,81 @@ __global__ __launch_bounds__(256) void item_kernel(const PlanArgs a) {
     if (a.req_nonpos) atomicAdd(a.req_nonpos, (unsigned long long)nonpos);
   }
   if (a.mode != MODE_LOGLIK && !grad) return;
-  d4 none[KMAX];
-  write_slab<D>(lds_raw, obj, drho, dE, none, M, 0, a.slab + (int64_t)blockIdx.x * slab_width(D, M, 0));
+  write_head<D, true, WAVES>(lds_raw, obj, drho, dE, M, a.slab + (int64_t)blockIdx.x * slab_width(D, M, 0));
 }
 
 // ---------------------------------------------------------------------------
-// trunk reverse sweep, one trunk per wave: segments in reverse, G^T rows of a
-// segment in registers; adjoints injected at stored states (a descending list
-// per trunk, staged in LDS) are added on the way back
+// trunk reverse sweep, one trunk per workgroup of a single wave: ops in
+// reverse with the transposed rows; the adjoints injected at stored states
+// (64 ops at a time, staged in LDS) are added on the way back
 // ---------------------------------------------------------------------------
 template <int D>
-__global__ __launch_bounds__(256) void trunk_bwd_kernel(const PlanArgs a) {
+__global__ __launch_bounds__(64) void trunk_bwd_kernel(const PlanArgs a) {
   extern __shared__ double lds_raw[];
   const int K = a.K;
   const Lds s = carve(lds_raw, K);
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, i = lane & 15;
-  stage_gateset<D>(s, a.G, a.E, a.rho, K, a.M);
-  const double* gl = s.GTs + i * ROW;
-  double* inj_st = lds_raw + trunk_head_doubles(K) + (size_t)wave * SEGW * 16;
-  double* js = lds_raw + trunk_jump_doubles(K, wave, a.jump_levels);
+  const int lane = threadIdx.x & 63, i = lane & 15, team = lane >> 4;
+  stage_gateset<D, 64>(s, a.G, a.E, a.rho, K, a.M);
+  double* inj_st = lds_raw + trunk_head_doubles(K);
+  double* js = lds_raw + trunk_jump_doubles(K);
+  const bool st = (D == 16) || lane < D;
   double drho = 0.0;
-  for (int64_t t = a.t_begin + (int64_t)blockIdx.x * WAVES + wave; t < a.t_end; t += (int64_t)gridDim.x * WAVES) {
+  for (int64_t t = a.t_begin + blockIdx.x; t < a.t_end; t += gridDim.x) {
     const int64_t beg = a.trunk_ptr[t];
+    const int64_t o0 = a.op_ptr[t], o1 = a.op_ptr[t + 1];
     const uint32_t jp = (uint32_t)__builtin_amdgcn_readfirstlane((int)a.trunk_jpat[t]);
     if (jp != 0u) build_jumps(js, s.GTs, jp, a.trunk_jg3[t], a.jump_levels, true, lane);
-    double* ba = a.BA + beg * D + i;
-    const bool st = (D == 16) || lane < D;
-    const int64_t sg0 = a.seg_ptr[t], sg1 = a.seg_ptr[t + 1];
+    double* ba = a.BA + beg * D + i;  // adjoint after trunk step j: ba[j*D]
+    int64_t pos = a.trunk_ptr[t + 1] - beg;
     double b = 0.0;
-#define GST_TBSTEP(RT, J)                    \
-  {                                          \
-    if (st) ba[(int64_t)(J) * D] = b;        \
-    b = dot16(b, RT);                  \
-  }
-    // segments in reverse, 64 at a time: their descriptors in registers and
-    // their injected vectors (the adjoint arriving at the state after each
-    // segment's last step) staged in this wave's LDS, all loaded up front
-    for (int64_t ce = sg1; ce > sg0; ce -= SEGW) {
-    const int64_t cb = ce - SEGW > sg0 ? ce - SEGW : sg0;
-    const int n = (int)(ce - cb);
-    const SegLanes d = load_seg_lanes(a, cb + lane, ce, true);
-    wave_sync();  // the previous chunk's vectors have been read
-#pragma unroll 4
-    for (int q = 0; q < SEGW / 4; ++q) {
-      const int x = 4 * q + (lane >> 4);
-      const int64_t slot = __shfl(d.slot, x);
-      const double v = (x < n && slot >= 0 && i < D) ? a.inj[slot * D + i] : 0.0;
-      inj_st[x * 16 + i] = v;
-    }
-    wave_sync();
-    for (int x = n - 1; x >= 0; --x) {
-      const Seg g = seg_of(d, x);
-      b += inj_st[x * 16 + i];  // adjoint arriving at the state after the segment's last step
-      if (g.per == 0) {  // jumps in reverse with the transposed matrix
-        const Row16 RC = load_row(js + g.g1 * GATE_STRIDE + i * ROW);
-        const int stride = g.g0;
-        for (int c = g.count - 1; c >= 0; --c) GST_TBSTEP(RC, g.start + (c + 1) * stride - 1)
-        continue;
+    for (int64_t oe = o1; oe > o0; oe -= OPW) {
+      const int64_t ob = oe - OPW > o0 ? oe - OPW : o0;
+      const int n = (int)(oe - ob);
+      const uint32_t dl = ob + lane < oe ? a.op_desc[ob + lane] : 0u;
+      const int32_t sl = ob + lane < oe ? a.op_slot[ob + lane] : -1;
+      // the vectors injected at the states after these ops, all loads in flight
+      wave_sync();  // the previous batch's vectors have been read
+      double v[OPW / TPW];
+#pragma unroll
+      for (int q = 0; q < OPW / TPW; ++q) {
+        const int x = TPW * q + team;
+        const int32_t slot = __shfl(sl, x);
+        const bool use = x < n && slot >= 0 && i < D;
+        const double val = a.inj[(use ? (int64_t)slot * D + i : 0)];
+        v[q] = use ? val : 0.0;
       }
-      const Row16 R0 = load_row(gl + g.g0 * GATE_STRIDE);
-      if (g.per == 1) {
-        for (int c = g.count - 1; c >= 0; --c) GST_TBSTEP(R0, g.start + c)
-      } else if (g.per == 2) {
-        const Row16 R1 = load_row(gl + g.g1 * GATE_STRIDE);
-        for (int c = g.count - 1; c >= 0; --c) {
-          const int j0 = g.start + 2 * c;
-          GST_TBSTEP(R1, j0 + 1)
-          GST_TBSTEP(R0, j0)
-        }
-      } else if (g.per == 3) {
-        const Row16 R1 = load_row(gl + g.g1 * GATE_STRIDE);
-        const Row16 R2 = load_row(gl + g.g2 * GATE_STRIDE);
-        for (int c = g.count - 1; c >= 0; --c) {
-          const int j0 = g.start + 3 * c;
-          GST_TBSTEP(R2, j0 + 2)
-          GST_TBSTEP(R1, j0 + 1)
-          GST_TBSTEP(R0, j0)
-        }
-      } else {
-        const Row16 R1 = load_row(gl + g.g1 * GATE_STRIDE);
-        const Row16 R2 = load_row(gl + g.g2 * GATE_STRIDE);
-        const Row16 R3 = load_row(gl + g.g3 * GATE_STRIDE);
-        for (int c = g.count - 1; c >= 0; --c) {
-          const int j0 = g.start + 4 * c;
-          GST_TBSTEP(R3, j0 + 3)
-          GST_TBSTEP(R2, j0 + 2)
-          GST_TBSTEP(R1, j0 + 1)
-          GST_TBSTEP(R0, j0)
-        }
+#pragma unroll
+      for (int q = 0; q < OPW / TPW; ++q) inj_st[(TPW * q + team) * 16 + i] = v[q];
+      wave_sync();
+      Row16 RA = load_row(op_row(s.GTs, js, lane_u32(dl, n - 1), i));
+      int x = n - 1;
+      for (; x >= 1; x -= 2) {
+        const uint32_t d0 = lane_u32(dl, x), d1 = lane_u32(dl, x - 1);
+        const Row16 RB = load_row(op_row(s.GTs, js, d1, i));
+        b += inj_st[x * 16 + i];
+        if (st) ba[(pos - 1) * D] = b;
+        b = dot16(b, RA);
+        pos -= (d0 >> 8) & 0xffu;
+        RA = load_row(op_row(s.GTs, js, lane_u32(dl, x >= 2 ? x - 2 : x - 1), i));
+        b += inj_st[(x - 1) * 16 + i];
+        if (st) ba[(pos - 1) * D] = b;
+        b = dot16(b, RB);
+        pos -= (d1 >> 8) & 0xffu;
+      }
+      if (x == 0) {
+        b += inj_st[i];
+        if (st) ba[(pos - 1) * D] = b;
+        b = dot16(b, RA);
+        pos -= (lane_u32(dl, 0) >> 8) & 0xffu;
       }
     }
-    }
-#undef GST_TBSTEP
     if (lane < D) a.trunk_adj[t * D + i] = b;
     if (a.trunk_anchor[t] < 0) drho += b;
   }
   // lanes 16..63 repeat lanes 0..15: only row 0 contributes
   if (lane >= 16) drho = 0.0;
-  double dE[16];
-#pragma unroll
-  for (int m = 0; m < 16; ++m) dE[m] = 0.0;
-  d4 none[KMAX];
-  write_slab<D>(lds_raw, 0.0, drho, dE, none, a.M, 0, a.slab + (int64_t)blockIdx.x * slab_width(D, a.M, 0));
+  const double no_dE[16] = {};
+  write_head<D, false, 1>(lds_raw, 0.0, drho, no_dE, a.M, a.slab + (int64_t)blockIdx.x * slab_width(D, a.M, 0));
 }
 
 // ---------------------------------------------------------------------------
@@ -617,7 +561,17 @@ __global__ __launch_bounds__(256) void plan_reduce_stage1(const PlanReduce a) {
     G = parts_of(R.n);
     const int64_t per = (R.n + G - 1) / G, w0 = g * per, w1 = min(R.n, w0 + per);
     if (g < G)
-      for (int64_t w = w0 + ty; w < w1; w += 4) v += R.src[w * R.stride];
+      for (int64_t w = w0 + ty; w < w1; w += 32) {  // rows w, w+4, ..., eight loads in flight
+        double t[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int64_t ww = w + 4 * u;
+          const double val = R.src[(ww < w1 ? ww : w1 - 1) * R.stride];
+          t[u] = ww < w1 ? val : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v += t[u];
+      }
   }
   red[ty][tx] = v;
   __syncthreads();
@@ -633,9 +587,17 @@ __global__ __launch_bounds__(256) void plan_reduce_stage2(const PlanReduce a) {
   const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
   const int64_t x = (int64_t)blockIdx.x * 64 + tx;
   double v = 0.0;
-  if (x < a.P) {
+  if (x < a.P) {  // partials g = ty, ty+4, ... (at most 16), all loads in flight
     const int G = parts_of(rows_of(a, x).n);
-    for (int g = ty; g < G; g += 4) v += a.part[(int64_t)g * a.P + x];
+    double t[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int g = ty + 4 * u;
+      const double val = a.part[(int64_t)(g < G ? g : 0) * a.P + x];
+      t[u] = g < G ? val : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u) v += t[u];
   }
   red[ty][tx] = v;
   if (ty == 1) {
@@ -669,17 +631,16 @@ int item_blocks_for(int64_t n_items) {
 }
 
 int trunk_blocks_for(int64_t n) {
-  int64_t b = (n + WAVES - 1) / WAVES;
-  return (int)(b < 1 ? 1 : (b > 4096 ? 4096 : b));
+  return (int)(n < 1 ? 1 : (n > 65535 ? 65535 : n));  // one single-wave workgroup per trunk
 }
 
 hipError_t launch_trunk_fwd(const PlanArgs& a, hipStream_t stream) {
   const int blocks = trunk_blocks_for(a.t_end - a.t_begin);
   const size_t bytes = trunk_lds_bytes(a.K, a.jump_levels);
   if (a.D == 16)
-    hipLaunchKernelGGL(trunk_fwd_kernel<16>, dim3(blocks), dim3(256), bytes, stream, a);
+    hipLaunchKernelGGL(trunk_fwd_kernel<16>, dim3(blocks), dim3(64), bytes, stream, a);
   else if (a.D == 4)
-    hipLaunchKernelGGL(trunk_fwd_kernel<4>, dim3(blocks), dim3(256), bytes, stream, a);
+    hipLaunchKernelGGL(trunk_fwd_kernel<4>, dim3(blocks), dim3(64), bytes, stream, a);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
@@ -689,9 +650,9 @@ hipError_t launch_trunk_bwd(const PlanArgs& a, hipStream_t stream) {
   const int blocks = trunk_blocks_for(a.t_end - a.t_begin);
   const size_t bytes = trunk_lds_bytes(a.K, a.jump_levels);
   if (a.D == 16)
-    hipLaunchKernelGGL(trunk_bwd_kernel<16>, dim3(blocks), dim3(256), bytes, stream, a);
+    hipLaunchKernelGGL(trunk_bwd_kernel<16>, dim3(blocks), dim3(64), bytes, stream, a);
   else if (a.D == 4)
-    hipLaunchKernelGGL(trunk_bwd_kernel<4>, dim3(blocks), dim3(256), bytes, stream, a);
+    hipLaunchKernelGGL(trunk_bwd_kernel<4>, dim3(blocks), dim3(64), bytes, stream, a);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();

@@ -93,3 +93,12 @@ extern "C" void plan_copy_jumps(uint32_t* pattern, uint8_t* g3, int64_t* first, 
   std::memcpy(fpat, P.fill_pattern.data(), P.fill_pattern.size() * 4);
   std::memcpy(fg3, P.fill_gate3.data(), P.fill_gate3.size());
 }
+
+extern "C" int64_t plan_n_ops() { return (int64_t)g_plan.op_desc.size(); }
+
+extern "C" void plan_copy_ops(int64_t* op_ptr, uint32_t* desc, int32_t* slot) {
+  const gst::HostPlan& P = g_plan;
+  std::memcpy(op_ptr, P.op_ptr.data(), P.op_ptr.size() * 8);
+  std::memcpy(desc, P.op_desc.data(), P.op_desc.size() * 4);
+  std::memcpy(slot, P.op_slot.data(), P.op_slot.size() * 4);
+}

@@ -37,6 +37,8 @@ def planlib(tmp_path_factory):
     lib.plan_set_jump.argtypes = [ctypes.c_int, ctypes.c_int]
     lib.plan_jump_sizes.argtypes = [P]
     lib.plan_copy_jumps.argtypes = [P] * 7
+    lib.plan_n_ops.restype = ctypes.c_int64
+    lib.plan_copy_ops.argtypes = [P] * 3
     return lib
 
 
@@ -88,6 +90,12 @@ def get_plan(lib, sl, K, min_trunk=24, reanchor=8, ratio=0.8):
             P[k] = P[k][:nT]
         for k in ("fill_first", "fill_in", "fill_n", "fill_pattern", "fill_gate3"):
             P[k] = P[k][:nF]
+        nOp = int(lib.plan_n_ops())
+        P["op_ptr"] = np.zeros(nT + 1, np.int64)
+        P["op_desc"] = np.zeros(max(nOp, 1), np.uint32)
+        P["op_slot"] = np.zeros(max(nOp, 1), np.int32)
+        lib.plan_copy_ops(P["op_ptr"].ctypes.data, P["op_desc"].ctypes.data, P["op_slot"].ctypes.data)
+        P["op_desc"], P["op_slot"] = P["op_desc"][:nOp], P["op_slot"][:nOp]
     P["trunk_gates"] = P["trunk_gates"][:nTS]
     P["trunk_inj"] = P["trunk_inj"][:nTS]
     P["inj_loc"] = P["inj_loc"][:nJ]
@@ -478,3 +486,41 @@ def test_germ_power_jumps(planlib, name, jump):
                 for sg in range(P["seg_ptr"][t], P["seg_ptr"][t + 1]))
     if name == "c2" and jump == 8:
         assert chain * 4 < tp[t + 1] - tp[t]
+
+
+@pytest.mark.parametrize("name,jump", [("c1", 8), ("c2", 8), ("c2", 0)])
+def test_trunk_ops(planlib, name, jump):
+    """The trunk kernels' op lists: spans add up to the trunk, expanding the ops
+    (a gate, or a jump standing for 2^e repetitions of the trunk's pattern)
+    gives the trunk's word, and every state that receives an injection ends an
+    op and carries its slot there."""
+    w = W.structured_workload(name)
+    planlib.plan_set_jump(jump, 12)
+    try:
+        P = get_plan(planlib, w.seqs, w.model.K)
+    finally:
+        planlib.plan_set_jump(8, 12)
+    tp, tg, ti = P["trunk_ptr"], P["trunk_gates"], P["trunk_inj"]
+    op = P["op_ptr"]
+    n_jump_ops = 0
+    for t in range(len(tp) - 1):
+        word, pos = [], 0
+        for o in range(op[t], op[t + 1]):
+            d = int(P["op_desc"][o])
+            span = (d >> 8) & 0xff
+            if d & 0x80:
+                n_jump_ops += 1
+                e = d & 0x7f
+                gates = pattern_gates(int(P["jump_pattern"][t]), P["jump_gate3"][t])
+                assert span == (1 << e) * len(gates)
+                word += gates * (1 << e)
+                # no injection inside a jump
+                assert np.all(ti[tp[t] + pos:tp[t] + pos + span - 1] < 0)
+            else:
+                assert span == 1
+                word.append(d & 0x7f)
+            pos += span
+            assert P["op_slot"][o] == ti[tp[t] + pos - 1]
+        assert pos == tp[t + 1] - tp[t]
+        assert word == list(tg[tp[t]:tp[t + 1]])
+    assert (n_jump_ops > 0) == (jump > 0)
