@@ -199,11 +199,16 @@ __device__ __forceinline__ Lds carve(double* base, int K) {
   return l;
 }
 
+// Parts of the gate set a kernel stages (stage_gateset's PARTS).
+constexpr int STAGE_G = 1, STAGE_GT = 2, STAGE_E = 4, STAGE_ALL = 7;
+
 // Gate set into LDS, zero-padded to 16 x 16 (and the two padding columns of
-// each row zeroed).  Workgroups of NT threads (64 or 256): every thread loads
-// its entries (r, c) of every gate and of E up front, so the global loads are
-// in flight together, then writes them and their transposes.
-template <int D, int NT = 256>
+// each row zeroed): the gates (Gs), their transposes (GTs) and the effects
+// with their transposes, as PARTS selects; rho always.  Workgroups of NT
+// threads (64 or 256): every thread loads its entries (r, c) of every gate
+// and of E up front, so the global loads are in flight together, then writes
+// them.
+template <int D, int NT = 256, int PARTS = STAGE_ALL>
 __device__ void stage_gateset(const Lds& s, const double* __restrict__ G, const double* __restrict__ E,
                               const double* __restrict__ rho, int K, int M) {
   static_assert(NT == 64 || NT == 256, "workgroups of 64 or 256 threads");
@@ -222,9 +227,12 @@ __device__ void stage_gateset(const Lds& s, const double* __restrict__ G, const 
       const double x = g[use ? ((size_t)k * D + r) * D + c : 0];
       v[k][u] = use ? x : 0.0;
     }
-    const bool use_e = r < M && c < D;
-    const double y = e[use_e ? (size_t)r * D + c : 0];
-    ex[u] = use_e ? y : 0.0;
+    ex[u] = 0.0;
+    if (PARTS & STAGE_E) {
+      const bool use_e = r < M && c < D;
+      const double y = e[use_e ? (size_t)r * D + c : 0];
+      ex[u] = use_e ? y : 0.0;
+    }
   }
   const double rh = as_global(rho)[tid < D ? tid : 0];
 #pragma unroll
@@ -233,19 +241,23 @@ __device__ void stage_gateset(const Lds& s, const double* __restrict__ G, const 
 #pragma unroll
     for (int k = 0; k < KMAX; ++k) {
       if (k < K) {
-        s.Gs[k * GATE_STRIDE + r * ROW + c] = v[k][u];
-        s.GTs[k * GATE_STRIDE + c * ROW + r] = v[k][u];
-        if (c < ROW - 16) {
-          s.Gs[k * GATE_STRIDE + r * ROW + 16 + c] = 0.0;
-          s.GTs[k * GATE_STRIDE + r * ROW + 16 + c] = 0.0;
+        if (PARTS & STAGE_G) {
+          s.Gs[k * GATE_STRIDE + r * ROW + c] = v[k][u];
+          if (c < ROW - 16) s.Gs[k * GATE_STRIDE + r * ROW + 16 + c] = 0.0;
+        }
+        if (PARTS & STAGE_GT) {
+          s.GTs[k * GATE_STRIDE + c * ROW + r] = v[k][u];
+          if (c < ROW - 16) s.GTs[k * GATE_STRIDE + r * ROW + 16 + c] = 0.0;
         }
       }
     }
-    s.Es[r * ROW + c] = ex[u];
-    s.ETs[c * ROW + r] = ex[u];
-    if (c < ROW - 16) {
-      s.Es[r * ROW + 16 + c] = 0.0;
-      s.ETs[r * ROW + 16 + c] = 0.0;
+    if (PARTS & STAGE_E) {
+      s.Es[r * ROW + c] = ex[u];
+      s.ETs[c * ROW + r] = ex[u];
+      if (c < ROW - 16) {
+        s.Es[r * ROW + 16 + c] = 0.0;
+        s.ETs[r * ROW + 16 + c] = 0.0;
+      }
     }
   }
   if (tid < 16) s.rho[tid] = tid < D ? rh : 0.0;

@@ -375,20 +375,43 @@ bool build_plan(const int64_t* off, const uint8_t* gates, int64_t S, int K, cons
     }
     P.op_ptr[r + 1] = (int64_t)P.op_desc.size();
   }
-  // fill tasks longest first (load balance)
+  // fill tasks grouped by pattern period, longest first within a period, and
+  // each period's group padded to a multiple of four with empty tasks (one
+  // step, nothing to fill): the four tasks of a wave share their period, so
+  // the kernel keeps their pattern rows in registers and steps through the
+  // phases in lockstep
   if (!P.fill_first.empty()) {
     std::vector<int64_t> ord(P.fill_first.size());
     for (size_t x = 0; x < ord.size(); ++x) ord[x] = (int64_t)x;
-    std::stable_sort(ord.begin(), ord.end(), [&](int64_t x, int64_t y) { return P.fill_n[x] > P.fill_n[y]; });
-    auto perm = [&](auto& v) {
-      auto c = v;
-      for (size_t x = 0; x < ord.size(); ++x) v[x] = c[ord[x]];
-    };
-    perm(P.fill_first);
-    perm(P.fill_in);
-    perm(P.fill_n);
-    perm(P.fill_pattern);
-    perm(P.fill_gate3);
+    auto per_of = [&](int64_t x) { return (int)(P.fill_pattern[x] & 0xffu); };
+    std::stable_sort(ord.begin(), ord.end(), [&](int64_t x, int64_t y) {
+      return per_of(x) != per_of(y) ? per_of(x) < per_of(y) : P.fill_n[x] > P.fill_n[y];
+    });
+    std::vector<int64_t> first, in;
+    std::vector<int32_t> nn;
+    std::vector<uint32_t> pat;
+    std::vector<uint8_t> g3;
+    for (size_t x = 0; x < ord.size(); ++x) {
+      const int64_t o = ord[x];
+      first.push_back(P.fill_first[o]);
+      in.push_back(P.fill_in[o]);
+      nn.push_back(P.fill_n[o]);
+      pat.push_back(P.fill_pattern[o]);
+      g3.push_back(P.fill_gate3[o]);
+      const bool group_end = x + 1 == ord.size() || per_of(ord[x + 1]) != per_of(o);
+      while (group_end && first.size() % 4 != 0) {
+        first.push_back(0);
+        in.push_back(0);
+        nn.push_back(1);
+        pat.push_back((uint32_t)per_of(o));
+        g3.push_back(0);
+      }
+    }
+    P.fill_first.swap(first);
+    P.fill_in.swap(in);
+    P.fill_n.swap(nn);
+    P.fill_pattern.swap(pat);
+    P.fill_gate3.swap(g3);
   }
 
   P.trunk_anchor_inj.assign(nT, -1);

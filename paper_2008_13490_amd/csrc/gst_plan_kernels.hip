@@ -158,7 +158,7 @@ __global__ __launch_bounds__(64) void trunk_fwd_kernel(const PlanArgs a) {
   const int K = a.K;
   const Lds s = carve(lds_raw, K);
   const int lane = threadIdx.x & 63, i = lane & 15;
-  stage_gateset<D, 64>(s, a.G, a.E, a.rho, K, a.M);
+  stage_gateset<D, 64, STAGE_G>(s, a.G, a.E, a.rho, K, a.M);
   if (blockIdx.x == 0 && lane < D) a.FA[lane] = a.rho[lane];
   double* js = lds_raw + trunk_jump_doubles(K);
   const bool st = (D == 16) || lane < D;  // rows 1..3 store the same values as row 0
@@ -174,25 +174,25 @@ __global__ __launch_bounds__(64) void trunk_fwd_kernel(const PlanArgs a) {
     for (int64_t ob = o0; ob < o1; ob += OPW) {
       const int n = (int)(o1 - ob < OPW ? o1 - ob : OPW);
       const uint32_t dl = ob + lane < o1 ? a.op_desc[ob + lane] : 0u;
-      // two ops per iteration, the rows of the next op in flight
-      Row16 RA = load_row(op_row(s.Gs, js, lane_u32(dl, 0), i));
-      int x = 0;
-      for (; x + 2 <= n; x += 2) {
-        const uint32_t d0 = lane_u32(dl, x), d1 = lane_u32(dl, x + 1);
-        const Row16 RB = load_row(op_row(s.Gs, js, d1, i));
-        f = dot16(f, RA);
-        pos += (d0 >> 8) & 0xffu;
-        if (st) out[(pos - 1) * D] = f;
-        RA = load_row(op_row(s.Gs, js, lane_u32(dl, x + 2 < n ? x + 2 : x + 1), i));
-        f = dot16(f, RB);
-        pos += (d1 >> 8) & 0xffu;
-        if (st) out[(pos - 1) * D] = f;
-      }
-      if (x < n) {
-        f = dot16(f, RA);
+      // three ops per iteration, the rows of the next two ops in flight
+      auto rows = [&](int x) { return load_row(op_row(s.Gs, js, lane_u32(dl, x < n ? x : n - 1), i)); };
+      auto step = [&](const Row16& R, int x) {
+        f = dot16(f, R);
         pos += (lane_u32(dl, x) >> 8) & 0xffu;
         if (st) out[(pos - 1) * D] = f;
+      };
+      Row16 R0 = rows(0), R1 = rows(1);
+      int x = 0;
+      for (; x + 3 <= n; x += 3) {
+        const Row16 R2 = rows(x + 2);
+        step(R0, x);
+        R0 = rows(x + 3);
+        step(R1, x + 1);
+        R1 = rows(x + 4);
+        step(R2, x + 2);
       }
+      if (x < n) step(R0, x);
+      if (x + 1 < n) step(R1, x + 1);
     }
   }
 }
@@ -326,7 +326,7 @@ __global__ __launch_bounds__(64) void trunk_bwd_kernel(const PlanArgs a) {
   const int K = a.K;
   const Lds s = carve(lds_raw, K);
   const int lane = threadIdx.x & 63, i = lane & 15, team = lane >> 4;
-  stage_gateset<D, 64>(s, a.G, a.E, a.rho, K, a.M);
+  stage_gateset<D, 64, STAGE_GT>(s, a.G, a.E, a.rho, K, a.M);
   double* inj_st = lds_raw + trunk_head_doubles(K);
   double* js = lds_raw + trunk_jump_doubles(K);
   const bool st = (D == 16) || lane < D;
@@ -358,27 +358,26 @@ __global__ __launch_bounds__(64) void trunk_bwd_kernel(const PlanArgs a) {
 #pragma unroll
       for (int q = 0; q < OPW / TPW; ++q) inj_st[(TPW * q + team) * 16 + i] = v[q];
       wave_sync();
-      Row16 RA = load_row(op_row(s.GTs, js, lane_u32(dl, n - 1), i));
-      int x = n - 1;
-      for (; x >= 1; x -= 2) {
-        const uint32_t d0 = lane_u32(dl, x), d1 = lane_u32(dl, x - 1);
-        const Row16 RB = load_row(op_row(s.GTs, js, d1, i));
+      // three ops per iteration (descending), the rows of the next two in flight
+      auto rows = [&](int x) { return load_row(op_row(s.GTs, js, lane_u32(dl, x >= 0 ? x : 0), i)); };
+      auto step = [&](const Row16& R, int x) {
         b += inj_st[x * 16 + i];
         if (st) ba[(pos - 1) * D] = b;
-        b = dot16(b, RA);
-        pos -= (d0 >> 8) & 0xffu;
-        RA = load_row(op_row(s.GTs, js, lane_u32(dl, x >= 2 ? x - 2 : x - 1), i));
-        b += inj_st[(x - 1) * 16 + i];
-        if (st) ba[(pos - 1) * D] = b;
-        b = dot16(b, RB);
-        pos -= (d1 >> 8) & 0xffu;
+        b = dot16(b, R);
+        pos -= (lane_u32(dl, x) >> 8) & 0xffu;
+      };
+      Row16 R0 = rows(n - 1), R1 = rows(n - 2);
+      int x = n - 1;
+      for (; x >= 2; x -= 3) {
+        const Row16 R2 = rows(x - 2);
+        step(R0, x);
+        R0 = rows(x - 3);
+        step(R1, x - 1);
+        R1 = rows(x - 4);
+        step(R2, x - 2);
       }
-      if (x == 0) {
-        b += inj_st[i];
-        if (st) ba[(pos - 1) * D] = b;
-        b = dot16(b, RA);
-        pos -= (lane_u32(dl, 0) >> 8) & 0xffu;
-      }
+      if (x >= 0) step(R0, x);
+      if (x >= 1) step(R1, x - 1);
     }
     if (lane < D) a.trunk_adj[t * D + i] = b;
     if (a.trunk_anchor[t] < 0) drho += b;
@@ -413,38 +412,45 @@ __device__ void run_fills(const PlanArgs& a, const Lds& s, int64_t blk, int64_t 
       pat = a.fill_pattern[q];
       g3 = a.fill_gate3[q];
     }
-    const int per = (int)(pat & 0xffu);
+    // the four tasks of a wave share their period (the plan groups them):
+    // the pattern rows stay in registers and the phase is uniform
+    const int per = __builtin_amdgcn_readfirstlane((int)(pat & 0xffu));
     const int nw = wave_max4(n);
     const bool st = has && i < D;
-    auto gate = [&](int j) {
-      const int ph = j % per;
-      return ph == 0 ? (int)((pat >> 8) & 0xffu) : ph == 1 ? (int)((pat >> 16) & 0xffu)
-                                                 : ph == 2 ? (int)((pat >> 24) & 0xffu) : g3;
+    const Row16 R0 = load_row(gl + (int)((pat >> 8) & 0xffu) * GATE_STRIDE);
+    Row16 R1 = R0, R2 = R0, R3 = R0;
+    if (per > 1) R1 = load_row(gl + (int)((pat >> 16) & 0xffu) * GATE_STRIDE);
+    if (per > 2) R2 = load_row(gl + (int)((pat >> 24) & 0xffu) * GATE_STRIDE);
+    if (per > 3) R3 = load_row(gl + g3 * GATE_STRIDE);
+    auto apply = [&](double v, int ph) {
+      if (ph == 0) return dot16(v, R0);
+      if (ph == 1) return dot16(v, R1);
+      if (ph == 2) return dot16(v, R2);
+      return dot16(v, R3);
     };
     if (!REV) {
-      // states after steps 0 .. n-2 (the one after step n-1 is the jump's)
+      // states after steps 0 .. n-2 (the one after step n-1 is the jump's);
+      // step j applies pattern gate j % per
       double f = load_state(a.FA, in, D, i);
       double* o = a.FA + (1 + first) * D + i;
-      Row16 R = load_row(gl + gate(0) * GATE_STRIDE);
+      int ph = 0;
       for (int j = 0; j + 1 < nw; ++j) {
-        const Row16 Rn = load_row(gl + gate(j + 1) * GATE_STRIDE);
-        f = dot16(f, R);
+        f = apply(f, ph);
         if (st && j + 1 < n) o[(int64_t)j * D] = f;
-        R = Rn;
+        ph = ph + 1 == per ? 0 : ph + 1;
       }
     } else {
       // adjoints after steps n-2 .. 0, from the one after step n-1
       double b = st ? a.BA[(first + n - 1) * D + i] : 0.0;
       double* o = a.BA + first * D + i;
-      Row16 R = load_row(gl + gate(nw - 1) * GATE_STRIDE);
+      int ph = (nw - 1) % per;
       for (int j = nw - 1; j >= 1; --j) {
-        const Row16 Rn = load_row(gl + gate(j - 1) * GATE_STRIDE);
-        const double nb = dot16(b, R);
+        const double nb = apply(b, ph);
         if (j < n) {
           b = nb;
           if (st) o[(int64_t)(j - 1) * D] = b;
         }
-        R = Rn;
+        ph = ph == 0 ? per - 1 : ph - 1;
       }
     }
   }
@@ -455,7 +461,7 @@ template <int D>
 __global__ __launch_bounds__(256) void fill_rev_kernel(const PlanArgs a) {
   extern __shared__ double lds_raw[];
   const Lds s = carve(lds_raw, a.K);
-  stage_gateset<D>(s, a.G, a.E, a.rho, a.K, a.M);
+  stage_gateset<D, 256, STAGE_GT>(s, a.G, a.E, a.rho, a.K, a.M);
   run_fills<D, true>(a, s, blockIdx.x, gridDim.x);
 }
 
