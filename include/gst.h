@@ -211,13 +211,16 @@ int gst_set_plan_jump(gst_ctx* ctx, int reps);
 
 /*
  * Kernel timing (diagnostics).  While enabled, every kernel the context
- * enqueues is bracketed by two HIP events recorded on the context's stream.
+ * enqueues is launched with a pair of HIP events on the context's stream that
+ * the runtime stamps with the kernel's own start and end (no marker is queued
+ * between kernels).  A family's time is the sum over its kernels, and a
+ * kernel also counts for the families enclosing it ("batch").
  * gst_profile_read synchronizes the stream and returns, for the kernel family
  * `kernel` ("leaf", "reduce", "trunk_fwd", "trunk_bwd", "inject",
  * "grad_gemm", "fill", "tiles_2q", "tiles_1q", "tiles_reduce",
  * "chain_3q", "gemm_3q", "reduce_3q", or "batch" for a whole
  * gst_batch_run), the summed
- * elapsed milliseconds and the number of launches since profiling was
+ * elapsed milliseconds and the number of kernels since profiling was
  * enabled; the counters are not reset by reading.
  */
 int gst_profile_enable(gst_ctx* ctx, int enable);

@@ -15,6 +15,13 @@
 #include "gst_internal.h"
 #include "gst_plan.h"
 
+namespace gst {
+LaunchTimer*& launch_timer() {
+  static thread_local LaunchTimer* t = nullptr;
+  return t;
+}
+}  // namespace gst
+
 namespace {
 
 thread_local std::string g_err;
@@ -65,6 +72,7 @@ struct Profiler {
   struct Pending {
     int family;
     hipEvent_t a, b;
+    bool owner;  // returns the events to the pool (a kernel counts for every enclosing family)
   };
   std::vector<Pending> pending;
   std::vector<hipEvent_t> pool;
@@ -83,6 +91,7 @@ struct Profiler {
   }
   ~Profiler() {
     for (auto& p : pending) {
+      if (!p.owner) continue;
       (void)hipEventDestroy(p.a);
       (void)hipEventDestroy(p.b);
     }
@@ -123,26 +132,38 @@ struct gst_ctx {
 };
 
 // Brackets one launch with events when profiling is on.
-struct ProfScope {
+// Times the kernels launched in its lifetime as family `family`: each launch
+// gets its own event pair stamped with the kernel's start and end (no marker
+// between kernels), and the family's time is the sum over its kernels.
+struct ProfScope : gst::LaunchTimer {
   gst_ctx* c;
   int fam;
-  hipEvent_t a = nullptr;
+  gst::LaunchTimer* prev = nullptr;
+  ProfScope* outer = nullptr;  // the enclosing scope, if one is timing
+  bool active = false;
   ProfScope(gst_ctx* ctx, int family) : c(ctx), fam(family) {
     if (c && c->prof.on && (c->prof.only < 0 || c->prof.only == fam)) {
-      a = c->prof.get();
-      if (a) (void)hipEventRecord(a, c->stream);
+      active = true;
+      prev = gst::launch_timer();
+      outer = dynamic_cast<ProfScope*>(prev);
+      gst::launch_timer() = this;
     }
   }
-  ~ProfScope() {
-    if (c && c->prof.on && a) {
-      hipEvent_t b = c->prof.get();
-      if (b) {
-        (void)hipEventRecord(b, c->stream);
-        c->prof.pending.push_back({fam, a, b});
-      } else {
-        c->prof.pool.push_back(a);
-      }
+  bool events(hipEvent_t* start, hipEvent_t* stop) override {
+    hipEvent_t a = c->prof.get(), b = c->prof.get();
+    if (!a || !b) {
+      if (a) c->prof.pool.push_back(a);
+      if (b) c->prof.pool.push_back(b);
+      return false;
     }
+    c->prof.pending.push_back({fam, a, b, true});
+    for (ProfScope* o = outer; o; o = o->outer) c->prof.pending.push_back({o->fam, a, b, false});
+    *start = a;
+    *stop = b;
+    return true;
+  }
+  ~ProfScope() override {
+    if (active) gst::launch_timer() = prev;
   }
 };
 
@@ -779,8 +800,10 @@ int gst_profile_read(gst_ctx* ctx, const char* kernel, double* total_ms, int64_t
     HIP_TRY(hipEventElapsedTime(&ms, p.a, p.b));
     ctx->prof.total_ms[p.family] += ms;
     ctx->prof.launches[p.family] += 1;
-    ctx->prof.pool.push_back(p.a);
-    ctx->prof.pool.push_back(p.b);
+    if (p.owner) {
+      ctx->prof.pool.push_back(p.a);
+      ctx->prof.pool.push_back(p.b);
+    }
   }
   ctx->prof.pending.clear();
   if (total_ms) *total_ms = ctx->prof.total_ms[fam];

@@ -257,9 +257,9 @@ int batch_blocks_per_cu(int D, int kmax) {
 hipError_t launch_batch(const BatchLaunch& a, int n_blocks, hipStream_t stream) {
   const size_t bytes = batch_lds_bytes(a.kmax);
   if (a.D == 16)
-    hipLaunchKernelGGL(batch_kernel<16>, dim3(n_blocks), dim3(256), bytes, stream, a);
+    gst_launch(batch_kernel<16>, dim3(n_blocks), dim3(256), bytes, stream, a);
   else if (a.D == 4)
-    hipLaunchKernelGGL(batch_kernel<4>, dim3(n_blocks), dim3(256), bytes, stream, a);
+    gst_launch(batch_kernel<4>, dim3(n_blocks), dim3(256), bytes, stream, a);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
@@ -269,13 +269,13 @@ hipError_t launch_queue_reset(unsigned* q, unsigned long long* req_nonpos, int n
   int blocks = (n_req + 255) / 256;
   if (blocks < 1) blocks = 1;
   if (blocks > 256) blocks = 256;
-  hipLaunchKernelGGL(queue_reset_kernel, dim3(blocks), dim3(256), 0, stream, q, req_nonpos, n_req);
+  gst_launch(queue_reset_kernel, dim3(blocks), dim3(256), 0, stream, q, req_nonpos, n_req);
   return hipGetLastError();
 }
 
 hipError_t launch_batch_reduce(const BatchReduce& a, int n_items, hipStream_t stream) {
   if (n_items <= 0) return hipSuccess;
-  hipLaunchKernelGGL(batch_reduce_kernel, dim3(n_items), dim3(256), 0, stream, a);
+  gst_launch(batch_reduce_kernel, dim3(n_items), dim3(256), 0, stream, a);
   return hipGetLastError();
 }
 

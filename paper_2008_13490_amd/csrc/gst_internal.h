@@ -1,9 +1,29 @@
 // Internal declarations shared by the host-side library code and the kernels.
 #pragma once
 #include <stdint.h>
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 namespace gst {
+
+// Kernel timing.  While a LaunchTimer is installed on the calling thread,
+// every launch asks it for a pair of HIP events that the runtime stamps with
+// the kernel's own start and end (hipExtLaunchKernelGGL), so that no marker
+// is queued between kernels.
+struct LaunchTimer {
+  virtual bool events(hipEvent_t* start, hipEvent_t* stop) = 0;
+  virtual ~LaunchTimer() = default;
+};
+LaunchTimer*& launch_timer();  // per thread; null = no timing
+
+template <typename F, typename... Args>
+inline void gst_launch(F kernel, dim3 grid, dim3 block, size_t lds, hipStream_t stream, Args... args) {
+  hipEvent_t a = nullptr, b = nullptr;
+  if (LaunchTimer* t = launch_timer())
+    if (!t->events(&a, &b)) a = b = nullptr;
+  hipExtLaunchKernelGGL(kernel, grid, block, (uint32_t)lds, stream, a, b, 0u, args...);
+}
+
 
 // Evaluation modes of the sequence kernel.
 enum Mode : int { MODE_PROBS = 0, MODE_LOGLIK = 1, MODE_VJP = 2 };

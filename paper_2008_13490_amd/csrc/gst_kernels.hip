@@ -298,9 +298,9 @@ int leaf_blocks_for(int D, int64_t n_items) {
 hipError_t launch_leaf(const LeafLaunch& a, int n_blocks, hipStream_t stream) {
   const size_t bytes = lds_bytes(a.K);
   if (a.D == 16)
-    hipLaunchKernelGGL(leaf_kernel<16>, dim3(n_blocks), dim3(256), bytes, stream, a);
+    gst_launch(leaf_kernel<16>, dim3(n_blocks), dim3(256), bytes, stream, a);
   else if (a.D == 4)
-    hipLaunchKernelGGL(leaf_kernel<4>, dim3(n_blocks), dim3(256), bytes, stream, a);
+    gst_launch(leaf_kernel<4>, dim3(n_blocks), dim3(256), bytes, stream, a);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
@@ -315,9 +315,9 @@ hipError_t launch_reduce(const double* slab, int n_slabs, int64_t P, double* obj
                          const double* extra_rho, int D, double* part, hipStream_t stream) {
   const int G = reduce_parts(n_slabs);
   const int per = (n_slabs + G - 1) / G;
-  hipLaunchKernelGGL(reduce_stage1, dim3((unsigned)((P + 63) / 64), G), dim3(256), 0, stream, slab, n_slabs, P, per,
+  gst_launch(reduce_stage1, dim3((unsigned)((P + 63) / 64), G), dim3(256), 0, stream, slab, n_slabs, P, per,
                      part);
-  hipLaunchKernelGGL(reduce_stage2, dim3((unsigned)((P + 63) / 64)), dim3(256), 0, stream, part, G, P, objective, grad,
+  gst_launch(reduce_stage2, dim3((unsigned)((P + 63) / 64)), dim3(256), 0, stream, part, G, P, objective, grad,
                      extra_rho, D);
   return hipGetLastError();
 }

@@ -302,20 +302,20 @@ int chain64_blocks_per_cu(int K) {
 
 hipError_t launch_chain64(const Chain64Launch& a, int n_blocks, hipStream_t stream) {
   if (a.K < 1 || a.K > 5 || a.M < 1 || a.M > 16) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(chain64_kernel, dim3(n_blocks), dim3(CHAIN64_WAVES * 64), chain64_lds(a.K), stream, a);
+  gst_launch(chain64_kernel, dim3(n_blocks), dim3(CHAIN64_WAVES * 64), chain64_lds(a.K), stream, a);
   return hipGetLastError();
 }
 
 hipError_t launch_gemm64(const Gemm64Launch& a, hipStream_t stream) {
   if (a.n_chunks <= 0) return hipSuccess;
-  hipLaunchKernelGGL(gemm64_kernel, dim3(a.n_chunks), dim3(256), 0, stream, a);
+  gst_launch(gemm64_kernel, dim3(a.n_chunks), dim3(256), 0, stream, a);
   return hipGetLastError();
 }
 
 hipError_t launch_reduce64(const Reduce64Launch& a, hipStream_t stream) {
   const int64_t Y = (int64_t)a.K * GATE64;
   if (Y == 0 || !a.grad) return hipSuccess;
-  hipLaunchKernelGGL(reduce64_kernel, dim3((unsigned)((Y + 63) / 64)), dim3(256), 0, stream, a);
+  gst_launch(reduce64_kernel, dim3((unsigned)((Y + 63) / 64)), dim3(256), 0, stream, a);
   return hipGetLastError();
 }
 

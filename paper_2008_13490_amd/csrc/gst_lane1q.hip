@@ -329,10 +329,10 @@ int lane1q_blocks_per_cu(int K) {
 
 hipError_t launch_lane1q(const BatchLaunch& a, int K, int n_blocks, hipStream_t stream) {
   switch (K) {
-    case 1: hipLaunchKernelGGL(lane1q_kernel<1>, dim3(n_blocks), dim3(256), lane1q_lds(), stream, a); break;
-    case 2: hipLaunchKernelGGL(lane1q_kernel<2>, dim3(n_blocks), dim3(256), lane1q_lds(), stream, a); break;
-    case 3: hipLaunchKernelGGL(lane1q_kernel<3>, dim3(n_blocks), dim3(256), lane1q_lds(), stream, a); break;
-    case 4: hipLaunchKernelGGL(lane1q_kernel<4>, dim3(n_blocks), dim3(256), lane1q_lds(), stream, a); break;
+    case 1: gst_launch(lane1q_kernel<1>, dim3(n_blocks), dim3(256), lane1q_lds(), stream, a); break;
+    case 2: gst_launch(lane1q_kernel<2>, dim3(n_blocks), dim3(256), lane1q_lds(), stream, a); break;
+    case 3: gst_launch(lane1q_kernel<3>, dim3(n_blocks), dim3(256), lane1q_lds(), stream, a); break;
+    case 4: gst_launch(lane1q_kernel<4>, dim3(n_blocks), dim3(256), lane1q_lds(), stream, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -112,7 +112,7 @@ struct PlanOptions {
   int64_t max_item_steps = 1LL << 24;   // bound on stored item-step states (memory)
   int chunk = 128;                      // gradient GEMM records per chunk (the kernel takes at most 128)
   int jump = 8;                         // repetitions per germ-power jump (power of two, <= 16); 0 = none
-  int jump_min_save = 12;               // jump a run only if it shortens the chain by this many steps
+  int jump_min_save = 3;                // jump a run only if it shortens the chain by this many steps
 };
 
 // Builds the plan.  Returns false (plan unused: evaluate sequence by

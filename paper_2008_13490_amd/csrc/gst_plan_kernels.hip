@@ -644,9 +644,9 @@ hipError_t launch_trunk_fwd(const PlanArgs& a, hipStream_t stream) {
   const int blocks = trunk_blocks_for(a.t_end - a.t_begin);
   const size_t bytes = trunk_lds_bytes(a.K, a.jump_levels);
   if (a.D == 16)
-    hipLaunchKernelGGL(trunk_fwd_kernel<16>, dim3(blocks), dim3(64), bytes, stream, a);
+    gst_launch(trunk_fwd_kernel<16>, dim3(blocks), dim3(64), bytes, stream, a);
   else if (a.D == 4)
-    hipLaunchKernelGGL(trunk_fwd_kernel<4>, dim3(blocks), dim3(64), bytes, stream, a);
+    gst_launch(trunk_fwd_kernel<4>, dim3(blocks), dim3(64), bytes, stream, a);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
@@ -656,9 +656,9 @@ hipError_t launch_trunk_bwd(const PlanArgs& a, hipStream_t stream) {
   const int blocks = trunk_blocks_for(a.t_end - a.t_begin);
   const size_t bytes = trunk_lds_bytes(a.K, a.jump_levels);
   if (a.D == 16)
-    hipLaunchKernelGGL(trunk_bwd_kernel<16>, dim3(blocks), dim3(64), bytes, stream, a);
+    gst_launch(trunk_bwd_kernel<16>, dim3(blocks), dim3(64), bytes, stream, a);
   else if (a.D == 4)
-    hipLaunchKernelGGL(trunk_bwd_kernel<4>, dim3(blocks), dim3(64), bytes, stream, a);
+    gst_launch(trunk_bwd_kernel<4>, dim3(blocks), dim3(64), bytes, stream, a);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
@@ -669,9 +669,9 @@ hipError_t launch_items(const PlanArgs& a, int n_blocks, hipStream_t stream) {
   const size_t bytes = item_lds_bytes(a.K);
   const unsigned grid = (unsigned)n_blocks + (a.want_grad && a.n_fill > 0 ? (unsigned)fill_blocks_for(a.n_fill) : 0u);
   if (a.D == 16)
-    hipLaunchKernelGGL(item_kernel<16>, dim3(grid), dim3(256), bytes, stream, a);
+    gst_launch(item_kernel<16>, dim3(grid), dim3(256), bytes, stream, a);
   else if (a.D == 4)
-    hipLaunchKernelGGL(item_kernel<4>, dim3(grid), dim3(256), bytes, stream, a);
+    gst_launch(item_kernel<4>, dim3(grid), dim3(256), bytes, stream, a);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
@@ -681,7 +681,7 @@ hipError_t launch_inject(const InjectLaunch& a, hipStream_t stream) {
   const int64_t n = a.s_end - a.s_begin;
   if (n <= 0) return hipSuccess;
   const int blocks = (int)(n < 65536 ? n : 65536);
-  hipLaunchKernelGGL(inject_kernel, dim3(blocks), dim3(64), 0, stream, a);
+  gst_launch(inject_kernel, dim3(blocks), dim3(64), 0, stream, a);
   return hipGetLastError();
 }
 
@@ -690,9 +690,9 @@ hipError_t launch_fill_rev(const PlanArgs& a, hipStream_t stream) {
   const int blocks = fill_blocks_for(a.n_fill);
   const size_t bytes = item_lds_bytes(a.K);
   if (a.D == 16)
-    hipLaunchKernelGGL(fill_rev_kernel<16>, dim3((unsigned)blocks), dim3(256), bytes, stream, a);
+    gst_launch(fill_rev_kernel<16>, dim3((unsigned)blocks), dim3(256), bytes, stream, a);
   else if (a.D == 4)
-    hipLaunchKernelGGL(fill_rev_kernel<4>, dim3((unsigned)blocks), dim3(256), bytes, stream, a);
+    gst_launch(fill_rev_kernel<4>, dim3((unsigned)blocks), dim3(256), bytes, stream, a);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
@@ -701,17 +701,17 @@ hipError_t launch_fill_rev(const PlanArgs& a, hipStream_t stream) {
 hipError_t launch_reduce_plan(const PlanReduce& a, hipStream_t stream) {
   if (a.P <= 0 || a.n_part < 1 || a.n_part > 64 || a.K < 0 || a.K > 8) return hipErrorInvalidValue;
   const unsigned xb = (unsigned)((a.P + 63) / 64);
-  hipLaunchKernelGGL(plan_reduce_stage1, dim3(xb, (unsigned)a.n_part), dim3(256), 0, stream, a);
-  hipLaunchKernelGGL(plan_reduce_stage2, dim3(xb), dim3(256), 0, stream, a);
+  gst_launch(plan_reduce_stage1, dim3(xb, (unsigned)a.n_part), dim3(256), 0, stream, a);
+  gst_launch(plan_reduce_stage2, dim3(xb), dim3(256), 0, stream, a);
   return hipGetLastError();
 }
 
 hipError_t launch_grad_gemm(const GemmLaunch& a, hipStream_t stream) {
   if (a.n_chunks <= 0) return hipSuccess;
   if (a.D == 16)
-    hipLaunchKernelGGL(grad_gemm_kernel<16>, dim3((unsigned)a.n_chunks), dim3(256), 0, stream, a);
+    gst_launch(grad_gemm_kernel<16>, dim3((unsigned)a.n_chunks), dim3(256), 0, stream, a);
   else if (a.D == 4)
-    hipLaunchKernelGGL(grad_gemm_kernel<4>, dim3((unsigned)a.n_chunks), dim3(256), 0, stream, a);
+    gst_launch(grad_gemm_kernel<4>, dim3((unsigned)a.n_chunks), dim3(256), 0, stream, a);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();

@@ -195,7 +195,10 @@ def test_one_qubit_gate_counts(oracle_lib, gpu, K):
     ctx.sync()
     F, p_or, g_or, _, rc = oracle_lib.loglik(gs.rho, gs.effects, gs.gates, sl.offsets, sl.gates, counts)
     assert rc == 0
-    assert np.array_equal(p.cpu().numpy(), p_or)
+    if req.plan_info()["jump_trunks"] == 0:
+        assert np.array_equal(p.cpu().numpy(), p_or)
+    else:  # germ-power jumps of the sharing plan: 1e-12 relative
+        assert np.all(np.abs(p.cpu().numpy() - p_or) <= 1e-12 * np.abs(p_or))
     assert abs(float(obj.cpu()[0]) - F) <= 1e-10 * abs(F)
     assert np.abs(g.cpu().numpy() - g_or).max() <= 1e-10 * np.abs(g_or).max()
     other = W.random_workload("2q", 90, 60, 7)

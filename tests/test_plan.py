@@ -449,7 +449,7 @@ def test_germ_power_jumps(planlib, name, jump):
     try:
         P = get_plan(planlib, w.seqs, w.model.K)
     finally:
-        planlib.plan_set_jump(8, 12)
+        planlib.plan_set_jump(8, 3)
     assert P["used"] and len(P["fill_first"]) > 0 and P["jump_trunks"] > 0
     tp, ta, tg, ti = P["trunk_ptr"], P["trunk_anchor"], P["trunk_gates"], P["trunk_inj"]
     for t in range(len(ta)):
@@ -495,11 +495,11 @@ def test_trunk_ops(planlib, name, jump):
     gives the trunk's word, and every state that receives an injection ends an
     op and carries its slot there."""
     w = W.structured_workload(name)
-    planlib.plan_set_jump(jump, 12)
+    planlib.plan_set_jump(jump, 3)
     try:
         P = get_plan(planlib, w.seqs, w.model.K)
     finally:
-        planlib.plan_set_jump(8, 12)
+        planlib.plan_set_jump(8, 3)
     tp, tg, ti = P["trunk_ptr"], P["trunk_gates"], P["trunk_inj"]
     op = P["op_ptr"]
     n_jump_ops = 0
