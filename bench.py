@@ -136,8 +136,8 @@ def kernel_source_hash():
 
 
 def read_traffic(workload: str, family: str):
-    """HBM bytes per launch from the committed counter summary, if it was taken
-    on the current kernel sources; else None."""
+    """HBM bytes per launch of the resident path's kernels from the committed
+    counter summary, if it was taken on the current kernel sources; else None."""
     path = os.path.join(ROOT, "profiles", f"hbm_traffic_{workload}.txt")
     if not os.path.exists(path):
         return None
@@ -164,7 +164,7 @@ def main():
     ap.add_argument("--iters", type=int, default=20, help="c5 / serving: iterations per request")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving measurement of the default run")
     ap.add_argument("--no-autotune", action="store_true", help="c3: keep the default tile policy")
-    ap.add_argument("--round-work", type=float, default=4e6,
+    ap.add_argument("--round-work", type=float, default=8e6,
                     help="serving: bound on the work of one round, in two-qubit sequence steps")
     ap.add_argument("--path", choices=["resident", "plain"], default="resident")
     ap.add_argument("--sets", type=int, default=0, help="c3: use only the first N gate sets")
@@ -374,7 +374,8 @@ def run_structured(args):
         "dtype": "f64",
         "data": "synthetic",
         "config": dict(desc, path=args.path),
-        "roofline": _roofline(dom, fams, flops, read_traffic(args.workload, dom)),
+        "roofline": _roofline(dom, fams, flops,
+                              read_traffic(args.workload, dom) if args.path == "resident" else None),
         "kernels_ms_per_step": {f: brk[f][0] / n_break for f in brk},
         "plan": info,
         "useful_tflops": 6.0 * D * D * steps_eval / (elapsed / args.steps) / 1e12,
