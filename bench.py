@@ -489,8 +489,9 @@ def algorithmic_flops(family, D, M, S, sum_len, info):
     Per step of a chain: forward mat-vec 2D^2, adjoint mat-vec 2D^2, gradient
     outer product 2D^2; per sequence: readout, seed and effect gradient 2DM
     each.  Without the sharing plan every sequence is its own chain; with it,
-    the chains are the stored trunk steps plus the remaining item steps
-    (launch counts: one per trunk level)."""
+    the chains are the trunk chains (a germ-power jump is one mat-vec), the
+    states and adjoints filled in inside the jumps, and the remaining item
+    steps (launch counts: one per trunk level)."""
     if info is None:
         if family in ("leaf", "tiles_2q", "tiles_1q"):
             return 6.0 * D * D * sum_len + 6.0 * D * M * S
@@ -500,8 +501,11 @@ def algorithmic_flops(family, D, M, S, sum_len, info):
             return 2.0 * D * D * sum_len
         return 0.0
     ts, its, lv = info["trunk_steps"], info["item_steps"], max(1, info["levels"])
-    if family == "leaf":   # items: forward + adjoint mat-vecs, readout, seed, dE
-        return 4.0 * D * D * its + 6.0 * D * M * S
+    filled = ts - info.get("chain_steps", ts)   # trunk states / adjoints inside germ-power jumps
+    if family == "leaf":   # items: forward + adjoint mat-vecs, readout, seed, dE; the forward fill tasks
+        return 4.0 * D * D * its + 6.0 * D * M * S + 2.0 * D * D * filled
+    if family == "fill":   # reverse fill tasks
+        return 2.0 * D * D * filled
     if family in ("trunk_fwd", "trunk_bwd"):   # the chain's mat-vecs (a germ-power jump counts once)
         return 2.0 * D * D * info.get("chain_steps", ts) / lv
     if family == "grad_gemm":
