@@ -210,6 +210,31 @@ int gst_tune_set(gst_ctx* ctx, int n_qubits, int seqs_per_tile, int blocks_per_c
 int gst_set_plan_jump(gst_ctx* ctx, int reps);
 
 /*
+ * Predictions of repeated gate applications (thesis Eq. GSTPrediction):
+ *   probs[(p * n_gates + s) * (r_max + 1) + r][m] = <<E_m| (G_{gates[s]})^r G_prep(p) |rho>>
+ * for r = 0 .. r_max, every preparation word p (host CSR: prep_offsets[n_prep + 1],
+ * prep_gates in time order, at most 64 gates each, gate indices < n_gates of theta)
+ * and every gate index gates[s] (host array of n_gates).  One or two qubits; theta
+ * and probs are device pointers, probs holds n_prep * n_gates * (r_max + 1) * M
+ * doubles.  The powers run in blocks of 32 repetitions: a chain steps from block to
+ * block with (G_s)^32 (built per call by repeated squaring) and every block then
+ * takes single steps, so the probabilities for r < 32 equal the plain evaluation of
+ * the word bit for bit and later ones agree to rounding.  The host arrays are read
+ * before the call returns (it synchronizes the context stream).  GST_EINVAL for
+ * three qubits, a word longer than 64 gates, a gate index out of range,
+ * r_max outside 0 .. 2^24 or more than 2^24 (preparation, gate) pairs.
+ */
+int gst_predict(gst_ctx* ctx, const gst_gateset* theta, int n_prep, const int64_t* prep_offsets,
+                const uint8_t* prep_gates, int n_gates, const int32_t* gates, int r_max, double* probs);
+
+/*
+ * Statistical (total variation) distance of Eq. statisticaldistance for n rows of
+ * m probabilities: out[i] = 1/2 sum_j |p[i*m + j] - q[i*m + j]| (j ascending).
+ * Device pointers; stream-ordered.
+ */
+int gst_tv_distance(gst_ctx* ctx, const double* p, const double* q, int64_t n, int m, double* out);
+
+/*
  * Kernel timing (diagnostics).  While enabled, every kernel the context
  * enqueues is launched with a pair of HIP events on the context's stream that
  * the runtime stamps with the kernel's own start and end (no marker is queued

@@ -4,5 +4,5 @@ Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
 ``bench.py`` may import this package.  The product library never does.
 """
 from .binding import (  # noqa: F401
-    build, probs, probs_extended, loglik, vjp, OracleError, library_path,
+    build, probs, probs_extended, loglik, vjp, tv_distance, predict, OracleError, library_path,
 )

@@ -53,6 +53,7 @@ def _load():
         lib.oracle_probs_extended.argtypes = [I, I, I, P, P, P, L, P, P, P]
         lib.oracle_loglik.argtypes = [I, I, I, P, P, P, L, P, P, P, P, P, P, P]
         lib.oracle_vjp.argtypes = [I, I, I, P, P, P, L, P, P, P, P]
+        lib.oracle_tv_distance.argtypes = [L, I, P, P, P]
         for f in (lib.oracle_probs, lib.oracle_probs_extended, lib.oracle_loglik, lib.oracle_vjp):
             f.restype = I
         _lib = lib
@@ -132,3 +133,29 @@ def vjp(rho, E, G, offsets, gates, W) -> np.ndarray:
     if rc:
         raise OracleError(rc, _MSG.get(rc, "?"))
     return grad
+
+
+def tv_distance(p, q) -> np.ndarray:
+    """Statistical distance 1/2 sum_J |p_J - q_J| over the last axis (Eq. statisticaldistance)."""
+    p = _c(p, np.float64)
+    q = _c(q, np.float64)
+    assert p.shape == q.shape and p.ndim >= 1
+    m = p.shape[-1]
+    out = np.empty(p.shape[:-1], np.float64)
+    rc = _load().oracle_tv_distance(p.size // m, m, _ptr(p), _ptr(q), _ptr(out))
+    if rc:
+        raise OracleError(rc, _MSG.get(rc, "?"))
+    return out
+
+
+def predict(rho, E, G, preps, gates, r_max: int) -> np.ndarray:
+    """Predictions of repeated gate applications, Eq. GSTPrediction: the plain
+    probabilities of the words prep + [s] * r (time order) for every preparation
+    word, gate s and r = 0..r_max, as an array [n_prep, n_gates, r_max + 1, M]."""
+    words = [list(w) + [int(s)] * r for w in preps for s in gates for r in range(r_max + 1)]
+    off = np.zeros(len(words) + 1, np.int64)
+    for x, w in enumerate(words):
+        off[x + 1] = off[x] + len(w)
+    flat = np.fromiter((g for w in words for g in w), np.uint8, count=int(off[-1]))
+    p = probs(rho, E, G, off, flat)
+    return p.reshape(len(preps), len(gates), r_max + 1, -1)

@@ -23,6 +23,9 @@
  * IEEE binary64; compile with -ffp-contract=off so that no other
  * contraction is introduced.
  *
+ * Also (thesis Eq. statisticaldistance): the statistical distance
+ *   D = 1/2 sum_J |p_J - q_J|  of two outcome distributions, row by row.
+ *
  * Layouts: rho[D]; E[M][D] (row m = e_m); G[K][D][D] row-major with
  * G[k][i][j] = Tr(P_i G_k(P_j))/d; offsets[S+1] int64, gates[offsets[S]] uint8
  * in time order; counts[S][M] int32; probs[S][M]; gradient
@@ -251,5 +254,17 @@ int oracle_probs_extended(int D, int M, int K, const double* rho, const double* 
     }
   }
   free(f);
+  return OR_OK;
+}
+
+/* Statistical distance (total variation distance), Eq. statisticaldistance:
+ * out[i] = 1/2 * sum_{j ascending} |p[i][j] - q[i][j]| for i < n, rows of m. */
+int oracle_tv_distance(int64_t n, int m, const double* p, const double* q, double* out) {
+  if (n < 0 || m < 1 || (n > 0 && (!p || !q || !out))) return OR_EINVAL;
+  for (int64_t i = 0; i < n; ++i) {
+    double acc = 0.0;
+    for (int j = 0; j < m; ++j) acc += fabs(p[i * m + j] - q[i * m + j]);
+    out[i] = 0.5 * acc;
+  }
   return OR_OK;
 }

@@ -23,7 +23,7 @@ EXPORTED = [
     "gst_max_gates", "gst_create", "gst_destroy", "gst_sync", "gst_probs", "gst_loglik", "gst_vjp",
     "gst_req_create_host", "gst_req_footprint", "gst_req_eval", "gst_req_probs", "gst_req_vjp",
     "gst_req_destroy", "gst_req_plan_info", "gst_batch_create", "gst_batch_run", "gst_batch_nonpos",
-    "gst_batch_destroy", "gst_tune_set", "gst_set_plan_jump", "gst_profile_enable", "gst_profile_only", "gst_profile_read",
+    "gst_batch_destroy", "gst_tune_set", "gst_set_plan_jump", "gst_predict", "gst_tv_distance", "gst_profile_enable", "gst_profile_only", "gst_profile_read",
     "gst_last_error",
 ]
 
@@ -85,6 +85,10 @@ def load():
         lib.gst_tune_set.restype = I
         lib.gst_set_plan_jump.argtypes = [P, I]
         lib.gst_set_plan_jump.restype = I
+        lib.gst_predict.argtypes = [P, ctypes.POINTER(GstGateset), I, P, P, I, P, I, P]
+        lib.gst_predict.restype = I
+        lib.gst_tv_distance.argtypes = [P, P, P, I64, I, P]
+        lib.gst_tv_distance.restype = I
         lib.gst_profile_read.restype = I
         if hasattr(lib, "gst_req_create_host"):
             lib.gst_req_create_host.argtypes = [P, I, I, I, ctypes.POINTER(GstSeqlist), P, ctypes.POINTER(P)]

@@ -274,6 +274,33 @@ def tune_set(ctx: Context, n_qubits: int, seqs_per_tile: int = 0, blocks_per_cu:
     _lib.check(ctx.lib.gst_tune_set(ctx.handle, n_qubits, seqs_per_tile, blocks_per_cu))
 
 
+def predict(ctx: Context, gs: "DeviceGateSet", preps, gates, r_max: int) -> torch.Tensor:
+    """Predictions of repeated gate applications (``gst_predict``): a tensor
+    ``[len(preps), len(gates), r_max + 1, M]`` of <<E_m| G_s^r G_prep |rho>>;
+    ``preps`` are gate-index words in time order, ``gates`` gate indices."""
+    import numpy as np
+    off = np.zeros(len(preps) + 1, np.int64)
+    for x, w in enumerate(preps):
+        off[x + 1] = off[x] + len(w)
+    words = np.ascontiguousarray(np.concatenate([np.asarray(w, np.uint8) for w in preps])
+                                 if off[-1] > 0 else np.zeros(1, np.uint8))
+    g = np.ascontiguousarray(np.asarray(gates, np.int32))
+    out = torch.empty((len(preps), len(g), r_max + 1, gs.M), dtype=torch.float64, device=ctx._dev())
+    _lib.check(ctx.lib.gst_predict(ctx.handle, ctypes.byref(gs.as_struct()), len(preps), off.ctypes.data,
+                                   words.ctypes.data, len(g), g.ctypes.data, int(r_max), _ptr(out)))
+    return out
+
+
+def tv_distance(ctx: Context, p: torch.Tensor, q: torch.Tensor) -> torch.Tensor:
+    """Statistical distance 1/2 sum_m |p - q| over the last axis (``gst_tv_distance``)."""
+    assert p.shape == q.shape and p.dtype == torch.float64 and q.dtype == torch.float64
+    m = p.shape[-1]
+    p2, q2 = p.contiguous(), q.contiguous()
+    out = torch.empty(p.shape[:-1], dtype=torch.float64, device=p.device)
+    _lib.check(ctx.lib.gst_tv_distance(ctx.handle, _ptr(p2), _ptr(q2), p2.numel() // m, m, _ptr(out)))
+    return out
+
+
 def set_plan_jump(ctx: Context, reps: int):
     """Germ-power jump repetitions of the sharing plans of requests created
     afterwards on ``ctx`` (``gst_set_plan_jump``; 0 = off, bit-identical

@@ -759,6 +759,73 @@ int gst_tune_set(gst_ctx* ctx, int n_qubits, int seqs_per_tile, int blocks_per_c
   return GST_OK;
 }
 
+int gst_predict(gst_ctx* ctx, const gst_gateset* theta, int n_prep, const int64_t* prep_offsets,
+                const uint8_t* prep_gates, int n_gates, const int32_t* gates, int r_max, double* probs) {
+  if (!ctx) return fail(GST_EINVAL, "ctx is NULL");
+  int D = 0;
+  int rc = check_gateset(theta, &D);
+  if (rc) return rc;
+  if (D > 16) return fail(GST_EINVAL, "predictions take one or two qubits");
+  if (n_prep < 1 || n_gates < 1 || r_max < 0 || r_max > (1 << 24))
+    return fail(GST_EINVAL, "n_prep, n_gates >= 1 and 0 <= r_max <= 2^24 required");
+  if (!prep_offsets || !gates || !probs) return fail(GST_EINVAL, "NULL argument");
+  if ((int64_t)n_prep * n_gates > (1 << 24)) return fail(GST_EINVAL, "at most 2^24 (preparation, gate) pairs");
+  if (prep_offsets[0] != 0) return fail(GST_EINVAL, "prep_offsets[0] != 0");
+  for (int p = 0; p < n_prep; ++p) {
+    const int64_t L = prep_offsets[p + 1] - prep_offsets[p];
+    if (L < 0 || L > 64) return fail(GST_EINVAL, "preparation words take 0 to 64 gates");
+  }
+  const int64_t n_steps = prep_offsets[n_prep];
+  if (n_steps > 0 && !prep_gates) return fail(GST_EINVAL, "prep_gates is NULL");
+  for (int64_t x = 0; x < n_steps; ++x)
+    if (prep_gates[x] >= theta->n_gates) return fail(GST_EINVAL, "preparation gate index out of range");
+  for (int s = 0; s < n_gates; ++s)
+    if (gates[s] < 0 || gates[s] >= theta->n_gates) return fail(GST_EINVAL, "gate index out of range");
+  HIP_TRY(hipSetDevice(ctx->device));
+  const int levels = 6;  // blocks of 32 repetitions
+  const int B = 1 << (levels - 1);
+  const int Q = (r_max + 1 + B - 1) / B;
+  const int n_pairs = n_prep * n_gates;
+  Carver c;
+  const size_t o_po = c.take<int64_t>(n_prep + 1), o_pg = c.take<uint8_t>(n_steps + 1),
+               o_go = c.take<int32_t>(n_gates), o_v = c.take<double>((size_t)n_pairs * Q * D);
+  if ((rc = ctx->ws.reserve(c.off + 256, ctx->stream))) return rc;
+  char* b = reinterpret_cast<char*>(ctx->ws.p);
+  HIP_TRY(hipMemcpyAsync(b + o_po, prep_offsets, (size_t)(n_prep + 1) * 8, hipMemcpyHostToDevice, ctx->stream));
+  if (n_steps > 0) HIP_TRY(hipMemcpyAsync(b + o_pg, prep_gates, (size_t)n_steps, hipMemcpyHostToDevice, ctx->stream));
+  HIP_TRY(hipMemcpyAsync(b + o_go, gates, (size_t)n_gates * 4, hipMemcpyHostToDevice, ctx->stream));
+  gst::PredictLaunch a{};
+  a.D = D;
+  a.M = theta->n_outcomes;
+  a.K = theta->n_gates;
+  a.rho = theta->rho;
+  a.E = theta->effects;
+  a.G = theta->gates;
+  a.n_pairs = n_pairs;
+  a.n_gates = n_gates;
+  a.prep_off = reinterpret_cast<const int64_t*>(b + o_po);
+  a.prep_gates = reinterpret_cast<const uint8_t*>(b + o_pg);
+  a.gate_of = reinterpret_cast<const int32_t*>(b + o_go);
+  a.r_max = r_max;
+  a.levels = levels;
+  a.Q = Q;
+  a.V = reinterpret_cast<double*>(b + o_v);
+  a.probs = probs;
+  HIP_TRY(gst::launch_predict(a, ctx->stream));
+  // the host arrays are read by the copies above before the call returns
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  return GST_OK;
+}
+
+int gst_tv_distance(gst_ctx* ctx, const double* p, const double* q, int64_t n, int m, double* out) {
+  if (!ctx) return fail(GST_EINVAL, "ctx is NULL");
+  if (n < 0 || m < 1) return fail(GST_EINVAL, "n >= 0 and m >= 1 required");
+  if (n > 0 && (!p || !q || !out)) return fail(GST_EINVAL, "NULL argument");
+  HIP_TRY(hipSetDevice(ctx->device));
+  HIP_TRY(gst::launch_tv_distance(p, q, n, m, out, ctx->stream));
+  return GST_OK;
+}
+
 int gst_set_plan_jump(gst_ctx* ctx, int reps) {
   if (!ctx) return fail(GST_EINVAL, "ctx is NULL");
   if (reps != 0 && (reps < 2 || reps > 16 || (reps & (reps - 1)) != 0))

@@ -273,6 +273,24 @@ int trunk_blocks_for(int64_t n_trunks);
 hipError_t launch_inject(const InjectLaunch& a, hipStream_t stream);
 hipError_t launch_grad_gemm(const GemmLaunch& a, hipStream_t stream);
 hipError_t launch_reduce_plan(const PlanReduce& a, hipStream_t stream);
+// Predictions of repeated gate applications: V = block-start states
+// [n_pairs][Q][D], probs [n_pairs][r_max + 1][M]; pair = preparation * n_gates + gate.
+struct PredictLaunch {
+  int D, M, K;
+  const double* rho;
+  const double* E;
+  const double* G;
+  int n_pairs, n_gates;
+  const int64_t* prep_off;    // [n_prep + 1]
+  const uint8_t* prep_gates;
+  const int32_t* gate_of;     // [n_gates]
+  int r_max, levels, Q;       // blocks of 2^(levels-1) repetitions, Q blocks
+  double* V;
+  double* probs;
+};
+hipError_t launch_predict(const PredictLaunch& a, hipStream_t stream);
+hipError_t launch_tv_distance(const double* p, const double* q, int64_t n, int M, double* out, hipStream_t stream);
+
 // reverse fill tasks (adjoints inside the jumps into BA)
 hipError_t launch_fill_rev(const PlanArgs& a, hipStream_t stream);
 int fill_blocks_for(int64_t n_fill);

@@ -104,43 +104,6 @@ __host__ __device__ inline size_t trunk_lds_bytes(int K, int levels) {
   return a > r ? a : r;
 }
 
-// C = A B for 16 x 16 matrices in the gate layout, by one wave: column c of
-// C is A times column c of B, a dot16 per 16-lane team, four columns per team.
-__device__ __forceinline__ void wave_matmul(double* C, const double* A, const double* B, int lane) {
-  const int i = lane & 15, t = lane >> 4;
-  const Row16 Ar = load_row(A + i * ROW);
-  double y[4];
-#pragma unroll
-  for (int u = 0; u < 4; ++u) y[u] = dot16(B[i * ROW + 4 * u + t], Ar);
-#pragma unroll
-  for (int u = 0; u < 4; ++u) C[i * ROW + 4 * u + t] = y[u];
-  wave_sync();
-}
-
-// The trunk's jump matrices into the wave's slots js[e * GATE_STRIDE]: slot 0
-// = G_{g_per-1} ... G_{g_0} of the pattern (reverse: its transpose G_{g_0}^T
-// ... G_{g_per-1}^T, from the transposed gate set), slot e = slot e-1 squared.
-__device__ void build_jumps(double* js, const double* gates, uint32_t pat, int g3, int levels, bool rev,
-                            int lane) {
-  const int per = (int)(pat & 0xffu);
-  const int g[4] = {(int)((pat >> 8) & 0xffu), (int)((pat >> 16) & 0xffu), (int)((pat >> 24) & 0xffu), g3};
-  const int i = lane & 15, t = lane >> 4;
-  if (per == 1) {
-#pragma unroll
-    for (int u = 0; u < 4; ++u) js[i * ROW + 4 * u + t] = gates[g[0] * GATE_STRIDE + i * ROW + 4 * u + t];
-    wave_sync();
-  } else {
-    const double* src = gates + g[rev ? per - 1 : 0] * GATE_STRIDE;
-    for (int k = 1; k < per; ++k) {  // the last product lands in slot 0
-      double* dst = js + (((per - 1 - k) & 1) ? GATE_STRIDE : 0);
-      wave_matmul(dst, gates + g[rev ? per - 1 - k : k] * GATE_STRIDE, src, lane);
-      src = dst;
-    }
-  }
-  for (int e = 1; e < levels; ++e)
-    wave_matmul(js + e * GATE_STRIDE, js + (e - 1) * GATE_STRIDE, js + (e - 1) * GATE_STRIDE, lane);
-}
-
 // Lane i's row of the matrix of op `od`: a gate (of the gate set or its
 // transpose) or a jump matrix slot.
 __device__ __forceinline__ const double* op_row(const double* gates, const double* js, uint32_t od, int i) {

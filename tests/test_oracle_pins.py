@@ -480,3 +480,58 @@ def test_edge_cases(oracle_lib):
     assert rc == 0 and np.isfinite(F)
     _, gE, _ = W.unpack_params(grad, 1, 2, 2)
     assert np.all(gE[1] == 0.0) and np.any(gE[0] != 0.0)  # dF/de_1 is exactly zero
+
+
+# ---------------------------------------------------------------------------
+# Predictions of repeated gate applications and the statistical distance
+# (thesis Eqs. GSTPrediction, statisticaldistance)
+# ---------------------------------------------------------------------------
+def test_statistical_distance_pins(oracle_lib):
+    """D = 1/2 sum |p - q| is zero on equal distributions, one on disjoint point
+    masses, symmetric, bounded by one, obeys the triangle inequality, and equals
+    the largest difference of the probabilities of one event (max over subsets,
+    brute force)."""
+    rng = np.random.default_rng(5)
+    P = rng.dirichlet(np.ones(4), size=200)
+    Q = rng.dirichlet(np.ones(4), size=200)
+    R = rng.dirichlet(np.ones(4), size=200)
+    dpq = oracle_lib.tv_distance(P, Q)
+    assert np.all(oracle_lib.tv_distance(P, P) == 0.0)
+    assert np.array_equal(dpq, oracle_lib.tv_distance(Q, P))
+    assert np.all((dpq >= 0) & (dpq <= 1))
+    assert np.all(dpq <= oracle_lib.tv_distance(P, R) + oracle_lib.tv_distance(R, Q) + 1e-15)
+    eye = np.eye(4)
+    assert np.all(oracle_lib.tv_distance(eye[[0, 1, 2]], eye[[3, 2, 0]]) == 1.0)
+    subsets = [[j for j in range(4) if (a >> j) & 1] for a in range(16)]
+    for x in range(20):
+        best = max(abs(P[x, A].sum() - Q[x, A].sum()) for A in subsets)
+        assert abs(dpq[x] - best) <= 1e-15
+
+
+@pytest.mark.parametrize("kind", ["1q", "2q"])
+def test_prediction_depolarizing_closed_form(oracle_lib, kind):
+    """Predictions <<E| G_s^r G_prep |rho>> of lambda-depolarized ideal gates follow
+    p = 1/d + (1-lambda)^L (p_ideal - 1/d), L = r + |prep| (state vectors for
+    p_ideal), and the statistical distance between the predictions for two
+    values of lambda is |(1-l1)^L - (1-l2)^L| D(p_ideal, uniform)."""
+    names, Us, n = W.ideal_unitaries(kind)
+    d = 2 ** n
+    rho, E = ideal_spam(n)
+    preps = [[], [1, 1], [2, 1], [1, 2, 1]] if n == 1 else [[], [1, 1], [4, 3], [2, 2, 1, 1, 3, 5]]
+    gates = list(range(len(Us)))
+    r_max = 60
+    out = {}
+    for lam in (1e-3, 4e-3):
+        G = np.array([W.depolarizing_ptm(lam, n) @ W.ptm_from_unitary(U) for U in Us])
+        out[lam] = oracle_lib.predict(rho, E, G, preps, gates, r_max)
+    D = oracle_lib.tv_distance(out[1e-3], out[4e-3])
+    for p, w in enumerate(preps):
+        for si, s in enumerate(gates):
+            for r in (0, 1, 7, 60):
+                word = list(w) + [s] * r
+                pid = statevector_probs(Us, word, d)
+                L = len(word)
+                want = 1 / d + (1 - 1e-3) ** L * (pid - 1 / d)
+                assert np.allclose(out[1e-3][p, si, r], want, atol=5e-15)
+                dwant = abs((1 - 1e-3) ** L - (1 - 4e-3) ** L) * 0.5 * np.abs(pid - 1 / d).sum()
+                assert abs(D[p, si, r] - dwant) <= 1e-14
