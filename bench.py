@@ -27,6 +27,8 @@ sys.path.insert(0, ROOT)
 METRIC = "sequence evals/s incl. gradient (2q, FP64); p50/p99 latency of served fits"
 # MI355X published FP64 vector peak: 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
 PEAK_FP64 = 78.6
+# predictions: the oracle runs the same workload (r = 0..1000, ~2 s a pass)
+F3_CPU_RMAX = 1000
 
 
 _DESC = {
@@ -86,10 +88,23 @@ def _cpu_worker(args):
     name, seconds = args
     sys.path.insert(0, ROOT)
     import oracle
-    sample, _ = _cpu_sample(name)
     n = 0
     seqs = 0
     t0 = time.perf_counter()
+    if name == "f3":
+        from paper_2008_13490_amd import workloads as W
+        pw = W.prediction_workload(F3_CPU_RMAX)
+        g, gi = pw.estimate, pw.ideal
+        p_ideal = oracle.predict(gi.rho, gi.effects, gi.gates, pw.preps, pw.gates, pw.r_max)
+        t0 = time.perf_counter()
+        while True:
+            oracle.tv_distance(oracle.predict(g.rho, g.effects, g.gates, pw.preps, pw.gates, pw.r_max), p_ideal)
+            seqs += len(pw.preps) * len(pw.gates) * (pw.r_max + 1)
+            n += 1
+            if time.perf_counter() - t0 >= seconds:
+                break
+        return n, time.perf_counter() - t0, seqs
+    sample, _ = _cpu_sample(name)
     while True:
         for m, sl, cnt in sample:
             oracle.loglik(m.rho, m.effects, m.gates, sl.offsets, sl.gates, cnt)
@@ -104,7 +119,11 @@ def cpu_baseline(name: str, seconds: float, workers: int):
     import multiprocessing as mp
     import oracle
     oracle.build(force=not os.path.exists(oracle.library_path()))
-    _, what = _cpu_sample(name)
+    if name == "f3":
+        what = (f"the full workload: four initial states x 6 gates x r = 0..{F3_CPU_RMAX} as plain words, "
+                f"with the distance to the ideal predictions")
+    else:
+        _, what = _cpu_sample(name)
     ctx = mp.get_context("spawn")
     t0 = time.perf_counter()
     with ctx.Pool(workers) as pool:
@@ -115,10 +134,10 @@ def cpu_baseline(name: str, seconds: float, workers: int):
     busy = max(r[1] for r in res)
     return {
         "value": seqs / busy,
-        "unit": "sequence evals/s",
+        "unit": "predicted distributions/s" if name == "f3" else "sequence evals/s",
         "cores": workers,
         "kind": "oracle",
-        "sample": f"{what} evaluated {passes} times with gradient, "
+        "sample": f"{what} evaluated {passes} times{'' if name == 'f3' else ' with gradient'}, "
                   f"{workers} single-threaded processes for ~{seconds:.0f} s each (wall {wall:.1f} s)",
     }
 
@@ -158,7 +177,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5"])
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "f3"])
     ap.add_argument("--rate", type=float, default=100.0, help="c5 / serving: arrivals per second")
     ap.add_argument("--requests", type=int, default=100, help="c5 / serving: requests in the trace")
     ap.add_argument("--iters", type=int, default=20, help="c5 / serving: iterations per request")
@@ -193,6 +212,8 @@ def main():
         out = run_uneven(args)
     elif args.workload == "c5":
         out = run_serving(args)
+    elif args.workload == "f3":
+        out = run_predict(args)
     else:
         out = run_structured(args)
         if args.workload == "c2" and not args.no_serving:
@@ -476,6 +497,95 @@ def run_uneven(args):
         "autotune": {str(n): {"best": f"{v['best'][0]} seqs/tile x {v['best'][1] or 'max'} blocks/CU",
                               "ms": v["ms"]} for n, v in tuned.items()} if tuned else None,
     }
+
+
+def run_predict(args):
+    """Predictions of repeated gate applications (thesis Sec. 6.3, Eq.
+    GSTPrediction) and their statistical distance to the ideal predictions
+    (Eq. statisticaldistance).  One step = one gst_predict of the estimate for
+    the four initial states x 6 gates x r = 0..1000 plus the distance to the
+    ideal gate set's predictions (resident)."""
+    import torch
+    from paper_2008_13490_amd import api
+    from paper_2008_13490_amd import workloads as W
+
+    pw = W.prediction_workload(1000)
+    ctx = api.Context(0)
+    est, ide = (api.DeviceGateSet.from_numpy(g.n_qubits, g.rho, g.effects, g.gates) for g in (pw.estimate, pw.ideal))
+    pred = api.Predictor(ctx, pw.preps, pw.gates, pw.r_max)
+    p_ideal = pred(ide)
+    p = torch.empty_like(p_ideal)
+    d = torch.empty(p.shape[:-1], dtype=torch.float64, device=p.device)
+
+    def step():
+        pred(est, out=p)
+        api.tv_distance(ctx, p, p_ideal, out=d)
+
+    families = ("predict_chain", "predict_fill", "tv_distance")
+    for _ in range(args.warmup):
+        step()
+    ctx.sync()
+    n_break = max(1, min(args.steps, 20))
+    api.profile_enable(ctx, True)
+    for _ in range(n_break):
+        step()
+    ctx.sync()
+    brk = _profile(api, ctx, families)
+    dom = max(brk, key=lambda f: brk[f][0])
+    api.profile_only(ctx, dom)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ctx.sync()
+    tot = _profile(api, ctx, (dom,))
+    api.profile_only(ctx, None)
+    api.profile_enable(ctx, False)
+    fams = {dom: (tot[dom][0] - brk[dom][0], tot[dom][1] - brk[dom][1])}
+    elapsed = t1 - t0
+    n_pairs = len(pw.preps) * len(pw.gates)
+    per_step = n_pairs * (pw.r_max + 1)
+    D, M = pw.estimate.D, pw.estimate.M
+    flops = predict_flops(dom, D, M, [len(w) for w in pw.preps], len(pw.gates), pw.r_max)
+    return {
+        "metric": "predicted outcome distributions/s with statistical distance (2q, FP64)",
+        "value": per_step * args.steps / elapsed,
+        "unit": "predicted distributions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"f3: two-qubit predictions <<E|(G_s)^r G_prep|rho>> for the 4 initial states "
+                               f"x 6 gates x r = 0..{pw.r_max} of the C2 evaluation point, statistical distance "
+                               f"to the ideal gate set's predictions",
+                   "distributions_per_step": per_step},
+        "roofline": _roofline(dom, fams, flops, None),
+        "kernels_ms_per_step": {f: brk[f][0] / n_break for f in brk},
+    }
+
+
+def predict_flops(family, D, M, prep_lens, n_gates, r_max, B=32):
+    """FP64 flops one launch of a prediction kernel does: the chain applies each
+    preparation word and (Q - 1) block jumps per pair and builds (G_s)^B with
+    log2(B) squarings (2D^3 each); the fill steps through every block with
+    single mat-vecs (2D^2) and reads out every state (2DM)."""
+    Q = (r_max + 1 + B - 1) // B
+    pairs = len(prep_lens) * n_gates
+    if family == "predict_chain":
+        return 2.0 * D * D * (n_gates * sum(prep_lens) + pairs * (Q - 1)) + \
+            pairs * 5 * 2.0 * D ** 3
+    if family == "predict_fill":
+        return pairs * (2.0 * D * D * (r_max + 1 - Q) + 2.0 * D * M * (r_max + 1))
+    if family == "tv_distance":
+        return pairs * (r_max + 1) * 3.0 * M
+    return 0.0
 
 
 def req_plan_info(req):

@@ -220,7 +220,9 @@ int gst_set_plan_jump(gst_ctx* ctx, int reps);
  * block with (G_s)^32 (built per call by repeated squaring) and every block then
  * takes single steps, so the probabilities for r < 32 equal the plain evaluation of
  * the word bit for bit and later ones agree to rounding.  The host arrays are read
- * before the call returns (it synchronizes the context stream).  GST_EINVAL for
+ * before the call returns (copied into pinned staging memory); the evaluation is
+ * stream-ordered on the context's stream and the call does not wait for it.  The
+ * context's workspace holds the block-start states until the next call.  GST_EINVAL for
  * three qubits, a word longer than 64 gates, a gate index out of range,
  * r_max outside 0 .. 2^24 or more than 2^24 (preparation, gate) pairs.
  */
@@ -243,7 +245,8 @@ int gst_tv_distance(gst_ctx* ctx, const double* p, const double* q, int64_t n, i
  * gst_profile_read synchronizes the stream and returns, for the kernel family
  * `kernel` ("leaf", "reduce", "trunk_fwd", "trunk_bwd", "inject",
  * "grad_gemm", "fill", "tiles_2q", "tiles_1q", "tiles_reduce",
- * "chain_3q", "gemm_3q", "reduce_3q", or "batch" for a whole
+ * "chain_3q", "gemm_3q", "reduce_3q", "predict_chain", "predict_fill",
+ * "tv_distance", or "batch" for a whole
  * gst_batch_run), the summed
  * elapsed milliseconds and the number of kernels since profiling was
  * enabled; the counters are not reset by reading.

@@ -274,29 +274,55 @@ def tune_set(ctx: Context, n_qubits: int, seqs_per_tile: int = 0, blocks_per_cu:
     _lib.check(ctx.lib.gst_tune_set(ctx.handle, n_qubits, seqs_per_tile, blocks_per_cu))
 
 
-def predict(ctx: Context, gs: "DeviceGateSet", preps, gates, r_max: int) -> torch.Tensor:
-    """Predictions of repeated gate applications (``gst_predict``): a tensor
-    ``[len(preps), len(gates), r_max + 1, M]`` of <<E_m| G_s^r G_prep |rho>>;
-    ``preps`` are gate-index words in time order, ``gates`` gate indices."""
-    import numpy as np
-    off = np.zeros(len(preps) + 1, np.int64)
-    for x, w in enumerate(preps):
-        off[x + 1] = off[x] + len(w)
-    words = np.ascontiguousarray(np.concatenate([np.asarray(w, np.uint8) for w in preps])
-                                 if off[-1] > 0 else np.zeros(1, np.uint8))
-    g = np.ascontiguousarray(np.asarray(gates, np.int32))
-    out = torch.empty((len(preps), len(g), r_max + 1, gs.M), dtype=torch.float64, device=ctx._dev())
-    _lib.check(ctx.lib.gst_predict(ctx.handle, ctypes.byref(gs.as_struct()), len(preps), off.ctypes.data,
-                                   words.ctypes.data, len(g), g.ctypes.data, int(r_max), _ptr(out)))
-    return out
+class Predictor:
+    """Predictions of repeated gate applications (``gst_predict``) for fixed
+    preparation words (time order), gate indices and r_max: the host arrays are
+    marshalled once; each call evaluates a gate set into a tensor
+    ``[len(preps), len(gates), r_max + 1, M]`` of <<E_m| G_s^r G_prep |rho>>."""
+
+    def __init__(self, ctx: Context, preps, gates, r_max: int):
+        import numpy as np
+        self.ctx = ctx
+        self.n_prep = len(preps)
+        off = np.zeros(len(preps) + 1, np.int64)
+        for x, w in enumerate(preps):
+            off[x + 1] = off[x] + len(w)
+        self._off = off
+        self._words = np.ascontiguousarray(np.concatenate([np.asarray(w, np.uint8) for w in preps])
+                                           if off[-1] > 0 else np.zeros(1, np.uint8))
+        self._gates = np.ascontiguousarray(np.asarray(gates, np.int32))
+        self.r_max = int(r_max)
+
+    def shape(self, M: int):
+        return (self.n_prep, len(self._gates), self.r_max + 1, M)
+
+    def __call__(self, gs: "DeviceGateSet", out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        shape = self.shape(gs.M)
+        if out is None:
+            out = torch.empty(shape, dtype=torch.float64, device=self.ctx._dev())
+        if not (out.is_cuda and out.dtype == torch.float64 and out.is_contiguous() and tuple(out.shape) == shape):
+            raise ValueError(f"out must be a contiguous float64 device tensor of shape {shape}")
+        _lib.check(self.ctx.lib.gst_predict(self.ctx.handle, ctypes.byref(gs.as_struct()), self.n_prep,
+                                            self._off.ctypes.data, self._words.ctypes.data, len(self._gates),
+                                            self._gates.ctypes.data, self.r_max, _ptr(out)))
+        return out
 
 
-def tv_distance(ctx: Context, p: torch.Tensor, q: torch.Tensor) -> torch.Tensor:
+def predict(ctx: Context, gs: "DeviceGateSet", preps, gates, r_max: int,
+            out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """One-off ``Predictor(ctx, preps, gates, r_max)(gs, out)``."""
+    return Predictor(ctx, preps, gates, r_max)(gs, out)
+
+
+def tv_distance(ctx: Context, p: torch.Tensor, q: torch.Tensor,
+                out: Optional[torch.Tensor] = None) -> torch.Tensor:
     """Statistical distance 1/2 sum_m |p - q| over the last axis (``gst_tv_distance``)."""
     assert p.shape == q.shape and p.dtype == torch.float64 and q.dtype == torch.float64
     m = p.shape[-1]
     p2, q2 = p.contiguous(), q.contiguous()
-    out = torch.empty(p.shape[:-1], dtype=torch.float64, device=p.device)
+    if out is None:
+        out = torch.empty(p.shape[:-1], dtype=torch.float64, device=p.device)
+    assert out.shape == p.shape[:-1] and out.is_contiguous() and out.dtype == torch.float64
     _lib.check(ctx.lib.gst_tv_distance(ctx.handle, _ptr(p2), _ptr(q2), p2.numel() // m, m, _ptr(out)))
     return out
 

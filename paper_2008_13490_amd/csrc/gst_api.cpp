@@ -65,6 +65,38 @@ struct DevBuf {
   }
 };
 
+// Pinned host staging for small per-call host arrays: the caller's arrays are
+// copied into it on the host, then one asynchronous copy moves them to the
+// device, so the call returns without waiting for the stream.  The next user
+// waits for the previous copy out of the buffer (normally long finished).
+struct HostStage {
+  void* p = nullptr;
+  size_t bytes = 0;
+  hipEvent_t done = nullptr;
+  ~HostStage() {
+    if (done) (void)hipEventDestroy(done);
+    if (p) (void)hipHostFree(p);
+  }
+  int acquire(size_t need) {
+    if (done) HIP_TRY(hipEventSynchronize(done));
+    if (need > bytes) {
+      if (p) HIP_TRY(hipHostFree(p));
+      p = nullptr;
+      bytes = 0;
+      const size_t cap = std::max(need, (size_t)4096);
+      HIP_TRY(hipHostMalloc(&p, cap, hipHostMallocDefault));
+      bytes = cap;
+    }
+    if (!done) HIP_TRY(hipEventCreateWithFlags(&done, hipEventDisableTiming));
+    return GST_OK;
+  }
+  int copy_to(void* dst, size_t n, hipStream_t stream) {
+    HIP_TRY(hipMemcpyAsync(dst, p, n, hipMemcpyHostToDevice, stream));
+    HIP_TRY(hipEventRecord(done, stream));
+    return GST_OK;
+  }
+};
+
 // Per-kernel-family event timing (gst_profile_*).
 struct Profiler {
   bool on = false;
@@ -76,7 +108,7 @@ struct Profiler {
   };
   std::vector<Pending> pending;
   std::vector<hipEvent_t> pool;
-  static constexpr int kMaxFamilies = 16;
+  static constexpr int kMaxFamilies = 20;
   double total_ms[kMaxFamilies] = {0};
   int64_t launches[kMaxFamilies] = {0};
   hipEvent_t get() {
@@ -101,11 +133,13 @@ struct Profiler {
 
 enum Family { FAM_LEAF = 0, FAM_REDUCE = 1, FAM_TRUNK_FWD = 2, FAM_TRUNK_BWD = 3, FAM_INJECT = 4, FAM_GEMM = 5,
               FAM_BATCH = 6, FAM_TILES16 = 7, FAM_TILES4 = 8, FAM_TILES_RED = 9, FAM_CHAIN64 = 10,
-              FAM_GEMM64 = 11, FAM_REDUCE64 = 12, FAM_FILL = 13, FAM_N = 14 };
+              FAM_GEMM64 = 11, FAM_REDUCE64 = 12, FAM_FILL = 13, FAM_PRED_CHAIN = 14,
+              FAM_PRED_FILL = 15, FAM_TV = 16, FAM_N = 17 };
 static_assert(FAM_N <= Profiler::kMaxFamilies, "profiler arrays too small");
 static const char* kFamilyNames[FAM_N] = {"leaf",  "reduce",  "trunk_fwd", "trunk_bwd",   "inject",
                                           "grad_gemm", "batch", "tiles_2q",  "tiles_1q", "tiles_reduce",
-                                          "chain_3q",  "gemm_3q", "reduce_3q", "fill"};
+                                          "chain_3q",  "gemm_3q", "reduce_3q", "fill", "predict_chain",
+                                          "predict_fill", "tv_distance"};
 
 // Carve consecutive aligned regions out of one allocation.
 struct Carver {
@@ -128,6 +162,7 @@ struct gst_ctx {
   hipStream_t stream = nullptr;
   unsigned long long* status = nullptr;  // device [2]
   DevBuf ws;
+  HostStage stage;
   Profiler prof;
 };
 
@@ -791,9 +826,14 @@ int gst_predict(gst_ctx* ctx, const gst_gateset* theta, int n_prep, const int64_
                o_go = c.take<int32_t>(n_gates), o_v = c.take<double>((size_t)n_pairs * Q * D);
   if ((rc = ctx->ws.reserve(c.off + 256, ctx->stream))) return rc;
   char* b = reinterpret_cast<char*>(ctx->ws.p);
-  HIP_TRY(hipMemcpyAsync(b + o_po, prep_offsets, (size_t)(n_prep + 1) * 8, hipMemcpyHostToDevice, ctx->stream));
-  if (n_steps > 0) HIP_TRY(hipMemcpyAsync(b + o_pg, prep_gates, (size_t)n_steps, hipMemcpyHostToDevice, ctx->stream));
-  HIP_TRY(hipMemcpyAsync(b + o_go, gates, (size_t)n_gates * 4, hipMemcpyHostToDevice, ctx->stream));
+  // the three host arrays, laid out as in the workspace, in one copy
+  const size_t span = o_v - o_po;
+  if ((rc = ctx->stage.acquire(span))) return rc;
+  char* h = reinterpret_cast<char*>(ctx->stage.p);
+  std::memcpy(h + (o_po - o_po), prep_offsets, (size_t)(n_prep + 1) * 8);
+  if (n_steps > 0) std::memcpy(h + (o_pg - o_po), prep_gates, (size_t)n_steps);
+  std::memcpy(h + (o_go - o_po), gates, (size_t)n_gates * 4);
+  if ((rc = ctx->stage.copy_to(b + o_po, span, ctx->stream))) return rc;
   gst::PredictLaunch a{};
   a.D = D;
   a.M = theta->n_outcomes;
@@ -811,9 +851,14 @@ int gst_predict(gst_ctx* ctx, const gst_gateset* theta, int n_prep, const int64_
   a.Q = Q;
   a.V = reinterpret_cast<double*>(b + o_v);
   a.probs = probs;
-  HIP_TRY(gst::launch_predict(a, ctx->stream));
-  // the host arrays are read by the copies above before the call returns
-  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  {
+    ProfScope ps(ctx, FAM_PRED_CHAIN);
+    HIP_TRY(gst::launch_predict_chain(a, ctx->stream));
+  }
+  {
+    ProfScope ps(ctx, FAM_PRED_FILL);
+    HIP_TRY(gst::launch_predict_fill(a, ctx->stream));
+  }
   return GST_OK;
 }
 
@@ -822,6 +867,7 @@ int gst_tv_distance(gst_ctx* ctx, const double* p, const double* q, int64_t n, i
   if (n < 0 || m < 1) return fail(GST_EINVAL, "n >= 0 and m >= 1 required");
   if (n > 0 && (!p || !q || !out)) return fail(GST_EINVAL, "NULL argument");
   HIP_TRY(hipSetDevice(ctx->device));
+  ProfScope ps(ctx, FAM_TV);
   HIP_TRY(gst::launch_tv_distance(p, q, n, m, out, ctx->stream));
   return GST_OK;
 }

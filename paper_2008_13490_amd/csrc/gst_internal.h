@@ -288,7 +288,9 @@ struct PredictLaunch {
   double* V;
   double* probs;
 };
-hipError_t launch_predict(const PredictLaunch& a, hipStream_t stream);
+// The block-start chain (V), then the blocks with their readouts (probs).
+hipError_t launch_predict_chain(const PredictLaunch& a, hipStream_t stream);
+hipError_t launch_predict_fill(const PredictLaunch& a, hipStream_t stream);
 hipError_t launch_tv_distance(const double* p, const double* q, int64_t n, int M, double* out, hipStream_t stream);
 
 // reverse fill tasks (adjoints inside the jumps into BA)

@@ -96,22 +96,31 @@ __global__ __launch_bounds__(256) void tv_distance_kernel(const double* __restri
 
 }  // namespace
 
-hipError_t launch_predict(const PredictLaunch& a, hipStream_t stream) {
-  if (a.n_pairs <= 0 || a.Q <= 0 || a.levels < 1 || a.levels > 6) return hipErrorInvalidValue;
-  const size_t chain_bytes = (predict_head_doubles(a.K) + (size_t)a.levels * GATE_STRIDE) * 8 + 64;
-  const size_t fill_bytes = predict_head_doubles(a.K) * 8 + 64;
+static bool predict_args_ok(const PredictLaunch& a) {
+  return a.n_pairs > 0 && a.Q > 0 && a.levels >= 1 && a.levels <= 6 && (a.D == 4 || a.D == 16);
+}
+
+hipError_t launch_predict_chain(const PredictLaunch& a, hipStream_t stream) {
+  if (!predict_args_ok(a)) return hipErrorInvalidValue;
+  const size_t bytes = (predict_head_doubles(a.K) + (size_t)a.levels * GATE_STRIDE) * 8 + 64;
+  const int blocks = a.n_pairs < 65535 ? a.n_pairs : 65535;
+  if (a.D == 16)
+    gst_launch(predict_chain_kernel<16>, dim3(blocks), dim3(64), bytes, stream, a);
+  else
+    gst_launch(predict_chain_kernel<4>, dim3(blocks), dim3(64), bytes, stream, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_predict_fill(const PredictLaunch& a, hipStream_t stream) {
+  if (!predict_args_ok(a)) return hipErrorInvalidValue;
+  const size_t bytes = predict_head_doubles(a.K) * 8 + 64;
   const int64_t groups = ((int64_t)a.n_pairs * a.Q + TPW - 1) / TPW;
-  const int fill_blocks = (int)((groups + WAVES - 1) / WAVES < 4096 ? (groups + WAVES - 1) / WAVES : 4096);
-  const int chain_blocks = a.n_pairs < 65535 ? a.n_pairs : 65535;
-  if (a.D == 16) {
-    gst_launch(predict_chain_kernel<16>, dim3(chain_blocks), dim3(64), chain_bytes, stream, a);
-    gst_launch(predict_fill_kernel<16>, dim3(fill_blocks), dim3(256), fill_bytes, stream, a);
-  } else if (a.D == 4) {
-    gst_launch(predict_chain_kernel<4>, dim3(chain_blocks), dim3(64), chain_bytes, stream, a);
-    gst_launch(predict_fill_kernel<4>, dim3(fill_blocks), dim3(256), fill_bytes, stream, a);
-  } else {
-    return hipErrorInvalidValue;
-  }
+  const int64_t want = (groups + WAVES - 1) / WAVES;
+  const int blocks = (int)(want < 4096 ? want : 4096);
+  if (a.D == 16)
+    gst_launch(predict_fill_kernel<16>, dim3(blocks), dim3(256), bytes, stream, a);
+  else
+    gst_launch(predict_fill_kernel<4>, dim3(blocks), dim3(256), bytes, stream, a);
   return hipGetLastError();
 }
 

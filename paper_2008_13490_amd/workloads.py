@@ -239,6 +239,42 @@ def gateset_from_rotations(kind: str, lam: float, axes, deltas) -> GateSet:
 
 
 # ---------------------------------------------------------------------------
+# Predictions of repeated gate applications (Sec. 6.3, Eq. GSTPrediction)
+# ---------------------------------------------------------------------------
+# The four initial states of the prediction test (Eqs. GSTInitialStatePrep00 -
+# GSTInitialStatePrepPsi), as time-ordered words over the two-qubit gates
+# (Gii, Gxi, Gix, Gyi, Giy, Gcz).  The thesis's singlet preparation ends with
+# CNOT(0 -> 1); this gate set has CZ, and CNOT(0 -> 1) = (1 x Ry) CZ (1 x Ry^-1)
+# with Ry = Ry(pi/2) and Ry^-1 = Ry^3 up to phase, i.e. Giy Giy Giy Gcz Giy.
+PREDICTION_PREPS_2Q = {
+    "00": (),
+    "10": (1, 1),
+    "++": (4, 3),
+    "psi-": (2, 2, 1, 1, 3, 4, 4, 4, 5, 4),
+}
+
+
+@dataclasses.dataclass
+class PredictionWorkload:
+    estimate: GateSet      # the gate set whose predictions are evaluated
+    ideal: GateSet         # ideal gates and SPAM (the reference distribution p^(id))
+    preps: List[Tuple[int, ...]]
+    gates: List[int]
+    r_max: int
+
+
+def prediction_workload(r_max: int = 1000) -> PredictionWorkload:
+    """Two-qubit predictions for r = 0 .. r_max repetitions of every gate from the
+    four initial states; the estimate is the C2 evaluation point (1e-3
+    depolarizing and N(0, 0.01) over-rotations), the reference the ideal set."""
+    estimate = noisy_gateset("2q", LAMBDA, SIGMA, _streams("c2")[3])
+    names, Us, n = ideal_unitaries("2q")
+    G = np.ascontiguousarray(np.array([ptm_from_unitary(U) for U in Us]))
+    ideal = GateSet(n, names, estimate.rho.copy(), estimate.effects.copy(), G, np.array(Us), 0.0)
+    return PredictionWorkload(estimate, ideal, list(PREDICTION_PREPS_2Q.values()), list(range(6)), r_max)
+
+
+# ---------------------------------------------------------------------------
 # Sequence lists (Sec. 6.3.1, Eq. GSTFullFiducialsGerms)
 # ---------------------------------------------------------------------------
 def shortlex_words(alphabet: Sequence[int], count: int) -> List[Tuple[int, ...]]:

@@ -517,7 +517,7 @@ def test_prediction_depolarizing_closed_form(oracle_lib, kind):
     names, Us, n = W.ideal_unitaries(kind)
     d = 2 ** n
     rho, E = ideal_spam(n)
-    preps = [[], [1, 1], [2, 1], [1, 2, 1]] if n == 1 else [[], [1, 1], [4, 3], [2, 2, 1, 1, 3, 5]]
+    preps = [[], [1, 1], [2, 1], [1, 2, 1]] if n == 1 else [list(w) for w in W.PREDICTION_PREPS_2Q.values()]
     gates = list(range(len(Us)))
     r_max = 60
     out = {}
@@ -535,3 +535,23 @@ def test_prediction_depolarizing_closed_form(oracle_lib, kind):
                 assert np.allclose(out[1e-3][p, si, r], want, atol=5e-15)
                 dwant = abs((1 - 1e-3) ** L - (1 - 4e-3) ** L) * 0.5 * np.abs(pid - 1 / d).sum()
                 assert abs(D[p, si, r] - dwant) <= 1e-14
+
+
+def test_prediction_preparations_2q():
+    """The four initial states of the prediction test from their time-ordered
+    words over the ideal two-qubit gates (state vectors, up to global phase):
+    |00>, |10>, |++> and the singlet (|01> - |10>)/sqrt(2), whose CNOT is built
+    from CZ and Ry(pi/2) rotations of the target."""
+    names, Us, n = W.ideal_unitaries("2q")
+    want = {
+        "00": np.array([1, 0, 0, 0]),
+        "10": np.array([0, 0, 1, 0]),
+        "++": np.array([1, 1, 1, 1]) / 2,
+        "psi-": np.array([0, 1, -1, 0]) / np.sqrt(2),
+    }
+    for key, word in W.PREDICTION_PREPS_2Q.items():
+        psi = np.zeros(4, np.complex128)
+        psi[0] = 1
+        for g in word:
+            psi = Us[g] @ psi
+        assert abs(abs(np.vdot(want[key], psi)) - 1) < 1e-14, (key, psi)
