@@ -392,16 +392,26 @@ __device__ void write_slab(double* lds_raw, double obj, double drho, double (&dE
   }
 }
 
-// C = A B for 16 x 16 matrices in the gate layout, by one wave: column c of
-// C is A times column c of B, a dot16 per 16-lane team, four columns per team.
+// C = A B for 16 x 16 matrices in the gate layout (LDS), by one wave on the
+// FP64 matrix cores: four 16x16x4 MFMAs, the k-th (k = 0..3) adding columns
+// 4k..4k+3 of A times rows 4k..4k+3 of B.  Lane l supplies A[l & 15][4k + (l >> 4)]
+// and B[4k + (l >> 4)][l & 15] and ends with C[4v + (l >> 4)][l & 15] in
+// register v.  Each MFMA adds its four products as sequential fused
+// multiply-adds in ascending order, so every entry is the same fused
+// multiply-add chain over j = 0..15 as a dot product with a zero start.
 __device__ __forceinline__ void wave_matmul(double* C, const double* A, const double* B, int lane) {
   const int i = lane & 15, t = lane >> 4;
-  const Row16 Ar = load_row(A + i * ROW);
-  double y[4];
+  double a[4], b[4];
 #pragma unroll
-  for (int u = 0; u < 4; ++u) y[u] = dot16(B[i * ROW + 4 * u + t], Ar);
+  for (int k = 0; k < 4; ++k) {
+    a[k] = A[i * ROW + 4 * k + t];
+    b[k] = B[(4 * k + t) * ROW + i];
+  }
+  d4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-  for (int u = 0; u < 4; ++u) C[i * ROW + 4 * u + t] = y[u];
+  for (int k = 0; k < 4; ++k) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[k], b[k], acc, 0, 0, 0);
+#pragma unroll
+  for (int v = 0; v < 4; ++v) C[(4 * v + t) * ROW + i] = acc[v];
   wave_sync();
 }
 
