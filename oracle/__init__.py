@@ -6,3 +6,4 @@ Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
 from .binding import (  # noqa: F401
     build, probs, probs_extended, loglik, vjp, tv_distance, predict, OracleError, library_path,
 )
+from . import params  # noqa: F401  (parameterizations of the fit)
