@@ -237,6 +237,43 @@ int gst_predict(gst_ctx* ctx, const gst_gateset* theta, int n_prep, const int64_
 int gst_tv_distance(gst_ctx* ctx, const double* p, const double* q, int64_t n, int m, double* out);
 
 /*
+ * Parameterizations of the gate set: the estimation modes of the fit (thesis
+ * Sec. 6.3.2: fully unconstrained, trace-preserving, completely positive and
+ * trace-preserving).  A parameter vector theta (device, doubles) maps to the full
+ * parameterization (rho [D], effects [M][D], gates [K][D][D], the layout of
+ * gst_gateset), and the gradient with respect to the full parameters
+ * ([rho | effects | gates], the layout of gst_loglik's grad) maps back to theta.
+ *
+ *   GST_PARAM_FULL: theta is the full parameter vector itself.
+ *   GST_PARAM_TP:   row 0 of every gate is e_0 (trace preservation), rho[0] = 1/sqrt(d)
+ *                   (unit trace), effect M-1 = vec(1) - sum of the others (complete).
+ *                   theta = [rho[1..D-1] | effects 0..M-2 | rows 1..D-1 of each gate].
+ *   GST_PARAM_CPTP: G_k = exp(L_k) targets_k (Eq. GateDecompositionLindbladCorrespondence),
+ *                   L_k the transfer matrix of -i[H, .] + sum_jk C_jk (P_j . P_k - {P_k P_j, .}/2),
+ *                   H = sum_{k>=1} h_k P_k / 2 (Eq. GateDecompositionHamiltonian), C = T T^dagger
+ *                   (Eq. masterequation's form with a positive semidefinite coefficient
+ *                   matrix, so every gate is CPTP); rho = A A^dagger / tr(A A^dagger); effects as TP.
+ *                   theta = [A (D) | effects 0..M-2 | per gate: h (D-1), T ((D-1)^2)], A and T
+ *                   as their real diagonals followed by the entries below the diagonal in
+ *                   row-major order as (real, imaginary) pairs; P_j in the order of the basis.
+ *                   One and two qubits; `targets` = the fixed gates G0 [K][D][D] (device).
+ *
+ * gst_param_count: the length of theta.  gst_param_forward writes rho, effects
+ * and gates (device); gst_param_backward writes grad_theta (device, the length of
+ * theta) from grad_full.  Stream-ordered; TP maps are exact (bit-identical
+ * copies and differences), CPTP gates use a degree-16 Taylor polynomial with
+ * scaling and squaring (and its block form for the adjoint of the derivative).
+ * GST_EINVAL for an unknown mode, sizes out of range, CPTP with three qubits or
+ * without targets, NULL pointers.
+ */
+enum { GST_PARAM_FULL = 0, GST_PARAM_TP = 1, GST_PARAM_CPTP = 2 };
+int gst_param_count(int mode, int n_qubits, int n_outcomes, int n_gates, int64_t* count);
+int gst_param_forward(gst_ctx* ctx, int mode, int n_qubits, int n_outcomes, int n_gates, const double* theta,
+                      const double* targets, double* rho, double* effects, double* gates);
+int gst_param_backward(gst_ctx* ctx, int mode, int n_qubits, int n_outcomes, int n_gates, const double* theta,
+                       const double* targets, const double* grad_full, double* grad_theta);
+
+/*
  * Kernel timing (diagnostics).  While enabled, every kernel the context
  * enqueues is launched with a pair of HIP events on the context's stream that
  * the runtime stamps with the kernel's own start and end (no marker is queued
@@ -246,7 +283,7 @@ int gst_tv_distance(gst_ctx* ctx, const double* p, const double* q, int64_t n, i
  * `kernel` ("leaf", "reduce", "trunk_fwd", "trunk_bwd", "inject",
  * "grad_gemm", "fill", "tiles_2q", "tiles_1q", "tiles_reduce",
  * "chain_3q", "gemm_3q", "reduce_3q", "predict_chain", "predict_fill",
- * "tv_distance", or "batch" for a whole
+ * "tv_distance", "param_fwd", "param_bwd", or "batch" for a whole
  * gst_batch_run), the summed
  * elapsed milliseconds and the number of kernels since profiling was
  * enabled; the counters are not reset by reading.

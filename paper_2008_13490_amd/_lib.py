@@ -23,8 +23,9 @@ EXPORTED = [
     "gst_max_gates", "gst_create", "gst_destroy", "gst_sync", "gst_probs", "gst_loglik", "gst_vjp",
     "gst_req_create_host", "gst_req_footprint", "gst_req_eval", "gst_req_probs", "gst_req_vjp",
     "gst_req_destroy", "gst_req_plan_info", "gst_batch_create", "gst_batch_run", "gst_batch_nonpos",
-    "gst_batch_destroy", "gst_tune_set", "gst_set_plan_jump", "gst_predict", "gst_tv_distance", "gst_profile_enable", "gst_profile_only", "gst_profile_read",
-    "gst_last_error",
+    "gst_batch_destroy", "gst_tune_set", "gst_set_plan_jump", "gst_predict", "gst_tv_distance",
+    "gst_param_count", "gst_param_forward", "gst_param_backward", "gst_profile_enable", "gst_profile_only",
+    "gst_profile_read", "gst_last_error",
 ]
 
 
@@ -89,6 +90,11 @@ def load():
         lib.gst_predict.restype = I
         lib.gst_tv_distance.argtypes = [P, P, P, I64, I, P]
         lib.gst_tv_distance.restype = I
+        lib.gst_param_count.argtypes = [I, I, I, I, ctypes.POINTER(I64)]
+        lib.gst_param_forward.argtypes = [P, I, I, I, I, P, P, P, P, P]
+        lib.gst_param_backward.argtypes = [P, I, I, I, I, P, P, P, P]
+        for name in ("gst_param_count", "gst_param_forward", "gst_param_backward"):
+            getattr(lib, name).restype = I
         lib.gst_profile_read.restype = I
         if hasattr(lib, "gst_req_create_host"):
             lib.gst_req_create_host.argtypes = [P, I, I, I, ctypes.POINTER(GstSeqlist), P, ctypes.POINTER(P)]

@@ -327,6 +327,59 @@ def tv_distance(ctx: Context, p: torch.Tensor, q: torch.Tensor,
     return out
 
 
+class Parameterization:
+    """Estimation mode of a fit (``gst_param_*``): ``"full"``, ``"tp"`` or
+    ``"cptp"``.  ``forward(theta)`` gives the gate set of a parameter vector;
+    ``backward(theta, grad_full)`` the gradient with respect to theta from the
+    gradient with respect to the full parameters ([rho | effects | gates]).
+    ``targets`` (CPTP): the fixed gates G0, a float64 device tensor [K, D, D]."""
+
+    MODES = {"full": 0, "tp": 1, "cptp": 2}
+
+    def __init__(self, ctx: Context, mode: str, n_qubits: int, n_outcomes: int, n_gates: int,
+                 targets: Optional[torch.Tensor] = None):
+        self.ctx, self.mode = ctx, self.MODES[mode]
+        self.n_qubits, self.M, self.K = n_qubits, n_outcomes, n_gates
+        self.D = 4 ** n_qubits
+        cnt = ctypes.c_int64(0)
+        _lib.check(ctx.lib.gst_param_count(self.mode, n_qubits, n_outcomes, n_gates, ctypes.byref(cnt)))
+        self.count = int(cnt.value)
+        self.targets = None if targets is None else _require_cuda(targets, torch.float64, "targets")
+        if self.targets is not None and tuple(self.targets.shape) != (n_gates, self.D, self.D):
+            raise ValueError("targets must be [K, D, D]")
+
+    def _theta(self, theta: torch.Tensor) -> torch.Tensor:
+        theta = _require_cuda(theta, torch.float64, "theta")
+        if tuple(theta.shape) != (self.count,):
+            raise ValueError(f"theta must have {self.count} entries")
+        return theta
+
+    def forward(self, theta: torch.Tensor, out: Optional["DeviceGateSet"] = None) -> "DeviceGateSet":
+        theta = self._theta(theta)
+        if out is None:
+            dev = theta.device
+            out = DeviceGateSet(self.n_qubits, torch.empty(self.D, dtype=torch.float64, device=dev),
+                                torch.empty((self.M, self.D), dtype=torch.float64, device=dev),
+                                torch.empty((self.K, self.D, self.D), dtype=torch.float64, device=dev))
+        for t in (out.rho, out.effects, out.gates):
+            if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+                raise ValueError("out tensors must be contiguous float64 device tensors")
+        _lib.check(self.ctx.lib.gst_param_forward(self.ctx.handle, self.mode, self.n_qubits, self.M, self.K,
+                                                  _ptr(theta), _ptr(self.targets), _ptr(out.rho),
+                                                  _ptr(out.effects), _ptr(out.gates)))
+        return out
+
+    def backward(self, theta: torch.Tensor, grad_full: torch.Tensor,
+                 out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        theta = self._theta(theta)
+        grad_full = _require_cuda(grad_full, torch.float64, "grad_full")
+        if out is None:
+            out = torch.empty(self.count, dtype=torch.float64, device=theta.device)
+        _lib.check(self.ctx.lib.gst_param_backward(self.ctx.handle, self.mode, self.n_qubits, self.M, self.K,
+                                                   _ptr(theta), _ptr(self.targets), _ptr(grad_full), _ptr(out)))
+        return out
+
+
 def set_plan_jump(ctx: Context, reps: int):
     """Germ-power jump repetitions of the sharing plans of requests created
     afterwards on ``ctx`` (``gst_set_plan_jump``; 0 = off, bit-identical

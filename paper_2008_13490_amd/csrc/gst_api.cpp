@@ -134,12 +134,12 @@ struct Profiler {
 enum Family { FAM_LEAF = 0, FAM_REDUCE = 1, FAM_TRUNK_FWD = 2, FAM_TRUNK_BWD = 3, FAM_INJECT = 4, FAM_GEMM = 5,
               FAM_BATCH = 6, FAM_TILES16 = 7, FAM_TILES4 = 8, FAM_TILES_RED = 9, FAM_CHAIN64 = 10,
               FAM_GEMM64 = 11, FAM_REDUCE64 = 12, FAM_FILL = 13, FAM_PRED_CHAIN = 14,
-              FAM_PRED_FILL = 15, FAM_TV = 16, FAM_N = 17 };
+              FAM_PRED_FILL = 15, FAM_TV = 16, FAM_PARAM_FWD = 17, FAM_PARAM_BWD = 18, FAM_N = 19 };
 static_assert(FAM_N <= Profiler::kMaxFamilies, "profiler arrays too small");
 static const char* kFamilyNames[FAM_N] = {"leaf",  "reduce",  "trunk_fwd", "trunk_bwd",   "inject",
                                           "grad_gemm", "batch", "tiles_2q",  "tiles_1q", "tiles_reduce",
                                           "chain_3q",  "gemm_3q", "reduce_3q", "fill", "predict_chain",
-                                          "predict_fill", "tv_distance"};
+                                          "predict_fill", "tv_distance", "param_fwd", "param_bwd"};
 
 // Carve consecutive aligned regions out of one allocation.
 struct Carver {
@@ -163,6 +163,7 @@ struct gst_ctx {
   unsigned long long* status = nullptr;  // device [2]
   DevBuf ws;
   HostStage stage;
+  DevBuf param_tab[3];  // generator structure tables by qubit count (1, 2), uploaded on first use
   Profiler prof;
 };
 
@@ -869,6 +870,118 @@ int gst_tv_distance(gst_ctx* ctx, const double* p, const double* q, int64_t n, i
   HIP_TRY(hipSetDevice(ctx->device));
   ProfScope ps(ctx, FAM_TV);
   HIP_TRY(gst::launch_tv_distance(p, q, n, m, out, ctx->stream));
+  return GST_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Parameterizations (estimation modes)
+// ---------------------------------------------------------------------------
+static int64_t param_count_of(int mode, int D, int M, int K) {
+  if (mode == GST_PARAM_FULL) return D + (int64_t)M * D + (int64_t)K * D * D;
+  return (mode == GST_PARAM_TP ? D - 1 : D) + (int64_t)(M - 1) * D + (int64_t)K * D * (D - 1);
+}
+
+static int check_param_args(int mode, int n_qubits, int n_outcomes, int n_gates, int* D) {
+  if (mode != GST_PARAM_FULL && mode != GST_PARAM_TP && mode != GST_PARAM_CPTP)
+    return fail(GST_EINVAL, "mode must be GST_PARAM_FULL, GST_PARAM_TP or GST_PARAM_CPTP");
+  const int d = dim_of(n_qubits);
+  if (!d) return fail(GST_EINVAL, "n_qubits must be 1, 2 or 3");
+  if (mode == GST_PARAM_CPTP && n_qubits > 2) return fail(GST_EINVAL, "the CPTP parameterization takes one or two qubits");
+  if (n_gates < 1 || n_gates > gst_max_gates(n_qubits))
+    return fail(GST_EINVAL, "n_gates out of range for this qubit count (see gst_max_gates)");
+  if (n_outcomes < 1 || n_outcomes > std::min(d, 16)) return fail(GST_EINVAL, "n_outcomes must be in 1..min(D, 16)");
+  *D = d;
+  return GST_OK;
+}
+
+int gst_param_count(int mode, int n_qubits, int n_outcomes, int n_gates, int64_t* count) {
+  int D = 0;
+  int rc = check_param_args(mode, n_qubits, n_outcomes, n_gates, &D);
+  if (rc) return rc;
+  if (!count) return fail(GST_EINVAL, "count is NULL");
+  *count = param_count_of(mode, D, n_outcomes, n_gates);
+  return GST_OK;
+}
+
+static int param_launch(gst_ctx* ctx, int mode, int n_qubits, int n_outcomes, int n_gates, const double* theta,
+                        const double* targets, gst::ParamLaunch* a) {
+  int D = 0;
+  int rc = check_param_args(mode, n_qubits, n_outcomes, n_gates, &D);
+  if (rc) return rc;
+  if (!theta) return fail(GST_EINVAL, "theta is NULL");
+  if (mode == GST_PARAM_CPTP && !targets) return fail(GST_EINVAL, "the CPTP parameterization needs the target gates");
+  HIP_TRY(hipSetDevice(ctx->device));
+  *a = gst::ParamLaunch{};
+  a->mode = mode;
+  a->n = n_qubits;
+  a->D = D;
+  a->d = 1 << n_qubits;
+  a->M = n_outcomes;
+  a->K = n_gates;
+  a->sqrt_d = std::sqrt((double)a->d);
+  a->inv_sqrt_d = 1.0 / std::sqrt((double)a->d);
+  a->theta = theta;
+  a->targets = targets;
+  if (mode == GST_PARAM_CPTP) {
+    DevBuf& tab = ctx->param_tab[n_qubits];
+    const size_t nd = (size_t)D * D + 2 * (size_t)D * D * D;
+    if (!tab.p) {
+      std::vector<double> y, zr, zi;
+      gst::param_tables(n_qubits, &y, &zr, &zi);
+      std::vector<double> all(y);
+      all.insert(all.end(), zr.begin(), zr.end());
+      all.insert(all.end(), zi.begin(), zi.end());
+      if ((rc = tab.reserve(nd * sizeof(double), ctx->stream))) return rc;
+      HIP_TRY(hipMemcpyAsync(tab.p, all.data(), nd * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+      HIP_TRY(hipStreamSynchronize(ctx->stream));  // `all` is freed on return
+    }
+    const double* t = reinterpret_cast<const double*>(tab.p);
+    a->ty = t;
+    a->tzr = t + (size_t)D * D;
+    a->tzi = a->tzr + (size_t)D * D * D;
+  }
+  return GST_OK;
+}
+
+int gst_param_forward(gst_ctx* ctx, int mode, int n_qubits, int n_outcomes, int n_gates, const double* theta,
+                      const double* targets, double* rho, double* effects, double* gates) {
+  if (!ctx) return fail(GST_EINVAL, "ctx is NULL");
+  gst::ParamLaunch a;
+  int rc = param_launch(ctx, mode, n_qubits, n_outcomes, n_gates, theta, targets, &a);
+  if (rc) return rc;
+  if (!rho || !effects || !gates) return fail(GST_EINVAL, "output pointer is NULL");
+  if (mode == GST_PARAM_FULL) {
+    const int D = a.D, M = a.M, K = a.K;
+    HIP_TRY(hipMemcpyAsync(rho, theta, (size_t)D * 8, hipMemcpyDeviceToDevice, ctx->stream));
+    HIP_TRY(hipMemcpyAsync(effects, theta + D, (size_t)M * D * 8, hipMemcpyDeviceToDevice, ctx->stream));
+    HIP_TRY(hipMemcpyAsync(gates, theta + D + (size_t)M * D, (size_t)K * D * D * 8, hipMemcpyDeviceToDevice,
+                           ctx->stream));
+    return GST_OK;
+  }
+  a.rho = rho;
+  a.E = effects;
+  a.G = gates;
+  ProfScope ps(ctx, FAM_PARAM_FWD);
+  HIP_TRY(gst::launch_param_forward(a, ctx->stream));
+  return GST_OK;
+}
+
+int gst_param_backward(gst_ctx* ctx, int mode, int n_qubits, int n_outcomes, int n_gates, const double* theta,
+                       const double* targets, const double* grad_full, double* grad_theta) {
+  if (!ctx) return fail(GST_EINVAL, "ctx is NULL");
+  gst::ParamLaunch a;
+  int rc = param_launch(ctx, mode, n_qubits, n_outcomes, n_gates, theta, targets, &a);
+  if (rc) return rc;
+  if (!grad_full || !grad_theta) return fail(GST_EINVAL, "gradient pointer is NULL");
+  if (mode == GST_PARAM_FULL) {
+    HIP_TRY(hipMemcpyAsync(grad_theta, grad_full, (size_t)param_count_of(mode, a.D, a.M, a.K) * 8,
+                           hipMemcpyDeviceToDevice, ctx->stream));
+    return GST_OK;
+  }
+  a.grad_full = grad_full;
+  a.grad_theta = grad_theta;
+  ProfScope ps(ctx, FAM_PARAM_BWD);
+  HIP_TRY(gst::launch_param_backward(a, ctx->stream));
   return GST_OK;
 }
 

@@ -2,6 +2,10 @@
 #pragma once
 #include <stdint.h>
 #include <hip/hip_ext.h>
+
+#include <vector>
+
+#include "gst_param_tables.h"
 #include <hip/hip_runtime.h>
 
 namespace gst {
@@ -292,6 +296,26 @@ struct PredictLaunch {
 hipError_t launch_predict_chain(const PredictLaunch& a, hipStream_t stream);
 hipError_t launch_predict_fill(const PredictLaunch& a, hipStream_t stream);
 hipError_t launch_tv_distance(const double* p, const double* q, int64_t n, int M, double* out, hipStream_t stream);
+
+// Parameterizations of the gate set (TP and CPTP estimation modes).  theta and
+// grad_theta in the layout of gst.h; grad_full = [rho | effects | gates].
+struct ParamLaunch {
+  int mode;          // 1 = TP, 2 = CPTP
+  int n, D, d, M, K;
+  double sqrt_d, inv_sqrt_d;
+  const double* theta;
+  const double* targets;    // CPTP: G0 [K][D][D]
+  const double* grad_full;  // backward
+  double* rho;              // forward outputs
+  double* E;
+  double* G;
+  double* grad_theta;       // backward output
+  const double* ty;         // CPTP structure tables of the generator (D <= 16):
+  const double* tzr;        //   y [D][D], z [D][D][D] (real and imaginary parts)
+  const double* tzi;
+};
+hipError_t launch_param_forward(const ParamLaunch& a, hipStream_t stream);
+hipError_t launch_param_backward(const ParamLaunch& a, hipStream_t stream);
 
 // reverse fill tasks (adjoints inside the jumps into BA)
 hipError_t launch_fill_rev(const PlanArgs& a, hipStream_t stream);
