@@ -85,7 +85,7 @@ def _cpu_sample(name):
 
 
 def _cpu_worker(args):
-    name, seconds = args
+    name, seconds, param = args
     sys.path.insert(0, ROOT)
     import oracle
     n = 0
@@ -105,6 +105,22 @@ def _cpu_worker(args):
                 break
         return n, time.perf_counter() - t0, seqs
     sample, _ = _cpu_sample(name)
+    if param != "full":
+        from oracle import params as PR
+        from paper_2008_13490_amd import workloads as W
+        m, sl, cnt = sample[0]
+        kind = {1: "1q", 2: "2q"}[m.n_qubits]
+        G0 = W.ideal_targets(kind)
+        th = W.param_point(param, m, 7)
+        while True:
+            rho, E, G = PR.forward(param, th, m.n_qubits, m.M, m.K, G0)
+            _, _, g, _, _ = oracle.loglik(rho, E, G, sl.offsets, sl.gates, cnt)
+            PR.backward(param, th, m.n_qubits, m.M, m.K, g, G0)
+            seqs += sl.S
+            n += 1
+            if time.perf_counter() - t0 >= seconds:
+                break
+        return n, time.perf_counter() - t0, seqs
     while True:
         for m, sl, cnt in sample:
             oracle.loglik(m.rho, m.effects, m.gates, sl.offsets, sl.gates, cnt)
@@ -115,7 +131,7 @@ def _cpu_worker(args):
     return n, time.perf_counter() - t0, seqs
 
 
-def cpu_baseline(name: str, seconds: float, workers: int):
+def cpu_baseline(name: str, seconds: float, workers: int, param: str = "full"):
     import multiprocessing as mp
     import oracle
     oracle.build(force=not os.path.exists(oracle.library_path()))
@@ -125,10 +141,24 @@ def cpu_baseline(name: str, seconds: float, workers: int):
     else:
         _, what = _cpu_sample(name)
     ctx = mp.get_context("spawn")
+    # one thread per worker process: the parameterization oracle uses numpy /
+    # scipy, whose BLAS would otherwise start a thread pool in every worker
+    saved = {k: os.environ.get(k) for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS")}
+    for k in saved:
+        os.environ[k] = "1"
+    print(f"[bench] cpu baseline: {workers} oracle processes for ~{seconds:.0f} s", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
-    with ctx.Pool(workers) as pool:
-        res = pool.map(_cpu_worker, [(name, seconds)] * workers)
+    try:
+        with ctx.Pool(workers) as pool:
+            res = pool.map(_cpu_worker, [(name, seconds, param)] * workers)
+    finally:
+        for k, v in saved.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
     wall = time.perf_counter() - t0
+    print(f"[bench] cpu baseline done in {wall:.1f} s", file=sys.stderr, flush=True)
     passes = sum(r[0] for r in res)
     seqs = sum(r[2] for r in res)
     busy = max(r[1] for r in res)
@@ -137,7 +167,8 @@ def cpu_baseline(name: str, seconds: float, workers: int):
         "unit": "predicted distributions/s" if name == "f3" else "sequence evals/s",
         "cores": workers,
         "kind": "oracle",
-        "sample": f"{what} evaluated {passes} times{'' if name == 'f3' else ' with gradient'}, "
+        "sample": f"{what} evaluated {passes} times{'' if name == 'f3' else ' with gradient'}"
+                  f"{'' if param == 'full' else f' in the {param.upper()} parameterization'}, "
                   f"{workers} single-threaded processes for ~{seconds:.0f} s each (wall {wall:.1f} s)",
     }
 
@@ -186,6 +217,8 @@ def main():
     ap.add_argument("--round-work", type=float, default=8e6,
                     help="serving: bound on the work of one round, in two-qubit sequence steps")
     ap.add_argument("--path", choices=["resident", "plain"], default="resident")
+    ap.add_argument("--param", choices=["full", "tp", "cptp"], default="full",
+                    help="c1/c2: estimation mode; the step maps theta to the gate set and the gradient back")
     ap.add_argument("--sets", type=int, default=0, help="c3: use only the first N gate sets")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--cpu-workers", type=int, default=0)
@@ -207,7 +240,7 @@ def main():
     cpu = None
     if not args.no_cpu:
         workers = args.cpu_workers or max(1, min(16, os.cpu_count() or 1))
-        cpu = cpu_baseline(args.workload, args.cpu_seconds, workers)
+        cpu = cpu_baseline(args.workload, args.cpu_seconds, workers, args.param)
     if args.workload == "c3":
         out = run_uneven(args)
     elif args.workload == "c5":
@@ -330,7 +363,21 @@ def run_structured(args):
     dev = torch.device("cuda", 0)
     obj = torch.empty(1, dtype=torch.float64, device=dev)
     grad = torch.empty(m.n_params(), dtype=torch.float64, device=dev)
-    if args.path == "resident":
+    if args.param != "full":
+        if args.path != "resident" or m.n_qubits > 2:
+            raise SystemExit("--param tp/cptp: resident path, one or two qubits")
+        kind = {1: "1q", 2: "2q"}[m.n_qubits]
+        par = api.Parameterization(ctx, args.param, m.n_qubits, m.M, m.K,
+                                   torch.as_tensor(W.ideal_targets(kind), device=dev))
+        theta = torch.as_tensor(W.param_point(args.param, m, 7), device=dev)
+        gtheta = torch.empty(par.count, dtype=torch.float64, device=dev)
+        req = api.Request(ctx, m.n_qubits, m.K, m.M, w.seqs.offsets, w.seqs.gates, w.counts)
+
+        def step():
+            par.forward(theta, out=gs)
+            req.eval(gs, want_probs=False, want_grad=True, out=(obj, None, grad))
+            par.backward(theta, grad, out=gtheta)
+    elif args.path == "resident":
         req = api.Request(ctx, m.n_qubits, m.K, m.M, w.seqs.offsets, w.seqs.gates, w.counts)
 
         def step():
@@ -346,7 +393,7 @@ def run_structured(args):
                                               api._ptr(obj), api._ptr(grad)))
 
     families = ("leaf", "reduce", "trunk_fwd", "trunk_bwd", "inject", "grad_gemm", "fill", "tiles_2q", "tiles_1q",
-                "tiles_reduce", "chain_3q", "gemm_3q", "reduce_3q")
+                "tiles_reduce", "chain_3q", "gemm_3q", "reduce_3q", "param_fwd", "param_bwd")
     for _ in range(args.warmup):
         step()
     ctx.sync()
@@ -379,7 +426,8 @@ def run_structured(args):
     D, M = m.D, m.M
     L = w.seqs.lengths()
     info = req_plan_info(req) if args.path == "resident" else None
-    flops = algorithmic_flops(dom, D, M, S, int(L.sum()), info)
+    flops = (param_flops(dom, D, m.K) if dom.startswith("param_")
+             else algorithmic_flops(dom, D, M, S, int(L.sum()), info))
     steps_eval = (info["trunk_steps"] + info["item_steps"]) if info else int(L.sum())
     return {
         "metric": METRIC,
@@ -394,7 +442,7 @@ def run_structured(args):
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": dict(desc, path=args.path),
+        "config": dict(desc, path=args.path, param=args.param),
         "roofline": _roofline(dom, fams, flops,
                               read_traffic(args.workload, dom) if args.path == "resident" else None),
         "kernels_ms_per_step": {f: brk[f][0] / n_break for f in brk},
@@ -585,6 +633,22 @@ def predict_flops(family, D, M, prep_lens, n_gates, r_max, B=32):
         return pairs * (2.0 * D * D * (r_max + 1 - Q) + 2.0 * D * M * (r_max + 1))
     if family == "tv_distance":
         return pairs * (r_max + 1) * 3.0 * M
+    return 0.0
+
+
+def param_flops(family, D, K, taylor=16):
+    """FP64 flops of one launch of a CPTP parameterization kernel (without the
+    squarings, whose number depends on the generator's norm): per gate the
+    generator from the structure tables (2 (D-1) complex terms per entry), the
+    Taylor polynomial by Horner (one D x D product per degree) and the product
+    with the target; backward: the block polynomial (three products per degree)
+    and the contractions back to the parameters."""
+    mm = 2.0 * D ** 3
+    gen = 8.0 * D * D * (D - 1)
+    if family == "param_fwd":
+        return K * (gen + (taylor + 1) * mm)
+    if family == "param_bwd":
+        return K * (2 * gen + 3 * taylor * mm + mm)
     return 0.0
 
 

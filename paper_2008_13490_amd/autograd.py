@@ -6,6 +6,10 @@
 ``gst_probs(rho, E, G, target)`` outcome probabilities [S, M]; its backward is
                                  the library's vector-Jacobian product with the
                                  upstream weights dLoss/dp.
+``gst_gateset(theta, param)``    (rho, E, G) of a parameter vector of an
+                                 estimation mode (``api.Parameterization``: full,
+                                 TP or CPTP); its backward is the library's chain
+                                 rule ``gst_param_backward``.
 
 ``target`` is an ``api.Request`` (resident sequences and counts) or a tuple
 ``(api.Context, api.DeviceSeqs, counts or None)``.  Every number is computed
@@ -83,3 +87,29 @@ def gst_nll(rho, E, G, target):
 
 def gst_probs(rho, E, G, target):
     return _Probs.apply(rho, E, G, target)
+
+
+class _GateSet(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, theta, param):
+        th = theta.detach().contiguous()
+        gs = param.forward(th)
+        ctx.save_for_backward(th)
+        ctx.param = param
+        return gs.rho, gs.effects, gs.gates
+
+    @staticmethod
+    def backward(ctx, grho, gE, gG):
+        (th,) = ctx.saved_tensors
+        par = ctx.param
+        D, M, K = par.D, par.M, par.K
+        parts = []
+        for g, shape in ((grho, (D,)), (gE, (M, D)), (gG, (K, D, D))):
+            if g is None:
+                g = torch.zeros(shape, dtype=torch.float64, device=th.device)
+            parts.append(g.detach().to(torch.float64).reshape(-1))
+        return par.backward(th, torch.cat(parts).contiguous()), None
+
+
+def gst_gateset(theta, param):
+    return _GateSet.apply(theta, param)

@@ -311,7 +311,7 @@ struct ParamLaunch {
   double* G;
   double* grad_theta;       // backward output
   const double* ty;         // CPTP structure tables of the generator (D <= 16):
-  const double* tzr;        //   y [D][D], z [D][D][D] (real and imaginary parts)
+  const double* tzr;        //   y [D][D], z [D (j)][D][D] (real and imaginary parts)
   const double* tzi;
 };
 hipError_t launch_param_forward(const ParamLaunch& a, hipStream_t stream);

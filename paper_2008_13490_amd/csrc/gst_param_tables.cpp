@@ -6,7 +6,7 @@
 //     has entries h_{a^b} y[a][b] (P_k P_b is a multiple of P_a only for k = a^b);
 //   * the map sum_jk C_jk (P_j . P_k - {P_k P_j, .} / 2) (the dissipator of Eq.
 //     masterequation with coefficient matrix C) has entries
-//     sum_j Re(C_{j, a^b^j} z[a][b][j]).
+//     sum_j Re(C_{j, a^b^j} z[j][a][b]) (zero where a^b^j = 0).
 // Pauli labels multiply by XOR of their per-qubit codes (I, X, Y, Z = 0..3);
 // the phases follow from sigma_x sigma_y = i sigma_z and its cyclic versions.
 #include "gst_param_tables.h"
@@ -61,8 +61,8 @@ void param_tables(int n, std::vector<double>* y, std::vector<double>* zr, std::v
         // (tr(P_a P_j P_b P_k) - tr(P_a P_k P_j P_b) / 2 - tr(P_a P_b P_k P_j) / 2) / d
         const cplx v = phase_of({a, j, b, kk}, n) - 0.5 * phase_of({a, kk, j, b}, n) -
                        0.5 * phase_of({a, b, kk, j}, n);
-        (*zr)[((size_t)a * D + b) * D + j] = v.real();
-        (*zi)[((size_t)a * D + b) * D + j] = v.imag();
+        (*zr)[((size_t)j * D + a) * D + b] = v.real();
+        (*zi)[((size_t)j * D + a) * D + b] = v.imag();
       }
     }
 }

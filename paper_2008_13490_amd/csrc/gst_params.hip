@@ -21,7 +21,7 @@
 // block of exp([[L^T, X], [0, L^T]]) with X = dF/dG G0^T, computed by the same
 // scheme on block upper-triangular matrices.  From dF/dL the parameters'
 // gradient follows by the structure tables (h) and by C = T T^dagger:
-// dF/dT = (conj(Chat) + Chat^T) T with Chat_jk = sum_ab dF/dL_ab z_ab(j).
+// dF/dT = (conj(Chat) + Chat^T) T with Chat_jk = sum_ab dF/dL_ab z_j(a, b).
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -112,32 +112,41 @@ __device__ inline void pauli_entry(int i, int r, int c, int n, double* re, doubl
   *im = pi;
 }
 
-// lower-triangular complex d x d matrix A of the state parameters
-__device__ inline void load_cholesky(const double* x, int d, double (*Ar)[4], double (*Ai)[4]) {
-  for (int j = 0; j < 4; ++j)
-    for (int k = 0; k < 4; ++k) {
+// lower-triangular complex d x d matrix A of the state parameters (d fixed at
+// compile time, loops unrolled: the small matrices stay in registers)
+template <int d>
+__device__ inline void load_cholesky(const double* x, double (&Ar)[d][d], double (&Ai)[d][d]) {
+#pragma unroll
+  for (int j = 0; j < d; ++j)
+#pragma unroll
+    for (int k = 0; k < d; ++k) {
       Ar[j][k] = 0.0;
       Ai[j][k] = 0.0;
     }
-  int p = d;
+#pragma unroll
   for (int j = 0; j < d; ++j) {
     Ar[j][j] = x[j];
+#pragma unroll
     for (int k = 0; k < j; ++k) {
+      const int p = d + 2 * (j * (j - 1) / 2 + k);
       Ar[j][k] = x[p];
       Ai[j][k] = x[p + 1];
-      p += 2;
     }
   }
 }
 
 // rho = A A^dagger / t, t = tr(A A^dagger)
-__device__ inline void cholesky_state(const double* x, int d, double (*Ar)[4], double (*Ai)[4], double (*Rr)[4],
-                                      double (*Ri)[4], double* t) {
-  load_cholesky(x, d, Ar, Ai);
+template <int d>
+__device__ inline void cholesky_state(const double* x, double (&Ar)[d][d], double (&Ai)[d][d], double (&Rr)[d][d],
+                                      double (&Ri)[d][d], double* t) {
+  load_cholesky<d>(x, Ar, Ai);
   double tr = 0.0;
+#pragma unroll
   for (int r = 0; r < d; ++r)
+#pragma unroll
     for (int c = 0; c < d; ++c) {
       double sr = 0.0, si = 0.0;
+#pragma unroll
       for (int l = 0; l < d; ++l) {  // A_rl conj(A_cl)
         sr = fma(Ar[r][l], Ar[c][l], sr);
         sr = fma(Ai[r][l], Ai[c][l], sr);
@@ -148,12 +157,116 @@ __device__ inline void cholesky_state(const double* x, int d, double (*Ar)[4], d
       Ri[r][c] = si;
       if (r == c) tr += sr;
     }
+#pragma unroll
   for (int r = 0; r < d; ++r)
+#pragma unroll
     for (int c = 0; c < d; ++c) {
       Rr[r][c] /= tr;
       Ri[r][c] /= tr;
     }
   *t = tr;
+}
+
+// state coordinates v_i = Re tr(P_i rho) / sqrt(d) and the effects (TP form)
+template <int D, int d>
+__device__ void spam_forward(const ParamLaunch& a) {
+  const int tid = threadIdx.x, M = a.M;
+  const double* eth = a.theta + D;
+  if (tid < D) {
+    double Ar[d][d], Ai[d][d], Rr[d][d], Ri[d][d], t;
+    cholesky_state<d>(a.theta, Ar, Ai, Rr, Ri, &t);
+    double acc = 0.0;
+#pragma unroll
+    for (int r = 0; r < d; ++r)
+#pragma unroll
+      for (int c = 0; c < d; ++c) {
+        double pr, pi;
+        pauli_entry(tid, r, c, d == 2 ? 1 : 2, &pr, &pi);
+        acc = fma(pr, Rr[c][r], acc);
+        acc = fma(-pi, Ri[c][r], acc);
+      }
+    a.rho[tid] = acc * a.inv_sqrt_d;
+  }
+  for (int x = tid; x < M * D; x += blockDim.x) {
+    const int mm = x / D, c = x % D;
+    double v;
+    if (mm < M - 1) {
+      v = eth[x];
+    } else {
+      v = c == 0 ? a.sqrt_d : 0.0;
+      for (int q = 0; q < M - 1; ++q) v = v - eth[q * D + c];
+    }
+    a.E[x] = v;
+  }
+}
+
+// Q = sum_i gr_i P_i / sqrt(d); Q' = (Q - tr(Q rho)) / t; dF/dA = 2 Q' A (entries
+// below the diagonal as real and imaginary parts); the effects' differences
+template <int D, int d>
+__device__ void spam_backward(const ParamLaunch& a) {
+  const int tid = threadIdx.x, M = a.M;
+  const double* gr = a.grad_full;
+  const double* ge = gr + D;
+  if (tid < D) {
+    double Ar[d][d], Ai[d][d], Rr[d][d], Ri[d][d], t;
+    cholesky_state<d>(a.theta, Ar, Ai, Rr, Ri, &t);
+    double g[D];
+#pragma unroll
+    for (int i = 0; i < D; ++i) g[i] = gr[i];
+    double Qr[d][d], Qi[d][d];
+#pragma unroll
+    for (int r = 0; r < d; ++r)
+#pragma unroll
+      for (int c = 0; c < d; ++c) {
+        double sr = 0.0, si = 0.0;
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+          double pr, pi;
+          pauli_entry(i, r, c, d == 2 ? 1 : 2, &pr, &pi);
+          sr = fma(g[i], pr, sr);
+          si = fma(g[i], pi, si);
+        }
+        Qr[r][c] = sr * a.inv_sqrt_d;
+        Qi[r][c] = si * a.inv_sqrt_d;
+      }
+    double q = 0.0;  // Re tr(Q rho)
+#pragma unroll
+    for (int r = 0; r < d; ++r)
+#pragma unroll
+      for (int c = 0; c < d; ++c) {
+        q = fma(Qr[r][c], Rr[c][r], q);
+        q = fma(-Qi[r][c], Ri[c][r], q);
+      }
+#pragma unroll
+    for (int r = 0; r < d; ++r) {
+      Qr[r][r] -= q;
+#pragma unroll
+      for (int c = 0; c < d; ++c) {
+        Qr[r][c] /= t;
+        Qi[r][c] /= t;
+      }
+    }
+    double out = 0.0;
+#pragma unroll
+    for (int j = 0; j < d; ++j)
+#pragma unroll
+      for (int l = 0; l <= j; ++l) {
+        double gre = 0.0, gim = 0.0;  // (Q' A)_jl
+#pragma unroll
+        for (int k = 0; k < d; ++k) {
+          gre = fma(Qr[j][k], Ar[k][l], gre);
+          gre = fma(-Qi[j][k], Ai[k][l], gre);
+          gim = fma(Qr[j][k], Ai[k][l], gim);
+          gim = fma(Qi[j][k], Ar[k][l], gim);
+        }
+        const int p = d + 2 * (j * (j - 1) / 2 + l);
+        if (l == j && tid == j) out = 2.0 * gre;
+        if (l < j && tid == p) out = 2.0 * gre;
+        if (l < j && tid == p + 1) out = 2.0 * gim;
+      }
+    a.grad_theta[tid] = out;
+  }
+  for (int x = tid; x < (M - 1) * D; x += blockDim.x) a.grad_theta[D + x] = ge[x] - ge[(M - 1) * D + x % D];
 }
 
 // LDS of a gate workgroup (doubles)
@@ -229,13 +342,21 @@ __device__ void build_generator(const ParamLaunch& a, const double* tg, const Ga
     double l = 0.0;
     if (r < D && c < D) {
       const int rc = r ^ c;
-      if (rc) l = s.hs[rc] * a.ty[r * D + c];
-      const double* zr = a.tzr + (size_t)(r * D + c) * D;
-      const double* zi = a.tzi + (size_t)(r * D + c) * D;
+      // all table loads in flight together (z by j, then entry: coalesced)
+      double zr[D], zi[D];
+#pragma unroll
+      for (int j = 1; j < D; ++j) {
+        zr[j] = a.tzr[(size_t)j * D * D + r * D + c];
+        zi[j] = a.tzi[(size_t)j * D * D + r * D + c];
+      }
+      const double y = a.ty[r * D + c];
+      if (rc) l = s.hs[rc] * y;
+      // the term j = r^c has a zero coefficient (k = 0): it adds exact zeros
+#pragma unroll
       for (int j = 1; j < D; ++j) {
         const int k = rc ^ j;
-        if (k == 0) continue;
-        const double cr = s.Cr[(j - 1) * 16 + (k - 1)], ci = s.Ci[(j - 1) * 16 + (k - 1)];
+        const int kk = k ? k - 1 : 0;
+        const double cr = s.Cr[(j - 1) * 16 + kk], ci = s.Ci[(j - 1) * 16 + kk];
         l = fma(cr, zr[j], l);
         l = fma(-ci, zi[j], l);
       }
@@ -290,39 +411,64 @@ __device__ inline int scaling_of(const double* L, int lane) {
   return __builtin_amdgcn_readfirstlane(s);
 }
 
-// X <- scale * src (entrywise; zero padding kept), one wave
-__device__ inline void scaled_copy(double* X, const double* src, double scale, int lane) {
-  for (int x = lane; x < 16 * ROW; x += 64) X[x] = src[x] * scale;
+// Operands of the 16x16x4 FP64 MFMA in registers.  The product's layout (lane l
+// holds C[4v + (l >> 4)][l & 15] in register v) is the layout of the right
+// operand B (step k reads B[4k + (l >> 4)][l & 15]), so a chain of left
+// multiplications P <- X P keeps P in registers; the left operand (lane l:
+// A[l & 15][4k + (l >> 4)]) is loaded from LDS once.
+struct Frag {
+  double v[4];
+};
+
+__device__ inline Frag load_left(const double* A, double scale, int lane) {
+  const int i = lane & 15, t = lane >> 4;
+  Frag f;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) f.v[k] = A[i * ROW + 4 * k + t] * scale;
+  return f;
 }
 
-// exp(L) (L in LDS, padded) into the returned buffer among W[0..1]; one wave.
-__device__ double* expm_wave(const GateLds& s, int lane) {
-  const int i = lane & 15, t = lane >> 4;
-  const int sc = scaling_of(s.L, lane);
-  double* X = s.W[2];
-  scaled_copy(X, s.L, ldexp(1.0, -sc), lane);
-  double* P = s.W[0];
-  double* Pn = s.W[1];
-  for (int x = lane; x < 16 * ROW; x += 64) P[x] = (x / ROW == x % ROW) ? 1.0 : 0.0;
-  wave_sync();
-  for (int k = TAYLOR; k >= 1; --k) {
-    const d4 q = mm_acc(X, P, d4{0.0, 0.0, 0.0, 0.0}, lane);
+__device__ inline d4 mfma_left(const Frag& A, const Frag& B, d4 acc) {
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int r = 4 * v + t;
-      Pn[r * ROW + i] = (r == i ? 1.0 : 0.0) + q[v] / (double)k;
-    }
-    wave_sync();
-    double* tmp = P;
-    P = Pn;
-    Pn = tmp;
+  for (int k = 0; k < 4; ++k) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(A.v[k], B.v[k], acc, 0, 0, 0);
+  return acc;
+}
+
+__device__ inline void store_frag(double* C, const Frag& f, int lane) {
+  const int i = lane & 15, t = lane >> 4;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) C[(4 * v + t) * ROW + i] = f.v[v];
+}
+
+__device__ inline Frag identity_frag(int lane) {
+  const int i = lane & 15, t = lane >> 4;
+  Frag f;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) f.v[v] = (4 * v + t == i) ? 1.0 : 0.0;
+  return f;
+}
+
+// exp(L) (L in LDS, padded) as a right-operand fragment; one wave.  Horner's
+// rule for the Taylor polynomial of X = L / 2^s runs in registers; the s
+// squarings go through the LDS buffer W (P is needed as a left operand there).
+__device__ Frag expm_wave(const double* L, double* W, int lane) {
+  const int i = lane & 15, t = lane >> 4;
+  const int sc = scaling_of(L, lane);
+  const Frag X = load_left(L, ldexp(1.0, -sc), lane);
+  Frag P = identity_frag(lane);
+  for (int k = TAYLOR; k >= 1; --k) {
+    const double rk = 1.0 / (double)k;  // uniform: off the chain of dependent products
+    const d4 q = mfma_left(X, P, d4{0.0, 0.0, 0.0, 0.0});
+#pragma unroll
+    for (int v = 0; v < 4; ++v) P.v[v] = fma(q[v], rk, 4 * v + t == i ? 1.0 : 0.0);
   }
   for (int e = 0; e < sc; ++e) {
-    store_acc(Pn, mm_acc(P, P, d4{0.0, 0.0, 0.0, 0.0}, lane), lane);
+    store_frag(W, P, lane);
     wave_sync();
-    double* tmp = P;
-    P = Pn;
-    Pn = tmp;
+    const d4 q = mfma_left(load_left(W, 1.0, lane), P, d4{0.0, 0.0, 0.0, 0.0});
+    wave_sync();  // W is rewritten by the next squaring
+#pragma unroll
+    for (int v = 0; v < 4; ++v) P.v[v] = q[v];
   }
   return P;
 }
@@ -331,34 +477,9 @@ template <int D>
 __global__ __launch_bounds__(256) void cptp_forward_kernel(const ParamLaunch a) {
   extern __shared__ double lds_raw[];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int M = a.M, d = a.d;
-  const double* eth = a.theta + D;
-  const double* gth = eth + (int64_t)(M - 1) * D;
+  const double* gth = a.theta + D + (int64_t)(a.M - 1) * D;
   if (blockIdx.x == a.K) {  // state and effects
-    if (tid < D) {
-      double Ar[4][4], Ai[4][4], Rr[4][4], Ri[4][4], t;
-      cholesky_state(a.theta, d, Ar, Ai, Rr, Ri, &t);
-      double acc = 0.0;  // Re tr(P_i rho)
-      for (int r = 0; r < d; ++r)
-        for (int c = 0; c < d; ++c) {
-          double pr, pi;
-          pauli_entry(tid, r, c, a.n, &pr, &pi);
-          acc = fma(pr, Rr[c][r], acc);
-          acc = fma(-pi, Ri[c][r], acc);
-        }
-      a.rho[tid] = acc * a.inv_sqrt_d;
-    }
-    for (int x = tid; x < M * D; x += blockDim.x) {
-      const int mm = x / D, c = x % D;
-      double v;
-      if (mm < M - 1) {
-        v = eth[x];
-      } else {
-        v = c == 0 ? a.sqrt_d : 0.0;
-        for (int q = 0; q < M - 1; ++q) v = v - eth[q * D + c];
-      }
-      a.E[x] = v;
-    }
+    spam_forward<D, D == 16 ? 4 : 2>(a);
     return;
   }
   const int g = blockIdx.x;
@@ -373,8 +494,10 @@ __global__ __launch_bounds__(256) void cptp_forward_kernel(const ParamLaunch a) 
   }
   __syncthreads();
   if (wave == 0) {
-    const double* Ex = expm_wave(s, lane);
-    const d4 acc = mm_acc(Ex, G0, d4{0.0, 0.0, 0.0, 0.0}, lane);
+    const Frag Ex = expm_wave(s.L, s.W[0], lane);
+    store_frag(s.W[1], Ex, lane);
+    wave_sync();
+    const d4 acc = mm_acc(s.W[1], G0, d4{0.0, 0.0, 0.0, 0.0}, lane);
     const int i = lane & 15, t = lane >> 4;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
@@ -388,63 +511,10 @@ template <int D>
 __global__ __launch_bounds__(256) void cptp_backward_kernel(const ParamLaunch a) {
   extern __shared__ double lds_raw[];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int M = a.M, d = a.d;
-  const double* gr = a.grad_full;
-  const double* ge = gr + D;
-  const double* gg = ge + (int64_t)M * D;
-  const int64_t e_off = D, g_off = D + (int64_t)(M - 1) * D;
-  if (blockIdx.x == a.K) {
-    if (tid < D) {
-      // Q = sum_i gr_i P_i / sqrt(d); Q' = (Q - tr(Q rho)) / t; Gamma = 2 Q' A
-      double Ar[4][4], Ai[4][4], Rr[4][4], Ri[4][4], t;
-      cholesky_state(a.theta, d, Ar, Ai, Rr, Ri, &t);
-      double Qr[4][4], Qi[4][4];
-      for (int r = 0; r < d; ++r)
-        for (int c = 0; c < d; ++c) {
-          double sr = 0.0, si = 0.0;
-          for (int i = 0; i < D; ++i) {
-            double pr, pi;
-            pauli_entry(i, r, c, a.n, &pr, &pi);
-            sr = fma(gr[i], pr, sr);
-            si = fma(gr[i], pi, si);
-          }
-          Qr[r][c] = sr * a.inv_sqrt_d;
-          Qi[r][c] = si * a.inv_sqrt_d;
-        }
-      double q = 0.0;  // Re tr(Q rho)
-      for (int r = 0; r < d; ++r)
-        for (int c = 0; c < d; ++c) {
-          q = fma(Qr[r][c], Rr[c][r], q);
-          q = fma(-Qi[r][c], Ri[c][r], q);
-        }
-      for (int r = 0; r < d; ++r) {
-        Qr[r][r] -= q;
-        for (int c = 0; c < d; ++c) {
-          Qr[r][c] /= t;
-          Qi[r][c] /= t;
-        }
-      }
-      // this thread's parameter: a diagonal entry or one half of a pair
-      int j = 0, l = 0, part = 0;
-      if (tid < d) {
-        j = l = tid;
-      } else {
-        const int p = (tid - d) >> 1;
-        part = (tid - d) & 1;
-        j = 1;
-        while ((j * (j + 1)) / 2 <= p) ++j;
-        l = p - (j * (j - 1)) / 2;
-      }
-      double gre = 0.0, gim = 0.0;  // (2 Q' A)_jl
-      for (int k = 0; k < d; ++k) {
-        gre = fma(Qr[j][k], Ar[k][l], gre);
-        gre = fma(-Qi[j][k], Ai[k][l], gre);
-        gim = fma(Qr[j][k], Ai[k][l], gim);
-        gim = fma(Qi[j][k], Ar[k][l], gim);
-      }
-      a.grad_theta[tid] = 2.0 * (part ? gim : gre);
-    }
-    for (int x = tid; x < (M - 1) * D; x += blockDim.x) a.grad_theta[e_off + x] = ge[x] - ge[(M - 1) * D + x % D];
+  const double* gg = a.grad_full + D + (int64_t)a.M * D;
+  const int64_t g_off = D + (int64_t)(a.M - 1) * D;
+  if (blockIdx.x == a.K) {  // state and effects
+    spam_backward<D, D == 16 ? 4 : 2>(a);
     return;
   }
   const int g = blockIdx.x;
@@ -466,58 +536,42 @@ __global__ __launch_bounds__(256) void cptp_backward_kernel(const ParamLaunch a)
     const int i = lane & 15, t = lane >> 4;
     const int sc = scaling_of(s.L, lane);
     const double f = ldexp(1.0, -sc);
-    // A = L^T / 2^s into W[2]; Xs = (dF/dG G0^T) / 2^s into W[5]
-    scaled_copy(s.W[2], s.LT, f, lane);
-    {
-      const d4 x = mm_acc(s.W[3], s.W[4], d4{0.0, 0.0, 0.0, 0.0}, lane);
-      wave_sync();
-#pragma unroll
-      for (int v = 0; v < 4; ++v) s.W[5][(4 * v + t) * ROW + i] = x[v] * f;
-    }
-    // block Horner: P11 in W[0] / W[1], P12 in W[3] / W[4] (dF/dG and G0^T are done)
-    double* P11 = s.W[0];
-    double* N11 = s.W[1];
-    double* P12 = s.W[3];
-    double* N12 = s.W[4];
-    for (int x = lane; x < 16 * ROW; x += 64) {
-      P11[x] = (x / ROW == x % ROW) ? 1.0 : 0.0;
-      P12[x] = 0.0;
-    }
+    // X = dF/dG G0^T into W[5] (a left operand below)
+    store_acc(s.W[5], mm_acc(s.W[3], s.W[4], d4{0.0, 0.0, 0.0, 0.0}, lane), lane);
     wave_sync();
-    const double* Am = s.W[2];
-    const double* Xs = s.W[5];
+    const Frag A = load_left(s.LT, f, lane);   // L^T / 2^s
+    const Frag Xs = load_left(s.W[5], f, lane);
+    // block Horner: [[P11, P12], [0, P11]] <- I + [[A, Xs], [0, A]] [[P11, P12], [0, P11]] / k
+    Frag P11 = identity_frag(lane), P12;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) P12.v[v] = 0.0;
     for (int k = TAYLOR; k >= 1; --k) {
-      const d4 q11 = mm_acc(Am, P11, d4{0.0, 0.0, 0.0, 0.0}, lane);
-      const d4 q12 = mm_acc(Xs, P11, mm_acc(Am, P12, d4{0.0, 0.0, 0.0, 0.0}, lane), lane);
+      const double rk = 1.0 / (double)k;
+      const d4 q11 = mfma_left(A, P11, d4{0.0, 0.0, 0.0, 0.0});
+      const d4 q12 = mfma_left(Xs, P11, mfma_left(A, P12, d4{0.0, 0.0, 0.0, 0.0}));
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int r = 4 * v + t;
-        N11[r * ROW + i] = (r == i ? 1.0 : 0.0) + q11[v] / (double)k;
-        N12[r * ROW + i] = q12[v] / (double)k;
+        P11.v[v] = fma(q11[v], rk, 4 * v + t == i ? 1.0 : 0.0);
+        P12.v[v] = q12[v] * rk;
       }
-      wave_sync();
-      double* tmp = P11;
-      P11 = N11;
-      N11 = tmp;
-      tmp = P12;
-      P12 = N12;
-      N12 = tmp;
     }
+    // squarings: P11 <- P11 P11, P12 <- P11 P12 + P12 P11
     for (int e = 0; e < sc; ++e) {
-      const d4 q11 = mm_acc(P11, P11, d4{0.0, 0.0, 0.0, 0.0}, lane);
-      const d4 q12 = mm_acc(P12, P11, mm_acc(P11, P12, d4{0.0, 0.0, 0.0, 0.0}, lane), lane);
-      store_acc(N11, q11, lane);
-      store_acc(N12, q12, lane);
+      store_frag(s.W[0], P11, lane);
+      store_frag(s.W[1], P12, lane);
       wave_sync();
-      double* tmp = P11;
-      P11 = N11;
-      N11 = tmp;
-      tmp = P12;
-      P12 = N12;
-      N12 = tmp;
+      const Frag L11 = load_left(s.W[0], 1.0, lane), L12 = load_left(s.W[1], 1.0, lane);
+      wave_sync();
+      const d4 q11 = mfma_left(L11, P11, d4{0.0, 0.0, 0.0, 0.0});
+      const d4 q12 = mfma_left(L12, P11, mfma_left(L11, P12, d4{0.0, 0.0, 0.0, 0.0}));
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        P11.v[v] = q11[v];
+        P12.v[v] = q12[v];
+      }
     }
     // dF/dL into L's slot
-    for (int x = lane; x < 16 * ROW; x += 64) s.L[x] = P12[x];
+    store_frag(s.L, P12, lane);
   }
   __syncthreads();
   const double* Lb = s.L;
@@ -526,21 +580,32 @@ __global__ __launch_bounds__(256) void cptp_backward_kernel(const ParamLaunch a)
   // dF/dh_k = sum_a dF/dL[a][a^k] y[a][a^k]
   if (tid < m) {
     const int k = tid + 1;
+    double y[D];
+#pragma unroll
+    for (int r = 0; r < D; ++r) y[r] = a.ty[r * D + (r ^ k)];
     double v = 0.0;
-    for (int r = 0; r < D; ++r) v = fma(Lb[r * ROW + (r ^ k)], a.ty[r * D + (r ^ k)], v);
+#pragma unroll
+    for (int r = 0; r < D; ++r) v = fma(Lb[r * ROW + (r ^ k)], y[r], v);
     out[tid] = v;
   }
-  // Chat_jk = sum_a dF/dL[a][b] z[a][b][j], b = a ^ j ^ k  (into Cr / Ci)
+  // Chat_jk = sum_a dF/dL[a][b] z[j][a][b], b = a ^ j ^ k  (into Cr / Ci)
   {
     const int j = tid >> 4, k = tid & 15;
     double cr = 0.0, ci = 0.0;
     if (j < m && k < m) {
       const int jl = j + 1, kl = k + 1;
+      double zr[D], zi[D];
+#pragma unroll
       for (int r = 0; r < D; ++r) {
-        const int c = r ^ jl ^ kl;
-        const size_t x = (size_t)(r * D + c) * D + jl;
-        cr = fma(Lb[r * ROW + c], a.tzr[x], cr);
-        ci = fma(Lb[r * ROW + c], a.tzi[x], ci);
+        const size_t x = (size_t)jl * D * D + r * D + (r ^ jl ^ kl);
+        zr[r] = a.tzr[x];
+        zi[r] = a.tzi[x];
+      }
+#pragma unroll
+      for (int r = 0; r < D; ++r) {
+        const double lb = Lb[r * ROW + (r ^ jl ^ kl)];
+        cr = fma(lb, zr[r], cr);
+        ci = fma(lb, zi[r], ci);
       }
     }
     __syncthreads();  // C is no longer needed

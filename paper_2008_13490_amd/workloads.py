@@ -601,3 +601,36 @@ def unpack_params(theta: np.ndarray, n_qubits: int, M: int, K: int):
     E = theta[D:D + M * D].reshape(M, D)
     G = theta[D + M * D:].reshape(K, D, D)
     return rho, E, G
+
+
+def param_point(mode: str, gs: GateSet, seed: int, scale: float = 0.03) -> np.ndarray:
+    """A seeded parameter vector of an estimation mode (layouts of gst_param_*).
+
+    full: the gate set's own parameters.  tp: rho[1:], the first M - 1 effects
+    and rows 1.. of the gates of a trace-preserving set with a complete POVM
+    (as given).  cptp: the state parameter e_0 plus N(0, scale^2 / 100) entries
+    (|0..0> nearly), the first M - 1 effects of the set, and per gate a
+    Hamiltonian part h ~ N(0, scale^2) and a dissipator factor with diagonal
+    scale (1 + |N(0, 1)|) and entries below it ~ N(0, (0.3 scale)^2), about the
+    ideal gates as targets."""
+    D, M, K = gs.D, gs.M, gs.K
+    if mode == "full":
+        return pack_params(gs)
+    if mode == "tp":
+        return np.concatenate([gs.rho[1:], gs.effects[:M - 1].ravel(), gs.gates[:, 1:, :].ravel()])
+    assert mode == "cptp"
+    rng = np.random.default_rng(seed)
+    A = rng.normal(size=D) * scale * 0.1
+    A[0] = 1.0
+    m = D - 1
+    parts = [A, gs.effects[:M - 1].ravel()]
+    for _ in range(K):
+        parts += [rng.normal(size=m) * scale, scale * (1.0 + np.abs(rng.normal(size=m))),
+                  rng.normal(size=m * (m - 1)) * scale * 0.3]
+    return np.concatenate(parts)
+
+
+def ideal_targets(kind: str) -> np.ndarray:
+    """Transfer matrices of the ideal gates of ``kind`` (the CPTP targets)."""
+    _, Us, _ = ideal_unitaries(kind)
+    return np.ascontiguousarray(np.array([ptm_from_unitary(U) for U in Us]))

@@ -160,3 +160,24 @@ def test_likelihood_gradient_in_mode(oracle_lib, gpu, mode):
     rel = np.abs(g_theta - g_o).max() / np.abs(g_o).max()
     say(f"[params] {mode}: gradient max-norm relative difference {rel:.3g}")
     assert rel <= 1e-10
+
+
+def test_autograd_through_parameterization(gpu):
+    """gst_nll(*gst_gateset(theta, par), request).backward() gives the same dF/dtheta
+    as the explicit forward / evaluation / backward calls (bit for bit)."""
+    api, ctx, torch = gpu
+    from paper_2008_13490_amd import autograd as AG
+    w = W.structured_workload("c1")
+    n, M, K = 1, 2, 3
+    G0, _ = targets_of("1q")
+    th = theta_near("cptp", n, M, K, np.random.default_rng(31), 0.03)
+    par = api.Parameterization(ctx, "cptp", n, M, K, torch.as_tensor(G0, device="cuda"))
+    req = api.Request(ctx, n, K, M, w.seqs.offsets, w.seqs.gates, w.counts)
+    theta = torch.tensor(th, device="cuda", requires_grad=True)
+    F = AG.gst_nll(*AG.gst_gateset(theta, par), req)
+    F.backward()
+    tt = torch.as_tensor(th, device="cuda")
+    obj, _, grad = req.eval(par.forward(tt), want_probs=False, want_grad=True)
+    want = par.backward(tt, grad)
+    assert float(F.detach()) == float(obj[0])
+    assert torch.equal(theta.grad, want)

@@ -42,7 +42,7 @@ def test_tables_match_oracle_bases(tablib, n):
                 assert ham[k - 1, a, b] == want, (a, b, k)
             for j in range(1, D):
                 for k in range(1, D):
-                    want = zr[a, b, j] + 1j * zi[a, b, j] if k == (a ^ b ^ j) else 0.0
+                    want = zr[j, a, b] + 1j * zi[j, a, b] if k == (a ^ b ^ j) else 0.0
                     assert abs(Z[j - 1, k - 1, a, b] - want) <= 1e-15, (a, b, j, k)
     # every entry is a small multiple of 1/2
     assert np.all(2 * y == np.round(2 * y)) and np.all(2 * zr == np.round(2 * zr))
