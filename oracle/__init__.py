@@ -7,3 +7,4 @@ from .binding import (  # noqa: F401
     build, probs, probs_extended, loglik, vjp, tv_distance, predict, OracleError, library_path,
 )
 from . import params  # noqa: F401  (parameterizations of the fit)
+from . import fit  # noqa: F401  (LGST, MLGST, gauge optimization)

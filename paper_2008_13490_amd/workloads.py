@@ -634,3 +634,78 @@ def ideal_targets(kind: str) -> np.ndarray:
     """Transfer matrices of the ideal gates of ``kind`` (the CPTP targets)."""
     _, Us, _ = ideal_unitaries(kind)
     return np.ascontiguousarray(np.array([ptm_from_unitary(U) for U in Us]))
+
+
+# ---------------------------------------------------------------------------
+# The fit (Sec. 6.3.1-6.3.2): LGST sequences and iterative MLGST stages
+# ---------------------------------------------------------------------------
+# Informationally complete product fiducials over (Gii, Gxi, Gix, Gyi, Giy, Gcz):
+# per qubit {empty, X(pi/2), Y(pi/2), X(pi/2) X(pi/2)} (|0>, a Y and an X
+# eigenstate, |1>); the 16 combinations prepare, 11 of them measure (with four
+# outcomes each), as many as the thesis's list uses.
+FIT_PREP_FIDUCIALS_2Q = [a + b for a in ((), (1,), (3,), (1, 1)) for b in ((), (2,), (4,), (2, 2))]
+FIT_MEAS_FIDUCIALS_2Q = [(), (2,), (4,), (1,), (1, 2), (1, 4), (3,), (3, 2), (3, 4), (1, 1), (2, 2)]
+FIT_MAX_LENGTHS = (1, 2, 4, 8, 16, 32)
+
+
+@dataclasses.dataclass
+class FitWorkload:
+    truth: GateSet            # generates the counts
+    target: GateSet           # the ideal gates (CPTP targets, gauge optimization)
+    prep_fids: List[Tuple[int, ...]]
+    meas_fids: List[Tuple[int, ...]]
+    germs: List[Tuple[int, ...]]
+    max_lengths: Tuple[int, ...]
+    seqs: SeqList             # every sequence: LGST words first, then by stage
+    counts: np.ndarray        # int32 [S, M]
+    stage_end: List[int]      # stage s fits sequences [0, stage_end[s])
+
+
+def fit_words(prep_fids, meas_fids, germs, max_lengths, K):
+    """LGST words F_q F_p and F_q G_k F_p (time order: F_p first), then for each
+    maximum length L the words F_q g^p F_p with p = floor(L / |g|) >= 1 not
+    listed before; returns the words and the end of each stage (stage 0 = LGST)."""
+    words, seen, ends = [], set(), []
+
+    def add(w):
+        if w not in seen:
+            seen.add(w)
+            words.append(w)
+
+    for fp in prep_fids:
+        for fq in meas_fids:
+            add(tuple(fp) + tuple(fq))
+    for k in range(K):
+        for fp in prep_fids:
+            for fq in meas_fids:
+                add(tuple(fp) + (k,) + tuple(fq))
+    ends.append(len(words))
+    for L in max_lengths:
+        for g in germs:
+            p = L // len(g)
+            if p < 1:
+                continue
+            for fp in prep_fids:
+                for fq in meas_fids:
+                    add(tuple(fp) + tuple(g) * p + tuple(fq))
+        ends.append(len(words))
+    return words, ends
+
+
+def fit_workload() -> FitWorkload:
+    """The two-qubit fit: the C2 truth and germs, the informationally complete
+    fiducials above, maximum lengths 1..32 (at most 38 gates per sequence),
+    counts ~ Multinomial(1000) from the emulated device."""
+    kind = "2q"
+    r_rot, r_germ, r_cnt, _, _, _ = _streams("c2")
+    truth = noisy_gateset(kind, LAMBDA, SIGMA, r_rot)
+    germs = random_germs(truth.K, _STRUCTURED["c2"][3], r_germ)
+    words, ends = fit_words(FIT_PREP_FIDUCIALS_2Q, FIT_MEAS_FIDUCIALS_2Q, germs, FIT_MAX_LENGTHS, truth.K)
+    sl = from_words(words)
+    p = _device_probs_words(truth, sl, np.arange(sl.S))
+    counts = sample_counts(p, N_SHOTS, np.random.default_rng(np.random.SeedSequence(MASTER_SEEDS["c2"] + 100)))
+    names, Us, n = ideal_unitaries(kind)
+    G = np.ascontiguousarray(np.array([ptm_from_unitary(U) for U in Us]))
+    target = GateSet(n, names, truth.rho.copy(), truth.effects.copy(), G, np.array(Us), 0.0)
+    return FitWorkload(truth, target, list(FIT_PREP_FIDUCIALS_2Q), list(FIT_MEAS_FIDUCIALS_2Q), germs,
+                       FIT_MAX_LENGTHS, sl, counts, ends)
