@@ -274,6 +274,60 @@ int gst_param_backward(gst_ctx* ctx, int mode, int n_qubits, int n_outcomes, int
                        const double* targets, const double* grad_full, double* grad_theta);
 
 /*
+ * The fit (thesis Sec. 6.3.1).  The gate set is determined only up to the GST
+ * gauge (E -> E X^-1, G -> X G X^-1, rho -> X rho).
+ *
+ * gst_lgst: linear-inversion estimates from a host sequence list with counts.
+ * The list must hold, for every preparation fiducial F_j and measurement
+ * fiducial F_i (host CSR word lists, time order, each containing the empty
+ * word), the words F_j F_i and F_j G_k F_i for every gate k.  AB[J + M i][j] and
+ * B_k[J + M i][j] are their outcome frequencies; with AB = U S V^T truncated to
+ * rank D (each singular pair signed so that the largest-magnitude entry of its V
+ * column is positive) and Ahat = U^T AB V: G_k = Ahat^-1 U^T B_k V,
+ * rho = Ahat^-1 U^T AB[:, empty], E_J = AB[J + M empty, :] V (host outputs).
+ * GST_EINVAL if a word is missing, a fiducial list lacks the empty word, or AB
+ * has rank below D.
+ *
+ * gst_gauge_optimize: minimizes sum_k ||X G_k X^-1 - T_k||_F^2 + w (||X rho - rho_T||^2
+ * + sum_m ||X^-T e_m - e_T,m||^2) over X (L-BFGS until the largest gradient
+ * entry is <= gtol) from the least-squares solution of the same relations
+ * multiplied through by X (X G_k = T_k X, X rho = rho_T, X^T e_T,m = e_m: linear in
+ * X), and applies X to rho, effects and gates in place
+ * (host arrays); optional outputs: X (row-major D x D) and the objective.
+ *
+ * gst_mlgst: iterative MLGST on the GPU.  For each stage (resident requests of
+ * this context, same sizes, usually lists of growing length) it minimizes the
+ * negative log-likelihood per shot (F / sum of the stage's counts) over theta
+ * in the TP or CPTP parameterization (gst_param_*) with limited-memory BFGS
+ * (two-loop recursion with opt->memory pairs, backtracking Armijo line search
+ * from the unit step; a step with some p <= 0 where N > 0 counts as too long),
+ * starting from the previous stage's result.  theta: host array of
+ * gst_param_count entries, in/out.  reports (optional): one per stage.
+ * Errors pending on the context before the call are returned (gst_sync) and
+ * the fit does not start; the data-error counters are clear afterwards.
+ */
+typedef struct gst_fit_options {
+  int max_iter;  /* iterations per stage, >= 1 */
+  double gtol;   /* stop when max |dF/dtheta| / sum N <= gtol */
+  int memory;    /* correction pairs, 1..100 */
+} gst_fit_options;
+typedef struct gst_fit_report {
+  int iterations;
+  int evaluations;
+  int status;        /* 0 tolerance met, 1 iteration limit, 2 the line search found no decrease */
+  double objective;  /* F at the stage's result */
+  double grad_max;   /* max |dF/dtheta| / sum N there */
+} gst_fit_report;
+int gst_lgst(int n_qubits, int n_outcomes, int n_gates, int64_t n_seq, const int64_t* offsets, const uint8_t* gate_idx,
+             const int32_t* counts, int n_prep, const int64_t* prep_offsets, const uint8_t* prep_gates, int n_meas,
+             const int64_t* meas_offsets, const uint8_t* meas_gates, double* rho, double* effects, double* gates);
+int gst_gauge_optimize(int n_qubits, int n_outcomes, int n_gates, double* rho, double* effects, double* gates,
+                       const double* target_rho, const double* target_effects, const double* target_gates,
+                       double spam_weight, double gtol, double* gauge, double* objective);
+int gst_mlgst(gst_ctx* ctx, int n_stages, gst_req* const* stages, int mode, const double* targets, double* theta,
+              const gst_fit_options* opt, gst_fit_report* reports);
+
+/*
  * Kernel timing (diagnostics).  While enabled, every kernel the context
  * enqueues is launched with a pair of HIP events on the context's stream that
  * the runtime stamps with the kernel's own start and end (no marker is queued

@@ -18,12 +18,13 @@ Plain definitions with numpy / scipy as the library steps:
   empty measurement fiducial).  Each singular pair is signed so that the
   largest-magnitude entry of its V column is positive.
 * gauge_objective / gauge_opt: sum_k ||M G_k M^-1 - T_k||_F^2 + w (||M rho -
-  rho_T||^2 + sum_m ||M^-T e_m - e_T,m||^2), minimized over M from M = 1 with
-  scipy's L-BFGS-B.
+  rho_T||^2 + sum_m ||M^-T e_m - e_T,m||^2), minimized over M with scipy's
+  L-BFGS-B from the least-squares solution of the same relations multiplied
+  through by M (linear in M).
 * contract_tp: the TP parameters of an estimate (the entries TP leaves free).
 * mlgst: each stage minimizes the negative log-likelihood (the oracle's
   loglik) of its sequences, in the chosen parameterization, with the plain
-  L-BFGS below (its backtracking treats a step into p <= 0, objective +inf, as
+  L-BFGS below (its line search treats a step into p <= 0, objective +inf, as
   too long), starting from the previous stage's parameters.  The likelihood is
   bounded only where every sequence's probabilities sum to one (TP, CPTP).
 """
@@ -123,9 +124,41 @@ def gauge_objective(x, rho, E, G, rT, ET, GT, w: float):
     return f, gM.reshape(-1)
 
 
-def gauge_opt(rho, E, G, rT, ET, GT, w: float = 1.0, gtol: float = 1e-13, maxiter: int = 2000):
+def gauge_linear_start(rho, E, G, rT, ET, GT, w: float = 1.0) -> np.ndarray:
+    """X minimizing the quadratic sum_k ||X G_k - T_k X||_F^2 + w (||X rho - rho_T||^2
+    + sum_m ||X^T e_T,m - e_m||^2) (the gauge relations multiplied through by X):
+    linear least squares over the entries of X."""
     D = rho.shape[0]
-    res = so.minimize(gauge_objective, np.eye(D).reshape(-1), args=(rho, E, G, rT, ET, GT, w), jac=True,
+    rows, rhs = [], []
+    for g, t in zip(G, GT):
+        for a in range(D):
+            for b in range(D):
+                r = np.zeros((D, D))
+                r[a, :] += g[:, b]          # (X g)_ab = sum_c X_ac g_cb
+                r[:, b] -= t[a, :]          # (t X)_ab = sum_c t_ac X_cb
+                rows.append(r.reshape(-1))
+                rhs.append(0.0)
+    sw = np.sqrt(w)
+    for i in range(D):
+        r = np.zeros((D, D))
+        r[i, :] = rho
+        rows.append(sw * r.reshape(-1))
+        rhs.append(sw * rT[i])
+    for e, t in zip(E, ET):
+        for j in range(D):
+            r = np.zeros((D, D))
+            r[:, j] = t                     # (X^T t)_j = sum_i X_ij t_i
+            rows.append(sw * r.reshape(-1))
+            rhs.append(sw * e[j])
+    x, *_ = np.linalg.lstsq(np.array(rows), np.array(rhs), rcond=None)
+    return x.reshape(D, D)
+
+
+def gauge_opt(rho, E, G, rT, ET, GT, w: float = 1.0, gtol: float = 1e-13, maxiter: int = 2000, start=None):
+    """From the linear start (or `start`), scipy's L-BFGS-B on gauge_objective."""
+    D = rho.shape[0]
+    X0 = gauge_linear_start(rho, E, G, rT, ET, GT, w) if start is None else start
+    res = so.minimize(gauge_objective, np.asarray(X0, np.float64).reshape(-1), args=(rho, E, G, rT, ET, GT, w), jac=True,
                       method="L-BFGS-B", options={"gtol": gtol, "ftol": 1e-15, "maxiter": maxiter, "maxcor": 10})
     Mg = res.x.reshape(D, D)
     return Mg, gauge_transform(rho, E, G, Mg), res.fun
@@ -168,9 +201,10 @@ def mlgst(stages: Sequence[Tuple[np.ndarray, np.ndarray, np.ndarray]], theta0, m
 
 def lbfgs(f, x0, m: int = 10, gtol: float = 1e-10, maxiter: int = 1000):
     """A plain limited-memory BFGS (two-loop recursion, memory m, initial scaling
-    s^T y / y^T y) with a backtracking Armijo line search from the unit step;
-    pairs with s^T y <= 0 are skipped.  Stops when max |g| <= gtol, after
-    maxiter iterations, or when the line search cannot decrease f."""
+    s^T y / y^T y) with a strong Wolfe line search (c1 = 1e-4, c2 = 0.9:
+    bracketing by doubling from the unit step, then bisection; a non-finite
+    objective counts as too long); pairs with s^T y <= 0 are skipped.  Stops when
+    max |g| <= gtol, after maxiter iterations, or when no step decreases f."""
     x = np.asarray(x0, np.float64).copy()
     fx, g = f(x)
     S, Y = [], []
@@ -189,15 +223,49 @@ def lbfgs(f, x0, m: int = 10, gtol: float = 1e-10, maxiter: int = 1000):
             b = np.dot(y, q) / np.dot(y, s)
             q += (a - b) * s
         d = -q
-        t = 1.0
-        for _ in range(60):
-            xn = x + t * d
-            fn, gn = f(xn)
-            if fn <= fx + 1e-4 * t * np.dot(g, d):
-                break
-            t *= 0.5
-        else:
+        gd = np.dot(g, d)
+        if not gd < 0:
             break
+
+        def phi(a):
+            xn = x + a * d
+            fn, gn = f(xn)
+            return xn, fn, gn, np.dot(gn, d)
+
+        c1, c2 = 1e-4, 0.9
+        a_prev, f_prev, a = 0.0, fx, 1.0
+        found, zoom, lo, hi, f_lo = False, False, 0.0, 0.0, fx
+        for ls in range(60):
+            xn, fn, gn, dn = phi(a)
+            if not np.isfinite(fn) or fn > fx + c1 * a * gd or (ls > 0 and fn >= f_prev):
+                lo, f_lo, hi, zoom = a_prev, f_prev, a, True
+                break
+            if abs(dn) <= -c2 * gd:
+                found = True
+                break
+            if dn >= 0:
+                lo, f_lo, hi, zoom = a, fn, a_prev, True
+                break
+            a_prev, f_prev, a = a, fn, 2 * a
+        if zoom:
+            for _ in range(60):
+                a = 0.5 * (lo + hi)
+                xn, fn, gn, dn = phi(a)
+                if not np.isfinite(fn) or fn > fx + c1 * a * gd or fn >= f_lo:
+                    hi = a
+                else:
+                    if abs(dn) <= -c2 * gd:
+                        found = True
+                        break
+                    if dn * (hi - lo) >= 0:
+                        hi = lo
+                    lo, f_lo = a, fn
+        if not found:
+            if lo > 0 and np.isfinite(f_lo) and f_lo <= fx + c1 * lo * gd and f_lo < fx:
+                a = lo
+                xn, fn, gn, dn = phi(a)
+            else:
+                break
         s, y = xn - x, gn - g
         if np.dot(s, y) > 1e-300:
             S.append(s)

@@ -24,7 +24,8 @@ EXPORTED = [
     "gst_req_create_host", "gst_req_footprint", "gst_req_eval", "gst_req_probs", "gst_req_vjp",
     "gst_req_destroy", "gst_req_plan_info", "gst_batch_create", "gst_batch_run", "gst_batch_nonpos",
     "gst_batch_destroy", "gst_tune_set", "gst_set_plan_jump", "gst_predict", "gst_tv_distance",
-    "gst_param_count", "gst_param_forward", "gst_param_backward", "gst_profile_enable", "gst_profile_only",
+    "gst_param_count", "gst_param_forward", "gst_param_backward", "gst_lgst", "gst_gauge_optimize", "gst_mlgst",
+    "gst_profile_enable", "gst_profile_only",
     "gst_profile_read", "gst_last_error",
 ]
 
@@ -47,6 +48,15 @@ class GstSeqlist(ctypes.Structure):
 
 class GstDiag(ctypes.Structure):
     _fields_ = [("n_bad_index", ctypes.c_int64), ("n_nonpos", ctypes.c_int64)]
+
+
+class GstFitOptions(ctypes.Structure):
+    _fields_ = [("max_iter", ctypes.c_int), ("gtol", ctypes.c_double), ("memory", ctypes.c_int)]
+
+
+class GstFitReport(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int), ("evaluations", ctypes.c_int), ("status", ctypes.c_int),
+                ("objective", ctypes.c_double), ("grad_max", ctypes.c_double)]
 
 
 _lib = None
@@ -94,6 +104,11 @@ def load():
         lib.gst_param_forward.argtypes = [P, I, I, I, I, P, P, P, P, P]
         lib.gst_param_backward.argtypes = [P, I, I, I, I, P, P, P, P]
         for name in ("gst_param_count", "gst_param_forward", "gst_param_backward"):
+            getattr(lib, name).restype = I
+        lib.gst_lgst.argtypes = [I, I, I, I64, P, P, P, I, P, P, I, P, P, P, P, P]
+        lib.gst_gauge_optimize.argtypes = [I, I, I, P, P, P, P, P, P, ctypes.c_double, ctypes.c_double, P, P]
+        lib.gst_mlgst.argtypes = [P, I, P, I, P, P, ctypes.POINTER(GstFitOptions), P]
+        for name in ("gst_lgst", "gst_gauge_optimize", "gst_mlgst"):
             getattr(lib, name).restype = I
         lib.gst_profile_read.restype = I
         if hasattr(lib, "gst_req_create_host"):

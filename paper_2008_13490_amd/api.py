@@ -380,6 +380,75 @@ class Parameterization:
         return out
 
 
+def _csr_words(words):
+    import numpy as np
+    off = np.zeros(len(words) + 1, np.int64)
+    for i, w in enumerate(words):
+        off[i + 1] = off[i] + len(w)
+    flat = np.array([int(g) for w in words for g in w] or [0], np.uint8)
+    return off, flat
+
+
+def lgst(n_qubits: int, n_outcomes: int, n_gates: int, offsets, gates, counts, prep_fids, meas_fids):
+    """Linear-inversion estimates (``gst_lgst``) from a host sequence list with
+    counts and the fiducial words; returns numpy (rho [D], effects [M, D],
+    gates [K, D, D]) in the gauge of the truncated singular vectors."""
+    import numpy as np
+    lib = _lib.load()
+    D = 4 ** n_qubits
+    off = np.ascontiguousarray(offsets, np.int64)
+    g = np.ascontiguousarray(gates, np.uint8) if len(gates) else np.zeros(1, np.uint8)
+    cnt = np.ascontiguousarray(counts, np.int32)
+    po, pg = _csr_words(prep_fids)
+    mo, mg = _csr_words(meas_fids)
+    rho, E, G = np.zeros(D), np.zeros((n_outcomes, D)), np.zeros((n_gates, D, D))
+    _lib.check(lib.gst_lgst(n_qubits, n_outcomes, n_gates, len(off) - 1, off.ctypes.data, g.ctypes.data,
+                            cnt.ctypes.data, len(prep_fids), po.ctypes.data, pg.ctypes.data, len(meas_fids),
+                            mo.ctypes.data, mg.ctypes.data, rho.ctypes.data, E.ctypes.data, G.ctypes.data))
+    return rho, E, G
+
+
+def gauge_optimize(n_qubits: int, rho, E, G, target_rho, target_E, target_G, spam_weight: float = 1.0,
+                   gtol: float = 1e-12):
+    """Gauge optimization toward the targets (``gst_gauge_optimize``) on copies of
+    the host arrays; returns (rho, E, G, X, objective)."""
+    import numpy as np
+    lib = _lib.load()
+    rho, E, G = (np.array(a, np.float64, copy=True, order="C") for a in (rho, E, G))
+    tr, tE, tG = (np.ascontiguousarray(a, np.float64) for a in (target_rho, target_E, target_G))
+    D = rho.shape[0]
+    X = np.zeros((D, D))
+    obj = ctypes.c_double(0.0)
+    _lib.check(lib.gst_gauge_optimize(n_qubits, E.shape[0], G.shape[0], rho.ctypes.data, E.ctypes.data,
+                                      G.ctypes.data, tr.ctypes.data, tE.ctypes.data, tG.ctypes.data,
+                                      float(spam_weight), float(gtol), X.ctypes.data, ctypes.byref(obj)))
+    return rho, E, G, X, obj.value
+
+
+def mlgst(ctx: Context, stages, mode: str, theta0, targets: Optional[torch.Tensor] = None, max_iter: int = 500,
+          gtol: float = 1e-9, memory: int = 10):
+    """Iterative MLGST on the GPU (``gst_mlgst``): ``stages`` are ``Request``s of
+    growing lists; returns (theta, [report dict per stage])."""
+    import numpy as np
+    th = np.array(theta0, np.float64, copy=True, order="C")
+    arr = (ctypes.c_void_p * len(stages))(*[r.handle.value for r in stages])
+    reps = (_lib.GstFitReport * len(stages))()
+    opt = _lib.GstFitOptions(int(max_iter), float(gtol), int(memory))
+    tg = None if targets is None else _require_cuda(targets, torch.float64, "targets")
+    _lib.check(ctx.lib.gst_mlgst(ctx.handle, len(stages), arr, Parameterization.MODES[mode], _ptr(tg),
+                                 th.ctypes.data, ctypes.byref(opt), reps))
+    out = [dict(iterations=r.iterations, evaluations=r.evaluations, status=r.status, objective=r.objective,
+                grad_max=r.grad_max) for r in reps]
+    return th, out
+
+
+def contract_tp(rho, E, G):
+    """TP parameters of an estimate: the entries TP leaves free (rho[1:], the first
+    M - 1 effects, rows 1.. of every gate), in the layout of ``gst_param_*``."""
+    import numpy as np
+    return np.concatenate([np.asarray(rho)[1:], np.asarray(E)[:-1].ravel(), np.asarray(G)[:, 1:, :].ravel()])
+
+
 def set_plan_jump(ctx: Context, reps: int):
     """Germ-power jump repetitions of the sharing plans of requests created
     afterwards on ``ctx`` (``gst_set_plan_jump``; 0 = off, bit-identical

@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "../../include/gst.h"
+#include "gst_fit_core.h"
 #include "gst_internal.h"
 #include "gst_plan.h"
 
@@ -258,6 +259,7 @@ struct gst_req {
   gst_ctx* ctx = nullptr;
   int n_qubits = 0, D = 0, M = 0, K = 0;
   int64_t S = 0, max_len = 0;
+  double total_counts = 0.0;  // sum of all counts (the fit's per-shot scale)
   DevBuf data;  // offsets | gate indices | counts | order | tile slabs
   int64_t* offsets = nullptr;
   uint8_t* gates = nullptr;
@@ -1057,9 +1059,12 @@ int gst_req_create_host(gst_ctx* ctx, int n_qubits, int n_gates, int n_outcomes,
   const int64_t n_steps = S > 0 ? sl->offsets[S] : 0;
   for (int64_t t = 0; t < n_steps; ++t)
     if (sl->gate_idx[t] >= n_gates) return fail(GST_EINDEX, "gate index >= n_gates at step " + std::to_string(t));
+  double total_counts = 0.0;
   if (counts_host)
-    for (int64_t x = 0; x < S * n_outcomes; ++x)
+    for (int64_t x = 0; x < S * n_outcomes; ++x) {
       if (counts_host[x] < 0) return fail(GST_EINVAL, "negative count");
+      total_counts += counts_host[x];
+    }
   HIP_TRY(hipSetDevice(ctx->device));
   std::unique_ptr<gst_req> r(new (std::nothrow) gst_req());
   if (!r) return fail(GST_ENOMEM, "host allocation failed");
@@ -1070,6 +1075,7 @@ int gst_req_create_host(gst_ctx* ctx, int n_qubits, int n_gates, int n_outcomes,
   r->K = n_gates;
   r->S = S;
   r->max_len = max_len;
+  r->total_counts = total_counts;
   // batch tiles: sequences by length (descending, stable), kTileSeqs per tile
   std::vector<int64_t> order((size_t)S);
   for (int64_t q = 0; q < S; ++q) order[q] = q;
@@ -1624,3 +1630,157 @@ int plain_eval64(gst_ctx* ctx, const gst_gateset* gs, const gst_seqlist* sl, int
 }
 
 }  // namespace
+
+// ---------------------------------------------------------------------------
+// The fit: LGST, gauge optimization, iterative MLGST
+// ---------------------------------------------------------------------------
+int gst_lgst(int n_qubits, int n_outcomes, int n_gates, int64_t n_seq, const int64_t* offsets, const uint8_t* gate_idx,
+             const int32_t* counts, int n_prep, const int64_t* prep_offsets, const uint8_t* prep_gates, int n_meas,
+             const int64_t* meas_offsets, const uint8_t* meas_gates, double* rho, double* effects, double* gates) {
+  const int D = dim_of(n_qubits);
+  if (!D) return fail(GST_EINVAL, "n_qubits must be 1, 2 or 3");
+  if (n_outcomes < 1 || n_gates < 1 || n_gates > 255 || n_seq < 0) return fail(GST_EINVAL, "sizes out of range");
+  if (n_prep < D || (int64_t)n_meas * n_outcomes < D)
+    return fail(GST_EINVAL, "LGST needs at least D preparation fiducials and D measurement rows");
+  if (!offsets || !counts || !prep_offsets || !meas_offsets || !rho || !effects || !gates || (n_seq > 0 && !gate_idx))
+    return fail(GST_EINVAL, "NULL argument");
+  const uint8_t empty = 0;
+  std::vector<double> AB, Bk;
+  int j0 = -1, i0 = -1;
+  int rc = gst::lgst_matrices(n_seq, offsets, gate_idx ? gate_idx : &empty, counts, n_outcomes, n_gates, n_prep,
+                              prep_offsets, prep_gates ? prep_gates : &empty, n_meas, meas_offsets,
+                              meas_gates ? meas_gates : &empty, &AB, &Bk, &j0, &i0);
+  if (rc == -1) return fail(GST_EINVAL, "a fiducial pair (with or without a gate between) is not in the list");
+  if (rc == -2) return fail(GST_EINVAL, "both fiducial lists must contain the empty word");
+  if (rc == -3) return fail(GST_EINVAL, "an LGST sequence has no counts");
+  rc = gst::lgst_estimate(D, n_outcomes, n_gates, n_prep, n_meas, AB.data(), Bk.data(), j0, i0, rho, effects, gates);
+  if (rc == -4) return fail(GST_EINVAL, "the SVD of the AB matrix did not converge");
+  if (rc == -5) return fail(GST_EINVAL, "the AB matrix has rank below D (fiducials not informationally complete)");
+  return GST_OK;
+}
+
+int gst_gauge_optimize(int n_qubits, int n_outcomes, int n_gates, double* rho, double* effects, double* gates,
+                       const double* target_rho, const double* target_effects, const double* target_gates,
+                       double spam_weight, double gtol, double* gauge, double* objective) {
+  const int D = dim_of(n_qubits);
+  if (!D) return fail(GST_EINVAL, "n_qubits must be 1, 2 or 3");
+  if (n_outcomes < 1 || n_gates < 1 || !(spam_weight >= 0.0) || !(gtol > 0.0)) return fail(GST_EINVAL, "bad argument");
+  if (!rho || !effects || !gates || !target_rho || !target_effects || !target_gates) return fail(GST_EINVAL, "NULL argument");
+  const int M = n_outcomes, K = n_gates;
+  const size_t DD = (size_t)D * D;
+  std::vector<double> X(DD, 0.0), Xi(DD), t(DD);
+  if (!gst::gauge_linear_start(D, M, K, rho, effects, gates, target_rho, target_effects, target_gates, spam_weight,
+                               X.data()))
+    return fail(GST_EINVAL, "the linear gauge problem is singular");
+  auto f = [&](const double* x, double* g) {
+    return gst::gauge_objective(D, M, K, x, rho, effects, gates, target_rho, target_effects, target_gates, spam_weight, g);
+  };
+  gst::LbfgsResult r = gst::lbfgs((int)DD, X.data(), f, 10, gtol, 20000);
+  if (!gst::invert(D, X.data(), Xi.data())) return fail(GST_EINVAL, "the gauge optimization reached a singular matrix");
+  // rho <- X rho, E <- E X^-1, G <- X G X^-1
+  std::vector<double> v(D);
+  for (int i = 0; i < D; ++i) {
+    double s = 0.0;
+    for (int j = 0; j < D; ++j) s += X[(size_t)i * D + j] * rho[j];
+    v[i] = s;
+  }
+  std::copy(v.begin(), v.end(), rho);
+  for (int m = 0; m < M; ++m) {
+    for (int j = 0; j < D; ++j) {
+      double s = 0.0;
+      for (int i = 0; i < D; ++i) s += effects[(size_t)m * D + i] * Xi[(size_t)i * D + j];
+      v[j] = s;
+    }
+    std::copy(v.begin(), v.end(), effects + (size_t)m * D);
+  }
+  for (int k = 0; k < K; ++k) {
+    double* g = gates + k * DD;
+    for (int i = 0; i < D; ++i)
+      for (int j = 0; j < D; ++j) {
+        double s = 0.0;
+        for (int q = 0; q < D; ++q) s += g[(size_t)i * D + q] * Xi[(size_t)q * D + j];
+        t[(size_t)i * D + j] = s;
+      }
+    for (int i = 0; i < D; ++i)
+      for (int j = 0; j < D; ++j) {
+        double s = 0.0;
+        for (int q = 0; q < D; ++q) s += X[(size_t)i * D + q] * t[(size_t)q * D + j];
+        g[(size_t)i * D + j] = s;
+      }
+  }
+  if (gauge) std::copy(X.begin(), X.end(), gauge);
+  if (objective) *objective = r.f;
+  return GST_OK;
+}
+
+int gst_mlgst(gst_ctx* ctx, int n_stages, gst_req* const* stages, int mode, const double* targets, double* theta,
+              const gst_fit_options* opt, gst_fit_report* reports) {
+  if (!ctx || n_stages < 1 || !stages || !theta || !opt) return fail(GST_EINVAL, "NULL argument");
+  if (mode != GST_PARAM_TP && mode != GST_PARAM_CPTP)
+    return fail(GST_EINVAL, "MLGST needs the TP or CPTP parameterization (the likelihood of the full one is unbounded)");
+  if (opt->max_iter < 1 || !(opt->gtol > 0.0) || opt->memory < 1 || opt->memory > 100)
+    return fail(GST_EINVAL, "options out of range");
+  const gst_req* r0 = stages[0];
+  for (int s = 0; s < n_stages; ++s)
+    if (!stages[s] || stages[s]->ctx != ctx || stages[s]->n_qubits != r0->n_qubits || stages[s]->M != r0->M ||
+        stages[s]->K != r0->K)
+      return fail(GST_EINVAL, "every stage must be a request of this context with the same sizes");
+  const int nq = r0->n_qubits, D = r0->D, M = r0->M, K = r0->K;
+  int64_t n = 0;
+  int rc = gst_param_count(mode, nq, M, K, &n);
+  if (rc) return rc;
+  gst_diag dg;
+  if ((rc = gst_sync(ctx, &dg))) return rc;  // errors of earlier calls are reported, not absorbed
+  HIP_TRY(hipSetDevice(ctx->device));
+  // device: theta | rho | E | G | grad_full | objective | grad_theta
+  const int64_t P = D + (int64_t)M * D + (int64_t)K * D * D;
+  DevBuf buf;
+  if ((rc = buf.reserve((size_t)(n + P + P + 1 + n) * sizeof(double), ctx->stream))) return rc;
+  double* th_d = reinterpret_cast<double*>(buf.p);
+  double* rho_d = th_d + n;
+  double* E_d = rho_d + D;
+  double* G_d = E_d + (int64_t)M * D;
+  double* gf_d = G_d + (int64_t)K * D * D;
+  double* obj_d = gf_d + P;
+  double* gth_d = obj_d + 1;
+  double* pin = nullptr;  // [n] theta out, [1 + n] objective and gradient in
+  HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&pin), (size_t)(2 * n + 1) * sizeof(double), hipHostMallocDefault));
+  std::unique_ptr<double, void (*)(double*)> pin_guard(pin, [](double* q) { (void)hipHostFree(q); });
+  const gst_gateset gs{nq, K, M, rho_d, E_d, G_d};
+  int err = GST_OK;
+  for (int s = 0; s < n_stages && err == GST_OK; ++s) {
+    gst_req* req = stages[s];
+    const double scale = 1.0 / std::max(1.0, req->total_counts);
+    auto f = [&](const double* x, double* g) -> double {
+      if (err) return INFINITY;
+      std::memcpy(pin, x, (size_t)n * sizeof(double));
+      int e = GST_OK;
+      if (hipMemcpyAsync(th_d, pin, (size_t)n * 8, hipMemcpyHostToDevice, ctx->stream) != hipSuccess) e = GST_EDEVICE;
+      if (!e) e = gst_param_forward(ctx, mode, nq, M, K, th_d, targets, rho_d, E_d, G_d);
+      if (!e) e = gst_req_eval(req, &gs, nullptr, obj_d, gf_d);
+      if (!e) e = gst_param_backward(ctx, mode, nq, M, K, th_d, targets, gf_d, gth_d);
+      if (!e && hipMemcpyAsync(pin + n, obj_d, (size_t)(1 + n) * 8, hipMemcpyDeviceToHost, ctx->stream) != hipSuccess)
+        e = GST_EDEVICE;
+      if (!e && hipStreamSynchronize(ctx->stream) != hipSuccess) e = GST_EDEVICE;
+      if (e) {
+        err = e;
+        return INFINITY;
+      }
+      const double F = pin[n];
+      if (!std::isfinite(F)) return INFINITY;  // some p <= 0 with N > 0: the step was too long
+      for (int64_t i = 0; i < n; ++i) g[i] = pin[n + 1 + i] * scale;
+      return F * scale;
+    };
+    const gst::LbfgsResult r = gst::lbfgs((int)n, theta, f, opt->memory, opt->gtol, opt->max_iter);
+    if (reports) {
+      reports[s].iterations = r.iterations;
+      reports[s].evaluations = r.evaluations;
+      reports[s].status = r.status;
+      reports[s].objective = r.f / scale;
+      reports[s].grad_max = r.gmax;
+    }
+  }
+  (void)gst_sync(ctx, &dg);  // the counters hold only the fit's own rejected steps
+  if (err) return fail(err, "an evaluation failed during the fit");
+  return GST_OK;
+}
