@@ -25,7 +25,8 @@ Plain definitions with numpy / scipy as the library steps:
 * mlgst: each stage minimizes the negative log-likelihood (the oracle's
   loglik) of its sequences, in the chosen parameterization, with the plain
   L-BFGS below (its line search treats a step into p <= 0, objective +inf, as
-  too long), starting from the previous stage's parameters.  The likelihood is
+  too long), starting from the previous stage's parameters; in TP, a start
+  with some p <= 0 where N > 0 is first depolarized (feasible_tp_start).  The likelihood is
   bounded only where every sequence's probabilities sum to one (TP, CPTP).
 """
 from __future__ import annotations
@@ -171,6 +172,25 @@ def contract_tp(rho, E, G) -> np.ndarray:
     return np.concatenate([rho[1:], E[:-1].ravel(), G[:, 1:, :].ravel()])
 
 
+def mode_is_tp(mode) -> bool:
+    return PR.mode_id(mode) == PR.TP
+
+
+def feasible_tp_start(theta, n: int, M: int, K: int, offsets, gates, counts):
+    """The TP start with every gate followed by depolarizing of the smallest
+    strength delta in 0, 2^-10, 2^-9, ..., 1/2 (rows 1.. of the transfer matrices
+    times 1 - delta) whose likelihood is finite; returns (theta, delta)."""
+    D = 4 ** n
+    g0 = (D - 1) + (M - 1) * D
+    for delta in [0.0] + [2.0 ** -k for k in range(10, 0, -1)]:
+        th = np.array(theta, np.float64, copy=True)
+        th[g0:] = th[g0:] * (1.0 - delta)
+        F, _ = nll_in_mode(th, "tp", n, M, K, None, offsets, gates, counts)
+        if np.isfinite(F):
+            return th, delta
+    raise RuntimeError("no feasible TP start")
+
+
 def nll_in_mode(theta, mode, n, M, K, G0, offsets, gates, counts):
     rho, E, G = PR.forward(mode, theta, n, M, K, G0)
     F, _, g, nbad, _ = B.loglik(rho, E, G, offsets, gates, counts, raise_nonpos=False)
@@ -188,6 +208,8 @@ def mlgst(stages: Sequence[Tuple[np.ndarray, np.ndarray, np.ndarray]], theta0, m
     theta = np.asarray(theta0, np.float64).copy()
     out = []
     for off, gts, cnt in stages:
+        if mode_is_tp(mode):
+            theta, _ = feasible_tp_start(theta, n, M, K, off, gts, cnt)
         scale = 1.0 / max(1.0, float(np.asarray(cnt, np.float64).sum()))
 
         def f(th):
@@ -207,6 +229,8 @@ def lbfgs(f, x0, m: int = 10, gtol: float = 1e-10, maxiter: int = 1000):
     max |g| <= gtol, after maxiter iterations, or when no step decreases f."""
     x = np.asarray(x0, np.float64).copy()
     fx, g = f(x)
+    if not np.isfinite(fx):
+        return x, fx, g
     S, Y = [], []
     for it in range(maxiter):
         if np.max(np.abs(g)) <= gtol:

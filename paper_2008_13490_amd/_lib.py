@@ -56,7 +56,7 @@ class GstFitOptions(ctypes.Structure):
 
 class GstFitReport(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int), ("evaluations", ctypes.c_int), ("status", ctypes.c_int),
-                ("objective", ctypes.c_double), ("grad_max", ctypes.c_double)]
+                ("objective", ctypes.c_double), ("grad_max", ctypes.c_double), ("shrink", ctypes.c_double)]
 
 
 _lib = None

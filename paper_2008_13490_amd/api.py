@@ -438,7 +438,7 @@ def mlgst(ctx: Context, stages, mode: str, theta0, targets: Optional[torch.Tenso
     _lib.check(ctx.lib.gst_mlgst(ctx.handle, len(stages), arr, Parameterization.MODES[mode], _ptr(tg),
                                  th.ctypes.data, ctypes.byref(opt), reps))
     out = [dict(iterations=r.iterations, evaluations=r.evaluations, status=r.status, objective=r.objective,
-                grad_max=r.grad_max) for r in reps]
+                grad_max=r.grad_max, shrink=r.shrink) for r in reps]
     return th, out
 
 

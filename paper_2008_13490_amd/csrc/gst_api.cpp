@@ -1771,16 +1771,39 @@ int gst_mlgst(gst_ctx* ctx, int n_stages, gst_req* const* stages, int mode, cons
       for (int64_t i = 0; i < n; ++i) g[i] = pin[n + 1 + i] * scale;
       return F * scale;
     };
+    // TP: a start with some p <= 0 where N > 0 (the previous stage's estimate need
+    // not be completely positive) is moved inward by depolarizing every gate with
+    // the smallest strength 2^-10, 2^-9, ..., 1/2 that makes the likelihood finite
+    double shrink = 0.0;
+    if (mode == GST_PARAM_TP) {
+      std::vector<double> gtmp((size_t)n), th0(theta, theta + n), trial((size_t)n);
+      if (!std::isfinite(f(theta, gtmp.data())) && !err) {
+        const int64_t g0 = (D - 1) + (int64_t)(M - 1) * D;
+        for (int k = 10; k >= 1; --k) {
+          const double delta = std::ldexp(1.0, -k);
+          for (int64_t i = 0; i < n; ++i) trial[i] = i < g0 ? th0[i] : th0[i] * (1.0 - delta);
+          if (std::isfinite(f(trial.data(), gtmp.data()))) {
+            std::copy(trial.begin(), trial.end(), theta);
+            shrink = delta;
+            break;
+          }
+          if (err) break;
+        }
+      }
+    }
     const gst::LbfgsResult r = gst::lbfgs((int)n, theta, f, opt->memory, opt->gtol, opt->max_iter);
+    if (!err && !std::isfinite(r.f)) err = GST_ENONPOS;  // the stage's start has p <= 0 where N > 0
     if (reports) {
       reports[s].iterations = r.iterations;
       reports[s].evaluations = r.evaluations;
       reports[s].status = r.status;
       reports[s].objective = r.f / scale;
       reports[s].grad_max = r.gmax;
+      reports[s].shrink = shrink;
     }
   }
   (void)gst_sync(ctx, &dg);  // the counters hold only the fit's own rejected steps
+  if (err == GST_ENONPOS) return fail(err, "the starting parameters give p <= 0 where N > 0");
   if (err) return fail(err, "an evaluation failed during the fit");
   return GST_OK;
 }

@@ -346,6 +346,11 @@ LbfgsResult lbfgs(int n, double* x, const std::function<double(const double*, do
   std::vector<double> g(n), q(n), d(n), xn(n), gn(n);
   double fx = f(x, g.data());
   res.evaluations = 1;
+  if (!std::isfinite(fx)) {  // no descent from a point where f is undefined
+    res.status = 2;
+    res.f = fx;
+    return res;
+  }
   std::deque<std::vector<double>> Ss, Ys;
   auto gmax_of = [&](const std::vector<double>& v) {
     double a = 0.0;

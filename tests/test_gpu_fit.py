@@ -1,0 +1,183 @@
+"""Iterative MLGST on the GPU (gst_mlgst) against the oracle's fit (thesis
+Sec. 6.3.1): the same pipeline (LGST, gauge optimization, starting parameters,
+per-stage L-BFGS with a strong Wolfe line search on the per-shot likelihood)
+on both sides.  The GPU evaluations agree with the oracle's to about 1e-12, so
+the two minimizers follow the same path: per stage the objectives agree to
+1e-9 relative, the fitted probabilities to 1e-7 absolute, and both stop at
+the gradient tolerance or at the rounding floor just above it."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import fit as FT
+from oracle import params as PR
+from paper_2008_13490_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+FIDS_1Q = [(), (1,), (2,), (1, 1)]
+GERMS_1Q = [(0,), (1,), (2,), (1, 2)]
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2008_13490_amd import api
+    return api, api.Context(0), torch
+
+
+def one_qubit_problem(seed=5, max_lengths=(1, 2, 4, 8)):
+    rng = np.random.default_rng(seed)
+    truth = W.noisy_gateset("1q", 5e-3, 0.03, rng)
+    truth.rho = truth.rho * np.array([1.0, 1.0, 1.0, 0.98])
+    words, ends = W.fit_words(FIDS_1Q, FIDS_1Q, GERMS_1Q, max_lengths, 3)
+    sl = W.from_words(words)
+    import oracle
+    p = oracle.probs(truth.rho, truth.effects, truth.gates, sl.offsets, sl.gates)
+    counts = W.sample_counts(p, 1000, rng)
+    target = W.noisy_gateset("1q", 0.0, 0.0, rng)
+    return truth, target, sl, ends, counts
+
+
+def compare_fit(api, ctx, torch, mode, n, M, K, target, sl, ends, counts, prep, meas, n_stages=None, gtol=1e-9,
+                max_iter=400):
+    e0 = ends[0]
+    r, E, G = api.lgst(n, M, K, sl.offsets[:e0 + 1], sl.gates[:sl.offsets[e0]], counts[:e0], prep, meas)
+    r, E, G, _, _ = api.gauge_optimize(n, r, E, G, target.rho, target.effects, target.gates)
+    r_o, E_o, G_o = FT.lgst(sl.offsets[:e0 + 1], sl.gates[:sl.offsets[e0]], counts[:e0], prep, meas, n, K)
+    _, (r_o, E_o, G_o), _ = FT.gauge_opt(r_o, E_o, G_o, target.rho, target.effects, target.gates)
+    assert np.abs(G - G_o).max() <= 1e-6
+    from paper_2008_13490_amd.fit import cptp_start, stage_ends, feasible_tp_start
+    D = 4 ** n
+    ends_s = stage_ends(ends)[:n_stages]
+    reqs, stages = [], []
+    for e in ends_s:
+        sub = sl.subset(np.arange(e))
+        reqs.append(api.Request(ctx, n, K, M, sub.offsets, sub.gates, counts[:e]))
+        stages.append((sub.offsets, sub.gates, counts[:e]))
+    if mode == "tp":
+        # the pipeline's own search agrees with the oracle's
+        _, delta = feasible_tp_start(ctx, reqs[0], api.contract_tp(r, E, G), n, M, K)
+        _, delta_o = FT.feasible_tp_start(FT.contract_tp(r_o, E_o, G_o), n, M, K, *stages[0])
+        assert delta == delta_o
+        th0, th0_o = api.contract_tp(r, E, G), FT.contract_tp(r_o, E_o, G_o)
+        targets = None
+    else:
+        th0 = th0_o = cptp_start(target.effects, K, D)
+        targets = torch.as_tensor(np.ascontiguousarray(target.gates), device="cuda")
+    say(f"[fit] {mode} n={n}: {len(stages)} stages, {ends_s[-1]} sequences")
+    th, reps = api.mlgst(ctx, reqs, mode, th0, targets, max_iter=max_iter, gtol=gtol)
+    out_o = FT.mlgst(stages, th0_o, mode, n, M, K, target.gates if mode == "cptp" else None, maxiter=max_iter,
+                     gtol=gtol)
+    for s, (rep, (th_o, F_o)) in enumerate(zip(reps, out_o)):
+        say(f"[fit] stage {s}: gpu F={rep['objective']!r} it={rep['iterations']} ev={rep['evaluations']} "
+            f"status={rep['status']} gmax={rep['grad_max']:.2e} shrink={rep['shrink']}; oracle F={F_o!r}")
+        assert abs(rep["objective"] - F_o) <= 1e-9 * abs(F_o)
+    G0 = target.gates if mode == "cptp" else None
+    rg, Eg, Gg = PR.forward(mode, th, n, M, K, G0)
+    ro, Eo, Go = PR.forward(mode, out_o[-1][0], n, M, K, G0)
+    import oracle
+    sub = stages[-1]
+    pg = oracle.probs(rg, Eg, Gg, sub[0], sub[1])
+    po = oracle.probs(ro, Eo, Go, sub[0], sub[1])
+    say(f"[fit] max |dp| = {np.abs(pg - po).max():.3g}")
+    assert np.abs(pg - po).max() <= 1e-7
+    # converged: the tolerance met, or no further decrease at the rounding floor of
+    # the per-shot objective with a gradient within ten times the tolerance
+    for rep in reps:
+        assert rep["status"] == 0 or (rep["status"] == 2 and rep["grad_max"] <= 10 * gtol), rep
+    return th, reps
+
+
+def test_mlgst_one_qubit_tp(gpu):
+    api, ctx, torch = gpu
+    truth, target, sl, ends, counts = one_qubit_problem()
+    compare_fit(api, ctx, torch, "tp", 1, 2, 3, target, sl, ends, counts, FIDS_1Q, FIDS_1Q)
+
+
+def test_mlgst_one_qubit_cptp(oracle_lib, gpu):
+    """CPTP: the ML estimate of this list lies on the boundary of the positive
+    semidefinite cone (Cholesky diagonals of the dissipators go to zero, where
+    C = T T^dagger has a vanishing derivative), and L-BFGS, here and in the
+    oracle alike, creeps there for thousands of iterations; over such runs the
+    two paths separate by rounding.  Checked instead: the objective the GPU
+    fit reports is the oracle's likelihood at the returned parameters (1e-10),
+    both fits reach the same objective within 1e-6 relative after the same
+    iteration budget, and both descend from the start."""
+    api, ctx, torch = gpu
+    from paper_2008_13490_amd.fit import cptp_start, stage_ends
+    truth, target, sl, ends, counts = one_qubit_problem()
+    e = stage_ends(ends)[0]
+    sub = sl.subset(np.arange(e))
+    req = api.Request(ctx, 1, 3, 2, sub.offsets, sub.gates, counts[:e])
+    th0 = cptp_start(target.effects, 3, 4)
+    tg = torch.as_tensor(np.ascontiguousarray(target.gates), device="cuda")
+    th, reps = api.mlgst(ctx, [req], "cptp", th0, tg, max_iter=300, gtol=1e-9)
+    (th_o, F_o), = FT.mlgst([(sub.offsets, sub.gates, counts[:e])], th0, "cptp", 1, 2, 3, target.gates,
+                            maxiter=300, gtol=1e-9)
+    F = reps[0]["objective"]
+    F0 = FT.nll_in_mode(th0, "cptp", 1, 2, 3, target.gates, sub.offsets, sub.gates, counts[:e])[0]
+    r, E, G = PR.forward("cptp", th, 1, 2, 3, target.gates)
+    F_at = oracle_lib.loglik(r, E, G, sub.offsets, sub.gates, counts[:e])[0]
+    say(f"[fit] cptp: start {F0!r} gpu {F!r} (oracle at gpu theta {F_at!r}) oracle fit {F_o!r}")
+    assert abs(F - F_at) <= 1e-10 * F_at
+    assert abs(F - F_o) <= 1e-6 * F_o
+    assert F < F0 and F_o < F0
+
+
+def test_mlgst_two_qubit_cptp_first_iterations(oracle_lib, gpu):
+    """The two-qubit fit list in the CPTP parameterization (the thesis's reported
+    mode): with the same algorithm and evaluations that agree to ~1e-12, the GPU
+    fit and the oracle's follow the same path; compared after 15 iterations of
+    the first stage (the oracle's CPTP chain rule takes about a second per
+    evaluation), objectives to 1e-9 relative and probabilities to 1e-7."""
+    api, ctx, torch = gpu
+    from paper_2008_13490_amd.fit import cptp_start, stage_ends
+    fw = W.fit_workload()
+    e = stage_ends(fw.stage_end)[0]
+    sub = fw.seqs.subset(np.arange(e))
+    cnt = fw.counts[:e]
+    req = api.Request(ctx, 2, 6, 4, sub.offsets, sub.gates, cnt)
+    th0 = cptp_start(fw.target.effects, 6, 16)
+    tg = torch.as_tensor(np.ascontiguousarray(fw.target.gates), device="cuda")
+    th, reps = api.mlgst(ctx, [req], "cptp", th0, tg, max_iter=15, gtol=1e-12)
+    (th_o, F_o), = FT.mlgst([(sub.offsets, sub.gates, cnt)], th0, "cptp", 2, 4, 6, fw.target.gates, maxiter=15,
+                            gtol=1e-12)
+    F = reps[0]["objective"]
+    say(f"[fit] 2q cptp 15 iterations: gpu {F!r} ({reps[0]['evaluations']} evaluations) oracle {F_o!r}")
+    assert abs(F - F_o) <= 1e-9 * F_o
+    rg, Eg, Gg = PR.forward("cptp", th, 2, 4, 6, fw.target.gates)
+    ro, Eo, Go = PR.forward("cptp", th_o, 2, 4, 6, fw.target.gates)
+    pg = oracle_lib.probs(rg, Eg, Gg, sub.offsets, sub.gates)
+    po = oracle_lib.probs(ro, Eo, Go, sub.offsets, sub.gates)
+    assert np.abs(pg - po).max() <= 1e-7
+
+
+def test_mlgst_rejects_full_mode_and_reports_pending_errors(gpu):
+    api, ctx, torch = gpu
+    from paper_2008_13490_amd import _lib
+    truth, target, sl, ends, counts = one_qubit_problem()
+    req = api.Request(ctx, 1, 3, 2, sl.offsets, sl.gates, counts)
+    with pytest.raises(_lib.GSTError):
+        api.mlgst(ctx, [req], "full", np.zeros(4 + 8 + 48))
+    with pytest.raises(KeyError):
+        api.mlgst(ctx, [req], "nonsense", np.zeros(3))
+    # a start with p <= 0 where N > 0 is reported, not taken for convergence: the
+    # first effect 1.01 |0><0| leaves the completed second one with p = -0.01 on
+    # the empty sequence, whose counts of outcome 1 are positive
+    from paper_2008_13490_amd.fit import cptp_start
+    eff = np.array(target.effects, copy=True)
+    eff[0] *= 1.01
+    th = cptp_start(eff, 3, 4, mix=0.0)
+    tg = torch.as_tensor(np.ascontiguousarray(target.gates), device="cuda")
+    with pytest.raises(_lib.GSTError) as ei:
+        api.mlgst(ctx, [req], "cptp", th, tg)
+    assert ei.value.code == _lib.GST_ENONPOS
+    ctx.sync()   # the fit left no pending errors
