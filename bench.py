@@ -208,7 +208,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "f3"])
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "f2", "f3"])
+    ap.add_argument("--fit-iters", type=int, default=100, help="f2: L-BFGS iterations per MLGST stage")
     ap.add_argument("--rate", type=float, default=100.0, help="c5 / serving: arrivals per second")
     ap.add_argument("--requests", type=int, default=100, help="c5 / serving: requests in the trace")
     ap.add_argument("--iters", type=int, default=20, help="c5 / serving: iterations per request")
@@ -236,6 +237,10 @@ def main():
                                    "of it", "n_gpus": args.gpus}))
         sys.exit(2)
 
+    if args.workload == "f2":
+        out = run_fit_bench(args)
+        print(json.dumps(out))
+        return
     # CPU baseline first, before anything touches the GPU.
     cpu = None
     if not args.no_cpu:
@@ -616,6 +621,129 @@ def run_predict(args):
                    "distributions_per_step": per_step},
         "roofline": _roofline(dom, fams, flops, None),
         "kernels_ms_per_step": {f: brk[f][0] / n_break for f in brk},
+    }
+
+
+def run_fit_bench(args):
+    """The two-qubit GST fit (thesis Sec. 6.3.1-6.3.2) in the CPTP mode: LGST,
+    gauge optimization, iterative MLGST over the six stages (maximum lengths
+    1..32, at most --fit-iters L-BFGS iterations each) with the evaluations on
+    the GPU, final gauge optimization.  One step = one whole fit; the stage
+    requests (lists, counts and plans in HBM) are created before the timed
+    region."""
+    import torch
+    from paper_2008_13490_amd import api
+    from paper_2008_13490_amd import fit as FIT
+    from paper_2008_13490_amd import workloads as W
+
+    mode = "cptp" if args.param == "full" else args.param
+    fw = W.fit_workload()
+    ends = FIT.stage_ends(fw.stage_end)
+    ctx = api.Context(0)
+    reqs = []
+    for e in ends:
+        sub = fw.seqs.subset(np.arange(e))
+        reqs.append(api.Request(ctx, 2, 6, 4, sub.offsets, sub.gates, fw.counts[:e]))
+
+    def one_fit():
+        return FIT.run_fit(ctx, fw.seqs, fw.counts, fw.stage_end, fw.prep_fids, fw.meas_fids, fw.target, mode=mode,
+                           max_iter=args.fit_iters, gtol=1e-8, requests=reqs)
+
+    # a step is a whole fit: the defaults of the evaluation benches (200 / 20) become 2 / 1
+    steps = 2 if args.steps == 200 else args.steps
+    warm = 1 if args.warmup == 20 else args.warmup
+    for _ in range(warm):
+        one_fit()
+    families = ("leaf", "reduce", "trunk_fwd", "trunk_bwd", "inject", "grad_gemm", "fill", "tiles_2q", "param_fwd",
+                "param_bwd")
+    api.profile_enable(ctx, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    results = [one_fit() for _ in range(steps)]
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    fams = _profile(api, ctx, families)
+    api.profile_enable(ctx, False)
+    res = results[-1]
+    evals = [r["evaluations"] for r in res.reports]
+    n_eval = sum(evals)
+    dom = max(fams, key=lambda f: fams[f][0])
+    # algorithmic flops per launch of the dominant family, weighted by the
+    # evaluations of each stage
+    infos = [req_plan_info(r) for r in reqs]
+    tot = 0.0
+    for e_s, info, end in zip(evals, infos, ends):
+        L = np.diff(fw.seqs.offsets[:end + 1])
+        fl = param_flops(dom, 16, 6) if dom.startswith("param_") else algorithmic_flops(dom, 16, 4, end, int(L.sum()),
+                                                                                         info)
+        tot += e_s * fl
+    flops = tot / max(1, n_eval)
+    out = {
+        "metric": "seconds per two-qubit GST fit (LGST, gauge optimization, 6-stage CPTP MLGST, FP64)",
+        "value": elapsed / steps,
+        "unit": "s/fit",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": warm,
+        "ms_per_step": elapsed / steps * 1e3,
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"f2: two-qubit fit list ({fw.seqs.S} sequences, 16 prep x 11 meas product "
+                               f"fiducials, 12 germs, maximum lengths 1..32, at most 38 gates), counts ~ "
+                               f"Multinomial(1000) from the C2 truth; {mode.upper()} mode, <= {args.fit_iters} "
+                               f"L-BFGS iterations per stage", "stages": ends,
+                   "evaluations_per_fit": n_eval, "iterations": [r["iterations"] for r in res.reports],
+                   "objectives": [r["objective"] for r in res.reports]},
+        "roofline": _roofline(dom, {dom: fams[dom]}, flops, None),
+        "kernels_ms_per_fit": {f: fams[f][0] / steps for f in fams},
+        "host_seconds": res.seconds,
+        "gpu_evaluations_per_s": n_eval / (res.seconds["mlgst"]),
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = fit_cpu_baseline(fw, ends, evals, mode, args.cpu_seconds)
+    return out
+
+
+def fit_cpu_baseline(fw, ends, evals, mode, seconds):
+    """The oracle on a bounded sample of the fit: its evaluation (parameter map,
+    likelihood with gradient, chain rule) timed on each stage's list, times the
+    evaluations the GPU fit made in that stage, plus its own LGST and gauge
+    optimization; single-threaded."""
+    import oracle
+    from oracle import fit as FT
+    from paper_2008_13490_amd import fit as FIT
+    oracle.build(force=not os.path.exists(oracle.library_path()))
+    print(f"[bench] cpu baseline of the fit (~{seconds:.0f} s)", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    e0 = fw.stage_end[0]
+    r, E, G = FT.lgst(fw.seqs.offsets[:e0 + 1], fw.seqs.gates[:fw.seqs.offsets[e0]], fw.counts[:e0], fw.prep_fids,
+                      fw.meas_fids, 2, 6)
+    FT.gauge_opt(r, E, G, fw.target.rho, fw.target.effects, fw.target.gates)
+    t_lin = time.perf_counter() - t0
+    th = FIT.cptp_start(fw.target.effects, 6, 16) if mode == "cptp" else FT.contract_tp(r, E, G)
+    per_stage = []
+    budget = seconds / len(ends)
+    for e in ends:
+        sub = fw.seqs.subset(np.arange(e))
+        n, t1 = 0, time.perf_counter()
+        while True:
+            FT.nll_in_mode(th, mode, 2, 4, 6, fw.target.gates, sub.offsets, sub.gates, fw.counts[:e])
+            n += 1
+            if time.perf_counter() - t1 >= budget:
+                break
+        per_stage.append((time.perf_counter() - t1) / n)
+    est = t_lin + sum(t * k for t, k in zip(per_stage, evals))
+    return {
+        "value": est,
+        "unit": "s/fit",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": f"oracle LGST + gauge optimization run once ({t_lin:.2f} s); one {mode.upper()} evaluation "
+                  f"timed on each stage's list ({', '.join(f'{t:.3f}' for t in per_stage)} s) and multiplied by "
+                  f"the GPU fit's evaluations per stage ({evals}); one thread",
     }
 
 

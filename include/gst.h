@@ -303,10 +303,12 @@ int gst_param_backward(gst_ctx* ctx, int mode, int n_qubits, int n_outcomes, int
  * from the unit step; a step with some p <= 0 where N > 0 counts as too long),
  * starting from the previous stage's result.  theta: host array of
  * gst_param_count entries, in/out.  reports (optional): one per stage.
- * In the TP parameterization a stage whose start gives some p <= 0 where N > 0
- * (an estimate need not be completely positive) starts instead from it with
- * every gate depolarized (rows 1.. of the transfer matrices times 1 - delta) by
- * the smallest delta in 2^-10, 2^-9, ..., 1/2 that makes the likelihood finite.
+ * A stage whose start gives some p <= 0 where N > 0 starts instead from it moved
+ * inward by the smallest delta in 2^-10, 2^-9, ..., 1/2 that makes the
+ * likelihood finite: TP (an estimate need not be completely positive) with
+ * every gate depolarized (rows 1.. of the transfer matrices times 1 - delta);
+ * CPTP (gates and state are physical, the effects only complete) with the free
+ * effects mixed with the uniform POVM: e_m <- (1 - delta) e_m + delta vec(1)/M.
  * GST_ENONPOS if a stage still starts where some p <= 0 with N > 0 (no direction
  * of descent is defined there); theta then holds that start.
  * Errors pending on the context before the call are returned (gst_sync) and
@@ -323,7 +325,7 @@ typedef struct gst_fit_report {
   int status;        /* 0 tolerance met, 1 iteration limit, 2 the line search found no decrease */
   double objective;  /* F at the stage's result */
   double grad_max;   /* max |dF/dtheta| / sum N there */
-  double shrink;     /* TP: depolarizing applied to the stage's start (0 = none) */
+  double shrink;     /* delta applied to the stage's start (0 = none) */
 } gst_fit_report;
 int gst_lgst(int n_qubits, int n_outcomes, int n_gates, int64_t n_seq, const int64_t* offsets, const uint8_t* gate_idx,
              const int32_t* counts, int n_prep, const int64_t* prep_offsets, const uint8_t* prep_gates, int n_meas,

@@ -25,8 +25,9 @@ Plain definitions with numpy / scipy as the library steps:
 * mlgst: each stage minimizes the negative log-likelihood (the oracle's
   loglik) of its sequences, in the chosen parameterization, with the plain
   L-BFGS below (its line search treats a step into p <= 0, objective +inf, as
-  too long), starting from the previous stage's parameters; in TP, a start
-  with some p <= 0 where N > 0 is first depolarized (feasible_tp_start).  The likelihood is
+  too long), starting from the previous stage's parameters; a start with
+  some p <= 0 where N > 0 is first moved inward (feasible_tp_start: the gates
+  depolarized; feasible_cptp_start: the effects mixed with 1/M).  The likelihood is
   bounded only where every sequence's probabilities sum to one (TP, CPTP).
 """
 from __future__ import annotations
@@ -176,6 +177,23 @@ def mode_is_tp(mode) -> bool:
     return PR.mode_id(mode) == PR.TP
 
 
+def feasible_cptp_start(theta, n: int, M: int, K: int, G0, offsets, gates, counts):
+    """The CPTP start with its free effects mixed with the uniform POVM,
+    e_m <- (1 - delta) e_m + delta vec(1)/M, by the smallest delta in 0, 2^-10,
+    ..., 1/2 whose likelihood is finite (gates and state are physical)."""
+    D = 4 ** n
+    u = np.zeros(D)
+    u[0] = np.sqrt(np.sqrt(D)) / M
+    for delta in [0.0] + [2.0 ** -k for k in range(10, 0, -1)]:
+        th = np.array(theta, np.float64, copy=True)
+        e = th[D:D + (M - 1) * D].reshape(M - 1, D)
+        th[D:D + (M - 1) * D] = ((1.0 - delta) * e + delta * u[None, :]).reshape(-1)
+        F, _ = nll_in_mode(th, "cptp", n, M, K, G0, offsets, gates, counts)
+        if np.isfinite(F):
+            return th, delta
+    raise RuntimeError("no feasible CPTP start")
+
+
 def feasible_tp_start(theta, n: int, M: int, K: int, offsets, gates, counts):
     """The TP start with every gate followed by depolarizing of the smallest
     strength delta in 0, 2^-10, 2^-9, ..., 1/2 (rows 1.. of the transfer matrices
@@ -210,6 +228,8 @@ def mlgst(stages: Sequence[Tuple[np.ndarray, np.ndarray, np.ndarray]], theta0, m
     for off, gts, cnt in stages:
         if mode_is_tp(mode):
             theta, _ = feasible_tp_start(theta, n, M, K, off, gts, cnt)
+        else:
+            theta, _ = feasible_cptp_start(theta, n, M, K, G0, off, gts, cnt)
         scale = 1.0 / max(1.0, float(np.asarray(cnt, np.float64).sum()))
 
         def f(th):

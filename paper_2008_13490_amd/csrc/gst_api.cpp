@@ -1774,14 +1774,25 @@ int gst_mlgst(gst_ctx* ctx, int n_stages, gst_req* const* stages, int mode, cons
     // TP: a start with some p <= 0 where N > 0 (the previous stage's estimate need
     // not be completely positive) is moved inward by depolarizing every gate with
     // the smallest strength 2^-10, 2^-9, ..., 1/2 that makes the likelihood finite
+    // CPTP: gates and state are physical, only the effects (complete, not
+    // constrained positive) can give p < 0; they are mixed with the uniform POVM
+    // 1/M by the smallest such strength instead
     double shrink = 0.0;
-    if (mode == GST_PARAM_TP) {
+    {
       std::vector<double> gtmp((size_t)n), th0(theta, theta + n), trial((size_t)n);
       if (!std::isfinite(f(theta, gtmp.data())) && !err) {
-        const int64_t g0 = (D - 1) + (int64_t)(M - 1) * D;
+        const int64_t g0 = (D - 1) + (int64_t)(M - 1) * D;  // TP: first gate parameter
+        const int64_t e0 = D, e1 = D + (int64_t)(M - 1) * D;  // CPTP: the free effects
+        const double u0 = std::sqrt(std::sqrt((double)D)) / M;  // vec(1)/M, component 0
         for (int k = 10; k >= 1; --k) {
           const double delta = std::ldexp(1.0, -k);
-          for (int64_t i = 0; i < n; ++i) trial[i] = i < g0 ? th0[i] : th0[i] * (1.0 - delta);
+          for (int64_t i = 0; i < n; ++i) {
+            if (mode == GST_PARAM_TP)
+              trial[i] = i < g0 ? th0[i] : th0[i] * (1.0 - delta);
+            else
+              trial[i] = (i >= e0 && i < e1) ? (1.0 - delta) * th0[i] + delta * ((i - e0) % D == 0 ? u0 : 0.0)
+                                             : th0[i];
+          }
           if (std::isfinite(f(trial.data(), gtmp.data()))) {
             std::copy(trial.begin(), trial.end(), theta);
             shrink = delta;
