@@ -175,13 +175,23 @@ def cpu_baseline(name: str, seconds: float, workers: int, param: str = "full"):
 
 # ---------------------------------------------------------------------------
 def kernel_source_hash():
-    """Hash of the device code (kernels and the headers they include); the
-    HBM counters recorded in profiles/ are used only while it is unchanged."""
-    h = hashlib.sha256()
+    """Hash of the device code: the .hip sources and the headers they include
+    (transitively); the HBM counters recorded in profiles/ are used only while
+    it is unchanged.  Host-only sources do not enter it."""
+    import re
     csrc = os.path.join(ROOT, "paper_2008_13490_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
-        if f.endswith((".hip", ".h")):
-            h.update(open(os.path.join(csrc, f), "rb").read())
+    files = {f for f in os.listdir(csrc) if f.endswith(".hip")}
+    todo = sorted(files)
+    while todo:
+        f = todo.pop()
+        for inc in re.findall(r'#include\s+"([^"]+)"', open(os.path.join(csrc, f)).read()):
+            name = os.path.basename(inc)
+            if name not in files and os.path.exists(os.path.join(csrc, name)):
+                files.add(name)
+                todo.append(name)
+    h = hashlib.sha256()
+    for f in sorted(files):
+        h.update(open(os.path.join(csrc, f), "rb").read())
     return h.hexdigest()[:16]
 
 

@@ -96,6 +96,25 @@ def compare_fit(api, ctx, torch, mode, n, M, K, target, sl, ends, counts, prep, 
     return th, reps
 
 
+def test_mlgst_repairs_an_infeasible_cptp_start(gpu):
+    """An effect 1.01 |0><0| gives p = -0.01 on the empty sequence; the stage
+    starts from the effects mixed with the uniform POVM instead, as the oracle's
+    fit does, and the fit proceeds."""
+    api, ctx, torch = gpu
+    from paper_2008_13490_amd.fit import cptp_start, stage_ends
+    truth, target, sl, ends, counts = one_qubit_problem()
+    e = stage_ends(ends)[0]
+    sub = sl.subset(np.arange(e))
+    eff = np.array(target.effects, copy=True)
+    eff[0] *= 1.01
+    th0 = cptp_start(eff, 3, 4, mix=0.0)
+    req = api.Request(ctx, 1, 3, 2, sub.offsets, sub.gates, counts[:e])
+    tg = torch.as_tensor(np.ascontiguousarray(target.gates), device="cuda")
+    th, reps = api.mlgst(ctx, [req], "cptp", th0, tg, max_iter=5)
+    _, delta_o = FT.feasible_cptp_start(th0, 1, 2, 3, target.gates, sub.offsets, sub.gates, counts[:e])
+    assert reps[0]["shrink"] == delta_o > 0 and np.isfinite(reps[0]["objective"])
+
+
 def test_mlgst_one_qubit_tp(gpu):
     api, ctx, torch = gpu
     truth, target, sl, ends, counts = one_qubit_problem()
@@ -169,12 +188,13 @@ def test_mlgst_rejects_full_mode_and_reports_pending_errors(gpu):
         api.mlgst(ctx, [req], "full", np.zeros(4 + 8 + 48))
     with pytest.raises(KeyError):
         api.mlgst(ctx, [req], "nonsense", np.zeros(3))
-    # a start with p <= 0 where N > 0 is reported, not taken for convergence: the
-    # first effect 1.01 |0><0| leaves the completed second one with p = -0.01 on
-    # the empty sequence, whose counts of outcome 1 are positive
+    # a start with p <= 0 where N > 0 that mixing the effects with the uniform POVM
+    # cannot repair is reported, not taken for convergence: the first effect
+    # 3 |0><0| leaves the completed second one with p = -2 on the empty sequence
+    # (counts of outcome 1 positive), still -0.75 after mixing with delta = 1/2
     from paper_2008_13490_amd.fit import cptp_start
     eff = np.array(target.effects, copy=True)
-    eff[0] *= 1.01
+    eff[0] *= 3.0
     th = cptp_start(eff, 3, 4, mix=0.0)
     tg = torch.as_tensor(np.ascontiguousarray(target.gates), device="cuda")
     with pytest.raises(_lib.GSTError) as ei:
