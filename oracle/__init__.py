@@ -8,3 +8,4 @@ from .binding import (  # noqa: F401
 )
 from . import params  # noqa: F401  (parameterizations of the fit)
 from . import fit  # noqa: F401  (LGST, MLGST, gauge optimization)
+from . import metrics  # noqa: F401  (post-fit metrics)
