@@ -337,6 +337,33 @@ int gst_mlgst(gst_ctx* ctx, int n_stages, gst_req* const* stages, int mode, cons
               const gst_fit_options* opt, gst_fit_report* reports);
 
 /*
+ * Post-fit metrics of estimates (host arrays).
+ *
+ * gst_avg_gate_fidelity: for each gate k, the average gate fidelity (thesis Eq.
+ * gatemetricsaveragegatefidelity) of the transfer matrix gates[k] against the
+ * unitary channel with transfer matrix targets[k]: (Tr(T^T R) + N R[0][0]) /
+ * (N (N + 1)), N = 2^n (for R of rho -> M rho M^dagger the closed form Eq.
+ * gatemetricsaveragegatefidelityEvaluation).
+ *
+ * gst_diamond_unitary: diamond distance of the channels of the dim x dim
+ * unitaries U and V (row-major, interleaved real and imaginary parts), App. H
+ * Eq. appdiamondunitaryResult: 1 if the origin lies in the convex hull of the
+ * eigenvalues of U^dagger V, else half their largest distance.
+ *
+ * gst_hamiltonian_decomposition: App. J for the transfer matrix G: h (D entries,
+ * h[0] = 0) of the projection of the real principal logarithm of G onto the
+ * transfer matrices of -i[H, .], H = sum_k h_k P_k / 2 (Eq.
+ * GateDecompositionHamiltonianProjection); angle = |h| (Eq. GSTHamiltonianAngle,
+ * the axis is h / |h|); gamma = ||G - exp(L^H)||_F (Eq.
+ * GateDecompositionHamiltonianProjectionError).  GST_EINVAL where G has no real
+ * principal logarithm (an eigenvalue on the closed negative real axis, e.g. the
+ * ideal CZ).  angle and gamma may be NULL.
+ */
+int gst_avg_gate_fidelity(int n_qubits, int n_gates, const double* gates, const double* targets, double* f_avg);
+int gst_diamond_unitary(int dim, const double* U, const double* V, double* dist);
+int gst_hamiltonian_decomposition(int n_qubits, const double* G, double* h, double* angle, double* gamma);
+
+/*
  * Kernel timing (diagnostics).  While enabled, every kernel the context
  * enqueues is launched with a pair of HIP events on the context's stream that
  * the runtime stamps with the kernel's own start and end (no marker is queued

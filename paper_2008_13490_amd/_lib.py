@@ -25,6 +25,7 @@ EXPORTED = [
     "gst_req_destroy", "gst_req_plan_info", "gst_batch_create", "gst_batch_run", "gst_batch_nonpos",
     "gst_batch_destroy", "gst_tune_set", "gst_set_plan_jump", "gst_predict", "gst_tv_distance",
     "gst_param_count", "gst_param_forward", "gst_param_backward", "gst_lgst", "gst_gauge_optimize", "gst_mlgst",
+    "gst_avg_gate_fidelity", "gst_diamond_unitary", "gst_hamiltonian_decomposition",
     "gst_profile_enable", "gst_profile_only",
     "gst_profile_read", "gst_last_error",
 ]
@@ -109,6 +110,11 @@ def load():
         lib.gst_gauge_optimize.argtypes = [I, I, I, P, P, P, P, P, P, ctypes.c_double, ctypes.c_double, P, P]
         lib.gst_mlgst.argtypes = [P, I, P, I, P, P, ctypes.POINTER(GstFitOptions), P]
         for name in ("gst_lgst", "gst_gauge_optimize", "gst_mlgst"):
+            getattr(lib, name).restype = I
+        lib.gst_avg_gate_fidelity.argtypes = [I, I, P, P, P]
+        lib.gst_diamond_unitary.argtypes = [I, P, P, P]
+        lib.gst_hamiltonian_decomposition.argtypes = [I, P, P, P, P]
+        for name in ("gst_avg_gate_fidelity", "gst_diamond_unitary", "gst_hamiltonian_decomposition"):
             getattr(lib, name).restype = I
         lib.gst_profile_read.restype = I
         if hasattr(lib, "gst_req_create_host"):

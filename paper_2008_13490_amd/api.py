@@ -449,6 +449,42 @@ def contract_tp(rho, E, G):
     return np.concatenate([np.asarray(rho)[1:], np.asarray(E)[:-1].ravel(), np.asarray(G)[:, 1:, :].ravel()])
 
 
+def avg_gate_fidelity(n_qubits: int, gates, targets):
+    """Average gate fidelity of each transfer matrix against its unitary target's
+    transfer matrix (``gst_avg_gate_fidelity``); numpy [K]."""
+    import numpy as np
+    lib = _lib.load()
+    G = np.ascontiguousarray(gates, np.float64)
+    T = np.ascontiguousarray(targets, np.float64)
+    K = G.shape[0]
+    out = np.zeros(K)
+    _lib.check(lib.gst_avg_gate_fidelity(n_qubits, K, G.ctypes.data, T.ctypes.data, out.ctypes.data))
+    return out
+
+
+def diamond_unitary(U, V) -> float:
+    """Diamond distance of the channels of two unitaries (``gst_diamond_unitary``)."""
+    import numpy as np
+    lib = _lib.load()
+    u = np.ascontiguousarray(np.asarray(U, np.complex128)).view(np.float64)
+    v = np.ascontiguousarray(np.asarray(V, np.complex128)).view(np.float64)
+    out = ctypes.c_double(0.0)
+    _lib.check(lib.gst_diamond_unitary(np.asarray(U).shape[0], u.ctypes.data, v.ctypes.data, ctypes.byref(out)))
+    return out.value
+
+
+def hamiltonian_decomposition(n_qubits: int, G):
+    """(h [D], angle |h|, gamma) of a transfer matrix (``gst_hamiltonian_decomposition``)."""
+    import numpy as np
+    lib = _lib.load()
+    g = np.ascontiguousarray(G, np.float64)
+    h = np.zeros(4 ** n_qubits)
+    ang, gam = ctypes.c_double(0.0), ctypes.c_double(0.0)
+    _lib.check(lib.gst_hamiltonian_decomposition(n_qubits, g.ctypes.data, h.ctypes.data, ctypes.byref(ang),
+                                                 ctypes.byref(gam)))
+    return h, ang.value, gam.value
+
+
 def set_plan_jump(ctx: Context, reps: int):
     """Germ-power jump repetitions of the sharing plans of requests created
     afterwards on ``ctx`` (``gst_set_plan_jump``; 0 = off, bit-identical

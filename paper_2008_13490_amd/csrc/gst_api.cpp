@@ -13,6 +13,7 @@
 
 #include "../../include/gst.h"
 #include "gst_fit_core.h"
+#include "gst_metrics.h"
 #include "gst_internal.h"
 #include "gst_plan.h"
 
@@ -1816,5 +1817,42 @@ int gst_mlgst(gst_ctx* ctx, int n_stages, gst_req* const* stages, int mode, cons
   (void)gst_sync(ctx, &dg);  // the counters hold only the fit's own rejected steps
   if (err == GST_ENONPOS) return fail(err, "the starting parameters give p <= 0 where N > 0");
   if (err) return fail(err, "an evaluation failed during the fit");
+  return GST_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Post-fit metrics
+// ---------------------------------------------------------------------------
+int gst_avg_gate_fidelity(int n_qubits, int n_gates, const double* gates, const double* targets, double* f_avg) {
+  const int D = dim_of(n_qubits);
+  if (!D || n_gates < 1) return fail(GST_EINVAL, "sizes out of range");
+  if (!gates || !targets || !f_avg) return fail(GST_EINVAL, "NULL argument");
+  for (int k = 0; k < n_gates; ++k)
+    f_avg[k] = gst::avg_gate_fidelity(D, gates + (size_t)k * D * D, targets + (size_t)k * D * D);
+  return GST_OK;
+}
+
+int gst_diamond_unitary(int dim, const double* U, const double* V, double* dist) {
+  if (dim < 1 || dim > 64) return fail(GST_EINVAL, "dim must be in 1..64");
+  if (!U || !V || !dist) return fail(GST_EINVAL, "NULL argument");
+  const double d = gst::diamond_unitary(dim, U, V);
+  if (d < 0) return fail(GST_EINVAL, "the eigenvalues of U^dagger V did not converge");
+  *dist = d;
+  return GST_OK;
+}
+
+int gst_hamiltonian_decomposition(int n_qubits, const double* G, double* h, double* angle, double* gamma) {
+  const int D = dim_of(n_qubits);
+  if (!D) return fail(GST_EINVAL, "n_qubits must be 1, 2 or 3");
+  if (!G || !h) return fail(GST_EINVAL, "NULL argument");
+  double g = 0.0;
+  if (gst::hamiltonian_decomposition(n_qubits, G, h, &g))
+    return fail(GST_EINVAL, "no real principal logarithm (an eigenvalue on the closed negative real axis)");
+  if (gamma) *gamma = g;
+  if (angle) {
+    double s = 0.0;
+    for (int k = 0; k < D; ++k) s += h[k] * h[k];
+    *angle = std::sqrt(s);
+  }
   return GST_OK;
 }

@@ -1,0 +1,75 @@
+"""The library's post-fit metrics (host code through the C ABI, no GPU needed)
+against the oracle's: the average gate fidelity (transfer-matrix formula vs
+the 2-design average), the unitary diamond distance (Jacobi eigenvalues of a
+Hermitian combination vs numpy's), and the Hamiltonian decomposition
+(inverse scaling and squaring logarithm vs scipy's logm)."""
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+from oracle import metrics as MT
+from oracle import params as PR
+from paper_2008_13490_amd import workloads as W
+
+
+@pytest.fixture(scope="module")
+def api():
+    from paper_2008_13490_amd import api as A
+    A._lib.load()
+    return A
+
+
+def haar(d, rng):
+    Z = rng.normal(size=(d, d)) + 1j * rng.normal(size=(d, d))
+    Q, R = np.linalg.qr(Z)
+    return Q * (np.diag(R) / np.abs(np.diag(R)))
+
+
+@pytest.mark.parametrize("kind", ["1q", "2q"])
+def test_avg_gate_fidelity(api, kind):
+    rng = np.random.default_rng(1)
+    gs = W.noisy_gateset(kind, 2e-3, 0.03, rng)
+    _, Us, n = W.ideal_unitaries(kind)
+    T = np.array([W.ptm_from_unitary(U) for U in Us])
+    f = api.avg_gate_fidelity(n, gs.gates, T)
+    want = np.array([MT.avg_gate_fidelity(g, U) for g, U in zip(gs.gates, Us)])
+    assert np.abs(f - want).max() <= 1e-13
+    M = haar(2 ** n, rng) * 0.9            # a trace-decreasing single-operator map
+    f1 = api.avg_gate_fidelity(n, W.ptm_from_kraus([M])[None], T[:1])[0]
+    assert abs(f1 - MT.avg_gate_fidelity(W.ptm_from_kraus([M]), Us[0])) <= 1e-13
+
+
+def test_diamond_unitary(api):
+    rng = np.random.default_rng(2)
+    for d in (2, 4, 8):
+        for scale in (0.05, 0.5, 2.0):
+            U = haar(d, rng)
+            H = rng.normal(size=(d, d)) + 1j * rng.normal(size=(d, d))
+            V = U @ sla.expm(-1j * scale * (H + H.conj().T) / 2)
+            assert abs(api.diamond_unitary(U, V) - MT.diamond_unitary(U, V)) <= 1e-12
+    assert api.diamond_unitary(np.eye(4), np.diag([1, 1, 1, -1])) == 1.0
+    assert abs(api.diamond_unitary(np.eye(2), np.eye(2))) <= 1e-15
+
+
+@pytest.mark.parametrize("n", [1, 2])
+def test_hamiltonian_decomposition(api, n):
+    rng = np.random.default_rng(3)
+    D = 4 ** n
+    P = PR.paulis(n)
+    for noise in (0.0, 0.02):
+        h = np.zeros(D)
+        h[1:] = rng.normal(size=D - 1) * 0.5
+        G = W.ptm_from_unitary(sla.expm(-1j * np.einsum("k,kxy->xy", h, P) / 2))
+        if noise:
+            G = W.depolarizing_ptm(noise, n) @ G
+        hh, ang, gam = api.hamiltonian_decomposition(n, G)
+        h_o, g_o, a_o, _ = MT.hamiltonian_decomposition(G)
+        assert np.abs(hh - h_o).max() <= 1e-10 and abs(gam - g_o) <= 1e-10 and abs(ang - a_o) <= 1e-10
+    # the ideal X(pi/2) on one qubit: angle pi/2 about x
+    Ux = W.ideal_unitaries("1q")[1][1]
+    hh, ang, gam = api.hamiltonian_decomposition(1, W.ptm_from_unitary(Ux))
+    assert abs(ang - np.pi / 2) <= 1e-12 and abs(hh[1] - np.pi / 2) <= 1e-12 and gam <= 1e-12
+    # the ideal CZ has eigenvalues -1: no real principal logarithm
+    from paper_2008_13490_amd import _lib
+    with pytest.raises(_lib.GSTError):
+        api.hamiltonian_decomposition(2, W.ptm_from_unitary(W.cz(0, 1, 2)))
