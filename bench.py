@@ -712,9 +712,36 @@ def run_fit_bench(args):
         "host_seconds": res.seconds,
         "gpu_evaluations_per_s": n_eval / (res.seconds["mlgst"]),
     }
+    out["estimate_metrics"] = fit_metrics(api, fw, res)
     if not args.no_cpu:
         out["cpu_baseline"] = fit_cpu_baseline(fw, ends, evals, mode, args.cpu_seconds)
     return out
+
+
+def fit_metrics(api, fw, res):
+    """Post-fit metrics of the gauge-optimized estimate (thesis Sec. 6.3.3, App. J):
+    per gate the average gate fidelity against the ideal gate, the Hamiltonian
+    decomposition (rotation angle, decomposition error) where the transfer matrix
+    has a real principal logarithm, and the diamond distance between the ideal
+    unitary and the decomposition's exp(-iH)."""
+    import scipy.linalg as sla   # builds exp(-iH) of the reported h for the distance only
+    from paper_2008_13490_amd import _lib
+    t0 = time.perf_counter()
+    f = api.avg_gate_fidelity(2, res.gates, fw.target.gates)
+    P = [np.kron(a, b) for a in _PAULI1 for b in _PAULI1]
+    per = {}
+    for k, name in enumerate(fw.target.names):
+        row = {"avg_gate_fidelity": float(f[k])}
+        try:
+            h, ang, gam = api.hamiltonian_decomposition(2, res.gates[k])
+            U_eff = sla.expm(-1j * sum(h[i] * P[i] for i in range(16)) / 2)
+            row.update(angle=ang, decomposition_error=gam,
+                       diamond_to_ideal=api.diamond_unitary(fw.target.unitaries[k], U_eff))
+        except _lib.GSTError:
+            row["decomposition"] = "no real principal logarithm"
+        per[name] = row
+    return {"gates": per, "seconds": time.perf_counter() - t0}
+
 
 
 def fit_cpu_baseline(fw, ends, evals, mode, seconds):
@@ -755,6 +782,10 @@ def fit_cpu_baseline(fw, ends, evals, mode, seconds):
                   f"timed on each stage's list ({', '.join(f'{t:.3f}' for t in per_stage)} s) and multiplied by "
                   f"the GPU fit's evaluations per stage ({evals}); one thread",
     }
+
+
+_PAULI1 = (np.eye(2, dtype=complex), np.array([[0, 1], [1, 0]], dtype=complex),
+           np.array([[0, -1j], [1j, 0]]), np.array([[1, 0], [0, -1]], dtype=complex))
 
 
 def predict_flops(family, D, M, prep_lens, n_gates, r_max, B=32):
