@@ -292,7 +292,8 @@ int gst_param_backward(gst_ctx* ctx, int mode, int n_qubits, int n_outcomes, int
  * + sum_m ||X^-T e_m - e_T,m||^2) over X (L-BFGS until the largest gradient
  * entry is <= gtol) from the least-squares solution of the same relations
  * multiplied through by X (X G_k = T_k X, X rho = rho_T, X^T e_T,m = e_m: linear in
- * X), and applies X to rho, effects and gates in place
+ * X), and applies X to rho, effects and gates in place (one or two qubits: the
+ * linear start solves D^2 normal equations)
  * (host arrays); optional outputs: X (row-major D x D) and the objective.
  *
  * gst_mlgst: iterative MLGST on the GPU.  For each stage (resident requests of

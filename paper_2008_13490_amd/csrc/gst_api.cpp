@@ -1664,7 +1664,7 @@ int gst_gauge_optimize(int n_qubits, int n_outcomes, int n_gates, double* rho, d
                        const double* target_rho, const double* target_effects, const double* target_gates,
                        double spam_weight, double gtol, double* gauge, double* objective) {
   const int D = dim_of(n_qubits);
-  if (!D) return fail(GST_EINVAL, "n_qubits must be 1, 2 or 3");
+  if (!D || n_qubits > 2) return fail(GST_EINVAL, "gauge optimization takes one or two qubits");
   if (n_outcomes < 1 || n_gates < 1 || !(spam_weight >= 0.0) || !(gtol > 0.0)) return fail(GST_EINVAL, "bad argument");
   if (!rho || !effects || !gates || !target_rho || !target_effects || !target_gates) return fail(GST_EINVAL, "NULL argument");
   const int M = n_outcomes, K = n_gates;

@@ -42,3 +42,11 @@ def test_gauge_optimize_entry(api):
     # after fixing the gauge the LGST estimate (1000 shots per sequence) is near the
     # truth on average; before, in the gauge of the singular vectors, it is not
     assert np.abs(G2 - fw.truth.gates).mean() < 0.05 < 0.1 < np.abs(G - fw.truth.gates).mean()
+
+
+def test_gauge_optimize_rejects_three_qubits(api):
+    from paper_2008_13490_amd import _lib
+    D = 64
+    with pytest.raises(_lib.GSTError):
+        api.gauge_optimize(3, np.zeros(D), np.zeros((8, D)), np.zeros((5, D, D)), np.zeros(D), np.zeros((8, D)),
+                           np.zeros((5, D, D)))
