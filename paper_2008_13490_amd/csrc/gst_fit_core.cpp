@@ -102,6 +102,34 @@ bool invert(int n, const double* A, double* Ai) {
   return true;
 }
 
+bool solve(int n, const double* A, const double* b, double* x) {
+  std::vector<double> L(A, A + (size_t)n * n), y(b, b + n);
+  for (int k = 0; k < n; ++k) {
+    int p = k;
+    for (int r = k + 1; r < n; ++r)
+      if (fabs(L[(size_t)r * n + k]) > fabs(L[(size_t)p * n + k])) p = r;
+    if (L[(size_t)p * n + k] == 0.0) return false;
+    if (p != k) {
+      for (int c = 0; c < n; ++c) std::swap(L[(size_t)p * n + c], L[(size_t)k * n + c]);
+      std::swap(y[p], y[k]);
+    }
+    const double* rk = &L[(size_t)k * n];
+    for (int r = k + 1; r < n; ++r) {
+      double* rr = &L[(size_t)r * n];
+      const double f = rr[k] / rk[k];
+      if (f == 0.0) continue;
+      for (int c = k + 1; c < n; ++c) rr[c] -= f * rk[c];
+      y[r] -= f * y[k];
+    }
+  }
+  for (int i = n - 1; i >= 0; --i) {
+    double v = y[i];
+    for (int c = i + 1; c < n; ++c) v -= L[(size_t)i * n + c] * x[c];
+    x[i] = v / L[(size_t)i * n + i];
+  }
+  return true;
+}
+
 int lgst_matrices(int64_t S, const int64_t* offsets, const uint8_t* gates, const int32_t* counts, int M, int K,
                   int n_prep, const int64_t* prep_off, const uint8_t* prep_gates, int n_meas, const int64_t* meas_off,
                   const uint8_t* meas_gates, std::vector<double>* AB, std::vector<double>* Bk, int* j0, int* i0) {
@@ -210,13 +238,18 @@ int lgst_estimate(int D, int M, int K, int n_prep, int n_meas, const double* AB,
 
 namespace {
 // C = A B (n x n row-major)
+// i-k-j order: each C[i][j] still accumulates k in ascending order, and the
+// inner loop runs over contiguous rows
 void mm(int n, const double* A, const double* B, double* C) {
-  for (int i = 0; i < n; ++i)
-    for (int j = 0; j < n; ++j) {
-      double s = 0.0;
-      for (int k = 0; k < n; ++k) s += A[(size_t)i * n + k] * B[(size_t)k * n + j];
-      C[(size_t)i * n + j] = s;
+  for (int i = 0; i < n; ++i) {
+    double* c = C + (size_t)i * n;
+    for (int j = 0; j < n; ++j) c[j] = 0.0;
+    for (int k = 0; k < n; ++k) {
+      const double a = A[(size_t)i * n + k];
+      const double* b = B + (size_t)k * n;
+      for (int j = 0; j < n; ++j) c[j] += a * b[j];
     }
+  }
 }
 void transpose(int n, const double* A, double* At) {
   for (int i = 0; i < n; ++i)
@@ -284,7 +317,7 @@ double gauge_objective(int D, int M, int K, const double* X, const double* rho, 
 bool gauge_linear_start(int D, int M, int K, const double* rho, const double* E, const double* G, const double* rT,
                         const double* ET, const double* GT, double w, double* X) {
   const int n = D * D;
-  std::vector<double> N((size_t)n * n, 0.0), rhs(n, 0.0), Ni((size_t)n * n);
+  std::vector<double> N((size_t)n * n, 0.0), rhs(n, 0.0);
   std::vector<int> idx;
   std::vector<double> val;
   // adds the row (idx, val) with right-hand side b to the normal equations
@@ -331,13 +364,7 @@ bool gauge_linear_start(int D, int M, int K, const double* rho, const double* E,
       }
       add_row(sw * E[(size_t)m * D + j]);
     }
-  if (!invert(n, N.data(), Ni.data())) return false;
-  for (int i = 0; i < n; ++i) {
-    double s = 0.0;
-    for (int j = 0; j < n; ++j) s += Ni[(size_t)i * n + j] * rhs[j];
-    X[i] = s;
-  }
-  return true;
+  return solve(n, N.data(), rhs.data(), X);
 }
 
 LbfgsResult lbfgs(int n, double* x, const std::function<double(const double*, double*)>& f, int m, double gtol,

@@ -18,6 +18,9 @@ bool svd_jacobi(int m, int n, const double* A, double* U, double* S, double* V);
 // a pivot is zero.
 bool invert(int n, const double* A, double* Ai);
 
+// x = A^-1 b by LU with partial pivoting (row-major A); false if a pivot is zero.
+bool solve(int n, const double* A, const double* b, double* x);
+
 // The bare-experiment frequency matrices of LGST, found by word in the list:
 // AB [M n_meas][n_prep] (row J + M i: outcome J after measurement fiducial i),
 // Bk [K][M n_meas][n_prep] with gate k between the fiducials (time order: the

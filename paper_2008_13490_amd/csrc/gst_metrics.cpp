@@ -65,13 +65,18 @@ bool jacobi_sym(int n, std::vector<double>& A, std::vector<double>& V) {
   return false;
 }
 
+// i-k-j order: each C[i][j] still accumulates k in ascending order, and the
+// inner loop runs over contiguous rows
 void mm(int n, const double* A, const double* B, double* C) {
-  for (int i = 0; i < n; ++i)
-    for (int j = 0; j < n; ++j) {
-      double s = 0.0;
-      for (int k = 0; k < n; ++k) s += A[(size_t)i * n + k] * B[(size_t)k * n + j];
-      C[(size_t)i * n + j] = s;
+  for (int i = 0; i < n; ++i) {
+    double* c = C + (size_t)i * n;
+    for (int j = 0; j < n; ++j) c[j] = 0.0;
+    for (int k = 0; k < n; ++k) {
+      const double a = A[(size_t)i * n + k];
+      const double* b = B + (size_t)k * n;
+      for (int j = 0; j < n; ++j) c[j] += a * b[j];
     }
+  }
 }
 
 double fro(int n, const double* A) {
