@@ -164,7 +164,8 @@ int gst_req_plan_info(const gst_req* req, int64_t* info, int n);
  * alone or in any batch.  Requests with a plan run their own launch sequence
  * after the batched launch.
  *
- * gst_batch_create fixes the requests, the gate sets (device pointers whose
+ * gst_batch_create fixes the requests (each at most once: GST_EINVAL
+ * otherwise), the gate sets (device pointers whose
  * contents may change between runs) and the output pointers; any of probs,
  * objectives, grads may be NULL or hold NULL entries (an objective is needed
  * for a gradient).  capture_graph != 0 records the batched launch sequence

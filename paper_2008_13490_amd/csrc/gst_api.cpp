@@ -298,6 +298,7 @@ struct gst_batch {
   int n_tiles[6] = {0, 0, 0, 0, 0, 0}, grid_of[6] = {0, 0, 0, 0, 0, 0};
   gst::BatchLaunch launch[6] = {};
   int n_items = 0, kmax = 1;
+  int red_chunks = 0;                   // most chunks of the tile-slab sum over the requests
   int64_t max_len = 0;
   DevBuf desc;
   gst::BatchReduce red{};
@@ -1255,7 +1256,7 @@ static int run_tiles(gst_req* r, const gst_gateset* th, int mode, const double* 
     red.one.objective = objective;
     red.one.grad = grad;
     red.req_nonpos = l.req_nonpos;
-    HIP_TRY(gst::launch_batch_reduce(red, (int)((red.one.P + 63) / 64), ctx->stream));
+    HIP_TRY(gst::launch_batch_reduce(red, (int)((red.one.P + 63) / 64), gst::batch_reduce_chunks(nt), ctx->stream));
   }
   return GST_OK;
 }
@@ -1381,7 +1382,7 @@ static int batch_enqueue(gst_batch* b, hipStream_t stream, bool eager) {
   }
   if (b->n_items > 0) {
     ProfScope ps(pc, FAM_TILES_RED);
-    HIP_TRY(gst::launch_batch_reduce(b->red, b->n_items, stream));
+    HIP_TRY(gst::launch_batch_reduce(b->red, b->n_items, b->red_chunks, stream));
   }
   return GST_OK;
 }
@@ -1399,6 +1400,9 @@ int gst_batch_create(gst_ctx* ctx, int n, gst_req* const* reqs, const gst_gatese
   for (int x = 0; x < n; ++x) {
     gst_req* r = reqs[x];
     if (!r || r->ctx != ctx) return fail(GST_EINVAL, "request missing or from another context");
+    // a request's partial sums and workspace are its own: it can run once per launch
+    if (std::find(b->reqs.begin(), b->reqs.end(), r) != b->reqs.end())
+      return fail(GST_EINVAL, "request listed twice in one batch");
     int D = 0;
     int rc = check_gateset(&thetas[x], &D);
     if (rc) return rc;
@@ -1447,6 +1451,7 @@ int gst_batch_create(gst_ctx* ctx, int n, gst_req* const* reqs, const gst_gatese
     }
     if (ob) {
       const int64_t P = gst::slab_width(D, r->M, r->K);
+      b->red_chunks = std::max(b->red_chunks, gst::batch_reduce_chunks(r->n_tiles()));
       for (int64_t c0 = 0; c0 < P; c0 += 64) {
         gst::BatchReduceItem it{};
         it.req = x;

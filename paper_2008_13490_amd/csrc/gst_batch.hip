@@ -214,22 +214,55 @@ __global__ void queue_reset_kernel(unsigned* q, unsigned long long* req_nonpos, 
   for (int r = t; r < n_req; r += gridDim.x * blockDim.x) req_nonpos[r] = 0ull;
 }
 
-// For every request: the sum of its tile slabs in tile order (four
-// interleaved partial sums combined in a fixed order).
-__global__ __launch_bounds__(256) void batch_reduce_kernel(const BatchReduce a) {
+// For every request: the sum of its tile slabs, in two stages whose order
+// depends on the request's own tile count only, so that its sums are the same
+// alone and in any batch.  Stage 1: block (item, c) adds the rows of chunk c
+// (tiles [c R, c R + R)) over the item's 64 columns, as four interleaved
+// partial sums combined in a fixed order, and stores the chunk sum over the
+// chunk's first row (every read of that row is done before the barrier).
+// Stage 2: the chunk sums in ascending c, the same way.  Many chunks per
+// column block keep enough loads in flight to fill the chip; a single pass
+// over all rows leaves a request of P columns with only P / 64 workgroups.
+constexpr int RED_CHUNK = 32;
+
+__device__ inline BatchReduceItem reduce_item(const BatchReduce& a, int b) {
+  if (a.items) return a.items[b];
+  BatchReduceItem it = a.one;
+  it.col0 = (int64_t)b * 64;
+  return it;
+}
+
+__global__ __launch_bounds__(256) void batch_reduce_chunks_kernel(const BatchReduce a) {
   __shared__ double red[4][64];
   const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-  BatchReduceItem it;
-  if (a.items) {
-    it = a.items[blockIdx.x];
-  } else {
-    it = a.one;
-    it.col0 = (int64_t)blockIdx.x * 64;
+  const BatchReduceItem it = reduce_item(a, blockIdx.x);
+  const int64_t x = it.col0 + tx;
+  for (int c = blockIdx.y; (int64_t)c * RED_CHUNK < it.n_tiles; c += gridDim.y) {  // uniform over the block
+    const int t0 = c * RED_CHUNK, t1 = min(it.n_tiles, t0 + RED_CHUNK);
+    double v = 0.0;
+    if (x < it.P) {
+#pragma unroll
+      for (int j = 0; j < RED_CHUNK / 4; ++j) {
+        const int t = t0 + ty + 4 * j;
+        if (t < t1) v += it.slab[(int64_t)t * it.P + x];
+      }
+    }
+    red[ty][tx] = v;
+    __syncthreads();
+    if (ty == 0 && x < it.P) it.slab[(int64_t)t0 * it.P + x] = (red[0][tx] + red[1][tx]) + (red[2][tx] + red[3][tx]);
+    __syncthreads();
   }
+}
+
+__global__ __launch_bounds__(256) void batch_reduce_final_kernel(const BatchReduce a) {
+  __shared__ double red[4][64];
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  const BatchReduceItem it = reduce_item(a, blockIdx.x);
+  const int n_chunks = (it.n_tiles + RED_CHUNK - 1) / RED_CHUNK;
   const int64_t x = it.col0 + tx;
   double v = 0.0;
   if (x < it.P)
-    for (int t = ty; t < it.n_tiles; t += 4) v += it.slab[(int64_t)t * it.P + x];
+    for (int c = ty; c < n_chunks; c += 4) v += it.slab[(int64_t)c * RED_CHUNK * it.P + x];
   red[ty][tx] = v;
   __syncthreads();
   if (ty != 0 || x >= it.P) return;
@@ -273,9 +306,14 @@ hipError_t launch_queue_reset(unsigned* q, unsigned long long* req_nonpos, int n
   return hipGetLastError();
 }
 
-hipError_t launch_batch_reduce(const BatchReduce& a, int n_items, hipStream_t stream) {
+int batch_reduce_chunks(int64_t n_tiles) { return (int)((n_tiles + RED_CHUNK - 1) / RED_CHUNK); }
+
+hipError_t launch_batch_reduce(const BatchReduce& a, int n_items, int max_chunks, hipStream_t stream) {
   if (n_items <= 0) return hipSuccess;
-  gst_launch(batch_reduce_kernel, dim3(n_items), dim3(256), 0, stream, a);
+  if (max_chunks > 0)
+    gst_launch(batch_reduce_chunks_kernel, dim3(n_items, max_chunks < 65535 ? max_chunks : 65535), dim3(256), 0,
+               stream, a);
+  gst_launch(batch_reduce_final_kernel, dim3(n_items), dim3(256), 0, stream, a);
   return hipGetLastError();
 }
 

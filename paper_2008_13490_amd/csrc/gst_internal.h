@@ -198,7 +198,7 @@ struct BatchReduceItem {
   int n_tiles;
   int64_t P;
   int64_t col0;
-  const double* slab;
+  double* slab;  // [n_tiles][P]; stage 1 leaves the chunk sums in the first row of each chunk
   double* objective;
   double* grad;
 };
@@ -219,7 +219,10 @@ hipError_t launch_lane1q(const BatchLaunch& a, int K, int n_blocks, hipStream_t 
 int batch_blocks_per_cu(int D, int kmax);
 hipError_t launch_batch(const BatchLaunch& a, int n_blocks, hipStream_t stream);
 hipError_t launch_queue_reset(unsigned* q, unsigned long long* req_nonpos, int n_req, hipStream_t stream);
-hipError_t launch_batch_reduce(const BatchReduce& a, int n_items, hipStream_t stream);
+// Chunks of the two-stage tile-slab sum for a request of n_tiles tiles; the
+// launch takes the largest over its items.
+int batch_reduce_chunks(int64_t n_tiles);
+hipError_t launch_batch_reduce(const BatchReduce& a, int n_items, int max_chunks, hipStream_t stream);
 
 // Three-qubit gate sets (D = 64): one chain per wave, the gate set in LDS,
 // per-step records for the gate gradient (see gst_kernels64.hip).

@@ -12,6 +12,7 @@ import sys
 import numpy as np
 import pytest
 
+from paper_2008_13490_amd import _lib
 from paper_2008_13490_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
@@ -247,3 +248,39 @@ def test_tile_policy(oracle_lib, gpu):
         b.close()
     api.tune_set(ctx, 2, 0, 0)
     api.tune_set(ctx, 1, 0, 0)
+
+
+def test_tile_sums_across_chunk_edges(oracle_lib, gpu):
+    """The tile partial sums are added in chunks of 32 tiles and then over the
+    chunks: lists of 1, 32, 33 (one tile past a chunk) and 65 tiles (the last
+    tile ragged) against the oracle, and the same requests in one batch equal
+    to their standalone results bit for bit."""
+    api, ctx = gpu
+    api.tune_set(ctx, 2, 16, 0)  # 16 sequences per tile: the tile counts below are exact
+    try:
+        mix, reqs, thetas = [], [], []
+        for nt, short in ((1, 0), (32, 0), (33, 0), (65, 5)):
+            w = W.random_workload("2q", 16 * nt - short, 24, 100 + nt)
+            r = api.Request(ctx, 2, w.model.K, w.model.M, w.seqs.offsets, w.seqs.gates, w.counts)
+            assert r.plan_info()["plan_used"] == 0
+            mix.append((w.name, w.model, w.seqs, w.counts))
+            reqs.append(r)
+            thetas.append(api.DeviceGateSet.from_numpy(2, w.model.rho, w.model.effects, w.model.gates))
+        ref = _standalone(ctx, reqs, thetas)
+        for (label, gs, sl, counts), (o, p, g) in zip(mix, ref):
+            say(f"[batch] chunk edges: {label}")
+            F, p_or, g_or, _, _ = oracle_lib.loglik(gs.rho, gs.effects, gs.gates, sl.offsets, sl.gates, counts)
+            assert np.array_equal(p.cpu().numpy(), p_or), label
+            assert abs(float(o.cpu()[0]) - F) <= 1e-10 * abs(F), label
+            assert np.abs(g.cpu().numpy() - g_or).max() <= 1e-10 * np.abs(g_or).max(), label
+        b = api.Batch(ctx, reqs[::-1], thetas[::-1], want_probs=True, want_grad=True)
+        b.run()
+        ctx.sync()
+        _assert_same(b, ref[::-1], [m[0] for m in mix[::-1]])
+        b.close()
+        with pytest.raises(_lib.GSTError, match="twice"):
+            api.Batch(ctx, [reqs[0], reqs[1], reqs[0]], [thetas[0], thetas[1], thetas[0]], want_grad=True)
+        for r in reqs:
+            r.close()
+    finally:
+        api.tune_set(ctx, 2)
