@@ -8,7 +8,11 @@ its gradient with respect to every entry of rho, the effects and the gates
 set is new every step, as in the iterations of a fit).  Inputs are resident in
 HBM before the timed region starts.
 
-Prints one JSON line (see the design doc for the fields).
+Prints one JSON line: metric, value, unit, timing, the workload, the roofline
+of the dominant kernel family (algorithmic work per launch over its average
+launch time, against the FP64 vector peak, with the HBM bytes per launch from
+the committed counter file while the device sources are unchanged) and the
+oracle's throughput on the host cores.
 """
 from __future__ import annotations
 
@@ -242,9 +246,8 @@ def main():
         copy_calibration(args.copy_calibration)
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build measures one GPU only; the path shards by sequence and "
-                                   "all-reduces the gradient (see DESIGN.md), but no multi-GPU run is part "
-                                   "of it", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "one GPU only: the path would shard by sequence and all-reduce the "
+                                   "gradient, but it has no multi-GPU run", "n_gpus": args.gpus}))
         sys.exit(2)
 
     if args.workload == "f2":
