@@ -577,7 +577,12 @@ int run_plan(gst_req* r, const gst_gateset* th, int mode, const double* w, doubl
   // workgroups; one D x D tile per gradient chunk
   const int64_t H = gst::slab_width(D, r->M, 0);
   const int64_t Pw = want_grad ? gst::slab_width(D, r->M, r->K) : H;
-  const int item_blocks = gst::item_blocks_for(P.n_items());
+  // the item and fill workgroups of the launch within one round of resident
+  // workgroups: past that the waves take several groups of items each, where
+  // a second round of workgroups would start only as the first ends
+  const int64_t resident = (int64_t)ctx->n_cu * gst::item_blocks_per_cu(D, r->K);
+  const int64_t fill_blocks = want_grad && P.n_fill() > 0 ? gst::fill_blocks_for(P.n_fill()) : 0;
+  const int item_blocks = gst::item_blocks_for(P.n_items(), std::max<int64_t>(resident - fill_blocks, resident / 2));
   std::vector<int> tb_blocks(P.n_levels), tb_at(P.n_levels);
   int n_head = need_slab ? item_blocks : 0;
   for (int l = 0; l < P.n_levels; ++l) {

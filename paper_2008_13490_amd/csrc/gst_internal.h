@@ -275,7 +275,12 @@ hipError_t launch_reduce64(const Reduce64Launch& a, hipStream_t stream);
 hipError_t launch_trunk_fwd(const PlanArgs& a, hipStream_t stream);
 hipError_t launch_trunk_bwd(const PlanArgs& a, hipStream_t stream);
 hipError_t launch_items(const PlanArgs& a, int n_blocks, hipStream_t stream);
-int item_blocks_for(int64_t n_items);
+// Workgroups of the item launch: one per 16 items, at most max_blocks (> 0);
+// item_blocks_per_cu is the kernel's occupancy.  The launch adds
+// fill_blocks_for(n_fill) workgroups of forward fill tasks when it has them.
+int item_blocks_for(int64_t n_items, int64_t max_blocks);
+int item_blocks_per_cu(int D, int K);
+int fill_blocks_for(int64_t n_fill);
 int trunk_blocks_for(int64_t n_trunks);
 hipError_t launch_inject(const InjectLaunch& a, hipStream_t stream);
 hipError_t launch_grad_gemm(const GemmLaunch& a, hipStream_t stream);

@@ -198,6 +198,9 @@ __global__ __launch_bounds__(256) void item_kernel(const PlanArgs a) {
       anc = it[3];
       isp = a.item_step_ptr[q];
     }
+    // the counts of the readout are loaded now, with the anchor state, not after it
+    int32_t Nq = 0;
+    if (a.mode == MODE_LOGLIK) Nq = a.counts[(has && i < M) ? seq * M + i : 0];
     const int L = (int)(end - beg);
     const int Lw = wave_max4(L);
     const uint8_t* word = a.gates + beg;
@@ -228,7 +231,7 @@ __global__ __launch_bounds__(256) void item_kernel(const PlanArgs a) {
       const int64_t o = seq * M + i;
       if (a.probs) a.probs[o] = p;
       if (a.mode == MODE_LOGLIK) {
-        const int32_t N = a.counts[o];
+        const int32_t N = Nq;
         if (N > 0) {
           if (p <= 0.0) {
             ++nonpos;
@@ -592,10 +595,18 @@ int fill_blocks_for(int64_t n_fill) {
   return (int)(b < 1 ? 1 : (b > 1024 ? 1024 : b));
 }
 
-int item_blocks_for(int64_t n_items) {
+int item_blocks_per_cu(int D, int K) {
+  int n = 0;
+  const size_t bytes = item_lds_bytes(K);
+  const hipError_t e = D == 16 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, item_kernel<16>, 256, bytes)
+                               : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, item_kernel<4>, 256, bytes);
+  return (e == hipSuccess && n > 0) ? n : 1;
+}
+
+int item_blocks_for(int64_t n_items, int64_t max_blocks) {
   int64_t b = (n_items + WAVES * TPW - 1) / (WAVES * TPW);
   if (b < 1) b = 1;
-  if (b > 1024) b = 1024;  // four resident workgroups per CU
+  if (max_blocks > 0 && b > max_blocks) b = max_blocks;  // the waves then take several groups each
   return (int)b;
 }
 
