@@ -422,7 +422,18 @@ def run_structured(args):
         step()
     ctx.sync()
     brk = _profile(api, ctx, families)
-    dom = max(brk, key=lambda f: brk[f][0])
+    # the roofline is priced on the FP64 work of the longest family that has
+    # arithmetic (the ordered sums and the injection gather carry none)
+    D, M, S = m.D, m.M, w.seqs.S
+    L = w.seqs.lengths()
+    info = req_plan_info(req) if args.path == "resident" else None
+
+    def fam_flops(f):
+        return (param_flops(f, D, m.K) if f.startswith("param_")
+                else algorithmic_flops(f, D, M, S, int(L.sum()), info))
+
+    work = [f for f in brk if fam_flops(f) > 0] or list(brk)
+    dom = max(work, key=lambda f: brk[f][0])
     # timed region: events around the dominant family only
     api.profile_only(ctx, dom)
     torch.cuda.synchronize()
@@ -437,15 +448,8 @@ def run_structured(args):
     api.profile_enable(ctx, False)
     fams = {dom: (tot[dom][0] - brk[dom][0], tot[dom][1] - brk[dom][1])}
     elapsed = t1 - t0
-    S = w.seqs.S
     value = S * args.steps / elapsed
-
-    # dominant kernel and its algorithmic FP64 work per launch
-    D, M = m.D, m.M
-    L = w.seqs.lengths()
-    info = req_plan_info(req) if args.path == "resident" else None
-    flops = (param_flops(dom, D, m.K) if dom.startswith("param_")
-             else algorithmic_flops(dom, D, M, S, int(L.sum()), info))
+    flops = fam_flops(dom)  # algorithmic FP64 work per launch of the dominant family
     steps_eval = (info["trunk_steps"] + info["item_steps"]) if info else int(L.sum())
     return {
         "metric": METRIC,
