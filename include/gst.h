@@ -97,8 +97,10 @@ typedef struct gst_diag {
   int64_t n_nonpos;     /* entries with p <= 0 and N > 0 */
 } gst_diag;
 
-/* Largest K supported for a qubit count (register budget of the on-chip
-   gradient accumulation). */
+/* Largest K supported for a qubit count: 8 for one and two qubits (the
+   on-chip gradient tiles of the tile kernels), 5 for three (the gate set of
+   the per-sequence kernel fills the 160 KB of LDS of a CU); 0 for other qubit
+   counts.  Every call given more gates returns GST_EINVAL. */
 int gst_max_gates(int n_qubits);
 
 /* Create a context on device `device_ordinal` that enqueues work on
@@ -137,6 +139,14 @@ int gst_vjp(gst_ctx* ctx, const gst_gateset* gs, const gst_seqlist* seqs, const 
 int gst_req_create_host(gst_ctx* ctx, int n_qubits, int n_gates, int n_outcomes,
                         const gst_seqlist* seqs_host, const int32_t* counts_host,
                         gst_req** out);
+/* gst_req_create: the same with DEVICE pointers (offsets, gate_idx, counts on
+   the context's device, as for gst_loglik).  The call waits for the context's
+   stream, reads the list (and counts) back to build the plan on the host, and
+   returns with its own copies; the caller's buffers may be reused at once.
+   Argument errors as for gst_req_create_host, including GST_EINDEX for a gate
+   index >= n_gates (reported at creation, not through gst_sync). */
+int gst_req_create(gst_ctx* ctx, int n_qubits, int n_gates, int n_outcomes, const gst_seqlist* seqs,
+                   const int32_t* counts, gst_req** out);
 /* Device bytes held by the request (plan, copies of the inputs, workspace). */
 int gst_req_footprint(const gst_req* req, size_t* bytes);
 /* Evaluate at gate set `theta`; same outputs and conventions as gst_loglik. */
@@ -301,8 +311,10 @@ int gst_param_backward(gst_ctx* ctx, int mode, int n_qubits, int n_outcomes, int
  * this context, same sizes, usually lists of growing length) it minimizes the
  * negative log-likelihood per shot (F / sum of the stage's counts) over theta
  * in the TP or CPTP parameterization (gst_param_*) with limited-memory BFGS
- * (two-loop recursion with opt->memory pairs, backtracking Armijo line search
- * from the unit step; a step with some p <= 0 where N > 0 counts as too long),
+ * (two-loop recursion with opt->memory pairs; strong Wolfe line search with
+ * c1 = 1e-4, c2 = 0.9: the step doubles from 1 until it brackets an acceptable
+ * one, then the bracket is bisected; a step with some p <= 0 where N > 0
+ * counts as too long),
  * starting from the previous stage's result.  theta: host array of
  * gst_param_count entries, in/out.  reports (optional): one per stage.
  * A stage whose start gives some p <= 0 where N > 0 starts instead from it moved

@@ -21,7 +21,7 @@ _NAMES = {0: "GST_OK", -1: "GST_EINVAL", -2: "GST_EINDEX", -3: "GST_ENONPOS", -4
 
 EXPORTED = [
     "gst_max_gates", "gst_create", "gst_destroy", "gst_sync", "gst_probs", "gst_loglik", "gst_vjp",
-    "gst_req_create_host", "gst_req_footprint", "gst_req_eval", "gst_req_probs", "gst_req_vjp",
+    "gst_req_create_host", "gst_req_create", "gst_req_footprint", "gst_req_eval", "gst_req_probs", "gst_req_vjp",
     "gst_req_destroy", "gst_req_plan_info", "gst_batch_create", "gst_batch_run", "gst_batch_nonpos",
     "gst_batch_destroy", "gst_tune_set", "gst_set_plan_jump", "gst_predict", "gst_tv_distance",
     "gst_param_count", "gst_param_forward", "gst_param_backward", "gst_lgst", "gst_gauge_optimize", "gst_mlgst",
@@ -119,6 +119,8 @@ def load():
         lib.gst_profile_read.restype = I
         if hasattr(lib, "gst_req_create_host"):
             lib.gst_req_create_host.argtypes = [P, I, I, I, ctypes.POINTER(GstSeqlist), P, ctypes.POINTER(P)]
+            lib.gst_req_create.argtypes = [P, I, I, I, ctypes.POINTER(GstSeqlist), P, ctypes.POINTER(P)]
+            lib.gst_req_create.restype = I
             lib.gst_req_footprint.argtypes = [P, ctypes.POINTER(ctypes.c_size_t)]
             lib.gst_req_eval.argtypes = [P, ctypes.POINTER(GstGateset), P, P, P]
             lib.gst_req_vjp.argtypes = [P, ctypes.POINTER(GstGateset), P, P]

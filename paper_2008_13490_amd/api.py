@@ -182,6 +182,24 @@ class Request:
         self.M = n_outcomes
         self.n_params = 4 ** n_qubits * (1 + n_outcomes) + n_gates * 16 ** n_qubits
 
+    @classmethod
+    def from_device(cls, ctx: Context, n_qubits: int, n_gates: int, n_outcomes: int, seqs: "DeviceSeqs",
+                    counts: Optional[torch.Tensor] = None) -> "Request":
+        """A request from a sequence list and counts already on the device (``gst_req_create``)."""
+        self = cls.__new__(cls)
+        self.ctx, self.lib = ctx, ctx.lib
+        if counts is not None:
+            counts = _require_cuda(counts, torch.int32, "counts")
+        h = ctypes.c_void_p()
+        _lib.check(self.lib.gst_req_create(ctx.handle, n_qubits, n_gates, n_outcomes, ctypes.byref(seqs.as_struct()),
+                                           _ptr(counts), ctypes.byref(h)))
+        self.handle = h
+        self.has_counts = counts is not None
+        self.S = seqs.S
+        self.M = n_outcomes
+        self.n_params = 4 ** n_qubits * (1 + n_outcomes) + n_gates * 16 ** n_qubits
+        return self
+
     def plan_info(self) -> dict:
         v = (ctypes.c_int64 * 12)()
         _lib.check(self.lib.gst_req_plan_info(self.handle, v, 12))
@@ -483,6 +501,11 @@ def hamiltonian_decomposition(n_qubits: int, G):
     _lib.check(lib.gst_hamiltonian_decomposition(n_qubits, g.ctypes.data, h.ctypes.data, ctypes.byref(ang),
                                                  ctypes.byref(gam)))
     return h, ang.value, gam.value
+
+
+def max_gates(n_qubits: int) -> int:
+    """Largest gate count the library takes for ``n_qubits`` (``gst_max_gates``)."""
+    return int(_lib.load().gst_max_gates(int(n_qubits)))
 
 
 def set_plan_jump(ctx: Context, reps: int):

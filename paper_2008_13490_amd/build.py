@@ -5,6 +5,7 @@ import glob
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
@@ -27,17 +28,25 @@ def build(verbose: bool = False) -> str:
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     objdir = os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)
-    objs = []
+    jobs = []
     for src in sources():
         obj = os.path.join(objdir, os.path.basename(src) + ".o")
         lang = ["-x", "hip"] if src.endswith(".hip") else []
-        cmd = [hipcc] + HIP_FLAGS + lang + ["-I", CSRC, "-c", src, "-o", obj]
+        jobs.append((src, obj, [hipcc] + HIP_FLAGS + lang + ["-I", CSRC, "-c", src, "-o", obj]))
+
+    def compile_one(job):
+        src, obj, cmd = job
         if verbose:
             print(" ".join(cmd), file=sys.stderr)
-        r = subprocess.run(cmd, capture_output=True, text=True)
-        if r.returncode != 0:
-            raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr}")
-        objs.append(obj)
+        return src, subprocess.run(cmd, capture_output=True, text=True)
+
+    # one compiler process per source, a few at a time
+    workers = max(1, min(len(jobs), int(os.environ.get("MAX_JOBS", "0") or 0) or (os.cpu_count() or 1), 8))
+    with ThreadPoolExecutor(max_workers=workers) as ex:
+        for src, r in ex.map(compile_one, jobs):
+            if r.returncode != 0:
+                raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr}")
+    objs = [obj for _, obj, _ in jobs]
     tmp = LIB + ".tmp"
     cmd = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
     r = subprocess.run(cmd, capture_output=True, text=True)

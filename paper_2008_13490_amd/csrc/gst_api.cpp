@@ -1192,6 +1192,42 @@ int gst_req_create_host(gst_ctx* ctx, int n_qubits, int n_gates, int n_outcomes,
   return GST_OK;
 }
 
+// Device-pointer form: the list (and counts) are copied to the host in stream
+// order, then the request is built exactly as from host arrays.
+int gst_req_create(gst_ctx* ctx, int n_qubits, int n_gates, int n_outcomes, const gst_seqlist* sl,
+                   const int32_t* counts, gst_req** out) {
+  if (!ctx || !out) return fail(GST_EINVAL, "NULL argument");
+  const int D = dim_of(n_qubits);
+  if (!D) return fail(GST_EINVAL, "n_qubits must be 1, 2 or 3");
+  if (n_gates < 1 || n_gates > gst_max_gates(n_qubits)) return fail(GST_EINVAL, "n_gates out of range");
+  if (n_outcomes < 1 || n_outcomes > std::min(D, 16)) return fail(GST_EINVAL, "n_outcomes must be in 1..min(D, 16)");
+  int rc = check_seqs(sl);
+  if (rc) return rc;
+  HIP_TRY(hipSetDevice(ctx->device));
+  const int64_t S = sl->n_seq;
+  std::vector<int64_t> off((size_t)S + 1, 0);
+  if (S > 0) {
+    HIP_TRY(hipMemcpyAsync(off.data(), sl->offsets, off.size() * 8, hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+  }
+  if (off[0] != 0) return fail(GST_EINVAL, "offsets[0] != 0");
+  for (int64_t s = 0; s < S; ++s)
+    if (off[s + 1] < off[s]) return fail(GST_EINVAL, "offsets decrease");
+  const int64_t n_steps = off[(size_t)S];
+  std::vector<uint8_t> g((size_t)std::max<int64_t>(n_steps, 1), 0);
+  std::vector<int32_t> c;
+  if (n_steps > 0) HIP_TRY(hipMemcpyAsync(g.data(), sl->gate_idx, (size_t)n_steps, hipMemcpyDeviceToHost, ctx->stream));
+  if (counts && S > 0) {
+    c.resize((size_t)S * n_outcomes);
+    HIP_TRY(hipMemcpyAsync(c.data(), counts, c.size() * 4, hipMemcpyDeviceToHost, ctx->stream));
+  }
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  gst_seqlist h{S, off.data(), g.data(), -1};
+  const int32_t zero = 0;
+  return gst_req_create_host(ctx, n_qubits, n_gates, n_outcomes, &h,
+                             counts ? (c.empty() ? &zero : c.data()) : nullptr, out);
+}
+
 int gst_req_footprint(const gst_req* req, size_t* bytes) {
   if (!req || !bytes) return fail(GST_EINVAL, "NULL argument");
   *bytes = req->resident_bytes + std::max(req->ws.bytes, req->eval_ws_bytes);

@@ -17,7 +17,7 @@ def declared_functions():
 def test_header_declares_boundary():
     names = declared_functions()
     for f in ["gst_create", "gst_destroy", "gst_probs", "gst_loglik", "gst_vjp", "gst_sync",
-              "gst_req_create_host", "gst_req_eval", "gst_req_footprint", "gst_req_destroy", "gst_last_error"]:
+              "gst_req_create_host", "gst_req_create", "gst_req_eval", "gst_req_footprint", "gst_req_destroy", "gst_last_error"]:
         assert f in names
 
 
@@ -29,7 +29,8 @@ def test_library_exports_every_declared_symbol():
     missing = [f for f in declared_functions() if not hasattr(lib, f)]
     assert not missing, missing
     lib.gst_max_gates.restype = ctypes.c_int
-    assert lib.gst_max_gates(2) >= 6 and lib.gst_max_gates(7) == 0
+    # the documented gate-count caps (larger K is refused with GST_EINVAL)
+    assert [lib.gst_max_gates(n) for n in (0, 1, 2, 3, 4, 7)] == [0, 8, 8, 5, 0, 0]
     lib.gst_last_error.restype = ctypes.c_char_p
     assert isinstance(lib.gst_last_error(), bytes)
 

@@ -1,9 +1,9 @@
 """GPU parity of the three-qubit path (D = 64) against the oracle.
 
 Probabilities must be bit-identical to the oracle's (same fused multiply-add
-order); objective 1e-10 relative, gradient 1e-10 normwise.  At the full size
-of the structured three-qubit list the oracle checks sampled probabilities
-one sequence at a time, and the gradient is checked through the Euler
+order); objective 1e-10 relative, gradient 1e-10 normwise.  The full
+structured three-qubit list is checked entry by entry against the oracle run
+over shards of the list in parallel processes, and through the Euler
 identities of the multilinear likelihood (exact at any size).
 """
 import sys
@@ -109,7 +109,11 @@ def test_c4_subset(oracle_lib, gpu):
     _check(oracle_lib, gs, sl, cnt, obj, p, g, "c4 subset")
 
 
-def test_c4_full_sampled_and_euler(oracle_lib, gpu):
+def test_c4_full_against_oracle_and_euler(oracle_lib, gpu):
+    """The whole structured three-qubit list: every probability, the objective
+    and every gradient entry against the oracle (run over sequence shards in
+    parallel processes), and the Euler identities of the multilinear likelihood."""
+    from oracle_shards import loglik_sharded
     api, ctx = gpu
     w = W.structured_workload("c4")
     gs, sl = w.model, w.seqs
@@ -120,16 +124,16 @@ def test_c4_full_sampled_and_euler(oracle_lib, gpu):
     p = p.cpu().numpy()
     g = g.cpu().numpy()
     F = float(obj.cpu()[0])
-    rng = np.random.default_rng(5)
-    idx = np.sort(rng.choice(sl.S, 400, replace=False))
-    sub = sl.subset(idx)
-    p_or = oracle_lib.probs(gs.rho, gs.effects, gs.gates, sub.offsets, sub.gates)
-    assert np.array_equal(p[idx], p_or)
-    # the objective from the (sample-checked) probabilities
-    N = w.counts.astype(np.float64)
-    F_np = -np.sum(np.where(N > 0, N * np.log(np.where(N > 0, p, 1.0)), 0.0))
-    assert abs(F - F_np) <= 1e-10 * abs(F_np), (F, F_np)
+    say("[3q] c4 full: oracle over shards")
+    F_or, p_or, g_or = loglik_sharded(gs.rho, gs.effects, gs.gates, sl.offsets, sl.gates, w.counts)
+    say("[3q] c4 full: oracle done")
+    bad = np.abs(p - p_or) > 1e-12 * np.abs(p_or)
+    assert not bad.any(), f"{int(bad.sum())} probabilities differ beyond 1e-12, max {np.abs(p - p_or).max()}"
+    assert abs(F - F_or) <= 1e-10 * abs(F_or), (F, F_or)
+    err = np.abs(g - g_or).max() / np.abs(g_or).max()
+    assert err <= 1e-10, err
     # Euler identities of l = -F (multilinear in rho, in each e_m, in the gates)
+    N = w.counts.astype(np.float64)
     D, M, K = 64, gs.M, gs.K
     rho_g, E_g, G_g = g[:D], g[D:D + M * D].reshape(M, D), g[D + M * D:].reshape(K, D, D)
     total = N.sum()

@@ -144,3 +144,52 @@ def test_resident_vjp(oracle_lib, gpu):
     ctx.sync()
     want = oracle_lib.vjp(gs.rho, gs.effects, gs.gates, sl.offsets, sl.gates, Wt)
     assert np.abs(g - want).max() <= 1e-10 * np.abs(want).max()
+
+
+@pytest.mark.parametrize("kind", ["c2-plan", "1q", "3q"])
+def test_request_from_device_pointers(gpu, kind):
+    """gst_req_create (device list and counts) builds the same request as
+    gst_req_create_host: every output equal bit for bit."""
+    import torch
+    api, ctx = gpu
+    if kind == "c2-plan":
+        w = W.structured_workload("c2")
+        idx = np.arange(0, w.seqs.S, 7)
+        gs, sl, cnt = w.model, w.seqs.subset(idx), w.counts[idx]
+    else:
+        w = W.random_workload(kind, 150, 60, 51)
+        gs, sl, cnt = w.model, w.seqs, w.counts
+    say(f"[resident] from device: {kind} S={sl.S}")
+    th = api.DeviceGateSet.from_numpy(gs.n_qubits, gs.rho, gs.effects, gs.gates)
+    a = api.Request(ctx, gs.n_qubits, gs.K, gs.M, sl.offsets, sl.gates, cnt)
+    seqs = api.DeviceSeqs.from_numpy(sl.offsets, sl.gates)
+    b = api.Request.from_device(ctx, gs.n_qubits, gs.K, gs.M, seqs, torch.as_tensor(cnt, device="cuda"))
+    assert a.plan_info() == b.plan_info()
+    ra = a.eval(th, want_probs=True)
+    rb = b.eval(th, want_probs=True)
+    ctx.sync()
+    for x, y in zip(ra, rb):
+        assert torch.equal(x, y)
+    a.close()
+    b.close()
+
+
+def test_gate_count_limits(gpu):
+    """More gates than gst_max_gates allows, or a gate index >= K, is refused at
+    creation (GST_EINVAL, GST_EINDEX) for host and device lists alike."""
+    import torch
+    from paper_2008_13490_amd import _lib
+    api, ctx = gpu
+    off = np.array([0, 2, 3], np.int64)
+    gts = np.array([0, 1, 2], np.uint8)
+    for n in (1, 2, 3):
+        K = api.max_gates(n)
+        with pytest.raises(_lib.GSTError) as e:
+            api.Request(ctx, n, K + 1, 2, off, gts, None)
+        assert e.value.code == _lib.GST_EINVAL
+        with pytest.raises(_lib.GSTError) as e:
+            api.Request.from_device(ctx, n, K + 1, 2, api.DeviceSeqs.from_numpy(off, gts))
+        assert e.value.code == _lib.GST_EINVAL
+    with pytest.raises(_lib.GSTError) as e:
+        api.Request.from_device(ctx, 2, 2, 4, api.DeviceSeqs.from_numpy(off, gts))
+    assert e.value.code == _lib.GST_EINDEX

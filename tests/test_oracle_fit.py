@@ -5,7 +5,9 @@ and the singular vectors; the gauge objective's gradient against central
 differences; gauge optimization of an exact gauge transform of the target
 returns the target; the maximum-likelihood fit of data with exact frequencies
 returns the generating gate set's probabilities; the plain L-BFGS on the
-Rosenbrock function."""
+Rosenbrock function; the start repairs of MLGST against the closed-form
+threshold of the repair strength; the MLGST optimum against an independent
+trust-region minimizer."""
 import numpy as np
 import pytest
 
@@ -126,3 +128,115 @@ def test_plain_lbfgs_rosenbrock():
                                                                 200 * (b - a * a)])
     x, fx, g = FT.lbfgs(f, np.array([-1.2, 1.0]), gtol=1e-10, maxiter=5000)
     assert np.allclose(x, [1.0, 1.0], atol=1e-8) and fx < 1e-16
+
+
+# ---------------------------------------------------------------------------
+# The start repairs of iterative MLGST, pinned by closed forms.
+#
+# A gate whose Bloch part is stretched by c > 1 is not positive; after the
+# depolarizing repair (rows 1.. times 1 - delta) every Bloch component of a word
+# of L such gates is scaled by lambda^L, lambda = c (1 - delta), because the
+# uniform scaling commutes with the rotation.  With the ideal state |0> and the
+# computational-basis effects p_0(X_pi/2 X_pi/2) = 1/2 - lambda^2 / 2, positive
+# exactly when lambda < 1, i.e. delta > 1 - 1/c.  The ladder 0, 2^-10, ..., 1/2
+# must therefore return its first value above 1 - 1/c.
+# ---------------------------------------------------------------------------
+GX_PTM = np.array([[1.0, 0, 0, 0], [0, 1, 0, 0], [0, 0, 0, -1], [0, 0, 1, 0]])
+LADDER = [0.0] + [2.0 ** -k for k in range(10, 0, -1)]
+V0 = np.array([1.0, 0, 0, 1.0]) / np.sqrt(2.0)   # vec(|0><0|)
+V1 = np.array([1.0, 0, 0, -1.0]) / np.sqrt(2.0)  # vec(|1><1|)
+
+
+def _first_above(tau):
+    return next(d for d in LADDER if d > tau)
+
+
+def _ladder_words():
+    # the word X_pi/2 X_pi/2 (ideal outcome 1 with certainty) and the empty word
+    return np.array([0, 2, 2], np.int64), np.array([0, 0], np.uint8)
+
+
+@pytest.mark.parametrize("tau", [-0.01, 0.0007, 0.003, 0.011, 0.2, 0.45])
+def test_tp_start_repair_threshold_closed_form(oracle_lib, tau):
+    c = 1.0 / (1.0 - tau)
+    G = GX_PTM.copy()
+    G[1:, :] *= c
+    offsets, gates = _ladder_words()
+    # outcome 0 observed once on the word whose ideal p_0 is 0: finite only if lambda < 1
+    counts = np.array([[1, 999], [1000, 0]], np.int32)
+    theta = FT.contract_tp(V0, np.array([V0, V1]), G[None])
+    th, delta = FT.feasible_tp_start(theta, 1, 2, 1, offsets, gates, counts)
+    assert delta == (0.0 if tau < 0 else _first_above(tau))
+    rho, E, Gd = PR.forward("tp", th, 1, 2, 1)
+    lam = c * (1.0 - delta)
+    p = oracle_lib.probs(rho, E, Gd, offsets, gates)
+    assert abs(p[0, 0] - (0.5 - 0.5 * lam ** 2)) <= 1e-15
+    # the repair keeps the map trace preserving: first row e_0, unit trace, complete POVM
+    assert np.array_equal(Gd[0, 0], [1.0, 0, 0, 0]) and rho[0] == 1.0 / np.sqrt(2.0)
+    assert np.allclose(E.sum(axis=0), [np.sqrt(2.0), 0, 0, 0], atol=1e-16)
+    # minimal: the previous ladder value leaves the objective infinite
+    if delta > 0:
+        prev = LADDER[LADDER.index(delta) - 1]
+        th_prev = np.array(theta, copy=True)
+        th_prev[3 + 4:] *= 1.0 - prev
+        F, _ = FT.nll_in_mode(th_prev, "tp", 1, 2, 1, None, offsets, gates, counts)
+        assert not np.isfinite(F)
+
+
+# The CPTP repair mixes the free effects with the uniform POVM.  With the ideal
+# state |0> and the effect e_0 = (1 + eps) vec(|0><0|) the completed last effect
+# gives p_1(empty word) = -eps; after e_0 <- (1 - delta) e_0 + delta vec(1)/2,
+# p_1 = -eps + delta (1/2 + eps), positive exactly when delta > eps / (1/2 + eps).
+@pytest.mark.parametrize("eps", [0.0, 0.0004, 0.0015, 0.02, 0.3])
+def test_cptp_start_repair_threshold_closed_form(oracle_lib, eps):
+    offsets, gates = _ladder_words()
+    counts = np.array([[0, 1000], [990, 10]], np.int32)
+    # A = diag(1, 0) gives rho = |0><0|; h = 0, T = 0 give G = G0 (the ideal X_pi/2)
+    theta = np.concatenate([[1.0, 0.0, 0.0, 0.0], (1.0 + eps) * V0, np.zeros(3 + 9)])
+    th, delta = FT.feasible_cptp_start(theta, 1, 2, 1, GX_PTM[None], offsets, gates, counts)
+    tau = eps / (0.5 + eps)
+    assert delta == (0.0 if eps == 0.0 else _first_above(tau))
+    rho, E, G = PR.forward("cptp", th, 1, 2, 1, GX_PTM[None])
+    p = oracle_lib.probs(rho, E, G, offsets, gates)
+    assert abs(p[1, 1] - (-eps + delta * (0.5 + eps))) <= 1e-15
+    # gates and state are untouched; the effects stay complete
+    assert np.allclose(G[0], GX_PTM, atol=1e-15) and np.allclose(rho, V0, atol=1e-15)
+    assert np.allclose(E.sum(axis=0), [np.sqrt(2.0), 0, 0, 0], atol=1e-15)
+
+
+def test_mlgst_optimum_against_an_independent_minimizer(oracle_lib):
+    """The maximum of the likelihood is a property of the data, not of the
+    optimizer: scipy's trust-region method (no line search, no L-BFGS memory)
+    from the same start reaches the oracle's stage objective (sampled counts,
+    TP mode, an interior optimum)."""
+    rng = np.random.default_rng(7)
+    truth = W.noisy_gateset("1q", 5e-3, 0.03, rng)
+    truth.rho = truth.rho * np.array([1.0, 1.0, 1.0, 0.97])
+    sl, ends = one_qubit_fit_list((1, 2, 4))
+    p = exact_probs(oracle_lib, truth, sl)
+    counts = W.sample_counts(p, 1000, rng)
+    assert counts.min() > 0          # every outcome observed: the optimum is interior
+    rho, E, G = FT.lgst(sl.offsets, sl.gates, counts, FIDS_1Q, FIDS_1Q, 1, 3)
+    target = W.noisy_gateset("1q", 0.0, 0.0, rng)
+    _, (rho, E, G), _ = FT.gauge_opt(rho, E, G, target.rho, target.effects, target.gates)
+    theta0, delta = FT.feasible_tp_start(FT.contract_tp(rho, E, G), 1, 2, 3, sl.offsets, sl.gates, counts)
+    out = FT.mlgst([(sl.offsets, sl.gates, counts)], theta0, "tp", 1, 2, 3, gtol=1e-11)
+    F_oracle = out[0][1]
+    scale = 1.0 / counts.sum()
+
+    def f(th):
+        F, g = FT.nll_in_mode(th, "tp", 1, 2, 3, None, sl.offsets, sl.gates, counts)
+        return F * scale, g * scale
+
+    import warnings
+
+    import scipy.optimize as so
+    with warnings.catch_warnings():
+        warnings.simplefilter("ignore", UserWarning)   # its quasi-Newton update near convergence
+        res = so.minimize(f, theta0, jac=True, method="trust-constr", options={"gtol": 1e-11, "maxiter": 20000})
+    F_scipy = res.fun / scale
+    assert np.isfinite(F_scipy)
+    assert abs(F_oracle - F_scipy) <= 1e-9 * abs(F_scipy)
+    # and neither beats the other by more than that: both are at the same minimum
+    F_truth = oracle_lib.loglik(truth.rho, truth.effects, truth.gates, sl.offsets, sl.gates, counts)[0]
+    assert F_oracle < F_truth
