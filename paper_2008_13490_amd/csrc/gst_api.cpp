@@ -180,6 +180,8 @@ struct ProfScope : gst::LaunchTimer {
   ProfScope* outer = nullptr;  // the enclosing scope, if one is timing
   bool active = false;
   ProfScope(gst_ctx* ctx, int family) : c(ctx), fam(family) {
+    // a family indexes the profiler's per-family arrays
+    if (fam < 0 || fam >= FAM_N) return;
     if (c && c->prof.on && (c->prof.only < 0 || c->prof.only == fam)) {
       active = true;
       prev = gst::launch_timer();
@@ -1083,27 +1085,17 @@ int gst_req_create_host(gst_ctx* ctx, int n_qubits, int n_gates, int n_outcomes,
   r->S = S;
   r->max_len = max_len;
   r->total_counts = total_counts;
-  // batch tiles: sequences by length (descending, stable), kTileSeqs per tile
-  std::vector<int64_t> order((size_t)S);
-  for (int64_t q = 0; q < S; ++q) order[q] = q;
-  std::stable_sort(order.begin(), order.end(), [&](int64_t x, int64_t y) {
-    return sl->offsets[x + 1] - sl->offsets[x] > sl->offsets[y + 1] - sl->offsets[y];
-  });
-  // tiles of the one- and two-qubit tile kernel (three-qubit requests use
-  // their own tiles below)
+  // batch tiles: sequences by length (descending, stable), cut into tiles of
+  // the one- and two-qubit tile kernels (three-qubit requests use their own
+  // tiles below)
+  std::vector<int64_t> order;
   const int64_t tile_seqs = D == 64 ? std::max<int64_t>(S, 1) : tile_seqs_of_group(ctx, tile_group(D, n_gates), S);
-  for (int64_t q0 = 0; q0 < S && D <= 16; q0 += tile_seqs) {
-    r->tile_q.push_back(q0);
-    int64_t cost = 0;
-    for (int64_t q = q0; q < std::min(S, q0 + tile_seqs); ++q) cost += sl->offsets[order[q] + 1] - sl->offsets[order[q]];
-    r->tile_cost.push_back(cost);
+  gst::cut_tiles(sl->offsets, S, tile_seqs, &order, &r->tile_q, &r->tile_cost);
+  if (D == 64) {
+    r->tile_q.clear();
+    r->tile_cost.clear();
   }
-  if (S > 0 && D <= 16) r->tile_q.push_back(S);
-  std::vector<gst::BatchTile> tiles((size_t)r->n_tiles());
-  for (int64_t t = 0; t < r->n_tiles(); ++t) tiles[t] = gst::BatchTile{0, (int32_t)t, r->tile_q[t], r->tile_q[t + 1]};
-  std::stable_sort(tiles.begin(), tiles.end(), [&](const gst::BatchTile& x, const gst::BatchTile& y) {
-    return r->tile_cost[x.local] > r->tile_cost[y.local];
-  });
+  std::vector<gst::BatchTile> tiles = gst::batch_tiles({&r->tile_q}, {&r->tile_cost}, {0});
   const int64_t Pw = gst::slab_width(D, n_outcomes, n_gates);
   // three-qubit requests: tiles of 16 sequences for the chain kernel, and the
   // step positions of each gate (ascending) cut into chunks for the
@@ -1436,7 +1428,9 @@ int gst_batch_create(gst_ctx* ctx, int n, gst_req* const* reqs, const gst_gatese
   if (!b) return fail(GST_ENOMEM, "host allocation failed");
   b->ctx = ctx;
   std::vector<gst::BatchReq> rq;
-  std::vector<std::pair<int64_t, gst::BatchTile>> tiles[6];  // per tile kernel: (cost, tile)
+  // per tile kernel: the requests' tile cuts
+  std::vector<const std::vector<int64_t>*> group_q[6], group_cost[6];
+  std::vector<int> group_req[6];
   std::vector<gst::BatchReduceItem> items;
   for (int x = 0; x < n; ++x) {
     gst_req* r = reqs[x];
@@ -1482,14 +1476,9 @@ int gst_batch_create(gst_ctx* ctx, int n, gst_req* const* reqs, const gst_gatese
     rq.push_back(q);
     b->kmax = std::max(b->kmax, r->K);
     b->max_len = std::max(b->max_len, r->max_len);
-    for (int64_t t = 0; t < r->n_tiles(); ++t) {
-      gst::BatchTile T{};
-      T.req = x;
-      T.local = (int32_t)t;
-      T.q0 = r->tile_q[t];
-      T.q1 = r->tile_q[t + 1];
-      tiles[tile_group(D, r->K)].emplace_back(r->tile_cost[t], T);
-    }
+    group_q[tile_group(D, r->K)].push_back(&r->tile_q);
+    group_cost[tile_group(D, r->K)].push_back(&r->tile_cost);
+    group_req[tile_group(D, r->K)].push_back(x);
     if (ob) {
       const int64_t P = gst::slab_width(D, r->M, r->K);
       b->red_chunks = std::max(b->red_chunks, gst::batch_reduce_chunks(r->n_tiles()));
@@ -1506,17 +1495,26 @@ int gst_batch_create(gst_ctx* ctx, int n, gst_req* const* reqs, const gst_gatese
       }
     }
   }
-  // longest tiles first (balance); execution order does not change results
-  auto by_cost = [](const std::pair<int64_t, gst::BatchTile>& a, const std::pair<int64_t, gst::BatchTile>& c) {
-    return a.first > c.first;
-  };
+  // longest tiles first (balance); execution order does not change results.
+  // Every tile writes row `local` of its own request's slab: checked here
+  // against the cuts before anything is launched.
+  std::vector<gst::BatchTile> tiles[6];
+  std::vector<const std::vector<int64_t>*> cut_of_req((size_t)n, nullptr);
+  for (int x = 0; x < n; ++x)
+    if (!b->reqs[x]->plan.used && b->reqs[x]->D != 64) cut_of_req[x] = &b->reqs[x]->tile_q;
   int64_t ck_doubles = 0;
   for (int g = 0; g < 6; ++g) {
-    std::stable_sort(tiles[g].begin(), tiles[g].end(), by_cost);
+    tiles[g] = gst::batch_tiles(group_q[g], group_cost[g], group_req[g]);
     b->n_tiles[g] = (int)tiles[g].size();
     b->grid_of[g] = group_grid(ctx, g, b->kmax, b->n_tiles[g]);
     // the groups run one after another on the stream and share the checkpoints
     ck_doubles = std::max<int64_t>(ck_doubles, (int64_t)group_ckpt_doubles(g, b->grid_of[g], b->max_len));
+  }
+  {
+    std::vector<gst::BatchTile> all;
+    for (int g = 0; g < 6; ++g) all.insert(all.end(), tiles[g].begin(), tiles[g].end());
+    const std::string bad = gst::check_batch_tiles(all, cut_of_req);
+    if (!bad.empty()) return fail(GST_EINVAL, "internal: batch tile list: " + bad);
   }
   b->n_items = (int)items.size();
   Carver cv;
@@ -1529,11 +1527,9 @@ int gst_batch_create(gst_ctx* ctx, int n, gst_req* const* reqs, const gst_gatese
   if (rc) return rc;
   char* base = reinterpret_cast<char*>(b->desc.p);
   if (!rq.empty()) HIP_TRY(hipMemcpy(base + o_rq, rq.data(), rq.size() * sizeof(gst::BatchReq), hipMemcpyHostToDevice));
-  for (int g = 0; g < 6; ++g) {
-    std::vector<gst::BatchTile> v;
-    for (auto& pr : tiles[g]) v.push_back(pr.second);
-    if (!v.empty()) HIP_TRY(hipMemcpy(base + o_t[g], v.data(), v.size() * sizeof(gst::BatchTile), hipMemcpyHostToDevice));
-  }
+  for (int g = 0; g < 6; ++g)
+    if (!tiles[g].empty())
+      HIP_TRY(hipMemcpy(base + o_t[g], tiles[g].data(), tiles[g].size() * sizeof(gst::BatchTile), hipMemcpyHostToDevice));
   if (!items.empty())
     HIP_TRY(hipMemcpy(base + o_it, items.data(), items.size() * sizeof(gst::BatchReduceItem), hipMemcpyHostToDevice));
   unsigned* queues = reinterpret_cast<unsigned*>(base + o_q);

@@ -6,6 +6,7 @@
 #include <vector>
 
 #include "gst_param_tables.h"
+#include "gst_tiles.h"
 #include <hip/hip_runtime.h>
 
 namespace gst {
@@ -174,11 +175,6 @@ struct BatchReq {
   double* probs;
   double* slab;            // [n_tiles][P] of this request
   int M, K, mode, want_grad;
-};
-struct BatchTile {
-  int32_t req;    // index into reqs
-  int32_t local;  // tile index within its request (slab row)
-  int64_t q0, q1; // positions in the request's order
 };
 struct BatchLaunch {
   int D;
