@@ -411,7 +411,8 @@ def run_structured(args):
                                               api._ptr(obj), api._ptr(grad)))
 
     families = ("leaf", "reduce", "trunk_fwd", "trunk_bwd", "inject", "grad_gemm", "fill", "tiles_2q", "tiles_1q",
-                "tiles_reduce", "chain_3q", "gemm_3q", "reduce_3q", "param_fwd", "param_bwd")
+                "tiles_reduce", "chain_3q", "gemm_3q", "reduce_3q", "tiles_3q_fwd", "tiles_3q_bwd", "readout_3q",
+                "param_fwd", "param_bwd")
     for _ in range(args.warmup):
         step()
     ctx.sync()
@@ -450,7 +451,10 @@ def run_structured(args):
     elapsed = t1 - t0
     value = S * args.steps / elapsed
     flops = fam_flops(dom)  # algorithmic FP64 work per launch of the dominant family
-    steps_eval = (info["trunk_steps"] + info["item_steps"]) if info else int(L.sum())
+    if info and info.get("grouped"):
+        steps_eval = info["trie_nodes"] - 1
+    else:
+        steps_eval = (info["trunk_steps"] + info["item_steps"]) if info else int(L.sum())
     return {
         "metric": METRIC,
         "value": value,
@@ -852,6 +856,18 @@ def algorithmic_flops(family, D, M, S, sum_len, info):
             return 4.0 * D * D * sum_len + 6.0 * D * M * S
         if family == "gemm_3q":    # dG_k = sum b f^T
             return 2.0 * D * D * sum_len
+        return 0.0
+    if info.get("grouped"):
+        # three qubits, grouped chains: every trie node is one step of its
+        # chain (padding columns of a tile are not counted); launches per
+        # evaluation: one per level in each direction
+        nodes, lv = info["trie_nodes"] - 1, max(1, info["levels"])
+        if family in ("tiles_3q_fwd", "tiles_3q_bwd"):
+            return 2.0 * D * D * nodes / lv
+        if family == "readout_3q":   # readout, seed and effect gradient of every sequence
+            return 6.0 * D * M * S
+        if family == "gemm_3q":
+            return 2.0 * D * D * nodes
         return 0.0
     ts, its, lv = info["trunk_steps"], info["item_steps"], max(1, info["levels"])
     filled = ts - info.get("chain_steps", ts)   # trunk states / adjoints inside germ-power jumps

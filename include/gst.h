@@ -159,9 +159,10 @@ int gst_req_vjp(gst_req* req, const gst_gateset* theta, const double* w, double*
 int gst_req_destroy(gst_req* req);
 /* Sharing-plan statistics of a request (diagnostics): info[0..n) receives
    {plan used (0/1), total steps of the plain evaluation, trie nodes, trunks,
-    trunk steps, item steps, trunk levels, injection slots, chain mat-vecs of
+    trunk steps, item steps, levels, injection slots, chain mat-vecs of
     the trunks (jumps counted once), longest trunk chain, trunks with jumps,
-    fill tasks}; n <= 12. */
+    fill tasks, grouped-chain plan used (three qubits: 0/1), its tiles, its
+    chains, its state rows}; n <= 16. */
 int gst_req_plan_info(const gst_req* req, int64_t* info, int n);
 
 /*

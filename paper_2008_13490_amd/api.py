@@ -201,10 +201,10 @@ class Request:
         return self
 
     def plan_info(self) -> dict:
-        v = (ctypes.c_int64 * 12)()
-        _lib.check(self.lib.gst_req_plan_info(self.handle, v, 12))
+        v = (ctypes.c_int64 * 16)()
+        _lib.check(self.lib.gst_req_plan_info(self.handle, v, 16))
         keys = ["plan_used", "sum_len", "trie_nodes", "trunks", "trunk_steps", "item_steps", "levels", "inj_slots",
-                "chain_steps", "chain_max", "jump_trunks", "fill_tasks"]
+                "chain_steps", "chain_max", "jump_trunks", "fill_tasks", "grouped", "tiles", "chains", "rows"]
         return dict(zip(keys, [int(x) for x in v]))
 
     def footprint(self) -> int:

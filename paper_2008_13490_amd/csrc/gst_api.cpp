@@ -16,6 +16,7 @@
 #include "gst_metrics.h"
 #include "gst_internal.h"
 #include "gst_plan.h"
+#include "gst_plan64.h"
 
 namespace gst {
 LaunchTimer*& launch_timer() {
@@ -110,7 +111,7 @@ struct Profiler {
   };
   std::vector<Pending> pending;
   std::vector<hipEvent_t> pool;
-  static constexpr int kMaxFamilies = 20;
+  static constexpr int kMaxFamilies = 24;
   double total_ms[kMaxFamilies] = {0};
   int64_t launches[kMaxFamilies] = {0};
   hipEvent_t get() {
@@ -136,12 +137,14 @@ struct Profiler {
 enum Family { FAM_LEAF = 0, FAM_REDUCE = 1, FAM_TRUNK_FWD = 2, FAM_TRUNK_BWD = 3, FAM_INJECT = 4, FAM_GEMM = 5,
               FAM_BATCH = 6, FAM_TILES16 = 7, FAM_TILES4 = 8, FAM_TILES_RED = 9, FAM_CHAIN64 = 10,
               FAM_GEMM64 = 11, FAM_REDUCE64 = 12, FAM_FILL = 13, FAM_PRED_CHAIN = 14,
-              FAM_PRED_FILL = 15, FAM_TV = 16, FAM_PARAM_FWD = 17, FAM_PARAM_BWD = 18, FAM_N = 19 };
+              FAM_PRED_FILL = 15, FAM_TV = 16, FAM_PARAM_FWD = 17, FAM_PARAM_BWD = 18, FAM_P64_FWD = 19,
+              FAM_P64_BWD = 20, FAM_P64_READ = 21, FAM_N = 22 };
 static_assert(FAM_N <= Profiler::kMaxFamilies, "profiler arrays too small");
 static const char* kFamilyNames[FAM_N] = {"leaf",  "reduce",  "trunk_fwd", "trunk_bwd",   "inject",
                                           "grad_gemm", "batch", "tiles_2q",  "tiles_1q", "tiles_reduce",
                                           "chain_3q",  "gemm_3q", "reduce_3q", "fill", "predict_chain",
-                                          "predict_fill", "tv_distance", "param_fwd", "param_bwd"};
+                                          "predict_fill", "tv_distance", "param_fwd", "param_bwd", "tiles_3q_fwd",
+                                          "tiles_3q_bwd", "readout_3q"};
 
 // Carve consecutive aligned regions out of one allocation.
 struct Carver {
@@ -243,6 +246,27 @@ struct DevicePlan {
   uint8_t* fill_gate3 = nullptr;
 };
 
+// Device copy of a three-qubit grouped-chain plan (gst_plan64.h) with its
+// arenas: the states and adjoints of every trie node, the seeds and chain
+// adjoints, the rearranged gate set and the partial sums.
+struct DevicePlan64 {
+  bool used = false;
+  gst::Plan64 host;          // sizes and level ranges (the big arrays are released after upload)
+  std::vector<int64_t> level_tile_ptr;
+  DevBuf buf;
+  int64_t *tile_row0 = nullptr, *tile_word = nullptr, *tile_ev = nullptr, *col_anchor = nullptr,
+          *col_chain = nullptr, *ev_ptr = nullptr, *ev_src = nullptr, *slot_row = nullptr, *slot_ptr = nullptr,
+          *slot_seq = nullptr, *root_chains = nullptr, *rec_b = nullptr, *rec_f = nullptr, *chunk_beg = nullptr,
+          *chunk_end = nullptr, *gate_chunk_ptr = nullptr;
+  int32_t *tile_len = nullptr, *ev_col = nullptr;
+  uint8_t* words = nullptr;
+  double *FA = nullptr, *BA = nullptr, *INJ = nullptr, *GA = nullptr, *GAT = nullptr, *slab = nullptr,
+         *part = nullptr, *chunk_slab = nullptr, *root_vec = nullptr;
+  int readout_blocks = 0;
+  int n_root_chains = 0;
+  int64_t n_chunks = 0;
+};
+
 // Sequences per batch tile: a request's sequences, sorted by length, are cut
 // into tiles of this many (16 chains x 8); fixed, so a request's tiling and
 // summation order depend on the request alone.
@@ -285,6 +309,7 @@ struct gst_req {
   double* part64 = nullptr;             // scratch of the ordered tile reduction
   size_t eval_ws_bytes = 0;             // context workspace one evaluation with gradient needs
   DevicePlan plan;
+  DevicePlan64 plan64;
   DevBuf ws;
   size_t resident_bytes = 0;
   int64_t n_tiles() const { return tile_q.empty() ? 0 : (int64_t)tile_q.size() - 1; }
@@ -561,6 +586,214 @@ int upload_plan(gst_req* r, const gst::HostPlan& P) {
   }
   d.inj_level_ptr[P.n_levels] = P.root_slot;
   d.used = true;
+  return GST_OK;
+}
+
+int upload_plan64(gst_req* r, gst::Plan64& P) {
+  DevicePlan64& d = r->plan64;
+  const int M = r->M, K = r->K;
+  const int64_t T = P.n_tiles(), TS = P.tile_steps(), NE = (int64_t)P.ev_col.size(), NR = (int64_t)P.rec_b.size(),
+                NC = (int64_t)P.chunk_beg.size(), NRC = (int64_t)P.root_chains.size();
+  d.readout_blocks = (int)std::min<int64_t>(std::max<int64_t>((P.n_slots + gst::READOUT64_WAVES - 1) /
+                                                                  gst::READOUT64_WAVES, 1),
+                                            (int64_t)gst::readout64_blocks_per_cu() * r->ctx->n_cu);
+  const int64_t n_waves = (int64_t)d.readout_blocks * gst::READOUT64_WAVES;
+  const int64_t Pc = 1 + 64 + (int64_t)M * 64;
+  Carver c;
+  const size_t o_r0 = c.take<int64_t>(T + 1), o_len = c.take<int32_t>(T + 1), o_w = c.take<int64_t>(T + 1),
+               o_tev = c.take<int64_t>(T + 1), o_anc = c.take<int64_t>(T * 16 + 1), o_ch = c.take<int64_t>(T * 16 + 1),
+               o_words = c.take<uint8_t>(P.words.size() + 1), o_evp = c.take<int64_t>(TS + 2),
+               o_evc = c.take<int32_t>(NE + 1), o_evs = c.take<int64_t>(NE + 1),
+               o_sr = c.take<int64_t>(P.n_slots + 1), o_sp = c.take<int64_t>(P.n_slots + 2),
+               o_sq = c.take<int64_t>(P.S + 1), o_rc = c.take<int64_t>(NRC + 1), o_rb = c.take<int64_t>(NR + 1),
+               o_rf = c.take<int64_t>(NR + 1), o_cb = c.take<int64_t>(NC + 1), o_ce = c.take<int64_t>(NC + 1),
+               o_gcp = c.take<int64_t>(K + 1), o_fa = c.take<double>((size_t)P.n_rows * 64),
+               o_ba = c.take<double>((size_t)P.n_rows * 64),
+               o_inj = c.take<double>((size_t)(P.n_slots + P.n_chains + 1) * 64),
+               o_ga = c.take<double>((size_t)K * 4096), o_gat = c.take<double>((size_t)K * 4096),
+               o_slab = c.take<double>((size_t)n_waves * Pc),
+               o_part = c.take<double>((size_t)gst::reduce_parts((int)n_waves) * Pc),
+               o_cs = c.take<double>((size_t)std::max<int64_t>(NC, 1) * 4096), o_root = c.take<double>(64);
+  int rc = d.buf.reserve(c.off + 256, r->ctx->stream);
+  if (rc) return rc;
+  char* b = reinterpret_cast<char*>(d.buf.p);
+  d.tile_row0 = reinterpret_cast<int64_t*>(b + o_r0);
+  d.tile_len = reinterpret_cast<int32_t*>(b + o_len);
+  d.tile_word = reinterpret_cast<int64_t*>(b + o_w);
+  d.tile_ev = reinterpret_cast<int64_t*>(b + o_tev);
+  d.col_anchor = reinterpret_cast<int64_t*>(b + o_anc);
+  d.col_chain = reinterpret_cast<int64_t*>(b + o_ch);
+  d.words = reinterpret_cast<uint8_t*>(b + o_words);
+  d.ev_ptr = reinterpret_cast<int64_t*>(b + o_evp);
+  d.ev_col = reinterpret_cast<int32_t*>(b + o_evc);
+  d.ev_src = reinterpret_cast<int64_t*>(b + o_evs);
+  d.slot_row = reinterpret_cast<int64_t*>(b + o_sr);
+  d.slot_ptr = reinterpret_cast<int64_t*>(b + o_sp);
+  d.slot_seq = reinterpret_cast<int64_t*>(b + o_sq);
+  d.root_chains = reinterpret_cast<int64_t*>(b + o_rc);
+  d.rec_b = reinterpret_cast<int64_t*>(b + o_rb);
+  d.rec_f = reinterpret_cast<int64_t*>(b + o_rf);
+  d.chunk_beg = reinterpret_cast<int64_t*>(b + o_cb);
+  d.chunk_end = reinterpret_cast<int64_t*>(b + o_ce);
+  d.gate_chunk_ptr = reinterpret_cast<int64_t*>(b + o_gcp);
+  d.FA = reinterpret_cast<double*>(b + o_fa);
+  d.BA = reinterpret_cast<double*>(b + o_ba);
+  d.INJ = reinterpret_cast<double*>(b + o_inj);
+  d.GA = reinterpret_cast<double*>(b + o_ga);
+  d.GAT = reinterpret_cast<double*>(b + o_gat);
+  d.slab = reinterpret_cast<double*>(b + o_slab);
+  d.part = reinterpret_cast<double*>(b + o_part);
+  d.chunk_slab = reinterpret_cast<double*>(b + o_cs);
+  d.root_vec = reinterpret_cast<double*>(b + o_root);
+  auto put = [&](void* dst, const void* src, size_t bytes) -> int {
+    if (bytes) HIP_TRY(hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice));
+    return GST_OK;
+  };
+  if ((rc = put(d.tile_row0, P.tile_row0.data(), T * 8))) return rc;
+  if ((rc = put(d.tile_len, P.tile_len.data(), T * 4))) return rc;
+  if ((rc = put(d.tile_word, P.tile_word.data(), T * 8))) return rc;
+  if ((rc = put(d.tile_ev, P.tile_ev.data(), T * 8))) return rc;
+  if ((rc = put(d.col_anchor, P.col_anchor.data(), T * 16 * 8))) return rc;
+  if ((rc = put(d.col_chain, P.col_chain.data(), T * 16 * 8))) return rc;
+  if ((rc = put(d.words, P.words.data(), P.words.size()))) return rc;
+  if ((rc = put(d.ev_ptr, P.ev_ptr.data(), P.ev_ptr.size() * 8))) return rc;
+  if ((rc = put(d.ev_col, P.ev_col.data(), NE * 4))) return rc;
+  if ((rc = put(d.ev_src, P.ev_src.data(), NE * 8))) return rc;
+  if ((rc = put(d.slot_row, P.slot_row.data(), P.n_slots * 8))) return rc;
+  if ((rc = put(d.slot_ptr, P.slot_ptr.data(), P.slot_ptr.size() * 8))) return rc;
+  if ((rc = put(d.slot_seq, P.slot_seq.data(), P.slot_seq.size() * 8))) return rc;
+  if ((rc = put(d.root_chains, P.root_chains.data(), NRC * 8))) return rc;
+  if ((rc = put(d.rec_b, P.rec_b.data(), NR * 8))) return rc;
+  if ((rc = put(d.rec_f, P.rec_f.data(), NR * 8))) return rc;
+  if ((rc = put(d.chunk_beg, P.chunk_beg.data(), NC * 8))) return rc;
+  if ((rc = put(d.chunk_end, P.chunk_end.data(), NC * 8))) return rc;
+  if ((rc = put(d.gate_chunk_ptr, P.gate_chunk_ptr.data(), (K + 1) * 8))) return rc;
+  d.level_tile_ptr = P.level_tile_ptr;
+  d.n_root_chains = (int)NRC;
+  d.n_chunks = NC;
+  // keep the sizes, drop the host copies of the big arrays
+  d.host = gst::Plan64();
+  d.host.K = P.K;
+  d.host.S = P.S;
+  d.host.sum_len = P.sum_len;
+  d.host.n_nodes = P.n_nodes;
+  d.host.n_rows = P.n_rows;
+  d.host.n_chains = P.n_chains;
+  d.host.n_slots = P.n_slots;
+  d.host.n_levels = P.n_levels;
+  d.host.root_slot = P.root_slot;
+  d.host.tile_row0.resize((size_t)T);  // n_tiles()
+  d.used = true;
+  return GST_OK;
+}
+
+// One evaluation with the grouped-chain plan (three qubits): the gate set
+// rearranged for the MFMA operands, the chains forward level by level, the
+// readouts per seed slot, the chains backward deepest level first, the
+// gradient GEMM over the (adjoint, parent state) records, the root adjoint,
+// and the ordered sums.
+int run_plan64(gst_req* r, const gst_gateset* th, int mode, const double* w, double* probs, double* objective,
+               double* grad, unsigned long long* nonpos) {
+  gst_ctx* ctx = r->ctx;
+  DevicePlan64& d = r->plan64;
+  const bool want_grad = grad != nullptr;
+  unsigned long long* np = nonpos ? nonpos : reinterpret_cast<unsigned long long*>(r->queue + kQueueWords);
+  HIP_TRY(gst::launch_queue_reset(r->queue, np, 1, ctx->stream));
+  HIP_TRY(gst::launch_gate_prep64(th->gates, th->rho, r->K, d.GA, d.GAT, d.FA, ctx->stream));
+  gst::Plan64Launch a{};
+  a.GA = d.GA;
+  a.GAT = d.GAT;
+  a.tile_row0 = d.tile_row0;
+  a.tile_len = d.tile_len;
+  a.tile_word = d.tile_word;
+  a.tile_ev = d.tile_ev;
+  a.col_anchor = d.col_anchor;
+  a.col_chain = d.col_chain;
+  a.words = d.words;
+  a.ev_ptr = d.ev_ptr;
+  a.ev_col = d.ev_col;
+  a.ev_src = d.ev_src;
+  a.FA = d.FA;
+  a.BA = d.BA;
+  a.INJ = d.INJ;
+  a.n_slots = d.host.n_slots;
+  const int L = d.host.n_levels;
+  {
+    ProfScope ps(ctx, FAM_P64_FWD);
+    for (int l = 0; l < L; ++l) {
+      a.t_begin = d.level_tile_ptr[l];
+      HIP_TRY(gst::launch_plan64_fwd(a, (int)(d.level_tile_ptr[l + 1] - d.level_tile_ptr[l]), ctx->stream));
+    }
+  }
+  const bool need_slab = objective || grad;
+  {
+    ProfScope ps(ctx, FAM_P64_READ);
+    gst::Readout64Launch q{};
+    q.M = r->M;
+    q.E = th->effects;
+    q.FA = d.FA;
+    q.n_slots = d.host.n_slots;
+    q.slot_row = d.slot_row;
+    q.slot_ptr = d.slot_ptr;
+    q.slot_seq = d.slot_seq;
+    q.counts = r->counts;
+    q.W = w;
+    q.probs = probs;
+    q.mode = mode;
+    q.want_grad = want_grad ? 1 : 0;
+    q.INJ = d.INJ;
+    q.slab = need_slab ? d.slab : nullptr;
+    q.status = ctx->status;
+    q.nonpos = np;
+    HIP_TRY(gst::launch_readout64(q, d.readout_blocks, ctx->stream));
+  }
+  if (want_grad) {
+    {
+      ProfScope ps(ctx, FAM_P64_BWD);
+      for (int l = L - 1; l >= 0; --l) {
+        a.t_begin = d.level_tile_ptr[l];
+        HIP_TRY(gst::launch_plan64_bwd(a, (int)(d.level_tile_ptr[l + 1] - d.level_tile_ptr[l]), ctx->stream));
+      }
+    }
+    if (d.n_chunks > 0) {
+      ProfScope ps(ctx, FAM_GEMM64);
+      gst::Gemm64Launch g{};
+      g.rec_b = d.BA;
+      g.rec_f = d.FA;
+      g.row_b = d.rec_b;
+      g.row_f = d.rec_f;
+      g.chunk_beg = d.chunk_beg;
+      g.chunk_end = d.chunk_end;
+      g.slab = d.chunk_slab;
+      g.n_chunks = (int)d.n_chunks;
+      HIP_TRY(gst::launch_gemm64(g, ctx->stream));
+    }
+    gst::Root64Launch ro{};
+    ro.INJ = d.INJ;
+    ro.root_slot = d.host.root_slot;
+    ro.n_slots = d.host.n_slots;
+    ro.root_chains = d.root_chains;
+    ro.n_root_chains = d.n_root_chains;
+    ro.out = d.root_vec;
+    HIP_TRY(gst::launch_root64(ro, ctx->stream));
+  }
+  if (need_slab) {
+    ProfScope ps(ctx, FAM_REDUCE64);
+    const int64_t Pc = 1 + 64 + (int64_t)r->M * 64;
+    const int n_waves = d.readout_blocks * gst::READOUT64_WAVES;
+    HIP_TRY(gst::launch_reduce(d.slab, n_waves, Pc, objective, grad, want_grad ? d.root_vec : nullptr, 64, d.part,
+                               ctx->stream));
+    if (want_grad) {
+      gst::Reduce64Launch red{};
+      red.M = r->M;
+      red.K = r->K;
+      red.chunk_slab = d.chunk_slab;
+      red.gate_chunk_ptr = d.gate_chunk_ptr;
+      red.grad = grad;
+      red.nonpos = np;
+      HIP_TRY(gst::launch_reduce64(red, ctx->stream));
+    }
+  }
   return GST_OK;
 }
 
@@ -1101,7 +1334,11 @@ int gst_req_create_host(gst_ctx* ctx, int n_qubits, int n_gates, int n_outcomes,
   // step positions of each gate (ascending) cut into chunks for the
   // gate-gradient kernel
   std::vector<int64_t> pos64, cbeg64, cend64, gcp64;
-  if (D == 64) {
+  // three-qubit lists with deep sharing: the grouped-chain plan instead
+  gst::Plan64 p64;
+  const bool use_p64 = D == 64 && S > 0 && gst::build_plan64(sl->offsets, sl->gate_idx, S, n_gates,
+                                                              gst::Plan64Options(), &p64);
+  if (D == 64 && !use_p64) {
     r->tile_seqs64 = ctx->tune_tile[3] > 0 ? ctx->tune_tile[3] : 16;
     r->n_tiles64 = (S + r->tile_seqs64 - 1) / r->tile_seqs64;
     std::vector<int64_t> gp((size_t)n_gates + 1, 0);
@@ -1178,7 +1415,11 @@ int gst_req_create_host(gst_ctx* ctx, int n_qubits, int n_gates, int n_outcomes,
       if (rc) return rc;
     }
   }
-  r->resident_bytes = r->data.bytes + r->plan.buf.bytes;
+  if (use_p64) {
+    rc = upload_plan64(r.get(), p64);
+    if (rc) return rc;
+  }
+  r->resident_bytes = r->data.bytes + r->plan.buf.bytes + r->plan64.buf.bytes;
   (void)o_off;
   *out = r.release();
   return GST_OK;
@@ -1299,6 +1540,7 @@ static int run_tiles(gst_req* r, const gst_gateset* th, int mode, const double* 
 // the count of p <= 0 with N > 0 of this evaluation.
 static int run64(gst_req* r, const gst_gateset* th, int mode, const double* w, double* probs, double* objective,
                  double* grad, unsigned long long* nonpos = nullptr) {
+  if (r->plan64.used) return run_plan64(r, th, mode, w, probs, objective, grad, nonpos);
   gst_ctx* ctx = r->ctx;
   const bool want_grad = grad != nullptr;
   unsigned long long* np = nonpos ? nonpos : reinterpret_cast<unsigned long long*>(r->queue + kQueueWords);
@@ -1622,10 +1864,13 @@ int gst_req_plan_info(const gst_req* req, int64_t* info, int n) {
     chain += c;
     chain_max = std::max(chain_max, c);
   }
-  int64_t vals[12] = {req->plan.used ? 1 : 0, P.sum_len, P.n_nodes, P.n_trunks(), P.trunk_steps(),
-                      P.item_steps(), P.n_levels, (int64_t)P.inj_loc.size(), chain, chain_max,
-                      P.n_jump_trunks(), P.n_fill()};
-  for (int x = 0; x < n && x < 12; ++x) info[x] = vals[x];
+  const gst::Plan64& Q = req->plan64.host;
+  const bool q = req->plan64.used;
+  int64_t vals[16] = {req->plan.used || q ? 1 : 0, q ? Q.sum_len : P.sum_len, q ? Q.n_nodes : P.n_nodes,
+                      P.n_trunks(), P.trunk_steps(), P.item_steps(), q ? Q.n_levels : P.n_levels,
+                      (int64_t)P.inj_loc.size(), chain, chain_max, P.n_jump_trunks(), P.n_fill(),
+                      q ? 1 : 0, q ? Q.n_tiles() : 0, q ? Q.n_chains : 0, q ? Q.n_rows : 0};
+  for (int x = 0; x < n && x < 16; ++x) info[x] = vals[x];
   return GST_OK;
 }
 

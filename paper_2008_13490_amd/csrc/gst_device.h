@@ -121,6 +121,11 @@ __device__ __forceinline__ double dot16(double x, const Row16& r) { return dot16
 
 
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ int64_t uniform64(int64_t v) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)((uint64_t)v >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
 
 // A pointer read from memory is generic to the compiler, and a generic (flat)
 // load is counted by both vmcnt and lgkmcnt, so the first LDS wait after it

@@ -249,6 +249,8 @@ struct Chain64Launch {
 struct Gemm64Launch {
   const double* rec_b;
   const double* rec_f;
+  const int64_t* row_b;      // optional: rows of rec_b and rec_f of each record (else pos for both)
+  const int64_t* row_f;
   const int64_t* pos;        // step positions grouped by gate, ascending within a gate
   const int64_t* chunk_beg;  // [n_chunks] ranges in pos (one gate each)
   const int64_t* chunk_end;
@@ -262,6 +264,61 @@ struct Reduce64Launch {            // gate columns only
   double* grad;
   const unsigned long long* nonpos;
 };
+// Three-qubit sharing plan with grouped chains (gst_plan64.h): tiles of
+// sixteen chains with one word, stepped together on the matrix cores.
+struct Plan64Launch {
+  const double* GA;          // [K][4][16][64]: A operands of G, GA[k][w][kk][l] = G[k][16w + l%16][4kk + l/16]
+  const double* GAT;         // [K][4][16][64]: the same for G^T
+  int64_t t_begin;           // first tile of the launch (one workgroup per tile)
+  const int64_t* tile_row0;
+  const int32_t* tile_len;
+  const int64_t* tile_word;
+  const int64_t* tile_ev;
+  const int64_t* col_anchor; // [n_tiles][16]
+  const int64_t* col_chain;  // [n_tiles][16]
+  const uint8_t* words;
+  const int64_t* ev_ptr;
+  const int32_t* ev_col;
+  const int64_t* ev_src;
+  double* FA;                // [n_rows][64], row 0 = rho
+  double* BA;                // [n_rows][64]
+  double* INJ;               // [n_slots + n_chains][64]
+  int64_t n_slots;
+};
+constexpr int READOUT64_WAVES = 4;
+struct Readout64Launch {
+  int M;
+  const double* E;
+  const double* FA;
+  int64_t n_slots;
+  const int64_t* slot_row;
+  const int64_t* slot_ptr;
+  const int64_t* slot_seq;
+  const int32_t* counts;
+  const double* W;
+  double* probs;
+  int mode, want_grad;
+  double* INJ;               // seeds: rows 0 .. n_slots-1
+  double* slab;              // [waves][1 + 64 + 64 M]
+  unsigned long long* status;
+  unsigned long long* nonpos;
+};
+struct Root64Launch {        // the adjoint of rho: root seed + chains anchored at rho (ascending)
+  const double* INJ;
+  int64_t root_slot;         // -1 none
+  int64_t n_slots;
+  const int64_t* root_chains;
+  int n_root_chains;
+  double* out;               // [64]
+};
+hipError_t launch_gate_prep64(const double* G, const double* rho, int K, double* GA, double* GAT, double* FA,
+                              hipStream_t stream);
+hipError_t launch_plan64_fwd(const Plan64Launch& a, int n_tiles, hipStream_t stream);
+hipError_t launch_plan64_bwd(const Plan64Launch& a, int n_tiles, hipStream_t stream);
+hipError_t launch_readout64(const Readout64Launch& a, int n_blocks, hipStream_t stream);
+hipError_t launch_root64(const Root64Launch& a, hipStream_t stream);
+int readout64_blocks_per_cu();
+
 size_t chain64_lds(int K);
 int chain64_blocks_per_cu(int K);
 hipError_t launch_chain64(const Chain64Launch& a, int n_blocks, hipStream_t stream);

@@ -245,13 +245,17 @@ __global__ __launch_bounds__(256) void gemm64_kernel(const Gemm64Launch a) {
   d4 acc[4];
 #pragma unroll
   for (int tc = 0; tc < 4; ++tc) acc[tc] = d4{0.0, 0.0, 0.0, 0.0};
+  const auto* g_rb = as_global(a.row_b);
+  const auto* g_rf = as_global(a.row_f);
   for (int64_t r = r0; r < r1; r += 4) {
     const bool v = r + z < r1;
-    const int64_t p = g_pos[v ? r + z : r0];
-    const double av = v ? g_b[p * N64 + 16 * w + ii] : 0.0;
+    const int64_t idx = v ? r + z : r0;
+    const int64_t pb = a.row_b ? g_rb[idx] : g_pos[idx];
+    const int64_t pf = a.row_b ? g_rf[idx] : pb;
+    const double av = v ? g_b[pb * N64 + 16 * w + ii] : 0.0;
     double bv[4];
 #pragma unroll
-    for (int tc = 0; tc < 4; ++tc) bv[tc] = v ? g_f[p * N64 + 16 * tc + ii] : 0.0;
+    for (int tc = 0; tc < 4; ++tc) bv[tc] = v ? g_f[pf * N64 + 16 * tc + ii] : 0.0;
 #pragma unroll
     for (int tc = 0; tc < 4; ++tc) acc[tc] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv[tc], acc[tc], 0, 0, 0);
   }
@@ -289,7 +293,253 @@ __global__ __launch_bounds__(256) void reduce64_kernel(const Reduce64Launch a) {
   if (a.grad && !nonpos) a.grad[1 + N64 + (int64_t)a.M * N64 - 1 + y] = v;
 }
 
+// ---------------------------------------------------------------------------
+// The grouped-chain plan (gst_plan64.h).
+//
+// A tile holds sixteen chains with one gate word.  Its states form a 64 x 16
+// block V; a step is V <- G V, one FP64 MFMA product.  Wave w of the tile's
+// workgroup computes rows 16w .. 16w+15 with sixteen 16x16x4 MFMAs over the
+// inner index in ascending blocks of four; each MFMA adds its four products
+// one after another in ascending order, so every entry is the chain of fused
+// multiply-adds acc = fma(G[i][j], v[j], acc), j = 0 .. 63 from acc = 0 (the
+// plain definition's order: probabilities are bit-identical to it).  The block
+// lives in LDS in the operand order of the MFMA (Vs[kk][lane] = V[4kk +
+// lane/16][lane%16]), which is also the order in which the products come out,
+// so a step writes its rows straight back for the next one.  The A operands
+// come from a copy of the gate set rearranged once per evaluation so that every
+// operand load reads 512 consecutive bytes; the next step's operands are
+// loaded while the current step runs.
+// ---------------------------------------------------------------------------
+
+// GA[k][w][kk][l] = G[k][16w + l%16][4kk + l/16]; GAT the same for G^T.  Block 0
+// also writes rho into row 0 of the state arena.
+__global__ __launch_bounds__(256) void gate_prep64_kernel(const double* G, const double* rho, double* GA,
+                                                          double* GAT, double* FA) {
+  const int k = blockIdx.x;
+  const double* g = G + (int64_t)k * GATE64;
+  for (int x = threadIdx.x; x < GATE64; x += 256) {
+    const int w = x >> 10, kk = (x >> 6) & 15, l = x & 63;
+    GA[(int64_t)k * GATE64 + x] = g[(16 * w + (l & 15)) * N64 + 4 * kk + (l >> 4)];
+    GAT[(int64_t)k * GATE64 + x] = g[(4 * kk + (l >> 4)) * N64 + 16 * w + (l & 15)];
+  }
+  if (k == 0 && threadIdx.x < N64) FA[threadIdx.x] = rho[threadIdx.x];
+}
+
+__device__ __forceinline__ void load_ops(double (&dst)[16], const double* base, int lane) {
+  const auto* g = as_global(base);
+#pragma unroll
+  for (int kk = 0; kk < 16; ++kk) dst[kk] = g[kk * 64 + lane];
+}
+
+__global__ __launch_bounds__(256) void plan64_fwd_kernel(const Plan64Launch a) {
+  __shared__ double Vs[2][16 * 64];
+  const int tid = threadIdx.x, l = tid & 63, w = tid >> 6;
+  const int c = l & 15, r4 = l >> 4;
+  const int64_t tile = a.t_begin + blockIdx.x;
+  const int64_t anc = a.col_anchor[tile * 16 + c];
+  const auto* fa = as_global(a.FA);
+#pragma unroll
+  for (int v = 0; v < 4; ++v) Vs[0][(4 * w + v) * 64 + l] = fa[anc * N64 + 4 * (4 * w + v) + r4];
+  const int len = uniform(a.tile_len[tile]);
+  const uint8_t* word = a.words + a.tile_word[tile];
+  const int64_t row0 = a.tile_row0[tile];
+  double an[16];
+  if (len > 0) load_ops(an, a.GA + ((int64_t)word[0] * 4 + w) * 1024, l);
+  __syncthreads();
+  int cur = 0;
+  for (int t = 0; t < len; ++t) {
+    double ac[16];
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) ac[kk] = an[kk];
+    if (t + 1 < len) load_ops(an, a.GA + ((int64_t)uniform(word[t + 1]) * 4 + w) * 1024, l);
+    d4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ac[kk], Vs[cur][kk * 64 + l], acc, 0, 0, 0);
+    // rows 16w + 4v + r4 of column c: operand block kk = 4w + v of the next step
+    auto* dst = as_global(a.FA + (row0 + (int64_t)t * 16 + c) * N64 + 16 * w + r4);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      Vs[cur ^ 1][(4 * w + v) * 64 + l] = acc[v];
+      dst[4 * v] = acc[v];
+    }
+    __syncthreads();
+    cur ^= 1;
+  }
+}
+
+// Reverse sweep of a tile: b <- b + (seeds, adjoints of the chains anchored
+// here); store b; b <- G^T b.  At the end each chain delivers b to its anchor.
+__global__ __launch_bounds__(256) void plan64_bwd_kernel(const Plan64Launch a) {
+  __shared__ double Bs[2][16 * 64];
+  const int tid = threadIdx.x, l = tid & 63, w = tid >> 6;
+  const int c = l & 15, r4 = l >> 4;
+  const int64_t tile = a.t_begin + blockIdx.x;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) Bs[0][(4 * w + v) * 64 + l] = 0.0;
+  const int len = uniform(a.tile_len[tile]);
+  const uint8_t* word = a.words + a.tile_word[tile];
+  const int64_t row0 = a.tile_row0[tile];
+  const int64_t eb = a.tile_ev[tile];
+  const auto* inj = as_global(a.INJ);
+  double an[16];
+  if (len > 0) load_ops(an, a.GAT + ((int64_t)word[len - 1] * 4 + w) * 1024, l);
+  __syncthreads();
+  int cur = 0;
+  for (int t = len - 1; t >= 0; --t) {
+    double ac[16];
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) ac[kk] = an[kk];
+    if (t > 0) load_ops(an, a.GAT + ((int64_t)uniform(word[t - 1]) * 4 + w) * 1024, l);
+    // events of this node, in their fixed order; every thread adds to its own entries
+    const int64_t e0 = uniform64(a.ev_ptr[eb + t]), e1 = uniform64(a.ev_ptr[eb + t + 1]);
+    for (int64_t e = e0; e < e1; ++e) {
+      const int ce = uniform(a.ev_col[e]);
+      const int64_t src = uniform64(a.ev_src[e]);
+      if (c == ce) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) Bs[cur][(4 * w + v) * 64 + l] += inj[src * N64 + 4 * (4 * w + v) + r4];
+      }
+    }
+    __syncthreads();
+    auto* dst = as_global(a.BA + (row0 + (int64_t)t * 16 + c) * N64 + r4);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) dst[4 * (4 * w + v)] = Bs[cur][(4 * w + v) * 64 + l];
+    d4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ac[kk], Bs[cur][kk * 64 + l], acc, 0, 0, 0);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) Bs[cur ^ 1][(4 * w + v) * 64 + l] = acc[v];
+    __syncthreads();
+    cur ^= 1;
+  }
+  const int64_t ch = a.col_chain[tile * 16 + c];
+  if (ch >= 0) {
+    auto* out = as_global(a.INJ + (a.n_slots + ch) * N64 + r4);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) out[4 * (4 * w + v)] = Bs[cur][(4 * w + v) * 64 + l];
+  }
+}
+
+// Readouts per seed slot (the sequences ending at one node): p = E f in the
+// plain order, the objective, dL/dp, the seed E^T (sum of the slot's dL/dp),
+// and dL/dE.  Slot s goes to wave s mod (waves of the launch), so every sum
+// has a fixed order; each wave writes one partial row [objective | 0 | dL/dE].
+__global__ __launch_bounds__(READOUT64_WAVES * 64) void readout64_kernel(const Readout64Launch a) {
+  const int l = threadIdx.x & 63;
+  const int64_t wv = (int64_t)blockIdx.x * READOUT64_WAVES + (threadIdx.x >> 6);
+  const int64_t nw = (int64_t)gridDim.x * READOUT64_WAVES;
+  const int M = a.M;
+  const int mrow = l < M ? l : M - 1;
+  const double* Erow = a.E + (size_t)mrow * N64;
+  const auto* fa = as_global(a.FA);
+  const auto* g_counts = as_global(a.counts);
+  const auto* g_W = as_global(a.W);
+  auto* g_probs = as_global(a.probs);
+  const bool grad = a.want_grad != 0;
+  double obj = 0.0;
+  double dE[16];
+#pragma unroll
+  for (int m = 0; m < 16; ++m) dE[m] = 0.0;
+  unsigned nonpos = 0;
+  for (int64_t s = wv; s < a.n_slots; s += nw) {
+    const double f = fa[a.slot_row[s] * N64 + l];
+    const double p = mv_global_row(Erow, l, f);
+    double dps = 0.0;
+    const int64_t q1 = a.slot_ptr[s + 1];
+    for (int64_t q = a.slot_ptr[s]; q < q1; ++q) {
+      const int64_t seq = a.slot_seq[q];
+      if (l < M) {
+        const int64_t o = seq * M + l;
+        if (a.probs) g_probs[o] = p;
+        if (a.mode == MODE_LOGLIK) {
+          const int32_t N = g_counts[o];
+          if (N > 0) {
+            if (p <= 0.0) {
+              ++nonpos;
+              obj = INFINITY;
+            } else {
+              obj -= (double)N * log(p);
+              dps += -(double)N / p;
+            }
+          }
+        } else if (a.mode == MODE_VJP) {
+          dps += g_W[o];
+        }
+      }
+    }
+    if (!grad) continue;
+    double b = 0.0;
+#pragma unroll
+    for (int m = 0; m < 16; ++m) {
+      if (m < M) {
+        const double dpm = __shfl(dps, m);
+        dE[m] = fma(dpm, f, dE[m]);
+        b = fma(a.E[(size_t)m * N64 + l], dpm, b);
+      }
+    }
+    a.INJ[s * N64 + l] = b;
+  }
+  if (a.slab) {
+    const int64_t Pc = 1 + N64 + (int64_t)M * N64;
+    double* out = a.slab + wv * Pc;
+    const double o = wave_sum(obj);
+    if (l == 0) out[0] = o;
+    out[1 + l] = 0.0;
+#pragma unroll
+    for (int m = 0; m < 16; ++m)
+      if (m < M) out[1 + N64 + m * N64 + l] = dE[m];
+  }
+  const unsigned np = (unsigned)wave_sum((double)nonpos);
+  if (l == 0 && np) {
+    atomicAdd(a.status + 1, (unsigned long long)np);
+    atomicAdd(a.nonpos, (unsigned long long)np);
+  }
+}
+
+__global__ __launch_bounds__(64) void root64_kernel(const Root64Launch a) {
+  const int j = threadIdx.x;
+  double v = a.root_slot >= 0 ? a.INJ[a.root_slot * N64 + j] : 0.0;
+  for (int i = 0; i < a.n_root_chains; ++i) v += a.INJ[(a.n_slots + a.root_chains[i]) * N64 + j];
+  a.out[j] = v;
+}
+
 }  // namespace
+
+hipError_t launch_gate_prep64(const double* G, const double* rho, int K, double* GA, double* GAT, double* FA,
+                              hipStream_t stream) {
+  if (K < 1) return hipErrorInvalidValue;
+  gst_launch(gate_prep64_kernel, dim3(K), dim3(256), 0, stream, G, rho, GA, GAT, FA);
+  return hipGetLastError();
+}
+
+hipError_t launch_plan64_fwd(const Plan64Launch& a, int n_tiles, hipStream_t stream) {
+  if (n_tiles <= 0) return hipSuccess;
+  gst_launch(plan64_fwd_kernel, dim3(n_tiles), dim3(256), 0, stream, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_plan64_bwd(const Plan64Launch& a, int n_tiles, hipStream_t stream) {
+  if (n_tiles <= 0) return hipSuccess;
+  gst_launch(plan64_bwd_kernel, dim3(n_tiles), dim3(256), 0, stream, a);
+  return hipGetLastError();
+}
+
+int readout64_blocks_per_cu() {
+  int n = 0;
+  const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, readout64_kernel, READOUT64_WAVES * 64, 0);
+  return (e == hipSuccess && n > 0) ? n : 1;
+}
+
+hipError_t launch_readout64(const Readout64Launch& a, int n_blocks, hipStream_t stream) {
+  if (n_blocks <= 0 || a.M < 1 || a.M > 16) return hipErrorInvalidValue;
+  gst_launch(readout64_kernel, dim3(n_blocks), dim3(READOUT64_WAVES * 64), 0, stream, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_root64(const Root64Launch& a, hipStream_t stream) {
+  gst_launch(root64_kernel, dim3(1), dim3(64), 0, stream, a);
+  return hipGetLastError();
+}
 
 size_t chain64_lds(int K) { return (size_t)K * GATE64 * sizeof(double); }
 

@@ -240,6 +240,7 @@ bool build_plan64(const int64_t* off, const uint8_t* gates, int64_t S, int K, co
   for (int64_t ti = 0; ti < T; ++ti)
     for (int c = 0; c < P.tile_cols[ti]; ++c) P.col_anchor[ti * W + c] = node_row[anchor[P.col_chain[ti * W + c]]];
   if ((double)(N - 1) < opt.min_fill * (double)(P.n_rows - 1)) return false;
+  if ((double)(P.n_rows - 1) > opt.max_row_ratio * (double)P.sum_len) return false;
 
   // ---- 7. seed slots (terminal nodes in order of first appearance) ----
   std::vector<int64_t> slot_of_node((size_t)N, -1);

@@ -36,8 +36,8 @@ namespace gst {
 
 struct Plan64Options {
   int tile_cols = 16;                 // chains per tile (the MFMA width)
-  double max_row_ratio = 0.5;         // use the plan only if its rows <= ratio * total steps
-  double min_fill = 0.5;              // ... and live columns fill at least this share of tile rows
+  double max_row_ratio = 0.5;         // use the plan only if its rows (padding included) <= ratio * total steps
+  double min_fill = 0.0;              // ... and live columns fill at least this share of tile rows
   int64_t max_nodes = 1LL << 26;
   int chunk = 8192;                   // gradient records per chunk
 };

@@ -192,3 +192,77 @@ def test_3q_empty_list(gpu):
     obj, _, g = req.eval(_dev(api, gs))
     ctx.sync()
     assert float(obj.cpu()[0]) == 0.0 and not torch.any(g != 0)
+
+
+def _structured_3q(seed=7, n_fid=8, spec=((2, 4), (3, 4)), powers=(1, 2, 4, 8, 16, 32)):
+    rng = np.random.default_rng(seed)
+    gs = W.noisy_gateset("3q", 1e-3, 0.01, rng)
+    fids = W.shortlex_words((1, 2), n_fid)
+    germs = W.random_germs(gs.K, list(spec), rng)
+    sl = W.structured_list(fids, fids, germs, list(powers))
+    words = [list(sl.word(s)) for s in range(sl.S)]
+    words += [words[5], [], words[len(words) // 3], []]   # duplicates and empty words
+    sl = W.from_words(words)
+    import oracle
+    p = oracle.probs(gs.rho, gs.effects, gs.gates, sl.offsets, sl.gates)
+    counts = W.sample_counts(p, 1000, rng)
+    return gs, sl, counts
+
+
+def test_3q_grouped_plan(oracle_lib, gpu):
+    """A structured three-qubit list runs on the grouped-chain plan (tiles of
+    sixteen chains on the matrix cores): probabilities bit-identical to the
+    oracle, objective and gradient within 1e-10; probabilities-only, vjp and a
+    second evaluation give the same bits."""
+    import torch
+    api, ctx = gpu
+    gs, sl, counts = _structured_3q()
+    req = api.Request(ctx, 3, gs.K, gs.M, sl.offsets, sl.gates, counts)
+    info = req.plan_info()
+    say(f"[3q] grouped plan: S={sl.S} sumL={int(sl.offsets[-1])} {info}")
+    assert info["grouped"] == 1 and info["tiles"] > 0
+    th = _dev(api, gs)
+    obj, p, g = req.eval(th, want_probs=True, want_grad=True)
+    ctx.sync()
+    _check(oracle_lib, gs, sl, counts, obj, p, g, "grouped plan")
+    obj2, p2, g2 = req.eval(th, want_probs=True, want_grad=True)
+    p3 = req.probs(th)
+    ctx.sync()
+    assert torch.equal(obj2, obj) and torch.equal(p2, p) and torch.equal(g2, g) and torch.equal(p3, p)
+    rng = np.random.default_rng(3)
+    Wt = rng.standard_normal((sl.S, gs.M))
+    gv = req.vjp(th, torch.as_tensor(Wt, device="cuda"))
+    ctx.sync()
+    g_or = oracle_lib.vjp(gs.rho, gs.effects, gs.gates, sl.offsets, sl.gates, Wt)
+    err = np.abs(gv.cpu().numpy() - g_or).max() / np.abs(g_or).max()
+    assert err <= 1e-10, err
+
+
+def test_3q_grouped_plan_in_batch_and_nonpos(oracle_lib, gpu):
+    import torch
+    api, ctx = gpu
+    gs, sl, counts = _structured_3q(seed=8, n_fid=6, powers=(1, 2, 4, 8))
+    b = W.random_workload("2q", 200, 80, 44)
+    reqs = [api.Request(ctx, 3, gs.K, gs.M, sl.offsets, sl.gates, counts),
+            api.Request(ctx, 2, b.model.K, b.model.M, b.seqs.offsets, b.seqs.gates, b.counts)]
+    assert reqs[0].plan_info()["grouped"] == 1
+    th = [_dev(api, gs), _dev(api, b.model)]
+    ref = [r.eval(t, want_probs=True) for r, t in zip(reqs, th)]
+    ctx.sync()
+    say("[3q] grouped plan in a batch")
+    bt = api.Batch(ctx, reqs, th, want_probs=True, want_grad=True, capture_graph=True)
+    for _ in range(2):
+        bt.run()
+        ctx.sync()
+        for x, (o, p, g) in enumerate(ref):
+            assert torch.equal(bt.obj[x], o) and torch.equal(bt.probs[x], p) and torch.equal(bt.grad[x], g)
+    say("[3q] grouped plan: p <= 0 with N > 0")
+    E0 = gs.effects.copy()
+    E0[2] = 0.0
+    bad = api.DeviceGateSet.from_numpy(3, gs.rho, E0, gs.gates)
+    o, _, _ = reqs[0].eval(bad)
+    rc, _, nnp = ctx.sync(raise_on_error=False)
+    assert rc == -3 and nnp == int(np.count_nonzero(counts[:, 2] > 0)) and float(o.cpu()[0]) == float("inf")
+    o2, _, _ = reqs[0].eval(th[0])
+    ctx.sync()
+    assert torch.equal(o2, ref[0][0])
