@@ -14,6 +14,13 @@
   GateDecompositionHamiltonianPTM, GateDecompositionHamiltonianProjection), the
   decomposition error gamma = ||G - exp(L^H)||_F, the rotation angle |h| and
   axis h / |h| (Eqs. GSTHamiltonianAngle, GSTHamiltonianAxis).
+* hamiltonian_decomposition_toward: App. J's other route, for gates whose
+  transfer matrix has no real principal logarithm (eigenvalues on the
+  negative real axis, like the ideal CZ and CNOT): the coefficients h that
+  minimize gamma(h) = ||G - exp(L^H(h))||_F directly, starting from the
+  Hamiltonian of the intended target unitary U, H_U = i log U with the
+  principal branch of each eigenvalue's argument (the target's logarithm);
+  scipy's L-BFGS-B with the gradient from the Frechet derivative of exp.
 """
 from __future__ import annotations
 
@@ -111,6 +118,54 @@ def hamiltonian_decomposition(G: np.ndarray):
             h[k] = np.sum(L.T * s[k]) / den     # sum_ij L_ij s_kji
     LH = np.einsum("k,kji->ij", h, s)
     gamma = float(np.linalg.norm(G - sla.expm(LH)))
+    phi = float(np.linalg.norm(h))
+    axis = h / phi if phi > 0 else np.zeros(D)
+    return h, gamma, phi, axis
+
+
+def hamiltonian_ptm(h: np.ndarray) -> np.ndarray:
+    """L^H of Eq. GateDecompositionHamiltonianPTM: L^H_ij = sum_k h_k s_kji."""
+    D = h.shape[0]
+    n = int(round(np.log(D) / np.log(4)))
+    return np.einsum("k,kji->ij", h, supercommutator(n))
+
+
+def target_hamiltonian(U: np.ndarray) -> np.ndarray:
+    """h (h_0 = 0) of H = i log U, each eigenvalue's argument in (-pi, pi]: U = exp(-iH)
+    up to a global phase, H = sum_k h_k P_k / 2."""
+    N = U.shape[0]
+    n = int(round(np.log2(N)))
+    w, V = np.linalg.eig(U)
+    theta = np.angle(w)
+    theta[theta <= -np.pi + 1e-12] = np.pi        # the principal argument of -1 is pi
+    H = -(V * theta) @ np.linalg.inv(V)          # i log U = i V diag(i theta) V^-1
+    P = paulis(n)
+    h = np.array([2.0 * np.trace(P[k] @ H).real / N for k in range(N * N)])
+    h[0] = 0.0
+    return h
+
+
+def _gamma2(x, G):
+    h = np.concatenate([[0.0], x])
+    L = hamiltonian_ptm(h)
+    E = sla.expm(L)
+    R = G - E
+    # d||R||^2 / dh_k = -2 <R, Dexp_L(dL/dh_k)>, dL/dh_k = s_k^T
+    s = supercommutator(int(round(np.log(G.shape[0]) / np.log(4))))
+    g = np.array([-2.0 * np.sum(R * sla.expm_frechet(L, s[k].T, compute_expm=False)) for k in range(1, G.shape[0])])
+    return float(np.sum(R * R)), g
+
+
+def hamiltonian_decomposition_toward(G: np.ndarray, U: np.ndarray, gtol: float = 1e-14):
+    """(h [D] with h_0 = 0, gamma, angle |h|, axis h / |h|): h minimizing
+    ||G - exp(L^H(h))||_F from the target's Hamiltonian."""
+    import scipy.optimize as so
+    D = G.shape[0]
+    x0 = target_hamiltonian(U)[1:]
+    res = so.minimize(_gamma2, x0, args=(G,), jac=True, method="L-BFGS-B",
+                      options={"gtol": gtol, "ftol": 1e-30, "maxiter": 2000, "maxcor": 20})
+    h = np.concatenate([[0.0], res.x])
+    gamma = float(np.linalg.norm(G - sla.expm(hamiltonian_ptm(h))))
     phi = float(np.linalg.norm(h))
     axis = h / phi if phi > 0 else np.zeros(D)
     return h, gamma, phi, axis
