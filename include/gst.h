@@ -127,6 +127,23 @@ int gst_vjp(gst_ctx* ctx, const gst_gateset* gs, const gst_seqlist* seqs, const 
             double* grad);
 
 /*
+ * gst_loglik_noalloc: gst_loglik for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation).  Same arguments, outputs and kernels as gst_loglik; the
+ * kernels' scratch (partial sums, checkpoints) lives in a static device array
+ * of 128 MiB that each GPU running the library holds until the process ends,
+ * and the call allocates nothing.  One or two qubits; seqs->max_len must be
+ * given (>= 0), so that nothing is read back.  GST_EINVAL for three qubits, an
+ * unknown max_len, or a list whose scratch exceeds the array (the message
+ * names the bytes needed: about 8 (w P + 16 w (ceil(max_len / 8) + 1) 16)
+ * with w = ceil(S / 16) workgroups, at most 2048, and P = 1 + D + M D + K D^2).
+ * All calls on one GPU share the array: calls that overlap on one GPU (on
+ * different streams) race, so keep them on one stream.
+ */
+int gst_loglik_noalloc(gst_ctx* ctx, const gst_gateset* gs, const gst_seqlist* seqs,
+                       const int32_t* counts, double* probs, double* objective, double* grad);
+
+/*
  * Resident requests: the sequence list and the counts are copied to the
  * device once, the prefix-sharing plan (a trie of the sequences, thesis Eq.
  * GSTFullFiducialsGerms: every distinct prefix is evaluated once) is built

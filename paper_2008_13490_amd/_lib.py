@@ -21,6 +21,7 @@ _NAMES = {0: "GST_OK", -1: "GST_EINVAL", -2: "GST_EINDEX", -3: "GST_ENONPOS", -4
 
 EXPORTED = [
     "gst_max_gates", "gst_create", "gst_destroy", "gst_sync", "gst_probs", "gst_loglik", "gst_vjp",
+    "gst_loglik_noalloc",
     "gst_req_create_host", "gst_req_create", "gst_req_footprint", "gst_req_eval", "gst_req_probs", "gst_req_vjp",
     "gst_req_destroy", "gst_req_plan_info", "gst_batch_create", "gst_batch_run", "gst_batch_nonpos",
     "gst_batch_destroy", "gst_tune_set", "gst_set_plan_jump", "gst_predict", "gst_tv_distance",
@@ -82,6 +83,9 @@ def load():
         lib.gst_sync.argtypes = [P, ctypes.POINTER(GstDiag)]
         lib.gst_probs.argtypes = [P, ctypes.POINTER(GstGateset), ctypes.POINTER(GstSeqlist), P]
         lib.gst_loglik.argtypes = [P, ctypes.POINTER(GstGateset), ctypes.POINTER(GstSeqlist), P, P, P, P]
+        if hasattr(lib, "gst_loglik_noalloc"):
+            lib.gst_loglik_noalloc.argtypes = [P, ctypes.POINTER(GstGateset), ctypes.POINTER(GstSeqlist), P, P, P, P]
+            lib.gst_loglik_noalloc.restype = I
         lib.gst_vjp.argtypes = [P, ctypes.POINTER(GstGateset), ctypes.POINTER(GstSeqlist), P, P]
         lib.gst_last_error.argtypes = []
         lib.gst_last_error.restype = ctypes.c_char_p

@@ -149,6 +149,16 @@ class Context:
                                        _ptr(counts), _ptr(p), _ptr(obj), _ptr(g)))
         return obj, p, g
 
+    def loglik_noalloc(self, gs: DeviceGateSet, seqs: DeviceSeqs, counts: torch.Tensor, out):
+        """``gst_loglik_noalloc`` into preallocated outputs (objective [1], probs [S, M]
+        or None, grad [P] or None): the call allocates nothing."""
+        counts = _require_cuda(counts, torch.int32, "counts")
+        obj, p, g = out
+        _lib.check(self.lib.gst_loglik_noalloc(self.handle, ctypes.byref(gs.as_struct()),
+                                               ctypes.byref(seqs.as_struct()), _ptr(counts), _ptr(p), _ptr(obj),
+                                               _ptr(g)))
+        return obj, p, g
+
     def vjp(self, gs: DeviceGateSet, seqs: DeviceSeqs, w: torch.Tensor) -> torch.Tensor:
         w = _require_cuda(w, torch.float64, "w")
         g = torch.empty(gs.n_params(), dtype=torch.float64, device=self._dev())

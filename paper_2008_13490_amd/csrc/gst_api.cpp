@@ -430,24 +430,42 @@ int resolve_max_len(const gst_seqlist* sl, hipStream_t stream, int64_t* out) {
   return GST_OK;
 }
 
-// Enqueue the sequence kernel over `n_items` work items and the slab reduction.
-int run_leaf(gst_ctx* ctx, DevBuf& ws, const gst::LeafLaunch& base, int64_t max_len, double* objective,
-             double* grad) {
+// Scratch of the sequence kernel and its slab reduction: the slab of partial
+// sums, their first-stage sums and the checkpoints of the reverse sweeps.
+struct LeafScratch {
+  int blocks = 0;
+  int64_t P = 0, ck_team = 0;
+  size_t slab_bytes = 0, part_bytes = 0, ck_bytes = 0;
+  size_t total() const { return slab_bytes + part_bytes + ck_bytes; }
+};
+LeafScratch leaf_scratch(const gst::LeafLaunch& a, int64_t max_len) {
+  LeafScratch z;
+  const int D = a.D;
+  const bool need_slab = a.want_grad || a.mode == gst::MODE_LOGLIK;
+  z.blocks = gst::leaf_blocks_for(D, a.n_items);
+  z.P = gst::slab_width(D, a.M, a.K);
+  const int C = gst::leaf_ckpt_interval(D);
+  z.ck_team = a.want_grad ? ((max_len + C - 1) / C + 1) * 16 : 0;
+  z.slab_bytes = need_slab ? (size_t)z.blocks * z.P * 8 : 0;
+  z.part_bytes = need_slab ? (size_t)gst::reduce_parts(z.blocks) * z.P * 8 : 0;
+  z.ck_bytes = (size_t)z.blocks * gst::leaf_teams_per_block(D) * z.ck_team * 8;
+  return z;
+}
+
+// Enqueue the sequence kernel over `n_items` work items and the slab
+// reduction, with their scratch at `buf` (leaf_scratch(...).total() bytes).
+int enqueue_leaf(gst_ctx* ctx, const gst::LeafLaunch& base, int64_t max_len, double* objective, double* grad,
+                 void* buf) {
   gst::LeafLaunch a = base;
   const int D = a.D;
   const bool need_slab = a.want_grad || a.mode == gst::MODE_LOGLIK;
-  const int blocks = gst::leaf_blocks_for(D, a.n_items);
-  const int64_t P = gst::slab_width(D, a.M, a.K);
-  const int C = gst::leaf_ckpt_interval(D);
-  const int64_t ck_team = a.want_grad ? ((max_len + C - 1) / C + 1) * 16 : 0;
-  const size_t slab_bytes = need_slab ? (size_t)blocks * P * 8 : 0;
-  const size_t part_bytes = need_slab ? (size_t)gst::reduce_parts(blocks) * P * 8 : 0;
-  const size_t ck_bytes = (size_t)blocks * gst::leaf_teams_per_block(D) * ck_team * 8;
-  int rc = ws.reserve(slab_bytes + part_bytes + ck_bytes + 256, ctx->stream);
-  if (rc) return rc;
-  a.slab = need_slab ? reinterpret_cast<double*>(ws.p) : nullptr;
-  double* part = reinterpret_cast<double*>((char*)ws.p + slab_bytes);
-  a.ckpt = a.want_grad ? reinterpret_cast<double*>((char*)ws.p + slab_bytes + part_bytes) : nullptr;
+  const LeafScratch z = leaf_scratch(a, max_len);
+  const int blocks = z.blocks;
+  const int64_t P = z.P;
+  a.slab = need_slab ? reinterpret_cast<double*>(buf) : nullptr;
+  double* part = reinterpret_cast<double*>((char*)buf + z.slab_bytes);
+  a.ckpt = a.want_grad ? reinterpret_cast<double*>((char*)buf + z.slab_bytes + z.part_bytes) : nullptr;
+  const int64_t ck_team = z.ck_team;
   a.ckpt_per_team = ck_team;
   a.max_len = (int)max_len;
   a.status = ctx->status;
@@ -463,8 +481,18 @@ int run_leaf(gst_ctx* ctx, DevBuf& ws, const gst::LeafLaunch& base, int64_t max_
   return GST_OK;
 }
 
+int run_leaf(gst_ctx* ctx, DevBuf& ws, const gst::LeafLaunch& base, int64_t max_len, double* objective,
+             double* grad) {
+  int rc = ws.reserve(leaf_scratch(base, max_len).total() + 256, ctx->stream);
+  if (rc) return rc;
+  return enqueue_leaf(ctx, base, max_len, objective, grad, ws.p);
+}
+
 int plain_eval64(gst_ctx* ctx, const gst_gateset* gs, const gst_seqlist* sl, int mode, const int32_t* counts,
                  const double* w, double* probs, double* objective, double* grad);
+
+gst::LeafLaunch plain_launch(int D, const gst_gateset* gs, const gst_seqlist* sl, int mode, const int32_t* counts,
+                             const double* w, double* probs, double* grad);
 
 int plain_eval(gst_ctx* ctx, const gst_gateset* gs, const gst_seqlist* sl, int mode, const int32_t* counts,
                const double* w, double* probs, double* objective, double* grad) {
@@ -479,6 +507,12 @@ int plain_eval(gst_ctx* ctx, const gst_gateset* gs, const gst_seqlist* sl, int m
   int64_t max_len = 0;
   rc = resolve_max_len(sl, ctx->stream, &max_len);
   if (rc) return rc;
+  const gst::LeafLaunch a = plain_launch(D, gs, sl, mode, counts, w, probs, grad);
+  return run_leaf(ctx, ctx->ws, a, max_len, objective, grad);
+}
+
+gst::LeafLaunch plain_launch(int D, const gst_gateset* gs, const gst_seqlist* sl, int mode, const int32_t* counts,
+                             const double* w, double* probs, double* grad) {
   gst::LeafLaunch a{};
   a.D = D;
   a.M = gs->n_outcomes;
@@ -497,7 +531,7 @@ int plain_eval(gst_ctx* ctx, const gst_gateset* gs, const gst_seqlist* sl, int m
   a.probs = probs;
   a.mode = mode;
   a.want_grad = grad != nullptr;
-  return run_leaf(ctx, ctx->ws, a, max_len, objective, grad);
+  return a;
 }
 
 int upload_plan(gst_req* r, const gst::HostPlan& P) {
@@ -954,6 +988,32 @@ int run_plan(gst_req* r, const gst_gateset* th, int mode, const double* w, doubl
 
 }  // namespace
 
+int gst::ctx_device(const gst_ctx* ctx) { return ctx->device; }
+
+// gst_loglik on the caller's scratch (see gst_noalloc.hip): one or two qubits,
+// max_len given; no allocation anywhere on the way.
+int gst::loglik_into_scratch(gst_ctx* ctx, const gst_gateset* gs, const gst_seqlist* sl, const int32_t* counts,
+                             double* probs, double* objective, double* grad, void* scratch, size_t scratch_bytes) {
+  if (!ctx) return fail(GST_EINVAL, "ctx is NULL");
+  if (!objective) return fail(GST_EINVAL, "objective is NULL");
+  int D = 0;
+  int rc = check_gateset(gs, &D);
+  if (rc) return rc;
+  rc = check_seqs(sl);
+  if (rc) return rc;
+  if (D == 64) return fail(GST_EINVAL, "the allocation-free call takes one or two qubits");
+  if (sl->max_len < 0) return fail(GST_EINVAL, "the allocation-free call needs max_len");
+  if (sl->max_len > (int64_t)1 << 30) return fail(GST_EINVAL, "sequence too long");
+  if (!scratch) return fail(GST_EDEVICE, "no scratch array on this device");
+  const gst::LeafLaunch a = plain_launch(D, gs, sl, gst::MODE_LOGLIK, counts, nullptr, probs, grad);
+  const size_t need = leaf_scratch(a, sl->max_len).total();
+  if (need > scratch_bytes)
+    return fail(GST_EINVAL, "the evaluation needs " + std::to_string(need) + " bytes of scratch, the array holds " +
+                                std::to_string(scratch_bytes));
+  HIP_TRY(hipSetDevice(ctx->device));
+  return enqueue_leaf(ctx, a, sl->max_len, objective, grad, scratch);
+}
+
 extern "C" {
 
 int gst_max_gates(int n_qubits) {
@@ -980,6 +1040,8 @@ int gst_create(gst_ctx** out, int device_ordinal, void* hip_stream) {
   c->stream = reinterpret_cast<hipStream_t>(hip_stream);
   HIP_TRY(hipMalloc(&c->status, 2 * sizeof(unsigned long long)));
   HIP_TRY(hipMemset(c->status, 0, 2 * sizeof(unsigned long long)));
+  const int rc = gst::scratch_bind(device_ordinal);
+  if (rc) return fail(rc, "binding the scratch array of the allocation-free call failed");
   *out = c.release();
   return GST_OK;
 }

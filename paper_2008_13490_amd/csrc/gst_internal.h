@@ -5,6 +5,7 @@
 
 #include <vector>
 
+#include "../../include/gst.h"
 #include "gst_param_tables.h"
 #include "gst_tiles.h"
 #include <hip/hip_runtime.h>
@@ -381,6 +382,14 @@ hipError_t launch_param_backward(const ParamLaunch& a, hipStream_t stream);
 // reverse fill tasks (adjoints inside the jumps into BA)
 hipError_t launch_fill_rev(const PlanArgs& a, hipStream_t stream);
 int fill_blocks_for(int64_t n_fill);
+
+// The allocation-free evaluation (gst_noalloc.hip): the scratch array's address
+// on `device`, resolved once per device (0 or a gst_status), and gst_loglik on a
+// given scratch buffer (gst_api.cpp).
+int scratch_bind(int device);
+int ctx_device(const gst_ctx* ctx);
+int loglik_into_scratch(gst_ctx* ctx, const gst_gateset* gs, const gst_seqlist* sl, const int32_t* counts,
+                        double* probs, double* objective, double* grad, void* scratch, size_t scratch_bytes);
 
 __host__ __device__ inline int64_t slab_width(int D, int M, int K) { return 1 + D + (int64_t)M * D + (int64_t)K * D * D; }
 
