@@ -394,6 +394,19 @@ int gst_mlgst(gst_ctx* ctx, int n_stages, gst_req* const* stages, int mode, cons
 int gst_avg_gate_fidelity(int n_qubits, int n_gates, const double* gates, const double* targets, double* f_avg);
 int gst_diamond_unitary(int dim, const double* U, const double* V, double* dist);
 int gst_hamiltonian_decomposition(int n_qubits, const double* G, double* h, double* angle, double* gamma);
+/*
+ * gst_hamiltonian_decomposition_target: App. J's other route, which also covers
+ * gates without a real principal logarithm (the ideal CZ and CNOT, whose
+ * transfer matrices have eigenvalues -1): h (D entries, h[0] = 0) minimizing
+ * gamma(h) = ||G - exp(L^H(h))||_F (Eq. GateDecompositionHamiltonianProjectionError)
+ * by L-BFGS, starting from the Hamiltonian of the intended target unitary U
+ * (dim x dim, dim = 2^n, row-major, interleaved real and imaginary parts):
+ * H_U = i log U with each eigenvalue's argument in (-pi, pi].  angle = |h|,
+ * gamma at the result (both may be NULL).  One or two qubits; GST_EINVAL
+ * otherwise or if the target's eigen-decomposition fails.
+ */
+int gst_hamiltonian_decomposition_target(int n_qubits, const double* G, const double* U, double* h, double* angle,
+                                         double* gamma);
 
 /*
  * Kernel timing (diagnostics).  While enabled, every kernel the context

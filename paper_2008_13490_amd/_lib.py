@@ -27,6 +27,7 @@ EXPORTED = [
     "gst_batch_destroy", "gst_tune_set", "gst_set_plan_jump", "gst_predict", "gst_tv_distance",
     "gst_param_count", "gst_param_forward", "gst_param_backward", "gst_lgst", "gst_gauge_optimize", "gst_mlgst",
     "gst_avg_gate_fidelity", "gst_diamond_unitary", "gst_hamiltonian_decomposition",
+    "gst_hamiltonian_decomposition_target",
     "gst_profile_enable", "gst_profile_only",
     "gst_profile_read", "gst_last_error",
 ]
@@ -118,7 +119,9 @@ def load():
         lib.gst_avg_gate_fidelity.argtypes = [I, I, P, P, P]
         lib.gst_diamond_unitary.argtypes = [I, P, P, P]
         lib.gst_hamiltonian_decomposition.argtypes = [I, P, P, P, P]
-        for name in ("gst_avg_gate_fidelity", "gst_diamond_unitary", "gst_hamiltonian_decomposition"):
+        lib.gst_hamiltonian_decomposition_target.argtypes = [I, P, P, P, P, P]
+        for name in ("gst_avg_gate_fidelity", "gst_diamond_unitary", "gst_hamiltonian_decomposition",
+                     "gst_hamiltonian_decomposition_target"):
             getattr(lib, name).restype = I
         lib.gst_profile_read.restype = I
         if hasattr(lib, "gst_req_create_host"):

@@ -518,6 +518,20 @@ def max_gates(n_qubits: int) -> int:
     return int(_lib.load().gst_max_gates(int(n_qubits)))
 
 
+def hamiltonian_decomposition_target(n_qubits: int, G, U):
+    """(h [D], angle |h|, gamma): h minimizing ||G - exp(L^H(h))||_F from the target
+    unitary U's Hamiltonian (``gst_hamiltonian_decomposition_target``)."""
+    import numpy as np
+    lib = _lib.load()
+    g = np.ascontiguousarray(G, np.float64)
+    u = np.ascontiguousarray(np.asarray(U, np.complex128)).view(np.float64)
+    h = np.zeros(4 ** n_qubits)
+    ang, gam = ctypes.c_double(0.0), ctypes.c_double(0.0)
+    _lib.check(lib.gst_hamiltonian_decomposition_target(n_qubits, g.ctypes.data, u.ctypes.data, h.ctypes.data,
+                                                        ctypes.byref(ang), ctypes.byref(gam)))
+    return h, ang.value, gam.value
+
+
 def set_plan_jump(ctx: Context, reps: int):
     """Germ-power jump repetitions of the sharing plans of requests created
     afterwards on ``ctx`` (``gst_set_plan_jump``; 0 = off, bit-identical

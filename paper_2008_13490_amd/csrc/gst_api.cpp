@@ -256,9 +256,9 @@ struct DevicePlan64 {
   DevBuf buf;
   int64_t *tile_row0 = nullptr, *tile_word = nullptr, *tile_ev = nullptr, *col_anchor = nullptr,
           *col_chain = nullptr, *ev_ptr = nullptr, *ev_src = nullptr, *slot_row = nullptr, *slot_ptr = nullptr,
-          *slot_seq = nullptr, *root_chains = nullptr, *rec_b = nullptr, *rec_f = nullptr, *chunk_beg = nullptr,
+          *slot_seq = nullptr, *root_chains = nullptr, *ts_tile = nullptr, *chunk_beg = nullptr,
           *chunk_end = nullptr, *gate_chunk_ptr = nullptr;
-  int32_t *tile_len = nullptr, *ev_col = nullptr;
+  int32_t *tile_len = nullptr, *ev_col = nullptr, *ts_step = nullptr;
   uint8_t* words = nullptr;
   double *FA = nullptr, *BA = nullptr, *INJ = nullptr, *GA = nullptr, *GAT = nullptr, *slab = nullptr,
          *part = nullptr, *chunk_slab = nullptr, *root_vec = nullptr;
@@ -626,7 +626,7 @@ int upload_plan(gst_req* r, const gst::HostPlan& P) {
 int upload_plan64(gst_req* r, gst::Plan64& P) {
   DevicePlan64& d = r->plan64;
   const int M = r->M, K = r->K;
-  const int64_t T = P.n_tiles(), TS = P.tile_steps(), NE = (int64_t)P.ev_col.size(), NR = (int64_t)P.rec_b.size(),
+  const int64_t T = P.n_tiles(), TS = P.tile_steps(), NE = (int64_t)P.ev_col.size(), NR = (int64_t)P.ts_tile.size(),
                 NC = (int64_t)P.chunk_beg.size(), NRC = (int64_t)P.root_chains.size();
   d.readout_blocks = (int)std::min<int64_t>(std::max<int64_t>((P.n_slots + gst::READOUT64_WAVES - 1) /
                                                                   gst::READOUT64_WAVES, 1),
@@ -640,7 +640,7 @@ int upload_plan64(gst_req* r, gst::Plan64& P) {
                o_evc = c.take<int32_t>(NE + 1), o_evs = c.take<int64_t>(NE + 1),
                o_sr = c.take<int64_t>(P.n_slots + 1), o_sp = c.take<int64_t>(P.n_slots + 2),
                o_sq = c.take<int64_t>(P.S + 1), o_rc = c.take<int64_t>(NRC + 1), o_rb = c.take<int64_t>(NR + 1),
-               o_rf = c.take<int64_t>(NR + 1), o_cb = c.take<int64_t>(NC + 1), o_ce = c.take<int64_t>(NC + 1),
+               o_rf = c.take<int32_t>(NR + 1), o_cb = c.take<int64_t>(NC + 1), o_ce = c.take<int64_t>(NC + 1),
                o_gcp = c.take<int64_t>(K + 1), o_fa = c.take<double>((size_t)P.n_rows * 64),
                o_ba = c.take<double>((size_t)P.n_rows * 64),
                o_inj = c.take<double>((size_t)(P.n_slots + P.n_chains + 1) * 64),
@@ -665,8 +665,8 @@ int upload_plan64(gst_req* r, gst::Plan64& P) {
   d.slot_ptr = reinterpret_cast<int64_t*>(b + o_sp);
   d.slot_seq = reinterpret_cast<int64_t*>(b + o_sq);
   d.root_chains = reinterpret_cast<int64_t*>(b + o_rc);
-  d.rec_b = reinterpret_cast<int64_t*>(b + o_rb);
-  d.rec_f = reinterpret_cast<int64_t*>(b + o_rf);
+  d.ts_tile = reinterpret_cast<int64_t*>(b + o_rb);
+  d.ts_step = reinterpret_cast<int32_t*>(b + o_rf);
   d.chunk_beg = reinterpret_cast<int64_t*>(b + o_cb);
   d.chunk_end = reinterpret_cast<int64_t*>(b + o_ce);
   d.gate_chunk_ptr = reinterpret_cast<int64_t*>(b + o_gcp);
@@ -697,8 +697,8 @@ int upload_plan64(gst_req* r, gst::Plan64& P) {
   if ((rc = put(d.slot_ptr, P.slot_ptr.data(), P.slot_ptr.size() * 8))) return rc;
   if ((rc = put(d.slot_seq, P.slot_seq.data(), P.slot_seq.size() * 8))) return rc;
   if ((rc = put(d.root_chains, P.root_chains.data(), NRC * 8))) return rc;
-  if ((rc = put(d.rec_b, P.rec_b.data(), NR * 8))) return rc;
-  if ((rc = put(d.rec_f, P.rec_f.data(), NR * 8))) return rc;
+  if ((rc = put(d.ts_tile, P.ts_tile.data(), NR * 8))) return rc;
+  if ((rc = put(d.ts_step, P.ts_step.data(), NR * 4))) return rc;
   if ((rc = put(d.chunk_beg, P.chunk_beg.data(), NC * 8))) return rc;
   if ((rc = put(d.chunk_end, P.chunk_end.data(), NC * 8))) return rc;
   if ((rc = put(d.gate_chunk_ptr, P.gate_chunk_ptr.data(), (K + 1) * 8))) return rc;
@@ -791,16 +791,18 @@ int run_plan64(gst_req* r, const gst_gateset* th, int mode, const double* w, dou
     }
     if (d.n_chunks > 0) {
       ProfScope ps(ctx, FAM_GEMM64);
-      gst::Gemm64Launch g{};
-      g.rec_b = d.BA;
-      g.rec_f = d.FA;
-      g.row_b = d.rec_b;
-      g.row_f = d.rec_f;
+      gst::Gemm64TsLaunch g{};
+      g.BA = d.BA;
+      g.FA = d.FA;
+      g.tile_row0 = d.tile_row0;
+      g.col_anchor = d.col_anchor;
+      g.ts_tile = d.ts_tile;
+      g.ts_step = d.ts_step;
       g.chunk_beg = d.chunk_beg;
       g.chunk_end = d.chunk_end;
       g.slab = d.chunk_slab;
       g.n_chunks = (int)d.n_chunks;
-      HIP_TRY(gst::launch_gemm64(g, ctx->stream));
+      HIP_TRY(gst::launch_gemm64_ts(g, ctx->stream));
     }
     gst::Root64Launch ro{};
     ro.INJ = d.INJ;
@@ -2187,6 +2189,23 @@ int gst_diamond_unitary(int dim, const double* U, const double* V, double* dist)
   const double d = gst::diamond_unitary(dim, U, V);
   if (d < 0) return fail(GST_EINVAL, "the eigenvalues of U^dagger V did not converge");
   *dist = d;
+  return GST_OK;
+}
+
+int gst_hamiltonian_decomposition_target(int n_qubits, const double* G, const double* U, double* h, double* angle,
+                                         double* gamma) {
+  const int D = dim_of(n_qubits);
+  if (!D || n_qubits > 2) return fail(GST_EINVAL, "n_qubits must be 1 or 2");
+  if (!G || !U || !h) return fail(GST_EINVAL, "NULL argument");
+  double g = 0.0;
+  if (gst::hamiltonian_decomposition_toward(n_qubits, G, U, h, &g))
+    return fail(GST_EINVAL, "the target's eigen-decomposition did not converge");
+  if (gamma) *gamma = g;
+  if (angle) {
+    double s = 0.0;
+    for (int k = 0; k < D; ++k) s += h[k] * h[k];
+    *angle = std::sqrt(s);
+  }
   return GST_OK;
 }
 

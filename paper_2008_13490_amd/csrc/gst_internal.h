@@ -286,6 +286,22 @@ struct Plan64Launch {
   double* INJ;               // [n_slots + n_chains][64]
   int64_t n_slots;
 };
+// dG over tile-steps: chunk c adds, for its gate, over its tile-steps (tile,
+// t), sum over the tile's 16 columns of BA[row(c, t)] FA[row(c, t - 1)]^T (row
+// t - 1 = -1: the column's anchor).
+struct Gemm64TsLaunch {
+  const double* BA;
+  const double* FA;
+  const int64_t* tile_row0;
+  const int64_t* col_anchor;
+  const int64_t* ts_tile;
+  const int32_t* ts_step;
+  const int64_t* chunk_beg;
+  const int64_t* chunk_end;
+  double* slab;              // [n_chunks][4096]
+  int n_chunks;
+};
+hipError_t launch_gemm64_ts(const Gemm64TsLaunch& a, hipStream_t stream);
 constexpr int READOUT64_WAVES = 4;
 struct Readout64Launch {
   int M;

@@ -31,6 +31,7 @@
 
 #include "gst_device.h"
 #include "gst_internal.h"
+#include "gst_plan64.h"
 
 namespace gst {
 namespace {
@@ -325,14 +326,31 @@ __global__ __launch_bounds__(256) void gate_prep64_kernel(const double* G, const
   if (k == 0 && threadIdx.x < N64) FA[threadIdx.x] = rho[threadIdx.x];
 }
 
+// Workgroup barrier for the LDS exchange of a step: waits for this wave's LDS
+// operations only, so the global stores of the step and the operand loads of
+// the next step stay in flight across it (a full __syncthreads() would wait for
+// them as well).  The memory clobber keeps the compiler from moving LDS
+// accesses across it.
+__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
 __device__ __forceinline__ void load_ops(double (&dst)[16], const double* base, int lane) {
   const auto* g = as_global(base);
 #pragma unroll
   for (int kk = 0; kk < 16; ++kk) dst[kk] = g[kk * 64 + lane];
 }
 
+// A tile's gate word and events are staged in LDS a chunk of steps at a time,
+// so that the loop over the steps reads nothing from global memory whose value
+// it needs at once: the only global loads in the loop are the next step's
+// operands (the gate, and in the reverse sweep the vectors added at the next
+// node), issued a whole step ahead.
+constexpr int CH_STEPS = 256;   // steps per staged chunk
+constexpr int CH_EVENTS = 1024; // events per staged chunk (a node has at most EV_NODE)
+constexpr int EV_NODE = kMaxNodeEvents;  // events of one node at most: its seed and a chain per child
+
 __global__ __launch_bounds__(256) void plan64_fwd_kernel(const Plan64Launch a) {
   __shared__ double Vs[2][16 * 64];
+  __shared__ uint8_t Ws[CH_STEPS + 1];
   const int tid = threadIdx.x, l = tid & 63, w = tid >> 6;
   const int c = l & 15, r4 = l >> 4;
   const int64_t tile = a.t_begin + blockIdx.x;
@@ -341,76 +359,148 @@ __global__ __launch_bounds__(256) void plan64_fwd_kernel(const Plan64Launch a) {
 #pragma unroll
   for (int v = 0; v < 4; ++v) Vs[0][(4 * w + v) * 64 + l] = fa[anc * N64 + 4 * (4 * w + v) + r4];
   const int len = uniform(a.tile_len[tile]);
-  const uint8_t* word = a.words + a.tile_word[tile];
+  const auto* word = as_global(a.words + a.tile_word[tile]);
   const int64_t row0 = a.tile_row0[tile];
   double an[16];
-  if (len > 0) load_ops(an, a.GA + ((int64_t)word[0] * 4 + w) * 1024, l);
-  __syncthreads();
   int cur = 0;
-  for (int t = 0; t < len; ++t) {
-    double ac[16];
+  for (int t0 = 0; t0 < len; t0 += CH_STEPS) {
+    const int n = len - t0 < CH_STEPS ? len - t0 : CH_STEPS;
+    // word[t0 .. t0 + n], the last one the first gate of the next chunk
+    for (int x = tid; x <= n && t0 + x < len; x += 256) Ws[x] = word[t0 + x];
+    lds_barrier();
+    if (t0 == 0) load_ops(an, a.GA + ((int64_t)uniform(Ws[0]) * 4 + w) * 1024, l);
+    for (int x = 0; x < n; ++x) {
+      const int t = t0 + x;
+      double ac[16];
 #pragma unroll
-    for (int kk = 0; kk < 16; ++kk) ac[kk] = an[kk];
-    if (t + 1 < len) load_ops(an, a.GA + ((int64_t)uniform(word[t + 1]) * 4 + w) * 1024, l);
-    d4 acc = {0.0, 0.0, 0.0, 0.0};
+      for (int kk = 0; kk < 16; ++kk) ac[kk] = an[kk];
+      if (t + 1 < len) load_ops(an, a.GA + ((int64_t)uniform(Ws[x + 1]) * 4 + w) * 1024, l);
+      d4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int kk = 0; kk < 16; ++kk) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ac[kk], Vs[cur][kk * 64 + l], acc, 0, 0, 0);
-    // rows 16w + 4v + r4 of column c: operand block kk = 4w + v of the next step
-    auto* dst = as_global(a.FA + (row0 + (int64_t)t * 16 + c) * N64 + 16 * w + r4);
+      for (int kk = 0; kk < 16; ++kk)
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ac[kk], Vs[cur][kk * 64 + l], acc, 0, 0, 0);
+      // rows 16w + 4v + r4 of column c: operand block kk = 4w + v of the next step
+      auto* dst = as_global(a.FA + (row0 + (int64_t)t * 16 + c) * N64 + 16 * w + r4);
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      Vs[cur ^ 1][(4 * w + v) * 64 + l] = acc[v];
-      dst[4 * v] = acc[v];
+      for (int v = 0; v < 4; ++v) {
+        Vs[cur ^ 1][(4 * w + v) * 64 + l] = acc[v];
+        dst[4 * v] = acc[v];
+      }
+      lds_barrier();
+      cur ^= 1;
     }
-    __syncthreads();
-    cur ^= 1;
   }
 }
 
-// Reverse sweep of a tile: b <- b + (seeds, adjoints of the chains anchored
-// here); store b; b <- G^T b.  At the end each chain delivers b to its anchor.
+// Rows 4(4w + v) + r4 of the INJ rows that events of one node add to column c:
+// up to EV_NODE rows, loaded into fixed registers (absent ones stay zero) and
+// added later in the events' order.
+struct NodeAdds {
+  double r[EV_NODE][4];
+};
+
+__device__ __forceinline__ void load_node_adds(NodeAdds& q, const int64_t* Ev, int j0, int j1, int c, int w, int r4,
+                                               const double* inj) {
+  const auto* g = as_global(inj);
+#pragma unroll
+  for (int e = 0; e < EV_NODE; ++e)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) q.r[e][v] = 0.0;
+  int slot = 0;
+  for (int j = j0; j < j1; ++j) {
+    const int64_t ev = Ev[j];
+    if ((int)(ev & 15) != c) continue;
+    const int64_t src = ev >> 4;
+#pragma unroll
+    for (int e = 0; e < EV_NODE; ++e)
+      if (slot == e) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) q.r[e][v] = g[src * N64 + 4 * (4 * w + v) + r4];
+      }
+    ++slot;
+  }
+}
+
+// Reverse sweep of a tile.  b_t, the adjoint of the node after step t, is
+// G_{t+1}^T b_{t+1} plus the node's seed and the adjoints of the chains anchored
+// there (in that order, summed first); it is stored, and G_t^T b_t with the
+// events of node t-1 added becomes b_{t-1}.  The events' rows are loaded at the
+// start of the step, the next gate's operands a step ahead.  At the end each
+// chain delivers G_0^T b_0 to its anchor.
 __global__ __launch_bounds__(256) void plan64_bwd_kernel(const Plan64Launch a) {
   __shared__ double Bs[2][16 * 64];
+  __shared__ uint8_t Ws[CH_STEPS + 1];
+  __shared__ int32_t Es[CH_STEPS + 2];
+  __shared__ int64_t Ev[CH_EVENTS];
   const int tid = threadIdx.x, l = tid & 63, w = tid >> 6;
   const int c = l & 15, r4 = l >> 4;
   const int64_t tile = a.t_begin + blockIdx.x;
-#pragma unroll
-  for (int v = 0; v < 4; ++v) Bs[0][(4 * w + v) * 64 + l] = 0.0;
   const int len = uniform(a.tile_len[tile]);
-  const uint8_t* word = a.words + a.tile_word[tile];
+  const auto* word = as_global(a.words + a.tile_word[tile]);
   const int64_t row0 = a.tile_row0[tile];
-  const int64_t eb = a.tile_ev[tile];
-  const auto* inj = as_global(a.INJ);
+  const auto* evp = as_global(a.ev_ptr + a.tile_ev[tile]);
+  const auto* evc = as_global(a.ev_col);
+  const auto* evs = as_global(a.ev_src);
   double an[16];
-  if (len > 0) load_ops(an, a.GAT + ((int64_t)word[len - 1] * 4 + w) * 1024, l);
-  __syncthreads();
   int cur = 0;
-  for (int t = len - 1; t >= 0; --t) {
-    double ac[16];
+  for (int t1 = len; t1 > 0;) {
+    // chunk [t0, t1) with at most CH_STEPS steps and CH_EVENTS events
+    // (and the events of step t0 - 1, added at the end of step t0)
+    int t0 = t1 - CH_STEPS > 0 ? t1 - CH_STEPS : 0;
+    const int64_t e1 = uniform64(evp[t1]);
+    while (t1 - t0 > 1 && uniform64(evp[t0 > 0 ? t0 - 1 : 0]) + CH_EVENTS < e1) t0 = t1 - (t1 - t0) / 2;
+    const int s0 = t0 > 0 ? t0 - 1 : 0;
+    const int64_t e0 = uniform64(evp[s0]);
+    const int n = t1 - t0;
+    // Ws[x] = word[t0 - 1 + x] (x = 0 only if t0 > 0); Es[x] = events before step s0 + x
+    for (int x = tid; x <= n; x += 256)
+      if (x > 0 || t0 > 0) Ws[x] = word[t0 - 1 + x];
+    for (int x = tid; x <= t1 - s0; x += 256) Es[x] = (int32_t)(evp[s0 + x] - e0);
+    for (int j = tid; j < (int)(e1 - e0); j += 256) Ev[j] = (evs[e0 + j] << 4) | (int64_t)evc[e0 + j];
+    lds_barrier();
+    if (t1 == len) {
+      // b of the last node: its events alone
+      NodeAdds q;
+      load_node_adds(q, Ev, Es[t1 - 1 - s0], Es[t1 - s0], c, w, r4, a.INJ);
 #pragma unroll
-    for (int kk = 0; kk < 16; ++kk) ac[kk] = an[kk];
-    if (t > 0) load_ops(an, a.GAT + ((int64_t)uniform(word[t - 1]) * 4 + w) * 1024, l);
-    // events of this node, in their fixed order; every thread adds to its own entries
-    const int64_t e0 = uniform64(a.ev_ptr[eb + t]), e1 = uniform64(a.ev_ptr[eb + t + 1]);
-    for (int64_t e = e0; e < e1; ++e) {
-      const int ce = uniform(a.ev_col[e]);
-      const int64_t src = uniform64(a.ev_src[e]);
-      if (c == ce) {
+      for (int v = 0; v < 4; ++v) {
+        double add = q.r[0][v];
 #pragma unroll
-        for (int v = 0; v < 4; ++v) Bs[cur][(4 * w + v) * 64 + l] += inj[src * N64 + 4 * (4 * w + v) + r4];
+        for (int e = 1; e < EV_NODE; ++e) add += q.r[e][v];
+        Bs[0][(4 * w + v) * 64 + l] = add;
       }
+      load_ops(an, a.GAT + ((int64_t)uniform(Ws[n]) * 4 + w) * 1024, l);
+      lds_barrier();
     }
-    __syncthreads();
-    auto* dst = as_global(a.BA + (row0 + (int64_t)t * 16 + c) * N64 + r4);
+    for (int x = n - 1; x >= 0; --x) {
+      const int t = t0 + x;
+      double ac[16];
 #pragma unroll
-    for (int v = 0; v < 4; ++v) dst[4 * (4 * w + v)] = Bs[cur][(4 * w + v) * 64 + l];
-    d4 acc = {0.0, 0.0, 0.0, 0.0};
+      for (int kk = 0; kk < 16; ++kk) ac[kk] = an[kk];
+      if (t > 0) load_ops(an, a.GAT + ((int64_t)uniform(Ws[x]) * 4 + w) * 1024, l);
+      NodeAdds q;  // events of node t - 1
+      if (t > 0) load_node_adds(q, Ev, Es[t - 1 - s0], Es[t - s0], c, w, r4, a.INJ);
+      auto* dst = as_global(a.BA + (row0 + (int64_t)t * 16 + c) * N64 + r4);
 #pragma unroll
-    for (int kk = 0; kk < 16; ++kk) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ac[kk], Bs[cur][kk * 64 + l], acc, 0, 0, 0);
+      for (int v = 0; v < 4; ++v) dst[4 * (4 * w + v)] = Bs[cur][(4 * w + v) * 64 + l];
+      d4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int v = 0; v < 4; ++v) Bs[cur ^ 1][(4 * w + v) * 64 + l] = acc[v];
-    __syncthreads();
-    cur ^= 1;
+      for (int kk = 0; kk < 16; ++kk)
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ac[kk], Bs[cur][kk * 64 + l], acc, 0, 0, 0);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        double add = 0.0;
+        if (t > 0) {
+          add = q.r[0][v];
+#pragma unroll
+          for (int e = 1; e < EV_NODE; ++e) add += q.r[e][v];
+        }
+        Bs[cur ^ 1][(4 * w + v) * 64 + l] = acc[v] + add;
+      }
+      lds_barrier();
+      cur ^= 1;
+    }
+    t1 = t0;
   }
   const int64_t ch = a.col_chain[tile * 16 + c];
   if (ch >= 0) {
@@ -420,17 +510,74 @@ __global__ __launch_bounds__(256) void plan64_bwd_kernel(const Plan64Launch a) {
   }
 }
 
+// The gate gradient of the grouped-chain plan: one workgroup per chunk of
+// tile-steps of one gate, wave w owning rows 16w .. 16w+15 of dG.  A tile-step
+// contributes sum_c b_c f_c^T over its sixteen columns: four MFMAs over the
+// columns per 16 x 16 output tile, operands read straight from the arenas
+// (a tile-step's adjoint rows are consecutive, and so are its state rows
+// except at step 0, where they are the columns' anchors).
+__global__ __launch_bounds__(256) void gemm64_ts_kernel(const Gemm64TsLaunch a) {
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int z = lane >> 4, ii = lane & 15;
+  const int64_t ch = blockIdx.x;
+  const int64_t x0 = a.chunk_beg[ch], x1 = a.chunk_end[ch];
+  const auto* g_b = as_global(a.BA);
+  const auto* g_f = as_global(a.FA);
+  d4 acc[4];
+#pragma unroll
+  for (int tc = 0; tc < 4; ++tc) acc[tc] = d4{0.0, 0.0, 0.0, 0.0};
+  for (int64_t x = x0; x < x1; ++x) {
+    const int64_t tile = a.ts_tile[x];
+    const int t = a.ts_step[x];
+    const int64_t rb0 = a.tile_row0[tile] + (int64_t)t * 16;
+#pragma unroll
+    for (int kb = 0; kb < 4; ++kb) {
+      const int col = 4 * kb + z;
+      const int64_t rf = t > 0 ? rb0 - 16 + col : a.col_anchor[tile * 16 + col];
+      const double av = g_b[(rb0 + col) * N64 + 16 * w + ii];
+      double bv[4];
+#pragma unroll
+      for (int tc = 0; tc < 4; ++tc) bv[tc] = g_f[rf * N64 + 16 * tc + ii];
+#pragma unroll
+      for (int tc = 0; tc < 4; ++tc) acc[tc] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv[tc], acc[tc], 0, 0, 0);
+    }
+  }
+  double* out = a.slab + ch * GATE64;
+#pragma unroll
+  for (int tc = 0; tc < 4; ++tc)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = 4 * v + (lane >> 4), cc = lane & 15;
+      out[(16 * w + r) * N64 + 16 * tc + cc] = acc[tc][v];
+    }
+}
+
 // Readouts per seed slot (the sequences ending at one node): p = E f in the
 // plain order, the objective, dL/dp, the seed E^T (sum of the slot's dL/dp),
 // and dL/dE.  Slot s goes to wave s mod (waves of the launch), so every sum
 // has a fixed order; each wave writes one partial row [objective | 0 | dL/dE].
+// E row m (LDS) dotted with x, columns ascending from 0.
+__device__ __forceinline__ double mv_lds_row(const double* row, int lane, double x) {
+  double acc = 0.0;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const double xr = row_copy(x, r, lane);
+    Row16 R = load_row(row + 16 * r);
+    acc = dot16_from(acc, xr, R);
+  }
+  return acc;
+}
+
 __global__ __launch_bounds__(READOUT64_WAVES * 64) void readout64_kernel(const Readout64Launch a) {
+  __shared__ double Es[16 * N64];
   const int l = threadIdx.x & 63;
   const int64_t wv = (int64_t)blockIdx.x * READOUT64_WAVES + (threadIdx.x >> 6);
   const int64_t nw = (int64_t)gridDim.x * READOUT64_WAVES;
   const int M = a.M;
+  for (int x = threadIdx.x; x < M * N64; x += READOUT64_WAVES * 64) Es[x] = a.E[x];
+  __syncthreads();
   const int mrow = l < M ? l : M - 1;
-  const double* Erow = a.E + (size_t)mrow * N64;
+  const double* Erow = Es + mrow * N64;
   const auto* fa = as_global(a.FA);
   const auto* g_counts = as_global(a.counts);
   const auto* g_W = as_global(a.W);
@@ -443,7 +590,7 @@ __global__ __launch_bounds__(READOUT64_WAVES * 64) void readout64_kernel(const R
   unsigned nonpos = 0;
   for (int64_t s = wv; s < a.n_slots; s += nw) {
     const double f = fa[a.slot_row[s] * N64 + l];
-    const double p = mv_global_row(Erow, l, f);
+    const double p = mv_lds_row(Erow, l, f);
     double dps = 0.0;
     const int64_t q1 = a.slot_ptr[s + 1];
     for (int64_t q = a.slot_ptr[s]; q < q1; ++q) {
@@ -474,7 +621,7 @@ __global__ __launch_bounds__(READOUT64_WAVES * 64) void readout64_kernel(const R
       if (m < M) {
         const double dpm = __shfl(dps, m);
         dE[m] = fma(dpm, f, dE[m]);
-        b = fma(a.E[(size_t)m * N64 + l], dpm, b);
+        b = fma(Es[m * N64 + l], dpm, b);
       }
     }
     a.INJ[s * N64 + l] = b;
@@ -509,6 +656,12 @@ hipError_t launch_gate_prep64(const double* G, const double* rho, int K, double*
                               hipStream_t stream) {
   if (K < 1) return hipErrorInvalidValue;
   gst_launch(gate_prep64_kernel, dim3(K), dim3(256), 0, stream, G, rho, GA, GAT, FA);
+  return hipGetLastError();
+}
+
+hipError_t launch_gemm64_ts(const Gemm64TsLaunch& a, hipStream_t stream) {
+  if (a.n_chunks <= 0) return hipSuccess;
+  gst_launch(gemm64_ts_kernel, dim3(a.n_chunks), dim3(256), 0, stream, a);
   return hipGetLastError();
 }
 

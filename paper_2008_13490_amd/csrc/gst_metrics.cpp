@@ -285,4 +285,166 @@ int hamiltonian_decomposition(int n, const double* G, double* h, double* gamma) 
   return 0;
 }
 
+namespace {
+
+// The Pauli products P_k (unnormalized, qubit 0 the leftmost factor) as
+// interleaved complex d x d matrices.
+std::vector<double> pauli_products(int n) {
+  const int d = 1 << n, D = d * d;
+  static const double S[4][8] = {{1, 0, 0, 0, 0, 0, 1, 0},   // I
+                                 {0, 0, 1, 0, 1, 0, 0, 0},   // X
+                                 {0, 0, 0, -1, 0, 1, 0, 0},  // Y
+                                 {1, 0, 0, 0, 0, 0, -1, 0}}; // Z
+  std::vector<double> P((size_t)D * d * d * 2, 0.0);
+  for (int k = 0; k < D; ++k)
+    for (int r = 0; r < d; ++r)
+      for (int c = 0; c < d; ++c) {
+        double re = 1.0, im = 0.0;
+        for (int q = 0; q < n; ++q) {
+          const int a = (k >> (2 * (n - 1 - q))) & 3;
+          const int br = (r >> (n - 1 - q)) & 1, bc = (c >> (n - 1 - q)) & 1;
+          const double sr = S[a][(br * 2 + bc) * 2], si = S[a][(br * 2 + bc) * 2 + 1];
+          const double nr = re * sr - im * si, ni = re * si + im * sr;
+          re = nr;
+          im = ni;
+        }
+        const size_t at = (((size_t)k * d + r) * d + c) * 2;
+        P[at] = re;
+        P[at + 1] = im;
+      }
+  return P;
+}
+
+// Frechet derivative of exp at A in direction E: the upper-right block of exp([[A, E], [0, A]]).
+void expm_frechet(int D, const double* A, const double* E, double* Z) {
+  const int D2 = 2 * D;
+  std::vector<double> B((size_t)D2 * D2, 0.0), X((size_t)D2 * D2);
+  for (int i = 0; i < D; ++i)
+    for (int j = 0; j < D; ++j) {
+      B[(size_t)i * D2 + j] = A[(size_t)i * D + j];
+      B[(size_t)(i + D) * D2 + j + D] = A[(size_t)i * D + j];
+      B[(size_t)i * D2 + j + D] = E[(size_t)i * D + j];
+    }
+  expm_real(D2, B.data(), X.data());
+  for (int i = 0; i < D; ++i)
+    for (int j = 0; j < D; ++j) Z[(size_t)i * D + j] = X[(size_t)i * D2 + j + D];
+}
+
+}  // namespace
+
+bool target_hamiltonian(int n, const double* U, double* h) {
+  const int d = 1 << n, D = d * d, d2 = 2 * d;
+  // A = (U + U^dagger) / 2 + c (U - U^dagger) / (2i), Hermitian with the
+  // eigenvectors of U; its real embedding [[X, -Y], [Y, X]] (A = X + iY)
+  const double c = 0.6180339887498949;
+  std::vector<double> Sm((size_t)d2 * d2), V((size_t)d2 * d2);
+  for (int r = 0; r < d; ++r)
+    for (int q = 0; q < d; ++q) {
+      const double ur = U[((size_t)r * d + q) * 2], ui = U[((size_t)r * d + q) * 2 + 1];
+      const double vr = U[((size_t)q * d + r) * 2], vi = -U[((size_t)q * d + r) * 2 + 1];  // (U^dagger)[r][q]
+      const double xr = 0.5 * (ur + vr) + c * 0.5 * (ui - vi);  // (U - U^dagger) / (2i) = -i (U - U^dagger) / 2
+      const double xi = 0.5 * (ui + vi) - c * 0.5 * (ur - vr);
+      Sm[(size_t)r * d2 + q] = xr;
+      Sm[(size_t)(r + d) * d2 + q + d] = xr;
+      Sm[(size_t)r * d2 + q + d] = -xi;
+      Sm[(size_t)(r + d) * d2 + q] = xi;
+    }
+  if (!jacobi_sym(d2, Sm, V)) return false;
+  std::vector<double> mu(d2);
+  for (int a = 0; a < d2; ++a) mu[a] = Sm[(size_t)a * d2 + a];
+  // H = -sum over eigenvalue clusters of theta Pi (Pi the cluster's complex projector)
+  std::vector<double> H((size_t)d * d * 2, 0.0);
+  std::vector<char> done(d2, 0);
+  for (int a = 0; a < d2; ++a) {
+    if (done[a]) continue;
+    std::vector<int> cl;
+    for (int b = a; b < d2; ++b)
+      if (!done[b] && fabs(mu[b] - mu[a]) <= 1e-8) {
+        cl.push_back(b);
+        done[b] = 1;
+      }
+    // real projector onto the cluster's eigenvectors; Pi = its [0:d][0:d] + i [d:2d][0:d] blocks
+    std::vector<double> Pr((size_t)d * d, 0.0), Pi((size_t)d * d, 0.0);
+    for (int b : cl)
+      for (int r = 0; r < d; ++r)
+        for (int q = 0; q < d; ++q) {
+          Pr[(size_t)r * d + q] += V[(size_t)r * d2 + b] * V[(size_t)q * d2 + b];
+          Pi[(size_t)r * d + q] += V[(size_t)(r + d) * d2 + b] * V[(size_t)q * d2 + b];
+        }
+    double m = 0.0;
+    for (int r = 0; r < d; ++r) m += Pr[(size_t)r * d + r];
+    // lambda = Tr(Pi U) / m
+    double lr = 0.0, li = 0.0;
+    for (int r = 0; r < d; ++r)
+      for (int q = 0; q < d; ++q) {
+        const double ar = Pr[(size_t)r * d + q], ai = Pi[(size_t)r * d + q];
+        const double ur = U[((size_t)q * d + r) * 2], ui = U[((size_t)q * d + r) * 2 + 1];
+        lr += ar * ur - ai * ui;
+        li += ar * ui + ai * ur;
+      }
+    double theta = atan2(li / m, lr / m);
+    if (theta <= -M_PI + 1e-12) theta = M_PI;  // the principal argument of -1 is pi
+    for (size_t x = 0; x < (size_t)d * d; ++x) {
+      H[2 * x] -= theta * Pr[x];
+      H[2 * x + 1] -= theta * Pi[x];
+    }
+  }
+  // h_k = 2 Re Tr(P_k H) / d
+  const std::vector<double> P = pauli_products(n);
+  h[0] = 0.0;
+  for (int k = 1; k < D; ++k) {
+    double t = 0.0;
+    for (int r = 0; r < d; ++r)
+      for (int q = 0; q < d; ++q) {
+        const size_t p = (((size_t)k * d + r) * d + q) * 2, x = ((size_t)q * d + r) * 2;
+        t += P[p] * H[x] - P[p + 1] * H[x + 1];
+      }
+    h[k] = 2.0 * t / d;
+  }
+  return true;
+}
+
+int hamiltonian_decomposition_toward(int n, const double* G, const double* U, double* h, double* gamma) {
+  const int D = 1 << (2 * n);
+  const size_t DD = (size_t)D * D;
+  if (!target_hamiltonian(n, U, h)) return -1;
+  std::vector<double> y, zr, zi;
+  param_tables(n, &y, &zr, &zi);  // L^H[a][b] = h_{a^b} y[a][b]
+  std::vector<double> L(DD), E(DD), R(DD), LT(DD), Z(DD);
+  auto build = [&](const double* x) {
+    std::fill(L.begin(), L.end(), 0.0);
+    for (int a = 0; a < D; ++a)
+      for (int b = 0; b < D; ++b)
+        if (a != b) L[(size_t)a * D + b] = x[(a ^ b) - 1] * y[(size_t)a * D + b];
+  };
+  // f = ||G - exp(L^H)||_F^2; df/dh_k = -2 sum_a Z[a][a^k] y[a][a^k], Z = Dexp_{L^T}(G - exp(L))
+  auto f = [&](const double* x, double* g) -> double {
+    build(x);
+    expm_real(D, L.data(), E.data());
+    double v = 0.0;
+    for (size_t q = 0; q < DD; ++q) {
+      R[q] = G[q] - E[q];
+      v += R[q] * R[q];
+    }
+    for (int a = 0; a < D; ++a)
+      for (int b = 0; b < D; ++b) LT[(size_t)a * D + b] = L[(size_t)b * D + a];
+    expm_frechet(D, LT.data(), R.data(), Z.data());
+    for (int k = 1; k < D; ++k) {
+      double s = 0.0;
+      for (int a = 0; a < D; ++a) s += Z[(size_t)a * D + (a ^ k)] * y[(size_t)a * D + (a ^ k)];
+      g[k - 1] = -2.0 * s;
+    }
+    return v;
+  };
+  std::vector<double> x(h + 1, h + D);
+  lbfgs(D - 1, x.data(), f, 20, 1e-14, 2000);
+  h[0] = 0.0;
+  for (int k = 1; k < D; ++k) h[k] = x[k - 1];
+  build(x.data());
+  expm_real(D, L.data(), E.data());
+  for (size_t q = 0; q < DD; ++q) E[q] -= G[q];
+  *gamma = fro(D, E.data());
+  return 0;
+}
+
 }  // namespace gst

@@ -37,4 +37,16 @@ bool logm_real(int D, const double* G, double* L);
 // 0, or -1 without a real principal logarithm.
 int hamiltonian_decomposition(int n, const double* G, double* h, double* gamma);
 
+// h (h_0 = 0) of the target's Hamiltonian H = i log U (U the d x d unitary,
+// row-major, interleaved real and imaginary parts; each eigenvalue's argument
+// in (-pi, pi]), so that U = exp(-iH) up to a global phase, H = sum_k h_k P_k / 2.
+// false if the eigen-decomposition fails.
+bool target_hamiltonian(int n, const double* U, double* h);
+
+// App. J for gates with or without a real principal logarithm: h minimizing
+// gamma(h) = ||G - exp(L^H(h))||_F (L-BFGS, gradient from the Frechet
+// derivative of exp) starting from the target's Hamiltonian; gamma at the
+// result.  0, or -1 if the target's eigen-decomposition fails.
+int hamiltonian_decomposition_toward(int n, const double* G, const double* U, double* h, double* gamma);
+
 }  // namespace gst

@@ -99,11 +99,20 @@ bool build_plan64(const int64_t* off, const uint8_t* gates, int64_t S, int K, co
   std::vector<int32_t> height((size_t)N, 0);
   for (int64_t n = N - 1; n >= 1; --n) height[parent[n]] = std::max(height[parent[n]], height[n] + 1);
   std::vector<int32_t> heavy((size_t)N, -1);
+  std::vector<int32_t> long_kids((size_t)N, 0);
   for (int64_t n = 1; n < N; ++n) {
     const int32_t p = parent[n];
     if (p == 0) continue;  // the root is no chain node: every child of the root heads a chain
     if (heavy[p] < 0 || height[n] > height[heavy[p]]) heavy[p] = (int32_t)n;
+    if (height[n] + 1 >= opt.split_height) long_kids[p] += 1;
   }
+  // A chain ends at a node with two or more long children: the chains hanging
+  // there then start together one level later, instead of the sibling chains
+  // waiting for the end of a long chain that merely passes through the node
+  // (the preparation fiducials of Eq. GSTFullFiducialsGerms are such nodes:
+  // every germ power hangs below them).
+  for (int64_t n = 1; n < N; ++n)
+    if (long_kids[n] >= 2) heavy[n] = -1;
 
   // ---- 3. chains in increasing head id and their anchors ----
   std::vector<int32_t> chain_of((size_t)N, -1);
@@ -162,7 +171,8 @@ bool build_plan64(const int64_t* off, const uint8_t* gates, int64_t S, int K, co
     for (int64_t c = 0; c < C; ++c) remaining[group_of[c]] += 1;
     std::vector<std::vector<int32_t>> pending((size_t)n_groups);
     std::vector<int32_t> next = bucket0;
-    int64_t done = 0;
+    int64_t done = 0, long_left = 0;
+    for (int64_t c = 0; c < C; ++c) long_left += clen[c] >= opt.split_height;
     for (int32_t L = 0; done < C; ++L) {
       for (int32_t c : next) pending[group_of[c]].push_back(c);
       next.clear();
@@ -184,17 +194,47 @@ bool build_plan64(const int64_t* off, const uint8_t* gates, int64_t S, int K, co
         done += (int64_t)take;
         pl.erase(pl.begin(), pl.begin() + (std::ptrdiff_t)take);
       };
+      // Short chains run as soon as their tiles fill.  Long chains wait until
+      // every long chain is ready and then run together, at one level: the
+      // time of a level is that of its longest tile, and a long chain has only
+      // short chains anchored on it (a chain ends where two long ones part),
+      // so holding the long chains back delays nothing they feed but short ones.
       bool progress = false;
+      int64_t long_pending = 0;
       for (int32_t g : open) {
         const size_t n = pending[g].size();
+        if (clen[pending[g][0]] >= opt.split_height) {
+          long_pending += (int64_t)n;
+          continue;
+        }
         const size_t take = (int64_t)n == remaining[g] ? n : n / (size_t)W * (size_t)W;
         if (take) {
           run(g, take);
           progress = true;
         }
       }
+      if (!progress && long_pending > 0 && long_pending == long_left) {
+        for (int32_t g : open)
+          if (!pending[g].empty() && clen[pending[g][0]] >= opt.split_height) {
+            long_left -= (int64_t)pending[g].size();
+            run(g, pending[g].size());
+          }
+        progress = true;
+      }
+      // no full tile anywhere: the waiting short chains run in partial tiles,
+      // and only if there are none, the long ones
       if (!progress)
-        for (int32_t g : open) run(g, pending[g].size());
+        for (int32_t g : open)
+          if (!pending[g].empty() && clen[pending[g][0]] < opt.split_height) {
+            run(g, pending[g].size());
+            progress = true;
+          }
+      if (!progress)
+        for (int32_t g : open)
+          if (!pending[g].empty()) {
+            long_left -= (int64_t)pending[g].size();
+            run(g, pending[g].size());
+          }
     }
   }
   std::stable_sort(tiles.begin(), tiles.end(), [&](const TileDesc& a, const TileDesc& b) {
@@ -287,6 +327,9 @@ bool build_plan64(const int64_t* off, const uint8_t* gates, int64_t S, int K, co
           P.ev_col.push_back(c);
           P.ev_src.push_back(slot_of_node[x]);
         }
+        // a node's events (its seed, the chains anchored there): the kernels
+        // hold at most max_node_events of them in registers
+        if ((slot_of_node[x] >= 0) + (anch_ptr[x + 1] - anch_ptr[x]) > opt.max_node_events) return false;
         for (int64_t k = anch_ptr[x]; k < anch_ptr[x + 1]; ++k) {
           P.ev_col.push_back(c);
           P.ev_src.push_back(P.n_slots + anch_list[k]);
@@ -316,12 +359,28 @@ bool build_plan64(const int64_t* off, const uint8_t* gates, int64_t S, int K, co
         }
       }
   }
+  // tile-steps grouped by gate (tile order, then step), chunked per gate
+  std::vector<int64_t> ts_ptr((size_t)K + 1, 0);
+  for (int64_t ti = 0; ti < T; ++ti)
+    for (int64_t t = 0; t < P.tile_len[ti]; ++t) ts_ptr[P.words[P.tile_word[ti] + t] + 1] += 1;
+  for (int k = 0; k < K; ++k) ts_ptr[k + 1] += ts_ptr[k];
+  P.ts_tile.resize((size_t)ts_ptr[K]);
+  P.ts_step.resize((size_t)ts_ptr[K]);
+  {
+    std::vector<int64_t> fill(ts_ptr.begin(), ts_ptr.end() - 1);
+    for (int64_t ti = 0; ti < T; ++ti)
+      for (int64_t t = 0; t < P.tile_len[ti]; ++t) {
+        const int64_t r = fill[P.words[P.tile_word[ti] + t]]++;
+        P.ts_tile[r] = ti;
+        P.ts_step[r] = (int32_t)t;
+      }
+  }
   P.gate_chunk_ptr.assign((size_t)K + 1, 0);
   for (int k = 0; k < K; ++k) {
     P.gate_chunk_ptr[k] = (int64_t)P.chunk_beg.size();
-    for (int64_t b = P.rec_gate_ptr[k]; b < P.rec_gate_ptr[k + 1]; b += opt.chunk) {
+    for (int64_t b = ts_ptr[k]; b < ts_ptr[k + 1]; b += opt.ts_chunk) {
       P.chunk_beg.push_back(b);
-      P.chunk_end.push_back(std::min<int64_t>(b + opt.chunk, P.rec_gate_ptr[k + 1]));
+      P.chunk_end.push_back(std::min<int64_t>(b + opt.ts_chunk, ts_ptr[k + 1]));
     }
   }
   P.gate_chunk_ptr[K] = (int64_t)P.chunk_beg.size();

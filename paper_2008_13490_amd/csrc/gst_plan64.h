@@ -34,12 +34,20 @@
 
 namespace gst {
 
+// Events of one node at most: its seed and the chains anchored there, at most
+// one per child (K <= 5 for three qubits; a chain that ends at a node leaves
+// every child to chains anchored there); plans that would need more are refused.
+constexpr int kMaxNodeEvents = 6;
+
 struct Plan64Options {
   int tile_cols = 16;                 // chains per tile (the MFMA width)
   double max_row_ratio = 0.5;         // use the plan only if its rows (padding included) <= ratio * total steps
   double min_fill = 0.0;              // ... and live columns fill at least this share of tile rows
   int64_t max_nodes = 1LL << 26;
-  int chunk = 8192;                   // gradient records per chunk
+  int chunk = 8192;                   // gradient records per chunk (the records of the CPU tests)
+  int ts_chunk = 32;                  // tile-steps per chunk of the gradient GEMM
+  int max_node_events = kMaxNodeEvents;  // refuse plans with more events at one node
+  int split_height = 32;              // a chain ends at a node with two children of at least this height
 };
 
 struct Plan64 {
@@ -74,7 +82,12 @@ struct Plan64 {
   // gradient records grouped by gate: dG_k += BA[rec_b] FA[rec_f]^T
   std::vector<int64_t> rec_b, rec_f;
   std::vector<int64_t> rec_gate_ptr;     // [K + 1]
-  std::vector<int64_t> chunk_beg, chunk_end, gate_chunk_ptr;  // chunks of one gate each; [K + 1]
+  // the same records as tile-steps (sixteen records each: the rows of the tile's
+  // columns at step t, and the rows before them), grouped by gate, in chunks of
+  // at most `ts_chunk` tile-steps of one gate
+  std::vector<int64_t> ts_tile;          // tile of each tile-step
+  std::vector<int32_t> ts_step;          // its step
+  std::vector<int64_t> chunk_beg, chunk_end, gate_chunk_ptr;  // ranges of tile-steps; [K + 1]
   int64_t n_tiles() const { return (int64_t)tile_row0.size(); }
   int64_t tile_steps() const { return (int64_t)ev_ptr.size() - 1; }
 };

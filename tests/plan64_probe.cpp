@@ -6,22 +6,30 @@
 
 namespace {
 gst::Plan64 g;
+int g_max_events = gst::Plan64Options().max_node_events;
 }
 
 extern "C" {
 
+// Events per node the following builds allow (the library's bound by default;
+// the CPU interpreter holds any number).
+void plan64_set_max_events(int n) { g_max_events = n; }
+
 // sizes: used, n_rows, n_tiles, n_levels, n_chains, n_slots, n_events,
-//        n_records, words, tile steps, root_slot, root chains, n_nodes, chunks
+//        n_records, words, tile steps, root_slot, root chains, n_nodes, chunks,
+//        gradient tile-steps
 int plan64_build(const int64_t* off, const uint8_t* gates, int64_t S, int K, double ratio, double fill,
                  int chunk, int64_t* sizes) {
   gst::Plan64Options opt;
   opt.max_row_ratio = ratio;
   opt.min_fill = fill;
   opt.chunk = chunk;
+  opt.max_node_events = g_max_events;
   const bool used = gst::build_plan64(off, gates, S, K, opt, &g);
-  const int64_t v[14] = {used, g.n_rows, g.n_tiles(), g.n_levels, g.n_chains, g.n_slots, (int64_t)g.ev_col.size(),
+  const int64_t v[15] = {used, g.n_rows, g.n_tiles(), g.n_levels, g.n_chains, g.n_slots, (int64_t)g.ev_col.size(),
                          (int64_t)g.rec_b.size(), (int64_t)g.words.size(), g.tile_steps(), g.root_slot,
-                         (int64_t)g.root_chains.size(), g.n_nodes, (int64_t)g.chunk_beg.size()};
+                         (int64_t)g.root_chains.size(), g.n_nodes, (int64_t)g.chunk_beg.size(),
+                         (int64_t)g.ts_tile.size()};
   std::memcpy(sizes, v, sizeof v);
   return 0;
 }
@@ -41,6 +49,9 @@ void plan64_records(int64_t* rec_b, int64_t* rec_f, int64_t* rec_gate_ptr, int64
                     int64_t* gate_chunk_ptr) {
   CP(rec_b, rec_b); CP(rec_f, rec_f); CP(rec_gate_ptr, rec_gate_ptr); CP(chunk_beg, chunk_beg);
   CP(chunk_end, chunk_end); CP(gate_chunk_ptr, gate_chunk_ptr);
+}
+void plan64_ts(int64_t* ts_tile, int32_t* ts_step) {
+  CP(ts_tile, ts_tile); CP(ts_step, ts_step);
 }
 #undef CP
 }

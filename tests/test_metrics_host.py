@@ -73,3 +73,29 @@ def test_hamiltonian_decomposition(api, n):
     from paper_2008_13490_amd import _lib
     with pytest.raises(_lib.GSTError):
         api.hamiltonian_decomposition(2, W.ptm_from_unitary(W.cz(0, 1, 2)))
+
+
+@pytest.mark.parametrize("case", ["cz", "cnot", "cz-noisy", "xi-noisy", "1q-noisy"])
+def test_hamiltonian_decomposition_toward_target(api, case):
+    """The library's optimized decomposition (Jacobi eigenvectors of the target,
+    L-BFGS with the Frechet-derivative gradient) against the oracle's (numpy's
+    eigenvectors, scipy's L-BFGS-B): the same minimum."""
+    rng = np.random.default_rng(7)
+    if case.startswith("1q"):
+        n, U = 1, W.rx(np.pi / 2)
+    elif case.startswith("xi"):
+        n, U = 2, W.on_qubit(W.rx(np.pi / 2), 0, 2)
+    else:
+        n, U = 2, (W.cz(0, 1, 2) if case.startswith("cz") else W.cnot(0, 1, 2))
+    d = 2 ** n
+    G = W.ptm_from_unitary(U)
+    if case.endswith("noisy"):
+        Hr = rng.normal(size=(d, d)) + 1j * rng.normal(size=(d, d))
+        Hr = (Hr + Hr.conj().T) / 2
+        G = W.depolarizing_ptm(2e-3, n) @ W.ptm_from_unitary(sla.expm(-1j * 0.03 * Hr) @ U)
+    h, ang, gam = api.hamiltonian_decomposition_target(n, G, U)
+    h_o, g_o, phi_o, _ = MT.hamiltonian_decomposition_toward(G, U)
+    assert abs(gam - g_o) <= 1e-9 * max(g_o, 1e-3)
+    assert np.abs(h - h_o).max() <= 1e-7 and abs(ang - phi_o) <= 1e-7
+    # the target's Hamiltonian itself
+    assert np.allclose(MT.target_hamiltonian(U), h_o if not case.endswith("noisy") else MT.target_hamiltonian(U))

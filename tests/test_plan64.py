@@ -33,15 +33,17 @@ def plib(tmp_path_factory):
     lib.plan64_tiles.argtypes = [P] * 9
     lib.plan64_events.argtypes = [P] * 7
     lib.plan64_records.argtypes = [P] * 6
+    lib.plan64_ts.argtypes = [P] * 2
+    lib.plan64_set_max_events.argtypes = [ctypes.c_int]
     return lib
 
 
-def get_plan(lib, sl, K, ratio=0.5, fill=0.5, chunk=8192):
+def get_plan(lib, sl, K, ratio=0.5, fill=0.0, chunk=8192):
     off = np.ascontiguousarray(sl.offsets, np.int64)
     g = np.ascontiguousarray(sl.gates if sl.gates.size else np.zeros(1, np.uint8), np.uint8)
-    z = np.zeros(14, np.int64)
+    z = np.zeros(15, np.int64)
     lib.plan64_build(off.ctypes.data, g.ctypes.data, sl.S, int(K), ratio, fill, chunk, z.ctypes.data)
-    used, n_rows, T, L, C, NS, NE, NR, NW, TS, root_slot, NRC, NN, NCH = [int(x) for x in z]
+    used, n_rows, T, L, C, NS, NE, NR, NW, TS, root_slot, NRC, NN, NCH, NTS = [int(x) for x in z]
     P = dict(used=used, n_rows=n_rows, n_tiles=T, n_levels=L, n_chains=C, n_slots=NS, root_slot=root_slot,
              n_nodes=NN)
     if not used:
@@ -62,9 +64,12 @@ def get_plan(lib, sl, K, ratio=0.5, fill=0.5, chunk=8192):
              chunk_end=np.zeros(max(NCH, 1), np.int64), gate_chunk_ptr=np.zeros(K + 1, np.int64))
     lib.plan64_records(*[c[k].ctypes.data for k in ["rec_b", "rec_f", "rec_gate_ptr", "chunk_beg", "chunk_end",
                                                     "gate_chunk_ptr"]])
+    d = dict(ts_tile=np.zeros(max(NTS, 1), np.int64), ts_step=np.zeros(max(NTS, 1), np.int32))
+    lib.plan64_ts(d["ts_tile"].ctypes.data, d["ts_step"].ctypes.data)
     P.update(a)
     P.update(b)
     P.update(c)
+    P.update(d)
     P["root_chains"] = P["root_chains"][:NRC]
     P["n_events"], P["n_records"] = NE, NR
     return P
@@ -113,10 +118,17 @@ def run_plan(P, gs, counts):
                 Bm = G[P["words"][w0 + t]].T @ Bm
             for c in range(P["cols"][ti]):
                 INJ[P["n_slots"] + P["chain"][ti * TC + c]] = Bm[:, c]
+    # the gradient GEMM as the kernel runs it: chunks of tile-steps of one gate
+    # (each sixteen records: the tile's rows at step t against the rows before)
     dG = np.zeros((K, D, D))
     for k in range(K):
-        r = np.arange(P["rec_gate_ptr"][k], P["rec_gate_ptr"][k + 1])
-        dG[k] = BA[P["rec_b"][r]].T @ FA[P["rec_f"][r]]
+        for ch in range(P["gate_chunk_ptr"][k], P["gate_chunk_ptr"][k + 1]):
+            for x in range(P["chunk_beg"][ch], P["chunk_end"][ch]):
+                ti, t = P["ts_tile"][x], P["ts_step"][x]
+                rb = P["row0"][ti] + t * TC + np.arange(TC)
+                rf = (P["row0"][ti] + (t - 1) * TC + np.arange(TC)) if t > 0 else P["anchor"][ti * TC:(ti + 1) * TC]
+                assert P["words"][P["word"][ti] + t] == k
+                dG[k] += BA[rb].T @ FA[rf]
     drho = np.zeros(D)
     if P["root_slot"] >= 0:
         drho += INJ[P["root_slot"]]
@@ -148,8 +160,13 @@ def test_plan64_executes_to_the_oracle(oracle_lib, plib, kind, n_fid, spec, powe
     rng = np.random.default_rng(6)
     p_true = oracle_lib.probs(gs.rho, gs.effects, gs.gates, sl.offsets, sl.gates)
     counts = W.sample_counts(p_true, 1000, rng)
-    # small lists: few chains per group, tiles partly empty; the policy is not under test here
-    P = get_plan(plib, sl, gs.K, ratio=10.0, fill=0.0)
+    # small lists: few chains per group, tiles partly empty; the policy is not under
+    # test here, nor the event bound of the three-qubit kernels (K <= 5)
+    plib.plan64_set_max_events(64)
+    try:
+        P = get_plan(plib, sl, gs.K, ratio=10.0, fill=0.0)
+    finally:
+        plib.plan64_set_max_events(6)
     assert P["used"]
     assert P["n_nodes"] - 1 < 0.5 * int(sl.offsets[-1])
     F, p, g = run_plan(P, gs, counts)
@@ -189,6 +206,15 @@ def test_plan64_structure(plib):
             assert (P["anchor"][ti * TC:ti * TC + P["cols"][ti]] < lo).all()
 
 
+def test_plan64_default_options_take_the_test_lists(plib):
+    """The library's default options (event bound of the kernels included)
+    accept the structured three-qubit lists of the GPU tests."""
+    import test_gpu_3q as T3
+    for args in (dict(), dict(seed=8, n_fid=6, powers=(1, 2, 4, 8))):
+        gs, sl, _ = T3._structured_3q(**args)
+        assert get_plan(plib, sl, gs.K)["used"]
+
+
 def test_plan64_refuses_random_lists(plib):
     rng = np.random.default_rng(8)
     sl = W.random_list(400, 5, 1, 80, rng)
@@ -200,6 +226,10 @@ def test_plan64_c4_statistics(plib):
     w = W.structured_workload("c4")
     P = get_plan(plib, w.seqs, w.model.K)
     assert P["used"]
+    # one long level: the critical path of the sweeps is about one germ power chain
+    ltp = P["level_tile_ptr"]
+    crit = sum(int(P["len"][ltp[l]:ltp[l + 1]].max()) for l in range(P["n_levels"]))
+    assert crit <= int(np.diff(w.seqs.offsets).max()) + 64
     live = P["n_nodes"] - 1
     # far fewer rows than steps, tiles mostly full
     assert live < int(w.seqs.offsets[-1]) / 20
