@@ -217,6 +217,52 @@ def read_traffic(workload: str, family: str):
     return float(vals[key]) if key in vals else None
 
 
+def read_counters(workload: str, family: str):
+    """Counted FP64 flops and HBM bytes per launch of a kernel family from the
+    committed counter summary (profiles/counters_<workload>.txt), if it was
+    taken on the current kernel sources; else None.  FP64 flops are
+    64 (ADD + MUL + TRANS + 2 FMA) per VALU instruction count plus 512 per
+    MFMA_MOPS unit (the SQ_INSTS_VALU_*_F64 counters)."""
+    path = os.path.join(ROOT, "profiles", f"counters_{workload}.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if line.startswith("#") or "=" not in line:
+            continue
+        k, v = line.split("=", 1)
+        vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    out = {}
+    for q in ("fp64_flop", "fetch_bytes", "write_bytes"):
+        key = f"{family}_{q}_per_launch"
+        if key in vals:
+            out[q] = float(vals[key])
+    return out or None
+
+
+def with_counters(roof, counters):
+    """Adds the counter-measured figures to a roofline entry: FP64 FLOP/s and its
+    fraction of peak, the ratio of counted to algorithmic flops, HBM traffic."""
+    if not counters:
+        roof["counter_flop_per_launch"] = None
+        return roof
+    avg_s = roof["avg_launch_us"] * 1e-6
+    if "fp64_flop" in counters:
+        cf = counters["fp64_flop"]
+        roof["counter_flop_per_launch"] = cf
+        roof["counter_tflops"] = cf / avg_s / 1e12
+        roof["counter_frac"] = roof["counter_tflops"] / roof["peak"]
+        roof["counter_to_algorithmic"] = cf / roof["algorithmic_flop_per_launch"] \
+            if roof["algorithmic_flop_per_launch"] else None
+    if "fetch_bytes" in counters and "write_bytes" in counters:
+        tb = counters["fetch_bytes"] + counters["write_bytes"]
+        roof["traffic"] = tb
+        roof["hbm_gbs"] = tb / avg_s / 1e9
+    return roof
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -469,8 +515,11 @@ def run_structured(args):
         "dtype": "f64",
         "data": "synthetic",
         "config": dict(desc, path=args.path, param=args.param),
-        "roofline": _roofline(dom, fams, flops,
-                              read_traffic(args.workload, dom) if args.path == "resident" else None),
+        "roofline": with_counters(_roofline(dom, fams, flops,
+                                            read_traffic(args.workload, dom) if args.path == "resident" else None),
+                                  read_counters(args.workload, dom) if args.path == "resident" and args.param == "full"
+                                  else None),
+        "index_stream": index_stream(w, info, elapsed / args.steps),
         "kernels_ms_per_step": {f: brk[f][0] / n_break for f in brk},
         "plan": info,
         "useful_tflops": 6.0 * D * D * steps_eval / (elapsed / args.steps) / 1e12,
@@ -562,7 +611,9 @@ def run_uneven(args):
                                "two-qubit), S ~ U{500..20000}, random words of length U{1..1024}, one "
                                "graph-captured persistent launch per step; counts ~ Multinomial(1000, uniform)",
                    "sequences": S_tot, "sum_len": sum_len, "gate_sets": len(plan)},
-        "roofline": _roofline(dom, fams, dom_flops, read_traffic("c3", dom)),
+        "roofline": with_counters(_roofline(dom, fams, dom_flops, read_traffic("c3", dom)), read_counters("c3", dom)),
+        "index_stream": {"what": "gate indices, offsets, order", "bytes_per_eval": sum_len + 16 * S_tot,
+                         "gbs": (sum_len + 16 * S_tot) / (elapsed / args.steps) / 1e9},
         "kernels_ms_per_step": {f: fams[f][0] / n_prof for f in fams},
         "useful_tflops": (flops[16] + flops[4]) / (elapsed / args.steps) / 1e12,
         "plain_per_request": {"ms_per_step": plain_s * 1e3, "value": S_tot / plain_s,
@@ -838,6 +889,23 @@ def param_flops(family, D, K, taylor=16):
     if family == "param_bwd":
         return K * (2 * gen + 3 * taylor * mm + mm)
     return 0.0
+
+
+def index_stream(w, info, eval_s):
+    """Bytes of sequence-list data one evaluation reads and their rate.  The
+    per-sequence kernels stream the gate indices (1 B a step) with the offsets
+    and the length order (8 B a sequence each); the sharing plans read compact
+    plan tables instead: for the grouped three-qubit plan one gate index per
+    tile step, for the trie plan one op word per trunk op plus its item table."""
+    L = w.seqs.lengths()
+    S = int(w.seqs.S)
+    if info and info.get("grouped"):
+        kind, nbytes = "grouped-plan words", int(info["rows"]) // 16
+    elif info:
+        kind, nbytes = "trie-plan ops and items", int(info["chain_steps"]) * 8 + S * 32 + int(info["item_steps"])
+    else:
+        kind, nbytes = "gate indices, offsets, order", int(L.sum()) + 16 * S
+    return {"what": kind, "bytes_per_eval": nbytes, "gbs": nbytes / eval_s / 1e9}
 
 
 def req_plan_info(req):

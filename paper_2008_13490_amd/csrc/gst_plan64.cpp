@@ -207,7 +207,7 @@ bool build_plan64(const int64_t* off, const uint8_t* gates, int64_t S, int K, co
           long_pending += (int64_t)n;
           continue;
         }
-        const size_t take = (int64_t)n == remaining[g] ? n : n / (size_t)W * (size_t)W;
+        const size_t take = opt.short_asap || (int64_t)n == remaining[g] ? n : n / (size_t)W * (size_t)W;
         if (take) {
           run(g, take);
           progress = true;

@@ -48,6 +48,7 @@ struct Plan64Options {
   int ts_chunk = 32;                  // tile-steps per chunk of the gradient GEMM
   int max_node_events = kMaxNodeEvents;  // refuse plans with more events at one node
   int split_height = 32;              // a chain ends at a node with two children of at least this height
+  bool short_asap = false;            // short chains run as soon as they are ready (else: in full tiles)
 };
 
 struct Plan64 {
