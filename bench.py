@@ -268,7 +268,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "f2", "f3"])
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c2x64", "c3", "c4", "c5", "f2", "f3"])
     ap.add_argument("--fit-iters", type=int, default=100, help="f2: L-BFGS iterations per MLGST stage")
     ap.add_argument("--rate", type=float, default=100.0, help="c5 / serving: arrivals per second")
     ap.add_argument("--requests", type=int, default=100, help="c5 / serving: requests in the trace")
@@ -304,7 +304,7 @@ def main():
     cpu = None
     if not args.no_cpu:
         workers = args.cpu_workers or max(1, min(16, os.cpu_count() or 1))
-        cpu = cpu_baseline(args.workload, args.cpu_seconds, workers, args.param)
+        cpu = cpu_baseline(base_workload(args.workload), args.cpu_seconds, workers, args.param)
     if args.workload == "c3":
         out = run_uneven(args)
     elif args.workload == "c5":
@@ -317,6 +317,11 @@ def main():
             out["serving"] = serving_summary(args)
     out["cpu_baseline"] = cpu
     print(json.dumps(out))
+
+
+def base_workload(name: str) -> str:
+    """c2x64 is the c2 list evaluated for 64 gate sets at once."""
+    return "c2" if name == "c2x64" else name
 
 
 def serving_summary(args):
@@ -419,7 +424,7 @@ def run_structured(args):
     from paper_2008_13490_amd import api
     from paper_2008_13490_amd import workloads as W
 
-    w = W.structured_workload(args.workload)
+    w = W.structured_workload(base_workload(args.workload))
     desc = workload_desc(w)
     m = w.model
     ctx = api.Context(0)
@@ -427,7 +432,35 @@ def run_structured(args):
     dev = torch.device("cuda", 0)
     obj = torch.empty(1, dtype=torch.float64, device=dev)
     grad = torch.empty(m.n_params(), dtype=torch.float64, device=dev)
-    if args.param != "full":
+    n_sets = 1
+    batch_extra = None
+    if args.workload == "c2x64":
+        # 64 gate sets (the model and 63 seeded neighbours) over the one list:
+        # 64 resident requests, their sharing plans run as one launch per
+        # kernel and level; one step evaluates all of them
+        if args.path != "resident" or args.param != "full":
+            raise SystemExit("c2x64: resident path, full parameterization")
+        n_sets = 64
+        rng = np.random.default_rng(64)
+        sets = [m] + [W.noisy_gateset("2q", W.LAMBDA, W.SIGMA, rng) for _ in range(n_sets - 1)]
+        reqs = [api.Request(ctx, m.n_qubits, m.K, m.M, w.seqs.offsets, w.seqs.gates, w.counts)
+                for _ in range(n_sets)]
+        thetas = [api.DeviceGateSet.from_numpy(g.n_qubits, g.rho, g.effects, g.gates) for g in sets]
+        req = reqs[0]
+        batch = api.Batch(ctx, reqs, thetas, want_probs=False, want_grad=True, capture_graph=True)
+        desc = dict(desc, workload=f"c2x64: the c2 list for {n_sets} gate sets (the model and {n_sets - 1} seeded "
+                                   f"neighbours, same noise model) as {n_sets} resident requests in one batch; "
+                                   + desc["workload"])
+
+        def step():
+            batch.run()
+
+        def alone():
+            for r, t in zip(reqs, thetas):
+                r.eval(t, want_probs=False, want_grad=True)
+
+        batch_extra = (batch, alone)
+    elif args.param != "full":
         if args.path != "resident" or m.n_qubits > 2:
             raise SystemExit("--param tp/cptp: resident path, one or two qubits")
         kind = {1: "1q", 2: "2q"}[m.n_qubits]
@@ -495,8 +528,30 @@ def run_structured(args):
     api.profile_enable(ctx, False)
     fams = {dom: (tot[dom][0] - brk[dom][0], tot[dom][1] - brk[dom][1])}
     elapsed = t1 - t0
-    value = S * args.steps / elapsed
-    flops = fam_flops(dom)  # algorithmic FP64 work per launch of the dominant family
+    value = n_sets * S * args.steps / elapsed
+    extra = {}
+    if batch_extra is not None:
+        # the same steps replayed from the captured graph (no per-kernel
+        # events), and the 64 requests evaluated one after another
+        batch, alone = batch_extra
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            batch.run()
+        torch.cuda.synchronize()
+        g_s = (time.perf_counter() - t0) / args.steps
+        for _ in range(2):
+            alone()
+        ctx.sync()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            alone()
+        ctx.sync()
+        a_s = (time.perf_counter() - t0) / args.steps
+        extra = {"graph_replay": {"ms_per_step": g_s * 1e3, "value": n_sets * S / g_s},
+                 "one_by_one": {"ms_per_step": a_s * 1e3, "value": n_sets * S / a_s,
+                                "what": "the same 64 requests evaluated one after another (own launch sequences)"}}
+    flops = n_sets * fam_flops(dom)  # algorithmic FP64 work per launch of the dominant family
     if info and info.get("grouped"):
         steps_eval = info["trie_nodes"] - 1
     else:
@@ -519,10 +574,11 @@ def run_structured(args):
                                             read_traffic(args.workload, dom) if args.path == "resident" else None),
                                   read_counters(args.workload, dom) if args.path == "resident" and args.param == "full"
                                   else None),
-        "index_stream": index_stream(w, info, elapsed / args.steps),
+        "index_stream": index_stream(w, info, elapsed / args.steps / n_sets),
         "kernels_ms_per_step": {f: brk[f][0] / n_break for f in brk},
         "plan": info,
-        "useful_tflops": 6.0 * D * D * steps_eval / (elapsed / args.steps) / 1e12,
+        "useful_tflops": n_sets * 6.0 * D * D * steps_eval / (elapsed / args.steps) / 1e12,
+        **extra,
     }
 
 

@@ -320,7 +320,17 @@ struct gst_batch {
   std::vector<gst_req*> reqs;
   std::vector<gst_gateset> thetas;
   std::vector<double*> probs, objectives, grads;
-  std::vector<int> plan_reqs;           // evaluated through their own launch sequences
+  std::vector<int> plan_reqs;           // three-qubit: evaluated through their own launch sequences
+  // one- and two-qubit sharing plans, batched per D (0: D = 4, 1: D = 16): one
+  // launch per kernel and level for all of them
+  struct PlanGroup {
+    int D = 0, n = 0, K_max = 1, jl_max = 0, n_levels = 0;
+    bool any_grad = false, any_slab = false;
+    std::vector<int> fwd_grid, bwd_grid, inj_grid;  // per level
+    int item_grid = 0, fill_grid = 0, gemm_grid = 0, red_x = 0, red_parts = 1;
+    gst::PlanBatch dev{};
+  } pgroup[2];
+  DevBuf plan_ws;                       // the batched plans' scratch, one region per request
   // one group of tiles per tile kernel (see TileKind), each with its own queue
   int n_tiles[6] = {0, 0, 0, 0, 0, 0}, grid_of[6] = {0, 0, 0, 0, 0, 0};
   gst::BatchLaunch launch[6] = {};
@@ -836,38 +846,64 @@ int run_plan64(gst_req* r, const gst_gateset* th, int mode, const double* w, dou
 // One evaluation with the sharing plan: trunks forward (per level), items,
 // injections and trunks backward (deepest level first), the gradient GEMM
 // over all stored steps, and the slab reduction.
-int run_plan(gst_req* r, const gst_gateset* th, int mode, const double* w, double* probs, double* objective,
-             double* grad, unsigned long long* req_nonpos = nullptr) {
+// The launch arguments of one evaluation of a request's sharing plan, and the
+// sizes of its scratch: head rows [objective | dL/drho | dL/dE] from the item
+// and trunk-backward workgroups, one D x D tile per gradient chunk, and the
+// first-stage partials of the reduction.
+struct PlanSetup {
+  gst::PlanArgs a{};
+  gst::InjectLaunch in{};
+  gst::GemmLaunch g{};
+  gst::PlanReduce red{};
+  std::vector<int> tb_blocks, tb_at;  // per level: reverse trunk workgroups, their first head row
+  bool want_grad = false, need_slab = false;
+  int64_t H = 0;
+  size_t head_bytes = 0, tile_bytes = 0, part_bytes = 0;
+  size_t ws_bytes() const { return head_bytes + tile_bytes + part_bytes + 256; }
+  void bind(void* ws) {
+    double* slab = reinterpret_cast<double*>(ws);
+    double* tiles = reinterpret_cast<double*>((char*)ws + head_bytes);
+    double* part = reinterpret_cast<double*>((char*)ws + head_bytes + tile_bytes);
+    a.slab = slab;
+    g.tiles = tiles;
+    red.head = slab;
+    red.tiles = tiles;
+    red.part = part;
+  }
+};
+
+void plan_setup(gst_req* r, const gst_gateset* th, int mode, const double* w, double* probs, double* objective,
+                double* grad, unsigned long long* req_nonpos, PlanSetup* out) {
   gst_ctx* ctx = r->ctx;
   const DevicePlan& d = r->plan;
   const gst::HostPlan& P = d.host;
   const int D = r->D;
-  const bool want_grad = grad != nullptr;
-  const bool need_slab = want_grad || mode == gst::MODE_LOGLIK;
-  // head rows [objective | dL/drho | dL/dE] from the item and trunk-backward
-  // workgroups; one D x D tile per gradient chunk
-  const int64_t H = gst::slab_width(D, r->M, 0);
-  const int64_t Pw = want_grad ? gst::slab_width(D, r->M, r->K) : H;
+  PlanSetup& s = *out;
+  s.want_grad = grad != nullptr;
+  s.need_slab = s.want_grad || mode == gst::MODE_LOGLIK;
+  s.H = gst::slab_width(D, r->M, 0);
+  const int64_t Pw = s.want_grad ? gst::slab_width(D, r->M, r->K) : s.H;
   // the item and fill workgroups of the launch within one round of resident
   // workgroups: past that the waves take several groups of items each, where
   // a second round of workgroups would start only as the first ends
   const int64_t resident = (int64_t)ctx->n_cu * gst::item_blocks_per_cu(D, r->K);
-  const int64_t fill_blocks = want_grad && P.n_fill() > 0 ? gst::fill_blocks_for(P.n_fill()) : 0;
+  const int64_t fill_blocks = s.want_grad && P.n_fill() > 0 ? gst::fill_blocks_for(P.n_fill()) : 0;
   const int item_blocks = gst::item_blocks_for(P.n_items(), std::max<int64_t>(resident - fill_blocks, resident / 2));
-  std::vector<int> tb_blocks(P.n_levels), tb_at(P.n_levels);
-  int n_head = need_slab ? item_blocks : 0;
+  s.tb_blocks.assign(P.n_levels, 0);
+  s.tb_at.assign(P.n_levels, 0);
+  int n_head = s.need_slab ? item_blocks : 0;
   for (int l = 0; l < P.n_levels; ++l) {
-    tb_blocks[l] = gst::trunk_blocks_for(P.trunk_level_ptr[l + 1] - P.trunk_level_ptr[l]);
-    tb_at[l] = n_head;
-    if (want_grad) n_head += tb_blocks[l];
+    s.tb_blocks[l] = gst::trunk_blocks_for(P.trunk_level_ptr[l + 1] - P.trunk_level_ptr[l]);
+    s.tb_at[l] = n_head;
+    if (s.want_grad) n_head += s.tb_blocks[l];
   }
-  const int64_t n_chunks = want_grad ? P.n_chunks() : 0;
-  gst::PlanReduce red{};
+  const int64_t n_chunks = s.want_grad ? P.n_chunks() : 0;
+  gst::PlanReduce& red = s.red;
   red.D = D;
   red.M = r->M;
-  red.K = want_grad ? r->K : 0;
+  red.K = s.want_grad ? r->K : 0;
   red.n_head = n_head;
-  red.P = Pw;
+  red.P = s.need_slab ? Pw : 0;
   red.n_part = gst::reduce_parts(n_head);
   for (int k = 0; k <= red.K; ++k) {
     red.chunk_ptr[k] = std::lower_bound(P.chunk_gate.begin(), P.chunk_gate.end(), (int64_t)k) - P.chunk_gate.begin();
@@ -876,20 +912,13 @@ int run_plan(gst_req* r, const gst_gateset* th, int mode, const double* w, doubl
       red.n_part = std::max(red.n_part, gst::reduce_parts((int)std::min<int64_t>(nk, 1 << 20)));
     }
   }
-  const size_t head_bytes = (size_t)n_head * H * 8, tile_bytes = (size_t)n_chunks * D * D * 8;
-  const size_t part_bytes = need_slab ? (size_t)red.n_part * Pw * 8 : 0;
-  int rc = r->ws.reserve(head_bytes + tile_bytes + part_bytes + 256, ctx->stream);
-  if (rc) return rc;
-  double* slab = reinterpret_cast<double*>(r->ws.p);
-  double* tiles = reinterpret_cast<double*>((char*)r->ws.p + head_bytes);
-  double* part = reinterpret_cast<double*>((char*)r->ws.p + head_bytes + tile_bytes);
-  red.head = slab;
-  red.tiles = tiles;
-  red.part = part;
   red.objective = objective;
   red.grad = grad;
+  s.head_bytes = (size_t)n_head * s.H * 8;
+  s.tile_bytes = (size_t)n_chunks * D * D * 8;
+  s.part_bytes = s.need_slab ? (size_t)red.n_part * Pw * 8 : 0;
 
-  gst::PlanArgs a{};
+  gst::PlanArgs& a = s.a;
   a.D = D;
   a.M = r->M;
   a.K = r->K;
@@ -899,7 +928,6 @@ int run_plan(gst_req* r, const gst_gateset* th, int mode, const double* w, doubl
   a.nTS = P.trunk_steps();
   a.trunk_ptr = d.trunk_ptr;
   a.trunk_anchor = d.trunk_anchor;
-
   a.trunk_adj = d.trunk_adj;
   a.op_ptr = d.op_ptr;
   a.op_desc = d.op_desc;
@@ -913,11 +941,10 @@ int run_plan(gst_req* r, const gst_gateset* th, int mode, const double* w, doubl
   a.W = w;
   a.probs = probs;
   a.mode = mode;
-  a.want_grad = want_grad;
+  a.want_grad = s.want_grad;
   a.FA = d.FA;
   a.BA = d.BA;
   a.inj = d.inj;
-  a.slab = slab;
   a.status = ctx->status;
   a.req_nonpos = req_nonpos;
   a.trunk_jpat = d.trunk_jpat;
@@ -930,6 +957,44 @@ int run_plan(gst_req* r, const gst_gateset* th, int mode, const double* w, doubl
   a.fill_n = d.fill_n;
   a.fill_pattern = d.fill_pattern;
   a.fill_gate3 = d.fill_gate3;
+  a.n_levels = P.n_levels;
+  a.fill_blocks = (int)fill_blocks;
+
+  gst::InjectLaunch& in = s.in;
+  in.D = D;
+  in.inj_ptr = d.inj_ptr;
+  in.inj_src = d.inj_src;
+  in.item_adj = d.item_adj;
+  in.trunk_adj = d.trunk_adj;
+  in.inj = d.inj;
+  in.n_levels = s.want_grad ? P.n_levels : 0;
+
+  gst::GemmLaunch& g = s.g;
+  g.D = D;
+  g.M = r->M;
+  g.K = r->K;
+  g.n_chunks = n_chunks;
+  g.chunk_gate = d.chunk_gate;
+  g.chunk_beg = d.chunk_beg;
+  g.chunk_end = d.chunk_end;
+  g.rec_b = d.rec_b;
+  g.rec_f = d.rec_f;
+  g.FA = d.FA;
+  g.BA = d.BA;
+}
+
+int run_plan(gst_req* r, const gst_gateset* th, int mode, const double* w, double* probs, double* objective,
+             double* grad, unsigned long long* req_nonpos = nullptr) {
+  gst_ctx* ctx = r->ctx;
+  const DevicePlan& d = r->plan;
+  const gst::HostPlan& P = d.host;
+  PlanSetup s;
+  plan_setup(r, th, mode, w, probs, objective, grad, req_nonpos, &s);
+  int rc = r->ws.reserve(s.ws_bytes(), ctx->stream);
+  if (rc) return rc;
+  s.bind(r->ws.p);
+  gst::PlanArgs a = s.a;
+  double* slab = a.slab;
   for (int l = 0; l < P.n_levels; ++l) {
     a.t_begin = P.trunk_level_ptr[l];
     a.t_end = P.trunk_level_ptr[l + 1];
@@ -938,16 +1003,10 @@ int run_plan(gst_req* r, const gst_gateset* th, int mode, const double* w, doubl
   }
   {  // with the gradient, extra workgroups fill the states inside the jumps
     ProfScope ps(ctx, FAM_LEAF);
-    HIP_TRY(gst::launch_items(a, item_blocks, ctx->stream));
+    HIP_TRY(gst::launch_items(a, a.item_blocks, ctx->stream));
   }
-  if (want_grad) {
-    gst::InjectLaunch in{};
-    in.D = D;
-    in.inj_ptr = d.inj_ptr;
-    in.inj_src = d.inj_src;
-    in.item_adj = d.item_adj;
-    in.trunk_adj = d.trunk_adj;
-    in.inj = d.inj;
+  if (s.want_grad) {
+    gst::InjectLaunch in = s.in;
     for (int l = P.n_levels - 1; l >= 0; --l) {
       in.s_begin = d.inj_level_ptr[l];
       in.s_end = d.inj_level_ptr[l + 1];
@@ -957,7 +1016,7 @@ int run_plan(gst_req* r, const gst_gateset* th, int mode, const double* w, doubl
       }
       a.t_begin = P.trunk_level_ptr[l];
       a.t_end = P.trunk_level_ptr[l + 1];
-      a.slab = slab + (size_t)tb_at[l] * H;
+      a.slab = slab + (size_t)s.tb_at[l] * s.H;
       ProfScope ps(ctx, FAM_TRUNK_BWD);
       HIP_TRY(gst::launch_trunk_bwd(a, ctx->stream));
     }
@@ -965,25 +1024,12 @@ int run_plan(gst_req* r, const gst_gateset* th, int mode, const double* w, doubl
       ProfScope ps(ctx, FAM_FILL);
       HIP_TRY(gst::launch_fill_rev(a, ctx->stream));
     }
-    gst::GemmLaunch g{};
-    g.D = D;
-    g.M = r->M;
-    g.K = r->K;
-    g.n_chunks = P.n_chunks();
-    g.chunk_gate = d.chunk_gate;
-    g.chunk_beg = d.chunk_beg;
-    g.chunk_end = d.chunk_end;
-    g.rec_b = d.rec_b;
-    g.rec_f = d.rec_f;
-    g.FA = d.FA;
-    g.BA = d.BA;
-    g.tiles = tiles;
     ProfScope ps(ctx, FAM_GEMM);
-    HIP_TRY(gst::launch_grad_gemm(g, ctx->stream));
+    HIP_TRY(gst::launch_grad_gemm(s.g, ctx->stream));
   }
-  if (need_slab) {
+  if (s.need_slab) {
     ProfScope ps(ctx, FAM_REDUCE);
-    HIP_TRY(gst::launch_reduce_plan(red, ctx->stream));
+    HIP_TRY(gst::launch_reduce_plan(s.red, ctx->stream));
   }
   return GST_OK;
 }
@@ -1723,6 +1769,37 @@ static int batch_enqueue(gst_batch* b, hipStream_t stream, bool eager) {
     ProfScope ps(pc, FAM_TILES_RED);
     HIP_TRY(gst::launch_batch_reduce(b->red, b->n_items, b->red_chunks, stream));
   }
+  for (const gst_batch::PlanGroup& pg : b->pgroup) {
+    if (pg.n == 0) continue;
+    for (int l = 0; l < pg.n_levels; ++l) {
+      ProfScope ps(pc, FAM_TRUNK_FWD);
+      HIP_TRY(gst::launch_trunk_fwd_batch(pg.dev, pg.D, pg.n, l, pg.fwd_grid[l], pg.K_max, pg.jl_max, stream));
+    }
+    {
+      ProfScope ps(pc, FAM_LEAF);
+      HIP_TRY(gst::launch_items_batch(pg.dev, pg.D, pg.n, pg.item_grid, pg.K_max, stream));
+    }
+    if (pg.any_grad) {
+      for (int l = pg.n_levels - 1; l >= 0; --l) {
+        {
+          ProfScope ps(pc, FAM_INJECT);
+          HIP_TRY(gst::launch_inject_batch(pg.dev, pg.n, l, pg.inj_grid[l], stream));
+        }
+        ProfScope ps(pc, FAM_TRUNK_BWD);
+        HIP_TRY(gst::launch_trunk_bwd_batch(pg.dev, pg.D, pg.n, l, pg.bwd_grid[l], pg.K_max, pg.jl_max, stream));
+      }
+      if (pg.fill_grid > 0) {
+        ProfScope ps(pc, FAM_FILL);
+        HIP_TRY(gst::launch_fill_rev_batch(pg.dev, pg.D, pg.n, pg.fill_grid, pg.K_max, stream));
+      }
+      ProfScope ps(pc, FAM_GEMM);
+      HIP_TRY(gst::launch_grad_gemm_batch(pg.dev, pg.D, pg.n, pg.gemm_grid, stream));
+    }
+    if (pg.any_slab) {
+      ProfScope ps(pc, FAM_REDUCE);
+      HIP_TRY(gst::launch_reduce_plan_batch(pg.dev, pg.n, pg.red_x, pg.red_parts, stream));
+    }
+  }
   return GST_OK;
 }
 
@@ -1738,6 +1815,7 @@ int gst_batch_create(gst_ctx* ctx, int n, gst_req* const* reqs, const gst_gatese
   std::vector<const std::vector<int64_t>*> group_q[6], group_cost[6];
   std::vector<int> group_req[6];
   std::vector<gst::BatchReduceItem> items;
+  std::vector<int> plan_x[2];  // batched plan requests per D
   for (int x = 0; x < n; ++x) {
     gst_req* r = reqs[x];
     if (!r || r->ctx != ctx) return fail(GST_EINVAL, "request missing or from another context");
@@ -1759,8 +1837,13 @@ int gst_batch_create(gst_ctx* ctx, int n, gst_req* const* reqs, const gst_gatese
     b->probs.push_back(po);
     b->objectives.push_back(ob);
     b->grads.push_back(gr);
-    if (r->plan.used || r->D == 64) {
+    if (r->D == 64) {
       b->plan_reqs.push_back(x);
+      rq.push_back(gst::BatchReq{});
+      continue;
+    }
+    if (r->plan.used) {
+      plan_x[D == 16 ? 1 : 0].push_back(x);
       rq.push_back(gst::BatchReq{});
       continue;
     }
@@ -1823,15 +1906,111 @@ int gst_batch_create(gst_ctx* ctx, int n, gst_req* const* reqs, const gst_gatese
     if (!bad.empty()) return fail(GST_EINVAL, "internal: batch tile list: " + bad);
   }
   b->n_items = (int)items.size();
+  // batched plans: each request's launch arguments, its scratch region in
+  // plan_ws, and its level tables (trunk ranges, reverse head rows, slot ranges)
+  std::vector<PlanSetup> psetup[2];
+  std::vector<int64_t> lvl_tab[2];
+  std::vector<size_t> ws_at[2], lvl_at[2];
+  size_t ws_total = 0;
+  for (int gi = 0; gi < 2; ++gi) {
+    gst_batch::PlanGroup& pg = b->pgroup[gi];
+    pg.D = gi == 1 ? 16 : 4;
+    pg.n = (int)plan_x[gi].size();
+    psetup[gi].resize(pg.n);
+    for (int y = 0; y < pg.n; ++y) {
+      const int x = plan_x[gi][y];
+      gst_req* r = b->reqs[x];
+      const gst::HostPlan& P = r->plan.host;
+      PlanSetup& st = psetup[gi][y];
+      plan_setup(r, &b->thetas[x], b->objectives[x] ? gst::MODE_LOGLIK : gst::MODE_PROBS, nullptr, b->probs[x],
+                 b->objectives[x], b->grads[x], nullptr, &st);
+      ws_at[gi].push_back(ws_total);
+      ws_total += (st.ws_bytes() + 255) / 256 * 256;
+      lvl_at[gi].push_back(lvl_tab[gi].size());
+      for (int l = 0; l <= P.n_levels; ++l) lvl_tab[gi].push_back(P.trunk_level_ptr[l]);
+      for (int l = 0; l < P.n_levels; ++l) lvl_tab[gi].push_back(st.tb_at[l]);
+      for (int l = 0; l <= P.n_levels; ++l) lvl_tab[gi].push_back(r->plan.inj_level_ptr[l]);
+      pg.K_max = std::max(pg.K_max, r->K);
+      pg.jl_max = std::max(pg.jl_max, P.jump_levels);
+      if (P.n_levels > pg.n_levels) {
+        pg.n_levels = P.n_levels;
+        pg.fwd_grid.resize(pg.n_levels, 0);
+        pg.bwd_grid.resize(pg.n_levels, 0);
+        pg.inj_grid.resize(pg.n_levels, 0);
+      }
+      for (int l = 0; l < P.n_levels; ++l) {
+        pg.fwd_grid[l] = std::max(pg.fwd_grid[l], st.tb_blocks[l]);
+        if (st.want_grad) {
+          pg.bwd_grid[l] = std::max(pg.bwd_grid[l], st.tb_blocks[l]);
+          const int64_t ns = r->plan.inj_level_ptr[l + 1] - r->plan.inj_level_ptr[l];
+          pg.inj_grid[l] = std::max(pg.inj_grid[l], (int)std::min<int64_t>(ns, 65536));
+        }
+      }
+      pg.item_grid = std::max(pg.item_grid, st.a.item_blocks + st.a.fill_blocks);
+      if (st.want_grad) {
+        pg.any_grad = true;
+        if (st.a.n_fill > 0) pg.fill_grid = std::max(pg.fill_grid, st.a.fill_blocks);
+        pg.gemm_grid = (int)std::max<int64_t>(pg.gemm_grid, st.g.n_chunks);
+      }
+      if (st.need_slab) {
+        pg.any_slab = true;
+        pg.red_x = (int)std::max<int64_t>(pg.red_x, (st.red.P + 63) / 64);
+        pg.red_parts = std::max(pg.red_parts, st.red.n_part);
+      }
+    }
+  }
+  if (ws_total > 0) {
+    int rc = b->plan_ws.reserve(ws_total, ctx->stream);
+    if (rc) return rc;
+  }
   Carver cv;
-  size_t o_t[6];
+  size_t o_t[6], o_pa[2], o_pi[2], o_pg[2], o_pr[2], o_pl[2];
   const size_t o_rq = cv.take<gst::BatchReq>(rq.size() + 1);
   for (int g = 0; g < 6; ++g) o_t[g] = cv.take<gst::BatchTile>(tiles[g].size() + 1);
   const size_t o_it = cv.take<gst::BatchReduceItem>(items.size() + 1), o_q = cv.take<unsigned>(16 * 6),
                o_np = cv.take<unsigned long long>(rq.size() + 1), o_ck = cv.take<double>((size_t)ck_doubles + 1);
+  for (int gi = 0; gi < 2; ++gi) {
+    o_pa[gi] = cv.take<gst::PlanArgs>(psetup[gi].size() + 1);
+    o_pi[gi] = cv.take<gst::InjectLaunch>(psetup[gi].size() + 1);
+    o_pg[gi] = cv.take<gst::GemmLaunch>(psetup[gi].size() + 1);
+    o_pr[gi] = cv.take<gst::PlanReduce>(psetup[gi].size() + 1);
+    o_pl[gi] = cv.take<int64_t>(lvl_tab[gi].size() + 1);
+  }
   int rc = b->desc.reserve(cv.off + 256, ctx->stream);
   if (rc) return rc;
   char* base = reinterpret_cast<char*>(b->desc.p);
+  for (int gi = 0; gi < 2; ++gi) {
+    gst_batch::PlanGroup& pg = b->pgroup[gi];
+    if (pg.n == 0) continue;
+    const int64_t* lvl = reinterpret_cast<const int64_t*>(base + o_pl[gi]);
+    std::vector<gst::PlanArgs> va(pg.n);
+    std::vector<gst::InjectLaunch> vi(pg.n);
+    std::vector<gst::GemmLaunch> vg(pg.n);
+    std::vector<gst::PlanReduce> vr(pg.n);
+    for (int y = 0; y < pg.n; ++y) {
+      PlanSetup& st = psetup[gi][y];
+      const int x = plan_x[gi][y];
+      const int L = b->reqs[x]->plan.host.n_levels;
+      st.bind((char*)b->plan_ws.p + ws_at[gi][y]);
+      st.a.req_nonpos = reinterpret_cast<unsigned long long*>(base + o_np) + x;
+      st.a.lvl_trunk = lvl + lvl_at[gi][y];
+      st.a.lvl_head = lvl + lvl_at[gi][y] + (L + 1);
+      st.in.lvl_inj = lvl + lvl_at[gi][y] + (2 * L + 1);
+      va[y] = st.a;
+      vi[y] = st.in;
+      vg[y] = st.g;
+      vr[y] = st.red;
+    }
+    HIP_TRY(hipMemcpy(base + o_pa[gi], va.data(), va.size() * sizeof(gst::PlanArgs), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(base + o_pi[gi], vi.data(), vi.size() * sizeof(gst::InjectLaunch), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(base + o_pg[gi], vg.data(), vg.size() * sizeof(gst::GemmLaunch), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(base + o_pr[gi], vr.data(), vr.size() * sizeof(gst::PlanReduce), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(base + o_pl[gi], lvl_tab[gi].data(), lvl_tab[gi].size() * 8, hipMemcpyHostToDevice));
+    pg.dev.args = reinterpret_cast<const gst::PlanArgs*>(base + o_pa[gi]);
+    pg.dev.inject = reinterpret_cast<const gst::InjectLaunch*>(base + o_pi[gi]);
+    pg.dev.gemm = reinterpret_cast<const gst::GemmLaunch*>(base + o_pg[gi]);
+    pg.dev.reduce = reinterpret_cast<const gst::PlanReduce*>(base + o_pr[gi]);
+  }
   if (!rq.empty()) HIP_TRY(hipMemcpy(base + o_rq, rq.data(), rq.size() * sizeof(gst::BatchReq), hipMemcpyHostToDevice));
   for (int g = 0; g < 6; ++g)
     if (!tiles[g].empty())
@@ -1888,10 +2067,7 @@ int gst_batch_run(gst_batch* b) {
   for (int x : b->plan_reqs) {
     gst_req* r = b->reqs[x];
     const int mode = b->objectives[x] ? gst::MODE_LOGLIK : gst::MODE_PROBS;
-    int rc = r->D == 64 ? run64(r, &b->thetas[x], mode, nullptr, b->probs[x], b->objectives[x], b->grads[x],
-                                b->req_nonpos + x)
-                        : run_plan(r, &b->thetas[x], mode, nullptr, b->probs[x], b->objectives[x], b->grads[x],
-                                   b->req_nonpos + x);
+    int rc = run64(r, &b->thetas[x], mode, nullptr, b->probs[x], b->objectives[x], b->grads[x], b->req_nonpos + x);
     if (rc) return rc;
   }
   return GST_OK;

@@ -115,6 +115,13 @@ struct PlanArgs {
   const int32_t* fill_n;
   const uint32_t* fill_pattern;
   const uint8_t* fill_gate3;
+  // batched launches only: the levels, the trunk range of each ([n_levels + 1],
+  // device), the first head row of each level's reverse trunk workgroups
+  // ([n_levels]), and the forward fill workgroups of the item launch
+  int n_levels;
+  const int64_t* lvl_trunk;
+  const int64_t* lvl_head;
+  int fill_blocks;
 };
 
 // inj[slot] = sum over its sources (ascending): item adjoints (src >= 0) and
@@ -127,6 +134,10 @@ struct InjectLaunch {
   const double* item_adj;   // [n_items][D]
   const double* trunk_adj;  // [n_trunks][D]
   double* inj;              // [n_inj][D]
+  // batched launches only: levels (0 = no reverse sweep) and the slot range of
+  // each ([n_levels + 1], device)
+  int n_levels;
+  const int64_t* lvl_inj;
 };
 
 // dG from the reverse-sweep records: chunk c adds, for gate chunk_gate[c],
@@ -355,6 +366,28 @@ int trunk_blocks_for(int64_t n_trunks);
 hipError_t launch_inject(const InjectLaunch& a, hipStream_t stream);
 hipError_t launch_grad_gemm(const GemmLaunch& a, hipStream_t stream);
 hipError_t launch_reduce_plan(const PlanReduce& a, hipStream_t stream);
+
+// The plans of n requests with the same D in one launch per kernel: request y
+// takes args[y], inject[y], gemm[y], reduce[y] (device arrays).  Each launch
+// spans the most workgroups any request's standalone launch has (grid_x);
+// K_max and jl_max size the LDS.  The sequence is: trunk_fwd per level
+// ascending, items, then (inject, trunk_bwd) per level descending, fill_rev,
+// grad_gemm, reduce.
+struct PlanBatch {
+  const PlanArgs* args;
+  const InjectLaunch* inject;
+  const GemmLaunch* gemm;
+  const PlanReduce* reduce;
+};
+hipError_t launch_trunk_fwd_batch(const PlanBatch& b, int D, int n, int level, int grid_x, int K_max, int jl_max,
+                                  hipStream_t stream);
+hipError_t launch_items_batch(const PlanBatch& b, int D, int n, int grid_x, int K_max, hipStream_t stream);
+hipError_t launch_inject_batch(const PlanBatch& b, int n, int level, int grid_x, hipStream_t stream);
+hipError_t launch_trunk_bwd_batch(const PlanBatch& b, int D, int n, int level, int grid_x, int K_max, int jl_max,
+                                  hipStream_t stream);
+hipError_t launch_fill_rev_batch(const PlanBatch& b, int D, int n, int grid_x, int K_max, hipStream_t stream);
+hipError_t launch_grad_gemm_batch(const PlanBatch& b, int D, int n, int grid_x, hipStream_t stream);
+hipError_t launch_reduce_plan_batch(const PlanBatch& b, int n, int grid_x, int parts, hipStream_t stream);
 // Predictions of repeated gate applications: V = block-start states
 // [n_pairs][Q][D], probs [n_pairs][r_max + 1][M]; pair = preparation * n_gates + gate.
 struct PredictLaunch {

@@ -115,17 +115,19 @@ __device__ __forceinline__ uint32_t lane_u32(uint32_t v, int x) {
   return (uint32_t)__builtin_amdgcn_readlane((int)v, x);
 }
 
+// Trunks t_begin + blk, t_begin + blk + nblk, ... of [t_begin, t_end).
 template <int D>
-__global__ __launch_bounds__(64) void trunk_fwd_kernel(const PlanArgs a) {
+__device__ __forceinline__ void trunk_fwd_body(const PlanArgs& a, int64_t t_begin, int64_t t_end, int64_t blk,
+                                               int64_t nblk) {
   extern __shared__ double lds_raw[];
   const int K = a.K;
   const Lds s = carve(lds_raw, K);
   const int lane = threadIdx.x & 63, i = lane & 15;
   stage_gateset<D, 64, STAGE_G>(s, a.G, a.E, a.rho, K, a.M);
-  if (blockIdx.x == 0 && lane < D) a.FA[lane] = a.rho[lane];
+  if (blk == 0 && lane < D) a.FA[lane] = a.rho[lane];
   double* js = lds_raw + trunk_jump_doubles(K);
   const bool st = (D == 16) || lane < D;  // rows 1..3 store the same values as row 0
-  for (int64_t t = a.t_begin + blockIdx.x; t < a.t_end; t += gridDim.x) {
+  for (int64_t t = t_begin + blk; t < t_end; t += nblk) {
     const int64_t beg = a.trunk_ptr[t];
     const int64_t anc = a.trunk_anchor[t];
     const int64_t o0 = a.op_ptr[t], o1 = a.op_ptr[t + 1];
@@ -160,6 +162,11 @@ __global__ __launch_bounds__(64) void trunk_fwd_kernel(const PlanArgs a) {
   }
 }
 
+template <int D>
+__global__ __launch_bounds__(64) void trunk_fwd_kernel(const PlanArgs a) {
+  trunk_fwd_body<D>(a, a.t_begin, a.t_end, blockIdx.x, gridDim.x);
+}
+
 // ---------------------------------------------------------------------------
 // items: one sequence per team, from its anchor state
 // ---------------------------------------------------------------------------
@@ -168,15 +175,16 @@ __device__ void run_fills(const PlanArgs& a, const Lds& s, int64_t blk, int64_t 
 
 // Workgroups from a.item_blocks on run the forward fill tasks instead (they
 // need only the trunk states, like the items).
+// Workgroup blk of nblk: the first a.item_blocks take items, the rest fill tasks.
 template <int D>
-__global__ __launch_bounds__(256) void item_kernel(const PlanArgs a) {
+__device__ __forceinline__ void item_body(const PlanArgs& a, int64_t blk, int64_t nblk) {
   extern __shared__ double lds_raw[];
   const int K = a.K, M = a.M;
   const Lds s = carve(lds_raw, K);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, i = lane & 15, team = lane >> 4;
   stage_gateset<D>(s, a.G, a.E, a.rho, K, M);
-  if ((int)blockIdx.x >= a.item_blocks) {
-    run_fills<D, false>(a, s, (int64_t)blockIdx.x - a.item_blocks, (int64_t)gridDim.x - a.item_blocks);
+  if ((int)blk >= a.item_blocks) {
+    run_fills<D, false>(a, s, blk - a.item_blocks, nblk - a.item_blocks);
     return;
   }
   const bool grad = a.want_grad != 0;
@@ -186,7 +194,7 @@ __global__ __launch_bounds__(256) void item_kernel(const PlanArgs a) {
   for (int m = 0; m < 16; ++m) dE[m] = 0.0;
   unsigned nonpos = 0;
   const int64_t n_groups = (a.n_items + TPW - 1) / TPW;
-  for (int64_t grp = (int64_t)blockIdx.x * WAVES + wave; grp < n_groups; grp += (int64_t)a.item_blocks * WAVES) {
+  for (int64_t grp = blk * WAVES + wave; grp < n_groups; grp += (int64_t)a.item_blocks * WAVES) {
     const int64_t q = grp * TPW + team;
     const bool has = q < a.n_items;
     int64_t seq = 0, beg = 0, end = 0, anc = -1, isp = 0;
@@ -278,7 +286,12 @@ __global__ __launch_bounds__(256) void item_kernel(const PlanArgs a) {
     if (a.req_nonpos) atomicAdd(a.req_nonpos, (unsigned long long)nonpos);
   }
   if (a.mode != MODE_LOGLIK && !grad) return;
-  write_head<D, true, WAVES>(lds_raw, obj, drho, dE, M, a.slab + (int64_t)blockIdx.x * slab_width(D, M, 0));
+  write_head<D, true, WAVES>(lds_raw, obj, drho, dE, M, a.slab + blk * slab_width(D, M, 0));
+}
+
+template <int D>
+__global__ __launch_bounds__(256) void item_kernel(const PlanArgs a) {
+  item_body<D>(a, blockIdx.x, gridDim.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -286,8 +299,10 @@ __global__ __launch_bounds__(256) void item_kernel(const PlanArgs a) {
 // reverse with the transposed rows; the adjoints injected at stored states
 // (64 ops at a time, staged in LDS) are added on the way back
 // ---------------------------------------------------------------------------
+// Trunks t_begin + blk, ... as in the forward; workgroup blk writes head row blk of `slab`.
 template <int D>
-__global__ __launch_bounds__(64) void trunk_bwd_kernel(const PlanArgs a) {
+__device__ __forceinline__ void trunk_bwd_body(const PlanArgs& a, int64_t t_begin, int64_t t_end, int64_t blk,
+                                               int64_t nblk, double* slab) {
   extern __shared__ double lds_raw[];
   const int K = a.K;
   const Lds s = carve(lds_raw, K);
@@ -297,7 +312,7 @@ __global__ __launch_bounds__(64) void trunk_bwd_kernel(const PlanArgs a) {
   double* js = lds_raw + trunk_jump_doubles(K);
   const bool st = (D == 16) || lane < D;
   double drho = 0.0;
-  for (int64_t t = a.t_begin + blockIdx.x; t < a.t_end; t += gridDim.x) {
+  for (int64_t t = t_begin + blk; t < t_end; t += nblk) {
     const int64_t beg = a.trunk_ptr[t];
     const int64_t o0 = a.op_ptr[t], o1 = a.op_ptr[t + 1];
     const uint32_t jp = (uint32_t)__builtin_amdgcn_readfirstlane((int)a.trunk_jpat[t]);
@@ -351,7 +366,12 @@ __global__ __launch_bounds__(64) void trunk_bwd_kernel(const PlanArgs a) {
   // lanes 16..63 repeat lanes 0..15: only row 0 contributes
   if (lane >= 16) drho = 0.0;
   const double no_dE[16] = {};
-  write_head<D, false, 1>(lds_raw, 0.0, drho, no_dE, a.M, a.slab + (int64_t)blockIdx.x * slab_width(D, a.M, 0));
+  write_head<D, false, 1>(lds_raw, 0.0, drho, no_dE, a.M, slab + blk * slab_width(D, a.M, 0));
+}
+
+template <int D>
+__global__ __launch_bounds__(64) void trunk_bwd_kernel(const PlanArgs a) {
+  trunk_bwd_body<D>(a, a.t_begin, a.t_end, blockIdx.x, gridDim.x, a.slab);
 }
 
 // ---------------------------------------------------------------------------
@@ -434,10 +454,11 @@ __global__ __launch_bounds__(256) void fill_rev_kernel(const PlanArgs a) {
 // One wave per injection slot: four groups of 16 lanes take every fourth
 // source (two independent partial sums each), then the groups are combined
 // in a fixed order.
-__global__ __launch_bounds__(64) void inject_kernel(const InjectLaunch a) {
+__device__ __forceinline__ void inject_body(const InjectLaunch& a, int64_t s_begin, int64_t s_end, int64_t blk,
+                                            int64_t nblk) {
   const int D = a.D;
   const int lane = threadIdx.x, g = lane >> 4, i = lane & 15;
-  for (int64_t slot = a.s_begin + blockIdx.x; slot < a.s_end; slot += gridDim.x) {
+  for (int64_t slot = s_begin + blk; slot < s_end; slot += nblk) {
     const int64_t z0 = a.inj_ptr[slot], z1 = a.inj_ptr[slot + 1];
     double v0 = 0.0, v1 = 0.0;
     if (i < D) {
@@ -459,15 +480,18 @@ __global__ __launch_bounds__(64) void inject_kernel(const InjectLaunch a) {
   }
 }
 
+__global__ __launch_bounds__(64) void inject_kernel(const InjectLaunch a) {
+  inject_body(a, a.s_begin, a.s_end, blockIdx.x, gridDim.x);
+}
+
 // ---------------------------------------------------------------------------
 // gradient GEMM over the stored (adjoint, state) pairs, one chunk of records
 // of one gate per workgroup; four records per MFMA 16x16x4
 // ---------------------------------------------------------------------------
 template <int D>
-__global__ __launch_bounds__(256) void grad_gemm_kernel(const GemmLaunch a) {
+__device__ __forceinline__ void grad_gemm_body(const GemmLaunch& a, int64_t c) {
   __shared__ double tile[WAVES][256];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, i = lane & 15, z = lane >> 4;
-  const int64_t c = blockIdx.x;
   const int64_t r0 = a.chunk_beg[c], r1 = a.chunk_end[c];
   const int k = (int)a.chunk_gate[c];
   d4 acc = {0.0, 0.0, 0.0, 0.0};
@@ -497,6 +521,11 @@ __global__ __launch_bounds__(256) void grad_gemm_kernel(const GemmLaunch a) {
   }
 }
 
+template <int D>
+__global__ __launch_bounds__(256) void grad_gemm_kernel(const GemmLaunch a) {
+  grad_gemm_body<D>(a, blockIdx.x);
+}
+
 // ---------------------------------------------------------------------------
 // ordered sum of head rows and per-gate chunk tiles (two stages, fixed order)
 // ---------------------------------------------------------------------------
@@ -521,11 +550,10 @@ __device__ inline Rows rows_of(const PlanReduce& a, int64_t x) {
 
 // Block (x, g): rows [g*per, (g+1)*per) of each column's region, four
 // interleaved partial sums combined in a fixed order.
-__global__ __launch_bounds__(256) void plan_reduce_stage1(const PlanReduce a) {
+__device__ __forceinline__ void reduce_stage1_body(const PlanReduce& a, int64_t bx, int g) {
   __shared__ double red[4][64];
   const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-  const int64_t x = (int64_t)blockIdx.x * 64 + tx;
-  const int g = blockIdx.y;
+  const int64_t x = bx * 64 + tx;
   double v = 0.0;
   int G = 0;
   if (x < a.P) {
@@ -550,14 +578,18 @@ __global__ __launch_bounds__(256) void plan_reduce_stage1(const PlanReduce a) {
   if (ty == 0 && x < a.P && g < G) a.part[(int64_t)g * a.P + x] = (red[0][tx] + red[1][tx]) + (red[2][tx] + red[3][tx]);
 }
 
+__global__ __launch_bounds__(256) void plan_reduce_stage1(const PlanReduce a) {
+  reduce_stage1_body(a, blockIdx.x, blockIdx.y);
+}
+
 // Column x adds its region's stage-1 partials in ascending g.  A +inf
 // objective partial marks p <= 0 with N > 0: the objective is then +inf and
 // the gradient is not written.
-__global__ __launch_bounds__(256) void plan_reduce_stage2(const PlanReduce a) {
+__device__ __forceinline__ void reduce_stage2_body(const PlanReduce& a, int64_t bx) {
   __shared__ double red[4][64];
   __shared__ int nonpos_sh;
   const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-  const int64_t x = (int64_t)blockIdx.x * 64 + tx;
+  const int64_t x = bx * 64 + tx;
   double v = 0.0;
   if (x < a.P) {  // partials g = ty, ty+4, ... (at most 16), all loads in flight
     const int G = parts_of(rows_of(a, x).n);
@@ -586,6 +618,84 @@ __global__ __launch_bounds__(256) void plan_reduce_stage2(const PlanReduce a) {
   } else if (a.grad && !nonpos) {
     a.grad[x - 1] = v;
   }
+}
+
+__global__ __launch_bounds__(256) void plan_reduce_stage2(const PlanReduce a) { reduce_stage2_body(a, blockIdx.x); }
+
+// ---------------------------------------------------------------------------
+// Batched forms: the plans of several requests in one launch per kernel.
+// Request blockIdx.y takes its launch arguments from a device array (copied to
+// registers before anything is stored); its workgroups are blockIdx.x < the
+// count of its standalone launch, split the same way (so its results are the
+// same bits as alone), and the others exit.  A request without the gradient
+// skips the reverse kernels; one with fewer levels skips the extra ones.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int64_t trunk_blocks_of(int64_t n) { return n < 1 ? 1 : (n > 65535 ? 65535 : n); }
+
+template <int D>
+__global__ __launch_bounds__(64) void trunk_fwd_batch(const PlanBatch b, int level) {
+  const PlanArgs a = b.args[blockIdx.y];
+  if (level >= a.n_levels) return;
+  const int64_t t0 = a.lvl_trunk[level], t1 = a.lvl_trunk[level + 1];
+  const int64_t n = trunk_blocks_of(t1 - t0);
+  if ((int64_t)blockIdx.x >= n) return;
+  trunk_fwd_body<D>(a, t0, t1, blockIdx.x, n);
+}
+
+template <int D>
+__global__ __launch_bounds__(256) void item_batch(const PlanBatch b) {
+  const PlanArgs a = b.args[blockIdx.y];
+  const int64_t n = (int64_t)a.item_blocks + a.fill_blocks;
+  if ((int64_t)blockIdx.x >= n) return;
+  item_body<D>(a, blockIdx.x, n);
+}
+
+template <int D>
+__global__ __launch_bounds__(64) void trunk_bwd_batch(const PlanBatch b, int level) {
+  const PlanArgs a = b.args[blockIdx.y];
+  if (!a.want_grad || level >= a.n_levels) return;
+  const int64_t t0 = a.lvl_trunk[level], t1 = a.lvl_trunk[level + 1];
+  const int64_t n = trunk_blocks_of(t1 - t0);
+  if ((int64_t)blockIdx.x >= n) return;
+  trunk_bwd_body<D>(a, t0, t1, blockIdx.x, n, a.slab + a.lvl_head[level] * slab_width(D, a.M, 0));
+}
+
+__global__ __launch_bounds__(64) void inject_batch(const PlanBatch b, int level) {
+  const InjectLaunch in = b.inject[blockIdx.y];
+  if (level >= in.n_levels) return;
+  const int64_t s0 = in.lvl_inj[level], s1 = in.lvl_inj[level + 1];
+  const int64_t n = s1 - s0 < 65536 ? s1 - s0 : 65536;
+  if ((int64_t)blockIdx.x >= n) return;
+  inject_body(in, s0, s1, blockIdx.x, n);
+}
+
+template <int D>
+__global__ __launch_bounds__(256) void fill_rev_batch(const PlanBatch b) {
+  const PlanArgs a = b.args[blockIdx.y];
+  if (!a.want_grad || a.n_fill <= 0 || (int64_t)blockIdx.x >= a.fill_blocks) return;
+  extern __shared__ double lds_raw[];
+  const Lds s = carve(lds_raw, a.K);
+  stage_gateset<D, 256, STAGE_GT>(s, a.G, a.E, a.rho, a.K, a.M);
+  run_fills<D, true>(a, s, blockIdx.x, a.fill_blocks);
+}
+
+template <int D>
+__global__ __launch_bounds__(256) void grad_gemm_batch(const PlanBatch b) {
+  const GemmLaunch g = b.gemm[blockIdx.y];
+  if ((int64_t)blockIdx.x >= g.n_chunks) return;
+  grad_gemm_body<D>(g, blockIdx.x);
+}
+
+__global__ __launch_bounds__(256) void reduce_stage1_batch(const PlanBatch b) {
+  const PlanReduce& r = b.reduce[blockIdx.z];  // chunk_ptr is indexed at run time: no register copy
+  if (r.P <= 0 || (int64_t)blockIdx.x * 64 >= r.P || (int)blockIdx.y >= r.n_part) return;
+  reduce_stage1_body(r, blockIdx.x, blockIdx.y);
+}
+
+__global__ __launch_bounds__(256) void reduce_stage2_batch(const PlanBatch b) {
+  const PlanReduce& r = b.reduce[blockIdx.z];  // chunk_ptr is indexed at run time: no register copy
+  if (r.P <= 0 || (int64_t)blockIdx.x * 64 >= r.P) return;
+  reduce_stage2_body(r, blockIdx.x);
 }
 
 }  // namespace
@@ -690,5 +800,65 @@ hipError_t launch_grad_gemm(const GemmLaunch& a, hipStream_t stream) {
     return hipErrorInvalidValue;
   return hipGetLastError();
 }
+
+#define GST_BATCH_D(kern, ...)                                             \
+  do {                                                                     \
+    if (D == 16)                                                           \
+      gst_launch(kern<16>, __VA_ARGS__);                                   \
+    else if (D == 4)                                                       \
+      gst_launch(kern<4>, __VA_ARGS__);                                    \
+    else                                                                   \
+      return hipErrorInvalidValue;                                         \
+  } while (0)
+
+hipError_t launch_trunk_fwd_batch(const PlanBatch& b, int D, int n, int level, int grid_x, int K_max, int jl_max,
+                                  hipStream_t stream) {
+  if (n <= 0 || grid_x <= 0) return hipSuccess;
+  GST_BATCH_D(trunk_fwd_batch, dim3((unsigned)grid_x, (unsigned)n), dim3(64), trunk_lds_bytes(K_max, jl_max), stream,
+              b, level);
+  return hipGetLastError();
+}
+
+hipError_t launch_items_batch(const PlanBatch& b, int D, int n, int grid_x, int K_max, hipStream_t stream) {
+  if (n <= 0 || grid_x <= 0) return hipSuccess;
+  GST_BATCH_D(item_batch, dim3((unsigned)grid_x, (unsigned)n), dim3(256), item_lds_bytes(K_max), stream, b);
+  return hipGetLastError();
+}
+
+hipError_t launch_inject_batch(const PlanBatch& b, int n, int level, int grid_x, hipStream_t stream) {
+  if (n <= 0 || grid_x <= 0) return hipSuccess;
+  gst_launch(inject_batch, dim3((unsigned)grid_x, (unsigned)n), dim3(64), 0, stream, b, level);
+  return hipGetLastError();
+}
+
+hipError_t launch_trunk_bwd_batch(const PlanBatch& b, int D, int n, int level, int grid_x, int K_max, int jl_max,
+                                  hipStream_t stream) {
+  if (n <= 0 || grid_x <= 0) return hipSuccess;
+  GST_BATCH_D(trunk_bwd_batch, dim3((unsigned)grid_x, (unsigned)n), dim3(64), trunk_lds_bytes(K_max, jl_max), stream,
+              b, level);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_rev_batch(const PlanBatch& b, int D, int n, int grid_x, int K_max, hipStream_t stream) {
+  if (n <= 0 || grid_x <= 0) return hipSuccess;
+  GST_BATCH_D(fill_rev_batch, dim3((unsigned)grid_x, (unsigned)n), dim3(256), item_lds_bytes(K_max), stream, b);
+  return hipGetLastError();
+}
+
+hipError_t launch_grad_gemm_batch(const PlanBatch& b, int D, int n, int grid_x, hipStream_t stream) {
+  if (n <= 0 || grid_x <= 0) return hipSuccess;
+  GST_BATCH_D(grad_gemm_batch, dim3((unsigned)grid_x, (unsigned)n), dim3(256), 0, stream, b);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_plan_batch(const PlanBatch& b, int n, int grid_x, int parts, hipStream_t stream) {
+  if (n <= 0 || grid_x <= 0) return hipSuccess;
+  if (parts < 1 || parts > 64) return hipErrorInvalidValue;
+  gst_launch(reduce_stage1_batch, dim3((unsigned)grid_x, (unsigned)parts, (unsigned)n), dim3(256), 0, stream, b);
+  gst_launch(reduce_stage2_batch, dim3((unsigned)grid_x, 1u, (unsigned)n), dim3(256), 0, stream, b);
+  return hipGetLastError();
+}
+
+#undef GST_BATCH_D
 
 }  // namespace gst

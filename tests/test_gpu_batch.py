@@ -284,3 +284,72 @@ def test_tile_sums_across_chunk_edges(oracle_lib, gpu):
             r.close()
     finally:
         api.tune_set(ctx, 2)
+
+
+def test_plans_batched_per_kernel_equal_standalone(gpu):
+    """Several sharing-plan requests (two-qubit structured list with three gate
+    sets, the one-qubit one with and without counts) next to plain-tile ones:
+    the plans run as one launch per kernel and level, and every request's
+    results are the same bits as its standalone evaluation, eager and replayed
+    from a graph with the gate sets changed in place between replays."""
+    import torch
+    api, ctx = gpu
+    c2 = W.structured_workload("c2")
+    c1 = W.structured_workload("c1")
+    rnd = W.random_workload("2q", 300, 150, 41)
+    rng = np.random.default_rng(42)
+    mix = [("c2-a", c2.model, c2.seqs, c2.counts),
+           ("c2-b", W.noisy_gateset("2q", 1e-3, 0.01, rng), c2.seqs, c2.counts),
+           ("random-2q", rnd.model, rnd.seqs, rnd.counts),
+           ("c1", c1.model, c1.seqs, c1.counts),
+           ("c2-c", W.noisy_gateset("2q", 2e-3, 0.02, rng), c2.seqs, c2.counts),
+           ("c1-probs", c1.model, c1.seqs, None)]
+    labels = [m[0] for m in mix]
+    reqs, thetas = [], []
+    for label, gs, sl, counts in mix:
+        r = api.Request(ctx, gs.n_qubits, gs.K, gs.M, sl.offsets, sl.gates, counts)
+        reqs.append(r)
+        thetas.append(api.DeviceGateSet.from_numpy(gs.n_qubits, gs.rho, gs.effects, gs.gates))
+        say(f"[plan batch] request {label}: S={sl.S} plan={r.plan_info()['plan_used']}")
+    assert sum(r.plan_info()["plan_used"] for r in reqs) == 5
+
+    def standalone():
+        out = []
+        for r, t in zip(reqs, thetas):
+            if r.has_counts:
+                o, p, g = r.eval(t, want_probs=True, want_grad=True)
+            else:
+                o, p, g = None, r.probs(t), None
+            out.append((o, p, g))
+        ctx.sync()
+        return out
+
+    def same(b, ref):
+        for x, (o, p, g) in enumerate(ref):
+            assert torch.equal(b.probs[x], p), labels[x]
+            if o is not None:
+                assert torch.equal(b.obj[x], o), (labels[x], b.obj[x], o)
+                assert torch.equal(b.grad[x], g), labels[x]
+
+    ref = standalone()
+    say("[plan batch] eager")
+    b = api.Batch(ctx, reqs, thetas, want_probs=True, want_grad=True, capture_graph=False)
+    for _ in range(2):
+        b.run()
+        ctx.sync()
+        same(b, ref)
+    assert b.nonpos() == [0] * len(reqs)
+    b.close()
+    say("[plan batch] graph replays")
+    b = api.Batch(ctx, reqs, thetas, want_probs=True, want_grad=True, capture_graph=True)
+    for rep in range(3):
+        if rep > 0:
+            for (label, gs, _, _), t in zip(mix, thetas):
+                g2 = W.noisy_gateset({1: "1q", 2: "2q"}[gs.n_qubits], 1e-3, 0.01, rng)
+                t.gates.copy_(torch.as_tensor(g2.gates, device="cuda"))
+        ref = standalone()
+        b.run()
+        torch.cuda.synchronize()
+        ctx.sync()
+        same(b, ref)
+    b.close()
