@@ -178,13 +178,26 @@ def cpu_baseline(name: str, seconds: float, workers: int, param: str = "full"):
 
 
 # ---------------------------------------------------------------------------
-def kernel_source_hash():
-    """Hash of the device code: the .hip sources and the headers they include
-    (transitively); the HBM counters recorded in profiles/ are used only while
-    it is unchanged.  Host-only sources do not enter it."""
+# the source file of each kernel family (the counters of a family stay valid
+# while this file and the headers it includes are unchanged)
+FAMILY_SOURCE = {
+    "leaf": "gst_plan_kernels.hip", "trunk_fwd": "gst_plan_kernels.hip", "trunk_bwd": "gst_plan_kernels.hip",
+    "inject": "gst_plan_kernels.hip", "fill": "gst_plan_kernels.hip", "grad_gemm": "gst_plan_kernels.hip",
+    "reduce": "gst_plan_kernels.hip", "tiles_3q_fwd": "gst_kernels64.hip", "tiles_3q_bwd": "gst_kernels64.hip",
+    "readout_3q": "gst_kernels64.hip", "gemm_3q": "gst_kernels64.hip", "reduce_3q": "gst_kernels64.hip",
+    "chain_3q": "gst_kernels64.hip", "tiles_2q": "gst_batch.hip", "tiles_1q": "gst_lane1q.hip",
+    "tiles_reduce": "gst_batch.hip",
+}
+
+
+def kernel_source_hash(sources=None):
+    """Hash of device code: the given .hip sources (default: all of them) and
+    the headers they include (transitively); the counters recorded in
+    profiles/ are used only while it is unchanged.  Host-only sources do not
+    enter it."""
     import re
     csrc = os.path.join(ROOT, "paper_2008_13490_amd", "csrc")
-    files = {f for f in os.listdir(csrc) if f.endswith(".hip")}
+    files = set(sources) if sources else {f for f in os.listdir(csrc) if f.endswith(".hip")}
     todo = sorted(files)
     while todo:
         f = todo.pop()
@@ -232,7 +245,8 @@ def read_counters(workload: str, family: str):
             continue
         k, v = line.split("=", 1)
         vals[k.strip()] = v.strip()
-    if vals.get("kernel_source_hash") != kernel_source_hash():
+    src = FAMILY_SOURCE.get(family)
+    if not src or vals.get(f"{family}_source_hash") != kernel_source_hash([src]):
         return None
     out = {}
     for q in ("fp64_flop", "fetch_bytes", "write_bytes"):
@@ -271,6 +285,8 @@ def main():
     ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c2x64", "c3", "c4", "c5", "f2", "f3"])
     ap.add_argument("--fit-iters", type=int, default=100, help="f2: L-BFGS iterations per MLGST stage")
     ap.add_argument("--rate", type=float, default=100.0, help="c5 / serving: arrivals per second")
+    ap.add_argument("--serving-rates", default="", help="c5: comma-separated arrival rates to sweep")
+    ap.add_argument("--slots", type=int, default=8, help="serving: requests admitted at once")
     ap.add_argument("--requests", type=int, default=100, help="c5 / serving: requests in the trace")
     ap.add_argument("--iters", type=int, default=20, help="c5 / serving: iterations per request")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving measurement of the default run")
@@ -324,7 +340,10 @@ def base_workload(name: str) -> str:
     return "c2" if name == "c2x64" else name
 
 
-def serving_summary(args):
+_SERVING_DATA = {}
+
+
+def serving_summary(args, rate=None):
     """Served fits (continuous batching) and the plain per-request path on the
     same Poisson trace of mixed one/two/three-qubit fit requests."""
     import torch
@@ -332,36 +351,56 @@ def serving_summary(args):
     from paper_2008_13490_amd import serving as SV
     from paper_2008_13490_amd import workloads as W
 
+    rate = args.rate if rate is None else rate
     t0 = time.perf_counter()
-    trace = W.serving_trace(args.rate, args.requests)
-    jobs = SV.make_jobs(trace, n_iter=args.iters)
+    trace = W.serving_trace(rate, args.requests)
+
+    def data_fn(kind, S, seed):   # the same requests at every rate: generated once
+        key = (kind, S, seed, args.iters)
+        if key not in _SERVING_DATA:
+            _SERVING_DATA[key] = W.serving_request(kind, S, seed, args.iters)
+        return _SERVING_DATA[key]
+
+    jobs = SV.make_jobs(trace, n_iter=args.iters, data_fn=data_fn)
     t_gen = time.perf_counter() - t0
-    print(f"[bench] serving trace: {len(jobs)} requests at {args.rate} /s, generated in {t_gen:.1f} s",
+    print(f"[bench] serving trace: {len(jobs)} requests at {rate} /s, generated in {t_gen:.1f} s",
           file=sys.stderr, flush=True)
-    ctx = api.Context(0)
+    # the library on its own stream: requests loaded on the host thread upload
+    # through the default stream without waiting for the rounds in flight
+    ctx = api.Context(0, stream=torch.cuda.Stream())
     free, _ = torch.cuda.mem_get_info()
     budget = int(0.8 * free)
-    served = SV.Scheduler(SV.GPUEngine(ctx), budget, max_active=64, round_work=args.round_work).run(jobs)
+    # (no graph capture here: uploads through the default stream on the loading
+    # thread would invalidate a capture taken meanwhile)
+    served = SV.Scheduler(SV.GPUEngine(ctx, capture_graph=False), budget, max_active=args.slots,
+                          round_work=args.round_work, depth=2, prefetch=True).run(jobs)
+    ctx.sync()
     print(f"[bench] served: {served}", file=sys.stderr, flush=True)
     SV.reset(jobs)
     plain = SV.Scheduler(SV.PlainEngine(ctx), budget, max_active=1).run(jobs)
+    ctx.sync()
     print(f"[bench] plain: {plain}", file=sys.stderr, flush=True)
+    ctx.close()
     kinds = [k for _, k, _, _ in trace]
     return {
-        "workload": f"c5: Poisson arrivals at {args.rate:g} requests/s, {len(jobs)} fit requests "
+        "workload": f"c5: Poisson arrivals at {rate:g} requests/s, {len(jobs)} fit requests "
                     f"({kinds.count('1q')} one-qubit, {kinds.count('2q')} two-qubit, {kinds.count('3q')} "
                     f"three-qubit), S log-uniform in [1000, 100000], random words (L <= 256, three qubits "
                     f"L <= 128), {args.iters} closed-loop iterations each with gradient, HBM budget "
-                    f"{budget / 2**30:.0f} GiB, 64 slots, rounds of <= {args.round_work:.0e} two-qubit steps",
+                    f"{budget / 2**30:.0f} GiB, {args.slots} slots, rounds of <= {args.round_work:.0e} two-qubit steps, "
+                    f"two rounds in flight, requests loaded on a host thread",
+        "rate": rate,
         "served": served,
         "plain_per_request": plain,
     }
 
 
 def run_serving(args):
-    s = serving_summary(args)
+    rates = [float(x) for x in args.serving_rates.split(",")] if args.serving_rates else [args.rate]
+    sweep = [serving_summary(args, r) for r in rates]
+    s = sweep[0] if len(sweep) == 1 else max(sweep, key=lambda x: x["rate"] == args.rate)
     sv = s["served"]
-    return {
+    out = {
         "metric": "p50/p99 latency of served fits; sequence evals/s (FP64, with gradient)",
         "value": sv["seq_evals_per_s"],
         "unit": "sequence evals/s",
@@ -377,6 +416,15 @@ def run_serving(args):
         "config": {"workload": s["workload"]},
         "serving": s,
     }
+    if len(sweep) > 1:
+        out["sweep"] = [{"rate": x["rate"],
+                         "served": {k: x["served"][k] for k in ("seq_evals_per_s", "request_latency_ms",
+                                                                 "iteration_latency_ms", "rounds", "mean_round_size",
+                                                                 "host_s")},
+                         "plain": {k: x["plain_per_request"][k] for k in ("seq_evals_per_s", "request_latency_ms",
+                                                                           "iteration_latency_ms")}}
+                        for x in sweep]
+    return out
 
 
 def copy_calibration(mib: int):

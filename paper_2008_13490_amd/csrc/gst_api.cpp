@@ -53,13 +53,16 @@ struct DevBuf {
   ~DevBuf() {
     if (p) (void)hipFree(p);
   }
-  // Ensure capacity; the stream is drained first so that no queued kernel
-  // still uses the old allocation.
+  // Ensure capacity; when an old allocation is replaced, the stream is
+  // drained first so that no queued kernel still uses it (a first
+  // allocation waits for nothing).
   int reserve(size_t need, hipStream_t stream) {
     if (need <= bytes) return GST_OK;
     const size_t cap = std::max(need, bytes + bytes / 2);
-    HIP_TRY(hipStreamSynchronize(stream));
-    if (p) HIP_TRY(hipFree(p));
+    if (p) {
+      HIP_TRY(hipStreamSynchronize(stream));
+      HIP_TRY(hipFree(p));
+    }
     p = nullptr;
     bytes = 0;
     HIP_TRY(hipMalloc(&p, cap));

@@ -194,31 +194,65 @@ __device__ __forceinline__ void item_body(const PlanArgs& a, int64_t blk, int64_
   for (int m = 0; m < 16; ++m) dE[m] = 0.0;
   unsigned nonpos = 0;
   const int64_t n_groups = (a.n_items + TPW - 1) / TPW;
-  for (int64_t grp = blk * WAVES + wave; grp < n_groups; grp += (int64_t)a.item_blocks * WAVES) {
-    const int64_t q = grp * TPW + team;
-    const bool has = q < a.n_items;
-    int64_t seq = 0, beg = 0, end = 0, anc = -1, isp = 0;
-    if (has) {
-      const int64_t* it = a.items + 4 * q;
-      seq = it[0];
-      beg = it[1];
-      end = it[2];
-      anc = it[3];
-      isp = a.item_step_ptr[q];
+  const int64_t stride = (int64_t)a.item_blocks * WAVES;
+  // Software pipeline over the team's items: the descriptor of the item after
+  // next and the anchor state, counts and first gate indices of the next item
+  // are loaded while the current one runs, so that the chain of dependent
+  // global loads of an item is off its critical path.
+  struct Desc {
+    int64_t q, seq, beg, end, anc, isp;
+    bool has;
+  };
+  auto desc_of = [&](int64_t g) {
+    Desc d{g * TPW + team, 0, 0, 0, -1, 0, false};
+    d.has = g < n_groups && d.q < a.n_items;
+    if (d.has) {
+      const int64_t* it = a.items + 4 * d.q;
+      d.seq = it[0];
+      d.beg = it[1];
+      d.end = it[2];
+      d.anc = it[3];
+      d.isp = a.item_step_ptr[d.q];
     }
-    // the counts of the readout are loaded now, with the anchor state, not after it
-    int32_t Nq = 0;
-    if (a.mode == MODE_LOGLIK) Nq = a.counts[(has && i < M) ? seq * M + i : 0];
+    return d;
+  };
+  struct Pre {
+    double f;
+    int32_t Nq;
+    int kv0;
+  };
+  auto pre_of = [&](const Desc& d) {
+    Pre r;
+    r.Nq = (a.mode == MODE_LOGLIK && d.has && i < M) ? a.counts[d.seq * M + i] : 0;
+    r.f = d.anc >= 0 ? load_state(a.FA, 1 + d.anc, D, i) : s.rho[i];
+    r.kv0 = i < d.end - d.beg ? (int)a.gates[d.beg + i] : 0;
+    return r;
+  };
+  int64_t grp = blk * WAVES + wave;
+  Desc cur = desc_of(grp);
+  Pre pc = pre_of(cur);
+  Desc nxt = desc_of(grp + stride);
+  for (; grp < n_groups; grp += stride) {
+    const Desc dn2 = desc_of(grp + 2 * stride);
+    const Pre pn = pre_of(nxt);
+    const int64_t q = cur.q;
+    const bool has = cur.has;
+    const int64_t seq = cur.seq, beg = cur.beg, end = cur.end, anc = cur.anc, isp = cur.isp;
+    const int32_t Nq = pc.Nq;
     const int L = (int)(end - beg);
     const int Lw = wave_max4(L);
     const uint8_t* word = a.gates + beg;
     double* fa = a.FA + (1 + a.nTS + isp) * D;  // state before item step x: fa[x*D + i]
     double* ba = a.BA + (a.nTS + isp) * D;      // adjoint after item step x
-    double f = anc >= 0 ? load_state(a.FA, 1 + anc, D, i) : s.rho[i];
+    double f = pc.f;
+    const int kv0 = pc.kv0;
+    cur = nxt;
+    nxt = dn2;
+    pc = pn;
 
     // ---- forward over the rest of the word ----
     for (int t0 = 0; t0 < Lw; t0 += 16) {
-      const int kv = (t0 + i < L) ? (int)word[t0 + i] : 0;
+      const int kv = t0 == 0 ? kv0 : ((t0 + i < L) ? (int)word[t0 + i] : 0);
 #define GST_IF(R)                                                        \
   if (t0 + R < Lw) {                                                     \
     const int x = t0 + R;                                                \
@@ -265,7 +299,7 @@ __device__ __forceinline__ void item_body(const PlanArgs& a, int64_t blk, int64_
     const int nb = (Lw + 15) / 16;
     for (int c = nb - 1; c >= 0; --c) {
       const int t0 = c * 16;
-      const int kv = (t0 + i < L) ? (int)word[t0 + i] : 0;
+      const int kv = t0 == 0 ? kv0 : ((t0 + i < L) ? (int)word[t0 + i] : 0);
 #define GST_IB(R)                                                         \
   if (t0 + R < Lw) {                                                      \
     const int x = t0 + R;                                                 \

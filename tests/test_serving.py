@@ -123,3 +123,74 @@ def test_round_work_bound_keeps_small_requests_moving():
     assert small.t_done <= min(j.t_done for j in big)      # rides along with the first large one
     assert small.t_done < sorted(j.t_done for j in big)[1]
     assert sch.round_sizes[:5] == [2] * 5 and max(sch.round_sizes) <= 2
+
+
+class FakeAsyncEngine(FakeEngine):
+    """A device timeline behind submit/finish: a round costs the host
+    `host_round` when it is submitted and the device `per_round + per_seq * S`
+    once the device is free; finish waits until the round has ended."""
+
+    def __init__(self, clock, host_round=1e-3, **kw):
+        super().__init__(clock, **kw)
+        self.host_round = host_round
+        self.free_at = 0.0
+        self.inflight = set()
+
+    def submit(self, active, keep=False):
+        for j in active:
+            assert j.rid in self.loaded and j.rid not in self.inflight   # one round at a time per request
+            self.inflight.add(j.rid)
+        self.clock.t += self.host_round
+        start = max(self.clock.t, self.free_at)
+        self.free_at = start + self.per_round + self.per_seq * sum(j.S for j in active)
+        return (self.free_at, [(j.rid, j.k) for j in active], [j.rid for j in active])
+
+    def finish(self, token):
+        end, res, rids = token
+        self.clock.t = max(self.clock.t, end)
+        for r in rids:
+            self.inflight.remove(r)
+        return res
+
+    def evaluate(self, active, keep=False):
+        return self.finish(self.submit(active, keep))
+
+
+@pytest.mark.parametrize("prefetch", [False, True])
+def test_pipelined_rounds_keep_the_loop_closed_and_hide_host_time(prefetch):
+    """Two rounds in flight: every request still sees its iterations in order,
+    one round at a time, and the device no longer waits for the host between
+    rounds, so the same trace finishes sooner than with one round in flight."""
+    res = {}
+    for depth in (1, 2):
+        clk = Clock()
+        eng = FakeAsyncEngine(clk, host_round=2e-3, per_round=2e-4, per_seq=1e-8)
+        jobs = _jobs(80, rate=2000.0, seed=5)
+        sch = SV.Scheduler(eng, 10 ** 13, 16, keep_results=True, clock=clk, sleep=clk.sleep, depth=depth,
+                           prefetch=prefetch)
+        out = sch.run(jobs)
+        assert out["iterations"] == 80 * 5 and not eng.loaded and not eng.inflight
+        for j in jobs:
+            assert j.results == [(j.rid, k) for k in range(5)]
+            assert j.arrival <= j.t_admit <= j.t_iter[0] <= j.t_done
+        res[depth] = out
+    if not prefetch:   # (with loads on a thread the virtual timeline depends on thread timing)
+        assert res[2]["wall_s"] < res[1]["wall_s"]
+        assert res[2]["seq_evals_per_s"] > res[1]["seq_evals_per_s"]
+
+
+def test_prefetch_respects_budget_and_order():
+    clk = Clock()
+    eng = FakeAsyncEngine(clk)
+    jobs = _jobs(50, rate=300.0, seed=6)
+    budget = 3 * 10 ** 7
+    sch = SV.Scheduler(eng, budget, 64, clock=clk, sleep=clk.sleep, depth=2, prefetch=True)
+    out = sch.run(jobs)
+    assert out["requests"] == 50 and sch.max_used <= budget
+    assert eng.order == sorted(eng.order)
+
+
+def test_depth_needs_submit():
+    clk = Clock()
+    with pytest.raises(ValueError):
+        SV.Scheduler(FakeEngine(clk), 10 ** 9, 4, depth=2)
