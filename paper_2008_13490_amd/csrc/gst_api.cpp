@@ -249,6 +249,12 @@ struct DevicePlan {
   uint8_t* fill_gate3 = nullptr;
 };
 
+// Levels whose longest chain has at least this many steps run the sweeps
+// with the gate operands held in registers (loaded once per tile); the others
+// load each step's operands (a tile of a few steps would load all K gates for
+// nothing).
+constexpr int kRegGateSteps = 32;
+
 // Device copy of a three-qubit grouped-chain plan (gst_plan64.h) with its
 // arenas: the states and adjoints of every trie node, the seeds and chain
 // adjoints, the rearranged gate set and the partial sums.
@@ -256,6 +262,7 @@ struct DevicePlan64 {
   bool used = false;
   gst::Plan64 host;          // sizes and level ranges (the big arrays are released after upload)
   std::vector<int64_t> level_tile_ptr;
+  std::vector<char> level_long;  // per level: chains long enough to keep the gates in registers
   DevBuf buf;
   int64_t *tile_row0 = nullptr, *tile_word = nullptr, *tile_ev = nullptr, *col_anchor = nullptr,
           *col_chain = nullptr, *ev_ptr = nullptr, *ev_src = nullptr, *slot_row = nullptr, *slot_ptr = nullptr,
@@ -716,6 +723,10 @@ int upload_plan64(gst_req* r, gst::Plan64& P) {
   if ((rc = put(d.chunk_end, P.chunk_end.data(), NC * 8))) return rc;
   if ((rc = put(d.gate_chunk_ptr, P.gate_chunk_ptr.data(), (K + 1) * 8))) return rc;
   d.level_tile_ptr = P.level_tile_ptr;
+  d.level_long.assign((size_t)P.n_levels, 0);
+  for (int l = 0; l < P.n_levels; ++l)
+    for (int64_t t = P.level_tile_ptr[l]; t < P.level_tile_ptr[l + 1]; ++t)
+      if (P.tile_len[t] >= kRegGateSteps) d.level_long[l] = 1;
   d.n_root_chains = (int)NRC;
   d.n_chunks = NC;
   // keep the sizes, drop the host copies of the big arrays
@@ -764,12 +775,14 @@ int run_plan64(gst_req* r, const gst_gateset* th, int mode, const double* w, dou
   a.BA = d.BA;
   a.INJ = d.INJ;
   a.n_slots = d.host.n_slots;
+  a.K = r->K;
   const int L = d.host.n_levels;
   {
     ProfScope ps(ctx, FAM_P64_FWD);
     for (int l = 0; l < L; ++l) {
       a.t_begin = d.level_tile_ptr[l];
-      HIP_TRY(gst::launch_plan64_fwd(a, (int)(d.level_tile_ptr[l + 1] - d.level_tile_ptr[l]), ctx->stream));
+      HIP_TRY(gst::launch_plan64_fwd(a, (int)(d.level_tile_ptr[l + 1] - d.level_tile_ptr[l]), d.level_long[l] != 0,
+                                     ctx->stream));
     }
   }
   const bool need_slab = objective || grad;
@@ -799,7 +812,8 @@ int run_plan64(gst_req* r, const gst_gateset* th, int mode, const double* w, dou
       ProfScope ps(ctx, FAM_P64_BWD);
       for (int l = L - 1; l >= 0; --l) {
         a.t_begin = d.level_tile_ptr[l];
-        HIP_TRY(gst::launch_plan64_bwd(a, (int)(d.level_tile_ptr[l + 1] - d.level_tile_ptr[l]), ctx->stream));
+        HIP_TRY(gst::launch_plan64_bwd(a, (int)(d.level_tile_ptr[l + 1] - d.level_tile_ptr[l]),
+                                       d.level_long[l] != 0, ctx->stream));
       }
     }
     if (d.n_chunks > 0) {

@@ -296,6 +296,7 @@ struct Plan64Launch {
   double* BA;                // [n_rows][64]
   double* INJ;               // [n_slots + n_chains][64]
   int64_t n_slots;
+  int K;                     // gates (<= 5)
 };
 // dG over tile-steps: chunk c adds, for its gate, over its tile-steps (tile,
 // t), sum over the tile's 16 columns of BA[row(c, t)] FA[row(c, t - 1)]^T (row
@@ -341,8 +342,8 @@ struct Root64Launch {        // the adjoint of rho: root seed + chains anchored 
 };
 hipError_t launch_gate_prep64(const double* G, const double* rho, int K, double* GA, double* GAT, double* FA,
                               hipStream_t stream);
-hipError_t launch_plan64_fwd(const Plan64Launch& a, int n_tiles, hipStream_t stream);
-hipError_t launch_plan64_bwd(const Plan64Launch& a, int n_tiles, hipStream_t stream);
+hipError_t launch_plan64_fwd(const Plan64Launch& a, int n_tiles, bool reg_gates, hipStream_t stream);
+hipError_t launch_plan64_bwd(const Plan64Launch& a, int n_tiles, bool reg_gates, hipStream_t stream);
 hipError_t launch_readout64(const Readout64Launch& a, int n_blocks, hipStream_t stream);
 hipError_t launch_root64(const Root64Launch& a, hipStream_t stream);
 int readout64_blocks_per_cu();

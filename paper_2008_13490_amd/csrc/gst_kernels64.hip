@@ -348,42 +348,119 @@ constexpr int CH_STEPS = 256;   // steps per staged chunk
 constexpr int CH_EVENTS = 1024; // events per staged chunk (a node has at most EV_NODE)
 constexpr int EV_NODE = kMaxNodeEvents;  // events of one node at most: its seed and a chain per child
 
+// A tile-step's 16 states in LDS: element (row 4k + r4, column c) at
+// k * VST + 16 r4 + c, which is where lane 16 r4 + c of an MFMA reads its B
+// operand of block k and writes row 4 v + r4 of its output block; the blocks
+// are padded by two doubles so that the row-wise reads below spread over the
+// banks.
+constexpr int VST = 66;
+
+// Where a step's gate operands come from.  RegGates: a wave's operand blocks of
+// all K <= 5 gates (16 doubles per lane each) stay in registers for the whole
+// sweep and a step picks its gate by a uniform branch, so the vector memory
+// path carries only the stored states, not 32 KB of gate operands per
+// tile-step; for the levels with long chains.  LoadGates: the operands of the
+// next step are loaded while the current one runs; for levels of short
+// chains, where loading all K gates up front would cost more than the steps.
+struct RegGates {
+  double g[5][16];
+  __device__ __forceinline__ void init(const double* base, int K, int w, int l) {
+#pragma unroll
+    for (int k = 0; k < 5; ++k)
+      if (k < K) load_ops(g[k], base + ((int64_t)k * 4 + w) * 1024, l);
+  }
+  __device__ __forceinline__ void start(const double*, int, int, int) {}
+  // the wave's 16 x 64 block of gate k times B, sixteen MFMAs in ascending k
+  __device__ __forceinline__ d4 product(const double*, int k, int, const double* B, int w, int l) {
+    (void)w;
+    d4 acc = {0.0, 0.0, 0.0, 0.0};
+    switch (k) {
+#define GST_P64_CASE(K)                                                                    \
+  case K:                                                                                  \
+    _Pragma("unroll") for (int kk = 0; kk < 16; ++kk)                                      \
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(g[K][kk], B[kk * VST + l], acc, 0, 0, 0);  \
+    break;
+      GST_P64_CASE(0) GST_P64_CASE(1) GST_P64_CASE(2) GST_P64_CASE(3)
+      default:
+        GST_P64_CASE(4)
+#undef GST_P64_CASE
+    }
+    return acc;
+  }
+};
+
+struct LoadGates {
+  double an[16];
+  __device__ __forceinline__ void init(const double*, int, int, int) {}
+  __device__ __forceinline__ void start(const double* base, int k, int w, int l) {
+    load_ops(an, base + ((int64_t)k * 4 + w) * 1024, l);
+  }
+  // operands of gate k (loaded a step ago); those of gate k_next (< 0: none) are loaded now
+  __device__ __forceinline__ d4 product(const double* base, int k, int k_next, const double* B, int w, int l) {
+    (void)k;
+    double ac[16];
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) ac[kk] = an[kk];
+    if (k_next >= 0) load_ops(an, base + ((int64_t)k_next * 4 + w) * 1024, l);
+    d4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ac[kk], B[kk * VST + l], acc, 0, 0, 0);
+    return acc;
+  }
+};
+
+
+// Writes the tile-step's 16 states (columns c = 0..15) to 16 consecutive arena
+// rows, two doubles per lane and store, so that every wave store covers 1 KB of
+// consecutive memory.
+typedef double d2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ void store_tile_rows(const double* V, double* out, int tid) {
+  auto* g = as_global(reinterpret_cast<d2*>(out));
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int f = 2 * (tid + 256 * h);  // column f >> 6, doubles (f & 63) and the next
+    const int cc = f >> 6, j = f & 63;
+    d2 v;
+    v.x = V[(j >> 2) * VST + (j & 3) * 16 + cc];
+    v.y = V[((j + 1) >> 2) * VST + ((j + 1) & 3) * 16 + cc];
+    g[f >> 1] = v;
+  }
+}
+
+template <class Gates>
 __global__ __launch_bounds__(256) void plan64_fwd_kernel(const Plan64Launch a) {
-  __shared__ double Vs[2][16 * 64];
+  __shared__ double Vs[2][16 * VST];
   __shared__ uint8_t Ws[CH_STEPS + 1];
   const int tid = threadIdx.x, l = tid & 63, w = tid >> 6;
   const int c = l & 15, r4 = l >> 4;
   const int64_t tile = a.t_begin + blockIdx.x;
   const int64_t anc = a.col_anchor[tile * 16 + c];
   const auto* fa = as_global(a.FA);
+  Gates gs;
+  gs.init(a.GA, a.K, w, l);
 #pragma unroll
-  for (int v = 0; v < 4; ++v) Vs[0][(4 * w + v) * 64 + l] = fa[anc * N64 + 4 * (4 * w + v) + r4];
+  for (int v = 0; v < 4; ++v) Vs[0][(4 * w + v) * VST + l] = fa[anc * N64 + 4 * (4 * w + v) + r4];
   const int len = uniform(a.tile_len[tile]);
   const auto* word = as_global(a.words + a.tile_word[tile]);
   const int64_t row0 = a.tile_row0[tile];
-  double an[16];
   int cur = 0;
   for (int t0 = 0; t0 < len; t0 += CH_STEPS) {
     const int n = len - t0 < CH_STEPS ? len - t0 : CH_STEPS;
     // word[t0 .. t0 + n], the last one the first gate of the next chunk
     for (int x = tid; x <= n && t0 + x < len; x += 256) Ws[x] = word[t0 + x];
     lds_barrier();
-    if (t0 == 0) load_ops(an, a.GA + ((int64_t)uniform(Ws[0]) * 4 + w) * 1024, l);
+    if (t0 == 0) gs.start(a.GA, uniform(Ws[0]), w, l);
     for (int x = 0; x < n; ++x) {
       const int t = t0 + x;
-      double ac[16];
-#pragma unroll
-      for (int kk = 0; kk < 16; ++kk) ac[kk] = an[kk];
-      if (t + 1 < len) load_ops(an, a.GA + ((int64_t)uniform(Ws[x + 1]) * 4 + w) * 1024, l);
-      d4 acc = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-      for (int kk = 0; kk < 16; ++kk)
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ac[kk], Vs[cur][kk * 64 + l], acc, 0, 0, 0);
+      const d4 acc = gs.product(a.GA, uniform(Ws[x]), t + 1 < len ? uniform(Ws[x + 1]) : -1, Vs[cur], w, l);
       // rows 16w + 4v + r4 of column c: operand block kk = 4w + v of the next step
+      // (stored straight from the registers: measured faster here than the
+      // row-wise stores through LDS that the reverse sweep uses)
       auto* dst = as_global(a.FA + (row0 + (int64_t)t * 16 + c) * N64 + 16 * w + r4);
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        Vs[cur ^ 1][(4 * w + v) * 64 + l] = acc[v];
+        Vs[cur ^ 1][(4 * w + v) * VST + l] = acc[v];
         dst[4 * v] = acc[v];
       }
       lds_barrier();
@@ -427,8 +504,9 @@ __device__ __forceinline__ void load_node_adds(NodeAdds& q, const int64_t* Ev, i
 // events of node t-1 added becomes b_{t-1}.  The events' rows are loaded at the
 // start of the step, the next gate's operands a step ahead.  At the end each
 // chain delivers G_0^T b_0 to its anchor.
+template <class Gates>
 __global__ __launch_bounds__(256) void plan64_bwd_kernel(const Plan64Launch a) {
-  __shared__ double Bs[2][16 * 64];
+  __shared__ double Bs[2][16 * VST];
   __shared__ uint8_t Ws[CH_STEPS + 1];
   __shared__ int32_t Es[CH_STEPS + 2];
   __shared__ int64_t Ev[CH_EVENTS];
@@ -441,7 +519,8 @@ __global__ __launch_bounds__(256) void plan64_bwd_kernel(const Plan64Launch a) {
   const auto* evp = as_global(a.ev_ptr + a.tile_ev[tile]);
   const auto* evc = as_global(a.ev_col);
   const auto* evs = as_global(a.ev_src);
-  double an[16];
+  Gates gs;
+  gs.init(a.GAT, a.K, w, l);
   int cur = 0;
   for (int t1 = len; t1 > 0;) {
     // chunk [t0, t1) with at most CH_STEPS steps and CH_EVENTS events
@@ -467,26 +546,17 @@ __global__ __launch_bounds__(256) void plan64_bwd_kernel(const Plan64Launch a) {
         double add = q.r[0][v];
 #pragma unroll
         for (int e = 1; e < EV_NODE; ++e) add += q.r[e][v];
-        Bs[0][(4 * w + v) * 64 + l] = add;
+        Bs[0][(4 * w + v) * VST + l] = add;
       }
-      load_ops(an, a.GAT + ((int64_t)uniform(Ws[n]) * 4 + w) * 1024, l);
+      gs.start(a.GAT, uniform(Ws[n]), w, l);
       lds_barrier();
     }
     for (int x = n - 1; x >= 0; --x) {
       const int t = t0 + x;
-      double ac[16];
-#pragma unroll
-      for (int kk = 0; kk < 16; ++kk) ac[kk] = an[kk];
-      if (t > 0) load_ops(an, a.GAT + ((int64_t)uniform(Ws[x]) * 4 + w) * 1024, l);
       NodeAdds q;  // events of node t - 1
       if (t > 0) load_node_adds(q, Ev, Es[t - 1 - s0], Es[t - s0], c, w, r4, a.INJ);
-      auto* dst = as_global(a.BA + (row0 + (int64_t)t * 16 + c) * N64 + r4);
-#pragma unroll
-      for (int v = 0; v < 4; ++v) dst[4 * (4 * w + v)] = Bs[cur][(4 * w + v) * 64 + l];
-      d4 acc = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-      for (int kk = 0; kk < 16; ++kk)
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ac[kk], Bs[cur][kk * 64 + l], acc, 0, 0, 0);
+      const d4 acc = gs.product(a.GAT, uniform(Ws[x + 1]), t > 0 ? uniform(Ws[x]) : -1, Bs[cur], w, l);
+      store_tile_rows(Bs[cur], a.BA + (row0 + (int64_t)t * 16) * N64, tid);
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         double add = 0.0;
@@ -495,7 +565,7 @@ __global__ __launch_bounds__(256) void plan64_bwd_kernel(const Plan64Launch a) {
 #pragma unroll
           for (int e = 1; e < EV_NODE; ++e) add += q.r[e][v];
         }
-        Bs[cur ^ 1][(4 * w + v) * 64 + l] = acc[v] + add;
+        Bs[cur ^ 1][(4 * w + v) * VST + l] = acc[v] + add;
       }
       lds_barrier();
       cur ^= 1;
@@ -506,7 +576,7 @@ __global__ __launch_bounds__(256) void plan64_bwd_kernel(const Plan64Launch a) {
   if (ch >= 0) {
     auto* out = as_global(a.INJ + (a.n_slots + ch) * N64 + r4);
 #pragma unroll
-    for (int v = 0; v < 4; ++v) out[4 * (4 * w + v)] = Bs[cur][(4 * w + v) * 64 + l];
+    for (int v = 0; v < 4; ++v) out[4 * (4 * w + v)] = Bs[cur][(4 * w + v) * VST + l];
   }
 }
 
@@ -665,15 +735,23 @@ hipError_t launch_gemm64_ts(const Gemm64TsLaunch& a, hipStream_t stream) {
   return hipGetLastError();
 }
 
-hipError_t launch_plan64_fwd(const Plan64Launch& a, int n_tiles, hipStream_t stream) {
+hipError_t launch_plan64_fwd(const Plan64Launch& a, int n_tiles, bool reg_gates, hipStream_t stream) {
   if (n_tiles <= 0) return hipSuccess;
-  gst_launch(plan64_fwd_kernel, dim3(n_tiles), dim3(256), 0, stream, a);
+  if (a.K < 1 || a.K > 5) return hipErrorInvalidValue;
+  if (reg_gates)
+    gst_launch(plan64_fwd_kernel<RegGates>, dim3(n_tiles), dim3(256), 0, stream, a);
+  else
+    gst_launch(plan64_fwd_kernel<LoadGates>, dim3(n_tiles), dim3(256), 0, stream, a);
   return hipGetLastError();
 }
 
-hipError_t launch_plan64_bwd(const Plan64Launch& a, int n_tiles, hipStream_t stream) {
+hipError_t launch_plan64_bwd(const Plan64Launch& a, int n_tiles, bool reg_gates, hipStream_t stream) {
   if (n_tiles <= 0) return hipSuccess;
-  gst_launch(plan64_bwd_kernel, dim3(n_tiles), dim3(256), 0, stream, a);
+  if (a.K < 1 || a.K > 5) return hipErrorInvalidValue;
+  if (reg_gates)
+    gst_launch(plan64_bwd_kernel<RegGates>, dim3(n_tiles), dim3(256), 0, stream, a);
+  else
+    gst_launch(plan64_bwd_kernel<LoadGates>, dim3(n_tiles), dim3(256), 0, stream, a);
   return hipGetLastError();
 }
 
