@@ -181,12 +181,12 @@ def cpu_baseline(name: str, seconds: float, workers: int, param: str = "full"):
 # the source file of each kernel family (the counters of a family stay valid
 # while this file and the headers it includes are unchanged)
 FAMILY_SOURCE = {
-    "leaf": "gst_plan_kernels.hip", "trunk_fwd": "gst_plan_kernels.hip", "trunk_bwd": "gst_plan_kernels.hip",
-    "inject": "gst_plan_kernels.hip", "fill": "gst_plan_kernels.hip", "grad_gemm": "gst_plan_kernels.hip",
-    "reduce": "gst_plan_kernels.hip", "tiles_3q_fwd": "gst_kernels64.hip", "tiles_3q_bwd": "gst_kernels64.hip",
-    "readout_3q": "gst_kernels64.hip", "gemm_3q": "gst_kernels64.hip", "reduce_3q": "gst_kernels64.hip",
-    "chain_3q": "gst_kernels64.hip", "tiles_2q": "gst_batch.hip", "tiles_1q": "gst_lane1q.hip",
-    "tiles_reduce": "gst_batch.hip",
+    "leaf": ["gst_plan_kernels.hip"], "trunk_fwd": ["gst_plan_kernels.hip"], "trunk_bwd": ["gst_plan_kernels.hip"],
+    "inject": ["gst_plan_kernels.hip"], "fill": ["gst_plan_kernels.hip"], "grad_gemm": ["gst_plan_kernels.hip"],
+    "reduce": ["gst_plan_kernels.hip"], "tiles_3q_fwd": ["gst_kernels64.hip"], "tiles_3q_bwd": ["gst_kernels64.hip"],
+    "readout_3q": ["gst_kernels64.hip"], "gemm_3q": ["gst_kernels64.hip"],
+    "reduce_3q": ["gst_kernels64.hip", "gst_kernels.hip"], "chain_3q": ["gst_kernels64.hip"],
+    "tiles_2q": ["gst_batch.hip"], "tiles_1q": ["gst_lane1q.hip"], "tiles_reduce": ["gst_batch.hip"],
 }
 
 
@@ -246,7 +246,7 @@ def read_counters(workload: str, family: str):
         k, v = line.split("=", 1)
         vals[k.strip()] = v.strip()
     src = FAMILY_SOURCE.get(family)
-    if not src or vals.get(f"{family}_source_hash") != kernel_source_hash([src]):
+    if not src or vals.get(f"{family}_source_hash") != kernel_source_hash(src):
         return None
     out = {}
     for q in ("fp64_flop", "fetch_bytes", "write_bytes"):
