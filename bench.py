@@ -290,6 +290,7 @@ def main():
     ap.add_argument("--requests", type=int, default=100, help="c5 / serving: requests in the trace")
     ap.add_argument("--iters", type=int, default=20, help="c5 / serving: iterations per request")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving measurement of the default run")
+    ap.add_argument("--no-batched", action="store_true", help="skip the c2x64 measurement of the default run")
     ap.add_argument("--no-autotune", action="store_true", help="c3: keep the default tile policy")
     ap.add_argument("--round-work", type=float, default=8e6,
                     help="serving: bound on the work of one round, in two-qubit sequence steps")
@@ -329,6 +330,16 @@ def main():
         out = run_predict(args)
     else:
         out = run_structured(args)
+        if args.workload == "c2" and args.path == "resident" and args.param == "full" and not args.no_batched:
+            # the same list for 64 gate sets in one batch: the steady state of many
+            # evaluations (one launch per kernel and level for all 64)
+            import copy
+            b_args = copy.copy(args)
+            b_args.workload, b_args.steps, b_args.warmup = "c2x64", 20, 3
+            b = run_structured(b_args)
+            out["batched_c2x64"] = {k: b[k] for k in ("value", "unit", "ms_per_step", "steps", "roofline",
+                                                      "graph_replay", "one_by_one")}
+            out["batched_c2x64"]["workload"] = b["config"]["workload"]
         if args.workload == "c2" and not args.no_serving:
             out["serving"] = serving_summary(args)
     out["cpu_baseline"] = cpu
