@@ -212,24 +212,6 @@ def kernel_source_hash(sources=None):
     return h.hexdigest()[:16]
 
 
-def read_traffic(workload: str, family: str):
-    """HBM bytes per launch of the resident path's kernels from the committed
-    counter summary, if it was taken on the current kernel sources; else None."""
-    path = os.path.join(ROOT, "profiles", f"hbm_traffic_{workload}.txt")
-    if not os.path.exists(path):
-        return None
-    vals = {}
-    for line in open(path):
-        if line.startswith("#") or "=" not in line:
-            continue
-        k, v = line.split("=", 1)
-        vals[k.strip()] = v.strip()
-    if vals.get("kernel_source_hash") != kernel_source_hash():
-        return None
-    key = f"{family}_bytes_per_launch"
-    return float(vals[key]) if key in vals else None
-
-
 def read_counters(workload: str, family: str):
     """Counted FP64 flops and HBM bytes per launch of a kernel family from the
     committed counter summary (profiles/counters_<workload>.txt), if it was
@@ -629,8 +611,7 @@ def run_structured(args):
         "dtype": "f64",
         "data": "synthetic",
         "config": dict(desc, path=args.path, param=args.param),
-        "roofline": with_counters(_roofline(dom, fams, flops,
-                                            read_traffic(args.workload, dom) if args.path == "resident" else None),
+        "roofline": with_counters(_roofline(dom, fams, flops, None),
                                   read_counters(args.workload, dom) if args.path == "resident" and args.param == "full"
                                   else None),
         "index_stream": index_stream(w, info, elapsed / args.steps / n_sets),
@@ -726,7 +707,7 @@ def run_uneven(args):
                                "two-qubit), S ~ U{500..20000}, random words of length U{1..1024}, one "
                                "graph-captured persistent launch per step; counts ~ Multinomial(1000, uniform)",
                    "sequences": S_tot, "sum_len": sum_len, "gate_sets": len(plan)},
-        "roofline": with_counters(_roofline(dom, fams, dom_flops, read_traffic("c3", dom)), read_counters("c3", dom)),
+        "roofline": with_counters(_roofline(dom, fams, dom_flops, None), read_counters("c3", dom)),
         "index_stream": {"what": "gate indices, offsets, order", "bytes_per_eval": sum_len + 16 * S_tot,
                          "gbs": (sum_len + 16 * S_tot) / (elapsed / args.steps) / 1e9},
         "kernels_ms_per_step": {f: fams[f][0] / n_prof for f in fams},
