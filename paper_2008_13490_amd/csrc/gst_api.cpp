@@ -334,7 +334,7 @@ struct gst_batch {
   // one- and two-qubit sharing plans, batched per D (0: D = 4, 1: D = 16): one
   // launch per kernel and level for all of them
   struct PlanGroup {
-    int D = 0, n = 0, K_max = 1, jl_max = 0, n_levels = 0;
+    int D = 0, n = 0, K_max = 1, M_max = 1, jl_max = 0, n_levels = 0;
     bool any_grad = false, any_slab = false;
     std::vector<int> fwd_grid, bwd_grid, inj_grid;  // per level
     int item_grid = 0, fill_grid = 0, gemm_grid = 0, red_x = 0, red_parts = 1;
@@ -903,12 +903,14 @@ void plan_setup(gst_req* r, const gst_gateset* th, int mode, const double* w, do
   // the item and fill workgroups of the launch within one round of resident
   // workgroups: past that the waves take several groups of items each, where
   // a second round of workgroups would start only as the first ends
-  const int64_t resident = (int64_t)ctx->n_cu * gst::item_blocks_per_cu(D, r->K);
+  const int64_t resident = (int64_t)ctx->n_cu * gst::item_blocks_per_cu(D, r->K, r->M);
   const int64_t fill_blocks = s.want_grad && P.n_fill() > 0 ? gst::fill_blocks_for(P.n_fill()) : 0;
   const int item_blocks = gst::item_blocks_for(P.n_items(), std::max<int64_t>(resident - fill_blocks, resident / 2));
   s.tb_blocks.assign(P.n_levels, 0);
   s.tb_at.assign(P.n_levels, 0);
-  int n_head = s.need_slab ? item_blocks : 0;
+  // one head row per chunk of items (whatever the item workgroups), then one
+  // per reverse trunk workgroup of each level
+  int n_head = s.need_slab ? (int)((P.n_items() + gst::kItemChunk - 1) / gst::kItemChunk) : 0;
   for (int l = 0; l < P.n_levels; ++l) {
     s.tb_blocks[l] = gst::trunk_blocks_for(P.trunk_level_ptr[l + 1] - P.trunk_level_ptr[l]);
     s.tb_at[l] = n_head;
@@ -1794,7 +1796,7 @@ static int batch_enqueue(gst_batch* b, hipStream_t stream, bool eager) {
     }
     {
       ProfScope ps(pc, FAM_LEAF);
-      HIP_TRY(gst::launch_items_batch(pg.dev, pg.D, pg.n, pg.item_grid, pg.K_max, stream));
+      HIP_TRY(gst::launch_items_batch(pg.dev, pg.D, pg.n, pg.item_grid, pg.K_max, pg.M_max, stream));
     }
     if (pg.any_grad) {
       for (int l = pg.n_levels - 1; l >= 0; --l) {
@@ -1807,7 +1809,7 @@ static int batch_enqueue(gst_batch* b, hipStream_t stream, bool eager) {
       }
       if (pg.fill_grid > 0) {
         ProfScope ps(pc, FAM_FILL);
-        HIP_TRY(gst::launch_fill_rev_batch(pg.dev, pg.D, pg.n, pg.fill_grid, pg.K_max, stream));
+        HIP_TRY(gst::launch_fill_rev_batch(pg.dev, pg.D, pg.n, pg.fill_grid, pg.K_max, pg.M_max, stream));
       }
       ProfScope ps(pc, FAM_GEMM);
       HIP_TRY(gst::launch_grad_gemm_batch(pg.dev, pg.D, pg.n, pg.gemm_grid, stream));
@@ -1948,6 +1950,7 @@ int gst_batch_create(gst_ctx* ctx, int n, gst_req* const* reqs, const gst_gatese
       for (int l = 0; l < P.n_levels; ++l) lvl_tab[gi].push_back(st.tb_at[l]);
       for (int l = 0; l <= P.n_levels; ++l) lvl_tab[gi].push_back(r->plan.inj_level_ptr[l]);
       pg.K_max = std::max(pg.K_max, r->K);
+      pg.M_max = std::max(pg.M_max, r->M);
       pg.jl_max = std::max(pg.jl_max, P.jump_levels);
       if (P.n_levels > pg.n_levels) {
         pg.n_levels = P.n_levels;
@@ -1963,10 +1966,8 @@ int gst_batch_create(gst_ctx* ctx, int n, gst_req* const* reqs, const gst_gatese
           pg.inj_grid[l] = std::max(pg.inj_grid[l], (int)std::min<int64_t>(ns, 65536));
         }
       }
-      pg.item_grid = std::max(pg.item_grid, st.a.item_blocks + st.a.fill_blocks);
       if (st.want_grad) {
         pg.any_grad = true;
-        if (st.a.n_fill > 0) pg.fill_grid = std::max(pg.fill_grid, st.a.fill_blocks);
         pg.gemm_grid = (int)std::max<int64_t>(pg.gemm_grid, st.g.n_chunks);
       }
       if (st.need_slab) {
@@ -1974,6 +1975,26 @@ int gst_batch_create(gst_ctx* ctx, int n, gst_req* const* reqs, const gst_gatese
         pg.red_x = (int)std::max<int64_t>(pg.red_x, (st.red.P + 63) / 64);
         pg.red_parts = std::max(pg.red_parts, st.red.n_part);
       }
+    }
+  }
+  // The batch fills the GPU with all requests' work at once, so each request's
+  // item chunks and fill tasks go to fewer workgroups than alone (each
+  // workgroup stages the gate set once for more work); the chunks keep their
+  // head rows, so the sums are those of the standalone evaluation.
+  for (int gi = 0; gi < 2; ++gi) {
+    gst_batch::PlanGroup& pg = b->pgroup[gi];
+    if (pg.n == 0) continue;
+    int64_t total = 0;
+    for (const PlanSetup& st : psetup[gi]) total += (st.a.n_items + gst::kItemChunk - 1) / gst::kItemChunk;
+    const int64_t resident = (int64_t)ctx->n_cu * gst::item_blocks_per_cu(pg.D, pg.K_max, pg.M_max);
+    const int64_t per_wg = std::max<int64_t>(1, total / std::max<int64_t>(1, 4 * resident));
+    for (PlanSetup& st : psetup[gi]) {
+      const int64_t nc = (st.a.n_items + gst::kItemChunk - 1) / gst::kItemChunk;
+      st.a.item_blocks = (int)std::max<int64_t>(1, std::min<int64_t>(st.a.item_blocks, (nc + per_wg - 1) / per_wg));
+      if (st.a.fill_blocks > 0)
+        st.a.fill_blocks = (int)std::max<int64_t>(1, (st.a.fill_blocks + per_wg - 1) / per_wg);
+      pg.item_grid = std::max(pg.item_grid, st.a.item_blocks + st.a.fill_blocks);
+      if (st.want_grad && st.a.n_fill > 0) pg.fill_grid = std::max(pg.fill_grid, st.a.fill_blocks);
     }
   }
   if (ws_total > 0) {

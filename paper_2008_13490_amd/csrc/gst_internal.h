@@ -67,6 +67,10 @@ struct LeafLaunch {
 //                   row 1 + nTS + x = state before item step x;
 //   adjoint arena BA: row j = adjoint after trunk step j,
 //                     row nTS + x = adjoint after item step x.
+// Items per chunk of the item kernel: each chunk has its own row of partial
+// sums, so a request's sums do not depend on how many workgroups run them.
+constexpr int kItemChunk = 32;
+
 struct PlanArgs {
   int D, M, K;
   const double* rho;
@@ -361,7 +365,7 @@ hipError_t launch_items(const PlanArgs& a, int n_blocks, hipStream_t stream);
 // item_blocks_per_cu is the kernel's occupancy.  The launch adds
 // fill_blocks_for(n_fill) workgroups of forward fill tasks when it has them.
 int item_blocks_for(int64_t n_items, int64_t max_blocks);
-int item_blocks_per_cu(int D, int K);
+int item_blocks_per_cu(int D, int K, int M);
 int fill_blocks_for(int64_t n_fill);
 int trunk_blocks_for(int64_t n_trunks);
 hipError_t launch_inject(const InjectLaunch& a, hipStream_t stream);
@@ -382,11 +386,13 @@ struct PlanBatch {
 };
 hipError_t launch_trunk_fwd_batch(const PlanBatch& b, int D, int n, int level, int grid_x, int K_max, int jl_max,
                                   hipStream_t stream);
-hipError_t launch_items_batch(const PlanBatch& b, int D, int n, int grid_x, int K_max, hipStream_t stream);
+hipError_t launch_items_batch(const PlanBatch& b, int D, int n, int grid_x, int K_max, int M_max,
+                              hipStream_t stream);
 hipError_t launch_inject_batch(const PlanBatch& b, int n, int level, int grid_x, hipStream_t stream);
 hipError_t launch_trunk_bwd_batch(const PlanBatch& b, int D, int n, int level, int grid_x, int K_max, int jl_max,
                                   hipStream_t stream);
-hipError_t launch_fill_rev_batch(const PlanBatch& b, int D, int n, int grid_x, int K_max, hipStream_t stream);
+hipError_t launch_fill_rev_batch(const PlanBatch& b, int D, int n, int grid_x, int K_max, int M_max,
+                                 hipStream_t stream);
 hipError_t launch_grad_gemm_batch(const PlanBatch& b, int D, int n, int grid_x, hipStream_t stream);
 hipError_t launch_reduce_plan_batch(const PlanBatch& b, int n, int grid_x, int parts, hipStream_t stream);
 // Predictions of repeated gate applications: V = block-start states

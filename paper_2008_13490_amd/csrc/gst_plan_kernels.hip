@@ -48,17 +48,20 @@ __host__ __device__ inline size_t trunk_head_doubles(int K) {
   return (size_t)2 * K * GATE_STRIDE + 2 * 16 * ROW + 16;
 }
 
-// A workgroup's head row [objective | dL/drho | dL/dE]: every 16-lane team
-// leaves its partial sums in LDS (no shuffles across teams), and the
-// workgroup adds the team partials in a fixed order.
-constexpr int HEAD_W = 1 + 16 + 256;
-__host__ __device__ inline size_t head_red_bytes(int n_waves) { return (size_t)n_waves * TPW * HEAD_W * 8; }
+// A head row [objective | dL/drho | dL/dE]: every 16-lane team leaves its
+// partial sums in LDS (no shuffles across teams, `hw` doubles per team: 17 +
+// 16 M with the effects, 17 without), and the workgroup adds the team partials
+// in a fixed order.
+__host__ __device__ inline int head_stride(int M) { return 17 + 16 * M; }
+__host__ __device__ inline size_t head_red_bytes(int n_waves, int M) {
+  return (size_t)n_waves * TPW * head_stride(M) * 8;
+}
 
 template <int D, bool WITH_E, int NW>
-__device__ void write_head(double* lds_raw, double obj, double drho, const double (&dE)[16], int M, double* out) {
+__device__ void write_head(double* red, int hw, double obj, double drho, const double (&dE)[16], int M, double* out) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, i = lane & 15, team = lane >> 4;
-  __syncthreads();  // LDS is reused from here on
-  double* mine = lds_raw + (size_t)(wave * TPW + team) * HEAD_W;
+  __syncthreads();  // the previous contents of `red` have been read
+  double* mine = red + (size_t)(wave * TPW + team) * hw;
   double o = obj;
 #pragma unroll
   for (int sh = 1; sh < 16; sh <<= 1) o += __shfl_xor(o, sh);
@@ -82,17 +85,16 @@ __device__ void write_head(double* lds_raw, double obj, double drho, const doubl
     double v = 0.0;
     if (src >= 0) {
 #pragma unroll
-      for (int p = 0; p < NW * TPW; ++p) v += lds_raw[p * HEAD_W + src];
+      for (int p = 0; p < NW * TPW; ++p) v += red[p * hw + src];
     }
     out[x] = v;
   }
 }
 
-// Item and fill workgroups hold only the gate set (no checkpoint stash); the
-// head-row reduction reuses it afterwards.
-__host__ __device__ inline size_t item_lds_bytes(int K) {
-  const size_t a = trunk_head_doubles(K) * 8, r = head_red_bytes(WAVES);
-  return (a > r ? a : r) + 64;
+// Item and fill workgroups hold the gate set and, behind it, the head-row
+// reduction of the item chunks.
+__host__ __device__ inline size_t item_lds_bytes(int K, int M) {
+  return trunk_head_doubles(K) * 8 + head_red_bytes(WAVES, M) + 64;
 }
 
 // After the staging area: the trunk's jump matrices in the gate layout.
@@ -100,7 +102,7 @@ __host__ __device__ inline size_t trunk_jump_doubles(int K) { return trunk_head_
 
 __host__ __device__ inline size_t trunk_lds_bytes(int K, int levels) {
   const size_t a = (trunk_jump_doubles(K) + (size_t)levels * GATE_STRIDE) * 8 + 64;
-  const size_t r = head_red_bytes(1);
+  const size_t r = head_red_bytes(1, 0);
   return a > r ? a : r;
 }
 
@@ -188,13 +190,23 @@ __device__ __forceinline__ void item_body(const PlanArgs& a, int64_t blk, int64_
     return;
   }
   const bool grad = a.want_grad != 0;
+  const bool need_head = a.mode == MODE_LOGLIK || grad;
+  double* red = lds_raw + trunk_head_doubles(K);
+  const int hw = head_stride(M);
   double obj = 0.0, drho = 0.0;
   double dE[16];
 #pragma unroll
   for (int m = 0; m < 16; ++m) dE[m] = 0.0;
   unsigned nonpos = 0;
-  const int64_t n_groups = (a.n_items + TPW - 1) / TPW;
-  const int64_t stride = (int64_t)a.item_blocks * WAVES;
+  // The items are cut into chunks of kItemChunk (two rounds of one item per
+  // team), each with its own head row, whatever the number of workgroups:
+  // workgroup blk takes chunks blk, blk + item_blocks, ...  Round u of the
+  // workgroup is round u & 1 of chunk blk + (u >> 1) item_blocks.
+  static_assert(kItemChunk == 2 * WAVES * TPW, "an item chunk is two rounds of the workgroup's teams");
+  const int64_t n_chunks = (a.n_items + kItemChunk - 1) / kItemChunk;
+  const int64_t my_chunks = blk < n_chunks ? (n_chunks - 1 - blk) / a.item_blocks + 1 : 0;
+  const int64_t n_u = 2 * my_chunks;
+  auto chunk_of = [&](int64_t u) { return blk + (u >> 1) * (int64_t)a.item_blocks; };
   // Software pipeline over the team's items: the descriptor of the item after
   // next and the anchor state, counts and first gate indices of the next item
   // are loaded while the current one runs, so that the chain of dependent
@@ -203,9 +215,9 @@ __device__ __forceinline__ void item_body(const PlanArgs& a, int64_t blk, int64_
     int64_t q, seq, beg, end, anc, isp;
     bool has;
   };
-  auto desc_of = [&](int64_t g) {
-    Desc d{g * TPW + team, 0, 0, 0, -1, 0, false};
-    d.has = g < n_groups && d.q < a.n_items;
+  auto desc_of = [&](int64_t u) {
+    Desc d{chunk_of(u) * kItemChunk + (u & 1) * (WAVES * TPW) + wave * TPW + team, 0, 0, 0, -1, 0, false};
+    d.has = u < n_u && d.q < a.n_items;
     if (d.has) {
       const int64_t* it = a.items + 4 * d.q;
       d.seq = it[0];
@@ -228,12 +240,11 @@ __device__ __forceinline__ void item_body(const PlanArgs& a, int64_t blk, int64_
     r.kv0 = i < d.end - d.beg ? (int)a.gates[d.beg + i] : 0;
     return r;
   };
-  int64_t grp = blk * WAVES + wave;
-  Desc cur = desc_of(grp);
+  Desc cur = desc_of(0);
   Pre pc = pre_of(cur);
-  Desc nxt = desc_of(grp + stride);
-  for (; grp < n_groups; grp += stride) {
-    const Desc dn2 = desc_of(grp + 2 * stride);
+  Desc nxt = desc_of(1);
+  for (int64_t u = 0; u < n_u; ++u) {
+    const Desc dn2 = desc_of(u + 2);
     const Pre pn = pre_of(nxt);
     const int64_t q = cur.q;
     const bool has = cur.has;
@@ -287,19 +298,19 @@ __device__ __forceinline__ void item_body(const PlanArgs& a, int64_t blk, int64_
         dp = a.W[o];
       }
     }
-    if (!grad) continue;
+    if (grad) {
 #define GST_DE(R) \
   if (R < M) dE[R] = fma(bcast_f64<R>(dp), f, dE[R]);
-    GST_DE(0) GST_DE(1) GST_DE(2) GST_DE(3) GST_DE(4) GST_DE(5) GST_DE(6) GST_DE(7)
-    GST_DE(8) GST_DE(9) GST_DE(10) GST_DE(11) GST_DE(12) GST_DE(13) GST_DE(14) GST_DE(15)
+      GST_DE(0) GST_DE(1) GST_DE(2) GST_DE(3) GST_DE(4) GST_DE(5) GST_DE(6) GST_DE(7)
+      GST_DE(8) GST_DE(9) GST_DE(10) GST_DE(11) GST_DE(12) GST_DE(13) GST_DE(14) GST_DE(15)
 #undef GST_DE
-    double b = dot16(dp, load_row(s.ETs + i * ROW));
+      double b = dot16(dp, load_row(s.ETs + i * ROW));
 
-    // ---- reverse sweep of the rest of the word ----
-    const int nb = (Lw + 15) / 16;
-    for (int c = nb - 1; c >= 0; --c) {
-      const int t0 = c * 16;
-      const int kv = t0 == 0 ? kv0 : ((t0 + i < L) ? (int)word[t0 + i] : 0);
+      // ---- reverse sweep of the rest of the word ----
+      const int nb = (Lw + 15) / 16;
+      for (int c = nb - 1; c >= 0; --c) {
+        const int t0 = c * 16;
+        const int kv = t0 == 0 ? kv0 : ((t0 + i < L) ? (int)word[t0 + i] : 0);
 #define GST_IB(R)                                                         \
   if (t0 + R < Lw) {                                                      \
     const int x = t0 + R;                                                 \
@@ -308,19 +319,25 @@ __device__ __forceinline__ void item_body(const PlanArgs& a, int64_t blk, int64_
     const double bn = dot16(b, load_row(s.GTs + k * GATE_STRIDE + i * ROW)); \
     b = x < L ? bn : b;                                                   \
   }
-      GST_IB(15) GST_IB(14) GST_IB(13) GST_IB(12) GST_IB(11) GST_IB(10) GST_IB(9) GST_IB(8)
-      GST_IB(7) GST_IB(6) GST_IB(5) GST_IB(4) GST_IB(3) GST_IB(2) GST_IB(1) GST_IB(0)
+        GST_IB(15) GST_IB(14) GST_IB(13) GST_IB(12) GST_IB(11) GST_IB(10) GST_IB(9) GST_IB(8)
+        GST_IB(7) GST_IB(6) GST_IB(5) GST_IB(4) GST_IB(3) GST_IB(2) GST_IB(1) GST_IB(0)
 #undef GST_IB
+      }
+      if (has && i < D) a.item_adj[q * D + i] = b;
+      if (has && anc < 0) drho += b;
     }
-    if (has && i < D) a.item_adj[q * D + i] = b;
-    if (has && anc < 0) drho += b;
+    if ((u & 1) && need_head) {  // the chunk's head row
+      write_head<D, true, WAVES>(red, hw, obj, drho, dE, M, a.slab + chunk_of(u) * slab_width(D, M, 0));
+      obj = 0.0;
+      drho = 0.0;
+#pragma unroll
+      for (int m = 0; m < 16; ++m) dE[m] = 0.0;
+    }
   }
   if (nonpos) {
     atomicAdd(a.status + 1, (unsigned long long)nonpos);
     if (a.req_nonpos) atomicAdd(a.req_nonpos, (unsigned long long)nonpos);
   }
-  if (a.mode != MODE_LOGLIK && !grad) return;
-  write_head<D, true, WAVES>(lds_raw, obj, drho, dE, M, a.slab + blk * slab_width(D, M, 0));
 }
 
 template <int D>
@@ -400,7 +417,7 @@ __device__ __forceinline__ void trunk_bwd_body(const PlanArgs& a, int64_t t_begi
   // lanes 16..63 repeat lanes 0..15: only row 0 contributes
   if (lane >= 16) drho = 0.0;
   const double no_dE[16] = {};
-  write_head<D, false, 1>(lds_raw, 0.0, drho, no_dE, a.M, slab + blk * slab_width(D, a.M, 0));
+  write_head<D, false, 1>(lds_raw, head_stride(0), 0.0, drho, no_dE, a.M, slab + blk * slab_width(D, a.M, 0));
 }
 
 template <int D>
@@ -739,18 +756,18 @@ int fill_blocks_for(int64_t n_fill) {
   return (int)(b < 1 ? 1 : (b > 1024 ? 1024 : b));
 }
 
-int item_blocks_per_cu(int D, int K) {
+int item_blocks_per_cu(int D, int K, int M) {
   int n = 0;
-  const size_t bytes = item_lds_bytes(K);
+  const size_t bytes = item_lds_bytes(K, M);
   const hipError_t e = D == 16 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, item_kernel<16>, 256, bytes)
                                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, item_kernel<4>, 256, bytes);
   return (e == hipSuccess && n > 0) ? n : 1;
 }
 
 int item_blocks_for(int64_t n_items, int64_t max_blocks) {
-  int64_t b = (n_items + WAVES * TPW - 1) / (WAVES * TPW);
+  int64_t b = (n_items + kItemChunk - 1) / kItemChunk;
   if (b < 1) b = 1;
-  if (max_blocks > 0 && b > max_blocks) b = max_blocks;  // the waves then take several groups each
+  if (max_blocks > 0 && b > max_blocks) b = max_blocks;  // the workgroups then take several chunks each
   return (int)b;
 }
 
@@ -784,7 +801,7 @@ hipError_t launch_trunk_bwd(const PlanArgs& a, hipStream_t stream) {
 
 hipError_t launch_items(const PlanArgs& a, int n_blocks, hipStream_t stream) {
   if (a.item_blocks != n_blocks) return hipErrorInvalidValue;
-  const size_t bytes = item_lds_bytes(a.K);
+  const size_t bytes = item_lds_bytes(a.K, a.M);
   const unsigned grid = (unsigned)n_blocks + (a.want_grad && a.n_fill > 0 ? (unsigned)fill_blocks_for(a.n_fill) : 0u);
   if (a.D == 16)
     gst_launch(item_kernel<16>, dim3(grid), dim3(256), bytes, stream, a);
@@ -806,7 +823,7 @@ hipError_t launch_inject(const InjectLaunch& a, hipStream_t stream) {
 hipError_t launch_fill_rev(const PlanArgs& a, hipStream_t stream) {
   if (a.n_fill <= 0) return hipSuccess;
   const int blocks = fill_blocks_for(a.n_fill);
-  const size_t bytes = item_lds_bytes(a.K);
+  const size_t bytes = item_lds_bytes(a.K, a.M);
   if (a.D == 16)
     gst_launch(fill_rev_kernel<16>, dim3((unsigned)blocks), dim3(256), bytes, stream, a);
   else if (a.D == 4)
@@ -853,9 +870,10 @@ hipError_t launch_trunk_fwd_batch(const PlanBatch& b, int D, int n, int level, i
   return hipGetLastError();
 }
 
-hipError_t launch_items_batch(const PlanBatch& b, int D, int n, int grid_x, int K_max, hipStream_t stream) {
+hipError_t launch_items_batch(const PlanBatch& b, int D, int n, int grid_x, int K_max, int M_max,
+                              hipStream_t stream) {
   if (n <= 0 || grid_x <= 0) return hipSuccess;
-  GST_BATCH_D(item_batch, dim3((unsigned)grid_x, (unsigned)n), dim3(256), item_lds_bytes(K_max), stream, b);
+  GST_BATCH_D(item_batch, dim3((unsigned)grid_x, (unsigned)n), dim3(256), item_lds_bytes(K_max, M_max), stream, b);
   return hipGetLastError();
 }
 
@@ -873,9 +891,11 @@ hipError_t launch_trunk_bwd_batch(const PlanBatch& b, int D, int n, int level, i
   return hipGetLastError();
 }
 
-hipError_t launch_fill_rev_batch(const PlanBatch& b, int D, int n, int grid_x, int K_max, hipStream_t stream) {
+hipError_t launch_fill_rev_batch(const PlanBatch& b, int D, int n, int grid_x, int K_max, int M_max,
+                                 hipStream_t stream) {
   if (n <= 0 || grid_x <= 0) return hipSuccess;
-  GST_BATCH_D(fill_rev_batch, dim3((unsigned)grid_x, (unsigned)n), dim3(256), item_lds_bytes(K_max), stream, b);
+  GST_BATCH_D(fill_rev_batch, dim3((unsigned)grid_x, (unsigned)n), dim3(256), item_lds_bytes(K_max, M_max), stream,
+              b);
   return hipGetLastError();
 }
 
