@@ -97,11 +97,27 @@ __host__ __device__ inline size_t item_lds_bytes(int K, int M) {
   return trunk_head_doubles(K) * 8 + head_red_bytes(WAVES, M) + 64;
 }
 
-// After the staging area: the trunk's jump matrices in the gate layout.
-__host__ __device__ inline size_t trunk_jump_doubles(int K) { return trunk_head_doubles(K) + (size_t)OPW * 16; }
+// A trunk workgroup holds only what it uses: the gates (forward) or their
+// transposes (reverse) at the start, rho, the staged injected vectors
+// (reverse), and the trunk's jump matrices in the gate layout (at least two
+// slots: the germ product alternates between slots 0 and 1).  Fewer bytes let
+// more trunk workgroups share a CU when many requests run at once.
+__device__ __forceinline__ Lds carve_trunk(double* base, int K) {
+  Lds l;
+  l.Gs = base;
+  l.GTs = base;  // one of the two is staged
+  l.Es = nullptr;
+  l.ETs = nullptr;
+  l.rho = base + (size_t)K * GATE_STRIDE;
+  l.stash = nullptr;
+  l.sk = nullptr;
+  return l;
+}
+__host__ __device__ inline size_t trunk_inj_doubles(int K) { return (size_t)K * GATE_STRIDE + 16; }
+__host__ __device__ inline size_t trunk_jump_doubles(int K) { return trunk_inj_doubles(K) + (size_t)OPW * 16; }
 
 __host__ __device__ inline size_t trunk_lds_bytes(int K, int levels) {
-  const size_t a = (trunk_jump_doubles(K) + (size_t)levels * GATE_STRIDE) * 8 + 64;
+  const size_t a = (trunk_jump_doubles(K) + (size_t)(levels > 2 ? levels : 2) * GATE_STRIDE) * 8 + 64;
   const size_t r = head_red_bytes(1, 0);
   return a > r ? a : r;
 }
@@ -123,7 +139,7 @@ __device__ __forceinline__ void trunk_fwd_body(const PlanArgs& a, int64_t t_begi
                                                int64_t nblk) {
   extern __shared__ double lds_raw[];
   const int K = a.K;
-  const Lds s = carve(lds_raw, K);
+  const Lds s = carve_trunk(lds_raw, K);
   const int lane = threadIdx.x & 63, i = lane & 15;
   stage_gateset<D, 64, STAGE_G>(s, a.G, a.E, a.rho, K, a.M);
   if (blk == 0 && lane < D) a.FA[lane] = a.rho[lane];
@@ -356,10 +372,10 @@ __device__ __forceinline__ void trunk_bwd_body(const PlanArgs& a, int64_t t_begi
                                                int64_t nblk, double* slab) {
   extern __shared__ double lds_raw[];
   const int K = a.K;
-  const Lds s = carve(lds_raw, K);
+  const Lds s = carve_trunk(lds_raw, K);
   const int lane = threadIdx.x & 63, i = lane & 15, team = lane >> 4;
   stage_gateset<D, 64, STAGE_GT>(s, a.G, a.E, a.rho, K, a.M);
-  double* inj_st = lds_raw + trunk_head_doubles(K);
+  double* inj_st = lds_raw + trunk_inj_doubles(K);
   double* js = lds_raw + trunk_jump_doubles(K);
   const bool st = (D == 16) || lane < D;
   double drho = 0.0;
