@@ -158,6 +158,11 @@ __device__ __forceinline__ int wave_max4(int v) {
   return __builtin_amdgcn_readfirstlane(v);
 }
 
+// Barrier for the workgroup's LDS only: it waits for the wave's LDS accesses
+// (and scalar loads), not for its global stores, which __syncthreads would
+// also wait for.
+__device__ __forceinline__ void lds_sync() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();

@@ -60,7 +60,7 @@ __host__ __device__ inline size_t head_red_bytes(int n_waves, int M) {
 template <int D, bool WITH_E, int NW>
 __device__ void write_head(double* red, int hw, double obj, double drho, const double (&dE)[16], int M, double* out) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, i = lane & 15, team = lane >> 4;
-  __syncthreads();  // the previous contents of `red` have been read
+  lds_sync();  // the previous contents of `red` have been read (no wait for global stores)
   double* mine = red + (size_t)(wave * TPW + team) * hw;
   double o = obj;
 #pragma unroll
@@ -72,7 +72,7 @@ __device__ void write_head(double* red, int hw, double obj, double drho, const d
     for (int m = 0; m < 16; ++m)
       if (m < M) mine[17 + m * 16 + i] = dE[m];
   }
-  __syncthreads();
+  lds_sync();
   const int H = 1 + D + M * D;
   for (int x = tid; x < H; x += blockDim.x) {
     int src = -1;
@@ -91,10 +91,18 @@ __device__ void write_head(double* red, int hw, double obj, double drho, const d
   }
 }
 
+// A chunk's items staged in LDS: per item its descriptor (sequence, word
+// begin and end, anchor, first record row), its start state, its counts and
+// the first 16 gate indices of its word.
+constexpr int IST_DESC = 5;
+__host__ __device__ inline size_t item_stage_bytes() {
+  return (size_t)kItemChunk * (IST_DESC * 8 + 16 * 8 + 16 * 4 + 16 * 4);
+}
+
 // Item and fill workgroups hold the gate set and, behind it, the head-row
-// reduction of the item chunks.
+// reduction of the item chunks and the staged chunk.
 __host__ __device__ inline size_t item_lds_bytes(int K, int M) {
-  return trunk_head_doubles(K) * 8 + head_red_bytes(WAVES, M) + 64;
+  return trunk_head_doubles(K) * 8 + head_red_bytes(WAVES, M) + item_stage_bytes() + 64;
 }
 
 // A trunk workgroup holds only what it uses: the gates (forward) or their
@@ -216,66 +224,54 @@ __device__ __forceinline__ void item_body(const PlanArgs& a, int64_t blk, int64_
   unsigned nonpos = 0;
   // The items are cut into chunks of kItemChunk (two rounds of one item per
   // team), each with its own head row, whatever the number of workgroups:
-  // workgroup blk takes chunks blk, blk + item_blocks, ...  Round u of the
-  // workgroup is round u & 1 of chunk blk + (u >> 1) item_blocks.
+  // workgroup blk takes chunks blk, blk + item_blocks, ...  A chunk's item
+  // data is staged in LDS by the whole workgroup first (the descriptors, then
+  // what they point to), so that an item's chain starts from LDS instead of
+  // from two dependent global round trips of its own.
   static_assert(kItemChunk == 2 * WAVES * TPW, "an item chunk is two rounds of the workgroup's teams");
   const int64_t n_chunks = (a.n_items + kItemChunk - 1) / kItemChunk;
-  const int64_t my_chunks = blk < n_chunks ? (n_chunks - 1 - blk) / a.item_blocks + 1 : 0;
-  const int64_t n_u = 2 * my_chunks;
-  auto chunk_of = [&](int64_t u) { return blk + (u >> 1) * (int64_t)a.item_blocks; };
-  // Software pipeline over the team's items: the descriptor of the item after
-  // next and the anchor state, counts and first gate indices of the next item
-  // are loaded while the current one runs, so that the chain of dependent
-  // global loads of an item is off its critical path.
-  struct Desc {
-    int64_t q, seq, beg, end, anc, isp;
-    bool has;
-  };
-  auto desc_of = [&](int64_t u) {
-    Desc d{chunk_of(u) * kItemChunk + (u & 1) * (WAVES * TPW) + wave * TPW + team, 0, 0, 0, -1, 0, false};
-    d.has = u < n_u && d.q < a.n_items;
-    if (d.has) {
-      const int64_t* it = a.items + 4 * d.q;
-      d.seq = it[0];
-      d.beg = it[1];
-      d.end = it[2];
-      d.anc = it[3];
-      d.isp = a.item_step_ptr[d.q];
+  int64_t* st_desc = reinterpret_cast<int64_t*>(red + (size_t)WAVES * TPW * hw);  // [kItemChunk][IST_DESC]
+  double* st_f = reinterpret_cast<double*>(st_desc + kItemChunk * IST_DESC);      // [kItemChunk][16]
+  int32_t* st_n = reinterpret_cast<int32_t*>(st_f + kItemChunk * 16);             // [kItemChunk][16]
+  int32_t* st_kv = st_n + kItemChunk * 16;                                        // [kItemChunk][16]
+  for (int64_t chunk = blk; chunk < n_chunks; chunk += a.item_blocks) {
+    const int64_t q0 = chunk * kItemChunk;
+    // descriptors (the previous chunk's staged data has been read: write_head
+    // ends with a barrier, and so does the staging below)
+    if (tid < kItemChunk * IST_DESC) {
+      const int it = tid / IST_DESC, c = tid % IST_DESC;
+      const int64_t q = q0 + it;
+      int64_t v = c == 3 ? -1 : 0;
+      if (q < a.n_items) v = c < 4 ? a.items[4 * q + c] : a.item_step_ptr[q];
+      st_desc[tid] = v;
     }
-    return d;
-  };
-  struct Pre {
-    double f;
-    int32_t Nq;
-    int kv0;
-  };
-  auto pre_of = [&](const Desc& d) {
-    Pre r;
-    r.Nq = (a.mode == MODE_LOGLIK && d.has && i < M) ? a.counts[d.seq * M + i] : 0;
-    r.f = d.anc >= 0 ? load_state(a.FA, 1 + d.anc, D, i) : s.rho[i];
-    r.kv0 = i < d.end - d.beg ? (int)a.gates[d.beg + i] : 0;
-    return r;
-  };
-  Desc cur = desc_of(0);
-  Pre pc = pre_of(cur);
-  Desc nxt = desc_of(1);
-  for (int64_t u = 0; u < n_u; ++u) {
-    const Desc dn2 = desc_of(u + 2);
-    const Pre pn = pre_of(nxt);
-    const int64_t q = cur.q;
-    const bool has = cur.has;
-    const int64_t seq = cur.seq, beg = cur.beg, end = cur.end, anc = cur.anc, isp = cur.isp;
-    const int32_t Nq = pc.Nq;
+    lds_sync();
+    // start states, counts, first gate indices: item `it`, component `c`
+    for (int x = tid; x < kItemChunk * 16; x += WAVES * 64) {
+      const int it = x >> 4, c = x & 15;
+      const bool has_it = q0 + it < a.n_items;
+      const int64_t seq = st_desc[it * IST_DESC + 0], beg = st_desc[it * IST_DESC + 1];
+      const int64_t end = st_desc[it * IST_DESC + 2], anc = st_desc[it * IST_DESC + 3];
+      st_f[x] = anc >= 0 ? load_state(a.FA, 1 + anc, D, c) : s.rho[c];
+      st_n[x] = (a.mode == MODE_LOGLIK && has_it && c < M) ? a.counts[seq * M + c] : 0;
+      st_kv[x] = c < end - beg ? (int)a.gates[beg + c] : 0;
+    }
+    lds_sync();
+    for (int r = 0; r < 2; ++r) {
+    const int it = r * (WAVES * TPW) + wave * TPW + team;
+    const int64_t q = q0 + it;
+    const bool has = q < a.n_items;
+    const int64_t seq = st_desc[it * IST_DESC + 0], beg = st_desc[it * IST_DESC + 1];
+    const int64_t end = st_desc[it * IST_DESC + 2], anc = st_desc[it * IST_DESC + 3];
+    const int64_t isp = st_desc[it * IST_DESC + 4];
+    const int32_t Nq = st_n[it * 16 + i];
     const int L = (int)(end - beg);
     const int Lw = wave_max4(L);
     const uint8_t* word = a.gates + beg;
     double* fa = a.FA + (1 + a.nTS + isp) * D;  // state before item step x: fa[x*D + i]
     double* ba = a.BA + (a.nTS + isp) * D;      // adjoint after item step x
-    double f = pc.f;
-    const int kv0 = pc.kv0;
-    cur = nxt;
-    nxt = dn2;
-    pc = pn;
+    double f = st_f[it * 16 + i];
+    const int kv0 = st_kv[it * 16 + i];
 
     // ---- forward over the rest of the word ----
     for (int t0 = 0; t0 < Lw; t0 += 16) {
@@ -342,12 +338,15 @@ __device__ __forceinline__ void item_body(const PlanArgs& a, int64_t blk, int64_
       if (has && i < D) a.item_adj[q * D + i] = b;
       if (has && anc < 0) drho += b;
     }
-    if ((u & 1) && need_head) {  // the chunk's head row
-      write_head<D, true, WAVES>(red, hw, obj, drho, dE, M, a.slab + chunk_of(u) * slab_width(D, M, 0));
+    }
+    if (need_head) {  // the chunk's head row
+      write_head<D, true, WAVES>(red, hw, obj, drho, dE, M, a.slab + chunk * slab_width(D, M, 0));
       obj = 0.0;
       drho = 0.0;
 #pragma unroll
       for (int m = 0; m < 16; ++m) dE[m] = 0.0;
+    } else {
+      lds_sync();  // the staged chunk has been read
     }
   }
   if (nonpos) {
