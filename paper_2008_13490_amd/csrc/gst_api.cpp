@@ -266,9 +266,9 @@ struct DevicePlan64 {
   DevBuf buf;
   int64_t *tile_row0 = nullptr, *tile_word = nullptr, *tile_ev = nullptr, *col_anchor = nullptr,
           *col_chain = nullptr, *ev_ptr = nullptr, *ev_src = nullptr, *slot_row = nullptr, *slot_ptr = nullptr,
-          *slot_seq = nullptr, *root_chains = nullptr, *ts_tile = nullptr, *chunk_beg = nullptr,
+          *slot_seq = nullptr, *slot_pack = nullptr, *root_chains = nullptr, *ts_tile = nullptr, *chunk_beg = nullptr,
           *chunk_end = nullptr, *gate_chunk_ptr = nullptr;
-  int32_t *tile_len = nullptr, *ev_col = nullptr, *ts_step = nullptr;
+  int32_t *tile_len = nullptr, *ev_col = nullptr, *ts_step = nullptr, *slot_cnt = nullptr;
   uint8_t* words = nullptr;
   double *FA = nullptr, *BA = nullptr, *INJ = nullptr, *GA = nullptr, *GAT = nullptr, *slab = nullptr,
          *part = nullptr, *chunk_slab = nullptr, *root_vec = nullptr;
@@ -643,7 +643,7 @@ int upload_plan(gst_req* r, const gst::HostPlan& P) {
   return GST_OK;
 }
 
-int upload_plan64(gst_req* r, gst::Plan64& P) {
+int upload_plan64(gst_req* r, gst::Plan64& P, const int32_t* counts_host) {
   DevicePlan64& d = r->plan64;
   const int M = r->M, K = r->K;
   const int64_t T = P.n_tiles(), TS = P.tile_steps(), NE = (int64_t)P.ev_col.size(), NR = (int64_t)P.ts_tile.size(),
@@ -659,7 +659,9 @@ int upload_plan64(gst_req* r, gst::Plan64& P) {
                o_words = c.take<uint8_t>(P.words.size() + 1), o_evp = c.take<int64_t>(TS + 2),
                o_evc = c.take<int32_t>(NE + 1), o_evs = c.take<int64_t>(NE + 1),
                o_sr = c.take<int64_t>(P.n_slots + 1), o_sp = c.take<int64_t>(P.n_slots + 2),
-               o_sq = c.take<int64_t>(P.S + 1), o_rc = c.take<int64_t>(NRC + 1), o_rb = c.take<int64_t>(NR + 1),
+               o_sq = c.take<int64_t>(P.S + 1), o_spk = c.take<int64_t>(P.n_slots * 4 + 4),
+               o_scn = c.take<int32_t>(P.n_slots * M + 1), o_rc = c.take<int64_t>(NRC + 1),
+               o_rb = c.take<int64_t>(NR + 1),
                o_rf = c.take<int32_t>(NR + 1), o_cb = c.take<int64_t>(NC + 1), o_ce = c.take<int64_t>(NC + 1),
                o_gcp = c.take<int64_t>(K + 1), o_fa = c.take<double>((size_t)P.n_rows * 64),
                o_ba = c.take<double>((size_t)P.n_rows * 64),
@@ -684,6 +686,8 @@ int upload_plan64(gst_req* r, gst::Plan64& P) {
   d.slot_row = reinterpret_cast<int64_t*>(b + o_sr);
   d.slot_ptr = reinterpret_cast<int64_t*>(b + o_sp);
   d.slot_seq = reinterpret_cast<int64_t*>(b + o_sq);
+  d.slot_pack = reinterpret_cast<int64_t*>(b + o_spk);
+  d.slot_cnt = reinterpret_cast<int32_t*>(b + o_scn);
   d.root_chains = reinterpret_cast<int64_t*>(b + o_rc);
   d.ts_tile = reinterpret_cast<int64_t*>(b + o_rb);
   d.ts_step = reinterpret_cast<int32_t*>(b + o_rf);
@@ -716,6 +720,24 @@ int upload_plan64(gst_req* r, gst::Plan64& P) {
   if ((rc = put(d.slot_row, P.slot_row.data(), P.n_slots * 8))) return rc;
   if ((rc = put(d.slot_ptr, P.slot_ptr.data(), P.slot_ptr.size() * 8))) return rc;
   if ((rc = put(d.slot_seq, P.slot_seq.data(), P.slot_seq.size() * 8))) return rc;
+  {
+    // per slot: its node row, its first sequence and its sequence range, and
+    // the first sequence's counts (the readout loads them together, by slot)
+    std::vector<int64_t> pack((size_t)P.n_slots * 4);
+    std::vector<int32_t> cnt((size_t)P.n_slots * M, 0);
+    for (int64_t x = 0; x < P.n_slots; ++x) {
+      const int64_t q0 = P.slot_ptr[x], q1 = P.slot_ptr[x + 1];
+      const int64_t seq0 = q1 > q0 ? P.slot_seq[q0] : 0;
+      pack[4 * x + 0] = P.slot_row[x];
+      pack[4 * x + 1] = seq0;
+      pack[4 * x + 2] = q0;
+      pack[4 * x + 3] = q1;
+      if (counts_host && q1 > q0)
+        for (int m = 0; m < M; ++m) cnt[(size_t)x * M + m] = counts_host[seq0 * M + m];
+    }
+    if ((rc = put(d.slot_pack, pack.data(), pack.size() * 8))) return rc;
+    if ((rc = put(d.slot_cnt, cnt.data(), cnt.size() * 4))) return rc;
+  }
   if ((rc = put(d.root_chains, P.root_chains.data(), NRC * 8))) return rc;
   if ((rc = put(d.ts_tile, P.ts_tile.data(), NR * 8))) return rc;
   if ((rc = put(d.ts_step, P.ts_step.data(), NR * 4))) return rc;
@@ -796,6 +818,8 @@ int run_plan64(gst_req* r, const gst_gateset* th, int mode, const double* w, dou
     q.slot_row = d.slot_row;
     q.slot_ptr = d.slot_ptr;
     q.slot_seq = d.slot_seq;
+    q.slot_pack = d.slot_pack;
+    q.slot_cnt = d.slot_cnt;
     q.counts = r->counts;
     q.W = w;
     q.probs = probs;
@@ -1545,7 +1569,7 @@ int gst_req_create_host(gst_ctx* ctx, int n_qubits, int n_gates, int n_outcomes,
     }
   }
   if (use_p64) {
-    rc = upload_plan64(r.get(), p64);
+    rc = upload_plan64(r.get(), p64, counts_host);
     if (rc) return rc;
   }
   r->resident_bytes = r->data.bytes + r->plan.buf.bytes + r->plan64.buf.bytes;

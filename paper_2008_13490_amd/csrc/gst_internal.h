@@ -327,6 +327,8 @@ struct Readout64Launch {
   const int64_t* slot_row;
   const int64_t* slot_ptr;
   const int64_t* slot_seq;
+  const int64_t* slot_pack;  // [n_slots][4]: node row, first sequence, slot_ptr[s], slot_ptr[s + 1]
+  const int32_t* slot_cnt;   // [n_slots][M]: the first sequence's counts
   const int32_t* counts;
   const double* W;
   double* probs;

@@ -641,7 +641,7 @@ __device__ __forceinline__ double mv_lds_row(const double* row, int lane, double
 __global__ __launch_bounds__(READOUT64_WAVES * 64) void readout64_kernel(const Readout64Launch a) {
   __shared__ double Es[16 * N64];
   const int l = threadIdx.x & 63;
-  const int64_t wv = (int64_t)blockIdx.x * READOUT64_WAVES + (threadIdx.x >> 6);
+  const int64_t wv = (int64_t)blockIdx.x * READOUT64_WAVES + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t nw = (int64_t)gridDim.x * READOUT64_WAVES;
   const int M = a.M;
   for (int x = threadIdx.x; x < M * N64; x += READOUT64_WAVES * 64) Es[x] = a.E[x];
@@ -658,43 +658,75 @@ __global__ __launch_bounds__(READOUT64_WAVES * 64) void readout64_kernel(const R
 #pragma unroll
   for (int m = 0; m < 16; ++m) dE[m] = 0.0;
   unsigned nonpos = 0;
-  for (int64_t s = wv; s < a.n_slots; s += nw) {
-    const double f = fa[a.slot_row[s] * N64 + l];
-    const double p = mv_lds_row(Erow, l, f);
-    double dps = 0.0;
-    const int64_t q1 = a.slot_ptr[s + 1];
-    for (int64_t q = a.slot_ptr[s]; q < q1; ++q) {
-      const int64_t seq = a.slot_seq[q];
-      if (l < M) {
-        const int64_t o = seq * M + l;
-        if (a.probs) g_probs[o] = p;
-        if (a.mode == MODE_LOGLIK) {
-          const int32_t N = g_counts[o];
-          if (N > 0) {
-            if (p <= 0.0) {
-              ++nonpos;
-              obj = INFINITY;
-            } else {
-              obj -= (double)N * log(p);
-              dps += -(double)N / p;
+  // The wave's slots s = wv + j nw in groups of RG: the group's packed slot
+  // records and first-sequence counts are loaded together, then the group's
+  // states (and, for vector-Jacobian products, weights), so that a group costs
+  // two memory round trips instead of three per slot.  Slots are summed in the
+  // same order as one at a time.
+  constexpr int RG = 4;
+  const auto* g_pack = as_global(a.slot_pack);
+  const auto* g_cnt = as_global(a.slot_cnt);
+  const int64_t n_my = wv < a.n_slots ? (a.n_slots - 1 - wv) / nw + 1 : 0;
+  for (int64_t j0 = 0; j0 < n_my; j0 += RG) {
+    int64_t row[RG], seq0[RG], q0[RG], q1[RG];
+    int32_t c0[RG];
+#pragma unroll
+    for (int g = 0; g < RG; ++g) {
+      const bool valid = j0 + g < n_my;
+      const int64_t s = wv + (j0 + g) * nw;
+      const int64_t* pk = a.slot_pack + 4 * (valid ? s : 0);
+      row[g] = pk[0];
+      seq0[g] = pk[1];
+      q0[g] = pk[2];
+      q1[g] = valid ? pk[3] : pk[2];
+      c0[g] = (a.mode == MODE_LOGLIK && valid && l < M) ? g_cnt[s * M + l] : 0;
+    }
+    double fg[RG], w0[RG];
+#pragma unroll
+    for (int g = 0; g < RG; ++g) {
+      fg[g] = fa[row[g] * N64 + l];
+      w0[g] = (a.mode == MODE_VJP && q1[g] > q0[g] && l < M) ? g_W[seq0[g] * M + l] : 0.0;
+    }
+#pragma unroll
+    for (int g = 0; g < RG; ++g) {
+      if (j0 + g >= n_my) break;
+      const int64_t s = wv + (j0 + g) * nw;
+      const double f = fg[g];
+      const double p = mv_lds_row(Erow, l, f);
+      double dps = 0.0;
+      for (int64_t q = q0[g]; q < q1[g]; ++q) {
+        const int64_t seq = q == q0[g] ? seq0[g] : a.slot_seq[q];
+        if (l < M) {
+          const int64_t o = seq * M + l;
+          if (a.probs) g_probs[o] = p;
+          if (a.mode == MODE_LOGLIK) {
+            const int32_t N = q == q0[g] ? c0[g] : g_counts[o];
+            if (N > 0) {
+              if (p <= 0.0) {
+                ++nonpos;
+                obj = INFINITY;
+              } else {
+                obj -= (double)N * log(p);
+                dps += -(double)N / p;
+              }
             }
+          } else if (a.mode == MODE_VJP) {
+            dps += q == q0[g] ? w0[g] : g_W[o];
           }
-        } else if (a.mode == MODE_VJP) {
-          dps += g_W[o];
         }
       }
-    }
-    if (!grad) continue;
-    double b = 0.0;
+      if (!grad) continue;
+      double b = 0.0;
 #pragma unroll
-    for (int m = 0; m < 16; ++m) {
-      if (m < M) {
-        const double dpm = __shfl(dps, m);
-        dE[m] = fma(dpm, f, dE[m]);
-        b = fma(Es[m * N64 + l], dpm, b);
+      for (int m = 0; m < 16; ++m) {
+        if (m < M) {
+          const double dpm = __shfl(dps, m);
+          dE[m] = fma(dpm, f, dE[m]);
+          b = fma(Es[m * N64 + l], dpm, b);
+        }
       }
+      a.INJ[s * N64 + l] = b;
     }
-    a.INJ[s * N64 + l] = b;
   }
   if (a.slab) {
     const int64_t Pc = 1 + N64 + (int64_t)M * N64;
