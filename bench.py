@@ -571,6 +571,28 @@ def run_structured(args):
     elapsed = t1 - t0
     value = n_sets * S * args.steps / elapsed
     extra = {}
+    if batch_extra is None and args.path == "resident" and args.param == "full":
+        # the same evaluation through the torch.autograd.Function wrapper:
+        # forward (objective; the library computes the gradient in the same
+        # launch sequence) and backward (hands the gradient to the leaves)
+        from paper_2008_13490_amd import autograd as AG
+        leaves = [torch.as_tensor(x, device=dev).clone().requires_grad_(True) for x in (m.rho, m.effects, m.gates)]
+
+        def ag_step():
+            for t in leaves:
+                t.grad = None
+            AG.gst_nll(leaves[0], leaves[1], leaves[2], req).backward()
+
+        for _ in range(3):
+            ag_step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            ag_step()
+        torch.cuda.synchronize()
+        ag_s = (time.perf_counter() - t0) / args.steps
+        extra["autograd"] = {"ms_per_step": ag_s * 1e3, "value": S / ag_s,
+                             "what": "forward + backward through torch.autograd.Function (gst_nll)"}
     if batch_extra is not None:
         # the same steps replayed from the captured graph (no per-kernel
         # events), and the 64 requests evaluated one after another
