@@ -353,3 +353,33 @@ def test_plans_batched_per_kernel_equal_standalone(gpu):
         ctx.sync()
         same(b, ref)
     b.close()
+
+
+def test_many_plans_share_workgroups_and_equal_standalone(gpu):
+    """Twenty requests on the structured two-qubit list: enough item chunks
+    that the batch gives each request fewer item and fill workgroups than its
+    standalone launch (several chunks per workgroup); the chunks keep their
+    head rows, so every result is still the same bits as alone."""
+    import torch
+    api, ctx = gpu
+    c2 = W.structured_workload("c2")
+    rng = np.random.default_rng(77)
+    n = 20
+    reqs, thetas = [], []
+    for x in range(n):
+        gs = c2.model if x == 0 else W.noisy_gateset("2q", 1e-3, 0.01, rng)
+        reqs.append(api.Request(ctx, 2, gs.K, gs.M, c2.seqs.offsets, c2.seqs.gates, c2.counts))
+        thetas.append(api.DeviceGateSet.from_numpy(2, gs.rho, gs.effects, gs.gates))
+    ref = []
+    for r, t in zip(reqs, thetas):
+        o, p, g = r.eval(t, want_probs=True, want_grad=True)
+        ref.append((o, p, g))
+    ctx.sync()
+    say(f"[plan batch] {n} requests")
+    b = api.Batch(ctx, reqs, thetas, want_probs=True, want_grad=True, capture_graph=True)
+    for _ in range(2):
+        b.run()
+        ctx.sync()
+        for x, (o, p, g) in enumerate(ref):
+            assert torch.equal(b.obj[x], o) and torch.equal(b.probs[x], p) and torch.equal(b.grad[x], g), x
+    b.close()
