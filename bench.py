@@ -555,14 +555,21 @@ def run_structured(args):
 
     work = [f for f in brk if fam_flops(f) > 0] or list(brk)
     dom = max(work, key=lambda f: brk[f][0])
-    # timed region: events around the dominant family only
-    api.profile_only(ctx, dom)
+    # timed region: no events (a launch with timing events costs host and
+    # queue time between the kernels: about 5 us per c2 evaluation)
+    api.profile_enable(ctx, False)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
         step()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    # kernel pass: the same steps again, events around the dominant family
+    # only (kernel-stamped, so the kernel's own duration is what they time)
+    api.profile_enable(ctx, True)
+    api.profile_only(ctx, dom)
+    for _ in range(args.steps):
+        step()
     ctx.sync()
     tot = _profile(api, ctx, (dom,))
     api.profile_only(ctx, None)
@@ -775,13 +782,19 @@ def run_predict(args):
     ctx.sync()
     brk = _profile(api, ctx, families)
     dom = max(brk, key=lambda f: brk[f][0])
-    api.profile_only(ctx, dom)
+    # timed region without events, then the kernel pass with events on the
+    # dominant family (as in the evaluation benchmark)
+    api.profile_enable(ctx, False)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
         step()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    api.profile_enable(ctx, True)
+    api.profile_only(ctx, dom)
+    for _ in range(args.steps):
+        step()
     ctx.sync()
     tot = _profile(api, ctx, (dom,))
     api.profile_only(ctx, None)

@@ -224,7 +224,8 @@ struct DevicePlan {
   int64_t* trunk_anchor = nullptr;
 
   int64_t* inj_ptr = nullptr;
-  int64_t* inj_src = nullptr;
+  int32_t* item_src = nullptr;
+  int32_t* trunk_src = nullptr;
   int64_t* op_ptr = nullptr;
   uint32_t* op_desc = nullptr;
   int32_t* op_slot = nullptr;
@@ -236,8 +237,7 @@ struct DevicePlan {
   int64_t* chunk_end = nullptr;
   double* FA = nullptr;         // state arena [1 + trunk_steps + item_steps][D]
   double* BA = nullptr;         // adjoint arena [trunk_steps + item_steps][D]
-  double* item_adj = nullptr;   // [n_items][D]
-  double* trunk_adj = nullptr;  // [n_trunks][D]
+  double* src_adj = nullptr;    // [source rows][D]: adjoints arriving at stored states, slot by slot
   double* inj = nullptr;        // [n_inj][D]
   // germ-power jumps: each trunk's jump pattern, and the fill tasks
   uint32_t* trunk_jpat = nullptr;
@@ -566,12 +566,11 @@ int upload_plan(gst_req* r, const gst::HostPlan& P) {
   const size_t o_op = c.take<int64_t>(nT + 1), o_od = c.take<uint32_t>(nOp + 1), o_os = c.take<int32_t>(nOp + 1);
   const size_t o_items = c.take<int64_t>(4 * nI), o_tp = c.take<int64_t>(nT + 1), o_ta = c.take<int64_t>(nT + 1),
                o_ip = c.take<int64_t>(nJ + 1),
-               o_is = c.take<int64_t>(P.inj_src.size() + 1), o_isp = c.take<int64_t>(nI + 1),
+               o_isrc = c.take<int32_t>(nI + 1), o_tsrc = c.take<int32_t>(nT + 1), o_isp = c.take<int64_t>(nI + 1),
                o_rb = c.take<int64_t>(nR + 1), o_rf = c.take<int64_t>(nR + 1), o_cg = c.take<int64_t>(nC + 1),
                o_cb = c.take<int64_t>(nC + 1), o_ce = c.take<int64_t>(nC + 1),
                o_fa = c.take<double>((size_t)(1 + nTS + nIS) * D), o_ba = c.take<double>((size_t)(nTS + nIS + 1) * D),
-               o_ia = c.take<double>((size_t)(nI + 1) * D), o_tad = c.take<double>((size_t)(nT + 1) * D),
-               o_inj = c.take<double>((size_t)(nJ + 1) * D);
+               o_src = c.take<double>((size_t)(P.n_src_rows() + 1) * D), o_inj = c.take<double>((size_t)(nJ + 1) * D);
   const size_t nF = P.fill_first.size();
   const size_t o_jp = c.take<uint32_t>(nT + 1), o_jg3 = c.take<uint8_t>(nT + 1), o_ff = c.take<int64_t>(nF + 1),
                o_fi = c.take<int64_t>(nF + 1), o_fn = c.take<int32_t>(nF + 1), o_fp = c.take<uint32_t>(nF + 1),
@@ -586,7 +585,8 @@ int upload_plan(gst_req* r, const gst::HostPlan& P) {
   d.trunk_ptr = reinterpret_cast<int64_t*>(b + o_tp);
   d.trunk_anchor = reinterpret_cast<int64_t*>(b + o_ta);
   d.inj_ptr = reinterpret_cast<int64_t*>(b + o_ip);
-  d.inj_src = reinterpret_cast<int64_t*>(b + o_is);
+  d.item_src = reinterpret_cast<int32_t*>(b + o_isrc);
+  d.trunk_src = reinterpret_cast<int32_t*>(b + o_tsrc);
   d.item_step_ptr = reinterpret_cast<int64_t*>(b + o_isp);
   d.rec_b = reinterpret_cast<int64_t*>(b + o_rb);
   d.rec_f = reinterpret_cast<int64_t*>(b + o_rf);
@@ -595,8 +595,7 @@ int upload_plan(gst_req* r, const gst::HostPlan& P) {
   d.chunk_end = reinterpret_cast<int64_t*>(b + o_ce);
   d.FA = reinterpret_cast<double*>(b + o_fa);
   d.BA = reinterpret_cast<double*>(b + o_ba);
-  d.item_adj = reinterpret_cast<double*>(b + o_ia);
-  d.trunk_adj = reinterpret_cast<double*>(b + o_tad);
+  d.src_adj = reinterpret_cast<double*>(b + o_src);
   d.inj = reinterpret_cast<double*>(b + o_inj);
   d.trunk_jpat = reinterpret_cast<uint32_t*>(b + o_jp);
   d.trunk_jg3 = reinterpret_cast<uint8_t*>(b + o_jg3);
@@ -616,7 +615,8 @@ int upload_plan(gst_req* r, const gst::HostPlan& P) {
   if ((rc = put(d.trunk_ptr, P.trunk_ptr.data(), P.trunk_ptr.size() * 8))) return rc;
   if ((rc = put(d.trunk_anchor, P.trunk_anchor.data(), P.trunk_anchor.size() * 8))) return rc;
   if ((rc = put(d.inj_ptr, P.inj_ptr.data(), P.inj_ptr.size() * 8))) return rc;
-  if ((rc = put(d.inj_src, P.inj_src.data(), P.inj_src.size() * 8))) return rc;
+  if ((rc = put(d.item_src, P.item_src.data(), (size_t)nI * 4))) return rc;
+  if ((rc = put(d.trunk_src, P.trunk_src.data(), (size_t)nT * 4))) return rc;
   if ((rc = put(d.item_step_ptr, P.item_step_ptr.data(), P.item_step_ptr.size() * 8))) return rc;
   if ((rc = put(d.rec_b, P.rec_b.data(), P.rec_b.size() * 8))) return rc;
   if ((rc = put(d.rec_f, P.rec_f.data(), P.rec_f.size() * 8))) return rc;
@@ -971,7 +971,7 @@ void plan_setup(gst_req* r, const gst_gateset* th, int mode, const double* w, do
   a.nTS = P.trunk_steps();
   a.trunk_ptr = d.trunk_ptr;
   a.trunk_anchor = d.trunk_anchor;
-  a.trunk_adj = d.trunk_adj;
+  a.trunk_src = d.trunk_src;
   a.op_ptr = d.op_ptr;
   a.op_desc = d.op_desc;
   a.op_slot = d.op_slot;
@@ -979,7 +979,7 @@ void plan_setup(gst_req* r, const gst_gateset* th, int mode, const double* w, do
   a.items = d.items;
   a.item_step_ptr = d.item_step_ptr;
   a.gates = r->gates;
-  a.item_adj = d.item_adj;
+  a.item_src = d.item_src;
   a.counts = r->counts;
   a.W = w;
   a.probs = probs;
@@ -987,6 +987,7 @@ void plan_setup(gst_req* r, const gst_gateset* th, int mode, const double* w, do
   a.want_grad = s.want_grad;
   a.FA = d.FA;
   a.BA = d.BA;
+  a.src_adj = d.src_adj;
   a.inj = d.inj;
   a.status = ctx->status;
   a.req_nonpos = req_nonpos;
@@ -1006,9 +1007,7 @@ void plan_setup(gst_req* r, const gst_gateset* th, int mode, const double* w, do
   gst::InjectLaunch& in = s.in;
   in.D = D;
   in.inj_ptr = d.inj_ptr;
-  in.inj_src = d.inj_src;
-  in.item_adj = d.item_adj;
-  in.trunk_adj = d.trunk_adj;
+  in.src_adj = d.src_adj;
   in.inj = d.inj;
   in.n_levels = s.want_grad ? P.n_levels : 0;
 

@@ -20,6 +20,7 @@ constexpr int C = 8;                   // steps per reverse segment (checkpoint 
 constexpr int ENT = TPW * C;           // stash entries per wave (<= 64)
 
 typedef double d4 __attribute__((ext_vector_type(4)));
+typedef double d2 __attribute__((ext_vector_type(2)));
 
 // ---------------------------------------------------------------------------
 // cross-lane helpers

@@ -81,7 +81,7 @@ struct PlanArgs {
   int64_t t_begin, t_end;
   const int64_t* trunk_ptr;      // [n_trunks + 1]
   const int64_t* trunk_anchor;   // [n_trunks] location (state after trunk step), -1 = rho
-  double* trunk_adj;             // [n_trunks][D] adjoint arriving at the anchor
+  const int32_t* trunk_src;      // [n_trunks] source-arena row of the adjoint at the anchor, -1 = rho
   // each trunk's chain as ops: bits 0..6 gate index, or jump level with bit 7
   // set; bits 8..15 the steps the op spans; op_slot = injection slot of the
   // state after the op (-1 none)
@@ -93,15 +93,17 @@ struct PlanArgs {
   const int64_t* items;          // [n_items][4] seq, beg, end, anchor location
   const int64_t* item_step_ptr;  // [n_items + 1]
   const uint8_t* gates;          // sequence gate indices (beg/end index into it)
-  double* item_adj;              // [n_items][D]
+  const int32_t* item_src;       // [n_items] source-arena row of the item's adjoint, -1 = rho
   const int32_t* counts;
   const double* W;
   double* probs;
   int mode;
   int want_grad;
-  // arenas and injections
+  // arenas and injections: the adjoints arriving at stored states are rows
+  // of the source arena, slot by slot; inj holds each slot's sum
   double* FA;
   double* BA;
+  double* src_adj;               // [source rows][D]
   const double* inj;             // [n_inj][D]
   double* slab;                  // [blocks][1 + D + M*D]: objective, dL/drho, dL/dE
   unsigned long long* status;
@@ -128,15 +130,13 @@ struct PlanArgs {
   int fill_blocks;
 };
 
-// inj[slot] = sum over its sources (ascending): item adjoints (src >= 0) and
-// trunk anchor adjoints (src = -(t+1)).
+// inj[slot] = the sum of source-arena rows inj_ptr[slot] .. inj_ptr[slot + 1]
+// - 1 (the adjoints of the items and trunks anchored at the slot's state).
 struct InjectLaunch {
   int D;
   int64_t s_begin, s_end;
   const int64_t* inj_ptr;
-  const int64_t* inj_src;
-  const double* item_adj;   // [n_items][D]
-  const double* trunk_adj;  // [n_trunks][D]
+  const double* src_adj;    // [source rows][D]
   double* inj;              // [n_inj][D]
   // batched launches only: levels (0 = no reverse sweep) and the slot range of
   // each ([n_levels + 1], device)

@@ -413,7 +413,6 @@ struct LoadGates {
 // Writes the tile-step's 16 states (columns c = 0..15) to 16 consecutive arena
 // rows, two doubles per lane and store, so that every wave store covers 1 KB of
 // consecutive memory.
-typedef double d2 __attribute__((ext_vector_type(2)));
 
 __device__ __forceinline__ void store_tile_rows(const double* V, double* out, int tid) {
   auto* g = as_global(reinterpret_cast<d2*>(out));

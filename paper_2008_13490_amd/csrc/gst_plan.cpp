@@ -193,15 +193,78 @@ bool build_plan(const int64_t* off, const uint8_t* gates, int64_t S, int K, cons
   for (int64_t r = 0; r < nT; ++r) P.trunk_level_ptr[trunks[order[r]].level + 1] = r + 1;
   for (int l = 1; l <= P.n_levels; ++l) P.trunk_level_ptr[l] = std::max(P.trunk_level_ptr[l], P.trunk_level_ptr[l - 1]);
 
+  // ---- 3b. long periodic runs of the trunks' words ----
+  // A germ power g^l is a run of repetitions of g's gates.  A state that an
+  // item starts from ends the trunk's segment there (its adjoint is
+  // injected), so a start inside a repetition, or at a boundary few items
+  // share, breaks the run's germ-power jumps into short ones and single gate
+  // steps on the chain.  Such items start earlier instead, at a repetition
+  // boundary that others share, and take the steps in between themselves:
+  // the items run in parallel, the chain does not.  Runs are found greedily
+  // from the trunk's start, as the segments below find them; at each state
+  // of a run of at least rep_anchor_min repetitions, run_per is the period
+  // (0 elsewhere), run_ref the state before the run's first gate (boundaries
+  // are run_ref + k run_per; base - 1 for a run from the trunk's start) and
+  // run_lo the earliest state of the trunk an item may move back to.
+  std::vector<int32_t> run_per((size_t)P.trunk_ptr[nT], 0);
+  std::vector<int64_t> run_ref((size_t)P.trunk_ptr[nT], 0), run_lo((size_t)P.trunk_ptr[nT], 0);
+  if (opt.rep_anchor_min > 0) {
+    for (int64_t r = 0; r < nT; ++r) {
+      const int64_t base = P.trunk_ptr[r], L = P.trunk_ptr[r + 1] - base;
+      const uint8_t* w = P.trunk_gates.data() + base;
+      for (int64_t j = 0; j < L;) {
+        int bp = 1;
+        int64_t bc = 1;
+        for (int p = 1; p <= 4 && p <= L - j; ++p) {
+          int64_t c = 1;
+          while ((c + 1) * p <= L - j && std::memcmp(w + j, w + j + c * p, p) == 0) ++c;
+          if (c * p > bc * bp) {
+            bp = p;
+            bc = c;
+          }
+        }
+        if (bc >= opt.rep_anchor_min)
+          for (int64_t x = std::max<int64_t>(j - 1, 0); x < j + bp * bc; ++x) {
+            run_per[base + x] = bp;
+            run_ref[base + x] = base + j - 1;
+            run_lo[base + x] = base + std::max<int64_t>(j - 1, 0);
+          }
+        j += bp * bc;
+      }
+    }
+  }
   // ---- 4. items: each sequence from its deepest stored prefix ----
   std::vector<int64_t> it((size_t)S * 4);
   for (int64_t s = 0; s < S; ++s) {
     int32_t n = term[s];
     while (n != 0 && owner[n] < 0) n = parent[n];
+    int64_t loc = n == 0 ? -1 : loc_of(n), beg = off[s] + depth[n];
+    if (loc >= 0 && run_per[loc] > 1) {  // back to the start of the repetition (within the trunk)
+      const int64_t back = (loc - run_ref[loc]) % run_per[loc];
+      if (loc - back >= run_lo[loc]) {
+        loc -= back;
+        beg -= back;
+      }
+    }
     it[4 * s + 0] = s;
-    it[4 * s + 1] = off[s] + depth[n];
+    it[4 * s + 1] = beg;
     it[4 * s + 2] = off[s + 1];
-    it[4 * s + 3] = n == 0 ? -1 : loc_of(n);
+    it[4 * s + 3] = loc;
+  }
+  if (opt.rep_anchor_min > 0 && opt.anchor_min_share > 1) {
+    std::vector<int32_t> share((size_t)P.trunk_ptr[nT], 0);
+    for (int64_t s = 0; s < S; ++s)
+      if (it[4 * s + 3] >= 0) ++share[it[4 * s + 3]];
+    for (int64_t s = 0; s < S; ++s) {
+      const int64_t loc = it[4 * s + 3];
+      if (loc < 0 || run_per[loc] == 0 || share[loc] >= opt.anchor_min_share) continue;
+      for (int64_t b = loc - run_per[loc]; b >= run_lo[loc] && loc - b <= opt.anchor_max_back; b -= run_per[loc])
+        if (share[b] >= opt.anchor_min_share) {
+          it[4 * s + 1] -= loc - b;
+          it[4 * s + 3] = b;
+          break;
+        }
+    }
   }
   std::vector<int64_t> iorder((size_t)S);
   std::iota(iorder.begin(), iorder.end(), 0);
@@ -424,6 +487,17 @@ bool build_plan(const int64_t* off, const uint8_t* gates, int64_t S, int K, cons
   for (int64_t r = 0; r < nT; ++r)
     if (P.trunk_anchor[r] < 0) P.inj_src.push_back(-(r + 1));
   P.inj_ptr.push_back((int64_t)P.inj_src.size());
+  // rows of the source arena (the root slot's sources have none)
+  if (P.inj_src.size() >= (size_t)INT32_MAX) return false;
+  P.item_src.assign(S, -1);
+  P.trunk_src.assign(nT, -1);
+  for (int64_t z = 0; z < P.inj_ptr[P.root_slot]; ++z) {
+    const int64_t src = P.inj_src[z];
+    if (src >= 0)
+      P.item_src[src] = (int32_t)z;
+    else
+      P.trunk_src[-src - 1] = (int32_t)z;
+  }
 
   if ((double)P.plan_steps() > opt.max_share_ratio * (double)P.sum_len) return false;
 

@@ -90,6 +90,12 @@ struct HostPlan {
   std::vector<int64_t> op_ptr;           // [n_trunks + 1]
   std::vector<uint32_t> op_desc;
   std::vector<int32_t> op_slot;
+  // The adjoints that reach stored states, in source order: source z of the
+  // injection lists (z < inj_ptr[root_slot]) is row z of the source arena, so
+  // the sources of slot s are rows inj_ptr[s] .. inj_ptr[s + 1] - 1.  Item q
+  // writes its adjoint to row item_src[q] and trunk t to row trunk_src[t]
+  // (-1: anchored at rho, no row).
+  std::vector<int32_t> item_src, trunk_src;
   int64_t n_items() const { return (int64_t)items.size() / 4; }
   int64_t n_trunks() const { return (int64_t)trunk_anchor.size(); }
   int64_t trunk_steps() const { return (int64_t)trunk_gates.size(); }
@@ -97,6 +103,7 @@ struct HostPlan {
   int64_t item_steps() const { return item_step_ptr.empty() ? 0 : item_step_ptr.back(); }
   int64_t n_chunks() const { return (int64_t)chunk_gate.size(); }
   int64_t n_fill() const { return (int64_t)fill_first.size(); }
+  int64_t n_src_rows() const { return root_slot < 0 ? 0 : inj_ptr[root_slot]; }
   int64_t n_jump_trunks() const {
     int64_t n = 0;
     for (uint32_t p : trunk_jump_pattern) n += p != 0;
@@ -113,6 +120,10 @@ struct PlanOptions {
   int chunk = 128;                      // gradient GEMM records per chunk (the kernel takes at most 128)
   int jump = 8;                         // repetitions per germ-power jump (power of two, <= 16); 0 = none
   int jump_min_save = 3;                // jump a run only if it shortens the chain by this many steps
+  int rep_anchor_min = 4;               // inside a periodic run of a trunk's word with at least this many
+                                        // repetitions, items start only at repetition boundaries (0 = anywhere)
+  int anchor_min_share = 6;             // ... and an item whose start state fewer items share moves back to
+  int anchor_max_back = 12;             // an earlier boundary of the run that as many share, at most this far
 };
 
 // Builds the plan.  Returns false (plan unused: evaluate sequence by

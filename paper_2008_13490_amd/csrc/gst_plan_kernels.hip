@@ -9,7 +9,9 @@
 //   item_kernel       every sequence from its deepest stored state: the rest of
 //                     its word, readout, objective, seeds and the reverse sweep
 //                     of that rest; states before and adjoints after each step
-//                     go to the arenas;
+//                     go to the arenas, the adjoint at its start state to the
+//                     source arena (the sources of one stored state are
+//                     consecutive rows there);
 //   inject_kernel     adjoints arriving at each stored state, summed in a
 //                     fixed order;
 //   trunk_bwd_kernel  reverse sweep of the trunks, adding the injected
@@ -94,7 +96,7 @@ __device__ void write_head(double* red, int hw, double obj, double drho, const d
 // A chunk's items staged in LDS: per item its descriptor (sequence, word
 // begin and end, anchor, first record row), its start state, its counts and
 // the first 16 gate indices of its word.
-constexpr int IST_DESC = 5;
+constexpr int IST_DESC = 6;
 __host__ __device__ inline size_t item_stage_bytes() {
   return (size_t)kItemChunk * (IST_DESC * 8 + 16 * 8 + 16 * 4 + 16 * 4);
 }
@@ -141,7 +143,39 @@ __device__ __forceinline__ uint32_t lane_u32(uint32_t v, int x) {
   return (uint32_t)__builtin_amdgcn_readlane((int)v, x);
 }
 
-// Trunks t_begin + blk, t_begin + blk + nblk, ... of [t_begin, t_end).
+// A trunk's descriptors, read by every lane (uniform addresses; the fourth
+// jump gate is taken from the aligned word holding it, so that all of them
+// are word loads).
+struct TrunkMeta {
+  int64_t beg, end, anchor, o0, o1;
+  uint32_t jp;
+  int jg3;
+  int32_t src;
+};
+__device__ __forceinline__ TrunkMeta trunk_meta(const PlanArgs& a, int64_t t) {
+  TrunkMeta m;
+  m.beg = a.trunk_ptr[t];
+  m.end = a.trunk_ptr[t + 1];
+  m.anchor = a.trunk_anchor[t];
+  m.o0 = a.op_ptr[t];
+  m.o1 = a.op_ptr[t + 1];
+  m.jp = a.trunk_jpat[t];
+  m.jg3 = (int)((reinterpret_cast<const uint32_t*>(a.trunk_jg3)[t >> 2] >> (8 * (t & 3))) & 0xffu);
+  m.src = a.trunk_src[t];
+  return m;
+}
+
+// Op descriptors of ops ob .. ob + 63, lane x holding op ob + x; lanes past
+// the trunk's last op o1 - 1 read that op again (they are never used).  The
+// loads are not masked, so nothing waits for them before their first use.
+__device__ __forceinline__ uint32_t op_descs(const PlanArgs& a, int64_t ob, int64_t o1, int lane) {
+  return a.op_desc[ob + lane < o1 ? ob + lane : o1 - 1];
+}
+
+// Trunks t_begin + blk, t_begin + blk + nblk, ... of [t_begin, t_end).  The
+// loads a chain needs are issued early: the trunk's descriptors, first ops
+// and anchor state (before the gate set is staged, for the workgroup's first
+// trunk), and each batch's successor before the batch's chain.
 template <int D>
 __device__ __forceinline__ void trunk_fwd_body(const PlanArgs& a, int64_t t_begin, int64_t t_end, int64_t blk,
                                                int64_t nblk) {
@@ -149,27 +183,44 @@ __device__ __forceinline__ void trunk_fwd_body(const PlanArgs& a, int64_t t_begi
   const int K = a.K;
   const Lds s = carve_trunk(lds_raw, K);
   const int lane = threadIdx.x & 63, i = lane & 15;
+  int64_t t = t_begin + blk;
+  TrunkMeta m{};
+  // the trunk's first ops and its anchor state (a deeper trunk's, or rho:
+  // rho's address stands in for the load when there is none)
+  uint32_t dl = 0u;
+  double fa = 0.0;
+  auto first_ops = [&]() {
+    if (m.o1 > m.o0) dl = op_descs(a, m.o0, m.o1, lane);
+    fa = (m.anchor >= 0 ? a.FA + (1 + m.anchor) * D : a.rho)[i < D ? i : 0];
+  };
+  if (t < t_end) {
+    m = trunk_meta(a, t);
+    first_ops();
+  }
   stage_gateset<D, 64, STAGE_G>(s, a.G, a.E, a.rho, K, a.M);
   if (blk == 0 && lane < D) a.FA[lane] = a.rho[lane];
   double* js = lds_raw + trunk_jump_doubles(K);
   const bool st = (D == 16) || lane < D;  // rows 1..3 store the same values as row 0
-  for (int64_t t = t_begin + blk; t < t_end; t += nblk) {
-    const int64_t beg = a.trunk_ptr[t];
-    const int64_t anc = a.trunk_anchor[t];
-    const int64_t o0 = a.op_ptr[t], o1 = a.op_ptr[t + 1];
-    const uint32_t jp = (uint32_t)__builtin_amdgcn_readfirstlane((int)a.trunk_jpat[t]);
-    if (jp != 0u) build_jumps(js, s.Gs, jp, a.trunk_jg3[t], a.jump_levels, false, lane);
-    double f = anc >= 0 ? load_state(a.FA, 1 + anc, D, i) : s.rho[i];
-    double* out = a.FA + (1 + beg) * D + i;  // state after trunk step j: out[j*D]
-    int64_t pos = 0;                         // steps done
+  for (; t < t_end; t += nblk) {
+    if (t != t_begin + blk) {
+      m = trunk_meta(a, t);
+      first_ops();
+    }
+    const int64_t o0 = m.o0, o1 = m.o1;
+    const uint32_t jp = (uint32_t)__builtin_amdgcn_readfirstlane((int)m.jp);
+    if (jp != 0u) build_jumps(js, s.Gs, jp, (uint8_t)m.jg3, a.jump_levels, false, lane);
+    double f = m.anchor >= 0 ? (i < D ? fa : 0.0) : s.rho[i];
+    double* out = a.FA + (1 + m.beg) * D + i;  // state after trunk step j: out[j*D]
+    int64_t pos = 0;                           // steps done
     for (int64_t ob = o0; ob < o1; ob += OPW) {
       const int n = (int)(o1 - ob < OPW ? o1 - ob : OPW);
-      const uint32_t dl = ob + lane < o1 ? a.op_desc[ob + lane] : 0u;
+      const uint32_t dc = dl;
+      if (ob + OPW < o1) dl = op_descs(a, ob + OPW, o1, lane);  // the next batch, during this chain
       // three ops per iteration, the rows of the next two ops in flight
-      auto rows = [&](int x) { return load_row(op_row(s.Gs, js, lane_u32(dl, x < n ? x : n - 1), i)); };
+      auto rows = [&](int x) { return load_row(op_row(s.Gs, js, lane_u32(dc, x < n ? x : n - 1), i)); };
       auto step = [&](const Row16& R, int x) {
         f = dot16(f, R);
-        pos += (lane_u32(dl, x) >> 8) & 0xffu;
+        pos += (lane_u32(dc, x) >> 8) & 0xffu;
         if (st) out[(pos - 1) * D] = f;
       };
       Row16 R0 = rows(0), R1 = rows(1);
@@ -241,8 +292,8 @@ __device__ __forceinline__ void item_body(const PlanArgs& a, int64_t blk, int64_
     if (tid < kItemChunk * IST_DESC) {
       const int it = tid / IST_DESC, c = tid % IST_DESC;
       const int64_t q = q0 + it;
-      int64_t v = c == 3 ? -1 : 0;
-      if (q < a.n_items) v = c < 4 ? a.items[4 * q + c] : a.item_step_ptr[q];
+      int64_t v = (c == 3 || c == 5) ? -1 : 0;
+      if (q < a.n_items) v = c < 4 ? a.items[4 * q + c] : (c == 4 ? a.item_step_ptr[q] : (int64_t)a.item_src[q]);
       st_desc[tid] = v;
     }
     lds_sync();
@@ -263,7 +314,7 @@ __device__ __forceinline__ void item_body(const PlanArgs& a, int64_t blk, int64_
     const bool has = q < a.n_items;
     const int64_t seq = st_desc[it * IST_DESC + 0], beg = st_desc[it * IST_DESC + 1];
     const int64_t end = st_desc[it * IST_DESC + 2], anc = st_desc[it * IST_DESC + 3];
-    const int64_t isp = st_desc[it * IST_DESC + 4];
+    const int64_t isp = st_desc[it * IST_DESC + 4], zrow = st_desc[it * IST_DESC + 5];
     const int32_t Nq = st_n[it * 16 + i];
     const int L = (int)(end - beg);
     const int Lw = wave_max4(L);
@@ -335,7 +386,7 @@ __device__ __forceinline__ void item_body(const PlanArgs& a, int64_t blk, int64_
         GST_IB(7) GST_IB(6) GST_IB(5) GST_IB(4) GST_IB(3) GST_IB(2) GST_IB(1) GST_IB(0)
 #undef GST_IB
       }
-      if (has && i < D) a.item_adj[q * D + i] = b;
+      if (has && i < D && zrow >= 0) a.src_adj[zrow * D + i] = b;
       if (has && anc < 0) drho += b;
     }
     }
@@ -365,53 +416,97 @@ __global__ __launch_bounds__(256) void item_kernel(const PlanArgs a) {
 // reverse with the transposed rows; the adjoints injected at stored states
 // (64 ops at a time, staged in LDS) are added on the way back
 // ---------------------------------------------------------------------------
-// Trunks t_begin + blk, ... as in the forward; workgroup blk writes head row blk of `slab`.
+// Trunks t_begin + blk, ... as in the forward; workgroup blk writes head row
+// blk of `slab`.  Batches of 64 ops run from the trunk's end; the loads are
+// issued ahead: the trunk's descriptors and the ops of its first two batches
+// (before the gate set is staged, for the workgroup's first trunk), the first
+// batch's injected vectors before the jump matrices are built, and during the
+// chain of batch k the vectors of batch k + 1 and the ops of batch k + 2.
 template <int D>
 __device__ __forceinline__ void trunk_bwd_body(const PlanArgs& a, int64_t t_begin, int64_t t_end, int64_t blk,
                                                int64_t nblk, double* slab) {
   extern __shared__ double lds_raw[];
   const int K = a.K;
   const Lds s = carve_trunk(lds_raw, K);
-  const int lane = threadIdx.x & 63, i = lane & 15, team = lane >> 4;
+  const int lane = threadIdx.x & 63, i = lane & 15;
+  int64_t t = t_begin + blk;
+  TrunkMeta m{};
+  // batch k of the trunk: ops max(o0, o1 - 64 (k + 1)) .. o1 - 64 k - 1
+  auto batch_ob = [&](int64_t oe) { return oe - OPW > m.o0 ? oe - OPW : m.o0; };
+  auto slots = [&](int64_t ob, int64_t oe) { return a.op_slot[ob + lane < oe ? ob + lane : oe - 1]; };
+  // the ops of the trunk's first two batches
+  uint32_t dl = 0u, dl1 = 0u;
+  int32_t sl = -1, sl1 = -1;
+  auto first_ops = [&]() {
+    const int64_t ob = batch_ob(m.o1);
+    if (m.o1 > m.o0) {
+      dl = op_descs(a, ob, m.o1, lane);
+      sl = slots(ob, m.o1);
+    }
+    if (ob > m.o0) {
+      dl1 = op_descs(a, batch_ob(ob), ob, lane);
+      sl1 = slots(batch_ob(ob), ob);
+    }
+  };
+  if (t < t_end) {
+    m = trunk_meta(a, t);
+    first_ops();
+  }
   stage_gateset<D, 64, STAGE_GT>(s, a.G, a.E, a.rho, K, a.M);
   double* inj_st = lds_raw + trunk_inj_doubles(K);
   double* js = lds_raw + trunk_jump_doubles(K);
   const bool st = (D == 16) || lane < D;
   double drho = 0.0;
-  for (int64_t t = t_begin + blk; t < t_end; t += nblk) {
-    const int64_t beg = a.trunk_ptr[t];
-    const int64_t o0 = a.op_ptr[t], o1 = a.op_ptr[t + 1];
-    const uint32_t jp = (uint32_t)__builtin_amdgcn_readfirstlane((int)a.trunk_jpat[t]);
-    if (jp != 0u) build_jumps(js, s.GTs, jp, a.trunk_jg3[t], a.jump_levels, true, lane);
-    double* ba = a.BA + beg * D + i;  // adjoint after trunk step j: ba[j*D]
-    int64_t pos = a.trunk_ptr[t + 1] - beg;
+  for (; t < t_end; t += nblk) {
+    if (t != t_begin + blk) {
+      m = trunk_meta(a, t);
+      first_ops();
+    }
+    const int64_t o0 = m.o0, o1 = m.o1;
+    // the injected vector of the op at lane x of a batch, read whole by that
+    // lane (its slot is the lane's own), unmasked: `use` says whether the op
+    // receives one
+    auto inj_load = [&](int64_t ob, int64_t oe, int32_t sl, d2 (&v)[D / 2], bool& use) {
+      use = lane < oe - ob && sl >= 0;
+      const d2* src = reinterpret_cast<const d2*>(a.inj + (use ? (int64_t)sl * D : 0));
+#pragma unroll
+      for (int c = 0; c < D / 2; ++c) v[c] = src[c];
+    };
+    int64_t oe = o1, ob = batch_ob(oe);
+    // the first batch's vectors load while the jump matrices are built
+    d2 v[D / 2];
+    bool use = false;
+    if (oe > o0) inj_load(ob, oe, sl, v, use);
+    const uint32_t jp = (uint32_t)__builtin_amdgcn_readfirstlane((int)m.jp);
+    if (jp != 0u) build_jumps(js, s.GTs, jp, (uint8_t)m.jg3, a.jump_levels, true, lane);
+    double* ba = a.BA + m.beg * D + i;  // adjoint after trunk step j: ba[j*D]
+    int64_t pos = m.end - m.beg;
     double b = 0.0;
-    for (int64_t oe = o1; oe > o0; oe -= OPW) {
-      const int64_t ob = oe - OPW > o0 ? oe - OPW : o0;
+    for (; oe > o0; oe = ob, ob = batch_ob(ob)) {
       const int n = (int)(oe - ob);
-      const uint32_t dl = ob + lane < oe ? a.op_desc[ob + lane] : 0u;
-      const int32_t sl = ob + lane < oe ? a.op_slot[ob + lane] : -1;
-      // the vectors injected at the states after these ops, all loads in flight
       wave_sync();  // the previous batch's vectors have been read
-      double v[OPW / TPW];
+      d2* row = reinterpret_cast<d2*>(inj_st + lane * 16);  // row x of op x
 #pragma unroll
-      for (int q = 0; q < OPW / TPW; ++q) {
-        const int x = TPW * q + team;
-        const int32_t slot = __shfl(sl, x);
-        const bool use = x < n && slot >= 0 && i < D;
-        const double val = a.inj[(use ? (int64_t)slot * D + i : 0)];
-        v[q] = use ? val : 0.0;
-      }
-#pragma unroll
-      for (int q = 0; q < OPW / TPW; ++q) inj_st[(TPW * q + team) * 16 + i] = v[q];
+      for (int c = 0; c < 8; ++c) row[c] = (use && c < D / 2) ? v[c < D / 2 ? c : 0] : d2{0.0, 0.0};
       wave_sync();
+      // ahead: the next batch's vectors, the ops of the one after
+      const uint32_t dc = dl;
+      if (ob > o0) {
+        const int64_t ob1 = batch_ob(ob);
+        inj_load(ob1, ob, sl1, v, use);
+        dl = dl1;
+        if (ob1 > o0) {
+          dl1 = op_descs(a, batch_ob(ob1), ob1, lane);
+          sl1 = slots(batch_ob(ob1), ob1);
+        }
+      }
       // three ops per iteration (descending), the rows of the next two in flight
-      auto rows = [&](int x) { return load_row(op_row(s.GTs, js, lane_u32(dl, x >= 0 ? x : 0), i)); };
+      auto rows = [&](int x) { return load_row(op_row(s.GTs, js, lane_u32(dc, x >= 0 ? x : 0), i)); };
       auto step = [&](const Row16& R, int x) {
         b += inj_st[x * 16 + i];
         if (st) ba[(pos - 1) * D] = b;
         b = dot16(b, R);
-        pos -= (lane_u32(dl, x) >> 8) & 0xffu;
+        pos -= (lane_u32(dc, x) >> 8) & 0xffu;
       };
       Row16 R0 = rows(n - 1), R1 = rows(n - 2);
       int x = n - 1;
@@ -426,8 +521,8 @@ __device__ __forceinline__ void trunk_bwd_body(const PlanArgs& a, int64_t t_begi
       if (x >= 0) step(R0, x);
       if (x >= 1) step(R1, x - 1);
     }
-    if (lane < D) a.trunk_adj[t * D + i] = b;
-    if (a.trunk_anchor[t] < 0) drho += b;
+    if (lane < D && m.src >= 0) a.src_adj[(int64_t)m.src * D + i] = b;
+    if (m.anchor < 0) drho += b;
   }
   // lanes 16..63 repeat lanes 0..15: only row 0 contributes
   if (lane >= 16) drho = 0.0;
@@ -517,8 +612,9 @@ __global__ __launch_bounds__(256) void fill_rev_kernel(const PlanArgs a) {
   run_fills<D, true>(a, s, blockIdx.x, gridDim.x);
 }
 
-// One wave per injection slot: four groups of 16 lanes take every fourth
-// source (two independent partial sums each), then the groups are combined
+// One wave per injection slot: its sources are consecutive rows of the
+// source arena; four groups of 16 lanes take every fourth row, the first
+// eight rows of each group loaded at once, and the group sums are combined
 // in a fixed order.
 __device__ __forceinline__ void inject_body(const InjectLaunch& a, int64_t s_begin, int64_t s_end, int64_t blk,
                                             int64_t nblk) {
@@ -526,20 +622,16 @@ __device__ __forceinline__ void inject_body(const InjectLaunch& a, int64_t s_beg
   const int lane = threadIdx.x, g = lane >> 4, i = lane & 15;
   for (int64_t slot = s_begin + blk; slot < s_end; slot += nblk) {
     const int64_t z0 = a.inj_ptr[slot], z1 = a.inj_ptr[slot + 1];
-    double v0 = 0.0, v1 = 0.0;
-    if (i < D) {
-      int64_t z = z0 + g;
-      for (; z + 4 < z1; z += 8) {
-        const int64_t s0 = a.inj_src[z], s1 = a.inj_src[z + 4];
-        v0 += s0 >= 0 ? a.item_adj[s0 * D + i] : a.trunk_adj[(-s0 - 1) * D + i];
-        v1 += s1 >= 0 ? a.item_adj[s1 * D + i] : a.trunk_adj[(-s1 - 1) * D + i];
-      }
-      if (z < z1) {
-        const int64_t s0 = a.inj_src[z];
-        v0 += s0 >= 0 ? a.item_adj[s0 * D + i] : a.trunk_adj[(-s0 - 1) * D + i];
-      }
+    double t[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int64_t z = z0 + g + 4 * u;
+      t[u] = a.src_adj[(z < z1 && i < D) ? z * D + i : 0];
     }
-    double v = v0 + v1;
+    double v = 0.0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v += (z0 + g + 4 * u < z1 && i < D) ? t[u] : 0.0;
+    for (int64_t z = z0 + g + 32; z < z1; z += 4) v += i < D ? a.src_adj[z * D + i] : 0.0;
     v += __shfl_xor(v, 16);
     v += __shfl_xor(v, 32);
     if (lane < D) a.inj[slot * D + i] = v;

@@ -8,6 +8,17 @@ namespace {
 gst::HostPlan g_plan;
 int g_jump = gst::PlanOptions().jump;
 int g_jump_min_save = gst::PlanOptions().jump_min_save;
+int g_rep_anchor_min = gst::PlanOptions().rep_anchor_min;
+int g_anchor_min_share = gst::PlanOptions().anchor_min_share;
+int g_anchor_max_back = gst::PlanOptions().anchor_max_back;
+}
+
+// Start-state options of the following plan_build calls (items inside long
+// periodic runs start at repetition boundaries that enough items share).
+extern "C" void plan_set_anchor(int rep_min, int min_share, int max_back) {
+  g_rep_anchor_min = rep_min;
+  g_anchor_min_share = min_share;
+  g_anchor_max_back = max_back;
 }
 
 // Germ-power jump options of the following plan_build calls.
@@ -24,6 +35,9 @@ extern "C" int plan_build(const int64_t* off, const uint8_t* gates, int64_t S, i
   opt.max_share_ratio = ratio;
   opt.jump = g_jump;
   opt.jump_min_save = g_jump_min_save;
+  opt.rep_anchor_min = g_rep_anchor_min;
+  opt.anchor_min_share = g_anchor_min_share;
+  opt.anchor_max_back = g_anchor_max_back;
   const bool used = gst::build_plan(off, gates, S, K, opt, &g_plan);
   const gst::HostPlan& P = g_plan;
   sizes[0] = used;
@@ -101,4 +115,10 @@ extern "C" void plan_copy_ops(int64_t* op_ptr, uint32_t* desc, int32_t* slot) {
   std::memcpy(op_ptr, P.op_ptr.data(), P.op_ptr.size() * 8);
   std::memcpy(desc, P.op_desc.data(), P.op_desc.size() * 4);
   std::memcpy(slot, P.op_slot.data(), P.op_slot.size() * 4);
+}
+
+extern "C" void plan_copy_sources(int32_t* item_src, int32_t* trunk_src) {
+  const gst::HostPlan& P = g_plan;
+  std::memcpy(item_src, P.item_src.data(), P.item_src.size() * 4);
+  std::memcpy(trunk_src, P.trunk_src.data(), P.trunk_src.size() * 4);
 }

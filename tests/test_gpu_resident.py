@@ -124,6 +124,21 @@ def test_resident_two_levels(oracle_lib, gpu):
     assert req.plan_info()["levels"] >= 2
 
 
+def test_resident_crowded_state(oracle_lib, gpu):
+    """One stored state receives 300 item adjoints: more source rows than the
+    injection kernel loads at once (eight per group of lanes)."""
+    api, ctx = gpu
+    rng = np.random.default_rng(13)
+    base = list(rng.integers(0, 6, 48))
+    words = [base + list(rng.integers(0, 6, int(rng.integers(1, 5)))) for _ in range(300)]
+    words += [base[:20], [], base]
+    sl = W.from_words(words)
+    gs = W.noisy_gateset("2q", 1e-3, 0.01, rng)
+    counts = rng.integers(0, 30, size=(sl.S, gs.M)).astype(np.int32)
+    counts[oracle_lib.probs(gs.rho, gs.effects, gs.gates, sl.offsets, sl.gates) <= 0] = 0
+    run_request(oracle_lib, api, ctx, gs, sl, counts, "crowded state", expect_plan=True)
+
+
 def test_resident_random_words_plain(oracle_lib, gpu):
     api, ctx = gpu
     w = W.random_workload("2q", 300, 300, 17, lmin=0)

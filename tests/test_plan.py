@@ -39,6 +39,7 @@ def planlib(tmp_path_factory):
     lib.plan_copy_jumps.argtypes = [P] * 7
     lib.plan_n_ops.restype = ctypes.c_int64
     lib.plan_copy_ops.argtypes = [P] * 3
+    lib.plan_copy_sources.argtypes = [P] * 2
     return lib
 
 
@@ -96,6 +97,10 @@ def get_plan(lib, sl, K, min_trunk=24, reanchor=8, ratio=0.8):
         P["op_slot"] = np.zeros(max(nOp, 1), np.int32)
         lib.plan_copy_ops(P["op_ptr"].ctypes.data, P["op_desc"].ctypes.data, P["op_slot"].ctypes.data)
         P["op_desc"], P["op_slot"] = P["op_desc"][:nOp], P["op_slot"][:nOp]
+        P["item_src"] = np.zeros(max(nI, 1), np.int32)
+        P["trunk_src"] = np.zeros(max(nT, 1), np.int32)
+        lib.plan_copy_sources(P["item_src"].ctypes.data, P["trunk_src"].ctypes.data)
+        P["item_src"], P["trunk_src"] = P["item_src"][:nI], P["trunk_src"][:nT]
     P["trunk_gates"] = P["trunk_gates"][:nTS]
     P["trunk_inj"] = P["trunk_inj"][:nTS]
     P["inj_loc"] = P["inj_loc"][:nJ]
@@ -524,3 +529,65 @@ def test_trunk_ops(planlib, name, jump):
         assert pos == tp[t + 1] - tp[t]
         assert word == list(tg[tp[t]:tp[t + 1]])
     assert (n_jump_ops > 0) == (jump > 0)
+
+
+@pytest.mark.parametrize("name,jump", [("c1", 8), ("c2", 8), ("c2", 0), ("multilevel", 8)])
+def test_source_rows(planlib, name, jump):
+    """The adjoints that reach stored states in source order: the row of an
+    item or trunk is its position in the injection lists (none when anchored
+    at rho, that is for the root slot's sources), so the sources of slot s
+    are the consecutive rows inj_ptr[s] .. inj_ptr[s + 1] - 1."""
+    rng = np.random.default_rng(5)
+    planlib.plan_set_jump(jump, 3)
+    try:
+        if name == "multilevel":
+            P = get_plan(planlib, multilevel_list(rng), 3, min_trunk=8, reanchor=4, ratio=1.0)
+            assert P["n_levels"] >= 2
+        else:
+            w = W.structured_workload(name)
+            P = get_plan(planlib, w.seqs, w.model.K)
+    finally:
+        planlib.plan_set_jump(8, 3)
+    assert P["used"]
+    ip, src, root = P["inj_ptr"], P["inj_src"], P["root_slot"]
+    n_rows = int(ip[root])
+    assert np.array_equal(P["item_src"] < 0, P["items"][:, 3] < 0)
+    assert np.array_equal(P["trunk_src"] < 0, P["trunk_anchor"] < 0)
+    rows = np.full(n_rows, -1)
+    for q, z in enumerate(P["item_src"]):
+        if z >= 0:
+            assert src[z] == q and rows[z] < 0
+            rows[z] = z
+    for t, z in enumerate(P["trunk_src"]):
+        if z >= 0:
+            assert src[z] == -(t + 1) and rows[z] < 0
+            rows[z] = z
+    assert np.array_equal(rows, np.arange(n_rows))  # every row has exactly one writer
+    # the root slot's sources are the trunks anchored at rho, which have no row
+    assert sorted(-src[ip[root]:ip[root + 1]] - 1) == sorted(np.nonzero(P["trunk_anchor"] < 0)[0])
+
+
+def multilevel_list(rng):
+    """Two levels of trunks (a long common prefix, long branches below the
+    re-anchoring depth) with items anchored on both."""
+    base = list(rng.integers(0, 3, 40))
+    words = [base + list(rng.integers(0, 3, int(rng.integers(20, 40)))) + list(rng.integers(0, 3, k))
+             for k in range(6) for _ in range(3)]
+    words += [base[:30 + k] for k in range(5)] + [[]]
+    return W.from_words(words)
+
+
+def crowded_list(rng, n_items=300):
+    """A long shared prefix whose last state receives n_items sources."""
+    base = list(rng.integers(0, 3, 48))
+    words = [base + list(rng.integers(0, 3, int(rng.integers(1, 5)))) for _ in range(n_items)]
+    return W.from_words(words + [base[:20], []])
+
+
+def test_source_rows_crowded_state(planlib):
+    """A slot with hundreds of sources: more rows than the injection kernel
+    loads at once (eight per group of lanes)."""
+    rng = np.random.default_rng(6)
+    P = get_plan(planlib, crowded_list(rng), 3, min_trunk=24, reanchor=8, ratio=1.0)
+    assert P["used"]
+    assert np.diff(P["inj_ptr"]).max() > 192
