@@ -242,6 +242,7 @@ struct DevicePlan {
   // germ-power jumps: each trunk's jump pattern, and the fill tasks
   uint32_t* trunk_jpat = nullptr;
   uint8_t* trunk_jg3 = nullptr;
+  uint8_t* trunk_jlev = nullptr;
   int64_t* fill_first = nullptr;
   int64_t* fill_in = nullptr;
   int32_t* fill_n = nullptr;
@@ -572,7 +573,7 @@ int upload_plan(gst_req* r, const gst::HostPlan& P) {
                o_fa = c.take<double>((size_t)(1 + nTS + nIS) * D), o_ba = c.take<double>((size_t)(nTS + nIS + 1) * D),
                o_src = c.take<double>((size_t)(P.n_src_rows() + 1) * D), o_inj = c.take<double>((size_t)(nJ + 1) * D);
   const size_t nF = P.fill_first.size();
-  const size_t o_jp = c.take<uint32_t>(nT + 1), o_jg3 = c.take<uint8_t>(nT + 1), o_ff = c.take<int64_t>(nF + 1),
+  const size_t o_jp = c.take<uint32_t>(nT + 1), o_jg3 = c.take<uint8_t>(nT + 1), o_jlv = c.take<uint8_t>(nT + 1), o_ff = c.take<int64_t>(nF + 1),
                o_fi = c.take<int64_t>(nF + 1), o_fn = c.take<int32_t>(nF + 1), o_fp = c.take<uint32_t>(nF + 1),
                o_fg3 = c.take<uint8_t>(nF + 1);
   int rc = d.buf.reserve(c.off + 256, r->ctx->stream);
@@ -599,6 +600,7 @@ int upload_plan(gst_req* r, const gst::HostPlan& P) {
   d.inj = reinterpret_cast<double*>(b + o_inj);
   d.trunk_jpat = reinterpret_cast<uint32_t*>(b + o_jp);
   d.trunk_jg3 = reinterpret_cast<uint8_t*>(b + o_jg3);
+  d.trunk_jlev = reinterpret_cast<uint8_t*>(b + o_jlv);
   d.fill_first = reinterpret_cast<int64_t*>(b + o_ff);
   d.fill_in = reinterpret_cast<int64_t*>(b + o_fi);
   d.fill_n = reinterpret_cast<int32_t*>(b + o_fn);
@@ -625,6 +627,7 @@ int upload_plan(gst_req* r, const gst::HostPlan& P) {
   if ((rc = put(d.chunk_end, P.chunk_end.data(), P.chunk_end.size() * 8))) return rc;
   if ((rc = put(d.trunk_jpat, P.trunk_jump_pattern.data(), P.trunk_jump_pattern.size() * 4))) return rc;
   if ((rc = put(d.trunk_jg3, P.trunk_jump_gate3.data(), P.trunk_jump_gate3.size()))) return rc;
+  if ((rc = put(d.trunk_jlev, P.trunk_jump_levels.data(), P.trunk_jump_levels.size()))) return rc;
   if ((rc = put(d.fill_first, P.fill_first.data(), nF * 8))) return rc;
   if ((rc = put(d.fill_in, P.fill_in.data(), nF * 8))) return rc;
   if ((rc = put(d.fill_n, P.fill_n.data(), nF * 4))) return rc;
@@ -993,6 +996,7 @@ void plan_setup(gst_req* r, const gst_gateset* th, int mode, const double* w, do
   a.req_nonpos = req_nonpos;
   a.trunk_jpat = d.trunk_jpat;
   a.trunk_jg3 = d.trunk_jg3;
+  a.trunk_jlev = d.trunk_jlev;
   a.jump_levels = P.jump_levels;
   a.item_blocks = item_blocks;
   a.n_fill = P.n_fill();

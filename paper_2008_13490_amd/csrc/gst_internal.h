@@ -112,7 +112,8 @@ struct PlanArgs {
   // none), whose product powers the trunk kernels build in LDS
   const uint32_t* trunk_jpat;
   const uint8_t* trunk_jg3;
-  int jump_levels;
+  const uint8_t* trunk_jlev;     // the jump levels each trunk builds
+  int jump_levels;               // the most any trunk builds (sizes the LDS)
   int item_blocks;               // item workgroups; the item launch adds the forward fill workgroups
   // fill tasks: states (forward) or adjoints (reverse) inside each jump
   int64_t n_fill;

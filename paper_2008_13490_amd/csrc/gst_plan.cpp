@@ -304,21 +304,28 @@ bool build_plan(const int64_t* off, const uint8_t* gates, int64_t S, int K, cons
   P.seg_ptr.assign(nT + 1, 0);
   const int B = opt.jump;
   const bool jump_on = B >= 2 && B <= 16 && (B & (B - 1)) == 0;
-  int lb = 0;
-  while (jump_on && (1 << lb) < B) ++lb;
-  P.jump_levels = jump_on ? lb + 1 : 0;
+  // the longest jump of a pattern of period per: B repetitions, or more (a
+  // power of two) while it spans at most jump_span steps; lb_of = its log2
+  auto lb_of = [&](int per) {
+    int lb = 0;
+    while ((1 << (lb + 1)) <= B || (opt.jump_span > 0 && (2 << lb) * per <= opt.jump_span)) ++lb;
+    return lb;
+  };
+  P.jump_levels = 0;
   P.trunk_jump_pattern.assign(nT, 0);
   P.trunk_jump_gate3.assign(nT, 0);
+  P.trunk_jump_levels.assign(nT, 0);
   struct Run {
     int64_t j, count;
     int per;
     uint32_t pat;
     uint8_t g3;
   };
-  // chain mat-vecs of a run applied with jumps: count / B jumps by the B-th
-  // power, then one jump per set bit of the remainder (a one-gate pattern
-  // takes its last single repetition as an ordinary step)
+  // chain mat-vecs of a run applied with jumps: count / 2^lb jumps by the
+  // longest power, then one jump per set bit of the remainder (a one-gate
+  // pattern takes its last single repetition as an ordinary step)
   auto chain_of = [&](const Run& u) {
+    const int lb = lb_of(u.per);
     int64_t c = u.count >> lb;
     for (int e = 0; e < lb; ++e) c += (u.count >> e) & 1;
     return c;
@@ -369,6 +376,12 @@ bool build_plan(const int64_t* off, const uint8_t* gates, int64_t S, int K, cons
     }
     P.trunk_jump_pattern[r] = jp;
     P.trunk_jump_gate3[r] = jg3;
+    const int lb = jp ? lb_of((int)(jp & 0xffu)) : 0;
+    const int64_t Bt = (int64_t)1 << lb;
+    if (jp) {
+      P.trunk_jump_levels[r] = (uint8_t)(lb + 1);
+      P.jump_levels = std::max(P.jump_levels, lb + 1);
+    }
     auto emit_plain = [&](int64_t start, int64_t count, uint32_t pat, uint8_t g3, int64_t inj) {
       P.seg_start.push_back((int32_t)start);
       P.seg_count.push_back((int32_t)count);
@@ -400,7 +413,7 @@ bool build_plan(const int64_t* off, const uint8_t* gates, int64_t S, int K, cons
           P.fill_gate3.push_back(u.g3);
         }
       };
-      const int64_t q_full = u.count >> lb, rem = u.count & (B - 1);
+      const int64_t q_full = u.count >> lb, rem = u.count & (Bt - 1);
       if (q_full > 0) emit_jump(lb, q_full);
       for (int e = lb - 1; e >= 0; --e) {
         if (!((rem >> e) & 1)) continue;

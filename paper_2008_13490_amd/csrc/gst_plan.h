@@ -75,9 +75,10 @@ struct HostPlan {
   // stores only the state after each jump; the states inside a jump are
   // written by independent fill tasks that start from the stored state
   // before it.
-  int jump_levels = 0;                   // e = 0 .. jump_levels - 1
+  int jump_levels = 0;                   // e = 0 .. jump_levels - 1 (the most any trunk uses)
   std::vector<uint32_t> trunk_jump_pattern;  // [n_trunks] period and gates as in seg_pattern, 0 = no jumps
   std::vector<uint8_t> trunk_jump_gate3;     // fourth gate of the pattern
+  std::vector<uint8_t> trunk_jump_levels;    // the trunk's levels (its longest jump: 2^(levels-1) repetitions)
   std::vector<int64_t> fill_first;       // [n_fill] trunk-arena index of the task's first step
   std::vector<int64_t> fill_in;          // state row (0 = rho, 1 + j = after trunk step j) before that step
   std::vector<int32_t> fill_n;           // steps covered by the jump (n - 1 states are filled)
@@ -119,6 +120,7 @@ struct PlanOptions {
   int64_t max_item_steps = 1LL << 24;   // bound on stored item-step states (memory)
   int chunk = 128;                      // gradient GEMM records per chunk (the kernel takes at most 128)
   int jump = 8;                         // repetitions per germ-power jump (power of two, <= 16); 0 = none
+  int jump_span = 16;                   // ... or more, a power of two, while a jump spans at most this many steps
   int jump_min_save = 3;                // jump a run only if it shortens the chain by this many steps
   int rep_anchor_min = 4;               // inside a periodic run of a trunk's word with at least this many
                                         // repetitions, items start only at repetition boundaries (0 = anywhere)

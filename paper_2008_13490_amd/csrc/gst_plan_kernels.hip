@@ -149,7 +149,7 @@ __device__ __forceinline__ uint32_t lane_u32(uint32_t v, int x) {
 struct TrunkMeta {
   int64_t beg, end, anchor, o0, o1;
   uint32_t jp;
-  int jg3;
+  int jg3, jlev;
   int32_t src;
 };
 __device__ __forceinline__ TrunkMeta trunk_meta(const PlanArgs& a, int64_t t) {
@@ -161,6 +161,7 @@ __device__ __forceinline__ TrunkMeta trunk_meta(const PlanArgs& a, int64_t t) {
   m.o1 = a.op_ptr[t + 1];
   m.jp = a.trunk_jpat[t];
   m.jg3 = (int)((reinterpret_cast<const uint32_t*>(a.trunk_jg3)[t >> 2] >> (8 * (t & 3))) & 0xffu);
+  m.jlev = (int)((reinterpret_cast<const uint32_t*>(a.trunk_jlev)[t >> 2] >> (8 * (t & 3))) & 0xffu);
   m.src = a.trunk_src[t];
   return m;
 }
@@ -208,7 +209,7 @@ __device__ __forceinline__ void trunk_fwd_body(const PlanArgs& a, int64_t t_begi
     }
     const int64_t o0 = m.o0, o1 = m.o1;
     const uint32_t jp = (uint32_t)__builtin_amdgcn_readfirstlane((int)m.jp);
-    if (jp != 0u) build_jumps(js, s.Gs, jp, (uint8_t)m.jg3, a.jump_levels, false, lane);
+    if (jp != 0u) build_jumps(js, s.Gs, jp, (uint8_t)m.jg3, m.jlev, false, lane);
     double f = m.anchor >= 0 ? (i < D ? fa : 0.0) : s.rho[i];
     double* out = a.FA + (1 + m.beg) * D + i;  // state after trunk step j: out[j*D]
     int64_t pos = 0;                           // steps done
@@ -478,7 +479,7 @@ __device__ __forceinline__ void trunk_bwd_body(const PlanArgs& a, int64_t t_begi
     bool use = false;
     if (oe > o0) inj_load(ob, oe, sl, v, use);
     const uint32_t jp = (uint32_t)__builtin_amdgcn_readfirstlane((int)m.jp);
-    if (jp != 0u) build_jumps(js, s.GTs, jp, (uint8_t)m.jg3, a.jump_levels, true, lane);
+    if (jp != 0u) build_jumps(js, s.GTs, jp, (uint8_t)m.jg3, m.jlev, true, lane);
     double* ba = a.BA + m.beg * D + i;  // adjoint after trunk step j: ba[j*D]
     int64_t pos = m.end - m.beg;
     double b = 0.0;

@@ -11,7 +11,11 @@ int g_jump_min_save = gst::PlanOptions().jump_min_save;
 int g_rep_anchor_min = gst::PlanOptions().rep_anchor_min;
 int g_anchor_min_share = gst::PlanOptions().anchor_min_share;
 int g_anchor_max_back = gst::PlanOptions().anchor_max_back;
+int g_jump_span = gst::PlanOptions().jump_span;
 }
+
+// Longest span (steps) of a germ-power jump in the following plan_build calls.
+extern "C" void plan_set_span(int span) { g_jump_span = span; }
 
 // Start-state options of the following plan_build calls (items inside long
 // periodic runs start at repetition boundaries that enough items share).
@@ -38,6 +42,7 @@ extern "C" int plan_build(const int64_t* off, const uint8_t* gates, int64_t S, i
   opt.rep_anchor_min = g_rep_anchor_min;
   opt.anchor_min_share = g_anchor_min_share;
   opt.anchor_max_back = g_anchor_max_back;
+  opt.jump_span = g_jump_span;
   const bool used = gst::build_plan(off, gates, S, K, opt, &g_plan);
   const gst::HostPlan& P = g_plan;
   sizes[0] = used;
