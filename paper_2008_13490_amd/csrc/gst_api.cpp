@@ -225,6 +225,8 @@ struct DevicePlan {
 
   int64_t* inj_ptr = nullptr;
   int32_t* item_src = nullptr;
+  uint8_t* item_kv = nullptr;
+  int32_t* item_cnt = nullptr;   // counts in item order (null without counts)
   int32_t* trunk_src = nullptr;
   int64_t* op_ptr = nullptr;
   uint32_t* op_desc = nullptr;
@@ -555,7 +557,7 @@ gst::LeafLaunch plain_launch(int D, const gst_gateset* gs, const gst_seqlist* sl
   return a;
 }
 
-int upload_plan(gst_req* r, const gst::HostPlan& P) {
+int upload_plan(gst_req* r, const gst::HostPlan& P, const int32_t* counts_host) {
   DevicePlan& d = r->plan;
   d.host = P;
   const int D = r->D;
@@ -567,7 +569,8 @@ int upload_plan(gst_req* r, const gst::HostPlan& P) {
   const size_t o_op = c.take<int64_t>(nT + 1), o_od = c.take<uint32_t>(nOp + 1), o_os = c.take<int32_t>(nOp + 1);
   const size_t o_items = c.take<int64_t>(4 * nI), o_tp = c.take<int64_t>(nT + 1), o_ta = c.take<int64_t>(nT + 1),
                o_ip = c.take<int64_t>(nJ + 1),
-               o_isrc = c.take<int32_t>(nI + 1), o_tsrc = c.take<int32_t>(nT + 1), o_isp = c.take<int64_t>(nI + 1),
+               o_isrc = c.take<int32_t>(nI + 1), o_ikv = c.take<uint8_t>((size_t)nI * 16 + 1),
+               o_icnt = c.take<int32_t>((size_t)nI * r->M + 1), o_tsrc = c.take<int32_t>(nT + 1), o_isp = c.take<int64_t>(nI + 1),
                o_rb = c.take<int64_t>(nR + 1), o_rf = c.take<int64_t>(nR + 1), o_cg = c.take<int64_t>(nC + 1),
                o_cb = c.take<int64_t>(nC + 1), o_ce = c.take<int64_t>(nC + 1),
                o_fa = c.take<double>((size_t)(1 + nTS + nIS) * D), o_ba = c.take<double>((size_t)(nTS + nIS + 1) * D),
@@ -587,6 +590,8 @@ int upload_plan(gst_req* r, const gst::HostPlan& P) {
   d.trunk_anchor = reinterpret_cast<int64_t*>(b + o_ta);
   d.inj_ptr = reinterpret_cast<int64_t*>(b + o_ip);
   d.item_src = reinterpret_cast<int32_t*>(b + o_isrc);
+  d.item_kv = reinterpret_cast<uint8_t*>(b + o_ikv);
+  d.item_cnt = counts_host ? reinterpret_cast<int32_t*>(b + o_icnt) : nullptr;
   d.trunk_src = reinterpret_cast<int32_t*>(b + o_tsrc);
   d.item_step_ptr = reinterpret_cast<int64_t*>(b + o_isp);
   d.rec_b = reinterpret_cast<int64_t*>(b + o_rb);
@@ -618,6 +623,13 @@ int upload_plan(gst_req* r, const gst::HostPlan& P) {
   if ((rc = put(d.trunk_anchor, P.trunk_anchor.data(), P.trunk_anchor.size() * 8))) return rc;
   if ((rc = put(d.inj_ptr, P.inj_ptr.data(), P.inj_ptr.size() * 8))) return rc;
   if ((rc = put(d.item_src, P.item_src.data(), (size_t)nI * 4))) return rc;
+  if ((rc = put(d.item_kv, P.item_kv.data(), P.item_kv.size()))) return rc;
+  if (counts_host) {
+    std::vector<int32_t> cnt((size_t)nI * r->M);
+    for (int64_t q = 0; q < nI; ++q)
+      for (int m = 0; m < r->M; ++m) cnt[(size_t)q * r->M + m] = counts_host[P.items[4 * q] * r->M + m];
+    if ((rc = put(d.item_cnt, cnt.data(), cnt.size() * 4))) return rc;
+  }
   if ((rc = put(d.trunk_src, P.trunk_src.data(), (size_t)nT * 4))) return rc;
   if ((rc = put(d.item_step_ptr, P.item_step_ptr.data(), P.item_step_ptr.size() * 8))) return rc;
   if ((rc = put(d.rec_b, P.rec_b.data(), P.rec_b.size() * 8))) return rc;
@@ -983,6 +995,8 @@ void plan_setup(gst_req* r, const gst_gateset* th, int mode, const double* w, do
   a.item_step_ptr = d.item_step_ptr;
   a.gates = r->gates;
   a.item_src = d.item_src;
+  a.item_kv = d.item_kv;
+  a.item_cnt = d.item_cnt;
   a.counts = r->counts;
   a.W = w;
   a.probs = probs;
@@ -1567,7 +1581,7 @@ int gst_req_create_host(gst_ctx* ctx, int n_qubits, int n_gates, int n_outcomes,
     gst::PlanOptions opt;
     opt.jump = ctx->plan_jump;
     if (gst::build_plan(sl->offsets, sl->gate_idx, S, n_gates, opt, &hp)) {
-      rc = upload_plan(r.get(), hp);
+      rc = upload_plan(r.get(), hp, counts_host);
       if (rc) return rc;
     }
   }

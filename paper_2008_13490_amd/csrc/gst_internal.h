@@ -94,6 +94,8 @@ struct PlanArgs {
   const int64_t* item_step_ptr;  // [n_items + 1]
   const uint8_t* gates;          // sequence gate indices (beg/end index into it)
   const int32_t* item_src;       // [n_items] source-arena row of the item's adjoint, -1 = rho
+  const uint8_t* item_kv;        // [n_items][16] the first 16 gate indices of each item's word (0 past its end)
+  const int32_t* item_cnt;       // [n_items][M] the counts in item order (requests with counts)
   const int32_t* counts;
   const double* W;
   double* probs;

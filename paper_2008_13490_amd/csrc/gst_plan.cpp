@@ -275,6 +275,10 @@ bool build_plan(const int64_t* off, const uint8_t* gates, int64_t S, int K, cons
   for (int64_t q = 0; q < S; ++q)
     for (int c = 0; c < 4; ++c) P.items[4 * q + c] = it[4 * iorder[q] + c];
   for (int64_t q = 0; q < S; ++q) P.item_max_len = std::max(P.item_max_len, P.items[4 * q + 2] - P.items[4 * q + 1]);
+  P.item_kv.assign((size_t)S * 16, 0);
+  for (int64_t q = 0; q < S; ++q)
+    for (int64_t x = P.items[4 * q + 1], c = 0; x < P.items[4 * q + 2] && c < 16; ++x, ++c)
+      P.item_kv[(size_t)q * 16 + c] = gates[x];
 
   // ---- 5. injection slots: stored locations that receive adjoints ----
   // sources: items anchored there and trunks (level >= 1) anchored there.

@@ -43,6 +43,7 @@ struct HostPlan {
   int64_t trunk_max_len = 0;
   // items: (seq, beg, end, anchor location), sorted by end - beg descending
   std::vector<int64_t> items;            // [n_items * 4]
+  std::vector<uint8_t> item_kv;          // [n_items * 16] the first 16 gate indices of each item's word, 0 past its end
   int64_t item_max_len = 0;
   // injection slots: state location and the items / trunks feeding it
   std::vector<int64_t> inj_loc;          // [n_inj]

@@ -260,6 +260,30 @@ __device__ __forceinline__ void item_body(const PlanArgs& a, int64_t blk, int64_
   const int K = a.K, M = a.M;
   const Lds s = carve(lds_raw, K);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, i = lane & 15, team = lane >> 4;
+  const int64_t n_chunks = (a.n_items + kItemChunk - 1) / kItemChunk;
+  // A chunk's item-indexed data (descriptor fields, counts, the first gates
+  // of each word) is loaded into registers with clamped indices, nothing
+  // waiting for it until it is stored to LDS: the first chunk's before the
+  // gate set is staged, each next chunk's while the current one runs.
+  int64_t dq = 0;
+  int32_t nq[2] = {0, 0};
+  uint32_t kq[2] = {0u, 0u};
+  auto load_q = [&](int64_t chunk) {
+    const int64_t q0 = chunk * kItemChunk, ql = a.n_items - 1;
+    if (tid < kItemChunk * IST_DESC) {
+      const int it = tid / IST_DESC, c = tid % IST_DESC;
+      const int64_t q = q0 + it < ql ? q0 + it : ql;
+      dq = c < 4 ? a.items[4 * q + c] : (c == 4 ? a.item_step_ptr[q] : (int64_t)a.item_src[q]);
+    }
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int x = tid + WAVES * 64 * u, it = x >> 4, c = x & 15;
+      const int64_t q = q0 + it < ql ? q0 + it : ql;
+      if (a.item_cnt) nq[u] = a.item_cnt[q * M + (c < M ? c : M - 1)];
+      kq[u] = a.item_kv[q * 16 + c];
+    }
+  };
+  if ((int)blk < a.item_blocks && blk < n_chunks) load_q(blk);
   stage_gateset<D>(s, a.G, a.E, a.rho, K, M);
   if ((int)blk >= a.item_blocks) {
     run_fills<D, false>(a, s, blk - a.item_blocks, nblk - a.item_blocks);
@@ -277,37 +301,39 @@ __device__ __forceinline__ void item_body(const PlanArgs& a, int64_t blk, int64_
   // The items are cut into chunks of kItemChunk (two rounds of one item per
   // team), each with its own head row, whatever the number of workgroups:
   // workgroup blk takes chunks blk, blk + item_blocks, ...  A chunk's item
-  // data is staged in LDS by the whole workgroup first (the descriptors, then
-  // what they point to), so that an item's chain starts from LDS instead of
-  // from two dependent global round trips of its own.
+  // data is staged in LDS by the whole workgroup first (the item-indexed
+  // data, then the start states its descriptors point to), so that an item's
+  // chain starts from LDS instead of from dependent global round trips of its
+  // own.
   static_assert(kItemChunk == 2 * WAVES * TPW, "an item chunk is two rounds of the workgroup's teams");
-  const int64_t n_chunks = (a.n_items + kItemChunk - 1) / kItemChunk;
   int64_t* st_desc = reinterpret_cast<int64_t*>(red + (size_t)WAVES * TPW * hw);  // [kItemChunk][IST_DESC]
   double* st_f = reinterpret_cast<double*>(st_desc + kItemChunk * IST_DESC);      // [kItemChunk][16]
   int32_t* st_n = reinterpret_cast<int32_t*>(st_f + kItemChunk * 16);             // [kItemChunk][16]
   int32_t* st_kv = st_n + kItemChunk * 16;                                        // [kItemChunk][16]
   for (int64_t chunk = blk; chunk < n_chunks; chunk += a.item_blocks) {
     const int64_t q0 = chunk * kItemChunk;
-    // descriptors (the previous chunk's staged data has been read: write_head
-    // ends with a barrier, and so does the staging below)
+    // the item-indexed data (the previous chunk's staged data has been read:
+    // write_head ends with a barrier, and so does the staging below)
     if (tid < kItemChunk * IST_DESC) {
       const int it = tid / IST_DESC, c = tid % IST_DESC;
-      const int64_t q = q0 + it;
-      int64_t v = (c == 3 || c == 5) ? -1 : 0;
-      if (q < a.n_items) v = c < 4 ? a.items[4 * q + c] : (c == 4 ? a.item_step_ptr[q] : (int64_t)a.item_src[q]);
-      st_desc[tid] = v;
+      st_desc[tid] = q0 + it < a.n_items ? dq : ((c == 3 || c == 5) ? -1 : 0);
+    }
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int x = tid + WAVES * 64 * u, it = x >> 4, c = x & 15;
+      const bool has_it = q0 + it < a.n_items;
+      st_n[x] = (a.mode == MODE_LOGLIK && a.item_cnt && has_it && c < M) ? nq[u] : 0;
+      st_kv[x] = has_it ? (int)kq[u] : 0;
     }
     lds_sync();
-    // start states, counts, first gate indices: item `it`, component `c`
-    for (int x = tid; x < kItemChunk * 16; x += WAVES * 64) {
-      const int it = x >> 4, c = x & 15;
-      const bool has_it = q0 + it < a.n_items;
-      const int64_t seq = st_desc[it * IST_DESC + 0], beg = st_desc[it * IST_DESC + 1];
-      const int64_t end = st_desc[it * IST_DESC + 2], anc = st_desc[it * IST_DESC + 3];
+    // start states: item `it`, component `c`
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int x = tid + WAVES * 64 * u, it = x >> 4, c = x & 15;
+      const int64_t anc = st_desc[it * IST_DESC + 3];
       st_f[x] = anc >= 0 ? load_state(a.FA, 1 + anc, D, c) : s.rho[c];
-      st_n[x] = (a.mode == MODE_LOGLIK && has_it && c < M) ? a.counts[seq * M + c] : 0;
-      st_kv[x] = c < end - beg ? (int)a.gates[beg + c] : 0;
     }
+    if (chunk + a.item_blocks < n_chunks) load_q(chunk + a.item_blocks);
     lds_sync();
     for (int r = 0; r < 2; ++r) {
     const int it = r * (WAVES * TPW) + wave * TPW + team;
