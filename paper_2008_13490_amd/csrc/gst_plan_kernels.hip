@@ -248,8 +248,33 @@ __global__ __launch_bounds__(64) void trunk_fwd_kernel(const PlanArgs a) {
 // ---------------------------------------------------------------------------
 // items: one sequence per team, from its anchor state
 // ---------------------------------------------------------------------------
+// A team's fill task: its descriptors (loaded first, with a clamped index)
+// and the stored value it starts from (loaded once they are in).
+struct FillTask {
+  int64_t first, in;
+  int n, g3;
+  uint32_t pat;
+  double v;
+};
+__device__ __forceinline__ FillTask fill_task_desc(const PlanArgs& a, int64_t grp, int team) {
+  FillTask t;
+  const int64_t q = grp * TPW + team, qc = q < a.n_fill ? q : a.n_fill - 1;
+  t.first = a.fill_first[qc];
+  t.in = a.fill_in[qc];
+  t.n = a.fill_n[qc];
+  t.pat = a.fill_pattern[qc];
+  t.g3 = a.fill_gate3[qc];
+  t.v = 0.0;
+  return t;
+}
 template <int D, bool REV>
-__device__ void run_fills(const PlanArgs& a, const Lds& s, int64_t blk, int64_t n_blk);
+__device__ __forceinline__ void fill_task_start(const PlanArgs& a, FillTask& t, int i) {
+  const int c = i < D ? i : 0;
+  t.v = REV ? a.BA[(t.first + t.n - 1) * D + c] : a.FA[t.in * D + c];
+}
+
+template <int D, bool REV>
+__device__ void run_fills(const PlanArgs& a, const Lds& s, int64_t blk, int64_t n_blk, FillTask t0);
 
 // Workgroups from a.item_blocks on run the forward fill tasks instead (they
 // need only the trunk states, like the items).
@@ -283,10 +308,12 @@ __device__ __forceinline__ void item_body(const PlanArgs& a, int64_t blk, int64_
       kq[u] = a.item_kv[q * 16 + c];
     }
   };
+  FillTask t0{};
   if ((int)blk < a.item_blocks && blk < n_chunks) load_q(blk);
+  if ((int)blk >= a.item_blocks && a.n_fill > 0) t0 = fill_task_desc(a, (blk - a.item_blocks) * WAVES + wave, team);
   stage_gateset<D>(s, a.G, a.E, a.rho, K, M);
   if ((int)blk >= a.item_blocks) {
-    run_fills<D, false>(a, s, blk - a.item_blocks, nblk - a.item_blocks);
+    run_fills<D, false>(a, s, blk - a.item_blocks, nblk - a.item_blocks, t0);
     return;
   }
   const bool grad = a.want_grad != 0;
@@ -567,25 +594,23 @@ __global__ __launch_bounds__(64) void trunk_bwd_kernel(const PlanArgs a) {
 // task per 16-lane team, from the stored value at the jump's start (forward)
 // or end (reverse).  Step j of a task applies gate pattern[j % period].
 // ---------------------------------------------------------------------------
+// Workgroup blk of n_blk runs groups blk * WAVES + wave, + n_blk * WAVES, ...;
+// `t0` is the first group's task, its descriptors already loaded.
 template <int D, bool REV>
-__device__ void run_fills(const PlanArgs& a, const Lds& s, int64_t blk, int64_t n_blk) {
+__device__ void run_fills(const PlanArgs& a, const Lds& s, int64_t blk, int64_t n_blk, FillTask t0) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, i = lane & 15, team = lane >> 4;
   const double* gl = (REV ? s.GTs : s.Gs) + i * ROW;
   const int64_t n_groups = (a.n_fill + TPW - 1) / TPW;
+  FillTask t = t0;
   for (int64_t grp = blk * WAVES + wave; grp < n_groups; grp += n_blk * WAVES) {
-    const int64_t q = grp * TPW + team;
-    const bool has = q < a.n_fill;
-    int64_t first = 0, in = 0;
-    int n = 1;
-    uint32_t pat = 1u;
-    int g3 = 0;
-    if (has) {
-      first = a.fill_first[q];
-      in = a.fill_in[q];
-      n = a.fill_n[q];
-      pat = a.fill_pattern[q];
-      g3 = a.fill_gate3[q];
-    }
+    if (grp != blk * WAVES + wave) t = fill_task_desc(a, grp, team);
+    fill_task_start<D, REV>(a, t, i);
+    const bool has = grp * TPW + team < a.n_fill;
+    const int64_t first = t.first, in = t.in;
+    const int n = has ? t.n : 1;
+    const uint32_t pat = has ? t.pat : (t.pat & 0xffu);
+    const int g3 = t.g3;
+    (void)in;
     // the four tasks of a wave share their period (the plan groups them):
     // the pattern rows stay in registers and the phase is uniform
     const int per = __builtin_amdgcn_readfirstlane((int)(pat & 0xffu));
@@ -605,7 +630,7 @@ __device__ void run_fills(const PlanArgs& a, const Lds& s, int64_t blk, int64_t 
     if (!REV) {
       // states after steps 0 .. n-2 (the one after step n-1 is the jump's);
       // step j applies pattern gate j % per
-      double f = load_state(a.FA, in, D, i);
+      double f = i < D ? t.v : 0.0;
       double* o = a.FA + (1 + first) * D + i;
       int ph = 0;
       for (int j = 0; j + 1 < nw; ++j) {
@@ -615,7 +640,7 @@ __device__ void run_fills(const PlanArgs& a, const Lds& s, int64_t blk, int64_t 
       }
     } else {
       // adjoints after steps n-2 .. 0, from the one after step n-1
-      double b = st ? a.BA[(first + n - 1) * D + i] : 0.0;
+      double b = st ? t.v : 0.0;
       double* o = a.BA + first * D + i;
       int ph = (nw - 1) % per;
       for (int j = nw - 1; j >= 1; --j) {
@@ -635,8 +660,10 @@ template <int D>
 __global__ __launch_bounds__(256) void fill_rev_kernel(const PlanArgs a) {
   extern __shared__ double lds_raw[];
   const Lds s = carve(lds_raw, a.K);
+  // the first group's descriptors load while the gate set is staged
+  const FillTask t0 = fill_task_desc(a, (int64_t)blockIdx.x * WAVES + (threadIdx.x >> 6), (threadIdx.x & 63) >> 4);
   stage_gateset<D, 256, STAGE_GT>(s, a.G, a.E, a.rho, a.K, a.M);
-  run_fills<D, true>(a, s, blockIdx.x, gridDim.x);
+  run_fills<D, true>(a, s, blockIdx.x, gridDim.x, t0);
 }
 
 // One wave per injection slot: its sources are consecutive rows of the
@@ -860,8 +887,9 @@ __global__ __launch_bounds__(256) void fill_rev_batch(const PlanBatch b) {
   if (!a.want_grad || a.n_fill <= 0 || (int64_t)blockIdx.x >= a.fill_blocks) return;
   extern __shared__ double lds_raw[];
   const Lds s = carve(lds_raw, a.K);
+  const FillTask t0 = fill_task_desc(a, (int64_t)blockIdx.x * WAVES + (threadIdx.x >> 6), (threadIdx.x & 63) >> 4);
   stage_gateset<D, 256, STAGE_GT>(s, a.G, a.E, a.rho, a.K, a.M);
-  run_fills<D, true>(a, s, blockIdx.x, a.fill_blocks);
+  run_fills<D, true>(a, s, blockIdx.x, a.fill_blocks, t0);
 }
 
 template <int D>
