@@ -245,6 +245,7 @@ struct DevicePlan {
   uint32_t* trunk_jpat = nullptr;
   uint8_t* trunk_jg3 = nullptr;
   uint8_t* trunk_jlev = nullptr;
+  double* jump_t = nullptr;      // [n_trunks][jump_levels][256]: the jump matrices, transposed
   int64_t* fill_first = nullptr;
   int64_t* fill_in = nullptr;
   int32_t* fill_n = nullptr;
@@ -576,7 +577,8 @@ int upload_plan(gst_req* r, const gst::HostPlan& P, const int32_t* counts_host) 
                o_fa = c.take<double>((size_t)(1 + nTS + nIS) * D), o_ba = c.take<double>((size_t)(nTS + nIS + 1) * D),
                o_src = c.take<double>((size_t)(P.n_src_rows() + 1) * D), o_inj = c.take<double>((size_t)(nJ + 1) * D);
   const size_t nF = P.fill_first.size();
-  const size_t o_jp = c.take<uint32_t>(nT + 1), o_jg3 = c.take<uint8_t>(nT + 1), o_jlv = c.take<uint8_t>(nT + 1), o_ff = c.take<int64_t>(nF + 1),
+  const size_t o_jp = c.take<uint32_t>(nT + 1), o_jg3 = c.take<uint8_t>(nT + 1), o_jlv = c.take<uint8_t>(nT + 1),
+               o_jt = c.take<double>((size_t)nT * std::max(P.jump_levels, 1) * 256 + 1), o_ff = c.take<int64_t>(nF + 1),
                o_fi = c.take<int64_t>(nF + 1), o_fn = c.take<int32_t>(nF + 1), o_fp = c.take<uint32_t>(nF + 1),
                o_fg3 = c.take<uint8_t>(nF + 1);
   int rc = d.buf.reserve(c.off + 256, r->ctx->stream);
@@ -606,6 +608,7 @@ int upload_plan(gst_req* r, const gst::HostPlan& P, const int32_t* counts_host) 
   d.trunk_jpat = reinterpret_cast<uint32_t*>(b + o_jp);
   d.trunk_jg3 = reinterpret_cast<uint8_t*>(b + o_jg3);
   d.trunk_jlev = reinterpret_cast<uint8_t*>(b + o_jlv);
+  d.jump_t = reinterpret_cast<double*>(b + o_jt);
   d.fill_first = reinterpret_cast<int64_t*>(b + o_ff);
   d.fill_in = reinterpret_cast<int64_t*>(b + o_fi);
   d.fill_n = reinterpret_cast<int32_t*>(b + o_fn);
@@ -1011,6 +1014,7 @@ void plan_setup(gst_req* r, const gst_gateset* th, int mode, const double* w, do
   a.trunk_jpat = d.trunk_jpat;
   a.trunk_jg3 = d.trunk_jg3;
   a.trunk_jlev = d.trunk_jlev;
+  a.jump_t = d.jump_t;
   a.jump_levels = P.jump_levels;
   a.item_blocks = item_blocks;
   a.n_fill = P.n_fill();

@@ -116,6 +116,8 @@ struct PlanArgs {
   const uint8_t* trunk_jg3;
   const uint8_t* trunk_jlev;     // the jump levels each trunk builds
   int jump_levels;               // the most any trunk builds (sizes the LDS)
+  double* jump_t;                // [n_trunks][jump_levels][16][16]: the forward sweep's jump
+                                 // matrices, transposed, for the reverse sweep
   int item_blocks;               // item workgroups; the item launch adds the forward fill workgroups
   // fill tasks: states (forward) or adjoints (reverse) inside each jump
   int64_t n_fill;

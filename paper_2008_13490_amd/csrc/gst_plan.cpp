@@ -312,8 +312,8 @@ bool build_plan(const int64_t* off, const uint8_t* gates, int64_t S, int K, cons
   // power of two) while it spans at most jump_span steps; lb_of = its log2
   auto lb_of = [&](int per) {
     int lb = 0;
-    while ((1 << (lb + 1)) <= B || (opt.jump_span > 0 && (2 << lb) * per <= opt.jump_span)) ++lb;
-    return lb;
+    while (lb < 4 && ((1 << (lb + 1)) <= B || (opt.jump_span > 0 && (2 << lb) * per <= opt.jump_span))) ++lb;
+    return lb;  // at most 4: five levels, which the reverse trunk kernel holds in registers
   };
   P.jump_levels = 0;
   P.trunk_jump_pattern.assign(nT, 0);

@@ -209,7 +209,18 @@ __device__ __forceinline__ void trunk_fwd_body(const PlanArgs& a, int64_t t_begi
     }
     const int64_t o0 = m.o0, o1 = m.o1;
     const uint32_t jp = (uint32_t)__builtin_amdgcn_readfirstlane((int)m.jp);
-    if (jp != 0u) build_jumps(js, s.Gs, jp, (uint8_t)m.jg3, m.jlev, false, lane);
+    if (jp != 0u) {
+      build_jumps(js, s.Gs, jp, (uint8_t)m.jg3, m.jlev, false, lane);
+      // the transposes for the reverse sweep (element (r, c) of slot e is
+      // element (c, r) of the forward matrix); lane (i, q) writes rows 4v + q
+      double* jt = a.jump_t + (size_t)t * a.jump_levels * 256;
+      for (int e = 0; e < m.jlev; ++e)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int r = 4 * v + (lane >> 4);
+          jt[e * 256 + r * 16 + i] = js[e * GATE_STRIDE + i * ROW + r];
+        }
+    }
     double f = m.anchor >= 0 ? (i < D ? fa : 0.0) : s.rho[i];
     double* out = a.FA + (1 + m.beg) * D + i;  // state after trunk step j: out[j*D]
     int64_t pos = 0;                           // steps done
@@ -502,9 +513,20 @@ __device__ __forceinline__ void trunk_bwd_body(const PlanArgs& a, int64_t t_begi
       sl1 = slots(batch_ob(ob), ob);
     }
   };
+  // the forward sweep's transposed jump matrices of the trunk (at most five
+  // levels), lane (i, q) holding rows 4v + q
+  double jtv[5][4];
+  auto load_jt = [&](const TrunkMeta& mm, int64_t tt) {
+    const double* jt = a.jump_t + (size_t)tt * a.jump_levels * 256;
+#pragma unroll
+    for (int e = 0; e < 5; ++e)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) jtv[e][v] = jt[(e < mm.jlev ? e : 0) * 256 + (4 * v + (lane >> 4)) * 16 + i];
+  };
   if (t < t_end) {
     m = trunk_meta(a, t);
     first_ops();
+    if (m.jp != 0u) load_jt(m, t);
   }
   stage_gateset<D, 64, STAGE_GT>(s, a.G, a.E, a.rho, K, a.M);
   double* inj_st = lds_raw + trunk_inj_doubles(K);
@@ -532,7 +554,13 @@ __device__ __forceinline__ void trunk_bwd_body(const PlanArgs& a, int64_t t_begi
     bool use = false;
     if (oe > o0) inj_load(ob, oe, sl, v, use);
     const uint32_t jp = (uint32_t)__builtin_amdgcn_readfirstlane((int)m.jp);
-    if (jp != 0u) build_jumps(js, s.GTs, jp, (uint8_t)m.jg3, m.jlev, true, lane);
+    if (jp != 0u) {  // the forward sweep's jump matrices, transposed, into the slots
+      if (t != t_begin + blk) load_jt(m, t);
+      for (int e = 0; e < m.jlev; ++e)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) js[e * GATE_STRIDE + (4 * v + (lane >> 4)) * ROW + i] = jtv[e < 5 ? e : 0][v];
+      wave_sync();
+    }
     double* ba = a.BA + m.beg * D + i;  // adjoint after trunk step j: ba[j*D]
     int64_t pos = m.end - m.beg;
     double b = 0.0;
