@@ -410,9 +410,10 @@ struct LoadGates {
 };
 
 
-// Writes the tile-step's 16 states (columns c = 0..15) to 16 consecutive arena
-// rows, two doubles per lane and store, so that every wave store covers 1 KB of
-// consecutive memory.
+// Writes the tile-step's 16 adjoints (columns c = 0..15) to 16 consecutive
+// arena rows, two doubles per lane and store, so that every wave store covers
+// 1 KB of consecutive memory; non-temporal, since only the gradient GEMM reads
+// them (held in the L2 they would be written back at the kernel's end).
 
 __device__ __forceinline__ void store_tile_rows(const double* V, double* out, int tid) {
   auto* g = as_global(reinterpret_cast<d2*>(out));
@@ -423,7 +424,7 @@ __device__ __forceinline__ void store_tile_rows(const double* V, double* out, in
     d2 v;
     v.x = V[(j >> 2) * VST + (j & 3) * 16 + cc];
     v.y = V[((j + 1) >> 2) * VST + ((j + 1) & 3) * 16 + cc];
-    g[f >> 1] = v;
+    __builtin_nontemporal_store(v, &g[f >> 1]);
   }
 }
 

@@ -19,7 +19,11 @@
 //   grad_gemm_kernel  dG_k = sum over all steps with gate k of b f^T, as FP64
 //                     MFMA 16x16x4 rank-4 updates over the stored pairs.
 // The two chains (forward and reverse) are latency bound; the gradient GEMM
-// runs over all stored steps at once.
+// runs over all stored steps at once.  The records that only the gradient GEMM
+// reads (the items' states and adjoints, the states and adjoints filled inside
+// jumps) are stored non-temporally: written through to memory instead of
+// being held in the L2, whose write-back at the end of each kernel otherwise
+// lengthens the item and fill launches.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -396,7 +400,7 @@ __device__ __forceinline__ void item_body(const PlanArgs& a, int64_t blk, int64_
   if (t0 + R < Lw) {                                                     \
     const int x = t0 + R;                                                \
     const int k = bcast_i32<R>(kv);                                      \
-    if (grad && x < L && i < D) fa[(int64_t)x * D + i] = f;              \
+    if (grad && x < L && i < D) __builtin_nontemporal_store(f, &fa[(int64_t)x * D + i]);            \
     const double fn = dot16(f, load_row(s.Gs + k * GATE_STRIDE + i * ROW)); \
     f = x < L ? fn : f;                                                  \
   }
@@ -443,7 +447,7 @@ __device__ __forceinline__ void item_body(const PlanArgs& a, int64_t blk, int64_
   if (t0 + R < Lw) {                                                      \
     const int x = t0 + R;                                                 \
     const int k = bcast_i32<R>(kv);                                       \
-    if (x < L && i < D) ba[(int64_t)x * D + i] = b;                       \
+    if (x < L && i < D) __builtin_nontemporal_store(b, &ba[(int64_t)x * D + i]);                  \
     const double bn = dot16(b, load_row(s.GTs + k * GATE_STRIDE + i * ROW)); \
     b = x < L ? bn : b;                                                   \
   }
@@ -663,7 +667,7 @@ __device__ void run_fills(const PlanArgs& a, const Lds& s, int64_t blk, int64_t 
       int ph = 0;
       for (int j = 0; j + 1 < nw; ++j) {
         f = apply(f, ph);
-        if (st && j + 1 < n) o[(int64_t)j * D] = f;
+        if (st && j + 1 < n) __builtin_nontemporal_store(f, &o[(int64_t)j * D]);
         ph = ph + 1 == per ? 0 : ph + 1;
       }
     } else {
@@ -675,7 +679,7 @@ __device__ void run_fills(const PlanArgs& a, const Lds& s, int64_t blk, int64_t 
         const double nb = apply(b, ph);
         if (j < n) {
           b = nb;
-          if (st) o[(int64_t)(j - 1) * D] = b;
+          if (st) __builtin_nontemporal_store(b, &o[(int64_t)(j - 1) * D]);
         }
         ph = ph == 0 ? per - 1 : ph - 1;
       }
