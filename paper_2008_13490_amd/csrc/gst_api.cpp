@@ -272,7 +272,8 @@ struct DevicePlan64 {
           *col_chain = nullptr, *ev_ptr = nullptr, *ev_src = nullptr, *slot_row = nullptr, *slot_ptr = nullptr,
           *slot_seq = nullptr, *slot_pack = nullptr, *root_chains = nullptr, *ts_tile = nullptr, *chunk_beg = nullptr,
           *chunk_end = nullptr, *gate_chunk_ptr = nullptr;
-  int32_t *tile_len = nullptr, *ev_col = nullptr, *ts_step = nullptr, *slot_cnt = nullptr;
+  int32_t *tile_len = nullptr, *ts_step = nullptr, *slot_cnt = nullptr;
+  uint8_t* ev_cend = nullptr;
   uint8_t* words = nullptr;
   double *FA = nullptr, *BA = nullptr, *INJ = nullptr, *GA = nullptr, *GAT = nullptr, *slab = nullptr,
          *part = nullptr, *chunk_slab = nullptr, *root_vec = nullptr;
@@ -666,6 +667,9 @@ int upload_plan64(gst_req* r, gst::Plan64& P, const int32_t* counts_host) {
   const int M = r->M, K = r->K;
   const int64_t T = P.n_tiles(), TS = P.tile_steps(), NE = (int64_t)P.ev_col.size(), NR = (int64_t)P.ts_tile.size(),
                 NC = (int64_t)P.chunk_beg.size(), NRC = (int64_t)P.root_chains.size();
+  // the reverse kernel finds a column's events through the per-step table and
+  // stages the events' INJ rows as 32-bit indices
+  if ((int64_t)P.ev_cend.size() != TS * 16 || P.n_slots + P.n_chains >= INT32_MAX) return GST_EINVAL;
   d.readout_blocks = (int)std::min<int64_t>(std::max<int64_t>((P.n_slots + gst::READOUT64_WAVES - 1) /
                                                                   gst::READOUT64_WAVES, 1),
                                             (int64_t)gst::readout64_blocks_per_cu() * r->ctx->n_cu);
@@ -675,7 +679,7 @@ int upload_plan64(gst_req* r, gst::Plan64& P, const int32_t* counts_host) {
   const size_t o_r0 = c.take<int64_t>(T + 1), o_len = c.take<int32_t>(T + 1), o_w = c.take<int64_t>(T + 1),
                o_tev = c.take<int64_t>(T + 1), o_anc = c.take<int64_t>(T * 16 + 1), o_ch = c.take<int64_t>(T * 16 + 1),
                o_words = c.take<uint8_t>(P.words.size() + 1), o_evp = c.take<int64_t>(TS + 2),
-               o_evc = c.take<int32_t>(NE + 1), o_evs = c.take<int64_t>(NE + 1),
+               o_evc = c.take<uint8_t>(TS * 16 + 16), o_evs = c.take<int64_t>(NE + 1),
                o_sr = c.take<int64_t>(P.n_slots + 1), o_sp = c.take<int64_t>(P.n_slots + 2),
                o_sq = c.take<int64_t>(P.S + 1), o_spk = c.take<int64_t>(P.n_slots * 4 + 4),
                o_scn = c.take<int32_t>(P.n_slots * M + 1), o_rc = c.take<int64_t>(NRC + 1),
@@ -699,7 +703,7 @@ int upload_plan64(gst_req* r, gst::Plan64& P, const int32_t* counts_host) {
   d.col_chain = reinterpret_cast<int64_t*>(b + o_ch);
   d.words = reinterpret_cast<uint8_t*>(b + o_words);
   d.ev_ptr = reinterpret_cast<int64_t*>(b + o_evp);
-  d.ev_col = reinterpret_cast<int32_t*>(b + o_evc);
+  d.ev_cend = reinterpret_cast<uint8_t*>(b + o_evc);
   d.ev_src = reinterpret_cast<int64_t*>(b + o_evs);
   d.slot_row = reinterpret_cast<int64_t*>(b + o_sr);
   d.slot_ptr = reinterpret_cast<int64_t*>(b + o_sp);
@@ -733,7 +737,7 @@ int upload_plan64(gst_req* r, gst::Plan64& P, const int32_t* counts_host) {
   if ((rc = put(d.col_chain, P.col_chain.data(), T * 16 * 8))) return rc;
   if ((rc = put(d.words, P.words.data(), P.words.size()))) return rc;
   if ((rc = put(d.ev_ptr, P.ev_ptr.data(), P.ev_ptr.size() * 8))) return rc;
-  if ((rc = put(d.ev_col, P.ev_col.data(), NE * 4))) return rc;
+  if ((rc = put(d.ev_cend, P.ev_cend.data(), TS * 16))) return rc;
   if ((rc = put(d.ev_src, P.ev_src.data(), NE * 8))) return rc;
   if ((rc = put(d.slot_row, P.slot_row.data(), P.n_slots * 8))) return rc;
   if ((rc = put(d.slot_ptr, P.slot_ptr.data(), P.slot_ptr.size() * 8))) return rc;
@@ -809,7 +813,7 @@ int run_plan64(gst_req* r, const gst_gateset* th, int mode, const double* w, dou
   a.col_chain = d.col_chain;
   a.words = d.words;
   a.ev_ptr = d.ev_ptr;
-  a.ev_col = d.ev_col;
+  a.ev_cend = d.ev_cend;
   a.ev_src = d.ev_src;
   a.FA = d.FA;
   a.BA = d.BA;

@@ -299,8 +299,8 @@ struct Plan64Launch {
   const int64_t* col_chain;  // [n_tiles][16]
   const uint8_t* words;
   const int64_t* ev_ptr;
-  const int32_t* ev_col;
-  const int64_t* ev_src;
+  const uint8_t* ev_cend;    // [tile-steps][16]: byte c < 15 the step's events of columns <= c, byte 15 the most of one column
+  const int64_t* ev_src;     // < 2^31
   double* FA;                // [n_rows][64], row 0 = rho
   double* BA;                // [n_rows][64]
   double* INJ;               // [n_slots + n_chains][64]

@@ -347,6 +347,7 @@ __device__ __forceinline__ void load_ops(double (&dst)[16], const double* base, 
 constexpr int CH_STEPS = 256;   // steps per staged chunk
 constexpr int CH_EVENTS = 1024; // events per staged chunk (a node has at most EV_NODE)
 constexpr int EV_NODE = kMaxNodeEvents;  // events of one node at most: its seed and a chain per child
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));  // a step's row of the column table
 
 // A tile-step's 16 states in LDS: element (row 4k + r4, column c) at
 // k * VST + 16 r4 + c, which is where lane 16 r4 + c of an MFMA reads its B
@@ -470,54 +471,73 @@ __global__ __launch_bounds__(256) void plan64_fwd_kernel(const Plan64Launch a) {
 }
 
 // Rows 4(4w + v) + r4 of the INJ rows that events of one node add to column c:
-// up to EV_NODE rows, loaded into fixed registers (absent ones stay zero) and
-// added later in the events' order.
+// up to EV_NODE rows in fixed registers, added later in the events' order.
+// The node is step x of the staged chunk: its events are Ev[Es[x] ..
+// Es[x + 1]), ascending by column, and the step's row of the column table says
+// where column c's lie, so no lane scans the others'.  The loads run over the
+// most events of one column at this step (a uniform count); a lane with fewer
+// loads rows of the step's other events, which `n` masks out where they are
+// added.
 struct NodeAdds {
   double r[EV_NODE][4];
+  int n;
 };
 
-__device__ __forceinline__ void load_node_adds(NodeAdds& q, const int64_t* Ev, int j0, int j1, int c, int w, int r4,
-                                               const double* inj) {
+__device__ __forceinline__ void load_node_adds(NodeAdds& q, const int32_t* Es, const int32_t* Ev, const u32x4* Cc,
+                                               int x, int c, int w, int r4, const double* inj) {
   const auto* g = as_global(inj);
+  const int jb = uniform(Es[x]), tot = uniform(Es[x + 1]) - jb;
+  const auto* row = reinterpret_cast<const uint8_t*>(Cc + x);
+  const int most = uniform((int)row[15]);
+  const int lo = c > 0 ? (int)row[c - 1] : 0, hi = c < 15 ? (int)row[c] : tot;
+  q.n = hi - lo;
+  int src[EV_NODE];
+#pragma unroll
+  for (int e = 0; e < EV_NODE; ++e) {
+    const int j = jb + (lo + e < tot ? lo + e : tot - 1);
+    src[e] = Ev[j < 0 ? 0 : (j < CH_EVENTS ? j : CH_EVENTS - 1)];
+  }
 #pragma unroll
   for (int e = 0; e < EV_NODE; ++e)
 #pragma unroll
     for (int v = 0; v < 4; ++v) q.r[e][v] = 0.0;
-  int slot = 0;
-  for (int j = j0; j < j1; ++j) {
-    const int64_t ev = Ev[j];
-    if ((int)(ev & 15) != c) continue;
-    const int64_t src = ev >> 4;
 #pragma unroll
-    for (int e = 0; e < EV_NODE; ++e)
-      if (slot == e) {
+  for (int e = 0; e < EV_NODE; ++e)
+    if (e < most)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) q.r[e][v] = g[src * N64 + 4 * (4 * w + v) + r4];
-      }
-    ++slot;
-  }
+      for (int v = 0; v < 4; ++v) q.r[e][v] = g[(int64_t)src[e] * N64 + 4 * (4 * w + v) + r4];
+}
+
+// The node's events in their order (absent ones add zero).
+__device__ __forceinline__ double node_add(const NodeAdds& q, int v) {
+  double add = 0 < q.n ? q.r[0][v] : 0.0;
+#pragma unroll
+  for (int e = 1; e < EV_NODE; ++e) add += e < q.n ? q.r[e][v] : 0.0;
+  return add;
 }
 
 // Reverse sweep of a tile.  b_t, the adjoint of the node after step t, is
 // G_{t+1}^T b_{t+1} plus the node's seed and the adjoints of the chains anchored
 // there (in that order, summed first); it is stored, and G_t^T b_t with the
-// events of node t-1 added becomes b_{t-1}.  The events' rows are loaded at the
-// start of the step, the next gate's operands a step ahead.  At the end each
+// events of node t-1 added becomes b_{t-1}.  The events' rows are loaded while
+// the step's product runs, the next gate's operands a step ahead.  At the end each
 // chain delivers G_0^T b_0 to its anchor.
 template <class Gates>
 __global__ __launch_bounds__(256) void plan64_bwd_kernel(const Plan64Launch a) {
   __shared__ double Bs[2][16 * VST];
   __shared__ uint8_t Ws[CH_STEPS + 1];
   __shared__ int32_t Es[CH_STEPS + 2];
-  __shared__ int64_t Ev[CH_EVENTS];
+  __shared__ int32_t Ev[CH_EVENTS];
+  __shared__ u32x4 Cc[CH_STEPS + 1];
   const int tid = threadIdx.x, l = tid & 63, w = tid >> 6;
   const int c = l & 15, r4 = l >> 4;
   const int64_t tile = a.t_begin + blockIdx.x;
   const int len = uniform(a.tile_len[tile]);
   const auto* word = as_global(a.words + a.tile_word[tile]);
   const int64_t row0 = a.tile_row0[tile];
-  const auto* evp = as_global(a.ev_ptr + a.tile_ev[tile]);
-  const auto* evc = as_global(a.ev_col);
+  const int64_t tev = a.tile_ev[tile];
+  const auto* evp = as_global(a.ev_ptr + tev);
+  const auto* cend = as_global(reinterpret_cast<const u32x4*>(a.ev_cend) + tev);
   const auto* evs = as_global(a.ev_src);
   Gates gs;
   gs.init(a.GAT, a.K, w, l);
@@ -531,42 +551,32 @@ __global__ __launch_bounds__(256) void plan64_bwd_kernel(const Plan64Launch a) {
     const int s0 = t0 > 0 ? t0 - 1 : 0;
     const int64_t e0 = uniform64(evp[s0]);
     const int n = t1 - t0;
-    // Ws[x] = word[t0 - 1 + x] (x = 0 only if t0 > 0); Es[x] = events before step s0 + x
+    // Ws[x] = word[t0 - 1 + x] (x = 0 only if t0 > 0); Es[x] = events before
+    // step s0 + x; Cc[x] = the column table of step s0 + x
     for (int x = tid; x <= n; x += 256)
       if (x > 0 || t0 > 0) Ws[x] = word[t0 - 1 + x];
     for (int x = tid; x <= t1 - s0; x += 256) Es[x] = (int32_t)(evp[s0 + x] - e0);
-    for (int j = tid; j < (int)(e1 - e0); j += 256) Ev[j] = (evs[e0 + j] << 4) | (int64_t)evc[e0 + j];
+    for (int x = tid; x < t1 - s0; x += 256) Cc[x] = cend[s0 + x];
+    for (int j = tid; j < (int)(e1 - e0); j += 256) Ev[j] = (int32_t)evs[e0 + j];
     lds_barrier();
     if (t1 == len) {
       // b of the last node: its events alone
       NodeAdds q;
-      load_node_adds(q, Ev, Es[t1 - 1 - s0], Es[t1 - s0], c, w, r4, a.INJ);
+      load_node_adds(q, Es, Ev, Cc, t1 - 1 - s0, c, w, r4, a.INJ);
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        double add = q.r[0][v];
-#pragma unroll
-        for (int e = 1; e < EV_NODE; ++e) add += q.r[e][v];
-        Bs[0][(4 * w + v) * VST + l] = add;
-      }
+      for (int v = 0; v < 4; ++v) Bs[0][(4 * w + v) * VST + l] = node_add(q, v);
       gs.start(a.GAT, uniform(Ws[n]), w, l);
       lds_barrier();
     }
     for (int x = n - 1; x >= 0; --x) {
       const int t = t0 + x;
       NodeAdds q;  // events of node t - 1
-      if (t > 0) load_node_adds(q, Ev, Es[t - 1 - s0], Es[t - s0], c, w, r4, a.INJ);
+      q.n = 0;
+      if (t > 0) load_node_adds(q, Es, Ev, Cc, t - 1 - s0, c, w, r4, a.INJ);
       const d4 acc = gs.product(a.GAT, uniform(Ws[x + 1]), t > 0 ? uniform(Ws[x]) : -1, Bs[cur], w, l);
       store_tile_rows(Bs[cur], a.BA + (row0 + (int64_t)t * 16) * N64, tid);
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        double add = 0.0;
-        if (t > 0) {
-          add = q.r[0][v];
-#pragma unroll
-          for (int e = 1; e < EV_NODE; ++e) add += q.r[e][v];
-        }
-        Bs[cur ^ 1][(4 * w + v) * VST + l] = acc[v] + add;
-      }
+      for (int v = 0; v < 4; ++v) Bs[cur ^ 1][(4 * w + v) * VST + l] = acc[v] + (t > 0 ? node_add(q, v) : 0.0);
       lds_barrier();
       cur ^= 1;
     }

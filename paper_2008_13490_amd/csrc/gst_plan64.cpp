@@ -316,11 +316,16 @@ bool build_plan64(const int64_t* off, const uint8_t* gates, int64_t S, int K, co
   P.tile_ev.resize((size_t)T);
   P.ev_ptr.push_back(0);
   std::vector<int32_t> cur((size_t)W);
+  const bool cend = opt.max_node_events <= 15 && W == 16;
   for (int64_t ti = 0; ti < T; ++ti) {
     P.tile_ev[ti] = (int64_t)P.ev_ptr.size() - 1;
     for (int c = 0; c < P.tile_cols[ti]; ++c) cur[c] = head[P.col_chain[ti * W + c]];
     for (int64_t t = 0; t < P.tile_len[ti]; ++t) {
+      const size_t e_step = P.ev_col.size();
+      uint8_t row[16] = {};
+      int most = 0;
       for (int c = 0; c < P.tile_cols[ti]; ++c) {
+        const size_t e_col = P.ev_col.size();
         const int32_t x = cur[c];  // the node of column c at step t
         cur[c] = heavy[x];
         if (slot_of_node[x] >= 0) {
@@ -334,7 +339,12 @@ bool build_plan64(const int64_t* off, const uint8_t* gates, int64_t S, int K, co
           P.ev_col.push_back(c);
           P.ev_src.push_back(P.n_slots + anch_list[k]);
         }
+        most = std::max(most, (int)(P.ev_col.size() - e_col));
+        if (c < 15) row[c] = (uint8_t)(P.ev_col.size() - e_step);
       }
+      for (int c = P.tile_cols[ti]; c < 15; ++c) row[c] = (uint8_t)(P.ev_col.size() - e_step);
+      row[15] = (uint8_t)most;
+      if (cend) P.ev_cend.insert(P.ev_cend.end(), row, row + 16);
       P.ev_ptr.push_back((int64_t)P.ev_col.size());
     }
   }

@@ -71,8 +71,13 @@ struct Plan64 {
   // events of (tile, step): the INJ rows added to column `ev_col` before the
   // reverse sweep stores that step's adjoint (seed first, then chains by id)
   std::vector<int64_t> ev_ptr;           // [sum of tile lengths + 1]
-  std::vector<int32_t> ev_col;
+  std::vector<int32_t> ev_col;           // ascending within a tile-step
   std::vector<int64_t> ev_src;
+  // per tile-step 16 bytes, so that a column finds its events without a scan:
+  // byte c < 15 counts the step's events of columns <= c, byte 15 is the most
+  // events of one column (empty when the options allow more than 15 events
+  // at a node: such plans only serve the host-side interpreter)
+  std::vector<uint8_t> ev_cend;
   // readouts: slot -> FA row of its node, its sequences (ascending)
   std::vector<int64_t> slot_row;         // [n_slots]
   std::vector<int64_t> slot_ptr;         // [n_slots + 1]

@@ -53,5 +53,11 @@ void plan64_records(int64_t* rec_b, int64_t* rec_f, int64_t* rec_gate_ptr, int64
 void plan64_ts(int64_t* ts_tile, int32_t* ts_step) {
   CP(ts_tile, ts_tile); CP(ts_step, ts_step);
 }
+// the per-tile-step column table (16 bytes per tile-step; none when the build
+// allowed more than 15 events per node)
+int64_t plan64_cend(uint8_t* out) {
+  if (out) CP(out, ev_cend);
+  return (int64_t)g.ev_cend.size();
+}
 #undef CP
 }

@@ -198,6 +198,21 @@ def test_plan64_structure(plib):
     delivered = P["ev_src"][:P["n_events"]]
     delivered = delivered[delivered >= P["n_slots"]] - P["n_slots"]
     assert sorted(delivered.tolist() + P["root_chains"].tolist()) == list(range(P["n_chains"]))
+    # the column table: per tile-step, byte c < 15 counts the events of columns
+    # <= c (events ascend by column), byte 15 is the most events of one column
+    plib.plan64_cend.restype = ctypes.c_int64
+    plib.plan64_cend.argtypes = [ctypes.c_void_p]
+    TS = len(P["ev_ptr"]) - 1
+    assert plib.plan64_cend(None) == TS * 16
+    cend = np.zeros(TS * 16, np.uint8)
+    plib.plan64_cend(cend.ctypes.data)
+    cend = cend.reshape(TS, 16).astype(np.int64)
+    for ts in range(TS):
+        cols = P["ev_col"][P["ev_ptr"][ts]:P["ev_ptr"][ts + 1]]
+        assert (np.diff(cols) >= 0).all()
+        per = np.bincount(cols, minlength=16)
+        assert (cend[ts, :15] == np.cumsum(per)[:15]).all()
+        assert cend[ts, 15] == per.max()
     # anchors of level-l tiles lie on tiles of lower levels
     ltp = P["level_tile_ptr"]
     for lev in range(P["n_levels"]):
