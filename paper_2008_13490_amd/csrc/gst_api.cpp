@@ -670,7 +670,12 @@ int upload_plan64(gst_req* r, gst::Plan64& P, const int32_t* counts_host) {
   // the reverse kernel finds a column's events through the per-step table and
   // stages the events' INJ rows as 32-bit indices
   if ((int64_t)P.ev_cend.size() != TS * 16 || P.n_slots + P.n_chains >= INT32_MAX) return GST_EINVAL;
-  d.readout_blocks = (int)std::min<int64_t>(std::max<int64_t>((P.n_slots + gst::READOUT64_WAVES - 1) /
+  // the gradient GEMM stages a chunk's rows in LDS
+  for (int64_t i = 0; i < NC; ++i)
+    if (P.chunk_end[i] - P.chunk_beg[i] > gst::GEMM64_TS_CHUNK_MAX) return GST_EINVAL;
+  // the readout takes groups of 16 slots, a wave per group at a time
+  const int64_t n_groups = (P.n_slots + 15) / 16;
+  d.readout_blocks = (int)std::min<int64_t>(std::max<int64_t>((n_groups + gst::READOUT64_WAVES - 1) /
                                                                   gst::READOUT64_WAVES, 1),
                                             (int64_t)gst::readout64_blocks_per_cu() * r->ctx->n_cu);
   const int64_t n_waves = (int64_t)d.readout_blocks * gst::READOUT64_WAVES;

@@ -595,32 +595,59 @@ __global__ __launch_bounds__(256) void plan64_bwd_kernel(const Plan64Launch a) {
 // contributes sum_c b_c f_c^T over its sixteen columns: four MFMAs over the
 // columns per 16 x 16 output tile, operands read straight from the arenas
 // (a tile-step's adjoint rows are consecutive, and so are its state rows
-// except at step 0, where they are the columns' anchors).
+// except at step 0, where they are the columns' anchors).  The chunk's rows
+// are looked up once, into LDS, and each tile-step's operands are loaded
+// while the previous one's MFMAs run, so that a tile-step waits for one
+// memory round trip at most instead of a chain of dependent ones.
+constexpr int TS_CHUNK_MAX = GEMM64_TS_CHUNK_MAX;
+
+struct TsOps {
+  double av[4];     // adjoint rows 4kb + z, elements 16w + ii
+  double bv[4][4];  // state rows of the same columns, elements 16tc + ii
+};
+
+__device__ __forceinline__ void load_ts(TsOps& o, const double* BA, const double* FA, int64_t rb, const int64_t* rf,
+                                        int w, int z, int ii) {
+  const auto* g_b = as_global(BA);
+  const auto* g_f = as_global(FA);
+#pragma unroll
+  for (int kb = 0; kb < 4; ++kb) {
+    const int col = 4 * kb + z;
+    o.av[kb] = g_b[(rb + col) * N64 + 16 * w + ii];
+    const int64_t r = rf[col];
+#pragma unroll
+    for (int tc = 0; tc < 4; ++tc) o.bv[kb][tc] = g_f[r * N64 + 16 * tc + ii];
+  }
+}
+
 __global__ __launch_bounds__(256) void gemm64_ts_kernel(const Gemm64TsLaunch a) {
+  __shared__ int64_t Rb[TS_CHUNK_MAX];       // adjoint row of column 0 at each tile-step
+  __shared__ int64_t Rf[TS_CHUNK_MAX][16];   // the columns' state rows before it
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int z = lane >> 4, ii = lane & 15;
   const int64_t ch = blockIdx.x;
-  const int64_t x0 = a.chunk_beg[ch], x1 = a.chunk_end[ch];
-  const auto* g_b = as_global(a.BA);
-  const auto* g_f = as_global(a.FA);
+  const int64_t x0 = a.chunk_beg[ch];
+  const int n = (int)(a.chunk_end[ch] - x0);  // <= TS_CHUNK_MAX (checked on the host)
+  for (int e = tid; e < n * 16; e += 256) {
+    const int x = e >> 4, c = e & 15;
+    const int64_t tile = a.ts_tile[x0 + x];
+    const int t = a.ts_step[x0 + x];
+    const int64_t r0 = a.tile_row0[tile] + (int64_t)t * 16;
+    if (c == 0) Rb[x] = r0;
+    Rf[x][c] = t > 0 ? r0 - 16 + c : a.col_anchor[tile * 16 + c];
+  }
+  __syncthreads();
   d4 acc[4];
 #pragma unroll
   for (int tc = 0; tc < 4; ++tc) acc[tc] = d4{0.0, 0.0, 0.0, 0.0};
-  for (int64_t x = x0; x < x1; ++x) {
-    const int64_t tile = a.ts_tile[x];
-    const int t = a.ts_step[x];
-    const int64_t rb0 = a.tile_row0[tile] + (int64_t)t * 16;
+  for (int x = 0; x < n; ++x) {
+    TsOps cur;
+    load_ts(cur, a.BA, a.FA, Rb[x], Rf[x], w, z, ii);
 #pragma unroll
-    for (int kb = 0; kb < 4; ++kb) {
-      const int col = 4 * kb + z;
-      const int64_t rf = t > 0 ? rb0 - 16 + col : a.col_anchor[tile * 16 + col];
-      const double av = g_b[(rb0 + col) * N64 + 16 * w + ii];
-      double bv[4];
+    for (int kb = 0; kb < 4; ++kb)
 #pragma unroll
-      for (int tc = 0; tc < 4; ++tc) bv[tc] = g_f[rf * N64 + 16 * tc + ii];
-#pragma unroll
-      for (int tc = 0; tc < 4; ++tc) acc[tc] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv[tc], acc[tc], 0, 0, 0);
-    }
+      for (int tc = 0; tc < 4; ++tc)
+        acc[tc] = __builtin_amdgcn_mfma_f64_16x16x4f64(cur.av[kb], cur.bv[kb][tc], acc[tc], 0, 0, 0);
   }
   double* out = a.slab + ch * GATE64;
 #pragma unroll
@@ -632,111 +659,148 @@ __global__ __launch_bounds__(256) void gemm64_ts_kernel(const Gemm64TsLaunch a) 
     }
 }
 
-// Readouts per seed slot (the sequences ending at one node): p = E f in the
-// plain order, the objective, dL/dp, the seed E^T (sum of the slot's dL/dp),
-// and dL/dE.  Slot s goes to wave s mod (waves of the launch), so every sum
-// has a fixed order; each wave writes one partial row [objective | 0 | dL/dE].
-// E row m (LDS) dotted with x, columns ascending from 0.
-__device__ __forceinline__ double mv_lds_row(const double* row, int lane, double x) {
-  double acc = 0.0;
-#pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const double xr = row_copy(x, r, lane);
-    Row16 R = load_row(row + 16 * r);
-    acc = dot16_from(acc, xr, R);
-  }
-  return acc;
-}
+// Readouts per seed slot (the sequences ending at one node): p = E f, the
+// objective, dL/dp, the seed E^T (sum of the slot's dL/dp), and dL/dE, for
+// sixteen slots at a time on the matrix cores.  A wave takes the slot groups
+// wv, wv + (waves of the launch), ... and, per group:
+//   P^T = F^T E^T      (16 slots x 16 outcomes, K = 64: the slots' states as
+//                       the A operand, E in registers as the B operand)
+//   per (slot, outcome), in P's output layout: the objective terms and dL/dp
+//   dE += D^T F        (outcomes x states, K = 16 slots)
+//   S^T = D E          (slots x states, K = outcomes: the seeds)
+// where D holds dL/dp (slots x outcomes).  F and D change layout through a
+// small LDS tile per wave.  Lane l = 16 r4 + c owns, in an output block, rows
+// 4v + r4 (v = 0..3) of column c.  Each wave writes one partial row
+// [objective | 0 | dL/dE]; every sum has a fixed order.
+constexpr int RO_FST = 66;  // padded row stride (doubles) of a wave's staged states
+constexpr int RO_DST = 17;  // the same for its dL/dp tile
 
 __global__ __launch_bounds__(READOUT64_WAVES * 64) void readout64_kernel(const Readout64Launch a) {
-  __shared__ double Es[16 * N64];
-  const int l = threadIdx.x & 63;
-  const int64_t wv = (int64_t)blockIdx.x * READOUT64_WAVES + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  __shared__ double Fs[READOUT64_WAVES][16 * RO_FST];
+  __shared__ double Ds[READOUT64_WAVES][16 * RO_DST];
+  const int l = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int c = l & 15, r4 = l >> 4;
+  const int64_t wv = (int64_t)blockIdx.x * READOUT64_WAVES + w;
   const int64_t nw = (int64_t)gridDim.x * READOUT64_WAVES;
   const int M = a.M;
-  for (int x = threadIdx.x; x < M * N64; x += READOUT64_WAVES * 64) Es[x] = a.E[x];
-  __syncthreads();
-  const int mrow = l < M ? l : M - 1;
-  const double* Erow = Es + mrow * N64;
+  const auto* gE = as_global(a.E);
   const auto* fa = as_global(a.FA);
+  const auto* g_pack = as_global(a.slot_pack);
+  const auto* g_cnt = as_global(a.slot_cnt);
+  const auto* g_seq = as_global(a.slot_seq);
   const auto* g_counts = as_global(a.counts);
   const auto* g_W = as_global(a.W);
   auto* g_probs = as_global(a.probs);
   const bool grad = a.want_grad != 0;
+  // E as B operands: eP[kk] = E[c][4kk + r4] for P^T, eS[kk][tc] = E[4kk + r4][16tc + c] for S^T
+  double eP[16], eS[4][4];
+#pragma unroll
+  for (int kk = 0; kk < 16; ++kk) eP[kk] = c < M ? gE[c * N64 + 4 * kk + r4] : 0.0;
+#pragma unroll
+  for (int kk = 0; kk < 4; ++kk)
+#pragma unroll
+    for (int tc = 0; tc < 4; ++tc) eS[kk][tc] = 4 * kk + r4 < M ? gE[(4 * kk + r4) * N64 + 16 * tc + c] : 0.0;
+  d4 dE[4];
+#pragma unroll
+  for (int tc = 0; tc < 4; ++tc) dE[tc] = d4{0.0, 0.0, 0.0, 0.0};
   double obj = 0.0;
-  double dE[16];
-#pragma unroll
-  for (int m = 0; m < 16; ++m) dE[m] = 0.0;
   unsigned nonpos = 0;
-  // The wave's slots s = wv + j nw in groups of RG: the group's packed slot
-  // records and first-sequence counts are loaded together, then the group's
-  // states (and, for vector-Jacobian products, weights), so that a group costs
-  // two memory round trips instead of three per slot.  Slots are summed in the
-  // same order as one at a time.
-  constexpr int RG = 4;
-  const auto* g_pack = as_global(a.slot_pack);
-  const auto* g_cnt = as_global(a.slot_cnt);
-  const int64_t n_my = wv < a.n_slots ? (a.n_slots - 1 - wv) / nw + 1 : 0;
-  for (int64_t j0 = 0; j0 < n_my; j0 += RG) {
-    int64_t row[RG], seq0[RG], q0[RG], q1[RG];
-    int32_t c0[RG];
+  double* Fw = Fs[w];
+  double* Dw = Ds[w];
+  const int64_t n_groups = (a.n_slots + 15) / 16;
+  for (int64_t gi = wv; gi < n_groups; gi += nw) {
+    // slot 16 gi + c: its state row, the A operand of P^T (elements 4kk + r4)
+    const int64_t sc = gi * 16 + c;
+    const int64_t rowc = g_pack[4 * (sc < a.n_slots ? sc : 0)];
+    double fA[16];
 #pragma unroll
-    for (int g = 0; g < RG; ++g) {
-      const bool valid = j0 + g < n_my;
-      const int64_t s = wv + (j0 + g) * nw;
-      const int64_t* pk = a.slot_pack + 4 * (valid ? s : 0);
-      row[g] = pk[0];
-      seq0[g] = pk[1];
-      q0[g] = pk[2];
-      q1[g] = valid ? pk[3] : pk[2];
-      c0[g] = (a.mode == MODE_LOGLIK && valid && l < M) ? g_cnt[s * M + l] : 0;
+    for (int kk = 0; kk < 16; ++kk) fA[kk] = fa[rowc * N64 + 4 * kk + r4];
+    // slots 16 gi + 4v + r4 of the output rows: first sequence, sequence range,
+    // the first sequence's count (or weight) of outcome c
+    int64_t seq0[4], q0[4], q1[4];
+    double n0[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int64_t s = gi * 16 + 4 * v + r4;
+      const bool valid = s < a.n_slots;
+      const int64_t b = 4 * (valid ? s : 0);
+      seq0[v] = g_pack[b + 1];
+      q0[v] = g_pack[b + 2];
+      q1[v] = valid ? g_pack[b + 3] : q0[v];
+      n0[v] = 0.0;
+      if (a.mode == MODE_LOGLIK && valid && c < M) n0[v] = (double)g_cnt[s * M + c];
     }
-    double fg[RG], w0[RG];
+    if (a.mode == MODE_VJP) {
 #pragma unroll
-    for (int g = 0; g < RG; ++g) {
-      fg[g] = fa[row[g] * N64 + l];
-      w0[g] = (a.mode == MODE_VJP && q1[g] > q0[g] && l < M) ? g_W[seq0[g] * M + l] : 0.0;
+      for (int v = 0; v < 4; ++v) n0[v] = q1[v] > q0[v] && c < M ? g_W[seq0[v] * M + c] : 0.0;
     }
+    d4 p = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int g = 0; g < RG; ++g) {
-      if (j0 + g >= n_my) break;
-      const int64_t s = wv + (j0 + g) * nw;
-      const double f = fg[g];
-      const double p = mv_lds_row(Erow, l, f);
-      double dps = 0.0;
-      for (int64_t q = q0[g]; q < q1[g]; ++q) {
-        const int64_t seq = q == q0[g] ? seq0[g] : a.slot_seq[q];
-        if (l < M) {
-          const int64_t o = seq * M + l;
-          if (a.probs) g_probs[o] = p;
-          if (a.mode == MODE_LOGLIK) {
-            const int32_t N = q == q0[g] ? c0[g] : g_counts[o];
-            if (N > 0) {
-              if (p <= 0.0) {
-                ++nonpos;
-                obj = INFINITY;
-              } else {
-                obj -= (double)N * log(p);
-                dps += -(double)N / p;
-              }
+    for (int kk = 0; kk < 16; ++kk) p = __builtin_amdgcn_mfma_f64_16x16x4f64(fA[kk], eP[kk], p, 0, 0, 0);
+    if (grad) {
+#pragma unroll
+      for (int kk = 0; kk < 16; ++kk) Fw[c * RO_FST + 4 * kk + r4] = fA[kk];
+    }
+    double dps[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      dps[v] = 0.0;
+      if (c >= M) continue;
+      for (int64_t q = q0[v]; q < q1[v]; ++q) {
+        const int64_t seq = q == q0[v] ? seq0[v] : g_seq[q];
+        const int64_t o = seq * M + c;
+        if (a.probs) g_probs[o] = p[v];
+        if (a.mode == MODE_LOGLIK) {
+          const double N = q == q0[v] ? n0[v] : (double)g_counts[o];
+          if (N > 0.0) {
+            if (p[v] <= 0.0) {
+              ++nonpos;
+              obj = INFINITY;
+            } else {
+              obj -= N * log(p[v]);
+              dps[v] += -N / p[v];
             }
-          } else if (a.mode == MODE_VJP) {
-            dps += q == q0[g] ? w0[g] : g_W[o];
           }
+        } else if (a.mode == MODE_VJP) {
+          dps[v] += q == q0[v] ? n0[v] : g_W[o];
         }
       }
-      if (!grad) continue;
-      double b = 0.0;
-#pragma unroll
-      for (int m = 0; m < 16; ++m) {
-        if (m < M) {
-          const double dpm = __shfl(dps, m);
-          dE[m] = fma(dpm, f, dE[m]);
-          b = fma(Es[m * N64 + l], dpm, b);
-        }
-      }
-      a.INJ[s * N64 + l] = b;
     }
+    if (!grad) continue;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) Dw[(4 * v + r4) * RO_DST + c] = dps[v];
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    // dE += D^T F: A = dps (outcome c, slot 4kk + r4), B = F[slot 4kk + r4][16tc + c]
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk)
+#pragma unroll
+      for (int tc = 0; tc < 4; ++tc)
+        dE[tc] = __builtin_amdgcn_mfma_f64_16x16x4f64(dps[kk], Fw[(4 * kk + r4) * RO_FST + 16 * tc + c], dE[tc], 0, 0,
+                                                      0);
+    // S^T = D E: A = D[slot c][outcome 4kk + r4], B = eS
+    double dA[4];
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) dA[kk] = Dw[c * RO_DST + 4 * kk + r4];
+    d4 st[4];
+#pragma unroll
+    for (int tc = 0; tc < 4; ++tc) {
+      st[tc] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) st[tc] = __builtin_amdgcn_mfma_f64_16x16x4f64(dA[kk], eS[kk][tc], st[tc], 0, 0, 0);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int64_t s = gi * 16 + 4 * v + r4;
+      if (s < a.n_slots) {
+        auto* out = as_global(a.INJ + s * N64 + c);
+#pragma unroll
+        for (int tc = 0; tc < 4; ++tc) out[16 * tc] = st[tc][v];
+      }
+    }
+    // the tiles are rewritten by the next group
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
   }
   if (a.slab) {
     const int64_t Pc = 1 + N64 + (int64_t)M * N64;
@@ -745,8 +809,12 @@ __global__ __launch_bounds__(READOUT64_WAVES * 64) void readout64_kernel(const R
     if (l == 0) out[0] = o;
     out[1 + l] = 0.0;
 #pragma unroll
-    for (int m = 0; m < 16; ++m)
-      if (m < M) out[1 + N64 + m * N64 + l] = dE[m];
+    for (int v = 0; v < 4; ++v) {
+      const int m = 4 * v + r4;
+      if (m < M)
+#pragma unroll
+        for (int tc = 0; tc < 4; ++tc) out[1 + N64 + m * N64 + 16 * tc + c] = dE[tc][v];
+    }
   }
   const unsigned np = (unsigned)wave_sum((double)nonpos);
   if (l == 0 && np) {
