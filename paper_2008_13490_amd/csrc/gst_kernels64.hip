@@ -529,6 +529,7 @@ __global__ __launch_bounds__(256) void plan64_bwd_kernel(const Plan64Launch a) {
   __shared__ int32_t Es[CH_STEPS + 2];
   __shared__ int32_t Ev[CH_EVENTS];
   __shared__ u32x4 Cc[CH_STEPS + 1];
+  __shared__ unsigned long long Em[5];  // bit x: step s0 + x of the chunk has events
   const int tid = threadIdx.x, l = tid & 63, w = tid >> 6;
   const int c = l & 15, r4 = l >> 4;
   const int64_t tile = a.t_begin + blockIdx.x;
@@ -558,7 +559,27 @@ __global__ __launch_bounds__(256) void plan64_bwd_kernel(const Plan64Launch a) {
     for (int x = tid; x <= t1 - s0; x += 256) Es[x] = (int32_t)(evp[s0 + x] - e0);
     for (int x = tid; x < t1 - s0; x += 256) Cc[x] = cend[s0 + x];
     for (int j = tid; j < (int)(e1 - e0); j += 256) Ev[j] = (int32_t)evs[e0 + j];
+    {
+      // which of the chunk's steps have events: a step without any skips the
+      // lookup (the steps s0 .. t1 - 1, at most CH_STEPS + 1)
+      const int xa = tid, xb = tid + 256;
+      const bool fa = xa < t1 - s0 && evp[s0 + xa + 1] > evp[s0 + xa];
+      const bool fb = xb < t1 - s0 && evp[s0 + xb + 1] > evp[s0 + xb];
+      const unsigned long long ba = __ballot(fa), bb = __ballot(fb);
+      if (l == 0) {
+        Em[w] = ba;
+        if (w == 0) Em[4] = bb;
+      }
+    }
     lds_barrier();
+    const unsigned long long em0 = uniform64((int64_t)Em[0]), em1 = uniform64((int64_t)Em[1]),
+                             em2 = uniform64((int64_t)Em[2]), em3 = uniform64((int64_t)Em[3]),
+                             em4 = uniform64((int64_t)Em[4]);
+    auto has_events = [&](int xs) {
+      const int wi = xs >> 6;
+      const unsigned long long b = wi == 0 ? em0 : wi == 1 ? em1 : wi == 2 ? em2 : wi == 3 ? em3 : em4;
+      return ((b >> (xs & 63)) & 1ull) != 0;
+    };
     if (t1 == len) {
       // b of the last node: its events alone
       NodeAdds q;
@@ -572,11 +593,17 @@ __global__ __launch_bounds__(256) void plan64_bwd_kernel(const Plan64Launch a) {
       const int t = t0 + x;
       NodeAdds q;  // events of node t - 1
       q.n = 0;
-      if (t > 0) load_node_adds(q, Es, Ev, Cc, t - 1 - s0, c, w, r4, a.INJ);
+      const bool ev = t > 0 && has_events(t - 1 - s0);
+      if (ev) load_node_adds(q, Es, Ev, Cc, t - 1 - s0, c, w, r4, a.INJ);
       const d4 acc = gs.product(a.GAT, uniform(Ws[x + 1]), t > 0 ? uniform(Ws[x]) : -1, Bs[cur], w, l);
       store_tile_rows(Bs[cur], a.BA + (row0 + (int64_t)t * 16) * N64, tid);
+      if (ev) {
 #pragma unroll
-      for (int v = 0; v < 4; ++v) Bs[cur ^ 1][(4 * w + v) * VST + l] = acc[v] + (t > 0 ? node_add(q, v) : 0.0);
+        for (int v = 0; v < 4; ++v) Bs[cur ^ 1][(4 * w + v) * VST + l] = acc[v] + node_add(q, v);
+      } else {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) Bs[cur ^ 1][(4 * w + v) * VST + l] = acc[v] + 0.0;
+      }
       lds_barrier();
       cur ^= 1;
     }
