@@ -322,7 +322,7 @@ struct Gemm64TsLaunch {
   double* slab;              // [n_chunks][4096]
   int n_chunks;
 };
-constexpr int GEMM64_TS_CHUNK_MAX = 32;  // tile-steps per chunk at most (staged in LDS)
+constexpr int GEMM64_TS_CHUNK_MAX = 64;  // tile-steps per chunk at most (staged in LDS)
 hipError_t launch_gemm64_ts(const Gemm64TsLaunch& a, hipStream_t stream);
 constexpr int READOUT64_WAVES = 4;
 struct Readout64Launch {

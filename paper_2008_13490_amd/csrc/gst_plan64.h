@@ -45,7 +45,7 @@ struct Plan64Options {
   double min_fill = 0.0;              // ... and live columns fill at least this share of tile rows
   int64_t max_nodes = 1LL << 26;
   int chunk = 8192;                   // gradient records per chunk (the records of the CPU tests)
-  int ts_chunk = 32;                  // tile-steps per chunk of the gradient GEMM
+  int ts_chunk = 64;                  // tile-steps per chunk of the gradient GEMM (<= GEMM64_TS_CHUNK_MAX)
   int max_node_events = kMaxNodeEvents;  // refuse plans with more events at one node
   int split_height = 32;              // a chain ends at a node with two children of at least this height
   bool short_asap = false;            // short chains run as soon as they are ready (else: in full tiles)
