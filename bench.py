@@ -264,7 +264,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c2x64", "c3", "c4", "c5", "f2", "f3"])
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c2x64", "c3", "c4", "c4x8", "c5", "f2", "f3"])
     ap.add_argument("--fit-iters", type=int, default=100, help="f2: L-BFGS iterations per MLGST stage")
     ap.add_argument("--rate", type=float, default=100.0, help="c5 / serving: arrivals per second")
     ap.add_argument("--serving-rates", default="", help="c5: comma-separated arrival rates to sweep")
@@ -272,7 +272,8 @@ def main():
     ap.add_argument("--requests", type=int, default=100, help="c5 / serving: requests in the trace")
     ap.add_argument("--iters", type=int, default=20, help="c5 / serving: iterations per request")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving measurement of the default run")
-    ap.add_argument("--no-batched", action="store_true", help="skip the c2x64 measurement of the default run")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the batched measurement (c2x64 with c2, c4x8 with c4)")
     ap.add_argument("--no-autotune", action="store_true", help="c3: keep the default tile policy")
     ap.add_argument("--round-work", type=float, default=8e6,
                     help="serving: bound on the work of one round, in two-qubit sequence steps")
@@ -312,16 +313,18 @@ def main():
         out = run_predict(args)
     else:
         out = run_structured(args)
-        if args.workload == "c2" and args.path == "resident" and args.param == "full" and not args.no_batched:
-            # the same list for 64 gate sets in one batch: the steady state of many
-            # evaluations (one launch per kernel and level for all 64)
+        batched = {"c2": "c2x64", "c4": "c4x8"}.get(args.workload)
+        if batched and args.path == "resident" and args.param == "full" and not args.no_batched:
+            # the same list for many gate sets in one batch: the steady state of many
+            # evaluations (one launch per kernel and level for all of them)
             import copy
             b_args = copy.copy(args)
-            b_args.workload, b_args.steps, b_args.warmup = "c2x64", 20, 3
+            b_args.workload, b_args.steps, b_args.warmup = batched, (20 if batched == "c2x64" else 10), 3
             b = run_structured(b_args)
-            out["batched_c2x64"] = {k: b[k] for k in ("value", "unit", "ms_per_step", "steps", "roofline",
-                                                      "graph_replay", "one_by_one")}
-            out["batched_c2x64"]["workload"] = b["config"]["workload"]
+            key = "batched_" + batched
+            out[key] = {k: b[k] for k in ("value", "unit", "ms_per_step", "steps", "roofline", "graph_replay",
+                                          "one_by_one")}
+            out[key]["workload"] = b["config"]["workload"]
         if args.workload == "c2" and not args.no_serving:
             out["serving"] = serving_summary(args)
     out["cpu_baseline"] = cpu
@@ -329,8 +332,9 @@ def main():
 
 
 def base_workload(name: str) -> str:
-    """c2x64 is the c2 list evaluated for 64 gate sets at once."""
-    return "c2" if name == "c2x64" else name
+    """c2x64 is the c2 list evaluated for 64 gate sets at once, c4x8 the c4
+    list for 8."""
+    return {"c2x64": "c2", "c4x8": "c4"}.get(name, name)
 
 
 _SERVING_DATA = {}
@@ -475,23 +479,25 @@ def run_structured(args):
     grad = torch.empty(m.n_params(), dtype=torch.float64, device=dev)
     n_sets = 1
     batch_extra = None
-    if args.workload == "c2x64":
-        # 64 gate sets (the model and 63 seeded neighbours) over the one list:
-        # 64 resident requests, their sharing plans run as one launch per
-        # kernel and level; one step evaluates all of them
+    if args.workload in ("c2x64", "c4x8"):
+        # many gate sets (the model and seeded neighbours) over the one list:
+        # resident requests whose plans run as one launch per kernel and level;
+        # one step evaluates all of them
         if args.path != "resident" or args.param != "full":
-            raise SystemExit("c2x64: resident path, full parameterization")
-        n_sets = 64
-        rng = np.random.default_rng(64)
-        sets = [m] + [W.noisy_gateset("2q", W.LAMBDA, W.SIGMA, rng) for _ in range(n_sets - 1)]
+            raise SystemExit(f"{args.workload}: resident path, full parameterization")
+        n_sets = 64 if args.workload == "c2x64" else 8
+        rng = np.random.default_rng(n_sets)
+        kind = {2: "2q", 3: "3q"}[m.n_qubits]
+        sets = [m] + [W.noisy_gateset(kind, W.LAMBDA, W.SIGMA, rng) for _ in range(n_sets - 1)]
         reqs = [api.Request(ctx, m.n_qubits, m.K, m.M, w.seqs.offsets, w.seqs.gates, w.counts)
                 for _ in range(n_sets)]
         thetas = [api.DeviceGateSet.from_numpy(g.n_qubits, g.rho, g.effects, g.gates) for g in sets]
         req = reqs[0]
         batch = api.Batch(ctx, reqs, thetas, want_probs=False, want_grad=True, capture_graph=True)
-        desc = dict(desc, workload=f"c2x64: the c2 list for {n_sets} gate sets (the model and {n_sets - 1} seeded "
-                                   f"neighbours, same noise model) as {n_sets} resident requests in one batch; "
-                                   + desc["workload"])
+        base = base_workload(args.workload)
+        desc = dict(desc, workload=f"{args.workload}: the {base} list for {n_sets} gate sets (the model and "
+                                   f"{n_sets - 1} seeded neighbours, same noise model) as {n_sets} resident requests "
+                                   f"in one batch; " + desc["workload"])
 
         def step():
             batch.run()
@@ -620,7 +626,7 @@ def run_structured(args):
         a_s = (time.perf_counter() - t0) / args.steps
         extra = {"graph_replay": {"ms_per_step": g_s * 1e3, "value": n_sets * S / g_s},
                  "one_by_one": {"ms_per_step": a_s * 1e3, "value": n_sets * S / a_s,
-                                "what": "the same 64 requests evaluated one after another (own launch sequences)"}}
+                                "what": f"the same {n_sets} requests evaluated one after another (own launch sequences)"}}
     flops = n_sets * fam_flops(dom)  # algorithmic FP64 work per launch of the dominant family
     if info and info.get("grouped"):
         steps_eval = info["trie_nodes"] - 1

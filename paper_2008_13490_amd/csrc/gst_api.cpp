@@ -275,6 +275,8 @@ struct DevicePlan64 {
   int32_t *tile_len = nullptr, *ts_step = nullptr, *slot_cnt = nullptr;
   uint8_t* ev_cend = nullptr;
   uint8_t* words = nullptr;
+  int64_t* lvl_tile = nullptr;   // device copies of level_tile_ptr and level_long
+  uint8_t* lvl_long = nullptr;
   double *FA = nullptr, *BA = nullptr, *INJ = nullptr, *GA = nullptr, *GAT = nullptr, *slab = nullptr,
          *part = nullptr, *chunk_slab = nullptr, *root_vec = nullptr;
   int readout_blocks = 0;
@@ -335,7 +337,14 @@ struct gst_batch {
   std::vector<gst_req*> reqs;
   std::vector<gst_gateset> thetas;
   std::vector<double*> probs, objectives, grads;
-  std::vector<int> plan_reqs;           // three-qubit: evaluated through their own launch sequences
+  std::vector<int> plan_reqs;           // three qubits without the grouped-chain plan: their own launch sequences
+  // three-qubit grouped-chain plans: one launch per kernel and level for all of them
+  struct P64Group {
+    int n = 0, K_max = 1, n_levels = 0, ro_grid = 0, gemm_grid = 0, red_x = 0, red_parts = 1, r64_x = 0;
+    bool any_grad = false, any_slab = false;
+    std::vector<int> grid_long, grid_short;  // per level: most tiles of a request's level of each kind
+    const gst::Plan64Req* dev = nullptr;
+  } p64;
   // one- and two-qubit sharing plans, batched per D (0: D = 4, 1: D = 16): one
   // launch per kernel and level for all of them
   struct PlanGroup {
@@ -696,7 +705,8 @@ int upload_plan64(gst_req* r, gst::Plan64& P, const int32_t* counts_host) {
                o_ga = c.take<double>((size_t)K * 4096), o_gat = c.take<double>((size_t)K * 4096),
                o_slab = c.take<double>((size_t)n_waves * Pc),
                o_part = c.take<double>((size_t)gst::reduce_parts((int)n_waves) * Pc),
-               o_cs = c.take<double>((size_t)std::max<int64_t>(NC, 1) * 4096), o_root = c.take<double>(64);
+               o_cs = c.take<double>((size_t)std::max<int64_t>(NC, 1) * 4096), o_root = c.take<double>(64),
+               o_lt = c.take<int64_t>(P.n_levels + 1), o_ll = c.take<uint8_t>(P.n_levels + 1);
   int rc = d.buf.reserve(c.off + 256, r->ctx->stream);
   if (rc) return rc;
   char* b = reinterpret_cast<char*>(d.buf.p);
@@ -730,6 +740,8 @@ int upload_plan64(gst_req* r, gst::Plan64& P, const int32_t* counts_host) {
   d.part = reinterpret_cast<double*>(b + o_part);
   d.chunk_slab = reinterpret_cast<double*>(b + o_cs);
   d.root_vec = reinterpret_cast<double*>(b + o_root);
+  d.lvl_tile = reinterpret_cast<int64_t*>(b + o_lt);
+  d.lvl_long = reinterpret_cast<uint8_t*>(b + o_ll);
   auto put = [&](void* dst, const void* src, size_t bytes) -> int {
     if (bytes) HIP_TRY(hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice));
     return GST_OK;
@@ -776,6 +788,8 @@ int upload_plan64(gst_req* r, gst::Plan64& P, const int32_t* counts_host) {
   for (int l = 0; l < P.n_levels; ++l)
     for (int64_t t = P.level_tile_ptr[l]; t < P.level_tile_ptr[l + 1]; ++t)
       if (P.tile_len[t] >= kRegGateSteps) d.level_long[l] = 1;
+  if ((rc = put(d.lvl_tile, d.level_tile_ptr.data(), d.level_tile_ptr.size() * 8))) return rc;
+  if ((rc = put(d.lvl_long, d.level_long.data(), d.level_long.size()))) return rc;
   d.n_root_chains = (int)NRC;
   d.n_chunks = NC;
   // keep the sizes, drop the host copies of the big arrays
@@ -799,15 +813,15 @@ int upload_plan64(gst_req* r, gst::Plan64& P, const int32_t* counts_host) {
 // readouts per seed slot, the chains backward deepest level first, the
 // gradient GEMM over the (adjoint, parent state) records, the root adjoint,
 // and the ordered sums.
-int run_plan64(gst_req* r, const gst_gateset* th, int mode, const double* w, double* probs, double* objective,
-               double* grad, unsigned long long* nonpos) {
-  gst_ctx* ctx = r->ctx;
+// The arguments of a request's grouped-chain evaluation: the standalone launch
+// sequence below and the batched one (gst_batch_run) read the same values.
+static gst::Plan64Req plan64_req(gst_req* r, const gst_gateset* th, int mode, const double* w, double* probs,
+                                 double* objective, double* grad, unsigned long long* np) {
   DevicePlan64& d = r->plan64;
   const bool want_grad = grad != nullptr;
-  unsigned long long* np = nonpos ? nonpos : reinterpret_cast<unsigned long long*>(r->queue + kQueueWords);
-  HIP_TRY(gst::launch_queue_reset(r->queue, np, 1, ctx->stream));
-  HIP_TRY(gst::launch_gate_prep64(th->gates, th->rho, r->K, d.GA, d.GAT, d.FA, ctx->stream));
-  gst::Plan64Launch a{};
+  const bool need_slab = objective || grad;
+  gst::Plan64Req q{};
+  gst::Plan64Launch& a = q.tiles;
   a.GA = d.GA;
   a.GAT = d.GAT;
   a.tile_row0 = d.tile_row0;
@@ -825,6 +839,83 @@ int run_plan64(gst_req* r, const gst_gateset* th, int mode, const double* w, dou
   a.INJ = d.INJ;
   a.n_slots = d.host.n_slots;
   a.K = r->K;
+  q.level_tile = d.lvl_tile;
+  q.level_long = d.lvl_long;
+  q.n_levels = d.host.n_levels;
+  q.want_grad = want_grad ? 1 : 0;
+  q.G = th->gates;
+  q.rho = th->rho;
+  gst::Readout64Launch& ro = q.ro;
+  ro.M = r->M;
+  ro.E = th->effects;
+  ro.FA = d.FA;
+  ro.n_slots = d.host.n_slots;
+  ro.slot_row = d.slot_row;
+  ro.slot_ptr = d.slot_ptr;
+  ro.slot_seq = d.slot_seq;
+  ro.slot_pack = d.slot_pack;
+  ro.slot_cnt = d.slot_cnt;
+  ro.counts = r->counts;
+  ro.W = w;
+  ro.probs = probs;
+  ro.mode = mode;
+  ro.want_grad = want_grad ? 1 : 0;
+  ro.INJ = d.INJ;
+  ro.slab = need_slab ? d.slab : nullptr;
+  ro.status = r->ctx->status;
+  ro.nonpos = np;
+  q.ro_blocks = d.readout_blocks;
+  if (want_grad && d.n_chunks > 0) {
+    gst::Gemm64TsLaunch& g = q.gemm;
+    g.BA = d.BA;
+    g.FA = d.FA;
+    g.tile_row0 = d.tile_row0;
+    g.col_anchor = d.col_anchor;
+    g.ts_tile = d.ts_tile;
+    g.ts_step = d.ts_step;
+    g.chunk_beg = d.chunk_beg;
+    g.chunk_end = d.chunk_end;
+    g.slab = d.chunk_slab;
+    g.n_chunks = (int)d.n_chunks;
+  }
+  q.root.INJ = d.INJ;
+  q.root.root_slot = d.host.root_slot;
+  q.root.n_slots = d.host.n_slots;
+  q.root.root_chains = d.root_chains;
+  q.root.n_root_chains = d.n_root_chains;
+  q.root.out = d.root_vec;
+  if (need_slab) {
+    q.slab = d.slab;
+    q.n_slabs = d.readout_blocks * gst::READOUT64_WAVES;
+    q.red_parts = gst::reduce_parts(q.n_slabs);
+    q.red_per = (q.n_slabs + q.red_parts - 1) / q.red_parts;
+    q.P = 1 + 64 + (int64_t)r->M * 64;
+    q.part = d.part;
+    q.objective = objective;
+    q.grad = grad;
+    q.extra_rho = want_grad ? d.root_vec : nullptr;
+    if (want_grad) {
+      q.r64.M = r->M;
+      q.r64.K = r->K;
+      q.r64.chunk_slab = d.chunk_slab;
+      q.r64.gate_chunk_ptr = d.gate_chunk_ptr;
+      q.r64.grad = grad;
+      q.r64.nonpos = np;
+    }
+  }
+  return q;
+}
+
+int run_plan64(gst_req* r, const gst_gateset* th, int mode, const double* w, double* probs, double* objective,
+               double* grad, unsigned long long* nonpos) {
+  gst_ctx* ctx = r->ctx;
+  DevicePlan64& d = r->plan64;
+  const bool want_grad = grad != nullptr;
+  unsigned long long* np = nonpos ? nonpos : reinterpret_cast<unsigned long long*>(r->queue + kQueueWords);
+  HIP_TRY(gst::launch_queue_reset(r->queue, np, 1, ctx->stream));
+  const gst::Plan64Req q = plan64_req(r, th, mode, w, probs, objective, grad, np);
+  HIP_TRY(gst::launch_gate_prep64(q.G, q.rho, r->K, d.GA, d.GAT, d.FA, ctx->stream));
+  gst::Plan64Launch a = q.tiles;
   const int L = d.host.n_levels;
   {
     ProfScope ps(ctx, FAM_P64_FWD);
@@ -834,29 +925,9 @@ int run_plan64(gst_req* r, const gst_gateset* th, int mode, const double* w, dou
                                      ctx->stream));
     }
   }
-  const bool need_slab = objective || grad;
   {
     ProfScope ps(ctx, FAM_P64_READ);
-    gst::Readout64Launch q{};
-    q.M = r->M;
-    q.E = th->effects;
-    q.FA = d.FA;
-    q.n_slots = d.host.n_slots;
-    q.slot_row = d.slot_row;
-    q.slot_ptr = d.slot_ptr;
-    q.slot_seq = d.slot_seq;
-    q.slot_pack = d.slot_pack;
-    q.slot_cnt = d.slot_cnt;
-    q.counts = r->counts;
-    q.W = w;
-    q.probs = probs;
-    q.mode = mode;
-    q.want_grad = want_grad ? 1 : 0;
-    q.INJ = d.INJ;
-    q.slab = need_slab ? d.slab : nullptr;
-    q.status = ctx->status;
-    q.nonpos = np;
-    HIP_TRY(gst::launch_readout64(q, d.readout_blocks, ctx->stream));
+    HIP_TRY(gst::launch_readout64(q.ro, q.ro_blocks, ctx->stream));
   }
   if (want_grad) {
     {
@@ -867,46 +938,16 @@ int run_plan64(gst_req* r, const gst_gateset* th, int mode, const double* w, dou
                                        d.level_long[l] != 0, ctx->stream));
       }
     }
-    if (d.n_chunks > 0) {
+    if (q.gemm.n_chunks > 0) {
       ProfScope ps(ctx, FAM_GEMM64);
-      gst::Gemm64TsLaunch g{};
-      g.BA = d.BA;
-      g.FA = d.FA;
-      g.tile_row0 = d.tile_row0;
-      g.col_anchor = d.col_anchor;
-      g.ts_tile = d.ts_tile;
-      g.ts_step = d.ts_step;
-      g.chunk_beg = d.chunk_beg;
-      g.chunk_end = d.chunk_end;
-      g.slab = d.chunk_slab;
-      g.n_chunks = (int)d.n_chunks;
-      HIP_TRY(gst::launch_gemm64_ts(g, ctx->stream));
+      HIP_TRY(gst::launch_gemm64_ts(q.gemm, ctx->stream));
     }
-    gst::Root64Launch ro{};
-    ro.INJ = d.INJ;
-    ro.root_slot = d.host.root_slot;
-    ro.n_slots = d.host.n_slots;
-    ro.root_chains = d.root_chains;
-    ro.n_root_chains = d.n_root_chains;
-    ro.out = d.root_vec;
-    HIP_TRY(gst::launch_root64(ro, ctx->stream));
+    HIP_TRY(gst::launch_root64(q.root, ctx->stream));
   }
-  if (need_slab) {
+  if (q.slab) {
     ProfScope ps(ctx, FAM_REDUCE64);
-    const int64_t Pc = 1 + 64 + (int64_t)r->M * 64;
-    const int n_waves = d.readout_blocks * gst::READOUT64_WAVES;
-    HIP_TRY(gst::launch_reduce(d.slab, n_waves, Pc, objective, grad, want_grad ? d.root_vec : nullptr, 64, d.part,
-                               ctx->stream));
-    if (want_grad) {
-      gst::Reduce64Launch red{};
-      red.M = r->M;
-      red.K = r->K;
-      red.chunk_slab = d.chunk_slab;
-      red.gate_chunk_ptr = d.gate_chunk_ptr;
-      red.grad = grad;
-      red.nonpos = np;
-      HIP_TRY(gst::launch_reduce64(red, ctx->stream));
-    }
+    HIP_TRY(gst::launch_reduce(q.slab, q.n_slabs, q.P, q.objective, q.grad, q.extra_rho, 64, q.part, ctx->stream));
+    if (want_grad) HIP_TRY(gst::launch_reduce64(q.r64, ctx->stream));
   }
   return GST_OK;
 }
@@ -1873,6 +1914,41 @@ static int batch_enqueue(gst_batch* b, hipStream_t stream, bool eager) {
       HIP_TRY(gst::launch_reduce_plan_batch(pg.dev, pg.n, pg.red_x, pg.red_parts, stream));
     }
   }
+  const gst_batch::P64Group& g = b->p64;
+  if (g.n > 0) {
+    // the three-qubit grouped-chain plans, in the order of the standalone sequence
+    HIP_TRY(gst::launch_gate_prep64_batch(g.dev, g.n, g.K_max, stream));
+    {
+      ProfScope ps(pc, FAM_P64_FWD);
+      for (int l = 0; l < g.n_levels; ++l) {
+        HIP_TRY(gst::launch_plan64_fwd_batch(g.dev, g.n, l, g.grid_long[l], true, stream));
+        HIP_TRY(gst::launch_plan64_fwd_batch(g.dev, g.n, l, g.grid_short[l], false, stream));
+      }
+    }
+    {
+      ProfScope ps(pc, FAM_P64_READ);
+      HIP_TRY(gst::launch_readout64_batch(g.dev, g.n, g.ro_grid, stream));
+    }
+    if (g.any_grad) {
+      {
+        ProfScope ps(pc, FAM_P64_BWD);
+        for (int l = g.n_levels - 1; l >= 0; --l) {
+          HIP_TRY(gst::launch_plan64_bwd_batch(g.dev, g.n, l, g.grid_long[l], true, stream));
+          HIP_TRY(gst::launch_plan64_bwd_batch(g.dev, g.n, l, g.grid_short[l], false, stream));
+        }
+      }
+      {
+        ProfScope ps(pc, FAM_GEMM64);
+        HIP_TRY(gst::launch_gemm64_ts_batch(g.dev, g.n, g.gemm_grid, stream));
+      }
+      HIP_TRY(gst::launch_root64_batch(g.dev, g.n, stream));
+    }
+    if (g.any_slab) {
+      ProfScope ps(pc, FAM_REDUCE64);
+      HIP_TRY(gst::launch_slab_sum64_batch(g.dev, g.n, g.red_x, g.red_parts, stream));
+      if (g.any_grad) HIP_TRY(gst::launch_reduce64_batch(g.dev, g.n, g.r64_x, stream));
+    }
+  }
   return GST_OK;
 }
 
@@ -1889,6 +1965,7 @@ int gst_batch_create(gst_ctx* ctx, int n, gst_req* const* reqs, const gst_gatese
   std::vector<int> group_req[6];
   std::vector<gst::BatchReduceItem> items;
   std::vector<int> plan_x[2];  // batched plan requests per D
+  std::vector<int> p64_x;      // batched three-qubit grouped-chain plans
   for (int x = 0; x < n; ++x) {
     gst_req* r = reqs[x];
     if (!r || r->ctx != ctx) return fail(GST_EINVAL, "request missing or from another context");
@@ -1911,7 +1988,10 @@ int gst_batch_create(gst_ctx* ctx, int n, gst_req* const* reqs, const gst_gatese
     b->objectives.push_back(ob);
     b->grads.push_back(gr);
     if (r->D == 64) {
-      b->plan_reqs.push_back(x);
+      if (r->plan64.used)
+        p64_x.push_back(x);
+      else
+        b->plan_reqs.push_back(x);
       rq.push_back(gst::BatchReq{});
       continue;
     }
@@ -2060,7 +2140,8 @@ int gst_batch_create(gst_ctx* ctx, int n, gst_req* const* reqs, const gst_gatese
   const size_t o_rq = cv.take<gst::BatchReq>(rq.size() + 1);
   for (int g = 0; g < 6; ++g) o_t[g] = cv.take<gst::BatchTile>(tiles[g].size() + 1);
   const size_t o_it = cv.take<gst::BatchReduceItem>(items.size() + 1), o_q = cv.take<unsigned>(16 * 6),
-               o_np = cv.take<unsigned long long>(rq.size() + 1), o_ck = cv.take<double>((size_t)ck_doubles + 1);
+               o_np = cv.take<unsigned long long>(rq.size() + 1), o_ck = cv.take<double>((size_t)ck_doubles + 1),
+               o_p64 = cv.take<gst::Plan64Req>(p64_x.size() + 1);
   for (int gi = 0; gi < 2; ++gi) {
     o_pa[gi] = cv.take<gst::PlanArgs>(psetup[gi].size() + 1);
     o_pi[gi] = cv.take<gst::InjectLaunch>(psetup[gi].size() + 1);
@@ -2126,6 +2207,44 @@ int gst_batch_create(gst_ctx* ctx, int n, gst_req* const* reqs, const gst_gatese
   }
   b->red.items = reinterpret_cast<const gst::BatchReduceItem*>(base + o_it);
   b->red.req_nonpos = b->req_nonpos;
+  if (!p64_x.empty()) {
+    // each request's standalone arguments; the launch grids are the largest
+    // of the requests' own
+    gst_batch::P64Group& g = b->p64;
+    std::vector<gst::Plan64Req> v;
+    for (int x : p64_x) {
+      gst_req* r = b->reqs[x];
+      const DevicePlan64& d = r->plan64;
+      const int mode = b->objectives[x] ? gst::MODE_LOGLIK : gst::MODE_PROBS;
+      v.push_back(plan64_req(r, &b->thetas[x], mode, nullptr, b->probs[x], b->objectives[x], b->grads[x],
+                             b->req_nonpos + x));
+      const gst::Plan64Req& q = v.back();
+      const int L = d.host.n_levels;
+      g.K_max = std::max(g.K_max, r->K);
+      g.n_levels = std::max(g.n_levels, L);
+      g.grid_long.resize((size_t)g.n_levels, 0);
+      g.grid_short.resize((size_t)g.n_levels, 0);
+      for (int l = 0; l < L; ++l) {
+        const int t = (int)(d.level_tile_ptr[l + 1] - d.level_tile_ptr[l]);
+        int& grid = d.level_long[l] ? g.grid_long[l] : g.grid_short[l];
+        grid = std::max(grid, t);
+      }
+      g.ro_grid = std::max(g.ro_grid, q.ro_blocks);
+      if (q.want_grad) {
+        g.any_grad = true;
+        g.gemm_grid = std::max(g.gemm_grid, q.gemm.n_chunks);
+        if (q.r64.grad) g.r64_x = std::max(g.r64_x, r->K * 64);  // K gate tiles of 4096 entries, 64 per workgroup
+      }
+      if (q.slab) {
+        g.any_slab = true;
+        g.red_x = std::max(g.red_x, (int)((q.P + 63) / 64));
+        g.red_parts = std::max(g.red_parts, q.red_parts);
+      }
+    }
+    g.n = (int)v.size();
+    HIP_TRY(hipMemcpy(base + o_p64, v.data(), v.size() * sizeof(gst::Plan64Req), hipMemcpyHostToDevice));
+    g.dev = reinterpret_cast<const gst::Plan64Req*>(base + o_p64);
+  }
   if (capture_graph && !b->reqs.empty()) {
     HIP_TRY(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
     HIP_TRY(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));

@@ -451,4 +451,54 @@ __device__ inline void build_jumps(double* js, const double* gates, uint32_t pat
 }
 
 }  // namespace
+
+// Slab sums in two deterministic stages.  Stage 1: block (x, g) adds slabs
+// [g*per, (g+1)*per) for 64 consecutive entries, four interleaved partial
+// sums combined in a fixed order.  Stage 2: entry p adds the stage-1
+// partials in ascending g, plus an optional extra vector on the rho entries.
+__device__ __forceinline__ void slab_sum_stage1(const double* __restrict__ slab, int n_slabs, int64_t P, int per,
+                                                double* __restrict__ part, int64_t bx, int g) {
+  __shared__ double red[4][64];
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  const int64_t p = bx * 64 + tx;
+  const int w0 = g * per, w1 = min(n_slabs, w0 + per);
+  double v = 0.0;
+  if (p < P)
+    for (int w = w0 + ty; w < w1; w += 4) v += slab[(int64_t)w * P + p];
+  red[ty][tx] = v;
+  __syncthreads();
+  if (ty == 0 && p < P) part[(int64_t)g * P + p] = (red[0][tx] + red[1][tx]) + (red[2][tx] + red[3][tx]);
+}
+
+__device__ __forceinline__ void slab_sum_stage2(const double* __restrict__ part, int n_part, int64_t P,
+                                                double* objective, double* grad, const double* __restrict__ extra_rho,
+                                                int D, int64_t bx) {
+  // An objective partial of +inf marks p <= 0 with N > 0 in this evaluation:
+  // the objective is then +inf and the gradient is not written.  Every block
+  // checks the n_part (<= 64) objective partials itself.
+  __shared__ double red[4][64];
+  __shared__ int nonpos_sh;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  const int64_t x = bx * 64 + tx;
+  double v = 0.0;
+  if (x < P)
+    for (int g = ty; g < n_part; g += 4) v += part[(int64_t)g * P + x];
+  red[ty][tx] = v;
+  if (ty == 1) {
+    const bool inf = tx < n_part && isinf(part[(int64_t)tx * P]);
+    const bool any = __ballot(inf) != 0ull;
+    if (tx == 0) nonpos_sh = any ? 1 : 0;
+  }
+  __syncthreads();
+  const bool nonpos = nonpos_sh != 0;
+  if (ty != 0 || x >= P) return;
+  v = (red[0][tx] + red[1][tx]) + (red[2][tx] + red[3][tx]);
+  if (extra_rho && x >= 1 && x <= D) v += extra_rho[x - 1];
+  if (x == 0) {
+    if (objective) *objective = nonpos ? INFINITY : v;
+  } else if (grad && !nonpos) {
+    grad[x - 1] = v;
+  }
+}
+
 }  // namespace gst

@@ -366,6 +366,44 @@ hipError_t launch_chain64(const Chain64Launch& a, int n_blocks, hipStream_t stre
 hipError_t launch_gemm64(const Gemm64Launch& a, hipStream_t stream);
 hipError_t launch_reduce64(const Reduce64Launch& a, hipStream_t stream);
 
+// One request of a batched launch of three-qubit grouped-chain plans: the
+// arguments of its standalone launch sequence.  The batched kernels take
+// request blockIdx.y (z for the slab sum), copy its arguments to registers and
+// run the standalone kernels' bodies on its own grid; workgroups beyond that
+// grid exit, so every request gets the bits of its standalone evaluation.
+struct Plan64Req {
+  Plan64Launch tiles;         // t_begin unused: the level ranges below
+  const int64_t* level_tile;  // [n_levels + 1] tile ranges of the levels
+  const uint8_t* level_long;  // [n_levels] 1: the level keeps the gates in registers
+  int n_levels;
+  int want_grad;
+  const double* G;            // the gate set and rho, for the operand layouts
+  const double* rho;
+  Readout64Launch ro;
+  int ro_blocks;
+  Gemm64TsLaunch gemm;        // n_chunks = 0: no gradient GEMM
+  Root64Launch root;
+  // the ordered sum of the readout's wave rows (slab = null: none)
+  const double* slab;
+  int n_slabs, red_parts, red_per;
+  int64_t P;                  // 1 + 64 + 64 M
+  double* part;
+  double* objective;
+  double* grad;
+  const double* extra_rho;    // the root adjoint, with the gradient
+  Reduce64Launch r64;         // r64.grad = null: no gate columns
+};
+hipError_t launch_gate_prep64_batch(const Plan64Req* reqs, int n, int K_max, hipStream_t stream);
+hipError_t launch_plan64_fwd_batch(const Plan64Req* reqs, int n, int level, int grid_x, bool reg_gates,
+                                   hipStream_t stream);
+hipError_t launch_readout64_batch(const Plan64Req* reqs, int n, int grid_x, hipStream_t stream);
+hipError_t launch_plan64_bwd_batch(const Plan64Req* reqs, int n, int level, int grid_x, bool reg_gates,
+                                   hipStream_t stream);
+hipError_t launch_gemm64_ts_batch(const Plan64Req* reqs, int n, int grid_x, hipStream_t stream);
+hipError_t launch_root64_batch(const Plan64Req* reqs, int n, hipStream_t stream);
+hipError_t launch_slab_sum64_batch(const Plan64Req* reqs, int n, int grid_x, int parts_max, hipStream_t stream);
+hipError_t launch_reduce64_batch(const Plan64Req* reqs, int n, int grid_x, hipStream_t stream);
+
 hipError_t launch_trunk_fwd(const PlanArgs& a, hipStream_t stream);
 hipError_t launch_trunk_bwd(const PlanArgs& a, hipStream_t stream);
 hipError_t launch_items(const PlanArgs& a, int n_blocks, hipStream_t stream);

@@ -275,10 +275,10 @@ __global__ __launch_bounds__(256) void gemm64_kernel(const Gemm64Launch a) {
 // partials of gate k, added in order with four interleaved partial sums.
 // (The tile columns [objective | rho | E] go through the two-stage ordered
 // reduction of the other kernels.)
-__global__ __launch_bounds__(256) void reduce64_kernel(const Reduce64Launch a) {
+__device__ __forceinline__ void reduce64_body(const Reduce64Launch& a, int64_t bx) {
   __shared__ double red[4][64];
   const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-  const int64_t y = (int64_t)blockIdx.x * 64 + tx;  // index into [K][4096]
+  const int64_t y = bx * 64 + tx;  // index into [K][4096]
   const int64_t Y = (int64_t)a.K * GATE64;
   double v = 0.0;
   if (y < Y) {
@@ -293,6 +293,8 @@ __global__ __launch_bounds__(256) void reduce64_kernel(const Reduce64Launch a) {
   const bool nonpos = a.nonpos && *a.nonpos != 0;
   if (a.grad && !nonpos) a.grad[1 + N64 + (int64_t)a.M * N64 - 1 + y] = v;
 }
+
+__global__ __launch_bounds__(256) void reduce64_kernel(const Reduce64Launch a) { reduce64_body(a, blockIdx.x); }
 
 // ---------------------------------------------------------------------------
 // The grouped-chain plan (gst_plan64.h).
@@ -314,9 +316,8 @@ __global__ __launch_bounds__(256) void reduce64_kernel(const Reduce64Launch a) {
 
 // GA[k][w][kk][l] = G[k][16w + l%16][4kk + l/16]; GAT the same for G^T.  Block 0
 // also writes rho into row 0 of the state arena.
-__global__ __launch_bounds__(256) void gate_prep64_kernel(const double* G, const double* rho, double* GA,
-                                                          double* GAT, double* FA) {
-  const int k = blockIdx.x;
+__device__ __forceinline__ void gate_prep64_body(const double* G, const double* rho, double* GA, double* GAT,
+                                                 double* FA, int k) {
   const double* g = G + (int64_t)k * GATE64;
   for (int x = threadIdx.x; x < GATE64; x += 256) {
     const int w = x >> 10, kk = (x >> 6) & 15, l = x & 63;
@@ -324,6 +325,11 @@ __global__ __launch_bounds__(256) void gate_prep64_kernel(const double* G, const
     GAT[(int64_t)k * GATE64 + x] = g[(4 * kk + (l >> 4)) * N64 + 16 * w + (l & 15)];
   }
   if (k == 0 && threadIdx.x < N64) FA[threadIdx.x] = rho[threadIdx.x];
+}
+
+__global__ __launch_bounds__(256) void gate_prep64_kernel(const double* G, const double* rho, double* GA,
+                                                          double* GAT, double* FA) {
+  gate_prep64_body(G, rho, GA, GAT, FA, blockIdx.x);
 }
 
 // Workgroup barrier for the LDS exchange of a step: waits for this wave's LDS
@@ -430,12 +436,11 @@ __device__ __forceinline__ void store_tile_rows(const double* V, double* out, in
 }
 
 template <class Gates>
-__global__ __launch_bounds__(256) void plan64_fwd_kernel(const Plan64Launch a) {
+__device__ __forceinline__ void plan64_fwd_body(const Plan64Launch& a, int64_t tile) {
   __shared__ double Vs[2][16 * VST];
   __shared__ uint8_t Ws[CH_STEPS + 1];
   const int tid = threadIdx.x, l = tid & 63, w = tid >> 6;
   const int c = l & 15, r4 = l >> 4;
-  const int64_t tile = a.t_begin + blockIdx.x;
   const int64_t anc = a.col_anchor[tile * 16 + c];
   const auto* fa = as_global(a.FA);
   Gates gs;
@@ -468,6 +473,11 @@ __global__ __launch_bounds__(256) void plan64_fwd_kernel(const Plan64Launch a) {
       cur ^= 1;
     }
   }
+}
+
+template <class Gates>
+__global__ __launch_bounds__(256) void plan64_fwd_kernel(const Plan64Launch a) {
+  plan64_fwd_body<Gates>(a, a.t_begin + blockIdx.x);
 }
 
 // Rows 4(4w + v) + r4 of the INJ rows that events of one node add to column c:
@@ -523,7 +533,7 @@ __device__ __forceinline__ double node_add(const NodeAdds& q, int v) {
 // the step's product runs, the next gate's operands a step ahead.  At the end each
 // chain delivers G_0^T b_0 to its anchor.
 template <class Gates>
-__global__ __launch_bounds__(256) void plan64_bwd_kernel(const Plan64Launch a) {
+__device__ __forceinline__ void plan64_bwd_body(const Plan64Launch& a, int64_t tile) {
   __shared__ double Bs[2][16 * VST];
   __shared__ uint8_t Ws[CH_STEPS + 1];
   __shared__ int32_t Es[CH_STEPS + 2];
@@ -532,7 +542,6 @@ __global__ __launch_bounds__(256) void plan64_bwd_kernel(const Plan64Launch a) {
   __shared__ unsigned long long Em[5];  // bit x: step s0 + x of the chunk has events
   const int tid = threadIdx.x, l = tid & 63, w = tid >> 6;
   const int c = l & 15, r4 = l >> 4;
-  const int64_t tile = a.t_begin + blockIdx.x;
   const int len = uniform(a.tile_len[tile]);
   const auto* word = as_global(a.words + a.tile_word[tile]);
   const int64_t row0 = a.tile_row0[tile];
@@ -617,6 +626,11 @@ __global__ __launch_bounds__(256) void plan64_bwd_kernel(const Plan64Launch a) {
   }
 }
 
+template <class Gates>
+__global__ __launch_bounds__(256) void plan64_bwd_kernel(const Plan64Launch a) {
+  plan64_bwd_body<Gates>(a, a.t_begin + blockIdx.x);
+}
+
 // The gate gradient of the grouped-chain plan: one workgroup per chunk of
 // tile-steps of one gate, wave w owning rows 16w .. 16w+15 of dG.  A tile-step
 // contributes sum_c b_c f_c^T over its sixteen columns: four MFMAs over the
@@ -647,12 +661,11 @@ __device__ __forceinline__ void load_ts(TsOps& o, const double* BA, const double
   }
 }
 
-__global__ __launch_bounds__(256) void gemm64_ts_kernel(const Gemm64TsLaunch a) {
+__device__ __forceinline__ void gemm64_ts_body(const Gemm64TsLaunch& a, int64_t ch) {
   __shared__ int64_t Rb[TS_CHUNK_MAX];       // adjoint row of column 0 at each tile-step
   __shared__ int64_t Rf[TS_CHUNK_MAX][16];   // the columns' state rows before it
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int z = lane >> 4, ii = lane & 15;
-  const int64_t ch = blockIdx.x;
   const int64_t x0 = a.chunk_beg[ch];
   const int n = (int)(a.chunk_end[ch] - x0);  // <= TS_CHUNK_MAX (checked on the host)
   for (int e = tid; e < n * 16; e += 256) {
@@ -686,6 +699,8 @@ __global__ __launch_bounds__(256) void gemm64_ts_kernel(const Gemm64TsLaunch a) 
     }
 }
 
+__global__ __launch_bounds__(256) void gemm64_ts_kernel(const Gemm64TsLaunch a) { gemm64_ts_body(a, blockIdx.x); }
+
 // Readouts per seed slot (the sequences ending at one node): p = E f, the
 // objective, dL/dp, the seed E^T (sum of the slot's dL/dp), and dL/dE, for
 // sixteen slots at a time on the matrix cores.  A wave takes the slot groups
@@ -702,13 +717,15 @@ __global__ __launch_bounds__(256) void gemm64_ts_kernel(const Gemm64TsLaunch a) 
 constexpr int RO_FST = 66;  // padded row stride (doubles) of a wave's staged states
 constexpr int RO_DST = 17;  // the same for its dL/dp tile
 
-__global__ __launch_bounds__(READOUT64_WAVES * 64) void readout64_kernel(const Readout64Launch a) {
+// Workgroup blk of n_blocks (the waves' slot groups depend on the count, so a
+// request's sums are the same in any launch that gives it n_blocks workgroups).
+__device__ __forceinline__ void readout64_body(const Readout64Launch& a, int64_t blk, int64_t n_blocks) {
   __shared__ double Fs[READOUT64_WAVES][16 * RO_FST];
   __shared__ double Ds[READOUT64_WAVES][16 * RO_DST];
   const int l = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int c = l & 15, r4 = l >> 4;
-  const int64_t wv = (int64_t)blockIdx.x * READOUT64_WAVES + w;
-  const int64_t nw = (int64_t)gridDim.x * READOUT64_WAVES;
+  const int64_t wv = blk * READOUT64_WAVES + w;
+  const int64_t nw = n_blocks * READOUT64_WAVES;
   const int M = a.M;
   const auto* gE = as_global(a.E);
   const auto* fa = as_global(a.FA);
@@ -850,11 +867,90 @@ __global__ __launch_bounds__(READOUT64_WAVES * 64) void readout64_kernel(const R
   }
 }
 
-__global__ __launch_bounds__(64) void root64_kernel(const Root64Launch a) {
+__global__ __launch_bounds__(READOUT64_WAVES * 64) void readout64_kernel(const Readout64Launch a) {
+  readout64_body(a, blockIdx.x, gridDim.x);
+}
+
+__device__ __forceinline__ void root64_body(const Root64Launch& a) {
   const int j = threadIdx.x;
   double v = a.root_slot >= 0 ? a.INJ[a.root_slot * N64 + j] : 0.0;
   for (int i = 0; i < a.n_root_chains; ++i) v += a.INJ[(a.n_slots + a.root_chains[i]) * N64 + j];
   a.out[j] = v;
+}
+
+__global__ __launch_bounds__(64) void root64_kernel(const Root64Launch a) { root64_body(a); }
+
+// ---------------------------------------------------------------------------
+// Batched forms of the grouped-chain plan kernels: request blockIdx.y (z for
+// the slab sum), its arguments read before anything is stored, its own grid.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void gate_prep64_batch(const Plan64Req* r) {
+  const Plan64Req& q = r[blockIdx.y];
+  if ((int)blockIdx.x >= q.tiles.K) return;
+  // the tile kernels read the operand layouts (const there); the prep writes them
+  gate_prep64_body(q.G, q.rho, const_cast<double*>(q.tiles.GA), const_cast<double*>(q.tiles.GAT), q.tiles.FA,
+                   blockIdx.x);
+}
+
+template <class Gates>
+__global__ __launch_bounds__(256) void plan64_fwd_batch(const Plan64Req* r, int level, int want_long) {
+  const Plan64Req& q = r[blockIdx.y];
+  if (level >= q.n_levels || (int)q.level_long[level] != want_long) return;
+  const int64_t t0 = q.level_tile[level], t1 = q.level_tile[level + 1];
+  if ((int64_t)blockIdx.x >= t1 - t0) return;
+  const Plan64Launch a = q.tiles;
+  plan64_fwd_body<Gates>(a, t0 + blockIdx.x);
+}
+
+template <class Gates>
+__global__ __launch_bounds__(256) void plan64_bwd_batch(const Plan64Req* r, int level, int want_long) {
+  const Plan64Req& q = r[blockIdx.y];
+  if (!q.want_grad || level >= q.n_levels || (int)q.level_long[level] != want_long) return;
+  const int64_t t0 = q.level_tile[level], t1 = q.level_tile[level + 1];
+  if ((int64_t)blockIdx.x >= t1 - t0) return;
+  const Plan64Launch a = q.tiles;
+  plan64_bwd_body<Gates>(a, t0 + blockIdx.x);
+}
+
+__global__ __launch_bounds__(READOUT64_WAVES * 64) void readout64_batch(const Plan64Req* r) {
+  const Plan64Req& q = r[blockIdx.y];
+  const int nb = q.ro_blocks;
+  if ((int)blockIdx.x >= nb) return;
+  const Readout64Launch a = q.ro;
+  readout64_body(a, blockIdx.x, nb);
+}
+
+__global__ __launch_bounds__(256) void gemm64_ts_batch(const Plan64Req* r) {
+  const Plan64Req& q = r[blockIdx.y];
+  if (!q.want_grad || (int)blockIdx.x >= q.gemm.n_chunks) return;
+  const Gemm64TsLaunch a = q.gemm;
+  gemm64_ts_body(a, blockIdx.x);
+}
+
+__global__ __launch_bounds__(64) void root64_batch(const Plan64Req* r) {
+  const Plan64Req& q = r[blockIdx.y];
+  if (!q.want_grad) return;
+  const Root64Launch a = q.root;
+  root64_body(a);
+}
+
+__global__ __launch_bounds__(256) void slab_sum64_stage1_batch(const Plan64Req* r) {
+  const Plan64Req& q = r[blockIdx.z];
+  if (!q.slab || (int64_t)blockIdx.x * 64 >= q.P || (int)blockIdx.y >= q.red_parts) return;
+  slab_sum_stage1(q.slab, q.n_slabs, q.P, q.red_per, q.part, blockIdx.x, blockIdx.y);
+}
+
+__global__ __launch_bounds__(256) void slab_sum64_stage2_batch(const Plan64Req* r) {
+  const Plan64Req& q = r[blockIdx.y];
+  if (!q.slab || (int64_t)blockIdx.x * 64 >= q.P) return;
+  slab_sum_stage2(q.part, q.red_parts, q.P, q.objective, q.grad, q.extra_rho, N64, blockIdx.x);
+}
+
+__global__ __launch_bounds__(256) void reduce64_batch(const Plan64Req* r) {
+  const Plan64Req& q = r[blockIdx.y];
+  if (!q.want_grad || !q.r64.grad || (int64_t)blockIdx.x * 64 >= (int64_t)q.r64.K * GATE64) return;
+  const Reduce64Launch a = q.r64;
+  reduce64_body(a, blockIdx.x);
 }
 
 }  // namespace
@@ -927,6 +1023,65 @@ hipError_t launch_chain64(const Chain64Launch& a, int n_blocks, hipStream_t stre
 hipError_t launch_gemm64(const Gemm64Launch& a, hipStream_t stream) {
   if (a.n_chunks <= 0) return hipSuccess;
   gst_launch(gemm64_kernel, dim3(a.n_chunks), dim3(256), 0, stream, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_gate_prep64_batch(const Plan64Req* reqs, int n, int K_max, hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  if (K_max < 1 || K_max > 5) return hipErrorInvalidValue;
+  gst_launch(gate_prep64_batch, dim3(K_max, n), dim3(256), 0, stream, reqs);
+  return hipGetLastError();
+}
+
+hipError_t launch_plan64_fwd_batch(const Plan64Req* reqs, int n, int level, int grid_x, bool reg_gates,
+                                   hipStream_t stream) {
+  if (n <= 0 || grid_x <= 0) return hipSuccess;
+  if (reg_gates)
+    gst_launch(plan64_fwd_batch<RegGates>, dim3(grid_x, n), dim3(256), 0, stream, reqs, level, 1);
+  else
+    gst_launch(plan64_fwd_batch<LoadGates>, dim3(grid_x, n), dim3(256), 0, stream, reqs, level, 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_plan64_bwd_batch(const Plan64Req* reqs, int n, int level, int grid_x, bool reg_gates,
+                                   hipStream_t stream) {
+  if (n <= 0 || grid_x <= 0) return hipSuccess;
+  if (reg_gates)
+    gst_launch(plan64_bwd_batch<RegGates>, dim3(grid_x, n), dim3(256), 0, stream, reqs, level, 1);
+  else
+    gst_launch(plan64_bwd_batch<LoadGates>, dim3(grid_x, n), dim3(256), 0, stream, reqs, level, 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_readout64_batch(const Plan64Req* reqs, int n, int grid_x, hipStream_t stream) {
+  if (n <= 0 || grid_x <= 0) return hipSuccess;
+  gst_launch(readout64_batch, dim3(grid_x, n), dim3(READOUT64_WAVES * 64), 0, stream, reqs);
+  return hipGetLastError();
+}
+
+hipError_t launch_gemm64_ts_batch(const Plan64Req* reqs, int n, int grid_x, hipStream_t stream) {
+  if (n <= 0 || grid_x <= 0) return hipSuccess;
+  gst_launch(gemm64_ts_batch, dim3(grid_x, n), dim3(256), 0, stream, reqs);
+  return hipGetLastError();
+}
+
+hipError_t launch_root64_batch(const Plan64Req* reqs, int n, hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  gst_launch(root64_batch, dim3(1, n), dim3(64), 0, stream, reqs);
+  return hipGetLastError();
+}
+
+hipError_t launch_slab_sum64_batch(const Plan64Req* reqs, int n, int grid_x, int parts_max, hipStream_t stream) {
+  if (n <= 0 || grid_x <= 0) return hipSuccess;
+  if (parts_max < 1 || parts_max > 64) return hipErrorInvalidValue;
+  gst_launch(slab_sum64_stage1_batch, dim3(grid_x, parts_max, n), dim3(256), 0, stream, reqs);
+  gst_launch(slab_sum64_stage2_batch, dim3(grid_x, n), dim3(256), 0, stream, reqs);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce64_batch(const Plan64Req* reqs, int n, int grid_x, hipStream_t stream) {
+  if (n <= 0 || grid_x <= 0) return hipSuccess;
+  gst_launch(reduce64_batch, dim3(grid_x, n), dim3(256), 0, stream, reqs);
   return hipGetLastError();
 }
 

@@ -266,3 +266,53 @@ def test_3q_grouped_plan_in_batch_and_nonpos(oracle_lib, gpu):
     o2, _, _ = reqs[0].eval(th[0])
     ctx.sync()
     assert torch.equal(o2, ref[0][0])
+
+
+def test_3q_grouped_plans_batched_per_kernel(gpu):
+    """Several grouped-chain plans in one batch run as one launch per kernel and
+    level (request = blockIdx.y): two gate sets on one list, a second list with
+    other levels, next to a two-qubit request and a three-qubit list without
+    sharing.  Every result equals the request's standalone result bit for bit,
+    eagerly and on graph replays, and a request with p <= 0 counts only its own."""
+    import torch
+    api, ctx = gpu
+    gs_a, sl_a, cnt_a = _structured_3q(seed=8, n_fid=6, powers=(1, 2, 4, 8))
+    gs_b = W.noisy_gateset("3q", 2e-3, 0.02, np.random.default_rng(21))
+    gs_c, sl_c, cnt_c = _structured_3q(seed=11, n_fid=5, spec=((2, 3), (3, 3)), powers=(1, 2, 4, 8, 16, 32, 64))
+    plain3 = W.random_workload("3q", 90, 40, 45)
+    two = W.random_workload("2q", 150, 60, 46)
+    reqs = [api.Request(ctx, 3, gs_a.K, gs_a.M, sl_a.offsets, sl_a.gates, cnt_a),
+            api.Request(ctx, 3, gs_a.K, gs_a.M, sl_a.offsets, sl_a.gates, cnt_a),
+            api.Request(ctx, 3, gs_c.K, gs_c.M, sl_c.offsets, sl_c.gates, cnt_c),
+            api.Request(ctx, 2, two.model.K, two.model.M, two.seqs.offsets, two.seqs.gates, two.counts),
+            api.Request(ctx, 3, plain3.model.K, plain3.model.M, plain3.seqs.offsets, plain3.seqs.gates,
+                        plain3.counts)]
+    grouped = [r.plan_info()["grouped"] for r in reqs]
+    assert grouped[:3] == [1, 1, 1] and grouped[4] == 0
+    th = [_dev(api, gs_a), _dev(api, gs_b), _dev(api, gs_c), _dev(api, two.model), _dev(api, plain3.model)]
+    ref = [r.eval(t, want_probs=True) for r, t in zip(reqs, th)]
+    ctx.sync()
+    for capture in (False, True):
+        say(f"[3q] grouped plans batched per kernel, capture={capture}")
+        bt = api.Batch(ctx, reqs, th, want_probs=True, want_grad=True, capture_graph=capture)
+        for _ in range(2):
+            bt.run()
+            ctx.sync()
+            for x, (o, p, g) in enumerate(ref):
+                assert torch.equal(bt.obj[x], o), x
+                assert torch.equal(bt.probs[x], p), x
+                assert torch.equal(bt.grad[x], g), x
+        assert bt.nonpos() == [0] * len(reqs)
+    say("[3q] grouped plans batched: p <= 0 with N > 0 in one request")
+    E0 = gs_c.effects.copy()
+    E0[2] = 0.0
+    th_bad = list(th)
+    th_bad[2] = api.DeviceGateSet.from_numpy(3, gs_c.rho, E0, gs_c.gates)
+    bt = api.Batch(ctx, reqs, th_bad, want_probs=True, want_grad=True, capture_graph=True)
+    bt.run()
+    rc, _, _ = ctx.sync(raise_on_error=False)
+    n_exp = int(np.count_nonzero(cnt_c[:, 2] > 0))
+    assert bt.nonpos() == [0, 0, n_exp, 0, 0]
+    assert float(bt.obj[2].cpu()[0]) == float("inf")
+    for x in (0, 1, 3, 4):
+        assert torch.equal(bt.obj[x], ref[x][0]) and torch.equal(bt.grad[x], ref[x][2]), x
