@@ -338,8 +338,9 @@ class _LibEngine:
 class GPUEngine(_LibEngine):
     """The chosen requests of a round in one batch (gst_batch): one persistent
     launch for the plain one- and two-qubit lists, one launch per kernel and
-    level for the shared-prefix plans, and the three-qubit requests' launch
-    sequences, all on the context's stream.  Batches are kept per
+    level for the shared-prefix plans (one, two and three qubits), and the
+    launch sequences of three-qubit lists without sharing, all on the
+    context's stream.  Batches are kept per
     composition; a composition is captured into a HIP graph the second time
     it is used (a first use runs eagerly: capturing costs more than one eager
     round).
