@@ -402,16 +402,23 @@ struct LoadGates {
   __device__ __forceinline__ void start(const double* base, int k, int w, int l) {
     load_ops(an, base + ((int64_t)k * 4 + w) * 1024, l);
   }
-  // operands of gate k (loaded a step ago); those of gate k_next (< 0: none) are loaded now
+  // operands of gate k (loaded a step ago); each register takes gate k_next's
+  // operand (< 0: none) as soon as its MFMA has read it, so one set of 16
+  // registers serves both
   __device__ __forceinline__ d4 product(const double* base, int k, int k_next, const double* B, int w, int l) {
     (void)k;
-    double ac[16];
-#pragma unroll
-    for (int kk = 0; kk < 16; ++kk) ac[kk] = an[kk];
-    if (k_next >= 0) load_ops(an, base + ((int64_t)k_next * 4 + w) * 1024, l);
     d4 acc = {0.0, 0.0, 0.0, 0.0};
+    if (k_next >= 0) {
+      const auto* g = as_global(base + ((int64_t)k_next * 4 + w) * 1024);
 #pragma unroll
-    for (int kk = 0; kk < 16; ++kk) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ac[kk], B[kk * VST + l], acc, 0, 0, 0);
+      for (int kk = 0; kk < 16; ++kk) {
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(an[kk], B[kk * VST + l], acc, 0, 0, 0);
+        an[kk] = g[kk * 64 + l];
+      }
+    } else {
+#pragma unroll
+      for (int kk = 0; kk < 16; ++kk) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(an[kk], B[kk * VST + l], acc, 0, 0, 0);
+    }
     return acc;
   }
 };
