@@ -370,6 +370,7 @@ constexpr int VST = 66;
 // next step are loaded while the current one runs; for levels of short
 // chains, where loading all K gates up front would cost more than the steps.
 struct RegGates {
+  static constexpr bool kReg = true;
   double g[5][16];
   __device__ __forceinline__ void init(const double* base, int K, int w, int l) {
 #pragma unroll
@@ -397,6 +398,7 @@ struct RegGates {
 };
 
 struct LoadGates {
+  static constexpr bool kReg = false;
   double an[16];
   __device__ __forceinline__ void init(const double*, int, int, int) {}
   __device__ __forceinline__ void start(const double* base, int k, int w, int l) {
@@ -488,49 +490,73 @@ __global__ __launch_bounds__(256) void plan64_fwd_kernel(const Plan64Launch a) {
 }
 
 // Rows 4(4w + v) + r4 of the INJ rows that events of one node add to column c:
-// up to EV_NODE rows in fixed registers, added later in the events' order.
+// up to EV_NODE rows, a window of them in fixed registers, added later in the
+// events' order.
 // The node is step x of the staged chunk: its events are Ev[Es[x] ..
 // Es[x + 1]), ascending by column, and the step's row of the column table says
 // where column c's lie, so no lane scans the others'.  The loads run over the
 // most events of one column at this step (a uniform count); a lane with fewer
 // loads rows of the step's other events, which `n` masks out where they are
 // added.
+template <int W>
 struct NodeAdds {
-  double r[EV_NODE][4];
-  int n;
+  double r[W][4];
+  int n;     // this column's events at the node
+  int most;  // the most events of one column at the node (uniform)
 };
 
-__device__ __forceinline__ void load_node_adds(NodeAdds& q, const int32_t* Es, const int32_t* Ev, const u32x4* Cc,
-                                               int x, int c, int w, int r4, const double* inj) {
+// Events e0 .. e0 + W - 1 of the node (a window of W rows; a node has up to
+// EV_NODE, so a window smaller than that is loaded in several rounds).
+template <int W>
+__device__ __forceinline__ void load_node_adds(NodeAdds<W>& q, const int32_t* Es, const int32_t* Ev, const u32x4* Cc,
+                                               int x, int e0, int c, int w, int r4, const double* inj) {
   const auto* g = as_global(inj);
   const int jb = uniform(Es[x]), tot = uniform(Es[x + 1]) - jb;
   const auto* row = reinterpret_cast<const uint8_t*>(Cc + x);
-  const int most = uniform((int)row[15]);
+  q.most = uniform((int)row[15]);
   const int lo = c > 0 ? (int)row[c - 1] : 0, hi = c < 15 ? (int)row[c] : tot;
   q.n = hi - lo;
-  int src[EV_NODE];
+  int src[W];
 #pragma unroll
-  for (int e = 0; e < EV_NODE; ++e) {
-    const int j = jb + (lo + e < tot ? lo + e : tot - 1);
+  for (int e = 0; e < W; ++e) {
+    const int j = jb + (lo + e0 + e < tot ? lo + e0 + e : tot - 1);
     src[e] = Ev[j < 0 ? 0 : (j < CH_EVENTS ? j : CH_EVENTS - 1)];
   }
 #pragma unroll
-  for (int e = 0; e < EV_NODE; ++e)
+  for (int e = 0; e < W; ++e)
 #pragma unroll
     for (int v = 0; v < 4; ++v) q.r[e][v] = 0.0;
 #pragma unroll
-  for (int e = 0; e < EV_NODE; ++e)
-    if (e < most)
+  for (int e = 0; e < W; ++e)
+    if (e0 + e < q.most)
 #pragma unroll
       for (int v = 0; v < 4; ++v) q.r[e][v] = g[(int64_t)src[e] * N64 + 4 * (4 * w + v) + r4];
 }
 
-// The node's events in their order (absent ones add zero).
-__device__ __forceinline__ double node_add(const NodeAdds& q, int v) {
-  double add = 0 < q.n ? q.r[0][v] : 0.0;
+// Adds the window's events to `add` in their order (absent ones add zero); the
+// first window starts the sum with its first row, so the node's sum is the same
+// chain of additions whatever the window.
+template <int W>
+__device__ __forceinline__ double node_add(const NodeAdds<W>& q, int e0, double add, int v) {
 #pragma unroll
-  for (int e = 1; e < EV_NODE; ++e) add += e < q.n ? q.r[e][v] : 0.0;
+  for (int e = 0; e < W; ++e) {
+    const double r = e0 + e < q.n ? q.r[e][v] : 0.0;
+    add = (e0 == 0 && e == 0) ? r : add + r;
+  }
   return add;
+}
+
+// A node's events summed: the first window loaded earlier (q), the others now.
+template <int W>
+__device__ __forceinline__ void node_sum(NodeAdds<W>& q, const int32_t* Es, const int32_t* Ev, const u32x4* Cc, int x,
+                                         int c, int w, int r4, const double* inj, double (&add)[4]) {
+#pragma unroll
+  for (int v = 0; v < 4; ++v) add[v] = node_add(q, 0, 0.0, v);
+  for (int e0 = W; e0 < q.most; e0 += W) {
+    load_node_adds(q, Es, Ev, Cc, x, e0, c, w, r4, inj);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) add[v] = node_add(q, e0, add[v], v);
+  }
 }
 
 // Reverse sweep of a tile.  b_t, the adjoint of the node after step t, is
@@ -539,7 +565,7 @@ __device__ __forceinline__ double node_add(const NodeAdds& q, int v) {
 // events of node t-1 added becomes b_{t-1}.  The events' rows are loaded while
 // the step's product runs, the next gate's operands a step ahead.  At the end each
 // chain delivers G_0^T b_0 to its anchor.
-template <class Gates>
+template <class Gates, int EVW>
 __device__ __forceinline__ void plan64_bwd_body(const Plan64Launch& a, int64_t tile) {
   __shared__ double Bs[2][16 * VST];
   __shared__ uint8_t Ws[CH_STEPS + 1];
@@ -598,24 +624,29 @@ __device__ __forceinline__ void plan64_bwd_body(const Plan64Launch& a, int64_t t
     };
     if (t1 == len) {
       // b of the last node: its events alone
-      NodeAdds q;
-      load_node_adds(q, Es, Ev, Cc, t1 - 1 - s0, c, w, r4, a.INJ);
+      NodeAdds<EVW> q;
+      load_node_adds(q, Es, Ev, Cc, t1 - 1 - s0, 0, c, w, r4, a.INJ);
+      double add[4];
+      node_sum(q, Es, Ev, Cc, t1 - 1 - s0, c, w, r4, a.INJ, add);
 #pragma unroll
-      for (int v = 0; v < 4; ++v) Bs[0][(4 * w + v) * VST + l] = node_add(q, v);
+      for (int v = 0; v < 4; ++v) Bs[0][(4 * w + v) * VST + l] = add[v];
       gs.start(a.GAT, uniform(Ws[n]), w, l);
       lds_barrier();
     }
     for (int x = n - 1; x >= 0; --x) {
       const int t = t0 + x;
-      NodeAdds q;  // events of node t - 1
+      NodeAdds<EVW> q;  // events of node t - 1 (the first window before the product)
       q.n = 0;
+      q.most = 0;
       const bool ev = t > 0 && has_events(t - 1 - s0);
-      if (ev) load_node_adds(q, Es, Ev, Cc, t - 1 - s0, c, w, r4, a.INJ);
+      if (ev) load_node_adds(q, Es, Ev, Cc, t - 1 - s0, 0, c, w, r4, a.INJ);
       const d4 acc = gs.product(a.GAT, uniform(Ws[x + 1]), t > 0 ? uniform(Ws[x]) : -1, Bs[cur], w, l);
       store_tile_rows(Bs[cur], a.BA + (row0 + (int64_t)t * 16) * N64, tid);
       if (ev) {
+        double add[4];
+        node_sum(q, Es, Ev, Cc, t - 1 - s0, c, w, r4, a.INJ, add);
 #pragma unroll
-        for (int v = 0; v < 4; ++v) Bs[cur ^ 1][(4 * w + v) * VST + l] = acc[v] + node_add(q, v);
+        for (int v = 0; v < 4; ++v) Bs[cur ^ 1][(4 * w + v) * VST + l] = acc[v] + add[v];
       } else {
 #pragma unroll
         for (int v = 0; v < 4; ++v) Bs[cur ^ 1][(4 * w + v) * VST + l] = acc[v] + 0.0;
@@ -633,9 +664,11 @@ __device__ __forceinline__ void plan64_bwd_body(const Plan64Launch& a, int64_t t
   }
 }
 
+// Event windows: the long level keeps all of a node's rows at once (a tile per
+// CU either way), the levels of short chains three (occupancy).
 template <class Gates>
 __global__ __launch_bounds__(256) void plan64_bwd_kernel(const Plan64Launch a) {
-  plan64_bwd_body<Gates>(a, a.t_begin + blockIdx.x);
+  plan64_bwd_body<Gates, Gates::kReg ? EV_NODE : 3>(a, a.t_begin + blockIdx.x);
 }
 
 // The gate gradient of the grouped-chain plan: one workgroup per chunk of
@@ -916,7 +949,9 @@ __global__ __launch_bounds__(256) void plan64_bwd_batch(const Plan64Req* r, int 
   const int64_t t0 = q.level_tile[level], t1 = q.level_tile[level + 1];
   if ((int64_t)blockIdx.x >= t1 - t0) return;
   const Plan64Launch a = q.tiles;
-  plan64_bwd_body<Gates>(a, t0 + blockIdx.x);
+  // several requests' long levels share the CUs: a window of two rows lets two
+  // of their tiles share a CU
+  plan64_bwd_body<Gates, Gates::kReg ? 2 : 3>(a, t0 + blockIdx.x);
 }
 
 __global__ __launch_bounds__(READOUT64_WAVES * 64) void readout64_batch(const Plan64Req* r) {
