@@ -193,16 +193,18 @@ int gst_req_plan_info(const gst_req* req, int64_t* info, int n);
  * together, one launch per plan kernel and level for all of them; each keeps
  * the partition of its partial sums (per item chunk, per trunk) of its
  * standalone evaluation, so its results too are identical alone and in any
- * batch.  Three-qubit requests run their own launch sequences after these.
+ * batch.  The three-qubit grouped-chain plans likewise run as one launch per
+ * kernel and level for all of them, each on its standalone grid; three-qubit
+ * lists without a plan run their own launch sequences after these.
  *
  * gst_batch_create fixes the requests (each at most once: GST_EINVAL
  * otherwise), the gate sets (device pointers whose
  * contents may change between runs) and the output pointers; any of probs,
  * objectives, grads may be NULL or hold NULL entries (an objective is needed
  * for a gradient).  capture_graph != 0 records the batched launch sequence
- * into a HIP graph once (the three-qubit sequences are enqueued eagerly after
- * it); gst_batch_run then replays it on the context stream (eagerly instead
- * while kernel timing is enabled).
+ * into a HIP graph once (the sequences of three-qubit lists without a plan are
+ * enqueued eagerly after it); gst_batch_run then replays it on the context
+ * stream (eagerly instead while kernel timing is enabled).
  * gst_batch_nonpos synchronizes and returns, per request, the number of
  * p <= 0 entries with positive counts in the last run (objective +inf).
  */
