@@ -316,3 +316,29 @@ def test_3q_grouped_plans_batched_per_kernel(gpu):
     assert float(bt.obj[2].cpu()[0]) == float("inf")
     for x in (0, 1, 3, 4):
         assert torch.equal(bt.obj[x], ref[x][0]) and torch.equal(bt.grad[x], ref[x][2]), x
+
+
+def test_c4_full_batched_equals_standalone(gpu):
+    """The whole c4 list for two gate sets in one batch (the batched long level
+    with its two-row event window, two tiles per CU): each request's
+    probabilities, objective and gradient are the bits of its standalone
+    evaluation."""
+    import torch
+    api, ctx = gpu
+    w = W.structured_workload("c4")
+    sets = [w.model, W.noisy_gateset("3q", W.LAMBDA, W.SIGMA, np.random.default_rng(81))]
+    say(f"[3q] c4 full batched: S={w.seqs.S}")
+    reqs = [api.Request(ctx, 3, g.K, g.M, w.seqs.offsets, w.seqs.gates, w.counts) for g in sets]
+    assert all(r.plan_info()["grouped"] == 1 for r in reqs)
+    th = [_dev(api, g) for g in sets]
+    ref = [r.eval(t, want_probs=True) for r, t in zip(reqs, th)]
+    ctx.sync()
+    bt = api.Batch(ctx, reqs, th, want_probs=True, want_grad=True, capture_graph=True)
+    for _ in range(2):
+        bt.run()
+        ctx.sync()
+        for x, (o, p, g) in enumerate(ref):
+            assert torch.equal(bt.obj[x], o), x
+            assert torch.equal(bt.probs[x], p), x
+            assert torch.equal(bt.grad[x], g), x
+    assert bt.nonpos() == [0, 0]
