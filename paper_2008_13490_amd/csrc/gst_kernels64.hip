@@ -768,7 +768,6 @@ __device__ __forceinline__ void readout64_body(const Readout64Launch& a, int64_t
   const int64_t nw = n_blocks * READOUT64_WAVES;
   const int M = a.M;
   const auto* gE = as_global(a.E);
-  const auto* fa = as_global(a.FA);
   const auto* g_pack = as_global(a.slot_pack);
   const auto* g_cnt = as_global(a.slot_cnt);
   const auto* g_seq = as_global(a.slot_seq);
@@ -796,9 +795,25 @@ __device__ __forceinline__ void readout64_body(const Readout64Launch& a, int64_t
     // slot 16 gi + c: its state row, the A operand of P^T (elements 4kk + r4)
     const int64_t sc = gi * 16 + c;
     const int64_t rowc = g_pack[4 * (sc < a.n_slots ? sc : 0)];
+    // the sixteen rows read whole (two rows of 512 B per load, 16 B per lane)
+    // into the wave's tile, then the A operand from there
+    {
+      const auto* fa2 = as_global(reinterpret_cast<const d2*>(a.FA));
+      d2 rv[8];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int64_t rr = __shfl(rowc, 2 * i + (l >> 5));
+        rv[i] = fa2[rr * (N64 / 2) + (l & 31)];
+      }
+      __builtin_amdgcn_wave_barrier();
+#pragma unroll
+      for (int i = 0; i < 8; ++i) *reinterpret_cast<d2*>(&Fw[(2 * i + (l >> 5)) * RO_FST + 2 * (l & 31)]) = rv[i];
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    }
     double fA[16];
 #pragma unroll
-    for (int kk = 0; kk < 16; ++kk) fA[kk] = fa[rowc * N64 + 4 * kk + r4];
+    for (int kk = 0; kk < 16; ++kk) fA[kk] = Fw[c * RO_FST + 4 * kk + r4];
     // slots 16 gi + 4v + r4 of the output rows: first sequence, sequence range,
     // the first sequence's count (or weight) of outcome c
     int64_t seq0[4], q0[4], q1[4];
@@ -821,10 +836,6 @@ __device__ __forceinline__ void readout64_body(const Readout64Launch& a, int64_t
     d4 p = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int kk = 0; kk < 16; ++kk) p = __builtin_amdgcn_mfma_f64_16x16x4f64(fA[kk], eP[kk], p, 0, 0, 0);
-    if (grad) {
-#pragma unroll
-      for (int kk = 0; kk < 16; ++kk) Fw[c * RO_FST + 4 * kk + r4] = fA[kk];
-    }
     double dps[4];
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
