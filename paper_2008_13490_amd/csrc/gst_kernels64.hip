@@ -701,9 +701,35 @@ __device__ __forceinline__ void load_ts(TsOps& o, const double* BA, const double
   }
 }
 
+constexpr int TS_SST = 80;  // padded row stride (doubles) of the staged rows: a half-wave's operand reads hit distinct banks
+
+// The 32 rows of tile-step x (16 adjoint rows, then the 16 state rows before
+// them), 16 bytes per thread and load, a row per 32 consecutive threads.
+__device__ __forceinline__ void load_ts_rows(d2 (&rg)[4], const double* BA, const double* FA, int64_t rb,
+                                             const int64_t* rf, int tid) {
+  const auto* gb = as_global(reinterpret_cast<const d2*>(BA));
+  const auto* gf = as_global(reinterpret_cast<const d2*>(FA));
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int item = tid + 256 * i, row = (item >> 5) & 15, j = item & 31;
+    rg[i] = item < 512 ? gb[(rb + row) * (N64 / 2) + j] : gf[rf[row] * (N64 / 2) + j];
+  }
+}
+
+__device__ __forceinline__ void store_ts_rows(const d2 (&rg)[4], double* Sb, double* Sf, int tid) {
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int item = tid + 256 * i, row = (item >> 5) & 15, j = item & 31;
+    double* dst = (item < 512 ? Sb : Sf) + row * TS_SST + 2 * j;
+    *reinterpret_cast<d2*>(dst) = rg[i];
+  }
+}
+
 __device__ __forceinline__ void gemm64_ts_body(const Gemm64TsLaunch& a, int64_t ch) {
   __shared__ int64_t Rb[TS_CHUNK_MAX];       // adjoint row of column 0 at each tile-step
   __shared__ int64_t Rf[TS_CHUNK_MAX][16];   // the columns' state rows before it
+  __shared__ double Sb[2][16 * TS_SST];      // a tile-step's adjoint rows, double-buffered
+  __shared__ double Sf[2][16 * TS_SST];      // its state rows
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int z = lane >> 4, ii = lane & 15;
   const int64_t x0 = a.chunk_beg[ch];
@@ -720,14 +746,25 @@ __device__ __forceinline__ void gemm64_ts_body(const Gemm64TsLaunch& a, int64_t 
   d4 acc[4];
 #pragma unroll
   for (int tc = 0; tc < 4; ++tc) acc[tc] = d4{0.0, 0.0, 0.0, 0.0};
+  d2 rg[4];
+  if (n > 0) {
+    load_ts_rows(rg, a.BA, a.FA, Rb[0], Rf[0], tid);
+    store_ts_rows(rg, Sb[0], Sf[0], tid);
+  }
+  lds_barrier();
   for (int x = 0; x < n; ++x) {
-    TsOps cur;
-    load_ts(cur, a.BA, a.FA, Rb[x], Rf[x], w, z, ii);
+    const int cur = x & 1;
+    if (x + 1 < n) load_ts_rows(rg, a.BA, a.FA, Rb[x + 1], Rf[x + 1], tid);
 #pragma unroll
-    for (int kb = 0; kb < 4; ++kb)
+    for (int kb = 0; kb < 4; ++kb) {
+      const int row = 4 * kb + z;
+      const double av = Sb[cur][row * TS_SST + 16 * w + ii];
 #pragma unroll
       for (int tc = 0; tc < 4; ++tc)
-        acc[tc] = __builtin_amdgcn_mfma_f64_16x16x4f64(cur.av[kb], cur.bv[kb][tc], acc[tc], 0, 0, 0);
+        acc[tc] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, Sf[cur][row * TS_SST + 16 * tc + ii], acc[tc], 0, 0, 0);
+    }
+    if (x + 1 < n) store_ts_rows(rg, Sb[cur ^ 1], Sf[cur ^ 1], tid);
+    lds_barrier();
   }
   double* out = a.slab + ch * GATE64;
 #pragma unroll
